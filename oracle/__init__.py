@@ -1,0 +1,256 @@
+"""ctypes/numpy view of the plain FP64 CPU oracle (``mlmc_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package; the product path
+in ``paper_1607_03252_amd`` never does, and the two share no code.
+
+Every array is an ``n x n x n`` float64 numpy array indexed ``[i, j, k]`` for
+the vertex ``(i h, j h, k h)`` with ``h = 1/(n-1)`` (k, the z index, fastest).
+Section and equation references are to arXiv 1607.03252.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mlmc_oracle.c")
+_LIB = os.path.join(_HERE, "libmlmc_oracle.so")
+
+OR_OK, OR_EINVAL, OR_ENOCONV = 0, -1, -3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+             "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        dp, ip, u32p, u64p = (C.POINTER(C.c_double), C.POINTER(C.c_int),
+                              C.POINTER(C.c_uint32), C.POINTER(C.c_uint64))
+        L.or_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.or_philox_words.argtypes = [C.c_uint64, C.c_uint32, u32p]
+        L.or_uniform_ints.argtypes = [C.c_uint64, C.c_uint32, u64p]
+        L.or_gaussians.argtypes = [C.c_uint64, C.c_uint32, dp]
+        L.or_kl_1d.argtypes = [C.c_double, C.c_int, dp, dp, dp]
+        L.or_kl_phi.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.or_kl_phi.restype = C.c_double
+        L.or_field.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
+        L.or_apply.argtypes = [C.c_int, dp, dp, dp]
+        L.or_residual.argtypes = [C.c_int, dp, dp, dp, dp]
+        L.or_rbgs_sweep.argtypes = [C.c_int, dp, dp, dp]
+        L.or_restrict.argtypes = [C.c_int, dp, dp]
+        L.or_prolong_add.argtypes = [C.c_int, dp, dp]
+        L.or_inject.argtypes = [C.c_int, dp, dp]
+        L.or_vcycle.argtypes = [C.c_int, dp, dp, dp, C.c_int, C.c_int]
+        L.or_norm2.argtypes = [C.c_int, dp]
+        L.or_norm2.restype = C.c_double
+        L.or_solve.argtypes = [C.c_int, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int,
+                               C.c_int, ip, dp, dp]
+        L.or_qoi.argtypes = [C.c_int, dp]
+        L.or_qoi.restype = C.c_double
+        L.or_mlmc_sample.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_double, C.c_double,
+                                     C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                     dp, dp, dp, ip]
+        L.or_sum.argtypes = [dp, C.c_long]
+        L.or_sum.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _check(st, what):
+    if st != OR_OK:
+        raise RuntimeError("oracle %s failed with status %d" % (what, st))
+
+
+# ---- counter-based RNG (Philox4x32-10, SC'11 definition) -------------------
+def philox4x32_10(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().or_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def philox_words(seed: int, level: int) -> np.ndarray:
+    o = np.zeros(128, dtype=np.uint32)
+    lib().or_philox_words(seed, level, o.ctypes.data_as(C.POINTER(C.c_uint32)))
+    return o
+
+
+def uniform_ints(seed: int, level: int) -> np.ndarray:
+    o = np.zeros(64, dtype=np.uint64)
+    lib().or_uniform_ints(seed, level, o.ctypes.data_as(C.POINTER(C.c_uint64)))
+    return o
+
+
+def gaussians(seed: int, level: int) -> np.ndarray:
+    o = np.zeros(64)
+    lib().or_gaussians(seed, level, _d(o))
+    return o
+
+
+# ---- KL expansion and field (Section 3.2, eq. def:expcov) -----------------
+def kl_1d(lam: float, nterms: int = 4):
+    om, th, nm = np.zeros(nterms), np.zeros(nterms), np.zeros(nterms)
+    _check(lib().or_kl_1d(lam, nterms, _d(om), _d(th), _d(nm)), "kl_1d")
+    return om, th, nm
+
+
+def kl_phi(lam, omega, norm, s):
+    return lib().or_kl_phi(lam, omega, norm, s)
+
+
+def field(n: int, sigma2: float, lam: float, xi: np.ndarray) -> np.ndarray:
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    k = np.zeros((n, n, n))
+    _check(lib().or_field(n, sigma2, lam, _d(xi), _d(k)), "field")
+    return k
+
+
+# ---- operator and multigrid pieces (Section 3, eq. modweak) ----------------
+def apply(k, u):
+    n = k.shape[0]
+    out = np.zeros_like(k)
+    _check(lib().or_apply(n, _d(k), _d(np.ascontiguousarray(u)), _d(out)), "apply")
+    return out
+
+
+def residual(k, b, u):
+    n = k.shape[0]
+    r = np.zeros_like(k)
+    _check(lib().or_residual(n, _d(k), _d(b), _d(np.ascontiguousarray(u)), _d(r)), "residual")
+    return r
+
+
+def rbgs_sweep(k, b, u):
+    """One red-then-black sweep; returns a new array."""
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    _check(lib().or_rbgs_sweep(k.shape[0], _d(k), _d(b), _d(u)), "rbgs")
+    return u
+
+
+def restrict(r):
+    n = r.shape[0]
+    nc = (n - 1) // 2 + 1
+    bc = np.zeros((nc, nc, nc))
+    _check(lib().or_restrict(n, _d(np.ascontiguousarray(r)), _d(bc)), "restrict")
+    return bc
+
+
+def prolong_add(ec, uf):
+    uf = np.array(uf, dtype=np.float64, copy=True, order="C")
+    _check(lib().or_prolong_add(ec.shape[0], _d(np.ascontiguousarray(ec)), _d(uf)), "prolong")
+    return uf
+
+
+def inject(kf):
+    n = kf.shape[0]
+    nc = (n - 1) // 2 + 1
+    kc = np.zeros((nc, nc, nc))
+    _check(lib().or_inject(n, _d(kf), _d(kc)), "inject")
+    return kc
+
+
+def vcycle(k, b, u, nu1=2, nu2=2):
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    _check(lib().or_vcycle(k.shape[0], _d(k), _d(b), _d(u), nu1, nu2), "vcycle")
+    return u
+
+
+def norm2(v):
+    return lib().or_norm2(v.shape[0], _d(np.ascontiguousarray(v)))
+
+
+def solve(k, b, u0=None, tol=1e-8, max_cycles=50, fixed_cycles=0, nu1=2, nu2=2,
+          allow_noconv=False):
+    """Returns (u, cycles, relres, history)."""
+    n = k.shape[0]
+    u = np.zeros_like(k) if u0 is None else np.array(u0, dtype=np.float64, copy=True, order="C")
+    cyc = C.c_int(0)
+    rel = C.c_double(0.0)
+    hist = np.zeros(max(max_cycles, fixed_cycles, 1))
+    st = lib().or_solve(n, _d(k), _d(b), _d(u), nu1, nu2, tol, max_cycles, fixed_cycles,
+                        C.byref(cyc), C.byref(rel), _d(hist))
+    if not (st == OR_OK or (allow_noconv and st == OR_ENOCONV)):
+        _check(st, "solve")
+    return u, cyc.value, rel.value, hist[:cyc.value].copy()
+
+
+def qoi(u):
+    return lib().or_qoi(u.shape[0], _d(np.ascontiguousarray(u)))
+
+
+def mlmc_sample(n0, level, seed, sigma2=1.0, lam=0.1, tol=1e-8, max_cycles=50,
+                fixed_cycles=0, nu1=2, nu2=2):
+    """Returns dict(Y, Qf, Qc, cycles=(fine, coarse))."""
+    Y, Qf, Qc = C.c_double(), C.c_double(), C.c_double()
+    cyc = (C.c_int * 2)()
+    st = lib().or_mlmc_sample(n0, level, seed, sigma2, lam, nu1, nu2, tol, max_cycles,
+                              fixed_cycles, C.byref(Y), C.byref(Qf), C.byref(Qc), cyc)
+    _check(st, "mlmc_sample")
+    return dict(Y=Y.value, Qf=Qf.value, Qc=Qc.value, cycles=(cyc[0], cyc[1]))
+
+
+def grid_n(n0: int, level: int) -> int:
+    """Vertices per axis of MLMC level `level` (h_l = 2^-l h_0, Section 2.3)."""
+    return (n0 - 1) * (1 << level) + 1
+
+
+def sample_fields(n0, level, seed, sigma2, lam):
+    """(k_fine, k_coarse or None) for one MLMC sample, from xi(seed, level)."""
+    xi = gaussians(seed, level)
+    kf = field(grid_n(n0, level), sigma2, lam, xi)
+    kc = field(grid_n(n0, level - 1), sigma2, lam, xi) if level > 0 else None
+    return kf, kc
+
+
+def rhs(n: int, f: float = 1.0) -> np.ndarray:
+    """b' = h^2 f on every vertex (boundary entries are ignored)."""
+    h = 1.0 / (n - 1)
+    return np.full((n, n, n), h * h * f)
+
+
+def csum(x) -> float:
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+    return lib().or_sum(_d(x), x.size)
+
+
+class LevelAcc(C.Structure):
+    """Shifted compensated accumulator for one MLMC level (Section 2.3)."""
+    _fields_ = [("n", C.c_long), ("shift", C.c_double), ("s1", C.c_double),
+                ("c1", C.c_double), ("s2", C.c_double), ("c2", C.c_double)]
+
+    def __init__(self):
+        super().__init__()
+        lib().or_acc_init(C.byref(self))
+
+    def add(self, y: float):
+        lib().or_acc_add(C.byref(self), C.c_double(y))
+
+    def result(self):
+        m, v = C.c_double(), C.c_double()
+        lib().or_acc_result(C.byref(self), C.byref(m), C.byref(v))
+        return m.value, v.value

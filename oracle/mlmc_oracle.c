@@ -1,0 +1,512 @@
+/*
+ * Plain FP64 CPU oracle for the per-sample hot path of multilevel Monte
+ * Carlo, arXiv 1607.03252 (Gmeiner, Drzisga, Ruede, Scheichl, Wohlmuth).
+ *
+ * TEST INFRASTRUCTURE ONLY: slow and obviously correct, loaded only by the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg.  Built
+ * with gcc -O2 -ffp-contract=off (no fast-math, no FMA contraction).
+ *
+ * What each function follows:
+ *   - MLMC sample Y_l = Q_l - Q_{l-1} on one shared omega, Y_0 = Q_0:
+ *     Section 2.2, eq. (MLMC_defn) and Algorithm 1 (steps 1.a.i-ii).
+ *   - Model problem -div(k grad u) = f on D = (0,1)^3, u = 0 on the
+ *     boundary, f deterministic (f = 1 in Section 7): Section 3, eq. (modweak).
+ *   - k = exp(Z), Z Gaussian with exponential covariance sigma^2, lambda;
+ *     Karhunen-Loeve expansion named as one way to sample Z: Section 3.2,
+ *     eq. (def:expcov).  Here the separable (product of 1D exponentials)
+ *     covariance truncated to the 4x4x4 block of 1D modes.
+ *   - Multigrid V-cycles with pre- and post-smoothing: Section 7.1 (the
+ *     paper uses FMG-2V(4,4)); here V(nu1,nu2) with red-black Gauss-Seidel
+ *     to a relative residual tolerance.
+ *   - Level statistics with divisor N: Section 2.3 (the estimator s_l^2).
+ *
+ * Readings where the paper is silent (all also listed in the design notes):
+ * 7-point finite differences with harmonic-mean face coefficients, scaled by
+ * h^2; coarse operators rediscretised with injected k; coarsest grid 3^3;
+ * Philox4x32-10 with key = seed and counter = (block, level, 0, 0);
+ * QoI = integral of u (trapezoidal, = h^3 * sum over interior vertices).
+ */
+#include "mlmc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define IDX(n, i, j, k) ((((size_t)(i)) * (size_t)(n) + (size_t)(j)) * (size_t)(n) + (size_t)(k))
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based random numbers.                                             */
+/* Philox4x32-10 as published by Salmon, Moraes, Dror and Shaw (SC'11):      */
+/* multipliers 0xD2511F53, 0xCD9E8D57; key increments (Weyl) 0x9E3779B9,     */
+/* 0xBB67AE85; ten rounds, the key bumped between rounds.                    */
+/* ------------------------------------------------------------------------ */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y1 = lo1;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    uint32_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* One omega per (seed, level): the two solves of a sample Y_l share it
+ * (Section 2.2), different levels draw independent numbers (Section 2.2,
+ * "independent samples across all levels"). */
+void or_philox_words(uint64_t seed, uint32_t level, uint32_t out[128]) {
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  for (uint32_t j = 0; j < 32; ++j) {
+    uint32_t ctr[4] = {j, level, 0u, 0u};
+    or_philox4x32_10(ctr, key, out + 4 * j);
+  }
+}
+
+void or_uniform_ints(uint64_t seed, uint32_t level, uint64_t out[64]) {
+  uint32_t w[128];
+  or_philox_words(seed, level, w);
+  for (int m = 0; m < 64; ++m) {
+    uint64_t hi = (uint64_t)(w[2 * m] >> 5);     /* 27 bits */
+    uint64_t lo = (uint64_t)(w[2 * m + 1] >> 6); /* 26 bits */
+    out[m] = hi * 67108864ull + lo;              /* hi * 2^26 + lo < 2^53 */
+  }
+}
+
+void or_gaussians(uint64_t seed, uint32_t level, double xi[64]) {
+  uint64_t M[64];
+  double U[64];
+  or_uniform_ints(seed, level, M);
+  for (int m = 0; m < 64; ++m) U[m] = ((double)M[m] + 1.0) * 0x1p-53; /* (0,1] exact */
+  const double two_pi = 6.283185307179586;
+  for (int p = 0; p < 32; ++p) {
+    double R = sqrt(-2.0 * log(U[2 * p]));
+    double a = two_pi * U[2 * p + 1];
+    xi[2 * p] = R * cos(a);
+    xi[2 * p + 1] = R * sin(a);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1D Karhunen-Loeve pairs of C(s,t) = exp(-|s-t|/lambda) on [0,1].          */
+/* Differentiating the integral eigen-equation twice gives phi'' = -w^2 phi  */
+/* with theta = 2 lambda/(1 + lambda^2 w^2) and the Robin conditions         */
+/* phi'(0) = phi(0)/lambda, phi'(1) = -phi(1)/lambda, hence                  */
+/* phi = sin(w s) + lambda w cos(w s) and the transcendental equation        */
+/* g(w) = (lambda^2 w^2 - 1) sin w - 2 lambda w cos w = 0, one root in each  */
+/* interval (m pi, (m+1) pi).                                                 */
+/* ------------------------------------------------------------------------ */
+static double kl_g(double lambda, double w) {
+  return (lambda * lambda * w * w - 1.0) * sin(w) - 2.0 * lambda * w * cos(w);
+}
+
+int or_kl_1d(double lambda, int nterms, double *omega, double *theta, double *norm) {
+  if (!(lambda > 0.0) || nterms < 1) return OR_EINVAL;
+  const double pi = 3.141592653589793;
+  for (int m = 0; m < nterms; ++m) {
+    double lo = m * pi, hi = (m + 1) * pi;
+    /* sign of g just right of m*pi is -(-1)^m (also for m = 0, where g ~ -(1+2 lambda) w) */
+    double slo = (m % 2 == 0) ? -1.0 : 1.0;
+    for (int it = 0; it < 200; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      double gm = kl_g(lambda, mid);
+      if (gm == 0.0) { lo = hi = mid; break; }
+      if ((gm < 0.0) == (slo < 0.0)) lo = mid; else hi = mid;
+    }
+    double w = 0.5 * (lo + hi);
+    omega[m] = w;
+    theta[m] = 2.0 * lambda / (1.0 + lambda * lambda * w * w);
+    /* N = int_0^1 (sin ws + lambda w cos ws)^2 ds in closed form */
+    double s2w = sin(2.0 * w), sw = sin(w);
+    norm[m] = 0.5 - s2w / (4.0 * w) + lambda * lambda * w * w * (0.5 + s2w / (4.0 * w)) +
+              lambda * sw * sw;
+  }
+  return OR_OK;
+}
+
+double or_kl_phi(double lambda, double omega, double norm, double s) {
+  return (sin(omega * s) + lambda * omega * cos(omega * s)) / sqrt(norm);
+}
+
+/* Z(x,y,z) = sigma * sum_{a,b,c<4} sqrt(theta_a theta_b theta_c) xi_{16a+4b+c}
+ *            phi_a(x) phi_b(y) phi_c(z),   k = exp(Z) at every vertex. */
+int or_field(int n, double sigma2, double lambda, const double xi[64], double *k) {
+  if (n < 3 || !(sigma2 >= 0.0) || !(lambda > 0.0)) return OR_EINVAL;
+  double om[4], th[4], nm[4];
+  int st = or_kl_1d(lambda, 4, om, th, nm);
+  if (st) return st;
+  double *phi = (double *)malloc(sizeof(double) * 4 * (size_t)n);
+  if (!phi) return OR_EINVAL;
+  for (int a = 0; a < 4; ++a)
+    for (int i = 0; i < n; ++i) phi[a * n + i] = or_kl_phi(lambda, om[a], nm[a], (double)i / (double)(n - 1));
+  double coef[64];
+  double sigma = sqrt(sigma2);
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int c = 0; c < 4; ++c)
+        coef[16 * a + 4 * b + c] = sigma * sqrt(th[a] * th[b] * th[c]) * xi[16 * a + 4 * b + c];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int kk = 0; kk < n; ++kk) {
+        double Z = 0.0;
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c)
+              Z += coef[16 * a + 4 * b + c] * phi[a * n + i] * phi[b * n + j] * phi[c * n + kk];
+        k[IDX(n, i, j, kk)] = exp(Z);
+      }
+  free(phi);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Operator: 7-point finite differences with harmonic-mean face              */
+/* coefficients c_pq = 2 k_p k_q / (k_p + k_q), scaled by h^2:               */
+/* (A'u)_p = D_p u_p - sum_q c_pq u_q, D_p = sum_q c_pq, u = 0 on boundary.  */
+/* Neighbour order: i-1, i+1, j-1, j+1, k-1, k+1.                            */
+/* ------------------------------------------------------------------------ */
+static double hmean(double a, double b) { return 2.0 * a * b / (a + b); }
+
+static void neighbours(int n, int i, int j, int kk, size_t q[6]) {
+  q[0] = IDX(n, i - 1, j, kk);
+  q[1] = IDX(n, i + 1, j, kk);
+  q[2] = IDX(n, i, j - 1, kk);
+  q[3] = IDX(n, i, j + 1, kk);
+  q[4] = IDX(n, i, j, kk - 1);
+  q[5] = IDX(n, i, j, kk + 1);
+}
+
+static int on_boundary(int n, size_t q) {
+  int kk = (int)(q % (size_t)n);
+  int j = (int)((q / (size_t)n) % (size_t)n);
+  int i = (int)(q / ((size_t)n * (size_t)n));
+  return i == 0 || j == 0 || kk == 0 || i == n - 1 || j == n - 1 || kk == n - 1;
+}
+
+/* value of u at vertex q, with the Dirichlet value 0 on the boundary */
+static double uval(int n, const double *u, size_t q) { return on_boundary(n, q) ? 0.0 : u[q]; }
+
+int or_apply(int n, const double *k, const double *u, double *out) {
+  if (n < 3) return OR_EINVAL;
+  size_t N = (size_t)n * n * n;
+  for (size_t p = 0; p < N; ++p) out[p] = 0.0;
+  for (int i = 1; i < n - 1; ++i)
+    for (int j = 1; j < n - 1; ++j)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        size_t p = IDX(n, i, j, kk), q[6];
+        neighbours(n, i, j, kk, q);
+        double D = 0.0, s = 0.0;
+        for (int t = 0; t < 6; ++t) {
+          double c = hmean(k[p], k[q[t]]);
+          D += c;
+          s += c * uval(n, u, q[t]);
+        }
+        out[p] = D * u[p] - s;
+      }
+  return OR_OK;
+}
+
+int or_residual(int n, const double *k, const double *b, const double *u, double *r) {
+  int st = or_apply(n, k, u, r);
+  if (st) return st;
+  for (int i = 1; i < n - 1; ++i)
+    for (int j = 1; j < n - 1; ++j)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        size_t p = IDX(n, i, j, kk);
+        r[p] = b[p] - r[p];
+      }
+  return OR_OK;
+}
+
+/* Gauss-Seidel point update u_p <- (b'_p + sum_q c_pq u_q) / D_p over the
+ * interior vertices of one colour ((i+j+k) even = red, odd = black). */
+static void gs_colour(int n, const double *k, const double *b, double *u, int colour) {
+  for (int i = 1; i < n - 1; ++i)
+    for (int j = 1; j < n - 1; ++j)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        if (((i + j + kk) & 1) != colour) continue;
+        size_t p = IDX(n, i, j, kk), q[6];
+        neighbours(n, i, j, kk, q);
+        double D = 0.0, s = 0.0;
+        for (int t = 0; t < 6; ++t) {
+          double c = hmean(k[p], k[q[t]]);
+          D += c;
+          s += c * uval(n, u, q[t]);
+        }
+        u[p] = (b[p] + s) / D;
+      }
+}
+
+int or_rbgs_sweep(int n, const double *k, const double *b, double *u) {
+  if (n < 3) return OR_EINVAL;
+  gs_colour(n, k, b, u, 0);
+  gs_colour(n, k, b, u, 1);
+  return OR_OK;
+}
+
+/* Full weighting: b'_c(I) = 4 * sum_{d in {-1,0,1}^3} 2^{-|d|_1} / 8 * r'(2I+d).
+ * The factor 4 = h_c^2 / h^2 converts the h^2-scaled fine residual into the
+ * h_c^2-scaled coarse right-hand side. */
+int or_restrict(int n, const double *r, double *bc) {
+  if (n < 5 || ((n - 1) & 1)) return OR_EINVAL;
+  int nc = (n - 1) / 2 + 1;
+  size_t Nc = (size_t)nc * nc * nc;
+  for (size_t p = 0; p < Nc; ++p) bc[p] = 0.0;
+  for (int I = 1; I < nc - 1; ++I)
+    for (int J = 1; J < nc - 1; ++J)
+      for (int K = 1; K < nc - 1; ++K) {
+        double s = 0.0;
+        for (int di = -1; di <= 1; ++di)
+          for (int dj = -1; dj <= 1; ++dj)
+            for (int dk = -1; dk <= 1; ++dk) {
+              int l1 = abs(di) + abs(dj) + abs(dk);
+              double w = ldexp(1.0, -l1) / 8.0;
+              s += w * r[IDX(n, 2 * I + di, 2 * J + dj, 2 * K + dk)];
+            }
+        bc[IDX(nc, I, J, K)] = 4.0 * s;
+      }
+  return OR_OK;
+}
+
+/* Trilinear interpolation: per axis, an even fine index 2I takes coarse I
+ * with weight 1, an odd one 2I+1 takes I and I+1 with weight 1/2 each; the
+ * coarse correction is 0 on the boundary. */
+int or_prolong_add(int nc, const double *ec, double *uf) {
+  if (nc < 3) return OR_EINVAL;
+  int n = 2 * (nc - 1) + 1;
+  for (int i = 1; i < n - 1; ++i)
+    for (int j = 1; j < n - 1; ++j)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        int ci[2], cj[2], ck[2];
+        double wi[2], wj[2], wk[2];
+        int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (kk & 1) ? 2 : 1;
+        ci[0] = i / 2; ci[1] = i / 2 + 1; wi[0] = wi[1] = (ni == 2) ? 0.5 : 1.0;
+        cj[0] = j / 2; cj[1] = j / 2 + 1; wj[0] = wj[1] = (nj == 2) ? 0.5 : 1.0;
+        ck[0] = kk / 2; ck[1] = kk / 2 + 1; wk[0] = wk[1] = (nk == 2) ? 0.5 : 1.0;
+        double s = 0.0;
+        for (int a = 0; a < ni; ++a)
+          for (int b = 0; b < nj; ++b)
+            for (int c = 0; c < nk; ++c) {
+              size_t q = IDX(nc, ci[a], cj[b], ck[c]);
+              double e = on_boundary(nc, q) ? 0.0 : ec[q];
+              s += wi[a] * wj[b] * wk[c] * e;
+            }
+        uf[IDX(n, i, j, kk)] += s;
+      }
+  return OR_OK;
+}
+
+int or_inject(int n, const double *kf, double *kc) {
+  if (n < 5 || ((n - 1) & 1)) return OR_EINVAL;
+  int nc = (n - 1) / 2 + 1;
+  for (int I = 0; I < nc; ++I)
+    for (int J = 0; J < nc; ++J)
+      for (int K = 0; K < nc; ++K) kc[IDX(nc, I, J, K)] = kf[IDX(n, 2 * I, 2 * J, 2 * K)];
+  return OR_OK;
+}
+
+static int valid_n(int n) {
+  if (n < 3) return 0;
+  int m = n - 1;
+  return (m & (m - 1)) == 0;
+}
+
+/* V-cycle on level with n vertices: nu1 sweeps, residual, restriction, a
+ * recursive cycle on the coarse grid from a zero guess, prolongation and
+ * correction, nu2 sweeps.  On 3^3 the single unknown is solved exactly. */
+static int vcycle_rec(int n, const double *k, const double *b, double *u, int nu1, int nu2) {
+  if (n == 3) {
+    size_t p = IDX(3, 1, 1, 1), q[6];
+    neighbours(3, 1, 1, 1, q);
+    double D = 0.0;
+    for (int t = 0; t < 6; ++t) D += hmean(k[p], k[q[t]]);
+    u[p] = b[p] / D;
+    return OR_OK;
+  }
+  size_t N = (size_t)n * n * n;
+  int nc = (n - 1) / 2 + 1;
+  size_t Nc = (size_t)nc * nc * nc;
+  double *r = (double *)malloc(sizeof(double) * N);
+  double *kc = (double *)malloc(sizeof(double) * Nc);
+  double *bc = (double *)malloc(sizeof(double) * Nc);
+  double *ec = (double *)calloc(Nc, sizeof(double));
+  if (!r || !kc || !bc || !ec) { free(r); free(kc); free(bc); free(ec); return OR_EINVAL; }
+  for (int s = 0; s < nu1; ++s) or_rbgs_sweep(n, k, b, u);
+  or_residual(n, k, b, u, r);
+  or_restrict(n, r, bc);
+  or_inject(n, k, kc);
+  vcycle_rec(nc, kc, bc, ec, nu1, nu2);
+  or_prolong_add(nc, ec, u);
+  for (int s = 0; s < nu2; ++s) or_rbgs_sweep(n, k, b, u);
+  free(r); free(kc); free(bc); free(ec);
+  return OR_OK;
+}
+
+int or_vcycle(int n, const double *k, const double *b, double *u, int nu1, int nu2) {
+  if (!valid_n(n) || nu1 < 0 || nu2 < 0) return OR_EINVAL;
+  return vcycle_rec(n, k, b, u, nu1, nu2);
+}
+
+/* Neumaier's compensated summation. */
+double or_sum(const double *x, long n) {
+  double s = 0.0, c = 0.0;
+  for (long i = 0; i < n; ++i) {
+    double t = s + x[i];
+    if (fabs(s) >= fabs(x[i])) c += (s - t) + x[i];
+    else c += (x[i] - t) + s;
+    s = t;
+  }
+  return s + c;
+}
+
+double or_norm2(int n, const double *v) {
+  double s = 0.0, c = 0.0;
+  for (int i = 1; i < n - 1; ++i)
+    for (int j = 1; j < n - 1; ++j)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        double x = v[IDX(n, i, j, kk)];
+        double y = x * x;
+        double t = s + y;
+        if (fabs(s) >= fabs(y)) c += (s - t) + y;
+        else c += (y - t) + s;
+        s = t;
+      }
+  return sqrt(s + c);
+}
+
+/* Cycle until ||b' - A'u||_2 / ||b'||_2 <= tol (checked after every full
+ * cycle) or, with fixed_cycles > 0, for exactly fixed_cycles cycles.  With
+ * ||b'|| = 0 the absolute residual norm is used instead. */
+int or_solve(int n, const double *k, const double *b, double *u, int nu1, int nu2,
+             double tol, int max_cycles, int fixed_cycles,
+             int *cycles, double *relres, double *hist) {
+  if (!valid_n(n) || nu1 < 0 || nu2 < 0) return OR_EINVAL;
+  if (fixed_cycles <= 0 && (max_cycles < 1 || !(tol > 0.0))) return OR_EINVAL;
+  size_t N = (size_t)n * n * n;
+  double *r = (double *)malloc(sizeof(double) * N);
+  if (!r) return OR_EINVAL;
+  /* Dirichlet boundary values of u are 0 */
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int kk = 0; kk < n; ++kk)
+        if (i == 0 || j == 0 || kk == 0 || i == n - 1 || j == n - 1 || kk == n - 1) u[IDX(n, i, j, kk)] = 0.0;
+  double bn = or_norm2(n, b);
+  double scale = bn > 0.0 ? bn : 1.0;
+  int limit = fixed_cycles > 0 ? fixed_cycles : max_cycles;
+  int m = 0, status = OR_ENOCONV;
+  double rho = 0.0;
+  for (m = 1; m <= limit; ++m) {
+    vcycle_rec(n, k, b, u, nu1, nu2);
+    or_residual(n, k, b, u, r);
+    rho = or_norm2(n, r) / scale;
+    if (hist) hist[m - 1] = rho;
+    if (fixed_cycles > 0) {
+      if (m == fixed_cycles) { status = OR_OK; break; }
+    } else if (rho <= tol) {
+      status = OR_OK;
+      break;
+    }
+  }
+  if (m > limit) m = limit;
+  if (cycles) *cycles = m;
+  if (relres) *relres = rho;
+  free(r);
+  return status;
+}
+
+/* QoI: the integral of u over D; u vanishes on the boundary, so the
+ * trapezoidal rule reduces to h^3 times the sum over interior vertices. */
+double or_qoi(int n, const double *u) {
+  double s = 0.0, c = 0.0;
+  for (int i = 1; i < n - 1; ++i)
+    for (int j = 1; j < n - 1; ++j)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        double x = u[IDX(n, i, j, kk)];
+        double t = s + x;
+        if (fabs(s) >= fabs(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+      }
+  double h = 1.0 / (double)(n - 1);
+  return h * h * h * (s + c);
+}
+
+/* Solve one grid for one sample: field, right-hand side h^2 * f with f = 1,
+ * zero initial guess, V-cycles, QoI. */
+static int solve_q(int n, double sigma2, double lambda, const double xi[64], int nu1, int nu2,
+                   double tol, int max_cycles, int fixed_cycles, double *Q, int *cycles) {
+  size_t N = (size_t)n * n * n;
+  double *k = (double *)malloc(sizeof(double) * N);
+  double *b = (double *)malloc(sizeof(double) * N);
+  double *u = (double *)calloc(N, sizeof(double));
+  if (!k || !b || !u) { free(k); free(b); free(u); return OR_EINVAL; }
+  int st = or_field(n, sigma2, lambda, xi, k);
+  double h = 1.0 / (double)(n - 1);
+  for (size_t p = 0; p < N; ++p) b[p] = h * h * 1.0;
+  if (!st) st = or_solve(n, k, b, u, nu1, nu2, tol, max_cycles, fixed_cycles, cycles, NULL, NULL);
+  *Q = or_qoi(n, u);
+  free(k); free(b); free(u);
+  return st;
+}
+
+int or_mlmc_sample(int n0, int level, uint64_t seed, double sigma2, double lambda,
+                   int nu1, int nu2, double tol, int max_cycles, int fixed_cycles,
+                   double *Y, double *Qf, double *Qc, int cycles[2]) {
+  if (!valid_n(n0) || level < 0 || level > 12) return OR_EINVAL;
+  double xi[64];
+  or_gaussians(seed, (uint32_t)level, xi);
+  int nf = (n0 - 1) * (1 << level) + 1;
+  double qf = 0.0, qc = 0.0;
+  int cf = 0, cc = 0;
+  int st = solve_q(nf, sigma2, lambda, xi, nu1, nu2, tol, max_cycles, fixed_cycles, &qf, &cf);
+  int st2 = OR_OK;
+  if (level > 0) {
+    int nc = (n0 - 1) * (1 << (level - 1)) + 1;
+    st2 = solve_q(nc, sigma2, lambda, xi, nu1, nu2, tol, max_cycles, fixed_cycles, &qc, &cc);
+  }
+  if (Qf) *Qf = qf;
+  if (Qc) *Qc = qc;
+  if (Y) *Y = qf - qc;
+  if (cycles) { cycles[0] = cf; cycles[1] = cc; }
+  return st ? st : st2;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level accumulator: shift K = first Y; compensated sums of (Y-K) and       */
+/* (Y-K)^2; mean = K + S1/N, s^2 = S2/N - (S1/N)^2 (divisor N as in the      */
+/* paper's estimator of V[Y_l]).                                            */
+/* ------------------------------------------------------------------------ */
+void or_acc_init(or_level_acc *a) { memset(a, 0, sizeof(*a)); }
+
+static void neumaier_add(double *s, double *c, double x) {
+  double t = *s + x;
+  if (fabs(*s) >= fabs(x)) *c += (*s - t) + x;
+  else *c += (x - t) + *s;
+  *s = t;
+}
+
+void or_acc_add(or_level_acc *a, double y) {
+  if (a->n == 0) a->shift = y;
+  double d = y - a->shift;
+  neumaier_add(&a->s1, &a->c1, d);
+  neumaier_add(&a->s2, &a->c2, d * d);
+  a->n += 1;
+}
+
+void or_acc_result(const or_level_acc *a, double *mean, double *var) {
+  if (a->n == 0) { *mean = 0.0; *var = 0.0; return; }
+  double N = (double)a->n;
+  double m1 = (a->s1 + a->c1) / N;
+  *mean = a->shift + m1;
+  *var = (a->s2 + a->c2) / N - m1 * m1;
+}
