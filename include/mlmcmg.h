@@ -1,0 +1,150 @@
+/*
+ * mlmcmg -- MI355X (gfx950) multilevel Monte Carlo multigrid hot path.
+ *
+ * C ABI of the HIP library libmlmcmg.so.  It computes the per-sample work of
+ * multilevel Monte Carlo as stated in arXiv 1607.03252 (Gmeiner, Drzisga,
+ * Ruede, Scheichl, Wohlmuth):
+ *   - the model problem -div(k(x,omega) grad u) = f on D = (0,1)^3 with
+ *     u = 0 on the boundary (Section 3, eq. modweak);
+ *   - a lognormal coefficient k = exp(Z) with exponential covariance
+ *     (Section 3.2, eq. def:expcov), here the separable covariance
+ *     sigma^2 prod_d exp(-|x_d - y_d|/lambda) truncated to its 4x4x4
+ *     Karhunen-Loeve block, driven by Philox4x32-10 numbers;
+ *   - the level differences Y_l = Q_l - Q_{l-1} computed from two solves on
+ *     one shared omega, Y_0 = Q_0 (Section 2.2, eq. MLMC_defn, Algorithm 1,
+ *     steps 1.a.i-ii), with Q = integral of u over D;
+ *   - multigrid V(nu1,nu2) cycles with red-black Gauss-Seidel smoothing
+ *     (the paper's solver is multigrid with pre/post smoothing, Section 7.1).
+ *
+ * Discretisation: an n x n x n vertex grid, n = 2^m + 1 (m >= 1), h = 1/(n-1),
+ * vertex (i,j,k) at (ih, jh, kh) stored at index (i*n + j)*n + k (k fastest).
+ * 7-point finite differences, face coefficient 2 k_p k_q / (k_p + k_q).
+ * MLMC level l uses n_l = (n0 - 1) 2^l + 1.
+ *
+ * Conventions for every call:
+ *   - "device" pointers are HIP device memory (e.g. torch CUDA tensors),
+ *     "host" pointers are ordinary CPU memory; the caller owns both.
+ *   - The plan owns its workspace and frees it in mg_plan_destroy.
+ *   - Calls are blocking unless stated: on return the plan's stream has been
+ *     synchronised and every output is written.
+ *   - Plans are not thread-safe; use one plan per host thread.
+ *   - Errors are returned as status codes (MG_*); mg_last_error gives text.
+ *     No C++ exception crosses this interface.
+ */
+#ifndef MLMCMG_H
+#define MLMCMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_plan_s* mg_plan;
+
+enum {
+  MG_OK = 0,
+  MG_EINVAL = -1,   /* bad argument (size, pointer, parameter) */
+  MG_ENOMEM = -2,   /* device allocation failed or HBM budget exceeded */
+  MG_ENOCONV = -3,  /* at least one solve missed tol within max_cycles */
+  MG_EHIP = -4,     /* a HIP runtime call failed */
+  MG_EBUSY = -5,    /* serving queue full */
+  MG_ENOTIMPL = -6  /* option not supported by this build */
+};
+
+enum { MG_FP64 = 0, MG_MIXED = 1 };
+
+typedef struct {
+  int n0;             /* vertices per axis of MLMC level 0, 2^m + 1, m >= 1     */
+  int max_level;      /* L >= 0: finest MLMC level, n_L = (n0-1) 2^L + 1       */
+  int nu1, nu2;       /* pre- and post-smoothing sweeps (>= 0, sum >= 1)       */
+  int max_cycles;     /* cycle cap per solve (>= 1)                            */
+  double tol;         /* relative residual ||b - Au|| / ||b|| to stop at (> 0) */
+  int precision;      /* MG_FP64 or MG_MIXED (FP32 inner cycles)               */
+  double sigma2;      /* variance sigma^2 of log k (>= 0)                      */
+  double corr_len;    /* correlation length lambda (> 0)                       */
+  int kl_per_axis;    /* 1D modes per axis; this build supports 4 (4^3 terms)  */
+  size_t hbm_budget;  /* bytes of workspace the plan may hold; 0 = no limit    */
+  void* stream;       /* hipStream_t to run on; NULL = the null stream         */
+} mg_plan_desc;
+
+/* Fill *d with the defaults: n0 = 33, max_level = 0, V(2,2), 50 cycles,
+ * tol = 1e-8, MG_FP64, sigma2 = 1, lambda = 0.1, 4 modes, no budget, NULL. */
+void mg_plan_desc_default(mg_plan_desc* d);
+
+/* Create a plan (validates *desc, precomputes the 1D KL tables for every
+ * grid of levels 0..max_level).  *out receives the handle.  Returns MG_OK,
+ * MG_EINVAL, MG_ENOMEM or MG_EHIP. */
+int mg_plan_create(const mg_plan_desc* desc, mg_plan* out);
+int mg_plan_destroy(mg_plan plan);
+
+/* Switch the stream later calls run on (e.g. torch's current stream). */
+int mg_plan_set_stream(mg_plan plan, void* stream);
+
+/* One multigrid solve of -div(k grad u) = f (Section 3, eq. modweak) on an
+ * n^3 grid, n = 2^m + 1.  Device pointers, n^3 doubles each, z fastest:
+ *   k: vertex values of the coefficient (> 0, boundary included);
+ *   f: right-hand side at vertices (boundary entries ignored);
+ *   u: in = initial guess, out = solution; its boundary entries are set to 0.
+ * Runs V(nu1,nu2) cycles (the plan's) until ||b - Au||_2/||b||_2 <= tol
+ * (tol <= 0: the plan's tol), or, when fixed_cycles > 0, exactly fixed_cycles
+ * cycles.  cycles/relres (host, may be NULL) receive the cycle count and the
+ * last relative residual.  MG_ENOCONV if max_cycles passed without reaching
+ * tol (u then holds the last iterate). */
+int mg_solve(mg_plan plan, int n, const double* k, const double* f, double* u,
+             double tol, int fixed_cycles, int* cycles, double* relres);
+
+/* n_samples MLMC samples of Y_level (Algorithm 1, steps 1.a.i-ii): for each
+ * seed s the normals xi(s, level) define omega; the solve on n_level and (for
+ * level > 0) the solve on n_{level-1} use the same omega, with f = 1 and a
+ * zero initial guess.  seeds: host uint64[n_samples].  Outputs (device,
+ * n_samples entries; Qf/Qc/cycles_out may be NULL):
+ *   Y_out: Q(u_level) - Q(u_{level-1}) (Y_0 = Q_0);  Qf_out, Qc_out: the two
+ *   QoIs (Qc = 0 at level 0);  cycles_out: int[2*n_samples], fine and coarse
+ *   cycle counts, -1 where a solve missed tol.
+ * fixed_cycles > 0 runs exactly that many cycles per solve (parity mode).
+ * Returns MG_ENOCONV if any solve missed tol (the others are complete). */
+int mlmc_sample_batch(mg_plan plan, int level, const uint64_t* seeds, int n_samples,
+                      double* Y_out, double* Qf_out, double* Qc_out, int* cycles_out,
+                      int fixed_cycles);
+
+/* Test and parity exports ------------------------------------------------- */
+
+/* Philox4x32-10 words of samples on the device: words_out (device) receives
+ * uint32[n_samples][128]; block j of sample s uses counter (j, level, 0, 0)
+ * and key (seed lo, seed hi).  normals_out (device, may be NULL) receives
+ * double[n_samples][64]: U_m = (M_m + 1) 2^-53 with
+ * M_m = (w[2m] >> 5) 2^26 + (w[2m+1] >> 6), then Box-Muller pairs. */
+int mlmc_philox(mg_plan plan, const uint64_t* seeds, int n_samples, int level,
+                uint32_t* words_out, double* normals_out);
+
+/* Coefficient k = exp(Z(seed, level)) at the n^3 vertices of an n grid (any
+ * n = 2^m + 1), computed by the same kernel the samples use.  k_out: device. */
+int mlmc_field(mg_plan plan, int n, uint64_t seed, int level, double* k_out);
+
+/* Host-side MLMC level statistics (Section 2.3: sample mean and s_l^2 with
+ * divisor N).  A shifted, compensated accumulator; add takes device or host
+ * arrays according to on_device. */
+typedef struct {
+  long long n;
+  double shift, s1, c1, s2, c2;
+} mlmc_level_acc;
+void mlmc_acc_init(mlmc_level_acc* a);
+int mlmc_acc_add(mlmc_level_acc* a, const double* y, int count, int on_device);
+/* mean = shift + S1/N, var = S2/N - (S1/N)^2 (N = count so far). */
+void mlmc_acc_result(const mlmc_level_acc* a, double* mean, double* var);
+
+/* Kernel timing: when enabled, the plan records HIP events around every
+ * launch of the smoothing kernel on the finest grids of a batch (on the
+ * plan's stream).  mg_profile_read returns the number of such launches and
+ * their summed duration in milliseconds since the last reset. */
+int mg_profile_enable(mg_plan plan, int on);
+int mg_profile_read(mg_plan plan, long long* launches, double* total_ms, double* nodes_per_launch);
+
+const char* mg_last_error(mg_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,250 @@
+"""Python binding of libmlmcmg (include/mlmcmg.h): argument marshalling only.
+
+Every step of the hot path runs in the HIP library; PyTorch supplies device
+memory (CUDA tensors on ROCm) and the stream.  There is no CPU fallback: if
+the library is missing or no GPU is present, calls raise.
+
+Functions carry the C names: ``mg_plan_create``, ``mg_solve``,
+``mlmc_sample_batch``, ``mlmc_philox``, ``mlmc_field``, ``mlmc_acc_*``,
+``mg_profile_*``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlmcmg.so")
+
+MG_OK, MG_EINVAL, MG_ENOMEM, MG_ENOCONV, MG_EHIP, MG_EBUSY, MG_ENOTIMPL = 0, -1, -2, -3, -4, -5, -6
+MG_FP64, MG_MIXED = 0, 1
+_NAMES = {0: "MG_OK", -1: "MG_EINVAL", -2: "MG_ENOMEM", -3: "MG_ENOCONV", -4: "MG_EHIP",
+          -5: "MG_EBUSY", -6: "MG_ENOTIMPL"}
+
+
+class MGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+class mg_plan_desc(C.Structure):
+    _fields_ = [("n0", C.c_int), ("max_level", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
+                ("max_cycles", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
+                ("sigma2", C.c_double), ("corr_len", C.c_double), ("kl_per_axis", C.c_int),
+                ("hbm_budget", C.c_size_t), ("stream", C.c_void_p)]
+
+
+class mlmc_level_acc(C.Structure):
+    _fields_ = [("n", C.c_longlong), ("shift", C.c_double), ("s1", C.c_double),
+                ("c1", C.c_double), ("s2", C.c_double), ("c2", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmlmcmg.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmlmcmg.so is not built: run `python -m paper_1607_03252_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+        L.mg_plan_desc_default.argtypes = [C.POINTER(mg_plan_desc)]
+        L.mg_plan_desc_default.restype = None
+        L.mg_plan_create.argtypes = [C.POINTER(mg_plan_desc), C.POINTER(vp)]
+        L.mg_plan_destroy.argtypes = [vp]
+        L.mg_plan_set_stream.argtypes = [vp, vp]
+        L.mg_solve.argtypes = [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, ip, dp]
+        L.mlmc_sample_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_uint64), C.c_int, vp, vp, vp,
+                                        vp, C.c_int]
+        L.mlmc_philox.argtypes = [vp, C.POINTER(C.c_uint64), C.c_int, C.c_int, vp, vp]
+        L.mlmc_field.argtypes = [vp, C.c_int, C.c_uint64, C.c_int, vp]
+        L.mlmc_acc_init.argtypes = [C.POINTER(mlmc_level_acc)]
+        L.mlmc_acc_init.restype = None
+        L.mlmc_acc_add.argtypes = [C.POINTER(mlmc_level_acc), vp, C.c_int, C.c_int]
+        L.mlmc_acc_result.argtypes = [C.POINTER(mlmc_level_acc), dp, dp]
+        L.mlmc_acc_result.restype = None
+        L.mg_profile_enable.argtypes = [vp, C.c_int]
+        L.mg_profile_read.argtypes = [vp, C.POINTER(C.c_longlong), dp, dp]
+        L.mg_last_error.argtypes = [vp]
+        L.mg_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names the public header declares (for the ABI check)."""
+    return ["mg_plan_desc_default", "mg_plan_create", "mg_plan_destroy", "mg_plan_set_stream",
+            "mg_solve", "mlmc_sample_batch", "mlmc_philox", "mlmc_field", "mlmc_acc_init",
+            "mlmc_acc_add", "mlmc_acc_result", "mg_profile_enable", "mg_profile_read",
+            "mg_last_error"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _current_stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype_name, numel=None, what="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % what)
+    if str(t.dtype) != "torch." + dtype_name:
+        raise ValueError("%s must be %s, got %s" % (what, dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s needs at least %d elements, has %d" % (what, numel, t.numel()))
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Owning handle of an mg_plan."""
+
+    def __init__(self, handle, desc):
+        self.handle = handle
+        self.desc = desc
+
+    def error(self):
+        return lib().mg_last_error(self.handle).decode()
+
+    def check(self, st, allow=(MG_OK,)):
+        if st not in allow:
+            raise MGError(st, self.error())
+        return st
+
+    def destroy(self):
+        if self.handle:
+            lib().mg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def mg_plan_desc_default() -> mg_plan_desc:
+    d = mg_plan_desc()
+    lib().mg_plan_desc_default(C.byref(d))
+    return d
+
+
+def mg_plan_create(desc: mg_plan_desc | None = None, **fields) -> Plan:
+    d = desc if desc is not None else mg_plan_desc_default()
+    for k, v in fields.items():
+        setattr(d, k, v)
+    h = C.c_void_p()
+    st = lib().mg_plan_create(C.byref(d), C.byref(h))
+    if st != MG_OK:
+        raise MGError(st, "mg_plan_create rejected the description")
+    return Plan(h, d)
+
+
+def mg_plan_destroy(plan: Plan):
+    plan.destroy()
+
+
+def mg_plan_set_stream(plan: Plan, stream=None):
+    s = _current_stream() if stream is None else C.c_void_p(stream)
+    return plan.check(lib().mg_plan_set_stream(plan.handle, s))
+
+
+def mg_solve(plan: Plan, n: int, k, f, u, tol: float = 0.0, fixed_cycles: int = 0):
+    """Returns (status, cycles, relres); status MG_OK or MG_ENOCONV, else raises."""
+    N = n * n * n
+    pk, pf, pu = _ptr(k, "float64", N, "k"), _ptr(f, "float64", N, "f"), _ptr(u, "float64", N, "u")
+    mg_plan_set_stream(plan)
+    cyc, rel = C.c_int(0), C.c_double(0.0)
+    st = lib().mg_solve(plan.handle, n, pk, pf, pu, tol, fixed_cycles, C.byref(cyc), C.byref(rel))
+    plan.check(st, (MG_OK, MG_ENOCONV))
+    return st, cyc.value, rel.value
+
+
+def _seeds(seeds):
+    a = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    return a, a.ctypes.data_as(C.POINTER(C.c_uint64))
+
+
+def mlmc_sample_batch(plan: Plan, level: int, seeds, n: int, Y_out, Qf_out=None, Qc_out=None,
+                      cycles_out=None, fixed_cycles: int = 0):
+    """n samples of Y_level; returns MG_OK or MG_ENOCONV, raises otherwise."""
+    arr, sp = _seeds(seeds)
+    if arr.size < n:
+        raise ValueError("need %d seeds" % n)
+    py = _ptr(Y_out, "float64", n, "Y_out")
+    pqf = _ptr(Qf_out, "float64", n, "Qf_out")
+    pqc = _ptr(Qc_out, "float64", n, "Qc_out")
+    pc = _ptr(cycles_out, "int32", 2 * n, "cycles_out")
+    mg_plan_set_stream(plan)
+    st = lib().mlmc_sample_batch(plan.handle, level, sp, n, py, pqf, pqc, pc, fixed_cycles)
+    return plan.check(st, (MG_OK, MG_ENOCONV))
+
+
+def mlmc_philox(plan: Plan, seeds, n: int, level: int, words_out=None, normals_out=None):
+    arr, sp = _seeds(seeds)
+    pw = _ptr(words_out, "int32", 128 * n, "words_out") if words_out is not None and \
+        str(words_out.dtype) == "torch.int32" else _ptr(words_out, "uint32", 128 * n, "words_out")
+    pn = _ptr(normals_out, "float64", 64 * n, "normals_out")
+    mg_plan_set_stream(plan)
+    return plan.check(lib().mlmc_philox(plan.handle, sp, n, level, pw, pn))
+
+
+def mlmc_field(plan: Plan, n: int, seed: int, level: int, k_out):
+    pk = _ptr(k_out, "float64", n * n * n, "k_out")
+    mg_plan_set_stream(plan)
+    return plan.check(lib().mlmc_field(plan.handle, n, seed, level, pk))
+
+
+def mlmc_acc_init() -> mlmc_level_acc:
+    a = mlmc_level_acc()
+    lib().mlmc_acc_init(C.byref(a))
+    return a
+
+
+def mlmc_acc_add(acc: mlmc_level_acc, y):
+    """y: CUDA float64 tensor or host array-like."""
+    torch = None
+    try:
+        import torch as _t
+        torch = _t
+    except ImportError:
+        pass
+    if torch is not None and isinstance(y, torch.Tensor) and y.is_cuda:
+        p = _ptr(y.contiguous(), "float64", None, "y")
+        st = lib().mlmc_acc_add(C.byref(acc), p, y.numel(), 1)
+    else:
+        a = np.ascontiguousarray(np.asarray(y, dtype=np.float64).ravel())
+        st = lib().mlmc_acc_add(C.byref(acc), C.c_void_p(a.ctypes.data), a.size, 0)
+    if st != MG_OK:
+        raise MGError(st, "mlmc_acc_add failed")
+
+
+def mlmc_acc_result(acc: mlmc_level_acc):
+    m, v = C.c_double(), C.c_double()
+    lib().mlmc_acc_result(C.byref(acc), C.byref(m), C.byref(v))
+    return m.value, v.value
+
+
+def mg_profile_enable(plan: Plan, on: bool = True):
+    return plan.check(lib().mg_profile_enable(plan.handle, 1 if on else 0))
+
+
+def mg_profile_read(plan: Plan):
+    """(launches, total_ms, nodes_per_launch) of the finest-grid smoothing launches."""
+    n, ms, nodes = C.c_longlong(), C.c_double(), C.c_double()
+    plan.check(lib().mg_profile_read(plan.handle, C.byref(n), C.byref(ms), C.byref(nodes)))
+    return n.value, ms.value, nodes.value

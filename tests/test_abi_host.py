@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/mlmcmg.h declares, rejects bad plan descriptions
+before touching the device, and its host-side level accumulator (mean and
+s^2 with divisor N, Section 2.3) matches correctly rounded sums."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlmcmg.h")
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_1607_03252_amd as M
+    if not os.path.exists(M.LIB_PATH):
+        from paper_1607_03252_amd import build
+        build.build()
+    M.lib()
+    return M
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for must in ("mg_plan_create", "mg_plan_destroy", "mg_solve", "mlmc_sample_batch",
+                 "mlmc_philox", "mlmc_field", "mg_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(M):
+    out = subprocess.check_output(["nm", "-D", "--defined-only", M.LIB_PATH], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    assert sorted(M.exported_symbols()) == declared_functions()
+    for n in declared_functions():
+        getattr(M.lib(), n)
+
+
+def test_plan_desc_defaults(M):
+    d = M.mg_plan_desc_default()
+    assert (d.n0, d.max_level, d.nu1, d.nu2, d.max_cycles) == (33, 0, 2, 2, 50)
+    assert d.tol == 1e-8 and d.sigma2 == 1.0 and d.corr_len == 0.1 and d.kl_per_axis == 4
+    assert C.sizeof(M.mg_plan_desc) == 80
+
+
+@pytest.mark.parametrize("field,value", [("n0", 32), ("n0", 2), ("max_level", -1), ("nu1", -1),
+                                         ("max_cycles", 0), ("tol", 0.0), ("sigma2", -1.0),
+                                         ("corr_len", 0.0), ("precision", 7)])
+def test_bad_plan_descriptions_rejected_on_host(M, field, value):
+    d = M.mg_plan_desc_default()
+    setattr(d, field, value)
+    h = C.c_void_p()
+    assert M.lib().mg_plan_create(C.byref(d), C.byref(h)) == M.MG_EINVAL
+    assert not h.value
+
+
+def test_unsupported_kl_modes(M):
+    d = M.mg_plan_desc_default()
+    d.kl_per_axis = 5
+    h = C.c_void_p()
+    assert M.lib().mg_plan_create(C.byref(d), C.byref(h)) == M.MG_ENOTIMPL
+
+
+def test_null_plan_calls_fail_cleanly(M):
+    L = M.lib()
+    assert L.mg_solve(None, 9, None, None, None, 0.0, 0, None, None) == M.MG_EINVAL
+    assert L.mlmc_sample_batch(None, 0, None, 1, None, None, None, None, 0) == M.MG_EINVAL
+    assert L.mg_plan_destroy(None) == M.MG_EINVAL
+
+
+def test_level_accumulator_host(M):
+    rng = np.random.default_rng(7)
+    y = 0.02 + 1e-6 * rng.standard_normal(20000)
+    acc = M.mlmc_acc_init()
+    M.mlmc_acc_add(acc, y[:7])
+    M.mlmc_acc_add(acc, y[7:])
+    mean, var = M.mlmc_acc_result(acc)
+    m_ref = math.fsum(y) / y.size
+    v_ref = math.fsum((v - m_ref) ** 2 for v in y) / y.size
+    assert abs(mean - m_ref) <= 2e-16 * abs(m_ref)
+    assert abs(var - v_ref) <= 1e-10 * v_ref
+    empty = M.mlmc_acc_init()
+    assert M.mlmc_acc_result(empty) == (0.0, 0.0)
