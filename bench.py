@@ -27,10 +27,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-# algorithmic bytes per interior node of one colour pass of the two-pass
-# smoother with a constant right-hand side: wh (8) + other-colour u (4) +
-# own-colour u written (4)
-COLOUR_PASS_BYTES_PER_NODE = 16.0
+# algorithmic bytes per interior node of one fused red-black sweep with a
+# constant right-hand side: wh (8) + u read (8) + u written (8)
+SWEEP_BYTES_PER_NODE = 24.0
 # byte model of one FP64 V(2,2) cycle per finest-grid node (whole hierarchy)
 VCYCLE_BYTES_PER_NODE = 195.0
 
@@ -53,6 +52,8 @@ def main():
     ap.add_argument("--samples", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=16)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -82,10 +83,12 @@ def main():
         st = M.mlmc_sample_batch(P, level, seeds, S, Y, Qf, Qc, cyc)
         assert st == M.MG_OK, st
 
+    if not args.no_autotune:
+        M.mg_autotune(P, level, S, 3)
+    tiles = {n: M.mg_get_tile(P, n) for n in (65, 33, 17, 9, 5)}
     for s in range(args.warmup):
         step(10**5 + s)
     torch.cuda.synchronize()
-    M.mg_profile_enable(P, True)
     cycles_f = []
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -93,14 +96,19 @@ def main():
         cycles_f.append(cyc.view(S, 2)[:, 0].float().mean())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    cyc_mean = float(torch.stack(cycles_f).mean().item())
+    # per-kernel timing of the finest-grid smoother: HIP events on the plan's
+    # stream around each launch (eager launches, same kernels and inputs)
+    M.mg_profile_enable(P, True)
+    for s in range(args.profile_steps):
+        step(s)
     launches, ms, nodes = M.mg_profile_read(P)
     M.mg_profile_enable(P, False)
-    cyc_mean = float(torch.stack(cycles_f).mean().item())
 
     value = S * args.steps / dt
     ms_step = 1e3 * dt / args.steps
     avg_ms = ms / max(launches, 1)
-    bytes_launch = COLOUR_PASS_BYTES_PER_NODE * nodes
+    bytes_launch = SWEEP_BYTES_PER_NODE * nodes
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     nf, nc = (n0 - 1) * 2**level + 1, (n0 - 1) * 2**(level - 1) + 1
     eff = VCYCLE_BYTES_PER_NODE * (nf**3 + nc**3) * S * cyc_mean * args.steps / dt / 1e9
@@ -120,13 +128,15 @@ def main():
         "data": "synthetic (Philox-seeded 64-term KL lognormal fields)",
         "config": {"workload": "mlmc_level_pair_fine65_coarse33_x64", "n0": n0, "level": level,
                    "samples_per_step": S, "sigma2": 1.0, "corr_len": 0.1, "tol": 1e-8,
-                   "cycle": "V(2,2) red-black GS", "parallelism": "single GPU"},
+                   "cycle": "V(2,2) red-black GS", "parallelism": "single GPU",
+                   "tiles": {str(k): list(v) for k, v in tiles.items()}},
         "per_level": {str(level): {"samples_per_s": value, "fine_cycles_mean": cyc_mean,
                                    "effective_vcycle_GBps": eff,
                                    "batch_latency_ms": ms_step}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_rbgs_colour (finest grids)", "launches": launches,
+                     "kernel": "k_sweep (fused red-black sweep, 65^3 grids)", "launches": launches,
+                     "tile": list(tiles[65]),
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_launch},
     }
     if not args.no_cpu_baseline:

@@ -109,6 +109,27 @@ int mlmc_sample_batch(mg_plan plan, int level, const uint64_t* seeds, int n_samp
                       double* Y_out, double* Qf_out, double* Qc_out, int* cycles_out,
                       int fixed_cycles);
 
+/* Execution options (no effect on results beyond rounding order unless
+ * stated):
+ *   "smoother": 0 = fused single-pass red-black sweep (default),
+ *               1 = two-pass in-place colour sweeps (same iterates);
+ *   "graph":    1 = capture the cycles of mlmc_sample_batch into HIP graphs
+ *               (default), 0 = launch eagerly.
+ * Returns MG_EINVAL for an unknown name or value. */
+int mg_plan_set_option(mg_plan plan, const char* name, long long value);
+
+/* Tile shape of the fused smoother on grids of size n: tj rows (j) by tk
+ * columns (k) per workgroup, the planes split into `chunks` pieces.  Only the
+ * compiled shapes whose tj, tk divide n-1 are accepted (MG_EINVAL otherwise). */
+int mg_set_tile(mg_plan plan, int n, int tj, int tk, int chunks);
+int mg_get_tile(mg_plan plan, int n, int* tj, int* tk, int* chunks);
+
+/* Autotuner: runs one batch of n_samples samples of `level` (seeds
+ * 0x5eed0000 + i), then times every compiled tile shape and chunk count of the
+ * smoother on each grid size of that batch (reps launches each, HIP events)
+ * and keeps the fastest per size in the plan. */
+int mg_autotune(mg_plan plan, int level, int n_samples, int reps);
+
 /* Test and parity exports ------------------------------------------------- */
 
 /* Philox4x32-10 words of samples on the device: words_out (device) receives

@@ -70,6 +70,10 @@ def lib():
         L.mlmc_acc_result.restype = None
         L.mg_profile_enable.argtypes = [vp, C.c_int]
         L.mg_profile_read.argtypes = [vp, C.POINTER(C.c_longlong), dp, dp]
+        L.mg_plan_set_option.argtypes = [vp, C.c_char_p, C.c_longlong]
+        L.mg_set_tile.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.mg_get_tile.argtypes = [vp, C.c_int, ip, ip, ip]
+        L.mg_autotune.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.mg_last_error.argtypes = [vp]
         L.mg_last_error.restype = C.c_char_p
         _lib = L
@@ -81,7 +85,7 @@ def exported_symbols():
     return ["mg_plan_desc_default", "mg_plan_create", "mg_plan_destroy", "mg_plan_set_stream",
             "mg_solve", "mlmc_sample_batch", "mlmc_philox", "mlmc_field", "mlmc_acc_init",
             "mlmc_acc_add", "mlmc_acc_result", "mg_profile_enable", "mg_profile_read",
-            "mg_last_error"]
+            "mg_last_error", "mg_plan_set_option", "mg_set_tile", "mg_get_tile", "mg_autotune"]
 
 
 def _torch():
@@ -161,6 +165,25 @@ def mg_plan_destroy(plan: Plan):
 def mg_plan_set_stream(plan: Plan, stream=None):
     s = _current_stream() if stream is None else C.c_void_p(stream)
     return plan.check(lib().mg_plan_set_stream(plan.handle, s))
+
+
+def mg_plan_set_option(plan: Plan, name: str, value: int):
+    return plan.check(lib().mg_plan_set_option(plan.handle, name.encode(), int(value)))
+
+
+def mg_set_tile(plan: Plan, n: int, tj: int, tk: int, chunks: int = 1):
+    return plan.check(lib().mg_set_tile(plan.handle, n, tj, tk, chunks))
+
+
+def mg_get_tile(plan: Plan, n: int):
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    plan.check(lib().mg_get_tile(plan.handle, n, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def mg_autotune(plan: Plan, level: int, n_samples: int, reps: int = 5):
+    mg_plan_set_stream(plan)
+    return plan.check(lib().mg_autotune(plan.handle, level, n_samples, reps))
 
 
 def mg_solve(plan: Plan, n: int, k, f, u, tol: float = 0.0, fixed_cycles: int = 0):

@@ -1,12 +1,16 @@
 // Plan, batch workspace, batched V-cycle driver and the C ABI of libmlmcmg.
 //
-// A batch is a set of solves (one per grid of an MLMC sample: the level-l
-// solve and, for l > 0, the level-(l-1) solve of the same omega).  Every
-// multigrid level of every solve gets its own buffers; all grids of one size
-// form one device list, so each step of the V-cycle is one launch for the
+// A batch is a set of solves (for an MLMC sample: the level-l solve and, for
+// l > 0, the level-(l-1) solve of the same omega, Algorithm 1 step 1.a).
+// Every multigrid level of every solve owns its buffers; all grids of one
+// size form one device list, so each step of the V-cycle is one launch for the
 // whole batch.  Grids of different top sizes nest: a solve with a smaller top
 // grid starts its cycle when the larger ones reach its size (the cycles are
-// aligned at the coarsest grid), so every launch sees grids of one size only.
+// aligned at the coarsest grid), so a launch only ever sees grids of one size.
+//
+// Work runs on a private stream of the plan (so it can be captured into HIP
+// graphs); it is ordered after the caller's stream at the start of each call
+// and every call synchronises before returning.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,20 +33,21 @@ struct HipError {
   const char* what;
 };
 
-#define CK(x)                                   \
-  do {                                          \
-    hipError_t e_ = (x);                        \
+#define CK(x)                                     \
+  do {                                            \
+    hipError_t e_ = (x);                          \
     if (e_ != hipSuccess) throw HipError{e_, #x}; \
   } while (0)
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-struct Level {
+template <typename T>
+struct LevelT {
   int n = 0;
-  double* u[2] = {nullptr, nullptr};
-  double* wh = nullptr;
-  double* b = nullptr;
-  double* r = nullptr;
+  T* u[2] = {nullptr, nullptr};
+  T* wh = nullptr;
+  T* b = nullptr;
+  T* r = nullptr;
 };
 
 struct BatchSpec {
@@ -50,51 +55,71 @@ struct BatchSpec {
   std::vector<int> share;   // solve whose levels 1.. supply this solve's wh (or -1)
   bool const_b_top = true;  // top right-hand side is the constant h^2 (f = 1)
   bool ext_u_top = false;   // top u is caller memory (mg_solve)
+  bool mixed = false;       // FP32 inner cycles inside FP64 defect correction
   std::string key() const {
     std::string s = const_b_top ? "c" : "v";
     s += ext_u_top ? "e" : "i";
-    for (size_t i = 0; i < top_n.size(); ++i) s += ":" + std::to_string(top_n[i]) + "/" + std::to_string(share[i]);
+    s += mixed ? "m" : "d";
+    for (size_t i = 0; i < top_n.size(); ++i)
+      s += ":" + std::to_string(top_n[i]) + "/" + std::to_string(share[i]);
     return s;
   }
+};
+
+template <typename T>
+struct Lists {
+  std::vector<std::vector<GridDescT<T>>> h;  // per size index
+  std::vector<GridDescT<T>*> d;
+  std::vector<std::vector<GridDescT<T>>> htop;  // per top size index
+  std::vector<GridDescT<T>*> dtop;
 };
 
 struct Batch {
   BatchSpec spec;
   int ns = 0;
-  std::vector<std::vector<Level>> lev;  // [solve][mg level]
-  std::vector<int> sizes;               // distinct grid sizes, descending (ends with 3)
-  std::vector<std::vector<GridDesc>> h_lists;
-  std::vector<GridDesc*> d_lists;
-  std::vector<int> top_sizes;           // distinct top sizes
-  std::vector<std::vector<GridDesc>> h_top;
-  std::vector<GridDesc*> d_top;
+  std::vector<std::vector<LevelT<double>>> lev;    // [solve][mg level]
+  std::vector<std::vector<LevelT<float>>> lev32;   // mixed precision only
+  std::vector<int> sizes;                          // distinct grid sizes, descending
+  std::vector<int> top_sizes;                      // distinct top sizes, descending
+  Lists<double> L64;
+  Lists<float> L32;
   SolveState ss{};
   int* d_count = nullptr;
-  int* h_count = nullptr;               // pinned
+  int* d_cycle = nullptr;                          // device cycle counter
+  int* h_count = nullptr;                          // pinned
   // MLMC sample plumbing
   int nsamples = 0;
   uint64_t* d_seeds = nullptr;
   double* d_normals = nullptr;
   int* d_fi = nullptr;
   int* d_ci = nullptr;
-  double** d_field_out = nullptr;       // top wh of the solves that own a field
+  double** d_field_out = nullptr;
   int* d_xi_index = nullptr;
-  int field_count = 0;
-  int field_n = 0;
-  // coefficient injection, per fine size (descending): pointer lists of the
-  // grids that own their wh and of their coarse children
+  // coefficient injection per fine size, and FP32 conversion per size
   std::vector<double**> d_inj_src, d_inj_dst;
   std::vector<int> inj_n, inj_count;
+  std::vector<double**> d_cvt_src;
+  std::vector<float**> d_cvt_dst;
+  std::vector<int> cvt_n, cvt_count;
+  bool uploaded = false;
+  // graphs of c consecutive cycles
+  std::map<int, hipGraphExec_t> graphs;
+  int last_cycles = 0;
   void* mem = nullptr;
   size_t bytes = 0;
-  std::vector<void*> extra;  // small device allocations owned by the batch
+  std::vector<void*> extra;
   void* dalloc(size_t bytes) {
     void* p = nullptr;
     CK(hipMalloc(&p, bytes));
     extra.push_back(p);
     return p;
   }
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
   ~Batch() {
+    drop_graphs();
     for (void* p : extra) (void)hipFree(p);
     if (mem) (void)hipFree(mem);
     if (h_count) (void)hipHostFree(h_count);
@@ -122,13 +147,19 @@ using namespace mg;
 
 struct mg_plan_s {
   mg_plan_desc desc{};
-  hipStream_t stream = nullptr;
+  hipStream_t caller = nullptr;  // stream the caller's data is ordered on
+  hipStream_t work = nullptr;    // the plan's own stream (default priority)
+  hipEvent_t order_ev = nullptr;
   std::string err;
   double omega[4]{}, theta[4]{}, scale[4]{};
   double* d_coef = nullptr;
   std::map<int, double*> d_phi;
   std::unique_ptr<Batch> batch;
   std::string batch_key;
+  // options
+  int smoother = 0;      // 0: fused single-pass sweep, 1: two-pass colour sweeps
+  int use_graph = 1;     // capture cycles into HIP graphs (mlmc_sample_batch)
+  std::map<int, SweepShape> shape;  // tile shape per grid size
   // profiling of the finest-grid smoothing launches
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -136,22 +167,29 @@ struct mg_plan_s {
   long long prof_launches = 0;
   double prof_ms = 0.0;
   double prof_nodes = 0.0;
-  // mg_solve workspace for the caller's problem
-  double* s_wh = nullptr;
-  double* s_b = nullptr;
-  int s_n = 0;
 
   ~mg_plan_s() {
     batch.reset();
     for (auto& kv : d_phi) (void)hipFree(kv.second);
     if (d_coef) (void)hipFree(d_coef);
-    if (s_wh) (void)hipFree(s_wh);
-    if (s_b) (void)hipFree(s_b);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
+    if (order_ev) (void)hipEventDestroy(order_ev);
+    if (work) (void)hipStreamDestroy(work);
   }
 };
 
 namespace mg {
+
+static SweepShape shape_for(mg_plan_s* P, int n) {
+  auto it = P->shape.find(n);
+  return it != P->shape.end() ? it->second : default_sweep_shape(n);
+}
+
+// Order the plan's stream after everything queued so far on the caller's.
+static void order_after_caller(mg_plan_s* P) {
+  CK(hipEventRecord(P->order_ev, P->caller));
+  CK(hipStreamWaitEvent(P->work, P->order_ev, 0));
+}
 
 static const double* phi_table(mg_plan_s* P, int n) {
   auto it = P->d_phi.find(n);
@@ -165,172 +203,219 @@ static const double* phi_table(mg_plan_s* P, int n) {
   return d;
 }
 
-// Allocate and describe a batch.  One device allocation holds every buffer.
+// Allocate a batch.  One device allocation holds every grid buffer.
 static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec) {
   auto B = std::make_unique<Batch>();
   B->spec = spec;
   const int ns = (int)spec.top_n.size();
   B->ns = ns;
   B->lev.resize(ns);
-  // pass 1: sizes
+  if (spec.mixed) B->lev32.resize(ns);
   size_t total = 0;
-  auto add = [&](size_t bytes) { total += align256(bytes); };
-  for (int s = 0; s < ns; ++s) {
-    const auto h = hierarchy(spec.top_n[s]);
-    for (size_t j = 0; j < h.size(); ++j) {
-      const size_t N = (size_t)h[j] * h[j] * h[j] * sizeof(double);
-      if (!(j == 0 && spec.ext_u_top)) add(N);        // u0
-      if (spec.share[s] < 0) add(N);                  // wh
-      if (!(j == 0 && spec.const_b_top)) add(N);      // b
-      if (h[j] > 3) add(N);                           // r
+  char* cur = nullptr;
+  // pass 0 sizes the allocation, pass 1 carves it
+  for (int pass = 0; pass < 2; ++pass) {
+    auto take = [&](size_t bytes) -> void* {
+      if (pass == 0) {
+        total += align256(bytes);
+        return nullptr;
+      }
+      void* p = cur;
+      cur += align256(bytes);
+      return p;
+    };
+    for (int s = 0; s < ns; ++s) {
+      const auto h = hierarchy(spec.top_n[s]);
+      B->lev[s].assign(h.size(), LevelT<double>{});
+      if (spec.mixed) B->lev32[s].assign(h.size(), LevelT<float>{});
+      for (size_t j = 0; j < h.size(); ++j) {
+        const size_t N = (size_t)h[j] * h[j] * h[j];
+        auto& L = B->lev[s][j];
+        L.n = h[j];
+        const bool top = j == 0;
+        if (spec.share[s] < 0) L.wh = (double*)take(N * 8);
+        else if (pass == 1) L.wh = B->lev[spec.share[s]][j + 1].wh;
+        if (!spec.mixed) {
+          if (!(top && spec.ext_u_top)) L.u[0] = (double*)take(N * 8);
+          L.u[1] = (double*)take(N * 8);
+          if (!(top && spec.const_b_top)) L.b = (double*)take(N * 8);
+          if (h[j] > 3) L.r = (double*)take(N * 8);
+        } else {
+          if (top && !spec.ext_u_top) L.u[0] = (double*)take(N * 8);
+          if (top && !spec.const_b_top) L.b = (double*)take(N * 8);
+          auto& F = B->lev32[s][j];
+          F.n = h[j];
+          F.u[0] = (float*)take(N * 4);
+          F.u[1] = (float*)take(N * 4);
+          if (spec.share[s] < 0) F.wh = (float*)take(N * 4);
+          else if (pass == 1) F.wh = B->lev32[spec.share[s]][j + 1].wh;
+          F.b = (float*)take(N * 4);
+          if (h[j] > 3) F.r = (float*)take(N * 4);
+        }
+      }
+    }
+    int npart = 0;
+    for (int s = 0; s < ns; ++s) npart += reduce_blocks(spec.top_n[s]);
+    int* ai = (int*)take(sizeof(int) * (ns * 2 + 2));
+    double* dd = (double*)take(sizeof(double) * ns * 3);
+    double* pp = (double*)take(sizeof(double) * npart);
+    if (pass == 0) {
+      if (P->desc.hbm_budget && total > P->desc.hbm_budget) return nullptr;
+      CK(hipMalloc(&B->mem, total));
+      // zero boundaries and state once; later kernels only write interiors
+      CK(hipMemsetAsync(B->mem, 0, total, P->work));
+      B->bytes = total;
+      cur = (char*)B->mem;
+    } else {
+      B->ss.active = ai;
+      B->ss.cycles = ai + ns;
+      B->d_count = ai + 2 * ns;
+      B->d_cycle = ai + 2 * ns + 1;
+      B->ss.relres = dd;
+      B->ss.bnorm = dd + ns;
+      B->ss.q = dd + 2 * ns;
+      B->ss.partials = pp;
     }
   }
-  int npart = 0;
-  for (int s = 0; s < ns; ++s) npart += reduce_blocks(spec.top_n[s]);
-  add(sizeof(int) * ns * 2);      // active, cycles
-  add(sizeof(double) * ns * 3);   // relres, bnorm, q
-  add(sizeof(double) * npart);
-  add(sizeof(int));               // count
-  if (P->desc.hbm_budget && total > P->desc.hbm_budget) return nullptr;
-  CK(hipMalloc(&B->mem, total));
-  CK(hipMemsetAsync(B->mem, 0, total, P->stream));
-  B->bytes = total;
-  char* cur = (char*)B->mem;
-  auto take = [&](size_t bytes) {
-    void* p = cur;
-    cur += align256(bytes);
-    return p;
-  };
-  // pass 2: carve (solves whose wh is shared must come after their parent)
-  for (int s = 0; s < ns; ++s) {
-    const auto h = hierarchy(spec.top_n[s]);
-    B->lev[s].resize(h.size());
-    for (size_t j = 0; j < h.size(); ++j) {
-      Level& L = B->lev[s][j];
-      L.n = h[j];
-      const size_t N = (size_t)h[j] * h[j] * h[j] * sizeof(double);
-      if (!(j == 0 && spec.ext_u_top)) L.u[0] = (double*)take(N);
-      if (spec.share[s] < 0) L.wh = (double*)take(N);
-      else L.wh = B->lev[spec.share[s]][j + 1].wh;
-      if (!(j == 0 && spec.const_b_top)) L.b = (double*)take(N);
-      if (h[j] > 3) L.r = (double*)take(N);
-    }
-  }
-  B->ss.active = (int*)take(sizeof(int) * ns * 2);
-  B->ss.cycles = B->ss.active + ns;
-  double* dd = (double*)take(sizeof(double) * ns * 3);
-  B->ss.relres = dd;
-  B->ss.bnorm = dd + ns;
-  B->ss.q = dd + 2 * ns;
-  B->ss.partials = (double*)take(sizeof(double) * npart);
-  B->d_count = (int*)take(sizeof(int));
   CK(hipHostMalloc((void**)&B->h_count, sizeof(int), hipHostMallocDefault));
-  // lists per size
   int nmax = 0;
   for (int n : spec.top_n) nmax = std::max(nmax, n);
   B->sizes = hierarchy(nmax);
-  B->h_lists.assign(B->sizes.size(), {});
-  for (int s = 0; s < ns; ++s) {
-    for (auto& L : B->lev[s]) {
-      const size_t si = std::find(B->sizes.begin(), B->sizes.end(), L.n) - B->sizes.begin();
-      B->h_lists[si].push_back(GridDesc{});
-    }
-  }
-  // top groups
   for (int s = 0; s < ns; ++s)
     if (std::find(B->top_sizes.begin(), B->top_sizes.end(), spec.top_n[s]) == B->top_sizes.end())
       B->top_sizes.push_back(spec.top_n[s]);
   std::sort(B->top_sizes.begin(), B->top_sizes.end(), std::greater<int>());
-  B->h_top.assign(B->top_sizes.size(), {});
   return B;
+}
+
+static size_t size_index(const std::vector<int>& v, int n) {
+  return std::find(v.begin(), v.end(), n) - v.begin();
+}
+
+template <typename T>
+static GridDescT<T> make_desc(const std::vector<LevelT<T>>& lv, size_t j, int solve, int poff) {
+  const LevelT<T>& L = lv[j];
+  GridDescT<T> d{};
+  d.u[0] = L.u[0];
+  d.u[1] = L.u[1];
+  d.wh = L.wh;
+  d.b = L.b;
+  d.r = L.r;
+  if (j + 1 < lv.size()) {
+    d.uc[0] = lv[j + 1].u[0];
+    d.uc[1] = lv[j + 1].u[1];
+    d.bc = lv[j + 1].b;
+  }
+  const double h = 1.0 / (double)(L.n - 1);
+  d.bconst = h * h;  // f = 1
+  d.solve = solve;
+  d.n = L.n;
+  d.poff = poff;
+  return d;
+}
+
+template <typename T>
+static void upload(Batch* B, Lists<T>& Ls, hipStream_t st) {
+  size_t cnt = 0;
+  for (auto& v : Ls.h) cnt += v.size();
+  for (auto& v : Ls.htop) cnt += v.size();
+  if (Ls.d.empty()) {
+    GridDescT<T>* base = (GridDescT<T>*)B->dalloc(sizeof(GridDescT<T>) * std::max<size_t>(cnt, 1));
+    size_t off = 0;
+    for (auto& v : Ls.h) { Ls.d.push_back(base + off); off += v.size(); }
+    for (auto& v : Ls.htop) { Ls.dtop.push_back(base + off); off += v.size(); }
+  }
+  for (size_t i = 0; i < Ls.h.size(); ++i)
+    if (!Ls.h[i].empty())
+      CK(hipMemcpyAsync(Ls.d[i], Ls.h[i].data(), sizeof(GridDescT<T>) * Ls.h[i].size(),
+                        hipMemcpyHostToDevice, st));
+  for (size_t i = 0; i < Ls.htop.size(); ++i)
+    if (!Ls.htop[i].empty())
+      CK(hipMemcpyAsync(Ls.dtop[i], Ls.htop[i].data(), sizeof(GridDescT<T>) * Ls.htop[i].size(),
+                        hipMemcpyHostToDevice, st));
 }
 
 // (Re)write the device descriptor lists from the current buffers.
 static void upload_lists(mg_plan_s* P, Batch* B) {
   const auto& spec = B->spec;
-  for (auto& v : B->h_lists) v.clear();
-  for (auto& v : B->h_top) v.clear();
+  B->L64.h.assign(B->sizes.size(), {});
+  B->L64.htop.assign(B->top_sizes.size(), {});
+  B->L32.h.assign(spec.mixed ? B->sizes.size() : 0, {});
+  B->L32.htop.assign(spec.mixed ? B->top_sizes.size() : 0, {});
   int poff = 0;
-  std::vector<int> poffs(B->ns);
   for (int s = 0; s < B->ns; ++s) {
-    poffs[s] = poff;
-    poff += reduce_blocks(spec.top_n[s]);
-  }
-  for (int s = 0; s < B->ns; ++s) {
-    auto& lv = B->lev[s];
+    const auto& lv = B->lev[s];
     for (size_t j = 0; j < lv.size(); ++j) {
-      const Level& L = lv[j];
-      GridDesc d{};
-      d.u[0] = L.u[0];
-      d.u[1] = L.u[1];
-      d.wh = L.wh;
-      d.b = L.b;
-      d.r = L.r;
-      if (j + 1 < lv.size()) {
-        d.uc = lv[j + 1].u[0];
-        d.bc = lv[j + 1].b;
-      }
-      const double h = 1.0 / (double)(L.n - 1);
-      d.bconst = h * h;  // f = 1
-      d.solve = s;
-      d.n = L.n;
-      d.poff = (j == 0) ? poffs[s] : 0;
-      const size_t si = std::find(B->sizes.begin(), B->sizes.end(), L.n) - B->sizes.begin();
-      B->h_lists[si].push_back(d);
+      const size_t si = size_index(B->sizes, lv[j].n);
+      const GridDesc d = make_desc(lv, j, s, j == 0 ? poff : 0);
+      B->L64.h[si].push_back(d);
+      if (spec.mixed) B->L32.h[si].push_back(make_desc(B->lev32[s], j, s, j == 0 ? poff : 0));
       if (j == 0) {
-        const size_t ti =
-            std::find(B->top_sizes.begin(), B->top_sizes.end(), L.n) - B->top_sizes.begin();
-        B->h_top[ti].push_back(d);
+        const size_t ti = size_index(B->top_sizes, lv[j].n);
+        B->L64.htop[ti].push_back(d);
+        if (spec.mixed) B->L32.htop[ti].push_back(make_desc(B->lev32[s], j, s, poff));
       }
     }
+    poff += reduce_blocks(spec.top_n[s]);
   }
-  // one device block for all lists (kept inside the batch allocation would
-  // complicate sizing; a separate small allocation is made once)
-  size_t cnt = 0;
-  for (auto& v : B->h_lists) cnt += v.size();
-  for (auto& v : B->h_top) cnt += v.size();
-  if (B->d_lists.empty()) {
-    GridDesc* base = (GridDesc*)B->dalloc(sizeof(GridDesc) * cnt);
-    size_t off = 0;
-    for (auto& v : B->h_lists) { B->d_lists.push_back(base + off); off += v.size(); }
-    for (auto& v : B->h_top) { B->d_top.push_back(base + off); off += v.size(); }
-    // injection lists: every grid that owns its wh feeds its coarse child
-    for (size_t si = 0; si + 1 < B->sizes.size(); ++si) {
-      std::vector<double*> src, dst;
+  upload(B, B->L64, P->work);
+  if (spec.mixed) upload(B, B->L32, P->work);
+  if (!B->uploaded) {
+    // coefficient injection (every grid that owns its wh feeds its coarse child)
+    // and, for mixed precision, the FP32 copies of every owned wh
+    for (size_t si = 0; si < B->sizes.size(); ++si) {
+      std::vector<double*> src, dst, csrc;
+      std::vector<float*> cdst;
       for (int s = 0; s < B->ns; ++s) {
         if (spec.share[s] >= 0) continue;
         const auto& lv = B->lev[s];
-        for (size_t j = 0; j + 1 < lv.size(); ++j)
-          if (lv[j].n == B->sizes[si]) {
+        for (size_t j = 0; j < lv.size(); ++j) {
+          if (lv[j].n != B->sizes[si]) continue;
+          if (j + 1 < lv.size()) {
             src.push_back(lv[j].wh);
             dst.push_back(lv[j + 1].wh);
           }
+          if (spec.mixed) {
+            csrc.push_back(lv[j].wh);
+            cdst.push_back(B->lev32[s][j].wh);
+          }
+        }
       }
-      if (src.empty()) continue;
-      double** ds = (double**)B->dalloc(sizeof(double*) * src.size());
-      double** dd = (double**)B->dalloc(sizeof(double*) * dst.size());
-      CK(hipMemcpy(ds, src.data(), sizeof(double*) * src.size(), hipMemcpyHostToDevice));
-      CK(hipMemcpy(dd, dst.data(), sizeof(double*) * dst.size(), hipMemcpyHostToDevice));
-      B->d_inj_src.push_back(ds);
-      B->d_inj_dst.push_back(dd);
-      B->inj_n.push_back(B->sizes[si]);
-      B->inj_count.push_back((int)src.size());
+      if (!src.empty()) {
+        double** ds = (double**)B->dalloc(sizeof(double*) * src.size());
+        double** dd = (double**)B->dalloc(sizeof(double*) * dst.size());
+        CK(hipMemcpyAsync(ds, src.data(), sizeof(double*) * src.size(), hipMemcpyHostToDevice, P->work));
+        CK(hipMemcpyAsync(dd, dst.data(), sizeof(double*) * dst.size(), hipMemcpyHostToDevice, P->work));
+        B->d_inj_src.push_back(ds);
+        B->d_inj_dst.push_back(dd);
+        B->inj_n.push_back(B->sizes[si]);
+        B->inj_count.push_back((int)src.size());
+      }
+      if (!csrc.empty()) {
+        double** ds = (double**)B->dalloc(sizeof(double*) * csrc.size());
+        float** dd = (float**)B->dalloc(sizeof(float*) * cdst.size());
+        CK(hipMemcpyAsync(ds, csrc.data(), sizeof(double*) * csrc.size(), hipMemcpyHostToDevice, P->work));
+        CK(hipMemcpyAsync(dd, cdst.data(), sizeof(float*) * cdst.size(), hipMemcpyHostToDevice, P->work));
+        B->d_cvt_src.push_back(ds);
+        B->d_cvt_dst.push_back(dd);
+        B->cvt_n.push_back(B->sizes[si]);
+        B->cvt_count.push_back((int)csrc.size());
+      }
     }
+    B->uploaded = true;
   }
-  for (size_t i = 0; i < B->h_lists.size(); ++i)
-    CK(hipMemcpyAsync(B->d_lists[i], B->h_lists[i].data(), sizeof(GridDesc) * B->h_lists[i].size(),
-                      hipMemcpyHostToDevice, P->stream));
-  for (size_t i = 0; i < B->h_top.size(); ++i)
-    CK(hipMemcpyAsync(B->d_top[i], B->h_top[i].data(), sizeof(GridDesc) * B->h_top[i].size(),
-                      hipMemcpyHostToDevice, P->stream));
-  CK(hipStreamSynchronize(P->stream));
+  CK(hipStreamSynchronize(P->work));
 }
 
-// Coarse-grid coefficients by injection, finest size first.
-static void inject_all(mg_plan_s* P, Batch* B) {
+// Coarse-grid coefficients by injection (finest size first), then the FP32
+// copies for mixed precision.
+static void prepare_coefficients(mg_plan_s* P, Batch* B) {
   for (size_t j = 0; j < B->inj_n.size(); ++j)
     launch_inject(B->inj_n[j], B->inj_count[j], (const double* const*)B->d_inj_src[j],
-                  B->d_inj_dst[j], P->stream);
+                  B->d_inj_dst[j], P->work);
+  for (size_t j = 0; j < B->cvt_n.size(); ++j)
+    launch_to_float(B->cvt_n[j], B->cvt_count[j], (const double* const*)B->d_cvt_src[j],
+                    B->d_cvt_dst[j], P->work);
 }
 
 static hipEvent_t next_event(mg_plan_s* P) {
@@ -344,7 +429,7 @@ static hipEvent_t next_event(mg_plan_s* P) {
 
 static void collect_profile(mg_plan_s* P) {
   if (P->ev_used == 0) return;
-  CK(hipStreamSynchronize(P->stream));
+  CK(hipStreamSynchronize(P->work));
   for (size_t i = 0; i + 1 < P->ev_used; i += 2) {
     float ms = 0.f;
     CK(hipEventElapsedTime(&ms, P->ev_pool[i], P->ev_pool[i + 1]));
@@ -354,71 +439,148 @@ static void collect_profile(mg_plan_s* P) {
   P->ev_used = 0;
 }
 
-static void smooth(mg_plan_s* P, Batch* B, size_t si, int sweeps) {
+// One red-black sweep on the grids of size index si; returns the new buffer.
+template <typename T>
+static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf, int cbuf,
+                       bool timed) {
   const int n = B->sizes[si];
-  const int cnt = (int)B->h_lists[si].size();
-  const bool timed = P->prof && si == 0;
-  for (int s = 0; s < sweeps; ++s) {
-    for (int colour = 0; colour < 2; ++colour) {
-      if (timed) {
-        if (P->ev_used + 2 > 4096) collect_profile(P);
-        CK(hipEventRecord(next_event(P), P->stream));
-      }
-      launch_rbgs_colour(B->d_lists[si], cnt, n, B->ss.active, colour, 0, P->stream);
-      if (timed) {
-        CK(hipEventRecord(next_event(P), P->stream));
-        P->prof_nodes = (double)cnt * (double)(n - 2) * (n - 2) * (n - 2);
-      }
-    }
+  const int cnt = (int)Ls.h[si].size();
+  hipStream_t st = P->work;
+  if (timed) {
+    if (P->ev_used + 4 > 8192) collect_profile(P);
+    CK(hipEventRecord(next_event(P), st));
   }
+  int out = buf;
+  if (P->smoother == 0) {
+    launch_sweep<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, shape_for(P, n), st);
+    out = 1 - buf;
+  } else {
+    if (cbuf >= 0) launch_prolong<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, st);
+    launch_rbgs_colour<T>(Ls.d[si], cnt, n, B->ss.active, 0, buf, st);
+    launch_rbgs_colour<T>(Ls.d[si], cnt, n, B->ss.active, 1, buf, st);
+  }
+  if (timed) {
+    CK(hipEventRecord(next_event(P), st));
+    P->prof_nodes = (double)cnt * (double)(n - 2) * (n - 2) * (n - 2);
+  }
+  return out;
 }
 
-// One V(nu1,nu2) cycle for every active solve of the batch.
-static void run_cycle(mg_plan_s* P, Batch* B) {
+// One V(nu1,nu2) cycle on every active solve.  Each level starts in buffer 0
+// (the iterate of a top grid, the zero guess of a coarse one); returns the
+// buffer that holds the top grids' iterates afterwards.
+template <typename T>
+static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
   const int nu1 = P->desc.nu1, nu2 = P->desc.nu2;
   const size_t L = B->sizes.size();
-  hipStream_t st = P->stream;
+  hipStream_t st = P->work;
+  std::vector<int> cur(L, 0);
   for (size_t si = 0; si < L; ++si) {
     const int n = B->sizes[si];
-    const int cnt = (int)B->h_lists[si].size();
+    const int cnt = (int)Ls.h[si].size();
     if (n == 3) {
-      launch_coarsest(B->d_lists[si], cnt, B->ss.active, st);
+      launch_coarsest<T>(Ls.d[si], cnt, B->ss.active, st);
       continue;
     }
-    smooth(P, B, si, nu1);
-    launch_residual(B->d_lists[si], cnt, n, B->ss.active, 0, st);
-    launch_restrict(B->d_lists[si], cnt, n, B->ss.active, st);
+    for (int s = 0; s < nu1; ++s)
+      cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0);
+    launch_residual<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);
+    launch_restrict<T>(Ls.d[si], cnt, n, B->ss.active, st);
   }
   for (size_t si = L - 1; si-- > 0;) {
     const int n = B->sizes[si];
-    const int cnt = (int)B->h_lists[si].size();
-    launch_prolong(B->d_lists[si], cnt, n, B->ss.active, 0, st);
-    smooth(P, B, si, nu2);
+    const int cnt = (int)Ls.h[si].size();
+    const int cbuf = cur[si + 1];
+    if (nu2 == 0) {
+      launch_prolong<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], cbuf, st);
+      continue;
+    }
+    cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], cbuf, P->prof && si == 0);
+    for (int s = 1; s < nu2; ++s)
+      cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0);
+  }
+  return cur[0];
+}
+
+void launch_tick(int* ctr, hipStream_t st);
+void launch_init_state2(int* active, int* cycles, int* cycle_ctr, int ns, hipStream_t st);
+void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
+                      const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
+                      hipStream_t st);
+
+// One outer iteration for every active solve (recorded into graphs as is).
+static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed) {
+  hipStream_t st = P->work;
+  launch_tick(B->d_cycle, st);
+  if (!B->spec.mixed) {
+    const int out = run_cycle<double>(P, B, B->L64);
+    if (out != 0)  // odd sweep count: bring the top iterates back to buffer 0
+      for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
+        launch_copy_buf<double>(B->L64.dtop[ti], (int)B->L64.htop[ti].size(), B->top_sizes[ti],
+                                B->ss.active, 1, st);
+    for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+      const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+      launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_RESID, B->ss.partials, st);
+      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, 0, fixed,
+                       P->desc.max_cycles, tol, st);
+    }
+  } else {
+    // defect of the current iterate (this also decides convergence of the
+    // previous outer step), one FP32 V-cycle, FP64 update
+    for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+      const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+      launch_defect(B->L64.dtop[ti], B->L32.dtop[ti], cnt, n, B->ss.active, B->ss.partials, st);
+      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, 1, fixed,
+                       P->desc.max_cycles, tol, st);
+    }
+    const int out = run_cycle<float>(P, B, B->L32);
+    for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
+      launch_correct(B->L64.dtop[ti], B->L32.dtop[ti], (int)B->L64.htop[ti].size(),
+                     B->top_sizes[ti], B->ss.active, out, st);
   }
 }
 
-static void reduce_tops(mg_plan_s* P, Batch* B, int mode, int cycle, int fixed, double tol) {
-  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
-    const int n = B->top_sizes[ti];
-    const int cnt = (int)B->h_top[ti].size();
-    launch_reduce(B->d_top[ti], cnt, n, B->ss.active, 0, mode, B->ss.partials, P->stream);
-    launch_finalize(B->d_top[ti], cnt, n, B->ss, mode, cycle, fixed, P->desc.max_cycles, tol,
-                    P->stream);
-  }
+static hipGraphExec_t graph_for(mg_plan_s* P, Batch* B, int c, double tol, int fixed) {
+  auto it = B->graphs.find(c);
+  if (it != B->graphs.end()) return it->second;
+  hipGraph_t g = nullptr;
+  CK(hipStreamBeginCapture(P->work, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < c; ++i) cycle_step(P, B, tol, fixed);
+  CK(hipStreamEndCapture(P->work, &g));
+  hipGraphExec_t ex = nullptr;
+  CK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  CK(hipGraphDestroy(g));
+  B->graphs[c] = ex;
+  return ex;
 }
 
-void launch_init_state(int* active, int* cycles, int ns, hipStream_t st);
-
-// Cycle all solves of the batch until each has converged (or run exactly
+// Cycle every solve of the batch until each has converged (or run exactly
 // fixed_cycles).  Returns true when every solve met tol.
-static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed_cycles) {
-  hipStream_t st = P->stream;
-  launch_init_state(B->ss.active, B->ss.cycles, B->ns, st);
-  reduce_tops(P, B, RED_BNORM, 0, fixed_cycles, tol);
-  const int limit = fixed_cycles > 0 ? fixed_cycles : P->desc.max_cycles;
-  for (int m = 1; m <= limit; ++m) {
-    run_cycle(P, B);
-    reduce_tops(P, B, RED_RESID, m, fixed_cycles, tol);
+static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graphs) {
+  hipStream_t st = P->work;
+  launch_init_state2(B->ss.active, B->ss.cycles, B->d_cycle, B->ns, st);
+  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_BNORM, B->ss.partials, st);
+    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, B->d_cycle, 0, fixed,
+                     P->desc.max_cycles, tol, st);
+  }
+  // mixed precision decides convergence one step late: one extra step
+  const int extra = B->spec.mixed ? 1 : 0;
+  const int limit = (fixed > 0 ? fixed : P->desc.max_cycles) + extra;
+  const bool use_graphs = graphs && P->use_graph && !P->prof;
+  int done = 0, maxc = 0;
+  while (done < limit) {
+    int c = 1;
+    if (use_graphs) {
+      // the first launch covers the cycles the last batch needed, less one
+      const int guess = fixed > 0 ? fixed + extra : B->last_cycles;
+      c = done == 0 ? std::max(1, std::min(limit, guess - 1)) : 1;
+      CK(hipGraphLaunch(graph_for(P, B, c, tol, fixed), st));
+    } else {
+      cycle_step(P, B, tol, fixed);
+    }
+    done += c;
     launch_count_active(B->ss.active, B->ns, B->d_count, st);
     CK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
@@ -427,9 +589,13 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed_cycles) {
   std::vector<int> cyc(B->ns);
   CK(hipMemcpyAsync(cyc.data(), B->ss.cycles, sizeof(int) * B->ns, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  for (int c : cyc)
-    if (c <= 0) return false;
-  return true;
+  bool ok = *B->h_count == 0;
+  for (int c : cyc) {
+    if (c < 0) ok = false;
+    maxc = std::max(maxc, c);
+  }
+  B->last_cycles = maxc + extra;
+  return ok;
 }
 
 static Batch* get_batch(mg_plan_s* P, const BatchSpec& spec, int* status) {
@@ -449,24 +615,80 @@ static Batch* get_batch(mg_plan_s* P, const BatchSpec& spec, int* status) {
   return P->batch.get();
 }
 
+static BatchSpec mlmc_spec(mg_plan_s* P, int level, int n_samples) {
+  const int nf = (P->desc.n0 - 1) * (1 << level) + 1;
+  const int nc = level > 0 ? (P->desc.n0 - 1) * (1 << (level - 1)) + 1 : 0;
+  BatchSpec spec;
+  for (int i = 0; i < n_samples; ++i) {
+    spec.top_n.push_back(nf);
+    spec.share.push_back(-1);
+    if (level > 0) {
+      spec.top_n.push_back(nc);
+      spec.share.push_back((int)spec.top_n.size() - 2);
+    }
+  }
+  spec.const_b_top = true;
+  spec.ext_u_top = false;
+  spec.mixed = P->desc.precision == MG_MIXED;
+  return spec;
+}
+
+// Fields, coefficient hierarchy and zero iterates for a batch of samples.
+static void setup_samples(mg_plan_s* P, Batch* B, int level, const uint64_t* seeds,
+                          int n_samples) {
+  hipStream_t st = P->work;
+  const int nf = (P->desc.n0 - 1) * (1 << level) + 1;
+  if (B->nsamples != n_samples) {
+    upload_lists(P, B);
+    B->nsamples = n_samples;
+    const int per = level > 0 ? 2 : 1;
+    B->d_seeds = (uint64_t*)B->dalloc(sizeof(uint64_t) * n_samples);
+    B->d_normals = (double*)B->dalloc(sizeof(double) * 64 * n_samples);
+    std::vector<int> fi(n_samples), ci(n_samples), xi(n_samples);
+    std::vector<double*> fo(n_samples);
+    for (int i = 0; i < n_samples; ++i) {
+      fi[i] = per * i;
+      ci[i] = level > 0 ? per * i + 1 : -1;
+      xi[i] = i;
+      fo[i] = B->lev[per * i][0].wh;
+    }
+    B->d_fi = (int*)B->dalloc(sizeof(int) * n_samples);
+    B->d_ci = (int*)B->dalloc(sizeof(int) * n_samples);
+    B->d_xi_index = (int*)B->dalloc(sizeof(int) * n_samples);
+    B->d_field_out = (double**)B->dalloc(sizeof(double*) * n_samples);
+    CK(hipMemcpy(B->d_fi, fi.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
+    CK(hipMemcpy(B->d_ci, ci.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
+    CK(hipMemcpy(B->d_xi_index, xi.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
+    CK(hipMemcpy(B->d_field_out, fo.data(), sizeof(double*) * n_samples, hipMemcpyHostToDevice));
+  }
+  CK(hipMemcpyAsync(B->d_seeds, seeds, sizeof(uint64_t) * n_samples, hipMemcpyHostToDevice, st));
+  launch_philox(B->d_seeds, n_samples, level, nullptr, B->d_normals, st);
+  launch_field(nf, n_samples, B->d_field_out, B->d_xi_index, B->d_normals, phi_table(P, nf),
+               P->d_coef, 0, st);
+  prepare_coefficients(P, B);
+  // every sample starts from the zero iterate (the workspace may hold the last batch)
+  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
+    launch_zero_u<double>(B->L64.dtop[ti], (int)B->L64.htop[ti].size(), B->top_sizes[ti], st);
+}
+
 }  // namespace mg
 
 // ============================== C ABI ==========================================
 
 #define API_BEGIN try {
-#define API_END(P)                                                                    \
-  }                                                                                   \
-  catch (const mg::HipError& he) {                                                    \
-    if (P) P->err = std::string(he.what) + ": " + hipGetErrorString(he.e);            \
-    return MG_EHIP;                                                                   \
-  }                                                                                   \
-  catch (const std::bad_alloc&) {                                                     \
-    if (P) P->err = "host allocation failed";                                         \
-    return MG_ENOMEM;                                                                 \
-  }                                                                                   \
-  catch (...) {                                                                       \
-    if (P) P->err = "unexpected error";                                               \
-    return MG_EHIP;                                                                   \
+#define API_END(P)                                                         \
+  }                                                                        \
+  catch (const mg::HipError& he) {                                         \
+    if (P) P->err = std::string(he.what) + ": " + hipGetErrorString(he.e); \
+    return MG_EHIP;                                                        \
+  }                                                                        \
+  catch (const std::bad_alloc&) {                                          \
+    if (P) P->err = "host allocation failed";                              \
+    return MG_ENOMEM;                                                      \
+  }                                                                        \
+  catch (...) {                                                            \
+    if (P) P->err = "unexpected error";                                    \
+    return MG_EHIP;                                                        \
   }
 
 extern "C" {
@@ -497,16 +719,18 @@ int mg_plan_create(const mg_plan_desc* desc, mg_plan* out) {
       (desc->precision != MG_FP64 && desc->precision != MG_MIXED))
     return MG_EINVAL;
   if (desc->kl_per_axis != 4) return MG_ENOTIMPL;
-  if ((long long)(desc->n0 - 1) * (1ll << desc->max_level) + 1 > 2049) return MG_EINVAL;
+  if ((long long)(desc->n0 - 1) * (1ll << desc->max_level) + 1 > 1025) return MG_EINVAL;
   mg_plan_s* P = new (std::nothrow) mg_plan_s();
   if (!P) return MG_ENOMEM;
   P->desc = *desc;
-  P->stream = (hipStream_t)desc->stream;
+  P->caller = (hipStream_t)desc->stream;
   try {
     if (!kl_1d_modes(desc->corr_len, 4, P->omega, P->theta, P->scale)) {
       delete P;
       return MG_EINVAL;
     }
+    CK(hipStreamCreateWithFlags(&P->work, hipStreamNonBlocking));
+    CK(hipEventCreateWithFlags(&P->order_ev, hipEventDisableTiming));
     double coef[64];
     const double sigma = std::sqrt(desc->sigma2);
     for (int a = 0; a < 4; ++a)
@@ -516,7 +740,7 @@ int mg_plan_create(const mg_plan_desc* desc, mg_plan* out) {
     CK(hipMalloc(&P->d_coef, sizeof(coef)));
     CK(hipMemcpy(P->d_coef, coef, sizeof(coef), hipMemcpyHostToDevice));
     for (int l = 0; l <= desc->max_level; ++l) phi_table(P, (desc->n0 - 1) * (1 << l) + 1);
-  } catch (const HipError& he) {
+  } catch (const HipError&) {
     delete P;
     return MG_EHIP;
   }
@@ -526,14 +750,53 @@ int mg_plan_create(const mg_plan_desc* desc, mg_plan* out) {
 
 int mg_plan_destroy(mg_plan P) {
   if (!P) return MG_EINVAL;
-  (void)hipStreamSynchronize(P->stream);
+  (void)hipStreamSynchronize(P->work);
   delete P;
   return MG_OK;
 }
 
 int mg_plan_set_stream(mg_plan P, void* stream) {
   if (!P) return MG_EINVAL;
-  P->stream = (hipStream_t)stream;
+  P->caller = (hipStream_t)stream;
+  return MG_OK;
+}
+
+int mg_plan_set_option(mg_plan P, const char* name, long long value) {
+  if (!P || !name) return MG_EINVAL;
+  const std::string k = name;
+  if (k == "smoother") {
+    if (value != 0 && value != 1) return MG_EINVAL;
+    P->smoother = (int)value;
+  } else if (k == "graph") {
+    P->use_graph = value != 0;
+  } else {
+    P->err = "unknown option " + k;
+    return MG_EINVAL;
+  }
+  if (P->batch) P->batch->drop_graphs();
+  return MG_OK;
+}
+
+int mg_set_tile(mg_plan P, int n, int tj, int tk, int chunks) {
+  if (!P) return MG_EINVAL;
+  SweepShape shapes[32];
+  const int c = sweep_shapes(n, shapes, 32);
+  for (int i = 0; i < c; ++i)
+    if (shapes[i].tj == tj && shapes[i].tk == tk && chunks >= 1 && chunks <= n - 2) {
+      P->shape[n] = SweepShape{tj, tk, chunks};
+      if (P->batch) P->batch->drop_graphs();
+      return MG_OK;
+    }
+  P->err = "mg_set_tile: no compiled tile shape for this grid size";
+  return MG_EINVAL;
+}
+
+int mg_get_tile(mg_plan P, int n, int* tj, int* tk, int* chunks) {
+  if (!P || !tj || !tk || !chunks) return MG_EINVAL;
+  const SweepShape s = shape_for(P, n);
+  *tj = s.tj;
+  *tk = s.tk;
+  *chunks = s.chunks;
   return MG_OK;
 }
 
@@ -557,21 +820,24 @@ int mg_solve(mg_plan P, int n, const double* k, const double* f, double* u, doub
   spec.share = {-1};
   spec.const_b_top = false;
   spec.ext_u_top = true;
+  spec.mixed = P->desc.precision == MG_MIXED;
   int status = MG_OK;
+  order_after_caller(P);
   Batch* B = get_batch(P, spec, &status);
   if (!B) return status;
-  // the caller's u is the top iterate; wh and b of the top grid live in the batch
-  B->lev[0][0].u[0] = u;
+  B->lev[0][0].u[0] = u;  // the caller's u is the top iterate
+  B->drop_graphs();
   upload_lists(P, B);
-  const Level& T = B->lev[0][0];
-  launch_prepare_problem(n, k, f, T.wh, T.b, u, P->stream);
-  inject_all(P, B);
-  const bool ok = run_solves(P, B, t, fixed_cycles);
+  const LevelT<double>& T = B->lev[0][0];
+  launch_prepare_problem(n, k, f, T.wh, T.b, u, P->work);
+  prepare_coefficients(P, B);
+  const bool ok = run_solves(P, B, t, fixed_cycles, false);
   int cyc = 0;
   double rel = 0.0;
   CK(hipMemcpy(&cyc, B->ss.cycles, sizeof(int), hipMemcpyDeviceToHost));
   CK(hipMemcpy(&rel, B->ss.relres, sizeof(double), hipMemcpyDeviceToHost));
-  if (cycles) *cycles = cyc > 0 ? cyc : P->desc.max_cycles;
+  if (P->prof) collect_profile(P);
+  if (cycles) *cycles = cyc >= 0 ? cyc : P->desc.max_cycles;
   if (relres) *relres = rel;
   if (!ok) {
     P->err = "mg_solve: tolerance not reached within max_cycles";
@@ -590,59 +856,19 @@ int mlmc_sample_batch(mg_plan P, int level, const uint64_t* seeds, int n_samples
     return MG_EINVAL;
   }
   API_BEGIN
-  const int nf = (P->desc.n0 - 1) * (1 << level) + 1;
-  const int nc = level > 0 ? (P->desc.n0 - 1) * (1 << (level - 1)) + 1 : 0;
-  BatchSpec spec;
-  for (int i = 0; i < n_samples; ++i) {
-    spec.top_n.push_back(nf);
-    spec.share.push_back(-1);
-    if (level > 0) {
-      spec.top_n.push_back(nc);
-      spec.share.push_back((int)spec.top_n.size() - 2);
-    }
-  }
-  spec.const_b_top = true;
-  spec.ext_u_top = false;
   int status = MG_OK;
-  const bool fresh = !P->batch || P->batch_key != spec.key();
-  Batch* B = get_batch(P, spec, &status);
+  order_after_caller(P);
+  Batch* B = get_batch(P, mlmc_spec(P, level, n_samples), &status);
   if (!B) return status;
-  hipStream_t st = P->stream;
-  if (fresh || B->nsamples != n_samples) {
-    upload_lists(P, B);
-    B->nsamples = n_samples;
-    const int per = level > 0 ? 2 : 1;
-    B->d_seeds = (uint64_t*)B->dalloc(sizeof(uint64_t) * n_samples);
-    B->d_normals = (double*)B->dalloc(sizeof(double) * 64 * n_samples);
-    std::vector<int> fi(n_samples), ci(n_samples), xi(n_samples);
-    std::vector<double*> fo(n_samples);
-    for (int i = 0; i < n_samples; ++i) {
-      fi[i] = per * i;
-      ci[i] = level > 0 ? per * i + 1 : -1;
-      xi[i] = i;
-      fo[i] = B->lev[per * i][0].wh;
-    }
-    B->d_fi = (int*)B->dalloc(sizeof(int) * n_samples);
-    B->d_ci = (int*)B->dalloc(sizeof(int) * n_samples);
-    B->d_xi_index = (int*)B->dalloc(sizeof(int) * n_samples);
-    B->d_field_out = (double**)B->dalloc(sizeof(double*) * n_samples);
-    CK(hipMemcpy(B->d_fi, fi.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
-    CK(hipMemcpy(B->d_ci, ci.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
-    CK(hipMemcpy(B->d_xi_index, xi.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
-    CK(hipMemcpy(B->d_field_out, fo.data(), sizeof(double*) * n_samples, hipMemcpyHostToDevice));
-    B->field_count = n_samples;
-    B->field_n = nf;
+  hipStream_t st = P->work;
+  setup_samples(P, B, level, seeds, n_samples);
+  if (fixed_cycles > 0) B->drop_graphs();  // graphs bake in the stopping mode
+  const bool ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0);
+  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_QOI, B->ss.partials, st);
+    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI, B->d_cycle, 0, 0, 0, 0.0, st);
   }
-  CK(hipMemcpyAsync(B->d_seeds, seeds, sizeof(uint64_t) * n_samples, hipMemcpyHostToDevice, st));
-  launch_philox(B->d_seeds, n_samples, level, nullptr, B->d_normals, st);
-  launch_field(nf, n_samples, B->d_field_out, B->d_xi_index, B->d_normals, phi_table(P, nf),
-               P->d_coef, 0, st);
-  inject_all(P, B);
-  // every sample starts from the zero iterate (the workspace may hold the last batch)
-  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
-    launch_zero_u(B->d_top[ti], (int)B->h_top[ti].size(), B->top_sizes[ti], st);
-  const bool ok = run_solves(P, B, P->desc.tol, fixed_cycles);
-  reduce_tops(P, B, RED_QOI, 0, 0, 0.0);
   launch_ydiff(B->ss.q, B->d_fi, B->d_ci, n_samples, Y_out, Qf_out, Qc_out, B->ss.cycles,
                cycles_out, st);
   CK(hipStreamSynchronize(st));
@@ -655,16 +881,78 @@ int mlmc_sample_batch(mg_plan P, int level, const uint64_t* seeds, int n_samples
   API_END(P)
 }
 
+int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
+  if (!P) return MG_EINVAL;
+  if (level < 0 || level > P->desc.max_level || n_samples < 1) return MG_EINVAL;
+  API_BEGIN
+  std::vector<uint64_t> seeds(n_samples);
+  for (int i = 0; i < n_samples; ++i) seeds[i] = 0x5eed0000ull + i;
+  double* d_y = nullptr;
+  CK(hipMalloc(&d_y, sizeof(double) * n_samples));
+  const int st = mlmc_sample_batch(P, level, seeds.data(), n_samples, d_y, nullptr, nullptr,
+                                   nullptr, 0);
+  CK(hipFree(d_y));
+  if (st != MG_OK && st != MG_ENOCONV) return st;
+  Batch* B = P->batch.get();
+  const bool mixed = B->spec.mixed;
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  reps = std::max(1, reps);
+  for (size_t si = 0; si < B->sizes.size(); ++si) {
+    const int n = B->sizes[si];
+    if (n < 5) continue;
+    SweepShape shapes[32];
+    const int c = sweep_shapes(n, shapes, 32);
+    double best = 1e30;
+    SweepShape pick = default_sweep_shape(n);
+    for (int i = 0; i < c; ++i)
+      for (int chunks : {1, 2, 4, 8}) {
+        if (chunks > 1 && (n - 2) / chunks < 4) continue;
+        SweepShape s = shapes[i];
+        s.chunks = chunks;
+        // every solve active while timing; the next batch reinitialises the workspace
+        launch_init_state2(B->ss.active, B->ss.cycles, B->d_cycle, B->ns, P->work);
+        auto one = [&]() {
+          if (mixed)
+            launch_sweep<float>(B->L32.d[si], (int)B->L32.h[si].size(), n, B->ss.active, 0, -1,
+                                s, P->work);
+          else
+            launch_sweep<double>(B->L64.d[si], (int)B->L64.h[si].size(), n, B->ss.active, 0, -1,
+                                 s, P->work);
+        };
+        one();
+        CK(hipEventRecord(e0, P->work));
+        for (int r = 0; r < reps; ++r) one();
+        CK(hipEventRecord(e1, P->work));
+        CK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          pick = s;
+        }
+      }
+    P->shape[n] = pick;
+  }
+  CK(hipEventDestroy(e0));
+  CK(hipEventDestroy(e1));
+  B->drop_graphs();
+  return MG_OK;
+  API_END(P)
+}
+
 int mlmc_philox(mg_plan P, const uint64_t* seeds, int n_samples, int level, uint32_t* words_out,
                 double* normals_out) {
   if (!P) return MG_EINVAL;
   if (!seeds || n_samples < 1 || level < 0 || (!words_out && !normals_out)) return MG_EINVAL;
   API_BEGIN
+  order_after_caller(P);
   uint64_t* d = nullptr;
   CK(hipMalloc(&d, sizeof(uint64_t) * n_samples));
-  CK(hipMemcpyAsync(d, seeds, sizeof(uint64_t) * n_samples, hipMemcpyHostToDevice, P->stream));
-  launch_philox(d, n_samples, level, words_out, normals_out, P->stream);
-  CK(hipStreamSynchronize(P->stream));
+  CK(hipMemcpyAsync(d, seeds, sizeof(uint64_t) * n_samples, hipMemcpyHostToDevice, P->work));
+  launch_philox(d, n_samples, level, words_out, normals_out, P->work);
+  CK(hipStreamSynchronize(P->work));
   CK(hipFree(d));
   return MG_OK;
   API_END(P)
@@ -674,6 +962,7 @@ int mlmc_field(mg_plan P, int n, uint64_t seed, int level, double* k_out) {
   if (!P) return MG_EINVAL;
   if (!valid_n(n) || n > 1025 || level < 0 || !k_out) return MG_EINVAL;
   API_BEGIN
+  order_after_caller(P);
   uint64_t* d_seed = nullptr;
   double* d_norm = nullptr;
   double** d_out = nullptr;
@@ -683,12 +972,12 @@ int mlmc_field(mg_plan P, int n, uint64_t seed, int level, double* k_out) {
   CK(hipMalloc(&d_out, sizeof(double*)));
   CK(hipMalloc(&d_xi, sizeof(int)));
   const int zero = 0;
-  CK(hipMemcpyAsync(d_seed, &seed, sizeof(uint64_t), hipMemcpyHostToDevice, P->stream));
-  CK(hipMemcpyAsync(d_out, &k_out, sizeof(double*), hipMemcpyHostToDevice, P->stream));
-  CK(hipMemcpyAsync(d_xi, &zero, sizeof(int), hipMemcpyHostToDevice, P->stream));
-  launch_philox(d_seed, 1, level, nullptr, d_norm, P->stream);
-  launch_field(n, 1, d_out, d_xi, d_norm, phi_table(P, n), P->d_coef, 1, P->stream);
-  CK(hipStreamSynchronize(P->stream));
+  CK(hipMemcpyAsync(d_seed, &seed, sizeof(uint64_t), hipMemcpyHostToDevice, P->work));
+  CK(hipMemcpyAsync(d_out, &k_out, sizeof(double*), hipMemcpyHostToDevice, P->work));
+  CK(hipMemcpyAsync(d_xi, &zero, sizeof(int), hipMemcpyHostToDevice, P->work));
+  launch_philox(d_seed, 1, level, nullptr, d_norm, P->work);
+  launch_field(n, 1, d_out, d_xi, d_norm, phi_table(P, n), P->d_coef, 1, P->work);
+  CK(hipStreamSynchronize(P->work));
   CK(hipFree(d_seed));
   CK(hipFree(d_norm));
   CK(hipFree(d_out));

@@ -1,8 +1,9 @@
 // Internal interfaces of libmlmcmg: device descriptors and kernel launchers.
 //
-// Storage: an n^3 vertex grid, z (k) fastest, boundary vertices included.
-// The coefficient is kept as wh = 1/(2k) per vertex, so the harmonic-mean face
-// coefficient 2 k_p k_q / (k_p + k_q) is the single reciprocal 1/(wh_p + wh_q).
+// Storage: an n^3 vertex grid, z (k) fastest, boundary vertices included,
+// n <= 1025 so every offset fits in 32 bits.  The coefficient is kept as
+// wh = 1/(2k) per vertex, so the harmonic-mean face coefficient
+// 2 k_p k_q / (k_p + k_q) is the single reciprocal 1/(wh_p + wh_q).
 // Right-hand sides are h^2-scaled: b' = h^2 f, so every level's operator is
 // (A'u)_p = D_p u_p - sum_q c_pq u_q with D_p = sum_q c_pq.
 #pragma once
@@ -14,84 +15,115 @@
 
 namespace mg {
 
-// One grid of one solve at one multigrid level.
-struct GridDesc {
-  double* u[2];       // iterate; u[1] is the second buffer of the out-of-place smoother
-  const double* wh;   // 1/(2k) at all n^3 vertices
-  double* b;          // h^2-scaled right-hand side, or nullptr for the constant bconst
-  double* r;          // residual scratch, n^3 (nullptr on the coarsest grid)
-  double* uc;         // u[0] of the next coarser grid of the same solve (nullptr on 3^3)
-  double* bc;         // b of the next coarser grid
-  float* u32;         // single-precision twins (mixed precision inner cycles)
-  const float* wh32;
-  float* b32;
-  float* r32;
-  float* uc32;
-  float* bc32;
-  double bconst;      // used when b == nullptr
-  int solve;          // owning solve: index into per-solve arrays
-  int n;              // vertices per axis
-  int poff;           // offset of this grid's reduction partials (top grids only)
+// One grid of one solve at one multigrid level, in precision T.
+template <typename T>
+struct GridDescT {
+  T* u[2];          // iterate: the smoother reads u[buf] and writes u[1-buf]
+  const T* wh;      // 1/(2k) at all n^3 vertices
+  T* b;             // h^2-scaled right-hand side, or nullptr for the constant bconst
+  T* r;             // residual scratch, n^3 (nullptr on 3^3)
+  T* uc[2];         // the coarser grid's iterate buffers (nullptr on 3^3)
+  T* bc;            // the coarser grid's right-hand side
+  double bconst;    // used when b == nullptr
+  int solve;        // owning solve: index into per-solve arrays
+  int n;            // vertices per axis
+  int poff;         // offset of this grid's reduction partials (top grids only)
   int pad_;
 };
+using GridDesc = GridDescT<double>;
+using GridDesc32 = GridDescT<float>;
 
 // Per-solve device state of a batch.
 struct SolveState {
-  int* active;        // 1 while the solve still cycles
-  int* cycles;        // cycles done when it stopped, -1 if it missed tol
-  double* relres;     // last relative residual
-  double* bnorm;      // ||b'||_2 (1 when b' = 0)
-  double* q;          // QoI of the solve's top grid
-  double* partials;   // reduction partials
+  int* active;      // 1 while the solve still cycles
+  int* cycles;      // cycles done when it stopped, -1 if it missed tol
+  double* relres;   // last relative residual
+  double* bnorm;    // ||b'||_2 (1 when b' = 0)
+  double* q;        // QoI of the solve's top grid
+  double* partials; // reduction partials
 };
 
 enum ReduceMode { RED_BNORM = 0, RED_RESID = 1, RED_QOI = 2 };
 
-// Reduction partial count of one grid of size n (256-thread blocks over the
-// interior vertices).
-__host__ __device__ inline int reduce_blocks(int n) {
-  const long m = n - 2;
-  return (int)((m * m * m + 255) / 256);
-}
+// Point kernels cover the interior (or, for the "full" kernels, every vertex)
+// with 256-thread blocks of 4 rows (j) x 64 columns (k) of one plane i.
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline int point_blocks(int m) { return m * ceil_div(m, 4) * ceil_div(m, 64); }
+// Reduction partial count of one grid of size n (one per interior block).
+__host__ __device__ inline int reduce_blocks(int n) { return point_blocks(n - 2); }
+
+// Tile shape of the fused smoother: TJ rows (j) x TK columns (k), streamed
+// over planes i in `chunks` pieces.
+struct SweepShape {
+  int tj, tk, chunks;
+};
+// Shapes with compiled kernels for grid size n (TJ, TK divide n-1).
+int sweep_shapes(int n, SweepShape* out, int max_out);
+SweepShape default_sweep_shape(int n);
 
 // ---- launchers (all asynchronous on `st`) --------------------------------
-// Random numbers and fields.
 void launch_philox(const uint64_t* d_seeds, int count, int level, uint32_t* d_words,
                    double* d_normals, hipStream_t st);
-// wh (mode 0) or k (mode 1) of the field sum_abc coef[abc] xi_s[abc] phi_a phi_b phi_c
-// on `count` grids of size n.  out[g] = destination of grid g, xi_index[g] = its
-// sample's row of d_normals.
+// wh (mode 0) or k (mode 1) of the KL field on `count` grids of size n.
 void launch_field(int n, int count, double* const* d_out, const int* d_xi_index,
                   const double* d_normals, const double* d_phi, const double* d_coef,
                   int mode, hipStream_t st);
 void launch_inject(int n_fine, int count, const double* const* d_fine, double* const* d_coarse,
                    hipStream_t st);
-// wh = 1/(2k) and b = h^2 f for a caller-supplied problem.
+// float copies of `count` arrays of n^3 doubles
+void launch_to_float(int n, int count, const double* const* d_src, float* const* d_dst,
+                     hipStream_t st);
+// wh = 1/(2k), b = h^2 f and a zero boundary for u, for a caller's problem.
 void launch_prepare_problem(int n, const double* k, const double* f, double* wh, double* b,
                             double* u, hipStream_t st);
 
-// Multigrid steps on a list of `count` grids of size n (device list).
-void launch_rbgs_colour(const GridDesc* d_list, int count, int n, const int* d_active,
+// Multigrid steps on a device list of `count` grids of size n.
+// The fused smoother: one red-black sweep from u[buf] into u[1-buf]; with
+// cbuf_prolong >= 0 the input is first corrected by the trilinear
+// interpolation of the coarse iterate uc[cbuf_prolong].
+template <typename T>
+void launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
+                  int cbuf_prolong, SweepShape shape, hipStream_t st);
+template <typename T>
+void launch_rbgs_colour(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                         int colour, int buf, hipStream_t st);
-void launch_residual(const GridDesc* d_list, int count, int n, const int* d_active, int buf,
+template <typename T>
+void launch_residual(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                      hipStream_t st);
-void launch_restrict(const GridDesc* d_list, int count, int n, const int* d_active,
+template <typename T>
+void launch_restrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                      hipStream_t st);
-void launch_coarsest(const GridDesc* d_list, int count, const int* d_active, hipStream_t st);
-void launch_prolong(const GridDesc* d_list, int count, int n, const int* d_active, int buf,
-                    hipStream_t st);
+template <typename T>
+void launch_coarsest(const GridDescT<T>* d_list, int count, const int* d_active, hipStream_t st);
+template <typename T>
+void launch_prolong(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
+                    int cbuf, hipStream_t st);
+template <typename T>
+void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_active, int from,
+                     hipStream_t st);
 // u[0] (and u[1] if present) = 0 on every vertex of the listed grids.
-void launch_zero_u(const GridDesc* d_list, int count, int n, hipStream_t st);
-void launch_copy_buf(const GridDesc* d_list, int count, int n, const int* d_active, int from,
-                     hipStream_t st);
+template <typename T>
+void launch_zero_u(const GridDescT<T>* d_list, int count, int n, hipStream_t st);
 
-// Reductions on the top grids of solves (list of `count` grids of size n).
+// Reductions on the top grids of solves.
 void launch_reduce(const GridDesc* d_list, int count, int n, const int* d_active, int buf,
                    int mode, double* d_partials, hipStream_t st);
-// Finalise per solve: modes as ReduceMode.  `cycle` is the cycle just done,
-// `fixed_cycles` > 0 selects fixed-count mode.
-void launch_finalize(const GridDesc* d_list, int count, int n, SolveState s, int mode,
-                     int cycle, int fixed_cycles, int max_cycles, double tol, hipStream_t st);
+// Mixed precision: r = b' - A'u in FP64 on the top grids, stored rounded to
+// FP32 as the inner right-hand side d_list32[g].b (whose u[0] is zeroed),
+// plus the partial sums of r^2.
+void launch_defect(const GridDesc* d_list, const GridDesc32* d_list32, int count, int n,
+                   const int* d_active, double* d_partials, hipStream_t st);
+// Mixed precision: u[0] += (double) e32 on the top grids.
+void launch_correct(const GridDesc* d_list, const GridDesc32* d_list32, int count, int n,
+                    const int* d_active, int buf32, hipStream_t st);
+// Finalise per solve.  The cycle judged is *cycle_ctr - lag; fixed_cycles > 0
+// selects fixed-count mode.
+void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
+                      const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
+                      hipStream_t st);
+// active = 1, cycles = 0, *cycle_ctr = 0; launch_tick: *cycle_ctr += 1.
+void launch_init_state2(int* active, int* cycles, int* cycle_ctr, int ns, hipStream_t st);
+void launch_tick(int* ctr, hipStream_t st);
 void launch_count_active(const int* d_active, int nsolves, int* d_count, hipStream_t st);
 void launch_ydiff(const double* d_q, const int* d_fine_idx, const int* d_coarse_idx, int count,
                   double* d_y, double* d_qf, double* d_qc, const int* d_cycles, int* d_cycles_out,
