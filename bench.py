@@ -54,6 +54,10 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--tile", action="append", default=[],
+                    help="n:tj:tk:chunks, pins a smoother tile shape (skips the autotuner)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -83,7 +87,10 @@ def main():
         st = M.mlmc_sample_batch(P, level, seeds, S, Y, Qf, Qc, cyc)
         assert st == M.MG_OK, st
 
-    if not args.no_autotune:
+    for spec in args.tile:
+        nn, tj, tk, ch = (int(x) for x in spec.split(":"))
+        M.mg_set_tile(P, nn, tj, tk, ch)
+    if not args.no_autotune and not args.tile:
         M.mg_autotune(P, level, S, 3)
     tiles = {n: M.mg_get_tile(P, n) for n in (65, 33, 17, 9, 5)}
     for s in range(args.warmup):
@@ -104,6 +111,13 @@ def main():
         step(s)
     launches, ms, nodes = M.mg_profile_read(P)
     M.mg_profile_enable(P, False)
+
+    if args.calib_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
 
     value = S * args.steps / dt
     ms_step = 1e3 * dt / args.steps

@@ -109,6 +109,16 @@ int mlmc_sample_batch(mg_plan plan, int level, const uint64_t* seeds, int n_samp
                       double* Y_out, double* Qf_out, double* Qc_out, int* cycles_out,
                       int fixed_cycles);
 
+/* Samples of several levels in one batch (levels: host int[n_samples], each
+ * in [0, max_level]; other arguments as mlmc_sample_batch).  Sample i is
+ * Y_{levels[i]} of seed seeds[i]; every grid of every sample that has the same
+ * size is advanced by the same launches (the V-cycles of smaller grids nest in
+ * those of larger ones), so a mix of levels runs as one batch.  Results equal
+ * those of mlmc_sample_batch on each level alone, bit for bit. */
+int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, int n_samples,
+                      double* Y_out, double* Qf_out, double* Qc_out, int* cycles_out,
+                      int fixed_cycles);
+
 /* Execution options (no effect on results beyond rounding order unless
  * stated):
  *   "smoother": 0 = fused single-pass red-black sweep (default),

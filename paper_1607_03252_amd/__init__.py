@@ -61,6 +61,8 @@ def lib():
         L.mg_solve.argtypes = [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, ip, dp]
         L.mlmc_sample_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_uint64), C.c_int, vp, vp, vp,
                                         vp, C.c_int]
+        L.mlmc_sample_mixed.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.c_int,
+                                        vp, vp, vp, vp, C.c_int]
         L.mlmc_philox.argtypes = [vp, C.POINTER(C.c_uint64), C.c_int, C.c_int, vp, vp]
         L.mlmc_field.argtypes = [vp, C.c_int, C.c_uint64, C.c_int, vp]
         L.mlmc_acc_init.argtypes = [C.POINTER(mlmc_level_acc)]
@@ -85,7 +87,8 @@ def exported_symbols():
     return ["mg_plan_desc_default", "mg_plan_create", "mg_plan_destroy", "mg_plan_set_stream",
             "mg_solve", "mlmc_sample_batch", "mlmc_philox", "mlmc_field", "mlmc_acc_init",
             "mlmc_acc_add", "mlmc_acc_result", "mg_profile_enable", "mg_profile_read",
-            "mg_last_error", "mg_plan_set_option", "mg_set_tile", "mg_get_tile", "mg_autotune"]
+            "mg_last_error", "mg_plan_set_option", "mg_set_tile", "mg_get_tile", "mg_autotune",
+            "mlmc_sample_mixed"]
 
 
 def _torch():
@@ -214,6 +217,23 @@ def mlmc_sample_batch(plan: Plan, level: int, seeds, n: int, Y_out, Qf_out=None,
     pc = _ptr(cycles_out, "int32", 2 * n, "cycles_out")
     mg_plan_set_stream(plan)
     st = lib().mlmc_sample_batch(plan.handle, level, sp, n, py, pqf, pqc, pc, fixed_cycles)
+    return plan.check(st, (MG_OK, MG_ENOCONV))
+
+
+def mlmc_sample_mixed(plan: Plan, levels, seeds, n: int, Y_out, Qf_out=None, Qc_out=None,
+                      cycles_out=None, fixed_cycles: int = 0):
+    """n samples, sample i of level levels[i]; returns MG_OK or MG_ENOCONV."""
+    lv = np.ascontiguousarray(np.asarray(levels, dtype=np.int32))
+    arr, sp = _seeds(seeds)
+    if arr.size < n or lv.size < n:
+        raise ValueError("need %d seeds and levels" % n)
+    py = _ptr(Y_out, "float64", n, "Y_out")
+    pqf = _ptr(Qf_out, "float64", n, "Qf_out")
+    pqc = _ptr(Qc_out, "float64", n, "Qc_out")
+    pc = _ptr(cycles_out, "int32", 2 * n, "cycles_out")
+    mg_plan_set_stream(plan)
+    st = lib().mlmc_sample_mixed(plan.handle, lv.ctypes.data_as(C.POINTER(C.c_int)), sp, n, py,
+                                 pqf, pqc, pc, fixed_cycles)
     return plan.check(st, (MG_OK, MG_ENOCONV))
 
 

@@ -91,10 +91,15 @@ struct Batch {
   int nsamples = 0;
   uint64_t* d_seeds = nullptr;
   double* d_normals = nullptr;
+  int* d_levels = nullptr;
   int* d_fi = nullptr;
   int* d_ci = nullptr;
-  double** d_field_out = nullptr;
-  int* d_xi_index = nullptr;
+  struct FieldGroup {
+    int n, count;
+    double** d_out;  // top wh of the fine solve of each sample of this level
+    int* d_xi;       // their rows of d_normals
+  };
+  std::vector<FieldGroup> fields;
   // coefficient injection per fine size, and FP32 conversion per size
   std::vector<double**> d_inj_src, d_inj_dst;
   std::vector<int> inj_n, inj_count;
@@ -102,6 +107,7 @@ struct Batch {
   std::vector<float**> d_cvt_dst;
   std::vector<int> cvt_n, cvt_count;
   bool uploaded = false;
+  std::vector<double*> const_plane;  // per size index: n^2 values h^2
   // graphs of c consecutive cycles
   std::map<int, hipGraphExec_t> graphs;
   int last_cycles = 0;
@@ -293,13 +299,15 @@ static size_t size_index(const std::vector<int>& v, int n) {
 }
 
 template <typename T>
-static GridDescT<T> make_desc(const std::vector<LevelT<T>>& lv, size_t j, int solve, int poff) {
+static GridDescT<T> make_desc(const std::vector<LevelT<T>>& lv, size_t j, int solve, int poff,
+                             T* const_plane) {
   const LevelT<T>& L = lv[j];
   GridDescT<T> d{};
   d.u[0] = L.u[0];
   d.u[1] = L.u[1];
   d.wh = L.wh;
-  d.b = L.b;
+  d.b = L.b ? L.b : const_plane;  // constant right-hand side: one plane, stride 0
+  d.bstride = L.b ? L.n * L.n : 0;
   d.r = L.r;
   if (j + 1 < lv.size()) {
     d.uc[0] = lv[j + 1].u[0];
@@ -338,6 +346,15 @@ static void upload(Batch* B, Lists<T>& Ls, hipStream_t st) {
 // (Re)write the device descriptor lists from the current buffers.
 static void upload_lists(mg_plan_s* P, Batch* B) {
   const auto& spec = B->spec;
+  if (B->const_plane.empty()) {
+    // h^2 (f = 1) on one n^2 plane per grid size, read with plane stride 0
+    for (int n : B->sizes) {
+      double* pl = (double*)B->dalloc(sizeof(double) * n * n);
+      const double h = 1.0 / (double)(n - 1);
+      launch_fill(pl, (long)n * n, h * h, P->work);
+      B->const_plane.push_back(pl);
+    }
+  }
   B->L64.h.assign(B->sizes.size(), {});
   B->L64.htop.assign(B->top_sizes.size(), {});
   B->L32.h.assign(spec.mixed ? B->sizes.size() : 0, {});
@@ -347,13 +364,14 @@ static void upload_lists(mg_plan_s* P, Batch* B) {
     const auto& lv = B->lev[s];
     for (size_t j = 0; j < lv.size(); ++j) {
       const size_t si = size_index(B->sizes, lv[j].n);
-      const GridDesc d = make_desc(lv, j, s, j == 0 ? poff : 0);
+      const GridDesc d = make_desc(lv, j, s, j == 0 ? poff : 0, B->const_plane[si]);
       B->L64.h[si].push_back(d);
-      if (spec.mixed) B->L32.h[si].push_back(make_desc(B->lev32[s], j, s, j == 0 ? poff : 0));
+      if (spec.mixed)
+        B->L32.h[si].push_back(make_desc<float>(B->lev32[s], j, s, j == 0 ? poff : 0, nullptr));
       if (j == 0) {
         const size_t ti = size_index(B->top_sizes, lv[j].n);
         B->L64.htop[ti].push_back(d);
-        if (spec.mixed) B->L32.htop[ti].push_back(make_desc(B->lev32[s], j, s, poff));
+        if (spec.mixed) B->L32.htop[ti].push_back(make_desc<float>(B->lev32[s], j, s, poff, nullptr));
       }
     }
     poff += reduce_blocks(spec.top_n[s]);
@@ -615,15 +633,18 @@ static Batch* get_batch(mg_plan_s* P, const BatchSpec& spec, int* status) {
   return P->batch.get();
 }
 
-static BatchSpec mlmc_spec(mg_plan_s* P, int level, int n_samples) {
-  const int nf = (P->desc.n0 - 1) * (1 << level) + 1;
-  const int nc = level > 0 ? (P->desc.n0 - 1) * (1 << (level - 1)) + 1 : 0;
+static int level_n(mg_plan_s* P, int level) { return (P->desc.n0 - 1) * (1 << level) + 1; }
+
+// Solves of a batch of samples: sample i owns solve fi[i] on n_{l_i} and, for
+// l_i > 0, solve fi[i] + 1 on n_{l_i - 1}, which shares the fine solve's
+// coefficients from its second multigrid level down.
+static BatchSpec mlmc_spec(mg_plan_s* P, const std::vector<int>& levels) {
   BatchSpec spec;
-  for (int i = 0; i < n_samples; ++i) {
-    spec.top_n.push_back(nf);
+  for (int l : levels) {
+    spec.top_n.push_back(level_n(P, l));
     spec.share.push_back(-1);
-    if (level > 0) {
-      spec.top_n.push_back(nc);
+    if (l > 0) {
+      spec.top_n.push_back(level_n(P, l - 1));
       spec.share.push_back((int)spec.top_n.size() - 2);
     }
   }
@@ -634,41 +655,80 @@ static BatchSpec mlmc_spec(mg_plan_s* P, int level, int n_samples) {
 }
 
 // Fields, coefficient hierarchy and zero iterates for a batch of samples.
-static void setup_samples(mg_plan_s* P, Batch* B, int level, const uint64_t* seeds,
-                          int n_samples) {
+static void setup_samples(mg_plan_s* P, Batch* B, const std::vector<int>& levels,
+                          const uint64_t* seeds) {
   hipStream_t st = P->work;
-  const int nf = (P->desc.n0 - 1) * (1 << level) + 1;
+  const int n_samples = (int)levels.size();
   if (B->nsamples != n_samples) {
     upload_lists(P, B);
     B->nsamples = n_samples;
-    const int per = level > 0 ? 2 : 1;
     B->d_seeds = (uint64_t*)B->dalloc(sizeof(uint64_t) * n_samples);
+    B->d_levels = (int*)B->dalloc(sizeof(int) * n_samples);
     B->d_normals = (double*)B->dalloc(sizeof(double) * 64 * n_samples);
-    std::vector<int> fi(n_samples), ci(n_samples), xi(n_samples);
-    std::vector<double*> fo(n_samples);
+    std::vector<int> fi(n_samples), ci(n_samples);
+    std::map<int, std::pair<std::vector<double*>, std::vector<int>>> groups;
+    int s = 0;
     for (int i = 0; i < n_samples; ++i) {
-      fi[i] = per * i;
-      ci[i] = level > 0 ? per * i + 1 : -1;
-      xi[i] = i;
-      fo[i] = B->lev[per * i][0].wh;
+      fi[i] = s;
+      ci[i] = levels[i] > 0 ? s + 1 : -1;
+      groups[levels[i]].first.push_back(B->lev[s][0].wh);
+      groups[levels[i]].second.push_back(i);
+      s += levels[i] > 0 ? 2 : 1;
     }
     B->d_fi = (int*)B->dalloc(sizeof(int) * n_samples);
     B->d_ci = (int*)B->dalloc(sizeof(int) * n_samples);
-    B->d_xi_index = (int*)B->dalloc(sizeof(int) * n_samples);
-    B->d_field_out = (double**)B->dalloc(sizeof(double*) * n_samples);
     CK(hipMemcpy(B->d_fi, fi.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
     CK(hipMemcpy(B->d_ci, ci.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
-    CK(hipMemcpy(B->d_xi_index, xi.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
-    CK(hipMemcpy(B->d_field_out, fo.data(), sizeof(double*) * n_samples, hipMemcpyHostToDevice));
+    CK(hipMemcpy(B->d_levels, levels.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
+    for (auto& kv : groups) {
+      Batch::FieldGroup g;
+      g.n = level_n(P, kv.first);
+      g.count = (int)kv.second.first.size();
+      g.d_out = (double**)B->dalloc(sizeof(double*) * g.count);
+      g.d_xi = (int*)B->dalloc(sizeof(int) * g.count);
+      CK(hipMemcpy(g.d_out, kv.second.first.data(), sizeof(double*) * g.count, hipMemcpyHostToDevice));
+      CK(hipMemcpy(g.d_xi, kv.second.second.data(), sizeof(int) * g.count, hipMemcpyHostToDevice));
+      B->fields.push_back(g);
+    }
   }
   CK(hipMemcpyAsync(B->d_seeds, seeds, sizeof(uint64_t) * n_samples, hipMemcpyHostToDevice, st));
-  launch_philox(B->d_seeds, n_samples, level, nullptr, B->d_normals, st);
-  launch_field(nf, n_samples, B->d_field_out, B->d_xi_index, B->d_normals, phi_table(P, nf),
-               P->d_coef, 0, st);
+  launch_philox(B->d_seeds, n_samples, 0, nullptr, B->d_normals, st, B->d_levels);
+  for (const auto& g : B->fields)
+    launch_field(g.n, g.count, g.d_out, g.d_xi, B->d_normals, phi_table(P, g.n), P->d_coef, 0, st);
   prepare_coefficients(P, B);
   // every sample starts from the zero iterate (the workspace may hold the last batch)
   for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
     launch_zero_u<double>(B->L64.dtop[ti], (int)B->L64.htop[ti].size(), B->top_sizes[ti], st);
+}
+
+// Samples of (possibly different) levels in one batch: one launch per grid
+// size and V-cycle step covers every sample that has a grid of that size.
+static int run_samples(mg_plan_s* P, const std::vector<int>& levels, const uint64_t* seeds,
+                       double* Y_out, double* Qf_out, double* Qc_out, int* cycles_out,
+                       int fixed_cycles) {
+  int status = MG_OK;
+  order_after_caller(P);
+  Batch* B = get_batch(P, mlmc_spec(P, levels), &status);
+  if (!B) return status;
+  hipStream_t st = P->work;
+  const int n_samples = (int)levels.size();
+  setup_samples(P, B, levels, seeds);
+  if (fixed_cycles > 0) B->drop_graphs();  // graphs bake in the stopping mode
+  const bool ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0);
+  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_QOI, B->ss.partials, st);
+    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI, B->d_cycle, 0, 0, 0, 0.0, st);
+  }
+  launch_ydiff(B->ss.q, B->d_fi, B->d_ci, n_samples, Y_out, Qf_out, Qc_out, B->ss.cycles,
+               cycles_out, st);
+  CK(hipStreamSynchronize(st));
+  if (P->prof) collect_profile(P);
+  if (!ok) {
+    P->err = "some solve missed tol within max_cycles";
+    return MG_ENOCONV;
+  }
+  return MG_OK;
 }
 
 }  // namespace mg
@@ -856,28 +916,27 @@ int mlmc_sample_batch(mg_plan P, int level, const uint64_t* seeds, int n_samples
     return MG_EINVAL;
   }
   API_BEGIN
-  int status = MG_OK;
-  order_after_caller(P);
-  Batch* B = get_batch(P, mlmc_spec(P, level, n_samples), &status);
-  if (!B) return status;
-  hipStream_t st = P->work;
-  setup_samples(P, B, level, seeds, n_samples);
-  if (fixed_cycles > 0) B->drop_graphs();  // graphs bake in the stopping mode
-  const bool ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0);
-  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
-    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
-    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_QOI, B->ss.partials, st);
-    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI, B->d_cycle, 0, 0, 0, 0.0, st);
+  const std::vector<int> levels(n_samples, level);
+  return run_samples(P, levels, seeds, Y_out, Qf_out, Qc_out, cycles_out, fixed_cycles);
+  API_END(P)
+}
+
+int mlmc_sample_mixed(mg_plan P, const int* levels, const uint64_t* seeds, int n_samples,
+                      double* Y_out, double* Qf_out, double* Qc_out, int* cycles_out,
+                      int fixed_cycles) {
+  if (!P) return MG_EINVAL;
+  if (!levels || !seeds || n_samples < 1 || !Y_out || fixed_cycles < 0) {
+    P->err = "mlmc_sample_mixed: levels/seeds/Y_out non-null, n >= 1";
+    return MG_EINVAL;
   }
-  launch_ydiff(B->ss.q, B->d_fi, B->d_ci, n_samples, Y_out, Qf_out, Qc_out, B->ss.cycles,
-               cycles_out, st);
-  CK(hipStreamSynchronize(st));
-  if (P->prof) collect_profile(P);
-  if (!ok) {
-    P->err = "mlmc_sample_batch: some solve missed tol within max_cycles";
-    return MG_ENOCONV;
-  }
-  return MG_OK;
+  for (int i = 0; i < n_samples; ++i)
+    if (levels[i] < 0 || levels[i] > P->desc.max_level) {
+      P->err = "mlmc_sample_mixed: every level must be in [0, max_level]";
+      return MG_EINVAL;
+    }
+  API_BEGIN
+  const std::vector<int> lv(levels, levels + n_samples);
+  return run_samples(P, lv, seeds, Y_out, Qf_out, Qc_out, cycles_out, fixed_cycles);
   API_END(P)
 }
 
@@ -907,8 +966,9 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
     double best = 1e30;
     SweepShape pick = default_sweep_shape(n);
     for (int i = 0; i < c; ++i)
-      for (int chunks : {1, 2, 4, 8}) {
+      for (int chunks : {1, 2, 4}) {
         if (chunks > 1 && (n - 2) / chunks < 4) continue;
+        if (n >= 33 && shapes[i].tj * shapes[i].tk < 64) continue;  // tiny tiles on big grids
         SweepShape s = shapes[i];
         s.chunks = chunks;
         // every solve active while timing; the next batch reinitialises the workspace

@@ -20,15 +20,16 @@ template <typename T>
 struct GridDescT {
   T* u[2];          // iterate: the smoother reads u[buf] and writes u[1-buf]
   const T* wh;      // 1/(2k) at all n^3 vertices
-  T* b;             // h^2-scaled right-hand side, or nullptr for the constant bconst
+  T* b;             // h^2-scaled right-hand side: b[i*bstride + j*n + k] (bstride 0:
+                    // one n^2 plane holding a constant right-hand side)
   T* r;             // residual scratch, n^3 (nullptr on 3^3)
   T* uc[2];         // the coarser grid's iterate buffers (nullptr on 3^3)
   T* bc;            // the coarser grid's right-hand side
-  double bconst;    // used when b == nullptr
+  double bconst;    // value of a constant right-hand side (h^2 for f = 1)
   int solve;        // owning solve: index into per-solve arrays
   int n;            // vertices per axis
   int poff;         // offset of this grid's reduction partials (top grids only)
-  int pad_;
+  int bstride;      // n*n for a full right-hand side array, 0 for a constant plane
 };
 using GridDesc = GridDescT<double>;
 using GridDesc32 = GridDescT<float>;
@@ -49,8 +50,11 @@ enum ReduceMode { RED_BNORM = 0, RED_RESID = 1, RED_QOI = 2 };
 // with 256-thread blocks of 4 rows (j) x 64 columns (k) of one plane i.
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int point_blocks(int m) { return m * ceil_div(m, 4) * ceil_div(m, 64); }
-// Reduction partial count of one grid of size n (one per interior block).
-__host__ __device__ inline int reduce_blocks(int n) { return point_blocks(n - 2); }
+// Column-marching kernels (residual, reductions): one 256-thread block per
+// 4 x 64 interior columns; reductions keep one partial per block.
+__host__ __device__ inline int reduce_blocks(int n) {
+  return ceil_div(n - 2, 4) * ceil_div(n - 2, 64);
+}
 
 // Tile shape of the fused smoother: TJ rows (j) x TK columns (k), streamed
 // over planes i in `chunks` pieces.
@@ -62,8 +66,10 @@ int sweep_shapes(int n, SweepShape* out, int max_out);
 SweepShape default_sweep_shape(int n);
 
 // ---- launchers (all asynchronous on `st`) --------------------------------
+// Normals of `count` samples; the counter's level word is d_levels[s] when
+// d_levels is given, else `level`.
 void launch_philox(const uint64_t* d_seeds, int count, int level, uint32_t* d_words,
-                   double* d_normals, hipStream_t st);
+                   double* d_normals, hipStream_t st, const int* d_levels = nullptr);
 // wh (mode 0) or k (mode 1) of the KL field on `count` grids of size n.
 void launch_field(int n, int count, double* const* d_out, const int* d_xi_index,
                   const double* d_normals, const double* d_phi, const double* d_coef,
@@ -76,6 +82,9 @@ void launch_to_float(int n, int count, const double* const* d_src, float* const*
 // wh = 1/(2k), b = h^2 f and a zero boundary for u, for a caller's problem.
 void launch_prepare_problem(int n, const double* k, const double* f, double* wh, double* b,
                             double* u, hipStream_t st);
+
+// Fill `count` doubles with `value`.
+void launch_fill(double* p, long count, double value, hipStream_t st);
 
 // Multigrid steps on a device list of `count` grids of size n.
 // The fused smoother: one red-black sweep from u[buf] into u[1-buf]; with

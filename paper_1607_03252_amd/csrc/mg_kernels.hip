@@ -1,8 +1,8 @@
 // Device kernels of libmlmcmg (gfx950, wave64).
 //
 // Every multigrid kernel takes a device list of grid descriptors of one grid
-// size and runs blockIdx.y over the list, so one launch advances every sample
-// of a batch that has a grid of that size.  A per-solve `active` flag freezes
+// size and spreads (grid, block) units over its workgroups (xcd_unit), so one
+// launch advances every sample of a batch that has a grid of that size.  A per-solve `active` flag freezes
 // solves that have converged.  Kernels are templated on the arithmetic type
 // (double for the FP64 path, float for the inner cycles of mixed precision).
 //
@@ -14,6 +14,8 @@
 // plane i-1, which need exactly those red values.  Planes of u, wh and the new
 // red values live in small LDS ring buffers.  The sweep reads u[buf] and
 // writes u[1-buf], so tiles never see a neighbour's half-updated values.
+#include <type_traits>
+
 #include "mg_internal.h"
 
 namespace mg {
@@ -43,6 +45,22 @@ __device__ __forceinline__ float rcp<float>(float x) {
 
 __device__ __forceinline__ int vidx(int n, int i, int j, int k) { return (i * n + j) * n + k; }
 
+// Grid buffers reach the kernels as generic pointers inside descriptors, so
+// plain dereferences compile to flat memory instructions, which count
+// against both vmcnt and lgkmcnt: every wait for LDS data would also drain
+// the in-flight global loads and stores.  These views put them in the global
+// address space so the compiler emits global_* instructions instead.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gview(T* p) {
+  return (gptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<const T> gview(const T* p) {
+  return (gptr<const T>)p;
+}
+
 // Interior point of block `bid` of a grid with m = n-2 interior points per
 // axis: blocks cover (plane i, 4 rows j, 64 columns k).
 struct Pt {
@@ -62,6 +80,26 @@ __device__ __forceinline__ Pt interior_point(int m, int bid) {
 __device__ __forceinline__ Pt full_point(int n, int bid) {
   Pt p = interior_point(n, bid);
   return {p.i - 1, p.j - 1, p.k - 1, p.ok};
+}
+
+// Workgroup -> (grid g, block blk of that grid).  Workgroups are dealt to
+// the 8 XCDs round-robin; this gives each XCD one contiguous range of the
+// count * per units, so the neighbouring tiles of a grid (whose halos
+// overlap) run under the same L2.
+__device__ __forceinline__ bool xcd_unit(int count, int per, int& g, int& blk) {
+  const int total = count * per;
+  const int Q = (total + 7) >> 3;
+  const int L = blockIdx.x;
+  const int u = (L & 7) * Q + (L >> 3);
+  g = u / per;
+  blk = u - g * per;
+  return u < total;
+}
+
+// Right-hand side at vertex (i, j, k): a full array or a constant plane.
+template <typename T>
+__device__ __forceinline__ T b_at(const GridDescT<T>& d, int i, int j, int k) {
+  return gview<T>(d.b)[i * d.bstride + j * d.n + k];
 }
 
 // Harmonic-mean face coefficients of vertex p and the stencil sums
@@ -95,22 +133,20 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // Trilinear interpolation of the coarse array e (size nc, zero on its
-// boundary) at fine interior vertex (i, j, k).
-template <typename T>
-__device__ __forceinline__ T prolong_at(const T* __restrict__ e, int nc, int i, int j, int k) {
-  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-  const int ni = (i & 1) + 1, nj = (j & 1) + 1;
-  const bool ko = (k & 1) != 0;
-  const T wij = (T)(((i & 1) ? 0.5 : 1.0) * ((j & 1) ? 0.5 : 1.0) * (ko ? 0.5 : 1.0));
-  T s = 0;
-  for (int a = 0; a < ni; ++a)
-    for (int b = 0; b < nj; ++b) {
-      const int row = vidx(nc, i0 + a, j0 + b, k0);
-      T z = e[row];
-      if (ko) z += e[row + 1];
-      s += z;
-    }
-  return wij * s;
+// boundary) at fine interior vertex (i, j, k): the 8 surrounding coarse values
+// with per-axis weights (1, 0) on even and (1/2, 1/2) on odd fine indices.
+// Branch-free, and the one formula both the fused sweep and k_prolong use.
+template <typename T, typename P>
+__device__ __forceinline__ T prolong_at(P e, int nc, int i, int j, int k) {
+  const T wi1 = (i & 1) ? (T)0.5 : (T)0, wi0 = (i & 1) ? (T)0.5 : (T)1;
+  const T wj1 = (j & 1) ? (T)0.5 : (T)0, wj0 = (j & 1) ? (T)0.5 : (T)1;
+  const T wk1 = (k & 1) ? (T)0.5 : (T)0, wk0 = (k & 1) ? (T)0.5 : (T)1;
+  const int base = ((i >> 1) * nc + (j >> 1)) * nc + (k >> 1), pl = nc * nc;
+  const T e000 = e[base], e001 = e[base + 1], e010 = e[base + nc], e011 = e[base + nc + 1];
+  const T e100 = e[base + pl], e101 = e[base + pl + 1];
+  const T e110 = e[base + pl + nc], e111 = e[base + pl + nc + 1];
+  return wi0 * (wj0 * (wk0 * e000 + wk1 * e001) + wj1 * (wk0 * e010 + wk1 * e011)) +
+         wi1 * (wj0 * (wk0 * e100 + wk1 * e101) + wj1 * (wk0 * e110 + wk1 * e111));
 }
 
 // ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ----------------------
@@ -135,12 +171,14 @@ __device__ __forceinline__ void philox_block(uint32_t c[4], uint32_t k0, uint32_
 // One 64-thread block per sample: 32 Philox blocks -> 128 words -> 64
 // uniforms on (0,1] with 53 random bits -> 32 Box-Muller pairs.
 __global__ void __launch_bounds__(64) k_philox(const uint64_t* __restrict__ seeds, int level,
+                                               const int* __restrict__ levels,
                                                uint32_t* __restrict__ words,
                                                double* __restrict__ normals) {
   __shared__ uint32_t w[128];
   __shared__ double U[64];
   const int s = blockIdx.x, t = threadIdx.x;
   const uint64_t seed = seeds[s];
+  if (levels) level = levels[s];
   if (t < 32) {
     uint32_t c[4] = {(uint32_t)t, (uint32_t)level, 0u, 0u};
     philox_block(c, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -167,13 +205,15 @@ __global__ void __launch_bounds__(kBlock) k_field(int n, double* const* __restri
                                                   const int* __restrict__ xi_index,
                                                   const double* __restrict__ normals,
                                                   const double* __restrict__ phi,
-                                                  const double* __restrict__ coef, int mode) {
+                                                  const double* __restrict__ coef, int mode,
+                                                  int count, int per) {
   __shared__ double C[64];
-  const int g = blockIdx.y;
+  int g, blk;
+  if (!xcd_unit(count, per, g, blk)) return;
   if (threadIdx.x < 64)
     C[threadIdx.x] = coef[threadIdx.x] * normals[(size_t)xi_index[g] * 64 + threadIdx.x];
   __syncthreads();
-  const Pt p = full_point(n, blockIdx.x);
+  const Pt p = full_point(n, blk);
   if (!p.ok) return;
   double px[4], py[4], pz[4];
 #pragma unroll
@@ -199,20 +239,25 @@ __global__ void __launch_bounds__(kBlock) k_field(int n, double* const* __restri
 }
 
 __global__ void __launch_bounds__(kBlock) k_inject(int nf, const double* const* __restrict__ fine,
-                                                   double* const* __restrict__ coarse) {
+                                                   double* const* __restrict__ coarse, int count,
+                                                   int per) {
   const int nc = (nf - 1) / 2 + 1;
-  const Pt p = full_point(nc, blockIdx.x);
+  int g, blk;
+  if (!xcd_unit(count, per, g, blk)) return;
+  const Pt p = full_point(nc, blk);
   if (!p.ok) return;
-  coarse[blockIdx.y][vidx(nc, p.i, p.j, p.k)] =
-      fine[blockIdx.y][vidx(nf, 2 * p.i, 2 * p.j, 2 * p.k)];
+  coarse[g][vidx(nc, p.i, p.j, p.k)] = fine[g][vidx(nf, 2 * p.i, 2 * p.j, 2 * p.k)];
 }
 
 __global__ void __launch_bounds__(kBlock) k_to_float(int n, const double* const* __restrict__ src,
-                                                     float* const* __restrict__ dst) {
-  const Pt p = full_point(n, blockIdx.x);
+                                                     float* const* __restrict__ dst, int count,
+                                                     int per) {
+  int g, blk;
+  if (!xcd_unit(count, per, g, blk)) return;
+  const Pt p = full_point(n, blk);
   if (!p.ok) return;
   const int v = vidx(n, p.i, p.j, p.k);
-  dst[blockIdx.y][v] = (float)src[blockIdx.y][v];
+  dst[g][v] = (float)src[g][v];
 }
 
 __global__ void __launch_bounds__(kBlock) k_prepare(int n, const double* __restrict__ k,
@@ -231,138 +276,173 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int n, const double* __restr
 }
 
 // ---- the fused red-black smoother --------------------------------------------
-template <typename T, int TJ, int TK>
-__global__ void __launch_bounds__(kBlock) k_sweep(const GridDescT<T>* __restrict__ list,
-                                                  const int* __restrict__ active, int buf,
-                                                  int cbuf, int tiles_k, int tiles_jk,
-                                                  int chunk_len) {
-  constexpr int W2 = TK + 4, H2 = TJ + 4, A2 = W2 * H2;  // tile + 2-point ring
-  constexpr int W1 = TK + 2, H1 = TJ + 2, A1 = W1 * H1;  // tile + 1-point ring
-  __shared__ T sU[3][A2];  // u[buf] planes (ring of 3)
-  __shared__ T sW[5][A2];  // wh planes (ring of 5)
-  __shared__ T sR[3][A1];  // new red values (ring of 3)
+// Thread layout: the workgroup covers the tile plus a two-point ring, T2 =
+// (TJ+4) x (TK+4) positions; each thread owns a pair of k-adjacent columns
+// (one red, one black on every plane) and marches the planes i keeping its
+// own columns' u, wh, b and new red values of three to four planes in
+// registers; the loads of plane i+2 are issued before the work on plane i.
+// Only the current planes are shared through LDS (for in-plane neighbours):
+// u_in(i) (1 buffer), wh (3 buffers) and the new red values (2 buffers).
+template <int TJ, int TK>
+struct SweepGeom {
+  static constexpr int W2 = TK + 4, H2 = TJ + 4, A2 = W2 * H2;
+  static constexpr int PAIRS = H2 * (W2 / 2);
+  static constexpr int THREADS = ((PAIRS + 63) / 64) * 64;
+};
 
-  const GridDescT<T> d = list[blockIdx.y];
+template <typename T, int TJ, int TK, bool PRO>
+__global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
+    k_sweep(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
+            int cbuf, int tiles_k, int tiles_jk, int chunk_len, int count, int per) {
+  using Geo = SweepGeom<TJ, TK>;
+  constexpr int W2 = Geo::W2, A2 = Geo::A2, HW = W2 / 2;
+  __shared__ T sU[A2];     // u_in of the current plane
+  __shared__ T sW[3][A2];  // wh, planes i % 3
+  __shared__ T sR[2][A2];  // new red values, planes i % 2
+
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDescT<T> d = list[gi];
   if (!active[d.solve]) return;
-  const int n = d.n, sn2 = n * n;
-  const int ch = blockIdx.x / tiles_jk, tile = blockIdx.x - ch * tiles_jk;
+  const int n = d.n, sn2 = n * n, bs = d.bstride;
+  const int ch = blk / tiles_jk, tile = blk - ch * tiles_jk;
   const int tj = tile / tiles_k, tk = tile - tj * tiles_k;
   const int j0 = 1 + tj * TJ, k0 = 1 + tk * TK;
   const int ia = 1 + ch * chunk_len;
   const int ib = min(n - 2, ia + chunk_len - 1);
-  const T* __restrict__ uin = (buf ? d.u[1] : d.u[0]);
-  T* __restrict__ uout = (buf ? d.u[0] : d.u[1]);
-  const T* __restrict__ wh = d.wh;
-  const T* __restrict__ bb = d.b;
-  const T bconst = (T)d.bconst;
-  const T* __restrict__ ec = cbuf < 0 ? nullptr : (cbuf ? d.uc[1] : d.uc[0]);
+  const gptr<const T> uin = gview<T>(buf ? d.u[1] : d.u[0]);
+  const gptr<T> uout = gview<T>(buf ? d.u[0] : d.u[1]);
+  const gptr<const T> wh = gview<T>(d.wh);
+  const gptr<const T> bb = gview<T>(d.b);
+  const gptr<const T> ec = gview<T>(PRO ? (cbuf ? d.uc[1] : d.uc[0]) : d.u[0]);
   const int nc = (n - 1) / 2 + 1;
 
-  auto load_plane = [&](int i) {
-    T* du = sU[i % 3];
-    T* dw = sW[i % 5];
-    for (int q = threadIdx.x; q < A2; q += kBlock) {
-      const int r = q / W2, c = q - r * W2;
-      const int j = j0 - 2 + r, k = k0 - 2 + c;
-      T uv = 0, wv = 0;
-      if (j >= 0 && j < n && k >= 0 && k < n) {
-        const int g = i * sn2 + j * n + k;
-        uv = uin[g];
-        wv = wh[g];
-        if (ec && i > 0 && i < n - 1 && j > 0 && j < n - 1 && k > 0 && k < n - 1)
-          uv += prolong_at<T>(ec, nc, i, j, k);
-      }
-      du[q] = uv;
-      dw[q] = wv;
-    }
-  };
+  // this thread's column pair: T2 row r, columns c = 2*c2, 2*c2 + 1
+  const int t = threadIdx.x;
+  const bool live = t < Geo::PAIRS;
+  const int r = live ? t / HW : 0, c2 = live ? t - (t / HW) * HW : 0;
+  const int j = j0 - 2 + r;
+  const int kA = k0 - 2 + 2 * c2;
+  const int q = r * W2 + 2 * c2;  // LDS index of column kA (kA+1 is q+1)
+  const bool rowin = live && j >= 0 && j < n;
+  const bool inA = rowin && kA >= 0 && kA < n;
+  const bool inB = rowin && kA + 1 < n;
+  const bool intJ = j >= 1 && j <= n - 2;
+  const bool intA = intJ && kA >= 1 && kA <= n - 2;
+  const bool intB = intJ && kA + 1 >= 1 && kA + 1 <= n - 2;
+  const bool t1row = r >= 1 && r <= TJ + 2;
+  const bool t1A = live && t1row && 2 * c2 >= 1 && 2 * c2 <= TK + 2;
+  const bool t1B = live && t1row && 2 * c2 + 1 <= TK + 2;
+  const bool tileRow = r >= 2 && r < TJ + 2;
+  const bool tileA = live && tileRow && 2 * c2 >= 2 && 2 * c2 < TK + 2;
+  const bool tileB = live && tileRow && 2 * c2 + 1 >= 2 && 2 * c2 + 1 < TK + 2;
+  // clamped in-range offsets: every load is unconditional
+  const int jc = min(max(j, 0), n - 1);
+  const int kAc = min(max(kA, 0), n - 1), kBc = min(max(kA + 1, 0), n - 1);
+  const int jI = min(max(j, 1), n - 2), aI = min(max(kA, 1), n - 2), bI = min(max(kA + 1, 1), n - 2);
 
-  // red points of plane i on the tile and its 1-point ring -> sR[i % 3]
-  auto red = [&](int i) {
-    T* R = sR[i % 3];
-    if (i >= n - 1) {
-      for (int q = threadIdx.x; q < A1; q += kBlock) R[q] = 0;
-      return;
-    }
-    const T* U0 = sU[(i + 2) % 3];
-    const T* U1 = sU[i % 3];
-    const T* U2 = sU[(i + 1) % 3];
-    const T* Wm = sW[(i + 4) % 5];
-    const T* W0 = sW[i % 5];
-    const T* Wp = sW[(i + 1) % 5];
-    constexpr int HR = W1 / 2;
-    for (int q = threadIdx.x; q < H1 * HR; q += kBlock) {
-      const int r = q / HR, c2 = q - r * HR;
-      const int j = j0 - 1 + r;
-      const int c = 2 * c2 + ((i + j + k0 - 1) & 1);  // (i + j + k) even
-      const int k = k0 - 1 + c;
-      T val = 0;
-      if (j >= 1 && j <= n - 2 && k >= 1 && k <= n - 2) {
-        const int q2 = (r + 1) * W2 + (c + 1);
-        const T w = W0[q2];
-        const T a0 = rcp<T>(w + Wm[q2]), a1 = rcp<T>(w + Wp[q2]);
-        const T a2 = rcp<T>(w + W0[q2 - W2]), a3 = rcp<T>(w + W0[q2 + W2]);
-        const T a4 = rcp<T>(w + W0[q2 - 1]), a5 = rcp<T>(w + W0[q2 + 1]);
-        const T D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
-        const T S = a0 * U0[q2] + a1 * U2[q2] + a2 * U1[q2 - W2] + a3 * U1[q2 + W2] +
-                    a4 * U1[q2 - 1] + a5 * U1[q2 + 1];
-        const T bp = bb ? bb[i * sn2 + j * n + k] : bconst;
-        val = (bp + S) * rcp<T>(D);
-      }
-      R[r * W1 + c] = val;
-    }
-  };
-
-  // black points of plane p on the tile, then both colours of the tile out
-  auto black = [&](int p) {
-    const T* Rm = sR[(p + 2) % 3];
-    const T* R0 = sR[p % 3];
-    const T* Rp = sR[(p + 1) % 3];
-    const T* Wm = sW[(p + 4) % 5];
-    const T* W0 = sW[p % 5];
-    const T* Wp = sW[(p + 1) % 5];
-    constexpr int HP = TK / 2;
-    for (int q = threadIdx.x; q < TJ * HP; q += kBlock) {
-      const int r = q / HP, c2 = q - r * HP;
-      const int j = j0 + r;
-      if (j > n - 2) continue;
-      const int kA = k0 + 2 * c2;  // pair (kA, kA+1): one red, one black
-      const bool redA = ((p + j + kA) & 1) == 0;
-      const int kb = redA ? kA + 1 : kA;
-      const int kr = redA ? kA : kA + 1;
-      const T vr = R0[(r + 1) * W1 + (kr - k0 + 1)];
-      T vb = 0;
-      if (kb <= n - 2) {
-        const int q1 = (r + 1) * W1 + (kb - k0 + 1);
-        const int q2 = (r + 2) * W2 + (kb - k0 + 2);
-        const T w = W0[q2];
-        const T a0 = rcp<T>(w + Wm[q2]), a1 = rcp<T>(w + Wp[q2]);
-        const T a2 = rcp<T>(w + W0[q2 - W2]), a3 = rcp<T>(w + W0[q2 + W2]);
-        const T a4 = rcp<T>(w + W0[q2 - 1]), a5 = rcp<T>(w + W0[q2 + 1]);
-        const T D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
-        const T S = a0 * Rm[q1] + a1 * Rp[q1] + a2 * R0[q1 - W1] + a3 * R0[q1 + W1] +
-                    a4 * R0[q1 - 1] + a5 * R0[q1 + 1];
-        const T bp = bb ? bb[p * sn2 + j * n + kb] : bconst;
-        vb = (bp + S) * rcp<T>(D);
-      }
-      const int g = p * sn2 + j * n + kA;
-      uout[g] = redA ? vr : vb;
-      if (kA + 1 <= n - 2) uout[g + 1] = redA ? vb : vr;
+  auto ld = [&](int i, T* u, T* w, T* b) {
+    const int ic = min(max(i, 0), n - 1);
+    const bool ok = i >= 0 && i <= n - 1;
+    const int gA = ic * sn2 + jc * n + kAc, gB = ic * sn2 + jc * n + kBc;
+    const int hA = ic * bs + jc * n + kAc, hB = ic * bs + jc * n + kBc;
+    const T ua = uin[gA], ub = uin[gB], wa = wh[gA], wb = wh[gB], ba = bb[hA], bbv = bb[hB];
+    u[0] = (ok && inA) ? ua : (T)0;
+    u[1] = (ok && inB) ? ub : (T)0;
+    w[0] = (ok && inA) ? wa : (T)0;
+    w[1] = (ok && inB) ? wb : (T)0;
+    b[0] = ba;
+    b[1] = bbv;
+    if (PRO) {  // the coarse correction, fused into the load
+      const int iI = min(max(i, 1), n - 2);
+      const bool iint = i >= 1 && i <= n - 2;
+      const T pa = prolong_at<T>(ec, nc, iI, jI, aI), pb = prolong_at<T>(ec, nc, iI, jI, bI);
+      u[0] += (iint && intA) ? pa : (T)0;
+      u[1] += (iint && intB) ? pb : (T)0;
     }
   };
 
   const int istart = ia > 1 ? ia - 1 : 1;
   const int iend = min(ib + 1, n - 1);
-  load_plane(istart - 1);
-  load_plane(istart);
-  if (istart == 1)
-    for (int q = threadIdx.x; q < A1; q += kBlock) sR[0][q] = 0;  // plane 0 is boundary
+  // registers: u at i-1, i, i+1; wh at i-2 .. i+1; b at i-1, i, i+1;
+  // new red values at i-2, i-1; the loads of plane i+2 in flight
+  T um[2], u0[2], up[2], wm2[2], wm[2], w0[2], wp[2], bm[2], b0[2], bp[2];
+  T nm[2] = {0, 0}, n0[2] = {0, 0};
+  T pfu[2], pfw[2], pfb[2];
+  ld(istart - 2, um, wm2, bm);
+  ld(istart - 1, um, wm, bm);
+  ld(istart, u0, w0, b0);
+  ld(istart + 1, up, wp, bp);
+  ld(istart + 2, pfu, pfw, pfb);
+
   for (int i = istart; i <= iend; ++i) {
-    if (i + 1 <= n - 1) load_plane(i + 1);
+    // share plane i
+    if (live) {
+      sU[q] = u0[0];
+      sU[q + 1] = u0[1];
+      sW[i % 3][q] = w0[0];
+      sW[i % 3][q + 1] = w0[1];
+    }
     __syncthreads();
-    red(i);
+    // red point of the pair on plane i: column kA if (i + j + kA) even
+    const int cr = ((i + j + kA) & 1) ? 1 : 0;
+    T np[2] = {0, 0};
+    {
+      const bool on = (cr ? (t1B && intB) : (t1A && intA)) && i <= n - 2;
+      const int qq = q + cr;
+      const T* W0 = sW[i % 3];
+      const T w = cr ? w0[1] : w0[0];
+      const T a0 = rcp<T>(w + (cr ? wm[1] : wm[0])), a1 = rcp<T>(w + (cr ? wp[1] : wp[0]));
+      const T a2 = rcp<T>(w + W0[qq - W2]), a3 = rcp<T>(w + W0[qq + W2]);
+      const T a4 = rcp<T>(w + W0[qq - 1]), a5 = rcp<T>(w + W0[qq + 1]);
+      const T D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
+      const T S = a0 * (cr ? um[1] : um[0]) + a1 * (cr ? up[1] : up[0]) + a2 * sU[qq - W2] +
+                  a3 * sU[qq + W2] + a4 * sU[qq - 1] + a5 * sU[qq + 1];
+      const T val = ((cr ? b0[1] : b0[0]) + S) * rcp<T>(D);
+      np[cr] = on ? val : (T)0;
+      if (live) {
+        sR[i % 2][q + cr] = np[cr];
+        sR[i % 2][q + 1 - cr] = 0;
+      }
+    }
     __syncthreads();
-    if (i - 1 >= ia && i - 1 <= ib) black(i - 1);
+    // black point of plane p = i - 1: the column that is red on plane i
+    const int p = i - 1;
+    if (p >= ia && p <= ib) {
+      const bool on = cr ? (tileB && intB) : (tileA && intA);
+      const int qq = q + cr;
+      const T* R0 = sR[p % 2];
+      const T* Wp0 = sW[p % 3];
+      const T w = cr ? wm[1] : wm[0];
+      const T a0 = rcp<T>(w + (cr ? wm2[1] : wm2[0])), a1 = rcp<T>(w + (cr ? w0[1] : w0[0]));
+      const T a2 = rcp<T>(w + Wp0[qq - W2]), a3 = rcp<T>(w + Wp0[qq + W2]);
+      const T a4 = rcp<T>(w + Wp0[qq - 1]), a5 = rcp<T>(w + Wp0[qq + 1]);
+      const T D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
+      const T S = a0 * (cr ? nm[1] : nm[0]) + a1 * np[cr] + a2 * R0[qq - W2] + a3 * R0[qq + W2] +
+                  a4 * R0[qq - 1] + a5 * R0[qq + 1];
+      const T vb = on ? ((cr ? bm[1] : bm[0]) + S) * rcp<T>(D) : (T)0;
+      // both columns of plane p leave: this black one and the other, red on p
+      const int g = p * sn2 + j * n + kA;
+      if (tileA && intA) uout[g] = cr ? n0[0] : vb;
+      if (tileB && intB) uout[g + 1] = cr ? vb : n0[1];
+    }
+    // roll the registers one plane on
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      nm[e] = n0[e];
+      n0[e] = np[e];
+      um[e] = u0[e];
+      u0[e] = up[e];
+      up[e] = pfu[e];
+      wm2[e] = wm[e];
+      wm[e] = w0[e];
+      w0[e] = wp[e];
+      wp[e] = pfw[e];
+      bm[e] = b0[e];
+      b0[e] = bp[e];
+      bp[e] = pfb[e];
+    }
+    if (i + 1 <= iend) ld(i + 3, pfu, pfw, pfb);
   }
 }
 
@@ -373,34 +453,78 @@ __global__ void __launch_bounds__(kBlock) k_sweep(const GridDescT<T>* __restrict
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_rbgs_colour(const GridDescT<T>* __restrict__ list,
                                                         const int* __restrict__ active,
-                                                        int colour, int buf) {
-  const GridDescT<T> d = list[blockIdx.y];
+                                                        int colour, int buf, int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDescT<T> d = list[gi];
   if (!active[d.solve]) return;
   const int n = d.n;
-  const Pt p = interior_point(n - 2, blockIdx.x);
+  const Pt p = interior_point(n - 2, blk);
   if (!p.ok || ((p.i + p.j + p.k) & 1) != colour) return;
   const int v = vidx(n, p.i, p.j, p.k);
   T* u = (buf ? d.u[1] : d.u[0]);
   T D, S;
   stencil<T>(u, d.wh, v, n, n * n, D, S);
-  const T bp = d.b ? d.b[v] : (T)d.bconst;
+  const T bp = b_at<T>(d, p.i, p.j, p.k);
   u[v] = (bp + S) * rcp<T>(D);
+}
+
+// Column marching: a 256-thread block owns 4 rows (j) x 64 columns (k) of
+// interior columns and walks the planes i, keeping u and wh of its own column
+// at i-1, i, i+1 in registers; the in-plane neighbours come through the cache.
+struct Col {
+  int j, k;
+  bool ok;
+};
+__device__ __forceinline__ Col column_of(int m, int bid) {
+  const int nkc = ceil_div(m, 64);
+  const int kc = bid % nkc, jc = bid / nkc;
+  const int k = kc * 64 + (threadIdx.x & 63), j = jc * 4 + (threadIdx.x >> 6);
+  return {1 + j, 1 + k, j < m && k < m};
+}
+
+// Walks the interior planes of column c, calling f(i, p, r) with the residual
+// r = b' - A'u at vertex p = (i, c.j, c.k).
+template <typename T, typename F>
+__device__ __forceinline__ void march_residual(const GridDescT<T>& d, const T* u_, Col c, F&& f) {
+  const int n = d.n, sn2 = n * n;
+  const gptr<const T> u = gview<T>(u_);
+  const gptr<const T> wh = gview<T>(d.wh);
+  const gptr<const T> bb = gview<T>(d.b);
+  const int bs = d.bstride;
+  int p = sn2 + c.j * n + c.k;
+  int pb = bs + c.j * n + c.k;
+  T um = 0, u0 = u[p], wm = wh[p - sn2], w0 = wh[p];
+  for (int i = 1; i <= n - 2; ++i, p += sn2) {
+    const T up = u[p + sn2], wp = wh[p + sn2];
+    const T a0 = rcp<T>(w0 + wm), a1 = rcp<T>(w0 + wp);
+    const T a2 = rcp<T>(w0 + wh[p - n]), a3 = rcp<T>(w0 + wh[p + n]);
+    const T a4 = rcp<T>(w0 + wh[p - 1]), a5 = rcp<T>(w0 + wh[p + 1]);
+    const T D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
+    const T S = a0 * um + a1 * up + a2 * u[p - n] + a3 * u[p + n] + a4 * u[p - 1] +
+                a5 * u[p + 1];
+    const T bp = bb[pb];
+    pb += bs;
+    f(i, p, bp - (D * u0 - S));
+    um = u0;
+    u0 = up;
+    wm = w0;
+    w0 = wp;
+  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_residual(const GridDescT<T>* __restrict__ list,
-                                                     const int* __restrict__ active, int buf) {
-  const GridDescT<T> d = list[blockIdx.y];
+                                                     const int* __restrict__ active, int buf,
+                                                     int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDescT<T> d = list[gi];
   if (!active[d.solve]) return;
-  const int n = d.n;
-  const Pt p = interior_point(n - 2, blockIdx.x);
-  if (!p.ok) return;
-  const int v = vidx(n, p.i, p.j, p.k);
-  const T* u = (buf ? d.u[1] : d.u[0]);
-  T D, S;
-  stencil<T>(u, d.wh, v, n, n * n, D, S);
-  const T bp = d.b ? d.b[v] : (T)d.bconst;
-  d.r[v] = bp - (D * u[v] - S);
+  const Col c = column_of(d.n - 2, blk);
+  if (!c.ok) return;
+  const gptr<T> r = gview<T>(d.r);
+  march_residual<T>(d, buf ? d.u[1] : d.u[0], c, [&](int, int p, T v) { r[p] = v; });
 }
 
 // Full weighting of the residual to the coarse right-hand side, h^2 scaling
@@ -408,11 +532,14 @@ __global__ void __launch_bounds__(kBlock) k_residual(const GridDescT<T>* __restr
 // cycle from a zero iterate in uc[0].
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict(const GridDescT<T>* __restrict__ list,
-                                                     const int* __restrict__ active) {
-  const GridDescT<T> d = list[blockIdx.y];
+                                                     const int* __restrict__ active, int count,
+                                                     int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDescT<T> d = list[gi];
   if (!active[d.solve]) return;
   const int n = d.n, nc = (n - 1) / 2 + 1;
-  const Pt p = interior_point(nc - 2, blockIdx.x);
+  const Pt p = interior_point(nc - 2, blk);
   if (!p.ok) return;
   const T* r = d.r;
   T s = 0;
@@ -442,7 +569,7 @@ __global__ void k_coarsest(const GridDescT<T>* __restrict__ list, int count,
   const T D = ((rcp<T>(w + d.wh[p - 9]) + rcp<T>(w + d.wh[p + 9])) +
                (rcp<T>(w + d.wh[p - 3]) + rcp<T>(w + d.wh[p + 3]))) +
               (rcp<T>(w + d.wh[p - 1]) + rcp<T>(w + d.wh[p + 1]));
-  const T bp = d.b ? d.b[p] : (T)d.bconst;
+  const T bp = b_at<T>(d, 1, 1, 1);
   d.u[0][p] = bp * rcp<T>(D);
 }
 
@@ -450,20 +577,26 @@ __global__ void k_coarsest(const GridDescT<T>* __restrict__ list, int count,
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong(const GridDescT<T>* __restrict__ list,
                                                     const int* __restrict__ active, int buf,
-                                                    int cbuf) {
-  const GridDescT<T> d = list[blockIdx.y];
+                                                    int cbuf, int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDescT<T> d = list[gi];
   if (!active[d.solve]) return;
   const int n = d.n;
-  const Pt p = interior_point(n - 2, blockIdx.x);
+  const Pt p = interior_point(n - 2, blk);
   if (!p.ok) return;
-  (buf ? d.u[1] : d.u[0])[vidx(n, p.i, p.j, p.k)] += prolong_at<T>((cbuf ? d.uc[1] : d.uc[0]), (n - 1) / 2 + 1, p.i, p.j, p.k);
+  gview<T>(buf ? d.u[1] : d.u[0])[vidx(n, p.i, p.j, p.k)] +=
+      prolong_at<T>(gview<T>(cbuf ? d.uc[1] : d.uc[0]), (n - 1) / 2 + 1, p.i, p.j, p.k);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_zero_u(const GridDescT<T>* __restrict__ list) {
-  const GridDescT<T> d = list[blockIdx.y];
+__global__ void __launch_bounds__(kBlock) k_zero_u(const GridDescT<T>* __restrict__ list,
+                                                   int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDescT<T> d = list[gi];
   const int n = d.n;
-  const Pt p = full_point(n, blockIdx.x);
+  const Pt p = full_point(n, blk);
   if (!p.ok) return;
   const int v = vidx(n, p.i, p.j, p.k);
   d.u[0][v] = 0;
@@ -472,11 +605,14 @@ __global__ void __launch_bounds__(kBlock) k_zero_u(const GridDescT<T>* __restric
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_copy_buf(const GridDescT<T>* __restrict__ list,
-                                                     const int* __restrict__ active, int from) {
-  const GridDescT<T> d = list[blockIdx.y];
+                                                     const int* __restrict__ active, int from,
+                                                     int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDescT<T> d = list[gi];
   if (!active[d.solve]) return;
   const int n = d.n;
-  const Pt p = full_point(n, blockIdx.x);
+  const Pt p = full_point(n, blk);
   if (!p.ok) return;
   const int v = vidx(n, p.i, p.j, p.k);
   if (from) d.u[0][v] = d.u[1][v];
@@ -485,33 +621,38 @@ __global__ void __launch_bounds__(kBlock) k_copy_buf(const GridDescT<T>* __restr
 
 // ---- reductions ---------------------------------------------------------------
 // Per-block partial sums over interior vertices of: b'^2 (RED_BNORM),
-// (b' - A'u)^2 (RED_RESID) or u (RED_QOI).  The block decomposition depends
-// only on the grid size, so a solve's sums never depend on the rest of the batch.
+// (b' - A'u)^2 (RED_RESID) or u (RED_QOI), blocks as in column marching.
+// The decomposition depends only on the grid size, so a solve's sums never
+// depend on the rest of the batch.
 __global__ void __launch_bounds__(kBlock) k_reduce(const GridDesc* __restrict__ list,
                                                    const int* __restrict__ active, int buf,
-                                                   int mode, double* __restrict__ partials) {
-  const GridDesc d = list[blockIdx.y];
+                                                   int mode, double* __restrict__ partials,
+                                                   int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDesc d = list[gi];
   if (mode == RED_RESID && !active[d.solve]) return;
-  const int n = d.n;
-  const Pt p = interior_point(n - 2, blockIdx.x);
-  double v = 0.0;
-  if (p.ok) {
-    const int q = vidx(n, p.i, p.j, p.k);
-    const double* u = (buf ? d.u[1] : d.u[0]);
-    const double bp = d.b ? d.b[q] : d.bconst;
-    if (mode == RED_BNORM) {
-      v = bp * bp;
-    } else if (mode == RED_RESID) {
-      double D, S;
-      stencil<double>(u, d.wh, q, n, n * n, D, S);
-      const double r = bp - (D * u[q] - S);
-      v = r * r;
+  const int n = d.n, sn2 = n * n;
+  const Col c = column_of(n - 2, blk);
+  const double* u = buf ? d.u[1] : d.u[0];
+  double acc = 0.0;
+  if (c.ok) {
+    if (mode == RED_RESID) {
+      march_residual<double>(d, u, c, [&](int, int, double r) { acc += r * r; });
     } else {
-      v = u[q];
+      int p = sn2 + c.j * n + c.k;
+      for (int i = 1; i <= n - 2; ++i, p += sn2) {
+        if (mode == RED_BNORM) {
+          const double bp = b_at<double>(d, i, c.j, c.k);
+          acc += bp * bp;
+        } else {
+          acc += u[p];
+        }
+      }
     }
   }
-  v = block_sum(v);
-  if (threadIdx.x == 0) partials[d.poff + blockIdx.x] = v;
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partials[d.poff + blk] = acc;
 }
 
 // Mixed precision outer step: r = b' - A'u (FP64) -> inner rhs (FP32), inner
@@ -519,36 +660,37 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const GridDesc* __restrict__ 
 __global__ void __launch_bounds__(kBlock) k_defect(const GridDesc* __restrict__ list,
                                                    const GridDesc32* __restrict__ list32,
                                                    const int* __restrict__ active,
-                                                   double* __restrict__ partials) {
-  const GridDesc d = list[blockIdx.y];
+                                                   double* __restrict__ partials, int count,
+                                                   int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDesc d = list[gi];
   if (!active[d.solve]) return;
-  const GridDesc32 e = list32[blockIdx.y];
-  const int n = d.n;
-  const Pt p = interior_point(n - 2, blockIdx.x);
-  double v = 0.0;
-  if (p.ok) {
-    const int q = vidx(n, p.i, p.j, p.k);
-    const double* u = d.u[0];
-    const double bp = d.b ? d.b[q] : d.bconst;
-    double D, S;
-    stencil<double>(u, d.wh, q, n, n * n, D, S);
-    const double r = bp - (D * u[q] - S);
-    v = r * r;
-    e.b[q] = (float)r;
-    e.u[0][q] = 0.0f;
-  }
-  v = block_sum(v);
-  if (threadIdx.x == 0) partials[d.poff + blockIdx.x] = v;
+  const GridDesc32 e = list32[gi];
+  const Col c = column_of(d.n - 2, blk);
+  double acc = 0.0;
+  const gptr<float> eb = gview<float>(e.b), eu = gview<float>(e.u[0]);
+  if (c.ok)
+    march_residual<double>(d, d.u[0], c, [&](int, int p, double r) {
+      acc += r * r;
+      eb[p] = (float)r;
+      eu[p] = 0.0f;
+    });
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partials[d.poff + blk] = acc;
 }
 
 __global__ void __launch_bounds__(kBlock) k_correct(const GridDesc* __restrict__ list,
                                                     const GridDesc32* __restrict__ list32,
-                                                    const int* __restrict__ active, int buf32) {
-  const GridDesc d = list[blockIdx.y];
+                                                    const int* __restrict__ active, int buf32,
+                                                    int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDesc d = list[gi];
   if (!active[d.solve]) return;
-  const GridDesc32 e = list32[blockIdx.y];
+  const GridDesc32 e = list32[gi];
   const int n = d.n;
-  const Pt p = interior_point(n - 2, blockIdx.x);
+  const Pt p = interior_point(n - 2, blk);
   if (!p.ok) return;
   const int q = vidx(n, p.i, p.j, p.k);
   d.u[0][q] += (double)(buf32 ? e.u[1] : e.u[0])[q];
@@ -633,8 +775,12 @@ __global__ void k_ydiff(const double* __restrict__ q, const int* __restrict__ fi
   }
 }
 
-inline dim3 interior_grid(int n, int count) { return dim3(point_blocks(n - 2), count); }
-inline dim3 full_grid(int n, int count) { return dim3(point_blocks(n), count); }
+__global__ void k_fill(double* __restrict__ p, long count, double value) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = value;
+}
+
+inline dim3 xcd_grid(int count, int per) { return dim3(8 * ceil_div(count * per, 8)); }
 
 template <typename T, int TJ, int TK>
 void sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
@@ -643,16 +789,23 @@ void sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_act
   const int tiles = tiles_k * tiles_j;
   const int chunk_len = ceil_div(n - 2, chunks);
   const int nch = ceil_div(n - 2, chunk_len);
-  hipLaunchKernelGGL((k_sweep<T, TJ, TK>), dim3(tiles * nch, count), dim3(kBlock), 0, st, d_list,
-                     d_active, buf, cbuf, tiles_k, tiles, chunk_len);
+  const int per = tiles * nch;
+  if (cbuf >= 0)
+    hipLaunchKernelGGL((k_sweep<T, TJ, TK, true>), xcd_grid(count, per),
+                       dim3(SweepGeom<TJ, TK>::THREADS), 0, st, d_list, d_active, buf, cbuf, tiles_k,
+                       tiles, chunk_len, count, per);
+  else
+    hipLaunchKernelGGL((k_sweep<T, TJ, TK, false>), xcd_grid(count, per),
+                       dim3(SweepGeom<TJ, TK>::THREADS), 0, st, d_list, d_active, buf, cbuf, tiles_k,
+                       tiles, chunk_len, count, per);
 }
 
 }  // namespace
 
 // ---- tile shapes ------------------------------------------------------------
 static const SweepShape kShapes[] = {
-    {4, 64, 1}, {16, 32, 1}, {8, 32, 1}, {4, 32, 1}, {16, 16, 1}, {8, 16, 1},
-    {4, 16, 1}, {8, 8, 1},   {4, 8, 1},  {4, 4, 1},  {2, 2, 1},
+    {8, 64, 1},  {4, 64, 1}, {16, 32, 1}, {8, 32, 1}, {4, 32, 1}, {16, 16, 1},
+    {8, 16, 1},  {4, 16, 1}, {8, 8, 1},   {4, 8, 1},  {4, 4, 1},  {2, 2, 1},
 };
 
 int sweep_shapes(int n, SweepShape* out, int max_out) {
@@ -674,35 +827,45 @@ SweepShape default_sweep_shape(int n) {
 
 // ---- launchers ------------------------------------------------------------------
 void launch_philox(const uint64_t* d_seeds, int count, int level, uint32_t* d_words,
-                   double* d_normals, hipStream_t st) {
+                   double* d_normals, hipStream_t st, const int* d_levels) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_philox, dim3(count), dim3(64), 0, st, d_seeds, level, d_words, d_normals);
+  hipLaunchKernelGGL(k_philox, dim3(count), dim3(64), 0, st, d_seeds, level, d_levels, d_words,
+                     d_normals);
 }
 
 void launch_field(int n, int count, double* const* d_out, const int* d_xi_index,
                   const double* d_normals, const double* d_phi, const double* d_coef, int mode,
                   hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_field, full_grid(n, count), dim3(kBlock), 0, st, n, d_out, d_xi_index,
-                     d_normals, d_phi, d_coef, mode);
+  const int per = point_blocks(n);
+  hipLaunchKernelGGL(k_field, xcd_grid(count, per), dim3(kBlock), 0, st, n, d_out, d_xi_index,
+                     d_normals, d_phi, d_coef, mode, count, per);
 }
 
 void launch_inject(int nf, int count, const double* const* d_fine, double* const* d_coarse,
                    hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_inject, full_grid((nf - 1) / 2 + 1, count), dim3(kBlock), 0, st, nf,
-                     d_fine, d_coarse);
+  const int per = point_blocks((nf - 1) / 2 + 1);
+  hipLaunchKernelGGL(k_inject, xcd_grid(count, per), dim3(kBlock), 0, st, nf, d_fine, d_coarse,
+                     count, per);
 }
 
 void launch_to_float(int n, int count, const double* const* d_src, float* const* d_dst,
                      hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_to_float, full_grid(n, count), dim3(kBlock), 0, st, n, d_src, d_dst);
+  const int per = point_blocks(n);
+  hipLaunchKernelGGL(k_to_float, xcd_grid(count, per), dim3(kBlock), 0, st, n, d_src, d_dst, count,
+                     per);
+}
+
+void launch_fill(double* p, long count, double value, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, value);
 }
 
 void launch_prepare_problem(int n, const double* k, const double* f, double* wh, double* b,
                             double* u, hipStream_t st) {
-  hipLaunchKernelGGL(k_prepare, full_grid(n, 1), dim3(kBlock), 0, st, n, k, f, wh, b, u);
+  hipLaunchKernelGGL(k_prepare, dim3(point_blocks(n)), dim3(kBlock), 0, st, n, k, f, wh, b, u);
 }
 
 template <typename T>
@@ -715,6 +878,7 @@ void launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_act
     sweep_launch<T, TJ_, TK_>(d_list, count, n, d_active, buf, cbuf, c, st);        \
     return;                                                                         \
   }
+  MG_SWEEP_CASE(8, 64)
   MG_SWEEP_CASE(4, 64)
   MG_SWEEP_CASE(16, 32)
   MG_SWEEP_CASE(8, 32)
@@ -733,24 +897,27 @@ template <typename T>
 void launch_rbgs_colour(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                         int colour, int buf, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_rbgs_colour<T>), interior_grid(n, count), dim3(kBlock), 0, st, d_list,
-                     d_active, colour, buf);
+  const int per = point_blocks(n - 2);
+  hipLaunchKernelGGL((k_rbgs_colour<T>), xcd_grid(count, per), dim3(kBlock), 0, st, d_list,
+                     d_active, colour, buf, count, per);
 }
 
 template <typename T>
 void launch_residual(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                      hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_residual<T>), interior_grid(n, count), dim3(kBlock), 0, st, d_list,
-                     d_active, buf);
+  const int per = reduce_blocks(n);
+  hipLaunchKernelGGL((k_residual<T>), xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
+                     buf, count, per);
 }
 
 template <typename T>
 void launch_restrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                      hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_restrict<T>), interior_grid((n - 1) / 2 + 1, count), dim3(kBlock), 0, st,
-                     d_list, d_active);
+  const int per = point_blocks((n - 1) / 2 - 1);
+  hipLaunchKernelGGL((k_restrict<T>), xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
+                     count, per);
 }
 
 template <typename T>
@@ -764,22 +931,25 @@ template <typename T>
 void launch_prolong(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                     int cbuf, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_prolong<T>), interior_grid(n, count), dim3(kBlock), 0, st, d_list,
-                     d_active, buf, cbuf);
+  const int per = point_blocks(n - 2);
+  hipLaunchKernelGGL((k_prolong<T>), xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
+                     buf, cbuf, count, per);
 }
 
 template <typename T>
 void launch_zero_u(const GridDescT<T>* d_list, int count, int n, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_zero_u<T>), full_grid(n, count), dim3(kBlock), 0, st, d_list);
+  const int per = point_blocks(n);
+  hipLaunchKernelGGL((k_zero_u<T>), xcd_grid(count, per), dim3(kBlock), 0, st, d_list, count, per);
 }
 
 template <typename T>
 void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_active, int from,
                      hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_copy_buf<T>), full_grid(n, count), dim3(kBlock), 0, st, d_list, d_active,
-                     from);
+  const int per = point_blocks(n);
+  hipLaunchKernelGGL((k_copy_buf<T>), xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
+                     from, count, per);
 }
 
 #define MG_INSTANTIATE(T)                                                                       \
@@ -801,22 +971,25 @@ MG_INSTANTIATE(float)
 void launch_reduce(const GridDesc* d_list, int count, int n, const int* d_active, int buf,
                    int mode, double* d_partials, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_reduce, interior_grid(n, count), dim3(kBlock), 0, st, d_list, d_active,
-                     buf, mode, d_partials);
+  const int per = reduce_blocks(n);
+  hipLaunchKernelGGL(k_reduce, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active, buf,
+                     mode, d_partials, count, per);
 }
 
 void launch_defect(const GridDesc* d_list, const GridDesc32* d_list32, int count, int n,
                    const int* d_active, double* d_partials, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_defect, interior_grid(n, count), dim3(kBlock), 0, st, d_list, d_list32,
-                     d_active, d_partials);
+  const int per = reduce_blocks(n);
+  hipLaunchKernelGGL(k_defect, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_list32,
+                     d_active, d_partials, count, per);
 }
 
 void launch_correct(const GridDesc* d_list, const GridDesc32* d_list32, int count, int n,
                     const int* d_active, int buf32, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_correct, interior_grid(n, count), dim3(kBlock), 0, st, d_list, d_list32,
-                     d_active, buf32);
+  const int per = point_blocks(n - 2);
+  hipLaunchKernelGGL(k_correct, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_list32,
+                     d_active, buf32, count, per);
 }
 
 void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,

@@ -146,3 +146,36 @@ def test_mixed_precision_batch(M, torch):
         r = O.mlmc_sample(33, 1, seeds[i])
         assert abs(Qf[i] - r["Qf"]) <= 1e-6 * abs(r["Qf"])
         assert abs(Qc[i] - r["Qc"]) <= 1e-6 * abs(r["Qc"])
+
+
+def test_mixed_level_batch_equals_per_level_batches(M, torch):
+    # four levels of n0 = 17 (17^3, 33^3, 65^3, 129^3 finest grids) in one batch
+    P = M.mg_plan_create(n0=17, max_level=3)
+    counts = {0: 6, 1: 4, 2: 3, 3: 2}
+    levels, seeds = [], []
+    for l, c in counts.items():
+        levels += [l] * c
+        seeds += [1000 * l + i for i in range(c)]
+    order = np.random.default_rng(0).permutation(len(levels))  # interleave the levels
+    levels = [levels[i] for i in order]
+    seeds = [seeds[i] for i in order]
+    n = len(levels)
+    Y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    Qf, Qc = torch.zeros_like(Y), torch.zeros_like(Y)
+    cyc = torch.zeros(2 * n, dtype=torch.int32, device="cuda")
+    assert M.mlmc_sample_mixed(P, levels, np.asarray(seeds, dtype=np.uint64), n, Y, Qf, Qc, cyc) == M.MG_OK
+    Y, Qf, Qc, cyc = Y.cpu().numpy(), Qf.cpu().numpy(), Qc.cpu().numpy(), cyc.cpu().numpy().reshape(n, 2)
+    P2 = M.mg_plan_create(n0=17, max_level=3)
+    for l in counts:
+        idx = [i for i in range(n) if levels[i] == l]
+        st, y, qf, qc, cy = _batch(M, torch, P2, l, [seeds[i] for i in idx])
+        assert st == M.MG_OK
+        assert np.array_equal(Y[idx], y) and np.array_equal(Qf[idx], qf) and np.array_equal(Qc[idx], qc)
+        assert np.array_equal(cyc[idx].ravel(), cy)
+    # and against the oracle for one sample of each level
+    for l in counts:
+        i = [k for k in range(n) if levels[k] == l][0]
+        r = O.mlmc_sample(17, l, seeds[i])
+        assert abs(Qf[i] - r["Qf"]) <= 1e-9 * abs(r["Qf"])
+        assert abs(Y[i] - r["Y"]) <= 1e-9 * (abs(r["Qf"]) + abs(r["Qc"]))
+        assert tuple(cyc[i]) == tuple(r["cycles"])
