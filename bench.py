@@ -32,16 +32,26 @@ HBM_PEAK_GBPS = 8000.0
 SWEEP_BYTES_PER_NODE = 24.0
 # byte model of one FP64 V(2,2) cycle per finest-grid node (whole hierarchy)
 VCYCLE_BYTES_PER_NODE = 195.0
+# mixed precision per outer step: FP32 V(2,2) (~98) + FP64 defect and update (48)
+MIXED_BYTES_PER_NODE = 146.0
 
 
-def cpu_baseline(n0, level, samples, threads):
+def cpu_baseline(n0, level, threads, min_seconds, max_samples=4096):
+    """The oracle on `threads` host threads, one sample per thread, in rounds
+    of `threads` samples until min_seconds have passed."""
     import oracle as O
-    seeds = list(range(10**6, 10**6 + samples))
+    done, seed = 0, 10**6
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(threads) as ex:
-        res = list(ex.map(lambda s: O.mlmc_sample(n0, level, s), seeds))
-    dt = time.perf_counter() - t0
-    return samples / dt, dt, res
+        while True:
+            seeds = list(range(seed, seed + threads))
+            list(ex.map(lambda s: O.mlmc_sample(n0, level, s), seeds))
+            seed += threads
+            done += threads
+            dt = time.perf_counter() - t0
+            if dt >= min_seconds or done >= max_samples:
+                break
+    return done / dt, dt, done
 
 
 def main():
@@ -51,7 +61,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--samples", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="minimum wall time of the CPU oracle baseline")
+    ap.add_argument("--workload", default="levelpair",
+                    choices=["levelpair", "single", "mixed", "fp32mix", "serve"])
+    ap.add_argument("--serve-requests", type=int, default=2048)
+    ap.add_argument("--serve-slots", default="128,64,16,4")
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
+    ap.add_argument("--no-fifo", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--tile", action="append", default=[],
@@ -72,8 +89,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
     if not os.path.exists(M.LIB_PATH):
-        from paper_1607_03252_amd import build
-        build.build()
+        raise SystemExit("libmlmcmg.so is not built: run `python -m paper_1607_03252_amd.build`")
+    if args.workload != "levelpair":
+        fn = {"single": bench_single, "mixed": bench_mixed, "fp32mix": bench_fp32mix,
+              "serve": bench_serve}[args.workload]
+        print(json.dumps(fn(args, M, torch, np)), flush=True)
+        return
 
     n0, level, S = 33, 1, args.samples
     P = M.mg_plan_create(n0=n0, max_level=level, sigma2=1.0, corr_len=0.1, tol=1e-8,
@@ -127,6 +148,17 @@ def main():
     nf, nc = (n0 - 1) * 2**level + 1, (n0 - 1) * 2**(level - 1) + 1
     eff = VCYCLE_BYTES_PER_NODE * (nf**3 + nc**3) * S * cyc_mean * args.steps / dt / 1e9
 
+    traffic, traffic_src = None, None
+    summ = os.path.join(ROOT, "profiles", "k_sweep_traffic_levelpair65_33x64.txt")
+    if os.path.exists(summ):
+        from paper_1607_03252_amd import profsum
+        rec = profsum.read_summary(summ)
+        # counters apply only to the same kernel source and tile shape
+        if rec.get("kernel_source_sha256") == profsum.source_hash() and \
+                list(rec.get("tile") or []) == list(tiles[65]):
+            traffic = rec.get("hbm_bytes_per_launch")
+            traffic_src = os.path.relpath(summ, ROOT)
+
     out = {
         "metric": "MLMC samples/sec per level + V-cycle HBM GB/s; p50/p99 solve latency",
         "value": value,
@@ -148,18 +180,283 @@ def main():
                                    "effective_vcycle_GBps": eff,
                                    "batch_latency_ms": ms_step}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "kernel": "k_sweep (fused red-black sweep, 65^3 grids)", "launches": launches,
                      "tile": list(tiles[65]),
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_launch},
     }
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
-        v, cdt, _ = cpu_baseline(n0, level, args.cpu_samples, threads)
+        v, cdt, done = cpu_baseline(n0, level, threads, args.cpu_seconds)
         out["cpu_baseline"] = {"value": v, "unit": "samples/s", "cores": threads, "kind": "oracle",
                                "sample": "%d samples of the same level pair (seeds 1e6..), one "
-                                         "sample per thread, %.1f s wall" % (args.cpu_samples, cdt)}
+                                         "sample per thread, %.1f s wall" % (done, cdt)}
     print(json.dumps(out), flush=True)
+
+
+# ---- the other execution forms (one JSON line each, --workload ...) ----------------
+
+def _line(metric, value, unit, steps, warmup, ms_step, config, higher=True, dtype="f64"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": ms_step, "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic (Philox-seeded 64-term KL lognormal fields)", "config": config}
+
+
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def _samples(M, torch, P, level, seeds):
+    n = len(seeds)
+    Y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    Qf, Qc = torch.zeros_like(Y), torch.zeros_like(Y)
+    cyc = torch.zeros(2 * n, dtype=torch.int32, device="cuda")
+    return Y, Qf, Qc, cyc
+
+
+def bench_single(args, M, torch, np):
+    """One sample of level 0 on 33^3 (31^3 unknowns, five multigrid levels):
+    latency per sample, HIP graphs vs eager launches, and of mg_solve alone."""
+    n0, reps = 33, max(200, args.steps)
+    P = M.mg_plan_create(n0=n0, max_level=0)
+    Y, Qf, Qc, cyc = _samples(M, torch, P, 0, [0])
+    seeds = np.zeros(1, dtype=np.uint64)
+    res = {}
+    for mode in (1, 0):
+        M.mg_plan_set_option(P, "graph", mode)
+        for _ in range(max(10, args.warmup)):
+            M.mlmc_sample_batch(P, 0, seeds, 1, Y, Qf, Qc, cyc)
+        lat = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            M.mlmc_sample_batch(P, 0, seeds, 1, Y, Qf, Qc, cyc)
+            lat.append(1e6 * (time.perf_counter() - t0))
+        res["graph" if mode else "eager"] = {"p50_us": _pct(lat, 50), "p99_us": _pct(lat, 99)}
+    cycles = int(cyc[0].item())
+    # the solve alone on the same coefficient (mg_solve: caller's k, f, u)
+    k = torch.empty(n0**3, dtype=torch.float64, device="cuda")
+    M.mlmc_field(P, n0, 0, 0, k)
+    f = torch.ones_like(k)
+    u = torch.zeros_like(k)
+    lat = []
+    for r in range(reps + 10):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M.mg_solve(P, n0, k, f, u)
+        if r >= 10:
+            lat.append(1e6 * (time.perf_counter() - t0))
+    res["mg_solve"] = {"p50_us": _pct(lat, 50), "p99_us": _pct(lat, 99)}
+    out = _line("single-sample latency (p50, HIP graphs)", res["graph"]["p50_us"], "us", reps,
+                args.warmup, res["graph"]["p50_us"] / 1e3,
+                {"workload": "single_sample_level0_n33", "n": n0, "seed": 0, "sigma2": 1.0,
+                 "corr_len": 0.1, "tol": 1e-8, "cycle": "V(2,2) red-black GS, 5 levels"},
+                higher=False)
+    out["latency"] = res
+    out["cycles"] = cycles
+    return out
+
+
+def bench_mixed(args, M, torch, np):
+    """Batched uneven form: levels 0..3 of n0 = 17 (17^3 .. 129^3 fine grids)
+    with 128/64/48/16 samples in one batch (384 solves), against the same
+    samples as per-level batches and one at a time."""
+    counts = {0: 128, 1: 64, 2: 48, 3: 16}
+    levels, seeds = [], []
+    s = 0
+    for l, c in counts.items():
+        levels += [l] * c
+        seeds += list(range(s, s + c))
+        s += c
+    n = len(levels)
+    P = M.mg_plan_create(n0=17, max_level=3)
+    Y, Qf, Qc, cyc = _samples(M, torch, P, 0, seeds)
+    sd = np.asarray(seeds, dtype=np.uint64)
+    for _ in range(max(1, args.warmup)):
+        M.mlmc_sample_mixed(P, levels, sd, n, Y, Qf, Qc, cyc)
+    steps = max(1, min(args.steps, 10))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        M.mlmc_sample_mixed(P, levels, sd, n, Y, Qf, Qc, cyc)
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / steps
+    cy = cyc.cpu().numpy().reshape(n, 2)
+    nodes = 0.0
+    for i, l in enumerate(levels):
+        nf = 16 * 2**l + 1
+        nodes += nf**3 * cy[i, 0] + ((nf - 1) // 2 + 1)**3 * cy[i, 1] * (l > 0)
+    # the same samples level by level, and one sample at a time
+    per_level, t_levels, t_plain = {}, 0.0, 0.0
+    for l, c in counts.items():
+        Pl = M.mg_plan_create(n0=17, max_level=3)
+        idx = [i for i in range(n) if levels[i] == l]
+        s_l = sd[idx]
+        Yl, Qfl, Qcl, cl = _samples(M, torch, Pl, l, idx)
+        M.mlmc_sample_batch(Pl, l, s_l, len(idx), Yl, Qfl, Qcl, cl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            M.mlmc_sample_batch(Pl, l, s_l, len(idx), Yl, Qfl, Qcl, cl)
+        torch.cuda.synchronize()
+        tl = (time.perf_counter() - t0) / steps
+        t_levels += tl
+        same = bool(torch.equal(Yl, Y[idx]))
+        P1 = M.mg_plan_create(n0=17, max_level=3)
+        Y1, Qf1, Qc1, c1 = _samples(M, torch, P1, l, [0])
+        M.mlmc_sample_batch(P1, l, s_l[:1], 1, Y1, Qf1, Qc1, c1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(len(idx)):
+            M.mlmc_sample_batch(P1, l, s_l[i:i + 1], 1, Y1, Qf1, Qc1, c1)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        t_plain += tp
+        per_level[str(l)] = {"samples": c, "fine_n": 16 * 2**l + 1,
+                             "level_batch_samples_per_s": c / tl,
+                             "one_at_a_time_samples_per_s": c / tp,
+                             "mixed_equals_level_batch": same}
+    value = n / t_mixed
+    out = _line("MLMC samples/s, levels 0..3 in one batch", value, "samples/s", steps,
+                args.warmup, 1e3 * t_mixed,
+                {"workload": "mixed_levels_n0_17_counts_128_64_48_16", "n0": 17,
+                 "levels": "0..3", "counts": [128, 64, 48, 16], "solves": 384, "sigma2": 1.0,
+                 "corr_len": 0.1, "tol": 1e-8})
+    out["per_level"] = per_level
+    out["speedup_vs_level_batches"] = t_levels / t_mixed
+    out["speedup_vs_one_at_a_time"] = t_plain / t_mixed
+    out["effective_vcycle_GBps"] = VCYCLE_BYTES_PER_NODE * nodes / t_mixed / 1e9
+    return out
+
+
+def bench_fp32mix(args, M, torch, np):
+    """Mixed precision: 16 samples on 257^3 (sigma^2 = 2, lambda = 0.05),
+    FP32 inner V-cycles in FP64 defect correction against plain FP64."""
+    S, n = 16, 257
+    seeds = np.arange(S, dtype=np.uint64)
+    res = {}
+    Q = {}
+    for name, prec in (("fp64", M.MG_FP64), ("mixed", M.MG_MIXED)):
+        P = M.mg_plan_create(n0=n, max_level=0, sigma2=2.0, corr_len=0.05, precision=prec)
+        Y, Qf, Qc, cyc = _samples(M, torch, P, 0, seeds)
+        M.mlmc_sample_batch(P, 0, seeds, S, Y, Qf, Qc, cyc)
+        steps = max(1, min(args.steps, 3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            M.mlmc_sample_batch(P, 0, seeds, S, Y, Qf, Qc, cyc)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        c = cyc.cpu().numpy().reshape(S, 2)[:, 0]
+        per_node = VCYCLE_BYTES_PER_NODE if prec == M.MG_FP64 else MIXED_BYTES_PER_NODE
+        res[name] = {"batch_s": dt, "samples_per_s": S / dt, "cycles_mean": float(c.mean()),
+                     "effective_GBps": per_node * n**3 * float(c.sum()) / dt / 1e9}
+        Q[name] = Qf.cpu().numpy()
+        del P
+        torch.cuda.empty_cache()
+    dq = float(np.max(np.abs(Q["mixed"] - Q["fp64"]) / np.abs(Q["fp64"])))
+    out = _line("MLMC samples/s, mixed precision 257^3", res["mixed"]["samples_per_s"],
+                "samples/s", 3, 1, 1e3 * res["mixed"]["batch_s"],
+                {"workload": "mixed_precision_n257_x16", "n": n, "samples": S, "sigma2": 2.0,
+                 "corr_len": 0.05, "tol": 1e-8}, dtype="f64+f32")
+    out["forms"] = res
+    out["speedup_mixed_vs_fp64"] = res["fp64"]["batch_s"] / res["mixed"]["batch_s"]
+    out["max_rel_dQ_mixed_vs_fp64"] = dq
+    return out
+
+
+def bench_serve(args, M, torch, np):
+    """Serving: requests for samples of levels 0..3 of n0 = 33 (33^3 .. 257^3
+    fine grids), level l with probability proportional to 4^-l, through the
+    continuous-batching server; saturation throughput, then Poisson arrivals
+    at fractions of it (p50/p99 latency), and the same traces through a plain
+    first-in-first-out path that solves one sample at a time."""
+    L, N = 3, args.serve_requests
+    slots = [int(x) for x in args.serve_slots.split(",")]
+    loads = [float(x) for x in args.serve_loads.split(",")]
+    p = np.array([4.0 ** -l for l in range(L + 1)])
+    lv = np.random.Generator(np.random.PCG64(0)).choice(L + 1, size=N, p=p / p.sum())
+    gaps = np.random.Generator(np.random.PCG64(1)).exponential(1.0, size=N)
+    P = M.mg_plan_create(n0=33, max_level=L)
+    S = M.Server(P, slots, queue_capacity=N + 1)
+
+    def run_server(arrivals):
+        # arrivals: server-clock times (None: all at once)
+        res = []
+        base = S.now()
+        i = 0
+        while len(res) < N:
+            now = S.now() - base
+            while i < N and (arrivals is None or arrivals[i] <= now):
+                S.submit(int(lv[i]), i, i, base + (0.0 if arrivals is None else arrivals[i]))
+                i += 1
+            q, r, _ = S.counts()
+            if q == 0 and r == 0 and i < N:
+                while S.now() - base < arrivals[i]:
+                    pass
+                continue
+            res += S.step(1)
+        lat = [x["t_done"] - x["t_arrival"] for x in res]
+        span = max(x["t_done"] for x in res) - base
+        return res, lat, span
+
+    # warm: graphs and every slot once
+    for i in range(sum(slots)):
+        S.submit(min(L, i % (L + 1)), 10**6 + i, -1)
+    while S.counts()[1] or S.counts()[0]:
+        S.step(1)
+    res, lat, span = run_server(None)
+    sat = N / span
+    acc = {l: M.mlmc_acc_init() for l in range(L + 1)}
+    for x in res:
+        M.mlmc_acc_add(acc[x["level"]], [x["Y"]])
+    est, var_sum = 0.0, 0.0
+    for l in range(L + 1):
+        m, v = M.mlmc_acc_result(acc[l])
+        est += m
+        var_sum += v / max(1, acc[l].n)
+    out = _line("served MLMC samples/s at saturation (levels 0..3 of n0=33)", sat, "samples/s",
+                N, sum(slots), 1e3 * span / N,
+                {"workload": "serve_n0_33_levels_0_3_p_4^-l", "n0": 33, "levels": "0..3",
+                 "requests": N, "slots_per_level": slots, "cycles_per_step": 1, "sigma2": 1.0,
+                 "corr_len": 0.1, "tol": 1e-8})
+    out["saturation"] = {"samples_per_s": sat, "p50_ms": 1e3 * _pct(lat, 50),
+                         "p99_ms": 1e3 * _pct(lat, 99),
+                         "mlmc_estimate": est, "sampling_rms": var_sum ** 0.5,
+                         "requests_per_level": [int((lv == l).sum()) for l in range(L + 1)]}
+    # the plain path: one plan per level, one sample per call, in arrival order
+    fifo_plans = {}
+    if not args.no_fifo:
+        for l in range(L + 1):
+            Pl = M.mg_plan_create(n0=33, max_level=L)
+            bufs = _samples(M, torch, Pl, l, [0])
+            M.mlmc_sample_batch(Pl, l, np.zeros(1, dtype=np.uint64), 1, *bufs)
+            fifo_plans[l] = (Pl, bufs)
+    out["loads"] = {}
+    for rho in loads:
+        lam = rho * sat
+        arr = np.cumsum(gaps) / lam
+        res, lat, span = run_server(arr)
+        rec = {"offered_per_s": lam, "served_per_s": N / span, "p50_ms": 1e3 * _pct(lat, 50),
+               "p99_ms": 1e3 * _pct(lat, 99)}
+        if fifo_plans:
+            lat_f = []
+            t0 = time.perf_counter()
+            for i in range(N):
+                while time.perf_counter() - t0 < arr[i]:
+                    pass
+                Pl, bufs = fifo_plans[int(lv[i])]
+                M.mlmc_sample_batch(Pl, int(lv[i]), np.array([i], dtype=np.uint64), 1, *bufs)
+                lat_f.append(time.perf_counter() - t0 - arr[i])
+            span_f = time.perf_counter() - t0
+            rec["fifo"] = {"served_per_s": N / span_f, "p50_ms": 1e3 * _pct(lat_f, 50),
+                           "p99_ms": 1e3 * _pct(lat_f, 99)}
+        out["loads"][str(rho)] = rec
+        print("load %.2f: %s" % (rho, json.dumps(rec)), file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":

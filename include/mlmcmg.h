@@ -140,6 +140,82 @@ int mg_get_tile(mg_plan plan, int n, int* tj, int* tk, int* chunks);
  * and keeps the fastest per size in the plan. */
 int mg_autotune(mg_plan plan, int level, int n_samples, int reps);
 
+/* Serving: continuous batching of MLMC sample requests --------------------
+ *
+ * A request asks for one sample Y_level(seed) (Algorithm 1, steps 1.a.i-ii,
+ * as mlmc_sample_batch with one seed).  The server keeps a fixed pool of
+ * resident sample slots per level in one workspace (its grids stay in HBM
+ * for the server's life), admits queued requests into free slots between
+ * cycles, advances every occupied slot by the same launches (as
+ * mlmc_sample_mixed), and retires each sample as soon as both of its solves
+ * have stopped.  A sample's results do not depend on what else is resident:
+ * they equal those of mlmc_sample_batch for that seed and level, bit for bit.
+ */
+
+/* Device bytes of one resident sample slot of `level` (fine and coarse
+ * hierarchies, FP32 twins in mixed precision, state).  *bytes: host. */
+int mg_sample_footprint(mg_plan plan, int level, size_t* bytes);
+
+/* Admission scheduler (host only, no device work; the server uses it).
+ * Requests wait in one queue in arrival order; level l owns slots
+ * [first_l, first_l + slots_per_level[l]).  mg_sched_admit walks the queue
+ * from its head and gives each request whose level has a free slot the
+ * lowest free slot of that level, so each level is served in arrival order
+ * and a full level does not hold back the others. */
+typedef struct mg_sched_s* mg_sched;
+typedef struct {
+  long long tag;     /* caller's request id */
+  uint64_t seed;
+  int level;
+  int slot;          /* assigned slot */
+  double t_arrival;  /* caller's arrival time, seconds */
+} mg_ticket;
+/* slots_per_level: host int[n_levels], each >= 0; queue_capacity >= 1. */
+int mg_sched_create(int n_levels, const int* slots_per_level, int queue_capacity, mg_sched* out);
+int mg_sched_destroy(mg_sched s);
+/* MG_EINVAL for a level outside [0, n_levels), MG_EBUSY when the queue is full. */
+int mg_sched_submit(mg_sched s, int level, uint64_t seed, long long tag, double t_arrival);
+/* Writes up to max_out admitted tickets to out (host) and their number to *n_out. */
+int mg_sched_admit(mg_sched s, mg_ticket* out, int max_out, int* n_out);
+/* MG_EINVAL if the slot is not busy. */
+int mg_sched_release(mg_sched s, int slot);
+int mg_sched_counts(mg_sched s, int* queued, int* busy);
+
+typedef struct mg_server_s* mg_server;
+typedef struct {
+  long long tag;
+  uint64_t seed;
+  int level;
+  int status;              /* MG_OK, or MG_ENOCONV if a solve missed tol   */
+  double Y, Qf, Qc;        /* as mlmc_sample_batch                          */
+  int cycles_fine, cycles_coarse;
+  double t_arrival;        /* as submitted                                  */
+  double t_admit, t_done;  /* server clock (mg_serve_now), seconds          */
+} mg_result;
+
+/* Create a server on a plan (levels 0..max_level of the plan).
+ * slots_per_level: host int[max_level + 1] (each >= 0), or NULL to size the
+ * pools from the plan's hbm_budget (8 GiB if 0): each level gets an equal
+ * share of the budget, divided by mg_sample_footprint, clamped to [1, 256].
+ * MG_ENOMEM if the pools exceed the budget.  The plan must outlive the
+ * server; calls on the plan and on its servers must not overlap. */
+int mg_serve_create(mg_plan plan, const int* slots_per_level, int queue_capacity, mg_server* out);
+int mg_serve_destroy(mg_server s);
+/* Queue one request.  t_arrival < 0: stamped with mg_serve_now(). */
+int mg_serve_submit(mg_server s, int level, uint64_t seed, long long tag, double t_arrival);
+/* One scheduling step: admit queued requests into free slots (their fields
+ * and coefficient hierarchies are generated on the device), advance every
+ * occupied slot by `cycles` V-cycles (>= 1; graph-captured), then return the
+ * samples that finished (up to max_out per call; the rest come with the
+ * next call).  out: host mg_result[max_out]; *n_out: how many were written.
+ * Blocking.  With nothing queued or resident it returns at once. */
+int mg_serve_step(mg_server s, int cycles, mg_result* out, int max_out, int* n_out);
+/* Seconds since the server was created (steady clock). */
+double mg_serve_now(mg_server s);
+int mg_serve_counts(mg_server s, int* queued, int* resident, long long* completed);
+/* Slot pool size of a level (after NULL sizing), or -1. */
+int mg_serve_slots(mg_server s, int level);
+
 /* Test and parity exports ------------------------------------------------- */
 
 /* Philox4x32-10 words of samples on the device: words_out (device) receives

@@ -5,8 +5,10 @@ memory (CUDA tensors on ROCm) and the stream.  There is no CPU fallback: if
 the library is missing or no GPU is present, calls raise.
 
 Functions carry the C names: ``mg_plan_create``, ``mg_solve``,
-``mlmc_sample_batch``, ``mlmc_philox``, ``mlmc_field``, ``mlmc_acc_*``,
-``mg_profile_*``.
+``mlmc_sample_batch``, ``mlmc_sample_mixed``, ``mlmc_philox``, ``mlmc_field``,
+``mlmc_acc_*``, ``mg_profile_*``, ``mg_sample_footprint``; the scheduler and
+the server are the classes ``Sched`` (mg_sched_*) and ``Server``
+(mg_serve_*).
 """
 from __future__ import annotations
 
@@ -35,6 +37,18 @@ class mg_plan_desc(C.Structure):
                 ("max_cycles", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
                 ("sigma2", C.c_double), ("corr_len", C.c_double), ("kl_per_axis", C.c_int),
                 ("hbm_budget", C.c_size_t), ("stream", C.c_void_p)]
+
+
+class mg_ticket(C.Structure):
+    _fields_ = [("tag", C.c_longlong), ("seed", C.c_uint64), ("level", C.c_int), ("slot", C.c_int),
+                ("t_arrival", C.c_double)]
+
+
+class mg_result(C.Structure):
+    _fields_ = [("tag", C.c_longlong), ("seed", C.c_uint64), ("level", C.c_int),
+                ("status", C.c_int), ("Y", C.c_double), ("Qf", C.c_double), ("Qc", C.c_double),
+                ("cycles_fine", C.c_int), ("cycles_coarse", C.c_int), ("t_arrival", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
 class mlmc_level_acc(C.Structure):
@@ -76,6 +90,21 @@ def lib():
         L.mg_set_tile.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.mg_get_tile.argtypes = [vp, C.c_int, ip, ip, ip]
         L.mg_autotune.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        L.mg_sample_footprint.argtypes = [vp, C.c_int, C.POINTER(C.c_size_t)]
+        L.mg_sched_create.argtypes = [C.c_int, ip, C.c_int, C.POINTER(vp)]
+        L.mg_sched_destroy.argtypes = [vp]
+        L.mg_sched_submit.argtypes = [vp, C.c_int, C.c_uint64, C.c_longlong, C.c_double]
+        L.mg_sched_admit.argtypes = [vp, C.POINTER(mg_ticket), C.c_int, ip]
+        L.mg_sched_release.argtypes = [vp, C.c_int]
+        L.mg_sched_counts.argtypes = [vp, ip, ip]
+        L.mg_serve_create.argtypes = [vp, ip, C.c_int, C.POINTER(vp)]
+        L.mg_serve_destroy.argtypes = [vp]
+        L.mg_serve_submit.argtypes = [vp, C.c_int, C.c_uint64, C.c_longlong, C.c_double]
+        L.mg_serve_step.argtypes = [vp, C.c_int, C.POINTER(mg_result), C.c_int, ip]
+        L.mg_serve_now.argtypes = [vp]
+        L.mg_serve_now.restype = C.c_double
+        L.mg_serve_counts.argtypes = [vp, ip, ip, C.POINTER(C.c_longlong)]
+        L.mg_serve_slots.argtypes = [vp, C.c_int]
         L.mg_last_error.argtypes = [vp]
         L.mg_last_error.restype = C.c_char_p
         _lib = L
@@ -88,7 +117,10 @@ def exported_symbols():
             "mg_solve", "mlmc_sample_batch", "mlmc_philox", "mlmc_field", "mlmc_acc_init",
             "mlmc_acc_add", "mlmc_acc_result", "mg_profile_enable", "mg_profile_read",
             "mg_last_error", "mg_plan_set_option", "mg_set_tile", "mg_get_tile", "mg_autotune",
-            "mlmc_sample_mixed"]
+            "mlmc_sample_mixed", "mg_sample_footprint", "mg_sched_create", "mg_sched_destroy",
+            "mg_sched_submit", "mg_sched_admit", "mg_sched_release", "mg_sched_counts",
+            "mg_serve_create", "mg_serve_destroy", "mg_serve_submit", "mg_serve_step",
+            "mg_serve_now", "mg_serve_counts", "mg_serve_slots"]
 
 
 def _torch():
@@ -291,3 +323,114 @@ def mg_profile_read(plan: Plan):
     n, ms, nodes = C.c_longlong(), C.c_double(), C.c_double()
     plan.check(lib().mg_profile_read(plan.handle, C.byref(n), C.byref(ms), C.byref(nodes)))
     return n.value, ms.value, nodes.value
+
+
+# ---- serving -------------------------------------------------------------------
+
+def mg_sample_footprint(plan: Plan, level: int) -> int:
+    b = C.c_size_t()
+    plan.check(lib().mg_sample_footprint(plan.handle, level, C.byref(b)))
+    return b.value
+
+
+class Sched:
+    """Admission scheduler (host only): mg_sched_* on one handle."""
+
+    def __init__(self, slots_per_level, queue_capacity=1 << 16):
+        a = np.ascontiguousarray(np.asarray(slots_per_level, dtype=np.int32))
+        h = C.c_void_p()
+        st = lib().mg_sched_create(int(a.size), a.ctypes.data_as(C.POINTER(C.c_int)),
+                                   int(queue_capacity), C.byref(h))
+        if st != MG_OK:
+            raise MGError(st, "mg_sched_create rejected its arguments")
+        self.handle = h
+
+    def submit(self, level, seed, tag, t_arrival=0.0):
+        """Returns the status (MG_OK, MG_EBUSY or MG_EINVAL)."""
+        return lib().mg_sched_submit(self.handle, int(level), int(seed), int(tag), float(t_arrival))
+
+    def admit(self, max_out=1024):
+        buf = (mg_ticket * max_out)()
+        n = C.c_int()
+        st = lib().mg_sched_admit(self.handle, buf, max_out, C.byref(n))
+        if st != MG_OK:
+            raise MGError(st, "mg_sched_admit")
+        return [(buf[i].tag, buf[i].seed, buf[i].level, buf[i].slot, buf[i].t_arrival)
+                for i in range(n.value)]
+
+    def release(self, slot):
+        return lib().mg_sched_release(self.handle, int(slot))
+
+    def counts(self):
+        q, b = C.c_int(), C.c_int()
+        lib().mg_sched_counts(self.handle, C.byref(q), C.byref(b))
+        return q.value, b.value
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().mg_sched_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving handle (mg_serve_*): continuous batching on one plan."""
+
+    def __init__(self, plan: Plan, slots_per_level=None, queue_capacity=1 << 16):
+        self.plan = plan
+        h = C.c_void_p()
+        if slots_per_level is None:
+            p = None
+        else:
+            self._slots = np.ascontiguousarray(np.asarray(slots_per_level, dtype=np.int32))
+            if self._slots.size != plan.desc.max_level + 1:
+                raise ValueError("slots_per_level needs max_level + 1 entries")
+            p = self._slots.ctypes.data_as(C.POINTER(C.c_int))
+        plan.check(lib().mg_serve_create(plan.handle, p, int(queue_capacity), C.byref(h)))
+        self.handle = h
+
+    def submit(self, level, seed, tag, t_arrival=-1.0):
+        """Returns MG_OK or MG_EBUSY (queue full); raises on bad arguments."""
+        st = lib().mg_serve_submit(self.handle, int(level), int(seed), int(tag), float(t_arrival))
+        return self.plan.check(st, (MG_OK, MG_EBUSY))
+
+    def step(self, cycles=1, max_out=4096):
+        """One scheduling step; returns the finished samples as dicts."""
+        buf = (mg_result * max_out)()
+        n = C.c_int()
+        self.plan.check(lib().mg_serve_step(self.handle, int(cycles), buf, max_out, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            r = buf[i]
+            out.append({"tag": r.tag, "seed": r.seed, "level": r.level, "status": r.status,
+                        "Y": r.Y, "Qf": r.Qf, "Qc": r.Qc, "cycles": (r.cycles_fine, r.cycles_coarse),
+                        "t_arrival": r.t_arrival, "t_admit": r.t_admit, "t_done": r.t_done})
+        return out
+
+    def now(self):
+        return lib().mg_serve_now(self.handle)
+
+    def counts(self):
+        q, r, c = C.c_int(), C.c_int(), C.c_longlong()
+        lib().mg_serve_counts(self.handle, C.byref(q), C.byref(r), C.byref(c))
+        return q.value, r.value, c.value
+
+    def slots(self, level):
+        return lib().mg_serve_slots(self.handle, int(level))
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().mg_serve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def mg_serve_create(plan: Plan, slots_per_level=None, queue_capacity=1 << 16) -> Server:
+    return Server(plan, slots_per_level, queue_capacity)

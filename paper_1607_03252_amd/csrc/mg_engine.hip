@@ -14,9 +14,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <string>
@@ -25,6 +27,7 @@
 #include "../../include/mlmcmg.h"
 #include "mg_internal.h"
 #include "mg_kl.h"
+#include "mg_sched.h"
 
 namespace mg {
 
@@ -209,8 +212,10 @@ static const double* phi_table(mg_plan_s* P, int n) {
   return d;
 }
 
-// Allocate a batch.  One device allocation holds every grid buffer.
-static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec) {
+// Allocate a batch.  One device allocation holds every grid buffer.  With
+// size_only, only the bytes that allocation would take are computed.
+static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
+                                          size_t* size_only = nullptr) {
   auto B = std::make_unique<Batch>();
   B->spec = spec;
   const int ns = (int)spec.top_n.size();
@@ -262,10 +267,14 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec) {
     }
     int npart = 0;
     for (int s = 0; s < ns; ++s) npart += reduce_blocks(spec.top_n[s]);
-    int* ai = (int*)take(sizeof(int) * (ns * 2 + 2));
+    int* ai = (int*)take(sizeof(int) * (ns * 4 + 2));
     double* dd = (double*)take(sizeof(double) * ns * 3);
     double* pp = (double*)take(sizeof(double) * npart);
     if (pass == 0) {
+      if (size_only) {
+        *size_only = total;
+        return nullptr;
+      }
       if (P->desc.hbm_budget && total > P->desc.hbm_budget) return nullptr;
       CK(hipMalloc(&B->mem, total));
       // zero boundaries and state once; later kernels only write interiors
@@ -275,8 +284,10 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec) {
     } else {
       B->ss.active = ai;
       B->ss.cycles = ai + ns;
-      B->d_count = ai + 2 * ns;
-      B->d_cycle = ai + 2 * ns + 1;
+      B->ss.start = ai + 2 * ns;
+      B->ss.qpend = ai + 3 * ns;
+      B->d_count = ai + 4 * ns;
+      B->d_cycle = ai + 4 * ns + 1;
       B->ss.relres = dd;
       B->ss.bnorm = dd + ns;
       B->ss.q = dd + 2 * ns;
@@ -521,7 +532,6 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
 }
 
 void launch_tick(int* ctr, hipStream_t st);
-void launch_init_state2(int* active, int* cycles, int* cycle_ctr, int ns, hipStream_t st);
 void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
                       const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
                       hipStream_t st);
@@ -576,7 +586,7 @@ static hipGraphExec_t graph_for(mg_plan_s* P, Batch* B, int c, double tol, int f
 // fixed_cycles).  Returns true when every solve met tol.
 static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graphs) {
   hipStream_t st = P->work;
-  launch_init_state2(B->ss.active, B->ss.cycles, B->d_cycle, B->ns, st);
+  launch_init_state2(B->ss, B->d_cycle, B->ns, st);
   for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
     const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
     launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_BNORM, B->ss.partials, st);
@@ -729,6 +739,239 @@ static int run_samples(mg_plan_s* P, const std::vector<int>& levels, const uint6
     return MG_ENOCONV;
   }
   return MG_OK;
+}
+
+
+// ---- serving: continuous batching over resident sample slots --------------------
+
+}  // namespace mg
+
+struct mg_server_s {
+  mg_plan_s* P = nullptr;
+  std::unique_ptr<mg::Batch> B;
+  std::unique_ptr<mg::Scheduler> sched;
+  int nslots = 0;
+  std::vector<int> slot_level, fi, ci;  // per slot: level, fine and coarse solve
+  std::vector<std::pair<int, int>> top_pos;  // per solve: (top size index, list index)
+  struct Slot {
+    bool busy = false;
+    long long tag = 0;
+    uint64_t seed = 0;
+    double t_arrival = 0, t_admit = 0;
+  };
+  std::vector<Slot> slot;
+  int resident = 0;
+  long long completed = 0;
+  std::deque<mg_result> done;
+  // staging of per-step admission lists (pinned host mirror + device copy)
+  char* h_stage = nullptr;
+  char* d_stage = nullptr;
+  size_t stage_bytes = 0;
+  double* d_normals = nullptr;
+  int* h_state = nullptr;     // active, cycles, start, qpend of every solve
+  double* h_q = nullptr;
+  std::map<int, hipGraphExec_t> graphs;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  ~mg_server_s() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (d_stage) (void)hipFree(d_stage);
+    if (d_normals) (void)hipFree(d_normals);
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (h_state) (void)hipHostFree(h_state);
+    if (h_q) (void)hipHostFree(h_q);
+  }
+};
+
+namespace mg {
+
+// Appends arrays to the pinned staging buffer; device addresses mirror it.
+struct Packer {
+  mg_server_s* S;
+  size_t used = 0;
+  template <typename T>
+  T* put(const std::vector<T>& v) {
+    used = (used + 255) & ~(size_t)255;
+    if (used + v.size() * sizeof(T) > S->stage_bytes) throw HipError{hipErrorOutOfMemory, "serve staging"};
+    std::memcpy(S->h_stage + used, v.data(), v.size() * sizeof(T));
+    T* d = (T*)(S->d_stage + used);
+    used += v.size() * sizeof(T);
+    return d;
+  }
+};
+
+static size_t sample_bytes(mg_plan_s* P, int level) {
+  size_t b = 0;
+  build_batch(P, mlmc_spec(P, std::vector<int>{level}), &b);
+  return b;
+}
+
+// Fields, coefficient hierarchies, zero iterates and solve state of the
+// samples just admitted into slots.
+static void serve_admit(mg_server_s* S, const std::vector<Ticket>& tk) {
+  mg_plan_s* P = S->P;
+  Batch* B = S->B.get();
+  hipStream_t st = P->work;
+  const int m = (int)tk.size();
+  Packer pk{S};
+  std::vector<uint64_t> seeds(m);
+  std::vector<int> levels(m), admit;
+  for (int j = 0; j < m; ++j) {
+    seeds[j] = tk[j].seed;
+    levels[j] = tk[j].level;
+    admit.push_back(S->fi[tk[j].slot]);
+    if (S->ci[tk[j].slot] >= 0) admit.push_back(S->ci[tk[j].slot]);
+  }
+  uint64_t* d_seeds = pk.put(seeds);
+  int* d_levels = pk.put(levels);
+  int* d_admit = pk.put(admit);
+  // fields of the fine solves, grouped by level
+  struct Group { int n, count; double** out; int* xi; };
+  std::vector<Group> fields;
+  for (int l = 0; l <= P->desc.max_level; ++l) {
+    std::vector<double*> out;
+    std::vector<int> xi;
+    for (int j = 0; j < m; ++j)
+      if (levels[j] == l) {
+        out.push_back(B->lev[S->fi[tk[j].slot]][0].wh);
+        xi.push_back(j);
+      }
+    if (!out.empty()) fields.push_back(Group{level_n(P, l), (int)out.size(), pk.put(out), pk.put(xi)});
+  }
+  // injection down each new fine hierarchy (finest size first) and FP32 copies
+  struct Lst { int n, count; double** src; double** dst; float** fdst; };
+  std::vector<Lst> inj, cvt;
+  for (size_t si = 0; si < B->sizes.size(); ++si) {
+    std::vector<double*> src, dst, csrc;
+    std::vector<float*> cdst;
+    for (int j = 0; j < m; ++j) {
+      const int fs = S->fi[tk[j].slot];
+      const auto& lv = B->lev[fs];
+      for (size_t q = 0; q < lv.size(); ++q) {
+        if (lv[q].n != B->sizes[si]) continue;
+        if (q + 1 < lv.size()) {
+          src.push_back(lv[q].wh);
+          dst.push_back(lv[q + 1].wh);
+        }
+        if (B->spec.mixed) {
+          csrc.push_back(lv[q].wh);
+          cdst.push_back(B->lev32[fs][q].wh);
+        }
+      }
+    }
+    if (!src.empty()) inj.push_back(Lst{B->sizes[si], (int)src.size(), pk.put(src), pk.put(dst), nullptr});
+    if (!csrc.empty()) cvt.push_back(Lst{B->sizes[si], (int)csrc.size(), pk.put(csrc), nullptr, pk.put(cdst)});
+  }
+  // top-grid descriptors of the new solves, per top size
+  std::vector<std::pair<int, GridDesc*>> zero;
+  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+    std::vector<GridDesc> v;
+    for (int sv : admit)
+      if (S->top_pos[sv].first == (int)ti) v.push_back(B->L64.htop[ti][S->top_pos[sv].second]);
+    if (!v.empty()) zero.push_back({(int)v.size(), pk.put(v)});
+    else zero.push_back({0, nullptr});
+  }
+  CK(hipMemcpyAsync(S->d_stage, S->h_stage, pk.used, hipMemcpyHostToDevice, st));
+  launch_philox(d_seeds, m, 0, nullptr, S->d_normals, st, d_levels);
+  for (const auto& g : fields)
+    launch_field(g.n, g.count, g.out, g.xi, S->d_normals, phi_table(P, g.n), P->d_coef, 0, st);
+  for (const auto& l : inj) launch_inject(l.n, l.count, (const double* const*)l.src, l.dst, st);
+  for (const auto& l : cvt) launch_to_float(l.n, l.count, (const double* const*)l.src, l.fdst, st);
+  for (size_t ti = 0; ti < zero.size(); ++ti)
+    if (zero[ti].first) launch_zero_u<double>(zero[ti].second, zero[ti].first, B->top_sizes[ti], st);
+  launch_admit(d_admit, (int)admit.size(), B->ss, B->d_cycle, st);
+}
+
+// c cycles of every resident solve, then the QoI of the solves that stopped.
+static void serve_cycles(mg_server_s* S, int c) {
+  mg_plan_s* P = S->P;
+  Batch* B = S->B.get();
+  for (int i = 0; i < c; ++i) cycle_step(P, B, P->desc.tol, 0);
+  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_QOI_PENDING, B->ss.partials,
+                  P->work, B->ss.qpend);
+    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI_PENDING, B->d_cycle, 0, 0, 0, 0.0,
+                     P->work);
+  }
+}
+
+static void serve_run(mg_server_s* S, int c) {
+  mg_plan_s* P = S->P;
+  if (!P->use_graph || P->prof) {
+    serve_cycles(S, c);
+    return;
+  }
+  auto it = S->graphs.find(c);
+  if (it == S->graphs.end()) {
+    hipGraph_t g = nullptr;
+    CK(hipStreamBeginCapture(P->work, hipStreamCaptureModeThreadLocal));
+    serve_cycles(S, c);
+    CK(hipStreamEndCapture(P->work, &g));
+    hipGraphExec_t ex = nullptr;
+    CK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    CK(hipGraphDestroy(g));
+    it = S->graphs.emplace(c, ex).first;
+  }
+  CK(hipGraphLaunch(it->second, P->work));
+}
+
+static void serve_step(mg_server_s* S, int c) {
+  mg_plan_s* P = S->P;
+  Batch* B = S->B.get();
+  hipStream_t st = P->work;
+  std::vector<Ticket> tk(S->nslots);
+  tk.resize(S->sched->admit(tk.data(), S->nslots));
+  if (!tk.empty()) {
+    const double t = S->now();
+    for (const Ticket& x : tk) {
+      auto& sl = S->slot[x.slot];
+      sl.busy = true;
+      sl.tag = x.tag;
+      sl.seed = x.seed;
+      sl.t_arrival = x.t_arrival;
+      sl.t_admit = t;
+      ++S->resident;
+    }
+    serve_admit(S, tk);
+  }
+  if (S->resident == 0) return;
+  serve_run(S, c);
+  const int ns = B->ns;
+  CK(hipMemcpyAsync(S->h_state, B->ss.active, sizeof(int) * 4 * ns, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(S->h_q, B->ss.q, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (P->prof) collect_profile(P);
+  const double t = S->now();
+  const int* cyc = S->h_state + ns;
+  const int* pend = S->h_state + 3 * ns;
+  for (int s = 0; s < S->nslots; ++s) {
+    auto& sl = S->slot[s];
+    if (!sl.busy) continue;
+    const int f = S->fi[s], g = S->ci[s];
+    if (pend[f] || (g >= 0 && pend[g])) continue;
+    mg_result r{};
+    r.tag = sl.tag;
+    r.seed = sl.seed;
+    r.level = S->slot_level[s];
+    r.Qf = S->h_q[f];
+    r.Qc = g >= 0 ? S->h_q[g] : 0.0;
+    r.Y = r.Qf - r.Qc;
+    r.cycles_fine = cyc[f];
+    r.cycles_coarse = g >= 0 ? cyc[g] : 0;
+    r.status = (r.cycles_fine < 0 || r.cycles_coarse < 0) ? MG_ENOCONV : MG_OK;
+    r.t_arrival = sl.t_arrival;
+    r.t_admit = sl.t_admit;
+    r.t_done = t;
+    S->done.push_back(r);
+    sl.busy = false;
+    --S->resident;
+    ++S->completed;
+    S->sched->release(s);
+  }
 }
 
 }  // namespace mg
@@ -972,7 +1215,7 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
         SweepShape s = shapes[i];
         s.chunks = chunks;
         // every solve active while timing; the next batch reinitialises the workspace
-        launch_init_state2(B->ss.active, B->ss.cycles, B->d_cycle, B->ns, P->work);
+        launch_init_state2(B->ss, B->d_cycle, B->ns, P->work);
         auto one = [&]() {
           if (mixed)
             launch_sweep<float>(B->L32.d[si], (int)B->L32.h[si].size(), n, B->ss.active, 0, -1,
@@ -1108,6 +1351,142 @@ int mg_profile_read(mg_plan P, long long* launches, double* total_ms, double* no
   if (nodes_per_launch) *nodes_per_launch = P->prof_nodes;
   return MG_OK;
   API_END(P)
+}
+
+int mg_sample_footprint(mg_plan P, int level, size_t* bytes) {
+  if (!P || !bytes || level < 0 || level > P->desc.max_level) return MG_EINVAL;
+  API_BEGIN
+  *bytes = sample_bytes(P, level);
+  return MG_OK;
+  API_END(P)
+}
+
+int mg_serve_create(mg_plan P, const int* slots_per_level, int queue_capacity, mg_server* out) {
+  if (!P || !out) return MG_EINVAL;
+  *out = nullptr;
+  if (queue_capacity < 1) {
+    P->err = "mg_serve_create: queue_capacity must be >= 1";
+    return MG_EINVAL;
+  }
+  API_BEGIN
+  const int L = P->desc.max_level;
+  const size_t budget = P->desc.hbm_budget ? P->desc.hbm_budget : ((size_t)8 << 30);
+  std::vector<int> cap(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    if (slots_per_level) {
+      cap[l] = slots_per_level[l];
+      if (cap[l] < 0) {
+        P->err = "mg_serve_create: negative slot count";
+        return MG_EINVAL;
+      }
+    } else {
+      const size_t f = sample_bytes(P, l);
+      const size_t c = budget / (size_t)(L + 1) / f;
+      cap[l] = (int)std::max<size_t>(1, std::min<size_t>(256, c));
+    }
+  }
+  std::vector<int> levels;
+  for (int l = 0; l <= L; ++l) levels.insert(levels.end(), cap[l], l);
+  if (levels.empty()) {
+    P->err = "mg_serve_create: no slots";
+    return MG_EINVAL;
+  }
+  const BatchSpec spec = mlmc_spec(P, levels);
+  size_t need = 0;
+  build_batch(P, spec, &need);
+  if (need > budget) {
+    P->err = "mg_serve_create: slot pools exceed the HBM budget";
+    return MG_ENOMEM;
+  }
+  auto S = std::make_unique<mg_server_s>();
+  S->P = P;
+  S->B = build_batch(P, spec);
+  if (!S->B) {
+    P->err = "mg_serve_create: slot pools exceed the HBM budget";
+    return MG_ENOMEM;
+  }
+  Batch* B = S->B.get();
+  upload_lists(P, B);
+  S->sched = std::make_unique<Scheduler>(cap, queue_capacity);
+  S->nslots = (int)levels.size();
+  S->slot_level = levels;
+  S->slot.assign(S->nslots, mg_server_s::Slot{});
+  int sv = 0;
+  for (int l : levels) {
+    S->fi.push_back(sv);
+    S->ci.push_back(l > 0 ? sv + 1 : -1);
+    sv += l > 0 ? 2 : 1;
+  }
+  S->top_pos.assign(B->ns, {-1, -1});
+  for (size_t ti = 0; ti < B->L64.htop.size(); ++ti)
+    for (size_t i = 0; i < B->L64.htop[ti].size(); ++i)
+      S->top_pos[B->L64.htop[ti][i].solve] = {(int)ti, (int)i};
+  // staging for one step's admissions (at most every slot at once)
+  S->stage_bytes = (size_t)S->nslots * 1536 + 65536;
+  CK(hipHostMalloc((void**)&S->h_stage, S->stage_bytes, hipHostMallocDefault));
+  CK(hipMalloc((void**)&S->d_stage, S->stage_bytes));
+  CK(hipMalloc((void**)&S->d_normals, sizeof(double) * 64 * S->nslots));
+  CK(hipHostMalloc((void**)&S->h_state, sizeof(int) * 4 * B->ns, hipHostMallocDefault));
+  CK(hipHostMalloc((void**)&S->h_q, sizeof(double) * B->ns, hipHostMallocDefault));
+  // ||b'|| of every solve (constant right-hand side, fixed for the server's
+  // life); the workspace starts zeroed: no solve active, counter 0
+  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_BNORM, B->ss.partials, P->work);
+    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, B->d_cycle, 0, 0,
+                     P->desc.max_cycles, P->desc.tol, P->work);
+  }
+  CK(hipStreamSynchronize(P->work));
+  S->t0 = std::chrono::steady_clock::now();
+  *out = S.release();
+  return MG_OK;
+  API_END(P)
+}
+
+int mg_serve_destroy(mg_server S) {
+  if (!S) return MG_EINVAL;
+  if (S->P && S->P->work) (void)hipStreamSynchronize(S->P->work);
+  delete S;
+  return MG_OK;
+}
+
+int mg_serve_submit(mg_server S, int level, uint64_t seed, long long tag, double t_arrival) {
+  if (!S) return MG_EINVAL;
+  const int st = S->sched->submit(level, seed, tag, t_arrival < 0 ? S->now() : t_arrival);
+  if (st == MG_EINVAL) S->P->err = "mg_serve_submit: level outside [0, max_level]";
+  if (st == MG_EBUSY) S->P->err = "mg_serve_submit: queue full";
+  return st;
+}
+
+int mg_serve_step(mg_server S, int cycles, mg_result* out, int max_out, int* n_out) {
+  if (!S || !n_out || cycles < 1 || max_out < 0 || (max_out > 0 && !out)) return MG_EINVAL;
+  mg_plan P = S->P;
+  *n_out = 0;
+  API_BEGIN
+  if (S->resident > 0 || S->sched->queued() > 0) serve_step(S, cycles);
+  int n = 0;
+  while (n < max_out && !S->done.empty()) {
+    out[n++] = S->done.front();
+    S->done.pop_front();
+  }
+  *n_out = n;
+  return MG_OK;
+  API_END(P)
+}
+
+double mg_serve_now(mg_server S) { return S ? S->now() : 0.0; }
+
+int mg_serve_counts(mg_server S, int* queued, int* resident, long long* completed) {
+  if (!S) return MG_EINVAL;
+  if (queued) *queued = S->sched->queued();
+  if (resident) *resident = S->resident;
+  if (completed) *completed = S->completed;
+  return MG_OK;
+}
+
+int mg_serve_slots(mg_server S, int level) {
+  if (!S || level < 0 || level >= S->sched->levels()) return -1;
+  return S->sched->first_slot(level + 1) - S->sched->first_slot(level);
 }
 
 }  // extern "C"

@@ -42,9 +42,13 @@ struct SolveState {
   double* bnorm;    // ||b'||_2 (1 when b' = 0)
   double* q;        // QoI of the solve's top grid
   double* partials; // reduction partials
+  int* start;       // cycle counter value when the solve was started
+  int* qpend;       // 1 from admission until the QoI of a stopped solve is taken
 };
 
-enum ReduceMode { RED_BNORM = 0, RED_RESID = 1, RED_QOI = 2 };
+// RED_QOI_PENDING: the QoI of solves that have stopped (active 0) but whose
+// QoI is still pending (qpend 1); it clears qpend.
+enum ReduceMode { RED_BNORM = 0, RED_RESID = 1, RED_QOI = 2, RED_QOI_PENDING = 3 };
 
 // Point kernels cover the interior (or, for the "full" kernels, every vertex)
 // with 256-thread blocks of 4 rows (j) x 64 columns (k) of one plane i.
@@ -115,8 +119,9 @@ template <typename T>
 void launch_zero_u(const GridDescT<T>* d_list, int count, int n, hipStream_t st);
 
 // Reductions on the top grids of solves.
+// d_pend: the solves' qpend flags (RED_QOI_PENDING only).
 void launch_reduce(const GridDesc* d_list, int count, int n, const int* d_active, int buf,
-                   int mode, double* d_partials, hipStream_t st);
+                   int mode, double* d_partials, hipStream_t st, const int* d_pend = nullptr);
 // Mixed precision: r = b' - A'u in FP64 on the top grids, stored rounded to
 // FP32 as the inner right-hand side d_list32[g].b (whose u[0] is zeroed),
 // plus the partial sums of r^2.
@@ -125,13 +130,18 @@ void launch_defect(const GridDesc* d_list, const GridDesc32* d_list32, int count
 // Mixed precision: u[0] += (double) e32 on the top grids.
 void launch_correct(const GridDesc* d_list, const GridDesc32* d_list32, int count, int n,
                     const int* d_active, int buf32, hipStream_t st);
-// Finalise per solve.  The cycle judged is *cycle_ctr - lag; fixed_cycles > 0
-// selects fixed-count mode.
+// Finalise per solve.  The cycle judged is *cycle_ctr - start - lag;
+// fixed_cycles > 0 selects fixed-count mode.
 void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
                       const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
                       hipStream_t st);
-// active = 1, cycles = 0, *cycle_ctr = 0; launch_tick: *cycle_ctr += 1.
-void launch_init_state2(int* active, int* cycles, int* cycle_ctr, int ns, hipStream_t st);
+// active = 1, cycles = 0, start = 0, qpend = 0, *cycle_ctr = 0;
+// launch_tick: *cycle_ctr += 1.
+void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st);
+// Start the listed solves now: active = 1, cycles = 0, start = *cycle_ctr,
+// qpend = 1.
+void launch_admit(const int* d_solves, int count, SolveState s, const int* cycle_ctr,
+                  hipStream_t st);
 void launch_tick(int* ctr, hipStream_t st);
 void launch_count_active(const int* d_active, int nsolves, int* d_count, hipStream_t st);
 void launch_ydiff(const double* d_q, const int* d_fine_idx, const int* d_coarse_idx, int count,

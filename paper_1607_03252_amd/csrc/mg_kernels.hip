@@ -627,11 +627,13 @@ __global__ void __launch_bounds__(kBlock) k_copy_buf(const GridDescT<T>* __restr
 __global__ void __launch_bounds__(kBlock) k_reduce(const GridDesc* __restrict__ list,
                                                    const int* __restrict__ active, int buf,
                                                    int mode, double* __restrict__ partials,
-                                                   int count, int per) {
+                                                   const int* __restrict__ pend, int count,
+                                                   int per) {
   int gi, blk;
   if (!xcd_unit(count, per, gi, blk)) return;
   const GridDesc d = list[gi];
   if (mode == RED_RESID && !active[d.solve]) return;
+  if (mode == RED_QOI_PENDING && (!pend[d.solve] || active[d.solve])) return;
   const int n = d.n, sn2 = n * n;
   const Col c = column_of(n - 2, blk);
   const double* u = buf ? d.u[1] : d.u[0];
@@ -707,6 +709,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
   const GridDesc d = list[blockIdx.x];
   const int sv = d.solve;
   if (mode == RED_RESID && !s.active[sv]) return;
+  if (mode == RED_QOI_PENDING && (!s.qpend[sv] || s.active[sv])) return;
   const int P = reduce_blocks(d.n);
   double v = 0.0;
   for (int q = threadIdx.x; q < P; q += kBlock) v += s.partials[d.poff + q];
@@ -716,7 +719,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
     const double nb = sqrt(v);
     s.bnorm[sv] = nb > 0.0 ? nb : 1.0;
   } else if (mode == RED_RESID) {
-    const int cycle = *cycle_ctr - lag;
+    const int cycle = *cycle_ctr - s.start[sv] - lag;
     const double rho = sqrt(v) / s.bnorm[sv];
     s.relres[sv] = rho;
     if (fixed_cycles > 0) {
@@ -734,16 +737,29 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
   } else {
     const double h = 1.0 / (double)(d.n - 1);
     s.q[sv] = h * h * h * v;
+    if (mode == RED_QOI_PENDING) s.qpend[sv] = 0;
   }
 }
 
-__global__ void k_init_state(int* __restrict__ active, int* __restrict__ cycles,
-                             int* __restrict__ cycle_ctr, int ns) {
+__global__ void k_init_state(SolveState s, int* __restrict__ cycle_ctr, int ns) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) *cycle_ctr = 0;
   if (t >= ns) return;
-  active[t] = 1;
-  cycles[t] = 0;
+  s.active[t] = 1;
+  s.cycles[t] = 0;
+  s.start[t] = 0;
+  s.qpend[t] = 0;
+}
+
+__global__ void k_admit(const int* __restrict__ solves, int count, SolveState s,
+                        const int* __restrict__ cycle_ctr) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int sv = solves[t];
+  s.active[sv] = 1;
+  s.cycles[sv] = 0;
+  s.start[sv] = *cycle_ctr;
+  s.qpend[sv] = 1;
 }
 
 __global__ void k_tick(int* __restrict__ ctr) {
@@ -969,11 +985,11 @@ MG_INSTANTIATE(float)
 #undef MG_INSTANTIATE
 
 void launch_reduce(const GridDesc* d_list, int count, int n, const int* d_active, int buf,
-                   int mode, double* d_partials, hipStream_t st) {
+                   int mode, double* d_partials, hipStream_t st, const int* d_pend) {
   if (count <= 0) return;
   const int per = reduce_blocks(n);
   hipLaunchKernelGGL(k_reduce, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active, buf,
-                     mode, d_partials, count, per);
+                     mode, d_partials, d_pend, count, per);
 }
 
 void launch_defect(const GridDesc* d_list, const GridDesc32* d_list32, int count, int n,
@@ -1000,9 +1016,15 @@ void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
                      fixed_cycles, max_cycles, tol);
 }
 
-void launch_init_state2(int* active, int* cycles, int* cycle_ctr, int ns, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_state, dim3((ns + 255) / 256), dim3(256), 0, st, active, cycles,
-                     cycle_ctr, ns);
+void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_state, dim3((ns + 255) / 256), dim3(256), 0, st, s, cycle_ctr, ns);
+}
+
+void launch_admit(const int* d_solves, int count, SolveState s, const int* cycle_ctr,
+                  hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_admit, dim3((count + 255) / 256), dim3(256), 0, st, d_solves, count, s,
+                     cycle_ctr);
 }
 
 void launch_tick(int* ctr, hipStream_t st) {
