@@ -129,27 +129,33 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
 int mg_plan_set_option(mg_plan plan, const char* name, long long value);
 
 /* Tile shape of the fused smoother on grids of size n: tj rows (j) by tk
- * columns (k) per workgroup, the planes split into `chunks` pieces.  Only the
- * compiled shapes whose tj, tk divide n-1 are accepted (MG_EINVAL otherwise). */
+ * columns (k) per workgroup, the planes split into `chunks` pieces (0 = chosen
+ * per launch from the number of grids: the march is split until the launch
+ * has about 1024 workgroups, at least four planes per piece).  Only the
+ * compiled shapes whose tj, tk divide n-1 are accepted (MG_EINVAL otherwise).
+ * A server captures the shapes in force at its first step. */
 int mg_set_tile(mg_plan plan, int n, int tj, int tk, int chunks);
 int mg_get_tile(mg_plan plan, int n, int* tj, int* tk, int* chunks);
 
 /* Autotuner: runs one batch of n_samples samples of `level` (seeds
- * 0x5eed0000 + i), then times every compiled tile shape and chunk count of the
- * smoother on each grid size of that batch (reps launches each, HIP events)
- * and keeps the fastest per size in the plan. */
+ * 0x5eed0000 + i), then times every compiled tile shape with chunk counts
+ * 0 (automatic), 1, 2, 4 of the smoother on each grid size of that batch
+ * (reps launches each, HIP events) and keeps the fastest per size in the
+ * plan. */
 int mg_autotune(mg_plan plan, int level, int n_samples, int reps);
 
 /* Serving: continuous batching of MLMC sample requests --------------------
  *
  * A request asks for one sample Y_level(seed) (Algorithm 1, steps 1.a.i-ii,
- * as mlmc_sample_batch with one seed).  The server keeps a fixed pool of
- * resident sample slots per level in one workspace (its grids stay in HBM
- * for the server's life), admits queued requests into free slots between
- * cycles, advances every occupied slot by the same launches (as
- * mlmc_sample_mixed), and retires each sample as soon as both of its solves
- * have stopped.  A sample's results do not depend on what else is resident:
- * they equal those of mlmc_sample_batch for that seed and level, bit for bit.
+ * as mlmc_sample_batch with one seed).  The server keeps, per level, a fixed
+ * pool of resident sample slots (a lane: one workspace, its own stream and
+ * graphs; the grids stay in HBM for the server's life).  Lanes progress
+ * independently: when a lane's launch has finished, its finished samples
+ * leave, queued requests of its level are admitted into the freed slots
+ * (fields and coefficient hierarchies generated on the device), and the lane
+ * is launched again while the other lanes' work is still on the device.  A
+ * sample's results do not depend on what else is resident: they equal those
+ * of mlmc_sample_batch for that seed and level, bit for bit.
  */
 
 /* Device bytes of one resident sample slot of `level` (fine and coarse
@@ -203,12 +209,13 @@ int mg_serve_create(mg_plan plan, const int* slots_per_level, int queue_capacity
 int mg_serve_destroy(mg_server s);
 /* Queue one request.  t_arrival < 0: stamped with mg_serve_now(). */
 int mg_serve_submit(mg_server s, int level, uint64_t seed, long long tag, double t_arrival);
-/* One scheduling step: admit queued requests into free slots (their fields
- * and coefficient hierarchies are generated on the device), advance every
- * occupied slot by `cycles` V-cycles (>= 1; graph-captured), then return the
- * samples that finished (up to max_out per call; the rest come with the
- * next call).  out: host mg_result[max_out]; *n_out: how many were written.
- * Blocking.  With nothing queued or resident it returns at once. */
+/* One scheduling step: harvest every lane whose last launch has finished,
+ * admit queued requests into the free slots of idle lanes, launch `cycles`
+ * V-cycles (>= 1; graph-captured) on every idle lane that holds samples, and
+ * wait until at least one lane has finished if none had.  Returns the
+ * samples that finished (up to max_out per call; the rest come with the next
+ * call).  out: host mg_result[max_out]; *n_out: how many were written.  With
+ * nothing queued or resident it returns at once. */
 int mg_serve_step(mg_server s, int cycles, mg_result* out, int max_out, int* n_out);
 /* Seconds since the server was created (steady clock). */
 double mg_serve_now(mg_server s);

@@ -22,6 +22,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mlmcmg.h"
@@ -79,6 +80,7 @@ struct Lists {
 
 struct Batch {
   BatchSpec spec;
+  hipStream_t st = nullptr;  // stream the batch's cycles run on
   int ns = 0;
   std::vector<std::vector<LevelT<double>>> lev;    // [solve][mg level]
   std::vector<std::vector<LevelT<float>>> lev32;   // mixed precision only
@@ -218,6 +220,7 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
                                           size_t* size_only = nullptr) {
   auto B = std::make_unique<Batch>();
   B->spec = spec;
+  B->st = P->work;
   const int ns = (int)spec.top_n.size();
   B->ns = ns;
   B->lev.resize(ns);
@@ -474,7 +477,7 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
                        bool timed) {
   const int n = B->sizes[si];
   const int cnt = (int)Ls.h[si].size();
-  hipStream_t st = P->work;
+  hipStream_t st = B->st;
   if (timed) {
     if (P->ev_used + 4 > 8192) collect_profile(P);
     CK(hipEventRecord(next_event(P), st));
@@ -502,7 +505,7 @@ template <typename T>
 static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
   const int nu1 = P->desc.nu1, nu2 = P->desc.nu2;
   const size_t L = B->sizes.size();
-  hipStream_t st = P->work;
+  hipStream_t st = B->st;
   std::vector<int> cur(L, 0);
   for (size_t si = 0; si < L; ++si) {
     const int n = B->sizes[si];
@@ -538,7 +541,7 @@ void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
 
 // One outer iteration for every active solve (recorded into graphs as is).
 static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed) {
-  hipStream_t st = P->work;
+  hipStream_t st = B->st;
   launch_tick(B->d_cycle, st);
   if (!B->spec.mixed) {
     const int out = run_cycle<double>(P, B, B->L64);
@@ -572,9 +575,9 @@ static hipGraphExec_t graph_for(mg_plan_s* P, Batch* B, int c, double tol, int f
   auto it = B->graphs.find(c);
   if (it != B->graphs.end()) return it->second;
   hipGraph_t g = nullptr;
-  CK(hipStreamBeginCapture(P->work, hipStreamCaptureModeThreadLocal));
+  CK(hipStreamBeginCapture(B->st, hipStreamCaptureModeThreadLocal));
   for (int i = 0; i < c; ++i) cycle_step(P, B, tol, fixed);
-  CK(hipStreamEndCapture(P->work, &g));
+  CK(hipStreamEndCapture(B->st, &g));
   hipGraphExec_t ex = nullptr;
   CK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
   CK(hipGraphDestroy(g));
@@ -585,7 +588,7 @@ static hipGraphExec_t graph_for(mg_plan_s* P, Batch* B, int c, double tol, int f
 // Cycle every solve of the batch until each has converged (or run exactly
 // fixed_cycles).  Returns true when every solve met tol.
 static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graphs) {
-  hipStream_t st = P->work;
+  hipStream_t st = B->st;
   launch_init_state2(B->ss, B->d_cycle, B->ns, st);
   for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
     const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
@@ -743,61 +746,80 @@ static int run_samples(mg_plan_s* P, const std::vector<int>& levels, const uint6
 
 
 // ---- serving: continuous batching over resident sample slots --------------------
+//
+// One lane per MLMC level: a batch holding that level's slot pool, its own
+// stream, graphs and staging buffers.  Lanes progress independently: a lane
+// whose launch has finished is harvested (finished samples leave, their
+// slots free up), admits queued requests of its level into free slots and is
+// launched again, while the other lanes' work is still on the device.  So a
+// small sample never waits for the cycles of larger ones.
+
+struct Lane {
+  int level = 0, first = 0, nslots = 0;
+  std::unique_ptr<Batch> B;
+  hipStream_t st = nullptr;
+  std::vector<int> fi, ci;                   // per local slot: fine and coarse solve
+  std::vector<std::pair<int, int>> top_pos;  // per solve: (top size index, list index)
+  char* h_stage = nullptr;
+  char* d_stage = nullptr;
+  size_t stage_bytes = 0;
+  double* d_normals = nullptr;
+  int* h_state = nullptr;  // active, cycles, start, qpend of every solve
+  double* h_q = nullptr;
+  hipEvent_t done = nullptr;
+  bool inflight = false;
+  int resident = 0;
+  std::map<int, hipGraphExec_t> graphs;
+  ~Lane() {
+    if (st) (void)hipStreamSynchronize(st);
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    B.reset();
+    if (d_stage) (void)hipFree(d_stage);
+    if (d_normals) (void)hipFree(d_normals);
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (h_state) (void)hipHostFree(h_state);
+    if (h_q) (void)hipHostFree(h_q);
+    if (done) (void)hipEventDestroy(done);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
 
 }  // namespace mg
 
 struct mg_server_s {
   mg_plan_s* P = nullptr;
-  std::unique_ptr<mg::Batch> B;
+  std::vector<std::unique_ptr<mg::Lane>> lanes;  // by level (empty pools: null)
   std::unique_ptr<mg::Scheduler> sched;
-  int nslots = 0;
-  std::vector<int> slot_level, fi, ci;  // per slot: level, fine and coarse solve
-  std::vector<std::pair<int, int>> top_pos;  // per solve: (top size index, list index)
   struct Slot {
     bool busy = false;
     long long tag = 0;
     uint64_t seed = 0;
     double t_arrival = 0, t_admit = 0;
   };
-  std::vector<Slot> slot;
+  std::vector<Slot> slot;  // global slot index
   int resident = 0;
   long long completed = 0;
   std::deque<mg_result> done;
-  // staging of per-step admission lists (pinned host mirror + device copy)
-  char* h_stage = nullptr;
-  char* d_stage = nullptr;
-  size_t stage_bytes = 0;
-  double* d_normals = nullptr;
-  int* h_state = nullptr;     // active, cycles, start, qpend of every solve
-  double* h_q = nullptr;
-  std::map<int, hipGraphExec_t> graphs;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
-  ~mg_server_s() {
-    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
-    if (d_stage) (void)hipFree(d_stage);
-    if (d_normals) (void)hipFree(d_normals);
-    if (h_stage) (void)hipHostFree(h_stage);
-    if (h_state) (void)hipHostFree(h_state);
-    if (h_q) (void)hipHostFree(h_q);
-  }
 };
 
 namespace mg {
 
-// Appends arrays to the pinned staging buffer; device addresses mirror it.
+// Appends arrays to a lane's pinned staging buffer; device addresses mirror it.
 struct Packer {
-  mg_server_s* S;
+  Lane* ln;
   size_t used = 0;
   template <typename T>
   T* put(const std::vector<T>& v) {
     used = (used + 255) & ~(size_t)255;
-    if (used + v.size() * sizeof(T) > S->stage_bytes) throw HipError{hipErrorOutOfMemory, "serve staging"};
-    std::memcpy(S->h_stage + used, v.data(), v.size() * sizeof(T));
-    T* d = (T*)(S->d_stage + used);
+    if (used + v.size() * sizeof(T) > ln->stage_bytes)
+      throw HipError{hipErrorOutOfMemory, "serve staging"};
+    std::memcpy(ln->h_stage + used, v.data(), v.size() * sizeof(T));
+    T* d = (T*)(ln->d_stage + used);
     used += v.size() * sizeof(T);
     return d;
   }
@@ -809,38 +831,68 @@ static size_t sample_bytes(mg_plan_s* P, int level) {
   return b;
 }
 
+static std::unique_ptr<Lane> make_lane(mg_plan_s* P, int level, int first, int nslots) {
+  auto ln = std::make_unique<Lane>();
+  ln->level = level;
+  ln->first = first;
+  ln->nslots = nslots;
+  CK(hipStreamCreateWithFlags(&ln->st, hipStreamNonBlocking));
+  CK(hipEventCreateWithFlags(&ln->done, hipEventDisableTiming));
+  ln->B = build_batch(P, mlmc_spec(P, std::vector<int>(nslots, level)));
+  if (!ln->B) return nullptr;
+  Batch* B = ln->B.get();
+  upload_lists(P, B);  // on the plan's stream, synchronised
+  B->st = ln->st;
+  for (int s = 0, sv = 0; s < nslots; ++s) {
+    ln->fi.push_back(sv);
+    ln->ci.push_back(level > 0 ? sv + 1 : -1);
+    sv += level > 0 ? 2 : 1;
+  }
+  ln->top_pos.assign(B->ns, {-1, -1});
+  for (size_t ti = 0; ti < B->L64.htop.size(); ++ti)
+    for (size_t i = 0; i < B->L64.htop[ti].size(); ++i)
+      ln->top_pos[B->L64.htop[ti][i].solve] = {(int)ti, (int)i};
+  ln->stage_bytes = (size_t)nslots * 1536 + 65536;
+  CK(hipHostMalloc((void**)&ln->h_stage, ln->stage_bytes, hipHostMallocDefault));
+  CK(hipMalloc((void**)&ln->d_stage, ln->stage_bytes));
+  CK(hipMalloc((void**)&ln->d_normals, sizeof(double) * 64 * nslots));
+  CK(hipHostMalloc((void**)&ln->h_state, sizeof(int) * 4 * B->ns, hipHostMallocDefault));
+  CK(hipHostMalloc((void**)&ln->h_q, sizeof(double) * B->ns, hipHostMallocDefault));
+  // ||b'|| of every solve (constant right-hand side, fixed for the lane's
+  // life); the workspace starts zeroed: no solve active, counter 0
+  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_BNORM, B->ss.partials, ln->st);
+    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, B->d_cycle, 0, 0,
+                     P->desc.max_cycles, P->desc.tol, ln->st);
+  }
+  CK(hipStreamSynchronize(ln->st));
+  return ln;
+}
+
 // Fields, coefficient hierarchies, zero iterates and solve state of the
-// samples just admitted into slots.
-static void serve_admit(mg_server_s* S, const std::vector<Ticket>& tk) {
-  mg_plan_s* P = S->P;
-  Batch* B = S->B.get();
-  hipStream_t st = P->work;
+// samples just admitted into a lane's slots (tickets carry global slots).
+static void serve_admit(mg_plan_s* P, Lane* ln, const std::vector<Ticket>& tk) {
+  Batch* B = ln->B.get();
+  hipStream_t st = ln->st;
   const int m = (int)tk.size();
-  Packer pk{S};
+  Packer pk{ln};
   std::vector<uint64_t> seeds(m);
-  std::vector<int> levels(m), admit;
+  std::vector<int> levels(m, ln->level), admit, xi(m);
+  std::vector<double*> out(m);
   for (int j = 0; j < m; ++j) {
+    const int s = tk[j].slot - ln->first;
     seeds[j] = tk[j].seed;
-    levels[j] = tk[j].level;
-    admit.push_back(S->fi[tk[j].slot]);
-    if (S->ci[tk[j].slot] >= 0) admit.push_back(S->ci[tk[j].slot]);
+    xi[j] = j;
+    out[j] = B->lev[ln->fi[s]][0].wh;
+    admit.push_back(ln->fi[s]);
+    if (ln->ci[s] >= 0) admit.push_back(ln->ci[s]);
   }
   uint64_t* d_seeds = pk.put(seeds);
   int* d_levels = pk.put(levels);
   int* d_admit = pk.put(admit);
-  // fields of the fine solves, grouped by level
-  struct Group { int n, count; double** out; int* xi; };
-  std::vector<Group> fields;
-  for (int l = 0; l <= P->desc.max_level; ++l) {
-    std::vector<double*> out;
-    std::vector<int> xi;
-    for (int j = 0; j < m; ++j)
-      if (levels[j] == l) {
-        out.push_back(B->lev[S->fi[tk[j].slot]][0].wh);
-        xi.push_back(j);
-      }
-    if (!out.empty()) fields.push_back(Group{level_n(P, l), (int)out.size(), pk.put(out), pk.put(xi)});
-  }
+  double** d_out = pk.put(out);
+  int* d_xi = pk.put(xi);
   // injection down each new fine hierarchy (finest size first) and FP32 copies
   struct Lst { int n, count; double** src; double** dst; float** fdst; };
   std::vector<Lst> inj, cvt;
@@ -848,7 +900,7 @@ static void serve_admit(mg_server_s* S, const std::vector<Ticket>& tk) {
     std::vector<double*> src, dst, csrc;
     std::vector<float*> cdst;
     for (int j = 0; j < m; ++j) {
-      const int fs = S->fi[tk[j].slot];
+      const int fs = ln->fi[tk[j].slot - ln->first];
       const auto& lv = B->lev[fs];
       for (size_t q = 0; q < lv.size(); ++q) {
         if (lv[q].n != B->sizes[si]) continue;
@@ -870,14 +922,14 @@ static void serve_admit(mg_server_s* S, const std::vector<Ticket>& tk) {
   for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
     std::vector<GridDesc> v;
     for (int sv : admit)
-      if (S->top_pos[sv].first == (int)ti) v.push_back(B->L64.htop[ti][S->top_pos[sv].second]);
+      if (ln->top_pos[sv].first == (int)ti) v.push_back(B->L64.htop[ti][ln->top_pos[sv].second]);
     if (!v.empty()) zero.push_back({(int)v.size(), pk.put(v)});
     else zero.push_back({0, nullptr});
   }
-  CK(hipMemcpyAsync(S->d_stage, S->h_stage, pk.used, hipMemcpyHostToDevice, st));
-  launch_philox(d_seeds, m, 0, nullptr, S->d_normals, st, d_levels);
-  for (const auto& g : fields)
-    launch_field(g.n, g.count, g.out, g.xi, S->d_normals, phi_table(P, g.n), P->d_coef, 0, st);
+  CK(hipMemcpyAsync(ln->d_stage, ln->h_stage, pk.used, hipMemcpyHostToDevice, st));
+  launch_philox(d_seeds, m, 0, nullptr, ln->d_normals, st, d_levels);
+  launch_field(level_n(P, ln->level), m, d_out, d_xi, ln->d_normals, phi_table(P, level_n(P, ln->level)),
+               P->d_coef, 0, st);
   for (const auto& l : inj) launch_inject(l.n, l.count, (const double* const*)l.src, l.dst, st);
   for (const auto& l : cvt) launch_to_float(l.n, l.count, (const double* const*)l.src, l.fdst, st);
   for (size_t ti = 0; ti < zero.size(); ++ti)
@@ -885,80 +937,64 @@ static void serve_admit(mg_server_s* S, const std::vector<Ticket>& tk) {
   launch_admit(d_admit, (int)admit.size(), B->ss, B->d_cycle, st);
 }
 
-// c cycles of every resident solve, then the QoI of the solves that stopped.
-static void serve_cycles(mg_server_s* S, int c) {
-  mg_plan_s* P = S->P;
-  Batch* B = S->B.get();
+// c cycles of every resident solve of a lane, then the QoI of the solves
+// that stopped.
+static void serve_cycles(mg_plan_s* P, Lane* ln, int c) {
+  Batch* B = ln->B.get();
   for (int i = 0; i < c; ++i) cycle_step(P, B, P->desc.tol, 0);
   for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
     const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
     launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_QOI_PENDING, B->ss.partials,
-                  P->work, B->ss.qpend);
+                  ln->st, B->ss.qpend);
     launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI_PENDING, B->d_cycle, 0, 0, 0, 0.0,
-                     P->work);
+                     ln->st);
   }
 }
 
-static void serve_run(mg_server_s* S, int c) {
-  mg_plan_s* P = S->P;
+// Launch c cycles of a lane and the copy of its state back to the host.
+static void lane_launch(mg_plan_s* P, Lane* ln, int c) {
+  Batch* B = ln->B.get();
   if (!P->use_graph || P->prof) {
-    serve_cycles(S, c);
-    return;
+    serve_cycles(P, ln, c);
+  } else {
+    auto it = ln->graphs.find(c);
+    if (it == ln->graphs.end()) {
+      hipGraph_t g = nullptr;
+      CK(hipStreamBeginCapture(ln->st, hipStreamCaptureModeThreadLocal));
+      serve_cycles(P, ln, c);
+      CK(hipStreamEndCapture(ln->st, &g));
+      hipGraphExec_t ex = nullptr;
+      CK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+      CK(hipGraphDestroy(g));
+      it = ln->graphs.emplace(c, ex).first;
+    }
+    CK(hipGraphLaunch(it->second, ln->st));
   }
-  auto it = S->graphs.find(c);
-  if (it == S->graphs.end()) {
-    hipGraph_t g = nullptr;
-    CK(hipStreamBeginCapture(P->work, hipStreamCaptureModeThreadLocal));
-    serve_cycles(S, c);
-    CK(hipStreamEndCapture(P->work, &g));
-    hipGraphExec_t ex = nullptr;
-    CK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-    CK(hipGraphDestroy(g));
-    it = S->graphs.emplace(c, ex).first;
-  }
-  CK(hipGraphLaunch(it->second, P->work));
+  const int ns = B->ns;
+  CK(hipMemcpyAsync(ln->h_state, B->ss.active, sizeof(int) * 4 * ns, hipMemcpyDeviceToHost, ln->st));
+  CK(hipMemcpyAsync(ln->h_q, B->ss.q, sizeof(double) * ns, hipMemcpyDeviceToHost, ln->st));
+  CK(hipEventRecord(ln->done, ln->st));
+  ln->inflight = true;
 }
 
-static void serve_step(mg_server_s* S, int c) {
-  mg_plan_s* P = S->P;
-  Batch* B = S->B.get();
-  hipStream_t st = P->work;
-  std::vector<Ticket> tk(S->nslots);
-  tk.resize(S->sched->admit(tk.data(), S->nslots));
-  if (!tk.empty()) {
-    const double t = S->now();
-    for (const Ticket& x : tk) {
-      auto& sl = S->slot[x.slot];
-      sl.busy = true;
-      sl.tag = x.tag;
-      sl.seed = x.seed;
-      sl.t_arrival = x.t_arrival;
-      sl.t_admit = t;
-      ++S->resident;
-    }
-    serve_admit(S, tk);
-  }
-  if (S->resident == 0) return;
-  serve_run(S, c);
-  const int ns = B->ns;
-  CK(hipMemcpyAsync(S->h_state, B->ss.active, sizeof(int) * 4 * ns, hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(S->h_q, B->ss.q, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  if (P->prof) collect_profile(P);
+// Finished samples of a lane whose launch has completed.
+static void lane_harvest(mg_server_s* S, Lane* ln) {
+  ln->inflight = false;
   const double t = S->now();
-  const int* cyc = S->h_state + ns;
-  const int* pend = S->h_state + 3 * ns;
-  for (int s = 0; s < S->nslots; ++s) {
-    auto& sl = S->slot[s];
+  const int ns = ln->B->ns;
+  const int* cyc = ln->h_state + ns;
+  const int* pend = ln->h_state + 3 * ns;
+  for (int s = 0; s < ln->nslots; ++s) {
+    auto& sl = S->slot[ln->first + s];
     if (!sl.busy) continue;
-    const int f = S->fi[s], g = S->ci[s];
+    const int f = ln->fi[s], g = ln->ci[s];
     if (pend[f] || (g >= 0 && pend[g])) continue;
     mg_result r{};
     r.tag = sl.tag;
     r.seed = sl.seed;
-    r.level = S->slot_level[s];
-    r.Qf = S->h_q[f];
-    r.Qc = g >= 0 ? S->h_q[g] : 0.0;
+    r.level = ln->level;
+    r.Qf = ln->h_q[f];
+    r.Qc = g >= 0 ? ln->h_q[g] : 0.0;
     r.Y = r.Qf - r.Qc;
     r.cycles_fine = cyc[f];
     r.cycles_coarse = g >= 0 ? cyc[g] : 0;
@@ -968,9 +1004,67 @@ static void serve_step(mg_server_s* S, int c) {
     r.t_done = t;
     S->done.push_back(r);
     sl.busy = false;
+    --ln->resident;
     --S->resident;
     ++S->completed;
-    S->sched->release(s);
+    S->sched->release(ln->first + s);
+  }
+}
+
+// Harvest finished lanes, admit into idle lanes and relaunch them.  Waits
+// until at least one lane has finished when nothing else can progress.
+static void serve_step(mg_server_s* S, int c) {
+  mg_plan_s* P = S->P;
+  const int L = (int)S->lanes.size();
+  bool harvested = false;
+  for (;;) {
+    for (auto& ln : S->lanes)
+      if (ln && ln->inflight) {
+        const hipError_t q = hipEventQuery(ln->done);
+        if (q == hipSuccess) {
+          lane_harvest(S, ln.get());
+          harvested = true;
+        } else if (q != hipErrorNotReady) {
+          throw HipError{q, "hipEventQuery"};
+        }
+      }
+    // admission into idle lanes only (an in-flight lane's staging is busy)
+    std::vector<char> open(L, 0);
+    for (int l = 0; l < L; ++l) open[l] = S->lanes[l] && !S->lanes[l]->inflight;
+    std::vector<Ticket> tk(S->slot.size());
+    tk.resize(S->sched->admit(tk.data(), (int)tk.size(), &open));
+    std::vector<std::vector<Ticket>> per(L);
+    const double t = S->now();
+    for (const Ticket& x : tk) {
+      auto& sl = S->slot[x.slot];
+      sl.busy = true;
+      sl.tag = x.tag;
+      sl.seed = x.seed;
+      sl.t_arrival = x.t_arrival;
+      sl.t_admit = t;
+      ++S->resident;
+      per[x.level].push_back(x);
+    }
+    bool launched = false;
+    for (int l = 0; l < L; ++l) {
+      Lane* ln = S->lanes[l].get();
+      if (!ln || ln->inflight) continue;
+      if (!per[l].empty()) {
+        ln->resident += (int)per[l].size();
+        serve_admit(P, ln, per[l]);
+      }
+      if (ln->resident > 0) {
+        lane_launch(P, ln, c);
+        launched = true;
+      }
+    }
+    if (harvested || S->resident == 0) return;
+    (void)launched;
+    // nothing finished yet: wait for the first lane to finish
+    bool any = false;
+    for (auto& ln : S->lanes) any = any || (ln && ln->inflight);
+    if (!any) return;
+    std::this_thread::yield();
   }
 }
 
@@ -1085,7 +1179,7 @@ int mg_set_tile(mg_plan P, int n, int tj, int tk, int chunks) {
   SweepShape shapes[32];
   const int c = sweep_shapes(n, shapes, 32);
   for (int i = 0; i < c; ++i)
-    if (shapes[i].tj == tj && shapes[i].tk == tk && chunks >= 1 && chunks <= n - 2) {
+    if (shapes[i].tj == tj && shapes[i].tk == tk && chunks >= 0 && chunks <= n - 2) {
       P->shape[n] = SweepShape{tj, tk, chunks};
       if (P->batch) P->batch->drop_graphs();
       return MG_OK;
@@ -1209,7 +1303,7 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
     double best = 1e30;
     SweepShape pick = default_sweep_shape(n);
     for (int i = 0; i < c; ++i)
-      for (int chunks : {1, 2, 4}) {
+      for (int chunks : {0, 1, 2, 4}) {
         if (chunks > 1 && (n - 2) / chunks < 4) continue;
         if (n >= 33 && shapes[i].tj * shapes[i].tk < 64) continue;  // tiny tiles on big grids
         SweepShape s = shapes[i];
@@ -1372,7 +1466,10 @@ int mg_serve_create(mg_plan P, const int* slots_per_level, int queue_capacity, m
   const int L = P->desc.max_level;
   const size_t budget = P->desc.hbm_budget ? P->desc.hbm_budget : ((size_t)8 << 30);
   std::vector<int> cap(L + 1);
+  size_t need = 0;
+  int total = 0;
   for (int l = 0; l <= L; ++l) {
+    const size_t f = sample_bytes(P, l);
     if (slots_per_level) {
       cap[l] = slots_per_level[l];
       if (cap[l] < 0) {
@@ -1380,63 +1477,37 @@ int mg_serve_create(mg_plan P, const int* slots_per_level, int queue_capacity, m
         return MG_EINVAL;
       }
     } else {
-      const size_t f = sample_bytes(P, l);
       const size_t c = budget / (size_t)(L + 1) / f;
       cap[l] = (int)std::max<size_t>(1, std::min<size_t>(256, c));
     }
+    if (cap[l] > 0) {
+      size_t b = 0;
+      build_batch(P, mlmc_spec(P, std::vector<int>(cap[l], l)), &b);
+      need += b;
+    }
+    total += cap[l];
   }
-  std::vector<int> levels;
-  for (int l = 0; l <= L; ++l) levels.insert(levels.end(), cap[l], l);
-  if (levels.empty()) {
+  if (total == 0) {
     P->err = "mg_serve_create: no slots";
     return MG_EINVAL;
   }
-  const BatchSpec spec = mlmc_spec(P, levels);
-  size_t need = 0;
-  build_batch(P, spec, &need);
   if (need > budget) {
     P->err = "mg_serve_create: slot pools exceed the HBM budget";
     return MG_ENOMEM;
   }
   auto S = std::make_unique<mg_server_s>();
   S->P = P;
-  S->B = build_batch(P, spec);
-  if (!S->B) {
-    P->err = "mg_serve_create: slot pools exceed the HBM budget";
-    return MG_ENOMEM;
-  }
-  Batch* B = S->B.get();
-  upload_lists(P, B);
   S->sched = std::make_unique<Scheduler>(cap, queue_capacity);
-  S->nslots = (int)levels.size();
-  S->slot_level = levels;
-  S->slot.assign(S->nslots, mg_server_s::Slot{});
-  int sv = 0;
-  for (int l : levels) {
-    S->fi.push_back(sv);
-    S->ci.push_back(l > 0 ? sv + 1 : -1);
-    sv += l > 0 ? 2 : 1;
+  S->slot.assign(total, mg_server_s::Slot{});
+  S->lanes.resize(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    if (cap[l] == 0) continue;
+    S->lanes[l] = make_lane(P, l, S->sched->first_slot(l), cap[l]);
+    if (!S->lanes[l]) {
+      P->err = "mg_serve_create: slot pools exceed the HBM budget";
+      return MG_ENOMEM;
+    }
   }
-  S->top_pos.assign(B->ns, {-1, -1});
-  for (size_t ti = 0; ti < B->L64.htop.size(); ++ti)
-    for (size_t i = 0; i < B->L64.htop[ti].size(); ++i)
-      S->top_pos[B->L64.htop[ti][i].solve] = {(int)ti, (int)i};
-  // staging for one step's admissions (at most every slot at once)
-  S->stage_bytes = (size_t)S->nslots * 1536 + 65536;
-  CK(hipHostMalloc((void**)&S->h_stage, S->stage_bytes, hipHostMallocDefault));
-  CK(hipMalloc((void**)&S->d_stage, S->stage_bytes));
-  CK(hipMalloc((void**)&S->d_normals, sizeof(double) * 64 * S->nslots));
-  CK(hipHostMalloc((void**)&S->h_state, sizeof(int) * 4 * B->ns, hipHostMallocDefault));
-  CK(hipHostMalloc((void**)&S->h_q, sizeof(double) * B->ns, hipHostMallocDefault));
-  // ||b'|| of every solve (constant right-hand side, fixed for the server's
-  // life); the workspace starts zeroed: no solve active, counter 0
-  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
-    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
-    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_BNORM, B->ss.partials, P->work);
-    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, B->d_cycle, 0, 0,
-                     P->desc.max_cycles, P->desc.tol, P->work);
-  }
-  CK(hipStreamSynchronize(P->work));
   S->t0 = std::chrono::steady_clock::now();
   *out = S.release();
   return MG_OK;
@@ -1445,8 +1516,7 @@ int mg_serve_create(mg_plan P, const int* slots_per_level, int queue_capacity, m
 
 int mg_serve_destroy(mg_server S) {
   if (!S) return MG_EINVAL;
-  if (S->P && S->P->work) (void)hipStreamSynchronize(S->P->work);
-  delete S;
+  delete S;  // each lane synchronises its stream before freeing
   return MG_OK;
 }
 

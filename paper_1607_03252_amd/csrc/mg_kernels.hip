@@ -14,6 +14,7 @@
 // plane i-1, which need exactly those red values.  Planes of u, wh and the new
 // red values live in small LDS ring buffers.  The sweep reads u[buf] and
 // writes u[1-buf], so tiles never see a neighbour's half-updated values.
+#include <algorithm>
 #include <type_traits>
 
 #include "mg_internal.h"
@@ -282,7 +283,8 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int n, const double* __restr
 // own columns' u, wh, b and new red values of three to four planes in
 // registers; the loads of plane i+2 are issued before the work on plane i.
 // Only the current planes are shared through LDS (for in-plane neighbours):
-// u_in(i) (1 buffer), wh (3 buffers) and the new red values (2 buffers).
+// u_in (2 buffers), wh (3 buffers) and the new red values (2 buffers), so
+// each plane needs a single barrier.
 template <int TJ, int TK>
 struct SweepGeom {
   static constexpr int W2 = TK + 4, H2 = TJ + 4, A2 = W2 * H2;
@@ -296,7 +298,7 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
             int cbuf, int tiles_k, int tiles_jk, int chunk_len, int count, int per) {
   using Geo = SweepGeom<TJ, TK>;
   constexpr int W2 = Geo::W2, A2 = Geo::A2, HW = W2 / 2;
-  __shared__ T sU[A2];     // u_in of the current plane
+  __shared__ T sU[2][A2];  // u_in, planes i % 2
   __shared__ T sW[3][A2];  // wh, planes i % 3
   __shared__ T sR[2][A2];  // new red values, planes i % 2
 
@@ -375,15 +377,16 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
   ld(istart + 1, up, wp, bp);
   ld(istart + 2, pfu, pfw, pfb);
 
+  // plane istart goes to LDS first; afterwards each iteration writes the
+  // next plane (and its own new red values) behind one barrier
+  if (live) {
+    sU[istart % 2][q] = u0[0];
+    sU[istart % 2][q + 1] = u0[1];
+    sW[istart % 3][q] = w0[0];
+    sW[istart % 3][q + 1] = w0[1];
+  }
+  __syncthreads();
   for (int i = istart; i <= iend; ++i) {
-    // share plane i
-    if (live) {
-      sU[q] = u0[0];
-      sU[q + 1] = u0[1];
-      sW[i % 3][q] = w0[0];
-      sW[i % 3][q + 1] = w0[1];
-    }
-    __syncthreads();
     // red point of the pair on plane i: column kA if (i + j + kA) even
     const int cr = ((i + j + kA) & 1) ? 1 : 0;
     T np[2] = {0, 0};
@@ -391,21 +394,17 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
       const bool on = (cr ? (t1B && intB) : (t1A && intA)) && i <= n - 2;
       const int qq = q + cr;
       const T* W0 = sW[i % 3];
+      const T* U0 = sU[i % 2];
       const T w = cr ? w0[1] : w0[0];
       const T a0 = rcp<T>(w + (cr ? wm[1] : wm[0])), a1 = rcp<T>(w + (cr ? wp[1] : wp[0]));
       const T a2 = rcp<T>(w + W0[qq - W2]), a3 = rcp<T>(w + W0[qq + W2]);
       const T a4 = rcp<T>(w + W0[qq - 1]), a5 = rcp<T>(w + W0[qq + 1]);
       const T D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
-      const T S = a0 * (cr ? um[1] : um[0]) + a1 * (cr ? up[1] : up[0]) + a2 * sU[qq - W2] +
-                  a3 * sU[qq + W2] + a4 * sU[qq - 1] + a5 * sU[qq + 1];
+      const T S = a0 * (cr ? um[1] : um[0]) + a1 * (cr ? up[1] : up[0]) + a2 * U0[qq - W2] +
+                  a3 * U0[qq + W2] + a4 * U0[qq - 1] + a5 * U0[qq + 1];
       const T val = ((cr ? b0[1] : b0[0]) + S) * rcp<T>(D);
       np[cr] = on ? val : (T)0;
-      if (live) {
-        sR[i % 2][q + cr] = np[cr];
-        sR[i % 2][q + 1 - cr] = 0;
-      }
     }
-    __syncthreads();
     // black point of plane p = i - 1: the column that is red on plane i
     const int p = i - 1;
     if (p >= ia && p <= ib) {
@@ -442,7 +441,18 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
       b0[e] = bp[e];
       bp[e] = pfb[e];
     }
+    // publish the new red values of plane i and plane i + 1's u and wh; the
+    // buffers written here are not the ones read in this iteration
+    if (live) {
+      sR[i % 2][q + cr] = n0[cr];
+      sR[i % 2][q + 1 - cr] = 0;
+      sU[(i + 1) % 2][q] = u0[0];
+      sU[(i + 1) % 2][q + 1] = u0[1];
+      sW[(i + 1) % 3][q] = w0[0];
+      sW[(i + 1) % 3][q + 1] = w0[1];
+    }
     if (i + 1 <= iend) ld(i + 3, pfu, pfw, pfb);
+    __syncthreads();
   }
 }
 
@@ -833,12 +843,12 @@ int sweep_shapes(int n, SweepShape* out, int max_out) {
 }
 
 SweepShape default_sweep_shape(int n) {
-  if (n - 1 >= 64) return {4, 64, 1};
-  if (n - 1 >= 32) return {8, 32, 1};
-  if (n - 1 >= 16) return {8, 16, 1};
-  if (n - 1 >= 8) return {8, 8, 1};
-  if (n - 1 >= 4) return {4, 4, 1};
-  return {2, 2, 1};
+  if (n - 1 >= 64) return {4, 64, 0};
+  if (n - 1 >= 32) return {8, 32, 0};
+  if (n - 1 >= 16) return {8, 16, 0};
+  if (n - 1 >= 8) return {8, 8, 0};
+  if (n - 1 >= 4) return {4, 4, 0};
+  return {2, 2, 0};
 }
 
 // ---- launchers ------------------------------------------------------------------
@@ -888,7 +898,14 @@ template <typename T>
 void launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                   int cbuf, SweepShape s, hipStream_t st) {
   if (count <= 0) return;
-  const int c = s.chunks < 1 ? 1 : s.chunks;
+  int c = s.chunks;
+  if (c < 1) {
+    // automatic: split the plane march until the launch has about 1024
+    // workgroups (small batches and small grids are latency-bound by the
+    // sequential march), keeping at least four planes per piece
+    const int tiles = ((n - 1) / s.tj) * ((n - 1) / s.tk);
+    c = std::max(1, std::min(ceil_div(1024, std::max(1, count * tiles)), (n - 2) / 4));
+  }
 #define MG_SWEEP_CASE(TJ_, TK_)                                                     \
   if (s.tj == TJ_ && s.tk == TK_) {                                                 \
     sweep_launch<T, TJ_, TK_>(d_list, count, n, d_active, buf, cbuf, c, st);        \

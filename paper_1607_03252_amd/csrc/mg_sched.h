@@ -31,7 +31,8 @@ class Scheduler {
   // 0 on success, -1 for a bad level, -5 when the queue is full.
   int submit(int level, uint64_t seed, long long tag, double t_arrival);
   // Admit up to max_out queued requests; returns how many were written.
-  int admit(Ticket* out, int max_out);
+  // With open (one flag per level), only levels whose flag is set admit.
+  int admit(Ticket* out, int max_out, const std::vector<char>* open = nullptr);
   // Free a busy slot; 0 on success, -1 if the slot is not busy.
   int release(int slot);
 

@@ -26,13 +26,14 @@ int Scheduler::submit(int level, uint64_t seed, long long tag, double t_arrival)
   return MG_OK;
 }
 
-int Scheduler::admit(Ticket* out, int max_out) {
+int Scheduler::admit(Ticket* out, int max_out, const std::vector<char>* open_levels) {
+  auto usable = [&](int l) { return free_count_[l] > 0 && (!open_levels || (*open_levels)[l]); };
   int n = 0;
-  int open = 0;  // levels that still have a free slot
-  for (int f : free_count_) open += f > 0;
+  int open = 0;  // levels that can still admit
+  for (int l = 0; l < levels(); ++l) open += usable(l);
   for (auto it = queue_.begin(); it != queue_.end() && n < max_out && open > 0;) {
     const int l = it->level;
-    if (free_count_[l] == 0) {
+    if (!usable(l)) {
       ++it;
       continue;
     }

@@ -101,7 +101,7 @@ def test_autotune_keeps_results(M, torch):
     before = _batch(M, torch, P, 1, seeds)
     M.mg_autotune(P, 1, 8, 2)
     tj, tk, ch = M.mg_get_tile(P, 65)
-    assert 64 % tj == 0 and 64 % tk == 0 and ch >= 1
+    assert 64 % tj == 0 and 64 % tk == 0 and ch >= 0  # 0: automatic chunking
     after = _batch(M, torch, P, 1, seeds)
     assert _same(before, after)
 
