@@ -103,9 +103,9 @@ def main():
     Qf, Qc = torch.zeros_like(Y), torch.zeros_like(Y)
     cyc = torch.zeros(2 * S, dtype=torch.int32, device="cuda")
 
-    def step(s):
+    def step(s, cyc_out=None):
         seeds = np.arange(s * S, (s + 1) * S, dtype=np.uint64)
-        st = M.mlmc_sample_batch(P, level, seeds, S, Y, Qf, Qc, cyc)
+        st = M.mlmc_sample_batch(P, level, seeds, S, Y, Qf, Qc, cyc if cyc_out is None else cyc_out)
         assert st == M.MG_OK, st
 
     for spec in args.tile:
@@ -117,14 +117,15 @@ def main():
     for s in range(args.warmup):
         step(10**5 + s)
     torch.cuda.synchronize()
-    cycles_f = []
+    # each step's cycle counts land in its own row (written by the library)
+    cyc_all = torch.zeros(args.steps, 2 * S, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        step(s)
-        cycles_f.append(cyc.view(S, 2)[:, 0].float().mean())
+        step(s, cyc_all[s])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    cyc_mean = float(torch.stack(cycles_f).mean().item())
+    cyc_mean = float(cyc_all.view(args.steps, S, 2)[:, :, 0].double().mean().item())
     # per-kernel timing of the finest-grid smoother: HIP events on the plan's
     # stream around each launch (eager launches, same kernels and inputs)
     M.mg_profile_enable(P, True)

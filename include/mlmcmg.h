@@ -124,7 +124,11 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *   "smoother": 0 = fused single-pass red-black sweep (default),
  *               1 = two-pass in-place colour sweeps (same iterates);
  *   "graph":    1 = capture the cycles of mlmc_sample_batch into HIP graphs
- *               (default), 0 = launch eagerly.
+ *               (default), 0 = launch eagerly;
+ *   "small_vcycle": 17 (default), 9 or 5 = from the largest grid of at most
+ *               this size down, each V-cycle runs in one launch with the
+ *               grids held in LDS; 0 = one launch per level and step
+ *               (same results, bit for bit).
  * Returns MG_EINVAL for an unknown name or value. */
 int mg_plan_set_option(mg_plan plan, const char* name, long long value);
 

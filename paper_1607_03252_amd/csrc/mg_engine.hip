@@ -76,6 +76,16 @@ struct Lists {
   std::vector<GridDescT<T>*> d;
   std::vector<std::vector<GridDescT<T>>> htop;  // per top size index
   std::vector<GridDescT<T>*> dtop;
+  // small-grid V-cycle: every solve's chain is rooted at its largest grid of
+  // at most the threshold size; one group per root size, descending;
+  // chain_si is the size index of the largest root (-1: no chains)
+  int chain_si = -1;
+  struct Group {
+    int ns;
+    std::vector<SmallChain<T>> h;
+    SmallChain<T>* d = nullptr;
+  };
+  std::vector<Group> chains;
 };
 
 struct Batch {
@@ -170,6 +180,7 @@ struct mg_plan_s {
   // options
   int smoother = 0;      // 0: fused single-pass sweep, 1: two-pass colour sweeps
   int use_graph = 1;     // capture cycles into HIP graphs (mlmc_sample_batch)
+  int small_ns = 17;     // grids of this size and below: the LDS V-cycle (0: off)
   std::map<int, SweepShape> shape;  // tile shape per grid size
   // profiling of the finest-grid smoothing launches
   bool prof = false;
@@ -338,6 +349,12 @@ static GridDescT<T> make_desc(const std::vector<LevelT<T>>& lv, size_t j, int so
 
 template <typename T>
 static void upload(Batch* B, Lists<T>& Ls, hipStream_t st) {
+  for (auto& g : Ls.chains) {
+    if (g.h.empty()) continue;
+    if (!g.d) g.d = (SmallChain<T>*)B->dalloc(sizeof(SmallChain<T>) * g.h.size());
+    CK(hipMemcpyAsync(g.d, g.h.data(), sizeof(SmallChain<T>) * g.h.size(),
+                      hipMemcpyHostToDevice, st));
+  }
   size_t cnt = 0;
   for (auto& v : Ls.h) cnt += v.size();
   for (auto& v : Ls.htop) cnt += v.size();
@@ -373,6 +390,27 @@ static void upload_lists(mg_plan_s* P, Batch* B) {
   B->L64.htop.assign(B->top_sizes.size(), {});
   B->L32.h.assign(spec.mixed ? B->sizes.size() : 0, {});
   B->L32.htop.assign(spec.mixed ? B->top_sizes.size() : 0, {});
+  // the small-grid V-cycle takes over from each solve's largest grid of at
+  // most P->small_ns (and at least 5) vertices per axis; a batch with a 3^3
+  // top grid keeps the per-level path
+  bool small_ok = P->small_ns >= 5;
+  for (int s = 0; s < B->ns; ++s)
+    if (spec.top_n[s] < 5) small_ok = false;
+  int chain_si = -1;
+  if (small_ok)
+    for (size_t si = 0; si < B->sizes.size(); ++si)
+      if (B->sizes[si] <= P->small_ns) {
+        chain_si = (int)si;
+        break;
+      }
+  B->L64.chain_si = B->L32.chain_si = chain_si;
+  if (B->L64.chains.empty() && chain_si >= 0)
+    for (size_t si = chain_si; si < B->sizes.size() && B->sizes[si] >= 5; ++si) {
+      B->L64.chains.push_back({B->sizes[si], {}, nullptr});
+      if (spec.mixed) B->L32.chains.push_back({B->sizes[si], {}, nullptr});
+    }
+  for (auto& g : B->L64.chains) g.h.clear();
+  for (auto& g : B->L32.chains) g.h.clear();
   int poff = 0;
   for (int s = 0; s < B->ns; ++s) {
     const auto& lv = B->lev[s];
@@ -382,6 +420,21 @@ static void upload_lists(mg_plan_s* P, Batch* B) {
       B->L64.h[si].push_back(d);
       if (spec.mixed)
         B->L32.h[si].push_back(make_desc<float>(B->lev32[s], j, s, j == 0 ? poff : 0, nullptr));
+      // the root of this solve's chain: its first grid at or below the threshold
+      const bool root = chain_si >= 0 && lv[j].n <= P->small_ns &&
+                        (j == 0 || lv[j - 1].n > P->small_ns);
+      if (root) {
+        SmallChain<double> c{};
+        SmallChain<float> c32{};
+        for (size_t q = j; q < lv.size() && q - j < 4; ++q) {
+          const size_t sq = size_index(B->sizes, lv[q].n);
+          c.lv[q - j] = make_desc(lv, q, s, q == 0 ? poff : 0, B->const_plane[sq]);
+          if (spec.mixed) c32.lv[q - j] = make_desc<float>(B->lev32[s], q, s, q == 0 ? poff : 0, nullptr);
+        }
+        const size_t gi = si - (size_t)chain_si;
+        B->L64.chains[gi].h.push_back(c);
+        if (spec.mixed) B->L32.chains[gi].h.push_back(c32);
+      }
       if (j == 0) {
         const size_t ti = size_index(B->top_sizes, lv[j].n);
         B->L64.htop[ti].push_back(d);
@@ -507,7 +560,9 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
   const size_t L = B->sizes.size();
   hipStream_t st = B->st;
   std::vector<int> cur(L, 0);
-  for (size_t si = 0; si < L; ++si) {
+  // sizes from `small` down run in the LDS V-cycle kernel
+  const size_t small = Ls.chain_si >= 0 ? (size_t)Ls.chain_si : L;
+  for (size_t si = 0; si < small; ++si) {
     const int n = B->sizes[si];
     const int cnt = (int)Ls.h[si].size();
     if (n == 3) {
@@ -519,7 +574,14 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
     launch_residual<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);
     launch_restrict<T>(Ls.d[si], cnt, n, B->ss.active, st);
   }
-  for (size_t si = L - 1; si-- > 0;) {
+  size_t up = L - 1;  // the levels above this one are corrected and post-smoothed
+  if (small < L) {
+    for (const auto& g : Ls.chains)
+      launch_vsmall<T>(g.d, (int)g.h.size(), g.ns, B->ss.active, nu1, nu2, st);
+    cur[small] = 0;
+    up = small;
+  }
+  for (size_t si = up; si-- > 0;) {
     const int n = B->sizes[si];
     const int cnt = (int)Ls.h[si].size();
     const int cbuf = cur[si + 1];
@@ -1166,6 +1228,11 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
     P->smoother = (int)value;
   } else if (k == "graph") {
     P->use_graph = value != 0;
+  } else if (k == "small_vcycle") {
+    if (value != 0 && value != 5 && value != 9 && value != 17) return MG_EINVAL;
+    P->small_ns = (int)value;
+    P->batch.reset();  // its lists are rebuilt for the new split
+    P->batch_key.clear();
   } else {
     P->err = "unknown option " + k;
     return MG_EINVAL;
@@ -1297,7 +1364,7 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
   reps = std::max(1, reps);
   for (size_t si = 0; si < B->sizes.size(); ++si) {
     const int n = B->sizes[si];
-    if (n < 5) continue;
+    if (n < 5 || n <= P->small_ns) continue;  // small grids run in the LDS V-cycle
     SweepShape shapes[32];
     const int c = sweep_shapes(n, shapes, 32);
     double best = 1e30;

@@ -34,6 +34,13 @@ struct GridDescT {
 using GridDesc = GridDescT<double>;
 using GridDesc32 = GridDescT<float>;
 
+// One grid of size 17, 9 or 5 and its coarser grids down to 3^3 (lv[0] is
+// the largest), for the small-grid V-cycle kernel.
+template <typename T>
+struct SmallChain {
+  GridDescT<T> lv[4];
+};
+
 // Per-solve device state of a batch.
 struct SolveState {
   int* active;      // 1 while the solve still cycles
@@ -117,6 +124,12 @@ void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_
 // u[0] (and u[1] if present) = 0 on every vertex of the listed grids.
 template <typename T>
 void launch_zero_u(const GridDescT<T>* d_list, int count, int n, hipStream_t st);
+
+// The rest of a V(nu1,nu2) cycle from grids of size ns (17, 9 or 5) down,
+// one workgroup per chain, in LDS; the iterate stays in u[0].
+template <typename T>
+void launch_vsmall(const SmallChain<T>* d_chains, int count, int ns, const int* d_active, int nu1,
+                   int nu2, hipStream_t st);
 
 // Reductions on the top grids of solves.
 // d_pend: the solves' qpend flags (RED_QOI_PENDING only).

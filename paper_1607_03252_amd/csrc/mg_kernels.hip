@@ -103,21 +103,62 @@ __device__ __forceinline__ T b_at(const GridDescT<T>& d, int i, int j, int k) {
   return gview<T>(d.b)[i * d.bstride + j * d.n + k];
 }
 
-// Harmonic-mean face coefficients of vertex p and the stencil sums
-// D = sum_q c_pq, S = sum_q c_pq u_q (neighbours i-1, i+1, j-1, j+1, k-1, k+1).
 template <typename T>
-__device__ __forceinline__ void stencil(const T* __restrict__ u, const T* __restrict__ wh, int p,
-                                        int sj, int si, T& D, T& S) {
-  const T w = wh[p];
-  const T c0 = rcp<T>(w + wh[p - si]);
-  const T c1 = rcp<T>(w + wh[p + si]);
-  const T c2 = rcp<T>(w + wh[p - sj]);
-  const T c3 = rcp<T>(w + wh[p + sj]);
-  const T c4 = rcp<T>(w + wh[p - 1]);
-  const T c5 = rcp<T>(w + wh[p + 1]);
-  D = ((c0 + c1) + (c2 + c3)) + (c4 + c5);
-  S = c0 * u[p - si] + c1 * u[p + si] + c2 * u[p - sj] + c3 * u[p + sj] + c4 * u[p - 1] +
-      c5 * u[p + 1];
+__device__ __forceinline__ T fmaT(T a, T b, T c);
+template <>
+__device__ __forceinline__ double fmaT<double>(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fmaT<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+// The 7-point stencil at one vertex: w = 1/(2k) there, w0..w5 and u0..u5 the
+// neighbours' values in the order i-1, i+1, j-1, j+1, k-1, k+1.  Face
+// coefficients c_q = 1/(w + w_q) (the harmonic mean 2 k k_q/(k + k_q)),
+// D = sum_q c_q and S = sum_q c_q u_q.  Every kernel evaluates the operator
+// through this one function (explicit FMAs, the rest rounded as written; the
+// library is compiled without contraction), so every code path that applies
+// the same update to the same data gets the same bits.
+template <typename T>
+struct St {
+  T D, S;
+};
+// D and S from the six face coefficients a0..a5 (same order).
+template <typename T>
+__device__ __forceinline__ St<T> stencil_faces(T a0, T a1, T a2, T a3, T a4, T a5, T u0, T u1,
+                                               T u2, T u3, T u4, T u5) {
+  St<T> s;
+  s.D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
+  T S = a0 * u0;
+  S = fmaT<T>(a1, u1, S);
+  S = fmaT<T>(a2, u2, S);
+  S = fmaT<T>(a3, u3, S);
+  S = fmaT<T>(a4, u4, S);
+  s.S = fmaT<T>(a5, u5, S);
+  return s;
+}
+template <typename T>
+__device__ __forceinline__ St<T> stencil6(T w, T w0, T w1, T w2, T w3, T w4, T w5, T u0, T u1,
+                                          T u2, T u3, T u4, T u5) {
+  return stencil_faces<T>(rcp<T>(w + w0), rcp<T>(w + w1), rcp<T>(w + w2), rcp<T>(w + w3),
+                          rcp<T>(w + w4), rcp<T>(w + w5), u0, u1, u2, u3, u4, u5);
+}
+// Gauss-Seidel value (b' + S)/D and residual b' - (D u - S).
+template <typename T>
+__device__ __forceinline__ T gs_value(St<T> s, T b) {
+  return (b + s.S) * rcp<T>(s.D);
+}
+template <typename T>
+__device__ __forceinline__ T res_value(St<T> s, T b, T u) {
+  return b - fmaT<T>(s.D, u, -s.S);
+}
+// The stencil at vertex p of arrays with plane stride si and row stride sj.
+template <typename T, typename PU, typename PW>
+__device__ __forceinline__ St<T> stencil_at(PU u, PW wh, int p, int sj, int si) {
+  return stencil6<T>(wh[p], wh[p - si], wh[p + si], wh[p - sj], wh[p + sj], wh[p - 1], wh[p + 1],
+                     u[p - si], u[p + si], u[p - sj], u[p + sj], u[p - 1], u[p + 1]);
 }
 
 // Deterministic block sum (wave64 shuffles, then the 4 waves in fixed order).
@@ -138,16 +179,30 @@ __device__ __forceinline__ double block_sum(double v) {
 // with per-axis weights (1, 0) on even and (1/2, 1/2) on odd fine indices.
 // Branch-free, and the one formula both the fused sweep and k_prolong use.
 template <typename T, typename P>
-__device__ __forceinline__ T prolong_at(P e, int nc, int i, int j, int k) {
+__device__ __forceinline__ void prolong_load(P e, int nc, int i, int j, int k, T (&v)[8]) {
+  const int base = ((i >> 1) * nc + (j >> 1)) * nc + (k >> 1), pl = nc * nc;
+  v[0] = e[base];
+  v[1] = e[base + 1];
+  v[2] = e[base + nc];
+  v[3] = e[base + nc + 1];
+  v[4] = e[base + pl];
+  v[5] = e[base + pl + 1];
+  v[6] = e[base + pl + nc];
+  v[7] = e[base + pl + nc + 1];
+}
+template <typename T>
+__device__ __forceinline__ T prolong_combine(int i, int j, int k, const T (&v)[8]) {
   const T wi1 = (i & 1) ? (T)0.5 : (T)0, wi0 = (i & 1) ? (T)0.5 : (T)1;
   const T wj1 = (j & 1) ? (T)0.5 : (T)0, wj0 = (j & 1) ? (T)0.5 : (T)1;
   const T wk1 = (k & 1) ? (T)0.5 : (T)0, wk0 = (k & 1) ? (T)0.5 : (T)1;
-  const int base = ((i >> 1) * nc + (j >> 1)) * nc + (k >> 1), pl = nc * nc;
-  const T e000 = e[base], e001 = e[base + 1], e010 = e[base + nc], e011 = e[base + nc + 1];
-  const T e100 = e[base + pl], e101 = e[base + pl + 1];
-  const T e110 = e[base + pl + nc], e111 = e[base + pl + nc + 1];
-  return wi0 * (wj0 * (wk0 * e000 + wk1 * e001) + wj1 * (wk0 * e010 + wk1 * e011)) +
-         wi1 * (wj0 * (wk0 * e100 + wk1 * e101) + wj1 * (wk0 * e110 + wk1 * e111));
+  return wi0 * (wj0 * (wk0 * v[0] + wk1 * v[1]) + wj1 * (wk0 * v[2] + wk1 * v[3])) +
+         wi1 * (wj0 * (wk0 * v[4] + wk1 * v[5]) + wj1 * (wk0 * v[6] + wk1 * v[7]));
+}
+template <typename T, typename P>
+__device__ __forceinline__ T prolong_at(P e, int nc, int i, int j, int k) {
+  T v[8];
+  prolong_load<T>(e, nc, i, j, k, v);
+  return prolong_combine<T>(i, j, k, v);
 }
 
 // ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ----------------------
@@ -277,14 +332,29 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int n, const double* __restr
 }
 
 // ---- the fused red-black smoother --------------------------------------------
-// Thread layout: the workgroup covers the tile plus a two-point ring, T2 =
-// (TJ+4) x (TK+4) positions; each thread owns a pair of k-adjacent columns
-// (one red, one black on every plane) and marches the planes i keeping its
-// own columns' u, wh, b and new red values of three to four planes in
-// registers; the loads of plane i+2 are issued before the work on plane i.
-// Only the current planes are shared through LDS (for in-plane neighbours):
-// u_in (2 buffers), wh (3 buffers) and the new red values (2 buffers), so
-// each plane needs a single barrier.
+// One pass computes a whole red-black sweep u_in -> u_out.  A workgroup owns
+// a TJ x TK column tile and marches the planes i; on plane i it updates the
+// red points of the tile plus a one-point ring (from u_in), and the black
+// points of plane i-1 (from the new red values of planes i-2, i-1, i).
+//
+// Each thread owns a pair of k-adjacent columns of the tile plus a two-point
+// ring (T2 = (TJ+4) x (TK+4) positions).  The pair is indexed by role, not
+// position: role 0 is the column that is red on planes istart, istart+2, ...
+// so on every plane all threads agree which role is red.  Every face of the
+// grid joins one red and one black point: the red update computes its six
+// face coefficients, and the black update reuses them (the two vertical
+// ones from the same thread's registers, the four in-plane ones through LDS),
+// so a black point needs no reciprocal but 1/D.  A red update reads no old
+// value of its own and a black update reads no old values at all, so only
+// the black position of each pair is loaded from u_in.
+//
+// Registers hold, per plane, in rings of four indexed by plane offset from
+// istart (the march is unrolled by four, so no value moves): the black
+// u_in, wh and b of both roles, the new red value and the red point's +i face.
+// The loads of plane i+3 are issued at the end of plane i.  LDS holds, per
+// plane parity: u_in and wh of black positions (for red neighbours), the new
+// red values and the +j / +k faces (for black points), so each plane needs a
+// single barrier.
 template <int TJ, int TK>
 struct SweepGeom {
   static constexpr int W2 = TK + 4, H2 = TJ + 4, A2 = W2 * H2;
@@ -298,9 +368,11 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
             int cbuf, int tiles_k, int tiles_jk, int chunk_len, int count, int per) {
   using Geo = SweepGeom<TJ, TK>;
   constexpr int W2 = Geo::W2, A2 = Geo::A2, HW = W2 / 2;
-  __shared__ T sU[2][A2];  // u_in, planes i % 2
-  __shared__ T sW[3][A2];  // wh, planes i % 3
-  __shared__ T sR[2][A2];  // new red values, planes i % 2
+  __shared__ T sU[2][A2];   // u_in of black positions, plane parity
+  __shared__ T sW[2][A2];   // wh of black positions
+  __shared__ T sR[2][A2];   // new red values
+  __shared__ T sFj[2][A2];  // face between x and x + W2 (x red or black)
+  __shared__ T sFk[2][A2];  // face between x and x + 1
 
   int gi, blk;
   if (!xcd_unit(count, per, gi, blk)) return;
@@ -312,6 +384,8 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
   const int j0 = 1 + tj * TJ, k0 = 1 + tk * TK;
   const int ia = 1 + ch * chunk_len;
   const int ib = min(n - 2, ia + chunk_len - 1);
+  const int istart = ia > 1 ? ia - 1 : 1;
+  const int iend = min(ib + 1, n - 1);
   const gptr<const T> uin = gview<T>(buf ? d.u[1] : d.u[0]);
   const gptr<T> uout = gview<T>(buf ? d.u[0] : d.u[1]);
   const gptr<const T> wh = gview<T>(d.wh);
@@ -319,140 +393,148 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
   const gptr<const T> ec = gview<T>(PRO ? (cbuf ? d.uc[1] : d.uc[0]) : d.u[0]);
   const int nc = (n - 1) / 2 + 1;
 
-  // this thread's column pair: T2 row r, columns c = 2*c2, 2*c2 + 1
+  // this thread's pair: T2 row r, positions 2*c2 and 2*c2 + 1
   const int t = threadIdx.x;
   const bool live = t < Geo::PAIRS;
   const int r = live ? t / HW : 0, c2 = live ? t - (t / HW) * HW : 0;
   const int j = j0 - 2 + r;
   const int kA = k0 - 2 + 2 * c2;
-  const int q = r * W2 + 2 * c2;  // LDS index of column kA (kA+1 is q+1)
-  const bool rowin = live && j >= 0 && j < n;
-  const bool inA = rowin && kA >= 0 && kA < n;
-  const bool inB = rowin && kA + 1 < n;
+  const int sw = (istart + j + kA) & 1;  // role rho sits at position 2*c2 + (rho ^ sw)
+  int kc[2], qr[2], col[2];
+  bool in[2], intr[2], t1[2], tl[2];
   const bool intJ = j >= 1 && j <= n - 2;
-  const bool intA = intJ && kA >= 1 && kA <= n - 2;
-  const bool intB = intJ && kA + 1 >= 1 && kA + 1 <= n - 2;
-  const bool t1row = r >= 1 && r <= TJ + 2;
-  const bool t1A = live && t1row && 2 * c2 >= 1 && 2 * c2 <= TK + 2;
-  const bool t1B = live && t1row && 2 * c2 + 1 <= TK + 2;
-  const bool tileRow = r >= 2 && r < TJ + 2;
-  const bool tileA = live && tileRow && 2 * c2 >= 2 && 2 * c2 < TK + 2;
-  const bool tileB = live && tileRow && 2 * c2 + 1 >= 2 && 2 * c2 + 1 < TK + 2;
-  // clamped in-range offsets: every load is unconditional
+#pragma unroll
+  for (int rho = 0; rho < 2; ++rho) {
+    const int x = 2 * c2 + (rho ^ sw);  // position in the T2 row
+    kc[rho] = kA + (rho ^ sw);
+    qr[rho] = r * W2 + x;
+    col[rho] = min(max(kc[rho], 0), n - 1);
+    in[rho] = live && j >= 0 && j < n && kc[rho] >= 0 && kc[rho] < n;
+    intr[rho] = intJ && kc[rho] >= 1 && kc[rho] <= n - 2;
+    t1[rho] = live && r >= 1 && r <= TJ + 2 && x >= 1 && x <= TK + 2;
+    tl[rho] = live && r >= 2 && r < TJ + 2 && x >= 2 && x < TK + 2 && intr[rho];
+  }
   const int jc = min(max(j, 0), n - 1);
-  const int kAc = min(max(kA, 0), n - 1), kBc = min(max(kA + 1, 0), n - 1);
-  const int jI = min(max(j, 1), n - 2), aI = min(max(kA, 1), n - 2), bI = min(max(kA + 1, 1), n - 2);
+  const int jI = min(max(j, 1), n - 2);
 
-  auto ld = [&](int i, T* u, T* w, T* b) {
-    const int ic = min(max(i, 0), n - 1);
-    const bool ok = i >= 0 && i <= n - 1;
-    const int gA = ic * sn2 + jc * n + kAc, gB = ic * sn2 + jc * n + kBc;
-    const int hA = ic * bs + jc * n + kAc, hB = ic * bs + jc * n + kBc;
-    const T ua = uin[gA], ub = uin[gB], wa = wh[gA], wb = wh[gB], ba = bb[hA], bbv = bb[hB];
-    u[0] = (ok && inA) ? ua : (T)0;
-    u[1] = (ok && inB) ? ub : (T)0;
-    w[0] = (ok && inA) ? wa : (T)0;
-    w[1] = (ok && inB) ? wb : (T)0;
-    b[0] = ba;
-    b[1] = bbv;
-    if (PRO) {  // the coarse correction, fused into the load
-      const int iI = min(max(i, 1), n - 2);
-      const bool iint = i >= 1 && i <= n - 2;
-      const T pa = prolong_at<T>(ec, nc, iI, jI, aI), pb = prolong_at<T>(ec, nc, iI, jI, bI);
-      u[0] += (iint && intA) ? pa : (T)0;
-      u[1] += (iint && intB) ? pb : (T)0;
+  T UB[4], W[4][2], B[4][2], NR[4], FIP[4];
+  T EC[8];
+  // plane m = istart + rel: black role (rel + 1) & 1
+  auto load = [&](int rel, T& ub, T (&w)[2], T (&b)[2]) {
+    const int m = istart + rel;
+    const int mc = min(max(m, 0), n - 1);
+    const bool ok = m >= 0 && m <= n - 1;
+    const int rb = (rel + 1) & 1;
+#pragma unroll
+    for (int rho = 0; rho < 2; ++rho) {
+      const T wv = wh[mc * sn2 + jc * n + col[rho]];
+      w[rho] = (ok && in[rho]) ? wv : (T)0;
+      b[rho] = bb[mc * bs + jc * n + col[rho]];
     }
+    const int g = mc * sn2 + jc * n + (rb ? col[1] : col[0]);
+    const T uv = uin[g];
+    ub = (ok && (rb ? in[1] : in[0])) ? uv : (T)0;
+  };
+  // coarse correction of the black u_in of plane istart + rel (PRO)
+  auto ec_issue = [&](int rel) {
+    const int m = istart + rel, rb = (rel + 1) & 1;
+    prolong_load<T>(ec, nc, min(max(m, 1), n - 2), jI, min(max(rb ? kc[1] : kc[0], 1), n - 2), EC);
+  };
+  auto ec_apply = [&](int rel, T& ub) {
+    const int m = istart + rel, rb = (rel + 1) & 1;
+    const int kk = rb ? kc[1] : kc[0];
+    const bool ok = m >= 1 && m <= n - 2 && (rb ? intr[1] : intr[0]);
+    const T pa = prolong_combine<T>(min(max(m, 1), n - 2), jI, min(max(kk, 1), n - 2), EC);
+    ub += ok ? pa : (T)0;
   };
 
-  const int istart = ia > 1 ? ia - 1 : 1;
-  const int iend = min(ib + 1, n - 1);
-  // registers: u at i-1, i, i+1; wh at i-2 .. i+1; b at i-1, i, i+1;
-  // new red values at i-2, i-1; the loads of plane i+2 in flight
-  T um[2], u0[2], up[2], wm2[2], wm[2], w0[2], wp[2], bm[2], b0[2], bp[2];
-  T nm[2] = {0, 0}, n0[2] = {0, 0};
-  T pfu[2], pfw[2], pfb[2];
-  ld(istart - 2, um, wm2, bm);
-  ld(istart - 1, um, wm, bm);
-  ld(istart, u0, w0, b0);
-  ld(istart + 1, up, wp, bp);
-  ld(istart + 2, pfu, pfw, pfb);
-
-  // plane istart goes to LDS first; afterwards each iteration writes the
-  // next plane (and its own new red values) behind one barrier
+  // prologue: planes istart-1 .. istart+2, the +i face of the red point below
+  // plane istart (the black points of plane istart use it), plane istart to LDS
+  load(-1, UB[3], W[3], B[3]);
+  load(0, UB[0], W[0], B[0]);
+  load(1, UB[1], W[1], B[1]);
+  load(2, UB[2], W[2], B[2]);
+  if (PRO) {
+    ec_issue(-1);
+    ec_apply(-1, UB[3]);
+    ec_issue(0);
+    ec_apply(0, UB[0]);
+    ec_issue(1);
+    ec_apply(1, UB[1]);
+    ec_issue(2);  // applied at the end of plane istart
+  }
+  NR[3] = 0;
+  NR[2] = 0;
+  FIP[3] = rcp<T>(W[3][1] + W[0][1]);  // plane istart-1 is red in role 1
+  FIP[2] = 0;
   if (live) {
-    sU[istart % 2][q] = u0[0];
-    sU[istart % 2][q + 1] = u0[1];
-    sW[istart % 3][q] = w0[0];
-    sW[istart % 3][q + 1] = w0[1];
+    sU[0][qr[1]] = UB[0];
+    sW[0][qr[1]] = W[0][1];
   }
   __syncthreads();
-  for (int i = istart; i <= iend; ++i) {
-    // red point of the pair on plane i: column kA if (i + j + kA) even
-    const int cr = ((i + j + kA) & 1) ? 1 : 0;
-    T np[2] = {0, 0};
-    {
-      const bool on = (cr ? (t1B && intB) : (t1A && intA)) && i <= n - 2;
-      const int qq = q + cr;
-      const T* W0 = sW[i % 3];
-      const T* U0 = sU[i % 2];
-      const T w = cr ? w0[1] : w0[0];
-      const T a0 = rcp<T>(w + (cr ? wm[1] : wm[0])), a1 = rcp<T>(w + (cr ? wp[1] : wp[0]));
-      const T a2 = rcp<T>(w + W0[qq - W2]), a3 = rcp<T>(w + W0[qq + W2]);
-      const T a4 = rcp<T>(w + W0[qq - 1]), a5 = rcp<T>(w + W0[qq + 1]);
-      const T D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
-      const T S = a0 * (cr ? um[1] : um[0]) + a1 * (cr ? up[1] : up[0]) + a2 * U0[qq - W2] +
-                  a3 * U0[qq + W2] + a4 * U0[qq - 1] + a5 * U0[qq + 1];
-      const T val = ((cr ? b0[1] : b0[0]) + S) * rcp<T>(D);
-      np[cr] = on ? val : (T)0;
-    }
-    // black point of plane p = i - 1: the column that is red on plane i
+
+  // one plane, K = (i - istart) mod 4 at compile time
+  auto plane = [&](auto kk, int i) {
+    constexpr int K = decltype(kk)::value;
+    constexpr int RHO = K & 1;                 // red role on plane i
+    constexpr int S0 = K, SM = (K + 3) & 3, SP = (K + 1) & 3, SM2 = (K + 2) & 3;
+    constexpr int PB = K & 1, PBM = (K + 1) & 1;  // LDS buffers of planes i and i-1
+    // stencil reads only for ring-1 positions (the others read a safe
+    // interior position; their results are not used)
+    const int qq = t1[RHO] ? qr[RHO] : W2 + 1;
+    // red point of plane i
+    const T wc = W[S0][RHO];
+    const T* Wl = sW[PB];
+    const T* Ul = sU[PB];
+    const T fim = rcp<T>(wc + W[SM][RHO]), fip = rcp<T>(wc + W[SP][RHO]);
+    const T fjm = rcp<T>(wc + Wl[qq - W2]), fjp = rcp<T>(wc + Wl[qq + W2]);
+    const T fkm = rcp<T>(wc + Wl[qq - 1]), fkp = rcp<T>(wc + Wl[qq + 1]);
+    const St<T> sr = stencil_faces<T>(fim, fip, fjm, fjp, fkm, fkp, UB[SM], UB[SP], Ul[qq - W2],
+                                      Ul[qq + W2], Ul[qq - 1], Ul[qq + 1]);
+    const T vr = gs_value<T>(sr, B[S0][RHO]);
+    NR[S0] = (t1[RHO] && intr[RHO] && i <= n - 2) ? vr : (T)0;
+    FIP[S0] = fip;
+    // black point of plane p = i - 1 (the column that is red on plane i)
     const int p = i - 1;
     if (p >= ia && p <= ib) {
-      const bool on = cr ? (tileB && intB) : (tileA && intA);
-      const int qq = q + cr;
-      const T* R0 = sR[p % 2];
-      const T* Wp0 = sW[p % 3];
-      const T w = cr ? wm[1] : wm[0];
-      const T a0 = rcp<T>(w + (cr ? wm2[1] : wm2[0])), a1 = rcp<T>(w + (cr ? w0[1] : w0[0]));
-      const T a2 = rcp<T>(w + Wp0[qq - W2]), a3 = rcp<T>(w + Wp0[qq + W2]);
-      const T a4 = rcp<T>(w + Wp0[qq - 1]), a5 = rcp<T>(w + Wp0[qq + 1]);
-      const T D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
-      const T S = a0 * (cr ? nm[1] : nm[0]) + a1 * np[cr] + a2 * R0[qq - W2] + a3 * R0[qq + W2] +
-                  a4 * R0[qq - 1] + a5 * R0[qq + 1];
-      const T vb = on ? ((cr ? bm[1] : bm[0]) + S) * rcp<T>(D) : (T)0;
-      // both columns of plane p leave: this black one and the other, red on p
-      const int g = p * sn2 + j * n + kA;
-      if (tileA && intA) uout[g] = cr ? n0[0] : vb;
-      if (tileB && intB) uout[g + 1] = cr ? vb : n0[1];
+      const T* Rl = sR[PBM];
+      const T* Fj = sFj[PBM];
+      const T* Fk = sFk[PBM];
+      const St<T> sb = stencil_faces<T>(FIP[SM2], fim, Fj[qq - W2], Fj[qq], Fk[qq - 1], Fk[qq],
+                                        NR[SM2], NR[S0], Rl[qq - W2], Rl[qq + W2], Rl[qq - 1],
+                                        Rl[qq + 1]);
+      const T vb = gs_value<T>(sb, B[SM][RHO]);
+      const int g = p * sn2 + j * n;
+      if (tl[RHO]) uout[g + kc[RHO]] = vb;
+      if (tl[1 - RHO]) uout[g + kc[1 - RHO]] = NR[SM];
     }
-    // roll the registers one plane on
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      nm[e] = n0[e];
-      n0[e] = np[e];
-      um[e] = u0[e];
-      u0[e] = up[e];
-      up[e] = pfu[e];
-      wm2[e] = wm[e];
-      wm[e] = w0[e];
-      w0[e] = wp[e];
-      wp[e] = pfw[e];
-      bm[e] = b0[e];
-      b0[e] = bp[e];
-      bp[e] = pfb[e];
+    // publish plane i's red values and faces, and plane i+1's black u_in and
+    // wh (the buffers read in this plane are the other parity)
+    if (t1[RHO]) {
+      sR[PB][qq] = NR[S0];
+      sFj[PB][qq - W2] = fjm;
+      sFj[PB][qq] = fjp;
+      sFk[PB][qq - 1] = fkm;
+      sFk[PB][qq] = fkp;
     }
-    // publish the new red values of plane i and plane i + 1's u and wh; the
-    // buffers written here are not the ones read in this iteration
     if (live) {
-      sR[i % 2][q + cr] = n0[cr];
-      sR[i % 2][q + 1 - cr] = 0;
-      sU[(i + 1) % 2][q] = u0[0];
-      sU[(i + 1) % 2][q + 1] = u0[1];
-      sW[(i + 1) % 3][q] = w0[0];
-      sW[(i + 1) % 3][q + 1] = w0[1];
+      sU[PBM][qr[RHO]] = UB[SP];
+      sW[PBM][qr[RHO]] = W[SP][RHO];
     }
-    if (i + 1 <= iend) ld(i + 3, pfu, pfw, pfb);
+    // loads of plane i+3 (into the ring slot plane i-1 leaves)
+    if (PRO) ec_apply(i - istart + 2, UB[SM2]);
+    if (i + 1 <= iend) {
+      load(i - istart + 3, UB[SM], W[SM], B[SM]);
+      if (PRO) ec_issue(i - istart + 3);
+    }
     __syncthreads();
+  };
+
+  for (int i = istart; i <= iend; i += 4) {
+    plane(std::integral_constant<int, 0>{}, i);
+    if (i + 1 <= iend) plane(std::integral_constant<int, 1>{}, i + 1);
+    if (i + 2 <= iend) plane(std::integral_constant<int, 2>{}, i + 2);
+    if (i + 3 <= iend) plane(std::integral_constant<int, 3>{}, i + 3);
   }
 }
 
@@ -472,11 +554,9 @@ __global__ void __launch_bounds__(kBlock) k_rbgs_colour(const GridDescT<T>* __re
   const Pt p = interior_point(n - 2, blk);
   if (!p.ok || ((p.i + p.j + p.k) & 1) != colour) return;
   const int v = vidx(n, p.i, p.j, p.k);
-  T* u = (buf ? d.u[1] : d.u[0]);
-  T D, S;
-  stencil<T>(u, d.wh, v, n, n * n, D, S);
-  const T bp = b_at<T>(d, p.i, p.j, p.k);
-  u[v] = (bp + S) * rcp<T>(D);
+  const gptr<T> u = gview<T>(buf ? d.u[1] : d.u[0]);
+  const St<T> st = stencil_at<T>(u, gview<T>(d.wh), v, n, n * n);
+  u[v] = gs_value<T>(st, b_at<T>(d, p.i, p.j, p.k));
 }
 
 // Column marching: a 256-thread block owns 4 rows (j) x 64 columns (k) of
@@ -507,15 +587,11 @@ __device__ __forceinline__ void march_residual(const GridDescT<T>& d, const T* u
   T um = 0, u0 = u[p], wm = wh[p - sn2], w0 = wh[p];
   for (int i = 1; i <= n - 2; ++i, p += sn2) {
     const T up = u[p + sn2], wp = wh[p + sn2];
-    const T a0 = rcp<T>(w0 + wm), a1 = rcp<T>(w0 + wp);
-    const T a2 = rcp<T>(w0 + wh[p - n]), a3 = rcp<T>(w0 + wh[p + n]);
-    const T a4 = rcp<T>(w0 + wh[p - 1]), a5 = rcp<T>(w0 + wh[p + 1]);
-    const T D = ((a0 + a1) + (a2 + a3)) + (a4 + a5);
-    const T S = a0 * um + a1 * up + a2 * u[p - n] + a3 * u[p + n] + a4 * u[p - 1] +
-                a5 * u[p + 1];
+    const St<T> st = stencil6<T>(w0, wm, wp, wh[p - n], wh[p + n], wh[p - 1], wh[p + 1], um, up,
+                                 u[p - n], u[p + n], u[p - 1], u[p + 1]);
     const T bp = bb[pb];
     pb += bs;
-    f(i, p, bp - (D * u0 - S));
+    f(i, p, res_value<T>(st, bp, u0));
     um = u0;
     u0 = up;
     wm = w0;
@@ -576,11 +652,9 @@ __global__ void k_coarsest(const GridDescT<T>* __restrict__ list, int count,
   if (!active[d.solve]) return;
   const int p = 13;
   const T w = d.wh[p];
-  const T D = ((rcp<T>(w + d.wh[p - 9]) + rcp<T>(w + d.wh[p + 9])) +
-               (rcp<T>(w + d.wh[p - 3]) + rcp<T>(w + d.wh[p + 3]))) +
-              (rcp<T>(w + d.wh[p - 1]) + rcp<T>(w + d.wh[p + 1]));
-  const T bp = b_at<T>(d, 1, 1, 1);
-  d.u[0][p] = bp * rcp<T>(D);
+  const St<T> st = stencil6<T>(w, d.wh[p - 9], d.wh[p + 9], d.wh[p - 3], d.wh[p + 3],
+                               d.wh[p - 1], d.wh[p + 1], (T)0, (T)0, (T)0, (T)0, (T)0, (T)0);
+  d.u[0][p] = gs_value<T>(st, b_at<T>(d, 1, 1, 1));
 }
 
 // u[buf] += P uc[cbuf] (trilinear).
@@ -627,6 +701,143 @@ __global__ void __launch_bounds__(kBlock) k_copy_buf(const GridDescT<T>* __restr
   const int v = vidx(n, p.i, p.j, p.k);
   if (from) d.u[0][v] = d.u[1][v];
   else d.u[1][v] = d.u[0][v];
+}
+
+// ---- the small-grid V-cycle in LDS ---------------------------------------------
+// One workgroup runs the whole remaining V-cycle of one grid of size NS
+// (17, 9 or 5) and its coarser grids down to 3^3: every level's u, wh, b and
+// r live in LDS (b of the top level is read from memory), so the cycle costs
+// one launch instead of several per level.  Each step is the same update as
+// the per-level kernels: red then black passes, residual, full weighting,
+// exact 3^3 solve, trilinear correction.
+constexpr int kSmallThreads = 512;
+
+template <int NS>
+struct SmallGeo {
+  static constexpr int J = NS == 17 ? 3 : NS == 9 ? 2 : 1;  // index of the 3^3 level
+  __host__ __device__ static constexpr int n(int j) { return (NS - 1) / (1 << j) + 1; }
+  __host__ __device__ static constexpr int vol(int j) { return n(j) * n(j) * n(j); }
+  // level j holds u, wh, b (not on level 0: its b is read from memory) and
+  // r (not on the coarsest level), in that order
+  __host__ __device__ static constexpr int base(int j) {
+    int o = 0;
+    for (int q = 0; q < j; ++q) o += vol(q) * (2 + (q > 0 ? 1 : 0) + (q < J ? 1 : 0));
+    return o;
+  }
+  __host__ __device__ static constexpr int off_u(int j) { return base(j); }
+  __host__ __device__ static constexpr int off_w(int j) { return base(j) + vol(j); }
+  __host__ __device__ static constexpr int off_b(int j) { return base(j) + 2 * vol(j); }
+  __host__ __device__ static constexpr int off_r(int j) { return base(j) + (j > 0 ? 3 : 2) * vol(j); }
+  static constexpr int total = base(J + 1);
+};
+
+template <typename T, int NS>
+__global__ void __launch_bounds__(kSmallThreads) k_vsmall(const SmallChain<T>* __restrict__ chains,
+                                                          const int* __restrict__ active,
+                                                          int nu1, int nu2) {
+  using Geo = SmallGeo<NS>;
+  constexpr int J = Geo::J;
+  __shared__ T lds[Geo::total];
+  const SmallChain<T>& ch = chains[blockIdx.x];
+  const GridDescT<T> top = ch.lv[0];
+  if (!active[top.solve]) return;
+  const int t = threadIdx.x;
+
+  // load wh of every level and u of the top level; coarse u and every r = 0
+  for (int j = 0; j <= J; ++j) {
+    const int v = Geo::vol(j);
+    const gptr<const T> w = gview<T>(ch.lv[j].wh);
+    for (int q = t; q < v; q += kSmallThreads) {
+      lds[Geo::off_w(j) + q] = w[q];
+      lds[Geo::off_u(j) + q] = j == 0 ? gview<T>(top.u[0])[q] : (T)0;
+      if (j < J) lds[Geo::off_r(j) + q] = 0;
+    }
+  }
+  __syncthreads();
+
+  auto bval = [&](int j, int i, int jj, int k) -> T {
+    const int n = Geo::n(j);
+    return j == 0 ? b_at<T>(top, i, jj, k) : lds[Geo::off_b(j) + (i * n + jj) * n + k];
+  };
+  // one colour pass on level j (in place)
+  auto colour = [&](int j, int c) {
+    const int n = Geo::n(j), m = n - 2;
+    T* u = lds + Geo::off_u(j);
+    const T* w = lds + Geo::off_w(j);
+    for (int q = t; q < m * m * m; q += kSmallThreads) {
+      const int i = q / (m * m) + 1, r = q % (m * m), jj = r / m + 1, k = r % m + 1;
+      if (((i + jj + k) & 1) != c) continue;
+      const int p = (i * n + jj) * n + k;
+      u[p] = gs_value<T>(stencil_at<T>(u, w, p, n, n * n), bval(j, i, jj, k));
+    }
+    __syncthreads();
+  };
+  auto sweep = [&](int j) {
+    colour(j, 0);
+    colour(j, 1);
+  };
+
+  for (int j = 0; j < J; ++j) {
+    for (int s = 0; s < nu1; ++s) sweep(j);
+    // residual of level j, then full weighting into b of level j + 1
+    {
+      const int n = Geo::n(j), m = n - 2;
+      const T* u = lds + Geo::off_u(j);
+      const T* w = lds + Geo::off_w(j);
+      T* r = lds + Geo::off_r(j);
+      for (int q = t; q < m * m * m; q += kSmallThreads) {
+        const int i = q / (m * m), rr = q % (m * m), jj = rr / m + 1, k = rr % m + 1;
+        const int p = ((i + 1) * n + jj) * n + k;
+        r[p] = res_value<T>(stencil_at<T>(u, w, p, n, n * n), bval(j, i + 1, jj, k), u[p]);
+      }
+      __syncthreads();
+      const int nc = Geo::n(j + 1), mc = nc - 2;
+      T* bc = lds + Geo::off_b(j + 1);
+      for (int q = t; q < mc * mc * mc; q += kSmallThreads) {
+        const int I = q / (mc * mc) + 1, rr = q % (mc * mc), Jj = rr / mc + 1, K = rr % mc + 1;
+        T acc = 0;
+        for (int di = -1; di <= 1; ++di) {
+          const T wi = di == 0 ? (T)1 : (T)0.5;
+          for (int dj = -1; dj <= 1; ++dj) {
+            const T wj = dj == 0 ? wi : (T)0.5 * wi;
+            const int row = ((2 * I + di) * n + 2 * Jj + dj) * n + 2 * K;
+            acc += wj * (r[row] + (T)0.5 * (r[row - 1] + r[row + 1]));
+          }
+        }
+        bc[(I * nc + Jj) * nc + K] = (T)0.5 * acc;
+      }
+      __syncthreads();
+    }
+  }
+  // the 3^3 level: one unknown, solved exactly
+  if (t == 0) {
+    const T* w = lds + Geo::off_w(J);
+    const St<T> st = stencil6<T>(w[13], w[4], w[22], w[10], w[16], w[12], w[14], (T)0, (T)0,
+                                 (T)0, (T)0, (T)0, (T)0);
+    lds[Geo::off_u(J) + 13] = gs_value<T>(st, lds[Geo::off_b(J) + 13]);
+  }
+  __syncthreads();
+  for (int j = J - 1; j >= 0; --j) {
+    {
+      const int n = Geo::n(j), m = n - 2, nc = Geo::n(j + 1);
+      T* u = lds + Geo::off_u(j);
+      const T* e = lds + Geo::off_u(j + 1);
+      for (int q = t; q < m * m * m; q += kSmallThreads) {
+        const int i = q / (m * m) + 1, rr = q % (m * m), jj = rr / m + 1, k = rr % m + 1;
+        u[(i * n + jj) * n + k] += prolong_at<T>(e, nc, i, jj, k);
+      }
+      __syncthreads();
+    }
+    for (int s = 0; s < nu2; ++s) sweep(j);
+  }
+  // the top level's iterate back to u[0]
+  const gptr<T> uo = gview<T>(top.u[0]);
+  const int n = NS, m = n - 2;
+  for (int q = t; q < m * m * m; q += kSmallThreads) {
+    const int i = q / (m * m) + 1, rr = q % (m * m), jj = rr / m + 1, k = rr % m + 1;
+    const int p = (i * n + jj) * n + k;
+    uo[p] = lds[Geo::off_u(0) + p];
+  }
 }
 
 // ---- reductions ---------------------------------------------------------------
@@ -1000,6 +1211,25 @@ void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_
 MG_INSTANTIATE(double)
 MG_INSTANTIATE(float)
 #undef MG_INSTANTIATE
+
+template <typename T>
+void launch_vsmall(const SmallChain<T>* d_chains, int count, int ns, const int* d_active, int nu1,
+                   int nu2, hipStream_t st) {
+  if (count <= 0) return;
+  if (ns == 17)
+    hipLaunchKernelGGL((k_vsmall<T, 17>), dim3(count), dim3(kSmallThreads), 0, st, d_chains,
+                       d_active, nu1, nu2);
+  else if (ns == 9)
+    hipLaunchKernelGGL((k_vsmall<T, 9>), dim3(count), dim3(kSmallThreads), 0, st, d_chains,
+                       d_active, nu1, nu2);
+  else if (ns == 5)
+    hipLaunchKernelGGL((k_vsmall<T, 5>), dim3(count), dim3(kSmallThreads), 0, st, d_chains,
+                       d_active, nu1, nu2);
+}
+template void launch_vsmall<double>(const SmallChain<double>*, int, int, const int*, int, int,
+                                    hipStream_t);
+template void launch_vsmall<float>(const SmallChain<float>*, int, int, const int*, int, int,
+                                   hipStream_t);
 
 void launch_reduce(const GridDesc* d_list, int count, int n, const int* d_active, int buf,
                    int mode, double* d_partials, hipStream_t st, const int* d_pend) {

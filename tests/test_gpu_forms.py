@@ -61,9 +61,36 @@ def test_fused_and_colour_smoothers_agree(M, torch):
     M.mg_plan_set_option(P, "smoother", 1)
     colour = _batch(M, torch, P, 2, seeds)
     assert fused[0] == colour[0] == M.MG_OK
-    assert np.array_equal(fused[4], colour[4])
-    for a, b in zip(fused[1:4], colour[1:4]):
-        assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(b))
+    assert _same(fused, colour)
+
+
+@pytest.mark.parametrize("n0,level,prec", [(17, 2, 0), (9, 1, 0), (17, 1, 1)])
+def test_small_vcycle_matches_per_level_launches(M, torch, n0, level, prec):
+    # the LDS V-cycle on grids <= 17 (one launch) against one launch per level
+    # and step: the same updates in the same arithmetic, bit for bit
+    seeds = [21, 22, 23, 24, 25]
+    out = {}
+    for ns in (17, 9, 5, 0):
+        P = M.mg_plan_create(n0=n0, max_level=level, precision=prec)
+        M.mg_plan_set_option(P, "small_vcycle", ns)
+        out[ns] = _batch(M, torch, P, level, seeds)
+        assert out[ns][0] == M.MG_OK
+    for ns in (17, 9, 5):
+        assert _same(out[ns], out[0]), ns
+
+
+def test_small_vcycle_single_solve(M, torch):
+    # a whole 17^3 solve in the LDS kernel (mg_solve), against per-level launches
+    n = 17
+    k = O.field(n, 1.0, 0.1, O.gaussians(9, 0))
+    f = np.ones_like(k)
+    res = {}
+    for ns in (17, 0):
+        P = M.mg_plan_create()
+        M.mg_plan_set_option(P, "small_vcycle", ns)
+        res[ns] = _solve(M, torch, P, k, f)
+    assert res[17][:2] == res[0][:2]
+    assert np.array_equal(res[17][3], res[0][3])
 
 
 @pytest.mark.parametrize("n0,level", [(33, 1), (65, 1)])
