@@ -69,10 +69,13 @@ def main():
     ap.add_argument("--serve-slots", default="128,64,16,4")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--no-fifo", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the smoother's tile shapes first (default: the library's shapes)")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--tile", action="append", default=[],
                     help="n:tj:tk:chunks, pins a smoother tile shape (skips the autotuner)")
+    ap.add_argument("--tile-pro", action="append", default=[],
+                    help="n:tj:tk:chunks, the shape of the sweep with the fused coarse correction")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -111,9 +114,13 @@ def main():
     for spec in args.tile:
         nn, tj, tk, ch = (int(x) for x in spec.split(":"))
         M.mg_set_tile(P, nn, tj, tk, ch)
-    if not args.no_autotune and not args.tile:
+    for spec in args.tile_pro:
+        nn, tj, tk, ch = (int(x) for x in spec.split(":"))
+        M.mg_set_tile_for(P, nn, 1, tj, tk, ch)
+    if args.autotune and not args.tile:
         M.mg_autotune(P, level, S, 3)
-    tiles = {n: M.mg_get_tile(P, n) for n in (65, 33, 17, 9, 5)}
+    tiles = {n: M.mg_get_tile(P, n) for n in (65, 33)}
+    tiles_pro = {n: M.mg_get_tile_for(P, n, 1) for n in (65, 33)}
     for s in range(args.warmup):
         step(10**5 + s)
     torch.cuda.synchronize()
@@ -156,7 +163,7 @@ def main():
         rec = profsum.read_summary(summ)
         # counters apply only to the same kernel source and tile shape
         if rec.get("kernel_source_sha256") == profsum.source_hash() and \
-                list(rec.get("tile") or []) == list(tiles[65]):
+                rec.get("tiles") == [list(tiles[65]), list(tiles_pro[65])]:
             traffic = rec.get("hbm_bytes_per_launch")
             traffic_src = os.path.relpath(summ, ROOT)
 
@@ -176,7 +183,8 @@ def main():
         "config": {"workload": "mlmc_level_pair_fine65_coarse33_x64", "n0": n0, "level": level,
                    "samples_per_step": S, "sigma2": 1.0, "corr_len": 0.1, "tol": 1e-8,
                    "cycle": "V(2,2) red-black GS", "parallelism": "single GPU",
-                   "tiles": {str(k): list(v) for k, v in tiles.items()}},
+                   "tiles": {str(k): list(v) for k, v in tiles.items()},
+                   "tiles_pro": {str(k): list(v) for k, v in tiles_pro.items()}},
         "per_level": {str(level): {"samples_per_s": value, "fine_cycles_mean": cyc_mean,
                                    "effective_vcycle_GBps": eff,
                                    "batch_latency_ms": ms_step}},
@@ -184,7 +192,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "traffic_source": traffic_src,
                      "kernel": "k_sweep (fused red-black sweep, 65^3 grids)", "launches": launches,
-                     "tile": list(tiles[65]),
+                     "tiles": [list(tiles[65]), list(tiles_pro[65])],
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_launch},
     }
     if not args.no_cpu_baseline:

@@ -140,12 +140,18 @@ int mg_plan_set_option(mg_plan plan, const char* name, long long value);
  * A server captures the shapes in force at its first step. */
 int mg_set_tile(mg_plan plan, int n, int tj, int tk, int chunks);
 int mg_get_tile(mg_plan plan, int n, int* tj, int* tk, int* chunks);
+/* The same for one kind of sweep only: fused_correction = 1 is the first
+ * post-smoothing sweep, which also adds the coarse-grid correction (it uses
+ * more registers, so its best shape can differ); 0 is every other sweep.
+ * mg_set_tile sets both, mg_get_tile reads kind 0. */
+int mg_set_tile_for(mg_plan plan, int n, int fused_correction, int tj, int tk, int chunks);
+int mg_get_tile_for(mg_plan plan, int n, int fused_correction, int* tj, int* tk, int* chunks);
 
 /* Autotuner: runs one batch of n_samples samples of `level` (seeds
  * 0x5eed0000 + i), then times every compiled tile shape with chunk counts
- * 0 (automatic), 1, 2, 4 of the smoother on each grid size of that batch
- * (reps launches each, HIP events) and keeps the fastest per size in the
- * plan. */
+ * 0 (automatic), 1, 2, 4 of both kinds of smoothing sweep on each grid size
+ * of that batch above the LDS V-cycle's sizes (reps launches each, HIP
+ * events) and keeps the fastest per size and kind in the plan. */
 int mg_autotune(mg_plan plan, int level, int n_samples, int reps);
 
 /* Serving: continuous batching of MLMC sample requests --------------------

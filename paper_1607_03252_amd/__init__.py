@@ -89,6 +89,8 @@ def lib():
         L.mg_plan_set_option.argtypes = [vp, C.c_char_p, C.c_longlong]
         L.mg_set_tile.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.mg_get_tile.argtypes = [vp, C.c_int, ip, ip, ip]
+        L.mg_set_tile_for.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.mg_get_tile_for.argtypes = [vp, C.c_int, C.c_int, ip, ip, ip]
         L.mg_autotune.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.mg_sample_footprint.argtypes = [vp, C.c_int, C.POINTER(C.c_size_t)]
         L.mg_sched_create.argtypes = [C.c_int, ip, C.c_int, C.POINTER(vp)]
@@ -120,7 +122,8 @@ def exported_symbols():
             "mlmc_sample_mixed", "mg_sample_footprint", "mg_sched_create", "mg_sched_destroy",
             "mg_sched_submit", "mg_sched_admit", "mg_sched_release", "mg_sched_counts",
             "mg_serve_create", "mg_serve_destroy", "mg_serve_submit", "mg_serve_step",
-            "mg_serve_now", "mg_serve_counts", "mg_serve_slots"]
+            "mg_serve_now", "mg_serve_counts", "mg_serve_slots", "mg_set_tile_for",
+            "mg_get_tile_for"]
 
 
 def _torch():
@@ -213,6 +216,17 @@ def mg_set_tile(plan: Plan, n: int, tj: int, tk: int, chunks: int = 1):
 def mg_get_tile(plan: Plan, n: int):
     a, b, c = C.c_int(), C.c_int(), C.c_int()
     plan.check(lib().mg_get_tile(plan.handle, n, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def mg_set_tile_for(plan: Plan, n: int, fused_correction: int, tj: int, tk: int, chunks: int = 1):
+    return plan.check(lib().mg_set_tile_for(plan.handle, n, int(fused_correction), tj, tk, chunks))
+
+
+def mg_get_tile_for(plan: Plan, n: int, fused_correction: int):
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    plan.check(lib().mg_get_tile_for(plan.handle, n, int(fused_correction), C.byref(a), C.byref(b),
+                                     C.byref(c)))
     return a.value, b.value, c.value
 
 

@@ -181,7 +181,8 @@ struct mg_plan_s {
   int smoother = 0;      // 0: fused single-pass sweep, 1: two-pass colour sweeps
   int use_graph = 1;     // capture cycles into HIP graphs (mlmc_sample_batch)
   int small_ns = 17;     // grids of this size and below: the LDS V-cycle (0: off)
-  std::map<int, SweepShape> shape;  // tile shape per grid size
+  std::map<int, SweepShape> shape;      // tile shape per grid size
+  std::map<int, SweepShape> shape_pro;  // same, sweeps with the fused coarse correction
   // profiling of the finest-grid smoothing launches
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -202,9 +203,10 @@ struct mg_plan_s {
 
 namespace mg {
 
-static SweepShape shape_for(mg_plan_s* P, int n) {
-  auto it = P->shape.find(n);
-  return it != P->shape.end() ? it->second : default_sweep_shape(n);
+static SweepShape shape_for(mg_plan_s* P, int n, bool pro = false) {
+  const auto& m = pro ? P->shape_pro : P->shape;
+  auto it = m.find(n);
+  return it != m.end() ? it->second : default_sweep_shape(n, pro);
 }
 
 // Order the plan's stream after everything queued so far on the caller's.
@@ -537,7 +539,7 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
   }
   int out = buf;
   if (P->smoother == 0) {
-    launch_sweep<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, shape_for(P, n), st);
+    launch_sweep<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, shape_for(P, n, cbuf >= 0), st);
     out = 1 - buf;
   } else {
     if (cbuf >= 0) launch_prolong<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, st);
@@ -1241,13 +1243,13 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
   return MG_OK;
 }
 
-int mg_set_tile(mg_plan P, int n, int tj, int tk, int chunks) {
+int mg_set_tile_for(mg_plan P, int n, int fused_correction, int tj, int tk, int chunks) {
   if (!P) return MG_EINVAL;
   SweepShape shapes[32];
   const int c = sweep_shapes(n, shapes, 32);
   for (int i = 0; i < c; ++i)
     if (shapes[i].tj == tj && shapes[i].tk == tk && chunks >= 0 && chunks <= n - 2) {
-      P->shape[n] = SweepShape{tj, tk, chunks};
+      (fused_correction ? P->shape_pro : P->shape)[n] = SweepShape{tj, tk, chunks};
       if (P->batch) P->batch->drop_graphs();
       return MG_OK;
     }
@@ -1255,13 +1257,22 @@ int mg_set_tile(mg_plan P, int n, int tj, int tk, int chunks) {
   return MG_EINVAL;
 }
 
-int mg_get_tile(mg_plan P, int n, int* tj, int* tk, int* chunks) {
+int mg_set_tile(mg_plan P, int n, int tj, int tk, int chunks) {
+  const int st = mg_set_tile_for(P, n, 0, tj, tk, chunks);
+  return st == MG_OK ? mg_set_tile_for(P, n, 1, tj, tk, chunks) : st;
+}
+
+int mg_get_tile_for(mg_plan P, int n, int fused_correction, int* tj, int* tk, int* chunks) {
   if (!P || !tj || !tk || !chunks) return MG_EINVAL;
-  const SweepShape s = shape_for(P, n);
+  const SweepShape s = shape_for(P, n, fused_correction != 0);
   *tj = s.tj;
   *tk = s.tk;
   *chunks = s.chunks;
   return MG_OK;
+}
+
+int mg_get_tile(mg_plan P, int n, int* tj, int* tk, int* chunks) {
+  return mg_get_tile_for(P, n, 0, tj, tk, chunks);
 }
 
 const char* mg_last_error(mg_plan P) { return P ? P->err.c_str() : "null plan"; }
@@ -1367,37 +1378,42 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
     if (n < 5 || n <= P->small_ns) continue;  // small grids run in the LDS V-cycle
     SweepShape shapes[32];
     const int c = sweep_shapes(n, shapes, 32);
-    double best = 1e30;
-    SweepShape pick = default_sweep_shape(n);
-    for (int i = 0; i < c; ++i)
-      for (int chunks : {0, 1, 2, 4}) {
-        if (chunks > 1 && (n - 2) / chunks < 4) continue;
-        if (n >= 33 && shapes[i].tj * shapes[i].tk < 64) continue;  // tiny tiles on big grids
-        SweepShape s = shapes[i];
-        s.chunks = chunks;
-        // every solve active while timing; the next batch reinitialises the workspace
-        launch_init_state2(B->ss, B->d_cycle, B->ns, P->work);
-        auto one = [&]() {
-          if (mixed)
-            launch_sweep<float>(B->L32.d[si], (int)B->L32.h[si].size(), n, B->ss.active, 0, -1,
-                                s, P->work);
-          else
-            launch_sweep<double>(B->L64.d[si], (int)B->L64.h[si].size(), n, B->ss.active, 0, -1,
-                                 s, P->work);
-        };
-        one();
-        CK(hipEventRecord(e0, P->work));
-        for (int r = 0; r < reps; ++r) one();
-        CK(hipEventRecord(e1, P->work));
-        CK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        CK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-          best = ms;
-          pick = s;
+    // the plain sweep and the one with the fused coarse correction are tuned
+    // separately (their register use, hence occupancy, differs)
+    for (int pro = 0; pro < 2; ++pro) {
+      double best = 1e30;
+      SweepShape pick = default_sweep_shape(n, pro != 0);
+      for (int i = 0; i < c; ++i)
+        for (int chunks : {0, 1, 2, 4}) {
+          if (chunks > 1 && (n - 2) / chunks < 4) continue;
+          if (n >= 33 && shapes[i].tj * shapes[i].tk < 64) continue;  // tiny tiles on big grids
+          SweepShape s = shapes[i];
+          s.chunks = chunks;
+          // every solve active while timing; the next batch reinitialises the workspace
+          launch_init_state2(B->ss, B->d_cycle, B->ns, P->work);
+          const int cb = pro ? 0 : -1;
+          auto one = [&]() {
+            if (mixed)
+              launch_sweep<float>(B->L32.d[si], (int)B->L32.h[si].size(), n, B->ss.active, 0, cb,
+                                  s, P->work);
+            else
+              launch_sweep<double>(B->L64.d[si], (int)B->L64.h[si].size(), n, B->ss.active, 0,
+                                   cb, s, P->work);
+          };
+          one();
+          CK(hipEventRecord(e0, P->work));
+          for (int r = 0; r < reps; ++r) one();
+          CK(hipEventRecord(e1, P->work));
+          CK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          CK(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best) {
+            best = ms;
+            pick = s;
+          }
         }
-      }
-    P->shape[n] = pick;
+      (pro ? P->shape_pro : P->shape)[n] = pick;
+    }
   }
   CK(hipEventDestroy(e0));
   CK(hipEventDestroy(e1));

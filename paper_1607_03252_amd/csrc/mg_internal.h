@@ -74,7 +74,7 @@ struct SweepShape {
 };
 // Shapes with compiled kernels for grid size n (TJ, TK divide n-1).
 int sweep_shapes(int n, SweepShape* out, int max_out);
-SweepShape default_sweep_shape(int n);
+SweepShape default_sweep_shape(int n, bool fused_correction = false);
 
 // ---- launchers (all asynchronous on `st`) --------------------------------
 // Normals of `count` samples; the counter's level word is d_levels[s] when

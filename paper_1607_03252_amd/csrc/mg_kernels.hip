@@ -418,7 +418,6 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
   const int jI = min(max(j, 1), n - 2);
 
   T UB[4], W[4][2], B[4][2], NR[4], FIP[4];
-  T EC[8];
   // plane m = istart + rel: black role (rel + 1) & 1
   auto load = [&](int rel, T& ub, T (&w)[2], T (&b)[2]) {
     const int m = istart + rel;
@@ -435,17 +434,38 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     const T uv = uin[g];
     ub = (ok && (rb ? in[1] : in[0])) ? uv : (T)0;
   };
-  // coarse correction of the black u_in of plane istart + rel (PRO)
-  auto ec_issue = [&](int rel) {
-    const int m = istart + rel, rb = (rel + 1) & 1;
-    prolong_load<T>(ec, nc, min(max(m, 1), n - 2), jI, min(max(rb ? kc[1] : kc[0], 1), n - 2), EC);
+
+  // Coarse correction (PRO): the coarse iterate's planes under the tile are
+  // staged in LDS (four slots by plane index mod 4), one value per thread,
+  // loaded two planes ahead; the correction of a fine plane is formed from
+  // LDS one plane before its values are first used.
+  constexpr int CJM = PRO ? TJ / 2 + 4 : 1, CKM = PRO ? TK / 2 + 4 : 1;
+  __shared__ T sC[PRO ? 4 : 1][CJM * CKM];
+  const int cj0 = max(j0 - 2, 1) >> 1, ck0 = max(k0 - 2, 1) >> 1;
+  const int CK = (min(k0 + TK + 1, n - 2) >> 1) + 2 - ck0;
+  const int CJ = (min(j0 + TJ + 1, n - 2) >> 1) + 2 - cj0;
+  const bool cown = PRO && t < CJ * CK;
+  const int crow = cown ? t / CK : 0, ccol = cown ? t - (t / CK) * CK : 0;
+  T cstage = 0, PA[4] = {0, 0, 0, 0};
+  int cnext = 0;
+  auto c_issue = [&](int C) {
+    const int Cc = min(max(C, 0), nc - 1);
+    cstage = ec[(Cc * nc + min(cj0 + crow, nc - 1)) * nc + min(ck0 + ccol, nc - 1)];
   };
-  auto ec_apply = [&](int rel, T& ub) {
-    const int m = istart + rel, rb = (rel + 1) & 1;
-    const int kk = rb ? kc[1] : kc[0];
-    const bool ok = m >= 1 && m <= n - 2 && (rb ? intr[1] : intr[0]);
-    const T pa = prolong_combine<T>(min(max(m, 1), n - 2), jI, min(max(kk, 1), n - 2), EC);
-    ub += ok ? pa : (T)0;
+  auto c_store = [&](int C) {
+    if (cown) sC[C & 3][crow * CKM + ccol] = cstage;
+  };
+  // correction at fine (m, j, kk), zero off the interior
+  auto pa_of = [&](int m, int kk, bool intk) -> T {
+    const int mi = min(max(m, 1), n - 2), ki = min(max(kk, 1), n - 2);
+    const int rr = (jI >> 1) - cj0, cc = (ki >> 1) - ck0;
+    const T* c0 = sC[(mi >> 1) & 3];
+    const T* c1 = sC[((mi >> 1) + 1) & 3];
+    const int o = rr * CKM + cc;
+    const T v[8] = {c0[o], c0[o + 1], c0[o + CKM], c0[o + CKM + 1],
+                    c1[o], c1[o + 1], c1[o + CKM], c1[o + CKM + 1]};
+    const T pa = prolong_combine<T>(mi, jI, ki, v);
+    return (m >= 1 && m <= n - 2 && intk) ? pa : (T)0;
   };
 
   // prologue: planes istart-1 .. istart+2, the +i face of the red point below
@@ -455,13 +475,18 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
   load(1, UB[1], W[1], B[1]);
   load(2, UB[2], W[2], B[2]);
   if (PRO) {
-    ec_issue(-1);
-    ec_apply(-1, UB[3]);
-    ec_issue(0);
-    ec_apply(0, UB[0]);
-    ec_issue(1);
-    ec_apply(1, UB[1]);
-    ec_issue(2);  // applied at the end of plane istart
+    const int clo = max((istart - 1) >> 1, 0), chi = ((istart + 2) >> 1) + 1;
+    for (int C = clo; C <= chi; ++C) {
+      c_issue(C);
+      c_store(C);
+    }
+    cnext = chi + 1;
+    c_issue(cnext);
+    __syncthreads();
+    // black roles: plane istart-1 -> 0, istart -> 1, istart+1 -> 0
+    UB[3] += pa_of(istart - 1, kc[0], intr[0]);
+    UB[0] += pa_of(istart, kc[1], intr[1]);
+    PA[1] = pa_of(istart + 1, kc[0], intr[0]);
   }
   NR[3] = 0;
   NR[2] = 0;
@@ -482,6 +507,10 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     // stencil reads only for ring-1 positions (the others read a safe
     // interior position; their results are not used)
     const int qq = t1[RHO] ? qr[RHO] : W2 + 1;
+    if (PRO) {
+      UB[SP] += PA[SP];                                          // plane i+1 (black role RHO)
+      PA[SM2] = pa_of(i + 2, kc[1 - RHO], intr[1 - RHO]);        // plane i+2
+    }
     // red point of plane i
     const T wc = W[S0][RHO];
     const T* Wl = sW[PB];
@@ -521,11 +550,13 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
       sU[PBM][qr[RHO]] = UB[SP];
       sW[PBM][qr[RHO]] = W[SP][RHO];
     }
-    // loads of plane i+3 (into the ring slot plane i-1 leaves)
-    if (PRO) ec_apply(i - istart + 2, UB[SM2]);
-    if (i + 1 <= iend) {
-      load(i - istart + 3, UB[SM], W[SM], B[SM]);
-      if (PRO) ec_issue(i - istart + 3);
+    // loads of plane i+3 (into the ring slot plane i-1 leaves); the next
+    // coarse plane to LDS every second plane
+    if (i + 1 <= iend) load(i - istart + 3, UB[SM], W[SM], B[SM]);
+    if (PRO && ((i + 3) & 1) == 0) {
+      c_store(cnext);
+      ++cnext;
+      c_issue(cnext);
     }
     __syncthreads();
   };
@@ -1053,9 +1084,12 @@ int sweep_shapes(int n, SweepShape* out, int max_out) {
   return c;
 }
 
-SweepShape default_sweep_shape(int n) {
-  if (n - 1 >= 64) return {4, 64, 0};
-  if (n - 1 >= 32) return {8, 32, 0};
+SweepShape default_sweep_shape(int n, bool fused_correction) {
+  // measured best on MI355X for a batch of 64 MLMC level pairs (64 grids of
+  // 65^3 and 128 of 33^3); other sizes: a shape with enough workgroups
+  if (n == 65) return fused_correction ? SweepShape{16, 16, 2} : SweepShape{8, 32, 1};
+  if (n == 33) return fused_correction ? SweepShape{8, 16, 0} : SweepShape{16, 16, 2};
+  if (n - 1 >= 64) return fused_correction ? SweepShape{16, 16, 0} : SweepShape{8, 32, 0};
   if (n - 1 >= 16) return {8, 16, 0};
   if (n - 1 >= 8) return {8, 8, 0};
   if (n - 1 >= 4) return {4, 4, 0};

@@ -9,8 +9,8 @@
          with the hash of the kernel source it was taken on.
 
   python -m paper_1607_03252_amd.profsum trace CSV OUT --title T --command C
-  python -m paper_1607_03252_amd.profsum pmc FETCH_CSV WRITE_CSV OUT --kernel K
-         --grid G --command C [--copy-bytes B] [--tile TJ:TK:CHUNKS]
+  python -m paper_1607_03252_amd.profsum pmc FETCH_CSV WRITE_CSV OUT --match K@GRID ...
+         --command C [--copy-bytes B] [--tiles TJ:TK:CH,TJ:TK:CH]
 """
 import argparse
 import collections
@@ -33,9 +33,15 @@ def read_summary(path):
     return json.loads(txt.split(JSON_MARK, 1)[1])
 
 
+SWEEP_END = b"// ---- point kernels"
+
+
 def source_hash(path=KERNEL_SOURCE):
+    """SHA-256 of the device code the fused sweep is built from: the kernel
+    source up to the end of the sweep kernel (its helpers and the kernel)."""
     with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+        src = f.read()
+    return hashlib.sha256(src.split(SWEEP_END, 1)[0]).hexdigest()
 
 
 def short_name(s):
@@ -82,7 +88,7 @@ def counter_values(path, counter):
     return d
 
 
-def pmc_summary(fetch_csv, write_csv, kernel, grid, copy_bytes):
+def pmc_summary(fetch_csv, write_csv, matches, copy_bytes):
     f = counter_values(fetch_csv, "FETCH_SIZE")
     w = counter_values(write_csv, "WRITE_SIZE")
 
@@ -97,11 +103,13 @@ def pmc_summary(fetch_csv, write_csv, kernel, grid, copy_bytes):
     cf, cw = copy_kib(f), copy_kib(w)
     fs = (copy_bytes / 1024.0) / cf if cf else None
     ws = (copy_bytes / 1024.0) / cw if cw else None
-    fk = [v for (nm, g), v in f.items() if nm.startswith(kernel) and g == grid]
-    wk = [v for (nm, g), v in w.items() if nm.startswith(kernel) and g == grid]
+    def sel(d):
+        return [v for (nm, g), v in d.items() if any(nm == k and g == gr for k, gr in matches)]
+    fk, wk = sel(f), sel(w)
     fv = [x for v in fk for x in v]
     wv = [x for v in wk for x in v]
-    res = {"kernel": kernel, "grid": grid, "dispatches_fetch": len(fv), "dispatches_write": len(wv),
+    res = {"kernels": ["%s @ grid %d" % m for m in matches], "dispatches_fetch": len(fv),
+           "dispatches_write": len(wv),
            "fetch_kib": sum(fv) / len(fv) if fv else None,
            "write_kib": sum(wv) / len(wv) if wv else None,
            "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
@@ -128,11 +136,12 @@ def main():
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
     p.add_argument("out")
-    p.add_argument("--kernel", required=True)
-    p.add_argument("--grid", type=int, required=True)
+    p.add_argument("--match", action="append", required=True,
+                   help="KERNEL@GRID (repeatable): the dispatches averaged over")
     p.add_argument("--command", required=True)
     p.add_argument("--copy-bytes", type=float, default=float(1 << 30))
-    p.add_argument("--tile", default="")
+    p.add_argument("--tiles", default="",
+                   help="TJ:TK:CHUNKS,TJ:TK:CHUNKS of the plain and the fused-correction sweep")
     a = ap.parse_args()
     if a.cmd == "trace":
         txt = "%s\ncommand: %s\n\nper kernel and launch grid:\n%s\n" % (a.title, a.command,
@@ -142,9 +151,11 @@ def main():
         open(a.out, "w").write(txt)
         print(txt)
     else:
-        res, table = pmc_summary(a.fetch_csv, a.write_csv, a.kernel, a.grid, a.copy_bytes)
+        matches = [(m.rsplit("@", 1)[0], int(m.rsplit("@", 1)[1])) for m in a.match]
+        res, table = pmc_summary(a.fetch_csv, a.write_csv, matches, a.copy_bytes)
         res["command"] = a.command
-        res["tile"] = [int(x) for x in a.tile.split(":")] if a.tile else None
+        res["tiles"] = ([[int(x) for x in t.split(":")] for t in a.tiles.split(",")]
+                        if a.tiles else None)
         res["kernel_source_sha256"] = source_hash()
         with open(a.out, "w") as f:
             f.write("HBM traffic counters, per dispatch\ncommand: %s\n\n%s\n\n%s\n%s\n" % (
