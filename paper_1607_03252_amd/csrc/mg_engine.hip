@@ -181,6 +181,7 @@ struct mg_plan_s {
   int smoother = 0;      // 0: fused single-pass sweep, 1: two-pass colour sweeps
   int use_graph = 1;     // capture cycles into HIP graphs (mlmc_sample_batch)
   int small_ns = 17;     // grids of this size and below: the LDS V-cycle (0: off)
+  int transfer = 0;      // 0: fused residual + restriction, 1: separate kernels
   std::map<int, SweepShape> shape;      // tile shape per grid size
   std::map<int, SweepShape> shape_pro;  // same, sweeps with the fused coarse correction
   // profiling of the finest-grid smoothing launches
@@ -573,8 +574,12 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
     }
     for (int s = 0; s < nu1; ++s)
       cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0);
-    launch_residual<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);
-    launch_restrict<T>(Ls.d[si], cnt, n, B->ss.active, st);
+    if (P->transfer == 0) {
+      launch_resrestrict<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);
+    } else {
+      launch_residual<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);
+      launch_restrict<T>(Ls.d[si], cnt, n, B->ss.active, st);
+    }
   }
   size_t up = L - 1;  // the levels above this one are corrected and post-smoothed
   if (small < L) {
@@ -1230,6 +1235,9 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
     P->smoother = (int)value;
   } else if (k == "graph") {
     P->use_graph = value != 0;
+  } else if (k == "transfer") {
+    if (value != 0 && value != 1) return MG_EINVAL;
+    P->transfer = (int)value;
   } else if (k == "small_vcycle") {
     if (value != 0 && value != 5 && value != 9 && value != 17) return MG_EINVAL;
     P->small_ns = (int)value;

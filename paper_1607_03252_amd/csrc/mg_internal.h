@@ -113,6 +113,10 @@ void launch_residual(const GridDescT<T>* d_list, int count, int n, const int* d_
 template <typename T>
 void launch_restrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                      hipStream_t st);
+// Residual of u[buf] and full weighting into bc, in one pass (r is not stored).
+template <typename T>
+void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
+                        int buf, hipStream_t st);
 template <typename T>
 void launch_coarsest(const GridDescT<T>* d_list, int count, const int* d_active, hipStream_t st);
 template <typename T>

@@ -615,18 +615,22 @@ __device__ __forceinline__ void march_residual(const GridDescT<T>& d, const T* u
   const int bs = d.bstride;
   int p = sn2 + c.j * n + c.k;
   int pb = bs + c.j * n + c.k;
-  T um = 0, u0 = u[p], wm = wh[p - sn2], w0 = wh[p];
+  T um = 0, u0 = u[p], w0 = wh[p];
+  // the face to the plane below is the previous plane's face to the plane above
+  T fim = rcp<T>(w0 + wh[p - sn2]);
   for (int i = 1; i <= n - 2; ++i, p += sn2) {
     const T up = u[p + sn2], wp = wh[p + sn2];
-    const St<T> st = stencil6<T>(w0, wm, wp, wh[p - n], wh[p + n], wh[p - 1], wh[p + 1], um, up,
-                                 u[p - n], u[p + n], u[p - 1], u[p + 1]);
+    const T fip = rcp<T>(w0 + wp);
+    const St<T> st = stencil_faces<T>(fim, fip, rcp<T>(w0 + wh[p - n]), rcp<T>(w0 + wh[p + n]),
+                                      rcp<T>(w0 + wh[p - 1]), rcp<T>(w0 + wh[p + 1]), um, up,
+                                      u[p - n], u[p + n], u[p - 1], u[p + 1]);
     const T bp = bb[pb];
     pb += bs;
     f(i, p, res_value<T>(st, bp, u0));
     um = u0;
     u0 = up;
-    wm = w0;
     w0 = wp;
+    fim = fip;
   }
 }
 
@@ -671,6 +675,98 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const GridDescT<T>* __restr
   const int pc = vidx(nc, p.i, p.j, p.k);
   d.bc[pc] = (T)0.5 * s;
   d.uc[0][pc] = 0;
+}
+
+// Residual and full weighting in one pass: a workgroup owns RJ x RK coarse
+// columns and the (2RJ+1) x (2RK+1) fine columns under them; every fine
+// thread marches its column computing r = b' - A'u (as the residual kernel),
+// puts each plane's residuals in LDS, and the coarse threads add that
+// plane's share of the 27-point weights to their running sums, plane by plane
+// in increasing order (the order of the separate restriction).  r never goes
+// to memory; the coarse iterate uc[0] is zeroed as by the restriction.
+template <int RJ, int RK>
+struct RRGeom {
+  static constexpr int FJ = 2 * RJ + 1, FK = 2 * RK + 1, FT = FJ * FK;
+  static constexpr int THREADS = ((FT + 63) / 64) * 64;
+};
+
+template <typename T, int RJ, int RK>
+__global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
+    k_resrestrict(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
+                  int tiles_k, int count, int per) {
+  using G = RRGeom<RJ, RK>;
+  __shared__ T R[2][G::FT];
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDescT<T> d = list[gi];
+  if (!active[d.solve]) return;
+  const int n = d.n, sn2 = n * n, nc = (n - 1) / 2 + 1, bs = d.bstride;
+  const int tj = blk / tiles_k, tk = blk - tj * tiles_k;
+  const int J0 = 1 + tj * RJ, K0 = 1 + tk * RK;
+  const int t = threadIdx.x;
+  // this thread's fine column (rows 2 J0 - 1 .., columns 2 K0 - 1 ..)
+  const bool fl = t < G::FT;
+  const int fj = fl ? t / G::FK : 0, fk = fl ? t - (t / G::FK) * G::FK : 0;
+  const int j = 2 * J0 - 1 + fj, k = 2 * K0 - 1 + fk;
+  const bool fin = fl && j <= n - 2 && k <= n - 2;
+  const int jj = fin ? j : 1, kk = fin ? k : 1;
+  // this thread's coarse column
+  const bool cl = t < RJ * RK;
+  const int cj = cl ? t / RK : 0, ck = cl ? t - (t / RK) * RK : 0;
+  const int J = J0 + cj, K = K0 + ck;
+  const bool cin = cl && J <= nc - 2 && K <= nc - 2;
+  const int o = (2 * cj + 1) * G::FK + 2 * ck + 1;  // LDS index of fine (2J, 2K)
+  const gptr<const T> u = gview<T>(buf ? d.u[1] : d.u[0]);
+  const gptr<const T> wh = gview<T>(d.wh);
+  const gptr<const T> bb = gview<T>(d.b);
+  const gptr<T> bc = gview<T>(d.bc);
+  const gptr<T> uc = gview<T>(d.uc[0]);
+  int p = sn2 + jj * n + kk, pb = bs + jj * n + kk;
+  T um = 0, u0 = u[p], w0 = wh[p];
+  T fim = rcp<T>(w0 + wh[p - sn2]);
+  T s = 0;
+  for (int i = 1; i <= n - 2; ++i, p += sn2) {
+    const T up = u[p + sn2], wp = wh[p + sn2];
+    const T fip = rcp<T>(w0 + wp);
+    const St<T> st = stencil_faces<T>(fim, fip, rcp<T>(w0 + wh[p - n]), rcp<T>(w0 + wh[p + n]),
+                                      rcp<T>(w0 + wh[p - 1]), rcp<T>(w0 + wh[p + 1]), um, up,
+                                      u[p - n], u[p + n], u[p - 1], u[p + 1]);
+    const T r = res_value<T>(st, bb[pb], u0);
+    pb += bs;
+    if (fl) R[i & 1][t] = fin ? r : (T)0;
+    __syncthreads();
+    if (cin) {
+      const T* Rp = R[i & 1];
+      const T wi = (i & 1) ? (T)0.5 : (T)1;
+      T tm[3];
+#pragma unroll
+      for (int dj = -1; dj <= 1; ++dj) {
+        const T wj = dj == 0 ? wi : (T)0.5 * wi;
+        const int row = o + dj * G::FK;
+        tm[dj + 1] = wj * (Rp[row] + (T)0.5 * (Rp[row - 1] + Rp[row + 1]));
+      }
+      s += tm[0];
+      s += tm[1];
+      s += tm[2];
+      if (i & 1) {
+        // plane i closes coarse plane (i-1)/2 and opens (i+1)/2
+        const int I = (i - 1) >> 1;
+        if (I >= 1) {
+          const int pc = (I * nc + J) * nc + K;
+          bc[pc] = (T)0.5 * s;
+          uc[pc] = 0;
+        }
+        s = 0;
+        s += tm[0];
+        s += tm[1];
+        s += tm[2];
+      }
+    }
+    um = u0;
+    u0 = up;
+    w0 = wp;
+    fim = fip;
+  }
 }
 
 // 3^3 grid: one unknown, solved exactly into u[0].
@@ -1190,6 +1286,22 @@ void launch_residual(const GridDescT<T>* d_list, int count, int n, const int* d_
 }
 
 template <typename T>
+void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
+                        int buf, hipStream_t st) {
+  if (count <= 0) return;
+  const int m = (n - 1) / 2 - 1;  // coarse interior points per axis
+  if (n >= 65) {
+    const int tk = ceil_div(m, 32), per = ceil_div(m, 4) * tk;
+    hipLaunchKernelGGL((k_resrestrict<T, 4, 32>), xcd_grid(count, per),
+                       dim3(RRGeom<4, 32>::THREADS), 0, st, d_list, d_active, buf, tk, count, per);
+  } else {
+    const int tk = ceil_div(m, 16), per = ceil_div(m, 8) * tk;
+    hipLaunchKernelGGL((k_resrestrict<T, 8, 16>), xcd_grid(count, per),
+                       dim3(RRGeom<8, 16>::THREADS), 0, st, d_list, d_active, buf, tk, count, per);
+  }
+}
+
+template <typename T>
 void launch_restrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                      hipStream_t st) {
   if (count <= 0) return;
@@ -1237,6 +1349,7 @@ void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_
                                       hipStream_t);                                             \
   template void launch_residual<T>(const GridDescT<T>*, int, int, const int*, int, hipStream_t); \
   template void launch_restrict<T>(const GridDescT<T>*, int, int, const int*, hipStream_t);      \
+  template void launch_resrestrict<T>(const GridDescT<T>*, int, int, const int*, int, hipStream_t); \
   template void launch_coarsest<T>(const GridDescT<T>*, int, const int*, hipStream_t);           \
   template void launch_prolong<T>(const GridDescT<T>*, int, int, const int*, int, int,           \
                                   hipStream_t);                                                 \

@@ -79,6 +79,20 @@ def test_small_vcycle_matches_per_level_launches(M, torch, n0, level, prec):
         assert _same(out[ns], out[0]), ns
 
 
+@pytest.mark.parametrize("n0,level,prec", [(33, 1, 0), (33, 2, 0), (33, 1, 1)])
+def test_fused_transfer_matches_separate_kernels(M, torch, n0, level, prec):
+    # residual + full weighting in one pass (r never stored) against the
+    # residual kernel followed by the restriction kernel: bit for bit
+    seeds = [31, 32, 33]
+    out = {}
+    for tr in (0, 1):
+        P = M.mg_plan_create(n0=n0, max_level=level, precision=prec)
+        M.mg_plan_set_option(P, "transfer", tr)
+        out[tr] = _batch(M, torch, P, level, seeds)
+        assert out[tr][0] == M.MG_OK
+    assert _same(out[0], out[1])
+
+
 def test_small_vcycle_single_solve(M, torch):
     # a whole 17^3 solve in the LDS kernel (mg_solve), against per-level launches
     n = 17
