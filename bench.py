@@ -450,7 +450,10 @@ def bench_serve(args, M, torch, np):
         arr = np.cumsum(gaps) / lam
         res, lat, span = run_server(arr)
         rec = {"offered_per_s": lam, "served_per_s": N / span, "p50_ms": 1e3 * _pct(lat, 50),
-               "p99_ms": 1e3 * _pct(lat, 99)}
+               "p99_ms": 1e3 * _pct(lat, 99),
+               "per_level_p50_p99_ms": {
+                   str(l): [1e3 * _pct([x["t_done"] - x["t_arrival"] for x in res if x["level"] == l], q)
+                            for q in (50, 99)] for l in range(L + 1)}}
         if fifo_plans:
             lat_f = []
             t0 = time.perf_counter()

@@ -125,9 +125,9 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *               1 = two-pass in-place colour sweeps (same iterates);
  *   "graph":    1 = capture the cycles of mlmc_sample_batch into HIP graphs
  *               (default), 0 = launch eagerly;
- *   "transfer": 0 = residual and full weighting in one pass (default),
- *               1 = separate residual and restriction kernels (same results,
- *               bit for bit);
+ *   "transfer": 0 = residual and full weighting in one pass where a launch
+ *               has at least 128 workgroups (default), 1 = always separate
+ *               residual and restriction kernels (same results, bit for bit);
  *   "small_vcycle": 17 (default), 9 or 5 = from the largest grid of at most
  *               this size down, each V-cycle runs in one launch with the
  *               grids held in LDS; 0 = one launch per level and step

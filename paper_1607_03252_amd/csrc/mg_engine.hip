@@ -574,7 +574,9 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
     }
     for (int s = 0; s < nu1; ++s)
       cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0);
-    if (P->transfer == 0) {
+    // the one-pass transfer marches planes with a barrier each: with few
+    // workgroups the separate kernels (same results) finish sooner
+    if (P->transfer == 0 && cnt * resrestrict_blocks(n) >= 128) {
       launch_resrestrict<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);
     } else {
       launch_residual<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);

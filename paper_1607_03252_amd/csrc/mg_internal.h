@@ -113,7 +113,9 @@ void launch_residual(const GridDescT<T>* d_list, int count, int n, const int* d_
 template <typename T>
 void launch_restrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                      hipStream_t st);
-// Residual of u[buf] and full weighting into bc, in one pass (r is not stored).
+// Residual of u[buf] and full weighting into bc, in one pass (r is not stored);
+// resrestrict_blocks: its workgroups per grid.
+int resrestrict_blocks(int n);
 template <typename T>
 void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                         int buf, hipStream_t st);

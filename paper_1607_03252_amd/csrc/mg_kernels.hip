@@ -837,7 +837,7 @@ __global__ void __launch_bounds__(kBlock) k_copy_buf(const GridDescT<T>* __restr
 // one launch instead of several per level.  Each step is the same update as
 // the per-level kernels: red then black passes, residual, full weighting,
 // exact 3^3 solve, trilinear correction.
-constexpr int kSmallThreads = 512;
+constexpr int kSmallThreads = 1024;
 
 template <int NS>
 struct SmallGeo {
@@ -857,6 +857,9 @@ struct SmallGeo {
   __host__ __device__ static constexpr int off_r(int j) { return base(j) + (j > 0 ? 3 : 2) * vol(j); }
   static constexpr int total = base(J + 1);
 };
+
+template <int L>
+using IC = std::integral_constant<int, L>;
 
 template <typename T, int NS>
 __global__ void __launch_bounds__(kSmallThreads) k_vsmall(const SmallChain<T>* __restrict__ chains,
@@ -882,60 +885,78 @@ __global__ void __launch_bounds__(kSmallThreads) k_vsmall(const SmallChain<T>* _
   }
   __syncthreads();
 
-  auto bval = [&](int j, int i, int jj, int k) -> T {
-    const int n = Geo::n(j);
-    return j == 0 ? b_at<T>(top, i, jj, k) : lds[Geo::off_b(j) + (i * n + jj) * n + k];
+  // every level's size is a compile-time constant below, so the index
+  // arithmetic needs no division
+  auto bval = [&](auto lvl, int i, int jj, int k) -> T {
+    constexpr int Lv = decltype(lvl)::value, n = Geo::n(Lv);
+    if constexpr (Lv == 0) return b_at<T>(top, i, jj, k);
+    else return lds[Geo::off_b(Lv) + (i * n + jj) * n + k];
   };
-  // one colour pass on level j (in place)
-  auto colour = [&](int j, int c) {
-    const int n = Geo::n(j), m = n - 2;
-    T* u = lds + Geo::off_u(j);
-    const T* w = lds + Geo::off_w(j);
-    for (int q = t; q < m * m * m; q += kSmallThreads) {
-      const int i = q / (m * m) + 1, r = q % (m * m), jj = r / m + 1, k = r % m + 1;
-      if (((i + jj + k) & 1) != c) continue;
+  // one colour pass on level L (in place), over the points of that colour only
+  auto colour = [&](auto lvl, int c) {
+    constexpr int Lv = decltype(lvl)::value, n = Geo::n(Lv), m = n - 2, hk = (m + 1) / 2;
+    T* u = lds + Geo::off_u(Lv);
+    const T* w = lds + Geo::off_w(Lv);
+    for (int q = t; q < m * m * hk; q += kSmallThreads) {
+      const int i = q / (m * hk) + 1, rr = q % (m * hk), jj = rr / hk + 1;
+      const int k = 2 - ((c + i + jj) & 1) + 2 * (rr % hk);
+      if (k > m) continue;
       const int p = (i * n + jj) * n + k;
-      u[p] = gs_value<T>(stencil_at<T>(u, w, p, n, n * n), bval(j, i, jj, k));
+      u[p] = gs_value<T>(stencil_at<T>(u, w, p, n, n * n), bval(lvl, i, jj, k));
     }
     __syncthreads();
   };
-  auto sweep = [&](int j) {
-    colour(j, 0);
-    colour(j, 1);
+  auto down = [&](auto lvl) {
+    constexpr int Lv = decltype(lvl)::value, n = Geo::n(Lv), m = n - 2;
+    for (int s = 0; s < nu1; ++s) {
+      colour(lvl, 0);
+      colour(lvl, 1);
+    }
+    // residual of this level, then full weighting into b of the next
+    const T* u = lds + Geo::off_u(Lv);
+    const T* w = lds + Geo::off_w(Lv);
+    T* r = lds + Geo::off_r(Lv);
+    for (int q = t; q < m * m * m; q += kSmallThreads) {
+      const int i = q / (m * m) + 1, rr = q % (m * m), jj = rr / m + 1, k = rr % m + 1;
+      const int p = (i * n + jj) * n + k;
+      r[p] = res_value<T>(stencil_at<T>(u, w, p, n, n * n), bval(lvl, i, jj, k), u[p]);
+    }
+    __syncthreads();
+    constexpr int nc = Geo::n(Lv + 1), mc = nc - 2;
+    T* bc = lds + Geo::off_b(Lv + 1);
+    for (int q = t; q < mc * mc * mc; q += kSmallThreads) {
+      const int I = q / (mc * mc) + 1, rr = q % (mc * mc), Jj = rr / mc + 1, K = rr % mc + 1;
+      T acc = 0;
+      for (int di = -1; di <= 1; ++di) {
+        const T wi = di == 0 ? (T)1 : (T)0.5;
+        for (int dj = -1; dj <= 1; ++dj) {
+          const T wj = dj == 0 ? wi : (T)0.5 * wi;
+          const int row = ((2 * I + di) * n + 2 * Jj + dj) * n + 2 * K;
+          acc += wj * (r[row] + (T)0.5 * (r[row - 1] + r[row + 1]));
+        }
+      }
+      bc[(I * nc + Jj) * nc + K] = (T)0.5 * acc;
+    }
+    __syncthreads();
+  };
+  auto up = [&](auto lvl) {
+    constexpr int Lv = decltype(lvl)::value, n = Geo::n(Lv), m = n - 2, nc = Geo::n(Lv + 1);
+    T* u = lds + Geo::off_u(Lv);
+    const T* e = lds + Geo::off_u(Lv + 1);
+    for (int q = t; q < m * m * m; q += kSmallThreads) {
+      const int i = q / (m * m) + 1, rr = q % (m * m), jj = rr / m + 1, k = rr % m + 1;
+      u[(i * n + jj) * n + k] += prolong_at<T>(e, nc, i, jj, k);
+    }
+    __syncthreads();
+    for (int s = 0; s < nu2; ++s) {
+      colour(lvl, 0);
+      colour(lvl, 1);
+    }
   };
 
-  for (int j = 0; j < J; ++j) {
-    for (int s = 0; s < nu1; ++s) sweep(j);
-    // residual of level j, then full weighting into b of level j + 1
-    {
-      const int n = Geo::n(j), m = n - 2;
-      const T* u = lds + Geo::off_u(j);
-      const T* w = lds + Geo::off_w(j);
-      T* r = lds + Geo::off_r(j);
-      for (int q = t; q < m * m * m; q += kSmallThreads) {
-        const int i = q / (m * m), rr = q % (m * m), jj = rr / m + 1, k = rr % m + 1;
-        const int p = ((i + 1) * n + jj) * n + k;
-        r[p] = res_value<T>(stencil_at<T>(u, w, p, n, n * n), bval(j, i + 1, jj, k), u[p]);
-      }
-      __syncthreads();
-      const int nc = Geo::n(j + 1), mc = nc - 2;
-      T* bc = lds + Geo::off_b(j + 1);
-      for (int q = t; q < mc * mc * mc; q += kSmallThreads) {
-        const int I = q / (mc * mc) + 1, rr = q % (mc * mc), Jj = rr / mc + 1, K = rr % mc + 1;
-        T acc = 0;
-        for (int di = -1; di <= 1; ++di) {
-          const T wi = di == 0 ? (T)1 : (T)0.5;
-          for (int dj = -1; dj <= 1; ++dj) {
-            const T wj = dj == 0 ? wi : (T)0.5 * wi;
-            const int row = ((2 * I + di) * n + 2 * Jj + dj) * n + 2 * K;
-            acc += wj * (r[row] + (T)0.5 * (r[row - 1] + r[row + 1]));
-          }
-        }
-        bc[(I * nc + Jj) * nc + K] = (T)0.5 * acc;
-      }
-      __syncthreads();
-    }
-  }
+  down(IC<0>{});
+  if constexpr (J > 1) down(IC<1>{});
+  if constexpr (J > 2) down(IC<2>{});
   // the 3^3 level: one unknown, solved exactly
   if (t == 0) {
     const T* w = lds + Geo::off_w(J);
@@ -944,22 +965,12 @@ __global__ void __launch_bounds__(kSmallThreads) k_vsmall(const SmallChain<T>* _
     lds[Geo::off_u(J) + 13] = gs_value<T>(st, lds[Geo::off_b(J) + 13]);
   }
   __syncthreads();
-  for (int j = J - 1; j >= 0; --j) {
-    {
-      const int n = Geo::n(j), m = n - 2, nc = Geo::n(j + 1);
-      T* u = lds + Geo::off_u(j);
-      const T* e = lds + Geo::off_u(j + 1);
-      for (int q = t; q < m * m * m; q += kSmallThreads) {
-        const int i = q / (m * m) + 1, rr = q % (m * m), jj = rr / m + 1, k = rr % m + 1;
-        u[(i * n + jj) * n + k] += prolong_at<T>(e, nc, i, jj, k);
-      }
-      __syncthreads();
-    }
-    for (int s = 0; s < nu2; ++s) sweep(j);
-  }
+  if constexpr (J > 2) up(IC<2>{});
+  if constexpr (J > 1) up(IC<1>{});
+  up(IC<0>{});
   // the top level's iterate back to u[0]
   const gptr<T> uo = gview<T>(top.u[0]);
-  const int n = NS, m = n - 2;
+  constexpr int n = NS, m = n - 2;
   for (int q = t; q < m * m * m; q += kSmallThreads) {
     const int i = q / (m * m) + 1, rr = q % (m * m), jj = rr / m + 1, k = rr % m + 1;
     const int p = (i * n + jj) * n + k;
@@ -1283,6 +1294,11 @@ void launch_residual(const GridDescT<T>* d_list, int count, int n, const int* d_
   const int per = reduce_blocks(n);
   hipLaunchKernelGGL((k_residual<T>), xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
                      buf, count, per);
+}
+
+int resrestrict_blocks(int n) {
+  const int m = (n - 1) / 2 - 1;
+  return n >= 65 ? ceil_div(m, 4) * ceil_div(m, 32) : ceil_div(m, 8) * ceil_div(m, 16);
 }
 
 template <typename T>
