@@ -62,6 +62,36 @@ __device__ __forceinline__ gptr<const T> gview(const T* p) {
   return (gptr<const T>)p;
 }
 
+// Raw buffer access: a descriptor (uniform base, range in bytes) and 32-bit
+// per-lane byte offsets.  Loads past the range read 0 and stores past it are
+// dropped, which lets a kernel express "outside the grid" by an offset.
+constexpr uint32_t kOut = 0x7ffffff0u;  // an offset past any range used here
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, T v);
+template <>
+__device__ __forceinline__ void bstore<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  typedef unsigned int v2u __attribute__((__vector_size__(8)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+
 // Interior point of block `bid` of a grid with m = n-2 interior points per
 // axis: blocks cover (plane i, 4 rows j, 64 columns k).
 struct Pt {
@@ -386,10 +416,6 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
   const int ib = min(n - 2, ia + chunk_len - 1);
   const int istart = ia > 1 ? ia - 1 : 1;
   const int iend = min(ib + 1, n - 1);
-  const gptr<const T> uin = gview<T>(buf ? d.u[1] : d.u[0]);
-  const gptr<T> uout = gview<T>(buf ? d.u[0] : d.u[1]);
-  const gptr<const T> wh = gview<T>(d.wh);
-  const gptr<const T> bb = gview<T>(d.b);
   const gptr<const T> ec = gview<T>(PRO ? (cbuf ? d.uc[1] : d.uc[0]) : d.u[0]);
   const int nc = (n - 1) / 2 + 1;
 
@@ -419,20 +445,30 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
 
   T UB[4], W[4][2], B[4][2], NR[4], FIP[4];
   // plane m = istart + rel: black role (rel + 1) & 1
+  // byte offsets within a plane of this thread's two columns (past the plane
+  // for positions outside the grid, which then read 0), and of its outputs
+  // (past the plane for positions outside the tile or the interior)
+  const uint32_t pbytes = (uint32_t)(sn2 * sizeof(T));
+  uint32_t offi[2], offo[2];
+#pragma unroll
+  for (int rho = 0; rho < 2; ++rho) {
+    offi[rho] = in[rho] ? (uint32_t)((jc * n + col[rho]) * sizeof(T)) : kOut;
+    offo[rho] = tl[rho] ? (uint32_t)((j * n + kc[rho]) * sizeof(T)) : kOut;
+  }
   auto load = [&](int rel, T& ub, T (&w)[2], T (&b)[2]) {
     const int m = istart + rel;
-    const int mc = min(max(m, 0), n - 1);
-    const bool ok = m >= 0 && m <= n - 1;
+    const bool ok = m >= 0 && m <= n - 1;  // uniform: a plane outside reads 0
+    const int mc = ok ? m : 0;
     const int rb = (rel + 1) & 1;
+    const auto rw = rsrc(d.wh + (size_t)mc * sn2, ok ? pbytes : 0u);
+    const auto rbb = rsrc(d.b + (size_t)mc * bs, pbytes);
+    const auto ru = rsrc((buf ? d.u[1] : d.u[0]) + (size_t)mc * sn2, ok ? pbytes : 0u);
 #pragma unroll
     for (int rho = 0; rho < 2; ++rho) {
-      const T wv = wh[mc * sn2 + jc * n + col[rho]];
-      w[rho] = (ok && in[rho]) ? wv : (T)0;
-      b[rho] = bb[mc * bs + jc * n + col[rho]];
+      w[rho] = bload<T>(rw, offi[rho]);
+      b[rho] = bload<T>(rbb, offi[rho]);
     }
-    const int g = mc * sn2 + jc * n + (rb ? col[1] : col[0]);
-    const T uv = uin[g];
-    ub = (ok && (rb ? in[1] : in[0])) ? uv : (T)0;
+    ub = bload<T>(ru, rb ? offi[1] : offi[0]);
   };
 
   // Coarse correction (PRO): the coarse iterate's planes under the tile are
@@ -447,7 +483,6 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
   const bool cown = PRO && t < CJ * CK;
   const int crow = cown ? t / CK : 0, ccol = cown ? t - (t / CK) * CK : 0;
   T cstage = 0, PA[4] = {0, 0, 0, 0};
-  int cnext = 0;
   auto c_issue = [&](int C) {
     const int Cc = min(max(C, 0), nc - 1);
     cstage = ec[(Cc * nc + min(cj0 + crow, nc - 1)) * nc + min(ck0 + ccol, nc - 1)];
@@ -480,8 +515,7 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
       c_issue(C);
       c_store(C);
     }
-    cnext = chi + 1;
-    c_issue(cnext);
+    c_issue(((istart + 3) >> 1) + 1);  // stored at the end of plane istart
     __syncthreads();
     // black roles: plane istart-1 -> 0, istart -> 1, istart+1 -> 0
     UB[3] += pa_of(istart - 1, kc[0], intr[0]);
@@ -524,8 +558,13 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     NR[S0] = (t1[RHO] && intr[RHO] && i <= n - 2) ? vr : (T)0;
     FIP[S0] = fip;
     // black point of plane p = i - 1 (the column that is red on plane i)
+    // (planes outside this chunk, including the ones the last unrolled step
+    // may run past the end, are computed and their stores dropped: the
+    // output descriptor then has an empty range; no branch keeps the memory
+    // counters' bookkeeping exact)
     const int p = i - 1;
-    if (p >= ia && p <= ib) {
+    {
+      const bool outp = p >= ia && p <= ib;
       const T* Rl = sR[PBM];
       const T* Fj = sFj[PBM];
       const T* Fk = sFk[PBM];
@@ -533,9 +572,10 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
                                         NR[SM2], NR[S0], Rl[qq - W2], Rl[qq + W2], Rl[qq - 1],
                                         Rl[qq + 1]);
       const T vb = gs_value<T>(sb, B[SM][RHO]);
-      const int g = p * sn2 + j * n;
-      if (tl[RHO]) uout[g + kc[RHO]] = vb;
-      if (tl[1 - RHO]) uout[g + kc[1 - RHO]] = NR[SM];
+      const auto ro = rsrc((buf ? d.u[0] : d.u[1]) + (size_t)(outp ? p : 0) * sn2,
+                           outp ? pbytes : 0u);
+      bstore<T>(ro, offo[RHO], vb);
+      bstore<T>(ro, offo[1 - RHO], NR[SM]);
     }
     // publish plane i's red values and faces, and plane i+1's black u_in and
     // wh (the buffers read in this plane are the other parity)
@@ -552,20 +592,23 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     }
     // loads of plane i+3 (into the ring slot plane i-1 leaves); the next
     // coarse plane to LDS every second plane
-    if (i + 1 <= iend) load(i - istart + 3, UB[SM], W[SM], B[SM]);
-    if (PRO && ((i + 3) & 1) == 0) {
-      c_store(cnext);
-      ++cnext;
-      c_issue(cnext);
+    load(i - istart + 3, UB[SM], W[SM], B[SM]);
+    if (PRO) {
+      // coarse plane ((i+3)>>1)+1 to LDS (a second store of the same plane
+      // rewrites identical values), the next one into the staging register
+      c_store(((i + 3) >> 1) + 1);
+      c_issue(((i + 4) >> 1) + 1);
     }
     __syncthreads();
   };
 
+  // whole groups of four planes (up to three past iend: loads there read
+  // zeros or clamped planes, stores are dropped, LDS values are not used)
   for (int i = istart; i <= iend; i += 4) {
     plane(std::integral_constant<int, 0>{}, i);
-    if (i + 1 <= iend) plane(std::integral_constant<int, 1>{}, i + 1);
-    if (i + 2 <= iend) plane(std::integral_constant<int, 2>{}, i + 2);
-    if (i + 3 <= iend) plane(std::integral_constant<int, 3>{}, i + 3);
+    plane(std::integral_constant<int, 1>{}, i + 1);
+    plane(std::integral_constant<int, 2>{}, i + 2);
+    plane(std::integral_constant<int, 3>{}, i + 3);
   }
 }
 
