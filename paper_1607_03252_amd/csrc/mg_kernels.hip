@@ -647,33 +647,184 @@ __device__ __forceinline__ Col column_of(int m, int bid) {
   return {1 + j, 1 + k, j < m && k < m};
 }
 
-// Walks the interior planes of column c, calling f(i, p, r) with the residual
-// r = b' - A'u at vertex p = (i, c.j, c.k).
+// Column data of one plane m for the residual at (m, j, k): the four
+// in-plane neighbours of u and wh, b', and the centre u, wh of plane m + 1.
+template <typename T>
+struct ColSlot {
+  T u4[4], w4[4], b, uc, wc;
+};
+// Loads of column slots through per-plane buffer descriptors: a plane outside
+// the grid (or, for b', outside the interior) reads zeros, so a march can run
+// past its last plane without branches.
+template <typename T>
+struct ColLoader {
+  const T* u;
+  const T* wh;
+  const T* b;
+  int n, sn2, bs;
+  uint32_t pbytes, oc, o4[4];
+  __device__ __forceinline__ ColLoader(const GridDescT<T>& d, const T* u_, int j, int k)
+      : u(u_), wh(d.wh), b(d.b), n(d.n), sn2(d.n * d.n), bs(d.bstride) {
+    pbytes = (uint32_t)(sn2 * sizeof(T));
+    oc = (uint32_t)((j * n + k) * sizeof(T));
+    o4[0] = oc - (uint32_t)(n * sizeof(T));
+    o4[1] = oc + (uint32_t)(n * sizeof(T));
+    o4[2] = oc - (uint32_t)sizeof(T);
+    o4[3] = oc + (uint32_t)sizeof(T);
+  }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane(const T* base, int m, bool ok) const {
+    return rsrc(base + (size_t)(ok ? m : 0) * sn2, ok ? pbytes : 0u);
+  }
+  __device__ __forceinline__ void load(int m, ColSlot<T>& s) const {
+    const bool ok0 = m <= n - 1, ok1 = m + 1 <= n - 1, okb = m <= n - 2;
+    const auto ru = plane(u, m, ok0), rw = plane(wh, m, ok0);
+    const auto ru1 = plane(u, m + 1, ok1), rw1 = plane(wh, m + 1, ok1);
+    const auto rb = rsrc(b + (size_t)(okb ? m : 0) * bs, okb ? pbytes : 0u);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s.u4[q] = bload<T>(ru, o4[q]);
+      s.w4[q] = bload<T>(rw, o4[q]);
+    }
+    s.b = bload<T>(rb, oc);
+    s.uc = bload<T>(ru1, oc);
+    s.wc = bload<T>(rw1, oc);
+  }
+};
+
+// Walks the interior planes of column (c.j, c.k), calling f(i, r) with the
+// residual r = b' - A'u at (i, c.j, c.k) for i = 1 .. n-2, then with r = 0 for
+// up to two planes past n-2 (callers drop those: stores through an
+// empty-range descriptor, sums of zeros).  Three planes of loads are in
+// flight (a ring of three slots, the march unrolled by three, no branch).
 template <typename T, typename F>
 __device__ __forceinline__ void march_residual(const GridDescT<T>& d, const T* u_, Col c, F&& f) {
-  const int n = d.n, sn2 = n * n;
-  const gptr<const T> u = gview<T>(u_);
-  const gptr<const T> wh = gview<T>(d.wh);
-  const gptr<const T> bb = gview<T>(d.b);
-  const int bs = d.bstride;
-  int p = sn2 + c.j * n + c.k;
-  int pb = bs + c.j * n + c.k;
-  T um = 0, u0 = u[p], w0 = wh[p];
+  const int n = d.n;
+  const ColLoader<T> L(d, u_, c.ok ? c.j : 1, c.ok ? c.k : 1);
+  ColSlot<T> S[3];
+  L.load(1, S[0]);
+  L.load(2, S[1]);
+  L.load(3, S[2]);
+  const auto r0 = L.plane(u_, 1, true), w0r = L.plane(d.wh, 1, true), wm0 = L.plane(d.wh, 0, true);
+  T um = 0, u0 = bload<T>(r0, L.oc), w0 = bload<T>(w0r, L.oc);
   // the face to the plane below is the previous plane's face to the plane above
-  T fim = rcp<T>(w0 + wh[p - sn2]);
-  for (int i = 1; i <= n - 2; ++i, p += sn2) {
-    const T up = u[p + sn2], wp = wh[p + sn2];
+  T fim = rcp<T>(w0 + bload<T>(wm0, L.oc));
+  auto step = [&](auto kk, int i) {
+    constexpr int K = decltype(kk)::value;
+    ColSlot<T>& sl = S[K];
+    const T up = sl.uc, wp = sl.wc;
     const T fip = rcp<T>(w0 + wp);
-    const St<T> st = stencil_faces<T>(fim, fip, rcp<T>(w0 + wh[p - n]), rcp<T>(w0 + wh[p + n]),
-                                      rcp<T>(w0 + wh[p - 1]), rcp<T>(w0 + wh[p + 1]), um, up,
-                                      u[p - n], u[p + n], u[p - 1], u[p + 1]);
-    const T bp = bb[pb];
-    pb += bs;
-    f(i, p, res_value<T>(st, bp, u0));
+    const St<T> st = stencil_faces<T>(fim, fip, rcp<T>(w0 + sl.w4[0]), rcp<T>(w0 + sl.w4[1]),
+                                      rcp<T>(w0 + sl.w4[2]), rcp<T>(w0 + sl.w4[3]), um, up,
+                                      sl.u4[0], sl.u4[1], sl.u4[2], sl.u4[3]);
+    const T r = res_value<T>(st, sl.b, u0);
+    f(i, (c.ok && i <= n - 2) ? r : (T)0);
     um = u0;
     u0 = up;
     w0 = wp;
     fim = fip;
+    L.load(i + 3, sl);
+    // keep each plane's loads where they are (issued two planes before use)
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  for (int i = 1; i <= n - 2; i += 3) {
+    step(std::integral_constant<int, 0>{}, i);
+    step(std::integral_constant<int, 1>{}, i + 1);
+    step(std::integral_constant<int, 2>{}, i + 2);
+  }
+}
+
+// The residual over a tile of 4 rows x 64 columns (one column per thread of
+// a 256-thread block, the column decomposition of column_of), marched over the
+// planes with each plane's u and wh of the tile and its one-point ring in LDS:
+// a thread loads only its own column (and 136 threads one ring position), the
+// in-plane neighbours come from LDS.  Calls f(i, r) for i = 1 .. n-2 with
+// r = b' - A'u at (i, c.j, c.k) (0 where c is not interior), then with r = 0
+// for up to three planes past n-2.  Loads run two planes ahead (rings of
+// four slots, the march unrolled by four, no branch); one barrier per plane.
+// The stencil operands and their order are those of march_residual, so the
+// values are identical.
+template <typename T, typename F>
+__device__ __forceinline__ void tile_residual(const GridDescT<T>& d, const T* u_, int blk, F&& f) {
+  constexpr int TJ = 4, TK = 64, W = TK + 2, H = TJ + 2, A = W * H;
+  __shared__ T LU[2][A], LW[2][A];
+  const int n = d.n, sn2 = n * n, m = n - 2;
+  const int nkc = ceil_div(m, TK);
+  const int kc = blk % nkc, jc = blk / nkc;
+  const int t = threadIdx.x;
+  const int r = t >> 6, cc = t & 63;
+  const int j = 1 + jc * TJ + r, k = 1 + kc * TK + cc;
+  const bool interior = j <= n - 2 && k <= n - 2;
+  const bool ingrid = j <= n - 1 && k <= n - 1;
+  const int q = (r + 1) * W + cc + 1;
+  // ring position of this thread (t < 136): rows above/below, columns left/right
+  int hr, hc;
+  if (t < 64) { hr = 0; hc = t + 1; }
+  else if (t < 128) { hr = H - 1; hc = t - 63; }
+  else if (t < 132) { hr = t - 127; hc = 0; }
+  else { hr = t - 131; hc = W - 1; }
+  const bool halo = t < 136;
+  const int hj = jc * TJ + hr, hk = kc * TK + hc;  // grid coordinates (row j0-1+hr)
+  const bool hgrid = halo && hj >= 0 && hj <= n - 1 && hk >= 0 && hk <= n - 1;
+  const int hq = hr * W + hc;
+  const uint32_t pbytes = (uint32_t)(sn2 * sizeof(T));
+  const uint32_t oo = ingrid ? (uint32_t)((j * n + k) * sizeof(T)) : kOut;
+  const uint32_t oh = hgrid ? (uint32_t)((hj * n + hk) * sizeof(T)) : kOut;
+  auto plane = [&](const T* base, int pm, bool ok) {
+    return rsrc(base + (size_t)(ok ? pm : 0) * sn2, ok ? pbytes : 0u);
+  };
+  T OU[4], OW[4], OB[4], HU[4], HW[4];
+  // plane pm into ring slot (pm - 1) & 3
+  auto load = [&](int pm, int sl) {
+    const bool ok = pm <= n - 1, okb = pm <= n - 2;
+    const auto ru = plane(u_, pm, ok), rw = plane(d.wh, pm, ok);
+    const auto rb = rsrc(d.b + (size_t)(okb ? pm : 0) * d.bstride, okb ? pbytes : 0u);
+    OU[sl] = bload<T>(ru, oo);
+    OW[sl] = bload<T>(rw, oo);
+    OB[sl] = bload<T>(rb, oo);
+    HU[sl] = bload<T>(ru, oh);
+    HW[sl] = bload<T>(rw, oh);
+  };
+  load(0, 3);
+  load(1, 0);
+  load(2, 1);
+  load(3, 2);
+  LU[1][q] = OU[0];
+  LW[1][q] = OW[0];
+  if (halo) {
+    LU[1][hq] = HU[0];
+    LW[1][hq] = HW[0];
+  }
+  __syncthreads();
+  T fim = rcp<T>(OW[0] + OW[3]);
+  auto step = [&](auto kk, int i) {
+    constexpr int K = decltype(kk)::value;
+    constexpr int S0 = K, SM = (K + 3) & 3, SP = (K + 1) & 3;
+    constexpr int PB = (K + 1) & 1, PN = K & 1;  // LDS buffers of planes i and i+1
+    const T w = OW[S0];
+    const T fip = rcp<T>(w + OW[SP]);
+    const T* Lu = LU[PB];
+    const T* Lw = LW[PB];
+    const St<T> st = stencil_faces<T>(fim, fip, rcp<T>(w + Lw[q - W]), rcp<T>(w + Lw[q + W]),
+                                      rcp<T>(w + Lw[q - 1]), rcp<T>(w + Lw[q + 1]), OU[SM],
+                                      OU[SP], Lu[q - W], Lu[q + W], Lu[q - 1], Lu[q + 1]);
+    const T rv = res_value<T>(st, OB[S0], OU[S0]);
+    f(i, (interior && i <= n - 2) ? rv : (T)0);
+    fim = fip;
+    // plane i+1 to LDS, loads of plane i+3 into the slot plane i-1 leaves
+    LU[PN][q] = OU[SP];
+    LW[PN][q] = OW[SP];
+    if (halo) {
+      LU[PN][hq] = HU[SP];
+      LW[PN][hq] = HW[SP];
+    }
+    load(i + 3, SM);
+    __syncthreads();
+  };
+  for (int i = 1; i <= n - 2; i += 4) {
+    step(std::integral_constant<int, 0>{}, i);
+    step(std::integral_constant<int, 1>{}, i + 1);
+    step(std::integral_constant<int, 2>{}, i + 2);
+    step(std::integral_constant<int, 3>{}, i + 3);
   }
 }
 
@@ -687,8 +838,12 @@ __global__ void __launch_bounds__(kBlock) k_residual(const GridDescT<T>* __restr
   if (!active[d.solve]) return;
   const Col c = column_of(d.n - 2, blk);
   if (!c.ok) return;
-  const gptr<T> r = gview<T>(d.r);
-  march_residual<T>(d, buf ? d.u[1] : d.u[0], c, [&](int, int p, T v) { r[p] = v; });
+  const int n = d.n, sn2 = n * n;
+  const uint32_t oc = (uint32_t)((c.j * n + c.k) * sizeof(T)), pbytes = (uint32_t)(sn2 * sizeof(T));
+  march_residual<T>(d, buf ? d.u[1] : d.u[0], c, [&](int i, T v) {
+    const bool ok = i <= n - 2;
+    bstore<T>(rsrc(d.r + (size_t)(ok ? i : 0) * sn2, ok ? pbytes : 0u), oc, v);
+  });
 }
 
 // Full weighting of the residual to the coarse right-hand side, h^2 scaling
@@ -1040,10 +1195,10 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const GridDesc* __restrict__ 
   const Col c = column_of(n - 2, blk);
   const double* u = buf ? d.u[1] : d.u[0];
   double acc = 0.0;
-  if (c.ok) {
-    if (mode == RED_RESID) {
-      march_residual<double>(d, u, c, [&](int, int, double r) { acc += r * r; });
-    } else {
+  if (mode == RED_RESID) {
+    tile_residual<double>(d, u, blk, [&](int, double r) { acc += r * r; });
+  } else if (c.ok) {
+    {
       int p = sn2 + c.j * n + c.k;
       for (int i = 1; i <= n - 2; ++i, p += sn2) {
         if (mode == RED_BNORM) {
@@ -1073,13 +1228,16 @@ __global__ void __launch_bounds__(kBlock) k_defect(const GridDesc* __restrict__ 
   const GridDesc32 e = list32[gi];
   const Col c = column_of(d.n - 2, blk);
   double acc = 0.0;
-  const gptr<float> eb = gview<float>(e.b), eu = gview<float>(e.u[0]);
-  if (c.ok)
-    march_residual<double>(d, d.u[0], c, [&](int, int p, double r) {
-      acc += r * r;
-      eb[p] = (float)r;
-      eu[p] = 0.0f;
-    });
+  const int n = d.n, sn2 = n * n;
+  const uint32_t oc = (uint32_t)((c.j * n + c.k) * sizeof(float));
+  const uint32_t pbytes = (uint32_t)(sn2 * sizeof(float));
+  const uint32_t ocx = c.ok ? oc : kOut;
+  tile_residual<double>(d, d.u[0], blk, [&](int i, double r) {
+    acc += r * r;
+    const bool ok = i <= n - 2;
+    bstore<float>(rsrc(e.b + (size_t)(ok ? i : 0) * sn2, ok ? pbytes : 0u), ocx, (float)r);
+    bstore<float>(rsrc(e.u[0] + (size_t)(ok ? i : 0) * sn2, ok ? pbytes : 0u), ocx, 0.0f);
+  });
   acc = block_sum(acc);
   if (threadIdx.x == 0) partials[d.poff + blk] = acc;
 }
