@@ -893,77 +893,139 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
     k_resrestrict(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
                   int tiles_k, int count, int per) {
   using G = RRGeom<RJ, RK>;
+  // fine tile FJ x FK with a one-point ring in LDS (u, wh per plane parity)
+  constexpr int FJ = G::FJ, FK = G::FK, W = FK + 2, H = FJ + 2, A = W * H;
+  constexpr int NH = 2 * FK + 2 * FJ;  // ring positions (corners are not needed)
+  __shared__ T LU[2][A], LW[2][A];
   __shared__ T R[2][G::FT];
   int gi, blk;
   if (!xcd_unit(count, per, gi, blk)) return;
   const GridDescT<T> d = list[gi];
   if (!active[d.solve]) return;
-  const int n = d.n, sn2 = n * n, nc = (n - 1) / 2 + 1, bs = d.bstride;
+  const int n = d.n, sn2 = n * n, nc = (n - 1) / 2 + 1;
   const int tj = blk / tiles_k, tk = blk - tj * tiles_k;
   const int J0 = 1 + tj * RJ, K0 = 1 + tk * RK;
+  const int jb = 2 * J0 - 1, kb = 2 * K0 - 1;  // fine origin of the tile
   const int t = threadIdx.x;
-  // this thread's fine column (rows 2 J0 - 1 .., columns 2 K0 - 1 ..)
+  // this thread's fine column
   const bool fl = t < G::FT;
-  const int fj = fl ? t / G::FK : 0, fk = fl ? t - (t / G::FK) * G::FK : 0;
-  const int j = 2 * J0 - 1 + fj, k = 2 * K0 - 1 + fk;
+  const int fj = fl ? t / FK : 0, fk = fl ? t - (t / FK) * FK : 0;
+  const int j = jb + fj, k = kb + fk;
   const bool fin = fl && j <= n - 2 && k <= n - 2;
-  const int jj = fin ? j : 1, kk = fin ? k : 1;
+  const bool fgrid = fl && j <= n - 1 && k <= n - 1;
+  const int q = (fj + 1) * W + fk + 1;
+  // ring position (t < NH): rows above/below the tile, then columns left/right
+  int hr = 0, hc = 0;
+  if (t < FK) { hr = 0; hc = t + 1; }
+  else if (t < 2 * FK) { hr = H - 1; hc = t - FK + 1; }
+  else if (t < 2 * FK + FJ) { hr = t - 2 * FK + 1; hc = 0; }
+  else if (t < NH) { hr = t - 2 * FK - FJ + 1; hc = W - 1; }
+  const bool halo = t < NH;
+  const int hj = jb - 1 + hr, hk = kb - 1 + hc;
+  const bool hgrid = halo && hj >= 0 && hj <= n - 1 && hk >= 0 && hk <= n - 1;
+  const int hq = hr * W + hc;
   // this thread's coarse column
   const bool cl = t < RJ * RK;
   const int cj = cl ? t / RK : 0, ck = cl ? t - (t / RK) * RK : 0;
   const int J = J0 + cj, K = K0 + ck;
   const bool cin = cl && J <= nc - 2 && K <= nc - 2;
-  const int o = (2 * cj + 1) * G::FK + 2 * ck + 1;  // LDS index of fine (2J, 2K)
-  const gptr<const T> u = gview<T>(buf ? d.u[1] : d.u[0]);
-  const gptr<const T> wh = gview<T>(d.wh);
-  const gptr<const T> bb = gview<T>(d.b);
-  const gptr<T> bc = gview<T>(d.bc);
-  const gptr<T> uc = gview<T>(d.uc[0]);
-  int p = sn2 + jj * n + kk, pb = bs + jj * n + kk;
-  T um = 0, u0 = u[p], w0 = wh[p];
-  T fim = rcp<T>(w0 + wh[p - sn2]);
+  const int o = (2 * cj + 1) * FK + 2 * ck + 1;  // R index of fine (2J, 2K)
+  const uint32_t pbytes = (uint32_t)(sn2 * sizeof(T));
+  const uint32_t cbytes = (uint32_t)(nc * nc * sizeof(T));
+  const uint32_t oo = fgrid ? (uint32_t)((j * n + k) * sizeof(T)) : kOut;
+  const uint32_t oh = hgrid ? (uint32_t)((hj * n + hk) * sizeof(T)) : kOut;
+  const uint32_t oco = cin ? (uint32_t)((J * nc + K) * sizeof(T)) : kOut;
+  const T* u_ = buf ? d.u[1] : d.u[0];
+  auto plane = [&](const T* base, int pm, bool ok) {
+    return rsrc(base + (size_t)(ok ? pm : 0) * sn2, ok ? pbytes : 0u);
+  };
+  T OU[4], OW[4], OB[4], HU[4], HW[4];
+  auto load = [&](int pm, int sl) {
+    const bool ok = pm <= n - 1, okb = pm <= n - 2;
+    const auto ru = plane(u_, pm, ok), rw = plane(d.wh, pm, ok);
+    const auto rb = rsrc(d.b + (size_t)(okb ? pm : 0) * d.bstride, okb ? pbytes : 0u);
+    OU[sl] = bload<T>(ru, oo);
+    OW[sl] = bload<T>(rw, oo);
+    OB[sl] = bload<T>(rb, oo);
+    HU[sl] = bload<T>(ru, oh);
+    HW[sl] = bload<T>(rw, oh);
+  };
+  load(0, 3);
+  load(1, 0);
+  load(2, 1);
+  load(3, 2);
+  if (fl) {
+    LU[1][q] = OU[0];
+    LW[1][q] = OW[0];
+  }
+  if (halo) {
+    LU[1][hq] = HU[0];
+    LW[1][hq] = HW[0];
+  }
+  __syncthreads();
+  T fim = rcp<T>(OW[0] + OW[3]);
   T s = 0;
-  for (int i = 1; i <= n - 2; ++i, p += sn2) {
-    const T up = u[p + sn2], wp = wh[p + sn2];
-    const T fip = rcp<T>(w0 + wp);
-    const St<T> st = stencil_faces<T>(fim, fip, rcp<T>(w0 + wh[p - n]), rcp<T>(w0 + wh[p + n]),
-                                      rcp<T>(w0 + wh[p - 1]), rcp<T>(w0 + wh[p + 1]), um, up,
-                                      u[p - n], u[p + n], u[p - 1], u[p + 1]);
-    const T r = res_value<T>(st, bb[pb], u0);
-    pb += bs;
-    if (fl) R[i & 1][t] = fin ? r : (T)0;
+  auto step = [&](auto kk, int i) {
+    constexpr int KS = decltype(kk)::value;
+    constexpr int S0 = KS, SM = (KS + 3) & 3, SP = (KS + 1) & 3;
+    constexpr int PB = (KS + 1) & 1, PN = KS & 1;  // buffers of planes i and i+1
+    const int qs = fl ? q : W + 1;
+    const T w = OW[S0];
+    const T fip = rcp<T>(w + OW[SP]);
+    const T* Lu = LU[PB];
+    const T* Lw = LW[PB];
+    const St<T> st = stencil_faces<T>(fim, fip, rcp<T>(w + Lw[qs - W]), rcp<T>(w + Lw[qs + W]),
+                                      rcp<T>(w + Lw[qs - 1]), rcp<T>(w + Lw[qs + 1]), OU[SM],
+                                      OU[SP], Lu[qs - W], Lu[qs + W], Lu[qs - 1], Lu[qs + 1]);
+    const T rv = res_value<T>(st, OB[S0], OU[S0]);
+    fim = fip;
+    if (fl) {
+      R[PB][t] = (fin && i <= n - 2) ? rv : (T)0;
+      LU[PN][q] = OU[SP];
+      LW[PN][q] = OW[SP];
+    }
+    if (halo) {
+      LU[PN][hq] = HU[SP];
+      LW[PN][hq] = HW[SP];
+    }
+    load(i + 3, SM);
     __syncthreads();
-    if (cin) {
-      const T* Rp = R[i & 1];
-      const T wi = (i & 1) ? (T)0.5 : (T)1;
+    // this plane's share of the 27-point weights (coarse threads: the first
+    // two waves), in increasing plane order; an odd plane closes coarse plane
+    // (i-1)/2 (stored if interior) and opens (i+1)/2
+    if (cl) {
+      const T* Rp = R[PB];
+      const bool odd = (i & 1) != 0;
+      const T wi = odd ? (T)0.5 : (T)1;
       T tm[3];
 #pragma unroll
       for (int dj = -1; dj <= 1; ++dj) {
         const T wj = dj == 0 ? wi : (T)0.5 * wi;
-        const int row = o + dj * G::FK;
+        const int row = o + dj * FK;
         tm[dj + 1] = wj * (Rp[row] + (T)0.5 * (Rp[row - 1] + Rp[row + 1]));
       }
-      s += tm[0];
-      s += tm[1];
-      s += tm[2];
-      if (i & 1) {
-        // plane i closes coarse plane (i-1)/2 and opens (i+1)/2
-        const int I = (i - 1) >> 1;
-        if (I >= 1) {
-          const int pc = (I * nc + J) * nc + K;
-          bc[pc] = (T)0.5 * s;
-          uc[pc] = 0;
-        }
-        s = 0;
-        s += tm[0];
-        s += tm[1];
-        s += tm[2];
-      }
+      T s1 = s;
+      s1 += tm[0];
+      s1 += tm[1];
+      s1 += tm[2];
+      const int I = (i - 1) >> 1;
+      const bool st_ok = odd && I >= 1 && I <= nc - 2;
+      bstore<T>(rsrc(d.bc + (size_t)(st_ok ? I : 0) * nc * nc, st_ok ? cbytes : 0u), oco,
+                (T)0.5 * s1);
+      bstore<T>(rsrc(d.uc[0] + (size_t)(st_ok ? I : 0) * nc * nc, st_ok ? cbytes : 0u), oco,
+                (T)0);
+      T s0 = 0;
+      s0 += tm[0];
+      s0 += tm[1];
+      s0 += tm[2];
+      s = odd ? s0 : s1;
     }
-    um = u0;
-    u0 = up;
-    w0 = wp;
-    fim = fip;
+  };
+  for (int i = 1; i <= n - 2; i += 4) {
+    step(std::integral_constant<int, 0>{}, i);
+    step(std::integral_constant<int, 1>{}, i + 1);
+    step(std::integral_constant<int, 2>{}, i + 2);
+    step(std::integral_constant<int, 3>{}, i + 3);
   }
 }
 
