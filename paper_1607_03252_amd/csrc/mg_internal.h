@@ -127,7 +127,8 @@ void launch_prolong(const GridDescT<T>* d_list, int count, int n, const int* d_a
 template <typename T>
 void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_active, int from,
                      hipStream_t st);
-// u[0] (and u[1] if present) = 0 on every vertex of the listed grids.
+// u[0] = 0 on every vertex of the listed grids (u[1] needs no clearing: the
+// first sweep of a level writes all its interior points before any read).
 template <typename T>
 void launch_zero_u(const GridDescT<T>* d_list, int count, int n, hipStream_t st);
 

@@ -300,27 +300,30 @@ __global__ void __launch_bounds__(kBlock) k_field(int n, double* const* __restri
     C[threadIdx.x] = coef[threadIdx.x] * normals[(size_t)xi_index[g] * 64 + threadIdx.x];
   __syncthreads();
   const Pt p = full_point(n, blk);
-  if (!p.ok) return;
-  double px[4], py[4], pz[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    px[a] = phi[a * n + p.i];
-    py[a] = phi[a * n + p.j];
-    pz[a] = phi[a * n + p.k];
-  }
-  double Z = 0.0;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    double g2 = 0.0;
+  // a wave covers one row (i, j): lane c < 4 forms the row's partial sum
+  // G_c = sum_b (sum_a C_abc phi_a(x_i)) phi_b(y_j), shared by shuffles
+  const int lane = threadIdx.x & 63;
+  // (the row's coordinates hold for every lane of the wave, also for lanes
+  // whose column lies past the grid)
+  const int ic = min(p.i, n - 1), jc = min(p.j, n - 1);
+  double G = 0.0;
+  if (lane < 4) {
+    const int c = lane;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       double g1 = 0.0;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) g1 += C[16 * a + 4 * b + c] * px[a];
-      g2 += g1 * py[b];
+      for (int a = 0; a < 4; ++a) g1 += C[16 * a + 4 * b + c] * phi[a * n + ic];
+      G += g1 * phi[b * n + jc];
     }
-    Z += g2 * pz[c];
   }
+  double Gc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Gc[c] = __shfl(G, c, 64);
+  if (!p.ok) return;
+  double Z = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Z += Gc[c] * phi[c * n + p.k];
   out[g][vidx(n, p.i, p.j, p.k)] = mode == 0 ? 0.5 * exp(-Z) : exp(Z);
 }
 
@@ -1063,15 +1066,20 @@ __global__ void __launch_bounds__(kBlock) k_prolong(const GridDescT<T>* __restri
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_zero_u(const GridDescT<T>* __restrict__ list,
                                                    int count, int per) {
+  // each plane as a flat range, 8 values per thread through a buffer
+  // descriptor (positions past the plane are dropped); u[1] needs no
+  // clearing: a level's first sweep writes all its interior points before any
+  // read, and its boundary stays zero from allocation
   int gi, blk;
   if (!xcd_unit(count, per, gi, blk)) return;
   const GridDescT<T> d = list[gi];
-  const int n = d.n;
-  const Pt p = full_point(n, blk);
-  if (!p.ok) return;
-  const int v = vidx(n, p.i, p.j, p.k);
-  d.u[0][v] = 0;
-  if (d.u[1]) d.u[1][v] = 0;
+  const int n = d.n, sn2 = n * n;
+  const int bpp = ceil_div(sn2, kBlock * 8);  // blocks per plane (offsets stay 32-bit)
+  const int pl = blk / bpp, ch = blk - pl * bpp;
+  const auto r = rsrc(d.u[0] + (size_t)pl * sn2, (uint32_t)(sn2 * sizeof(T)));
+  const uint32_t base = ((uint32_t)ch * kBlock * 8u + threadIdx.x) * (uint32_t)sizeof(T);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) bstore<T>(r, base + (uint32_t)(e * kBlock * sizeof(T)), (T)0);
 }
 
 template <typename T>
@@ -1608,7 +1616,7 @@ void launch_prolong(const GridDescT<T>* d_list, int count, int n, const int* d_a
 template <typename T>
 void launch_zero_u(const GridDescT<T>* d_list, int count, int n, hipStream_t st) {
   if (count <= 0) return;
-  const int per = point_blocks(n);
+  const int per = n * ceil_div(n * n, kBlock * 8);
   hipLaunchKernelGGL((k_zero_u<T>), xcd_grid(count, per), dim3(kBlock), 0, st, d_list, count, per);
 }
 
