@@ -207,7 +207,8 @@ namespace mg {
 static SweepShape shape_for(mg_plan_s* P, int n, bool pro = false) {
   const auto& m = pro ? P->shape_pro : P->shape;
   auto it = m.find(n);
-  return it != m.end() ? it->second : default_sweep_shape(n, pro);
+  return it != m.end() ? it->second
+                       : default_sweep_shape(n, pro, P->desc.precision == MG_MIXED);
 }
 
 // Order the plan's stream after everything queued so far on the caller's.
@@ -1392,7 +1393,7 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
     // separately (their register use, hence occupancy, differs)
     for (int pro = 0; pro < 2; ++pro) {
       double best = 1e30;
-      SweepShape pick = default_sweep_shape(n, pro != 0);
+      SweepShape pick = default_sweep_shape(n, pro != 0, mixed);
       for (int i = 0; i < c; ++i)
         for (int chunks : {0, 1, 2, 4}) {
           if (chunks > 1 && (n - 2) / chunks < 4) continue;

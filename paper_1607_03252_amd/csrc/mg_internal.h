@@ -74,7 +74,9 @@ struct SweepShape {
 };
 // Shapes with compiled kernels for grid size n (TJ, TK divide n-1).
 int sweep_shapes(int n, SweepShape* out, int max_out);
-SweepShape default_sweep_shape(int n, bool fused_correction = false);
+// fused_correction: the sweep that also adds the coarse correction;
+// single: FP32 sweeps (the inner cycles of mixed precision)
+SweepShape default_sweep_shape(int n, bool fused_correction = false, bool single = false);
 
 // ---- launchers (all asynchronous on `st`) --------------------------------
 // Normals of `count` samples; the counter's level word is d_levels[s] when

@@ -1462,12 +1462,20 @@ int sweep_shapes(int n, SweepShape* out, int max_out) {
   return c;
 }
 
-SweepShape default_sweep_shape(int n, bool fused_correction) {
-  // measured best on MI355X for a batch of 64 MLMC level pairs (64 grids of
-  // 65^3 and 128 of 33^3); other sizes: a shape with enough workgroups
-  if (n == 65) return fused_correction ? SweepShape{16, 16, 2} : SweepShape{8, 32, 1};
-  if (n == 33) return fused_correction ? SweepShape{8, 16, 0} : SweepShape{16, 16, 2};
-  if (n - 1 >= 64) return fused_correction ? SweepShape{16, 16, 0} : SweepShape{8, 32, 0};
+SweepShape default_sweep_shape(int n, bool fused_correction, bool single) {
+  // measured best on MI355X: 65^3 and 33^3 for a batch of 64 MLMC level pairs
+  // (64 grids of 65^3, 128 of 33^3); 257^3 and 129^3 for batches of 16 and 48
+  // grids; FP32 (the inner cycles of mixed precision) for 16 grids of 257^3
+  if (single) {
+    if (n >= 257) return fused_correction ? SweepShape{8, 64, 0} : SweepShape{8, 64, 4};
+    if (n == 129) return {8, 64, 1};
+    if (n == 65) return {16, 32, 4};
+    if (n == 33) return fused_correction ? SweepShape{16, 32, 0} : SweepShape{16, 16, 0};
+  } else {
+    if (n >= 129) return {16, 32, 1};
+    if (n == 65) return fused_correction ? SweepShape{16, 32, 1} : SweepShape{8, 64, 1};
+    if (n == 33) return fused_correction ? SweepShape{8, 16, 1} : SweepShape{16, 16, 1};
+  }
   if (n - 1 >= 16) return {8, 16, 0};
   if (n - 1 >= 8) return {8, 8, 0};
   if (n - 1 >= 4) return {4, 4, 0};
