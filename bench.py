@@ -76,6 +76,9 @@ def main():
                     help="n:tj:tk:chunks, pins a smoother tile shape (skips the autotuner)")
     ap.add_argument("--tile-pro", action="append", default=[],
                     help="n:tj:tk:chunks, the shape of the sweep with the fused coarse correction")
+    ap.add_argument("--opt", action="append", default=[],
+                    help="name=value, a plan option (mg_plan_set_option) for the level-pair "
+                         "workload, e.g. norm=0 or transfer=1")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -102,6 +105,9 @@ def main():
     n0, level, S = 33, 1, args.samples
     P = M.mg_plan_create(n0=n0, max_level=level, sigma2=1.0, corr_len=0.1, tol=1e-8,
                          nu1=2, nu2=2, max_cycles=50)
+    for spec in args.opt:
+        name, value = spec.split("=")
+        M.mg_plan_set_option(P, name, int(value))
     Y = torch.zeros(S, dtype=torch.float64, device="cuda")
     Qf, Qc = torch.zeros_like(Y), torch.zeros_like(Y)
     cyc = torch.zeros(2 * S, dtype=torch.int32, device="cuda")
@@ -184,7 +190,8 @@ def main():
                    "samples_per_step": S, "sigma2": 1.0, "corr_len": 0.1, "tol": 1e-8,
                    "cycle": "V(2,2) red-black GS", "parallelism": "single GPU",
                    "tiles": {str(k): list(v) for k, v in tiles.items()},
-                   "tiles_pro": {str(k): list(v) for k, v in tiles_pro.items()}},
+                   "tiles_pro": {str(k): list(v) for k, v in tiles_pro.items()},
+                   "options": dict(o.split("=") for o in args.opt)},
         "per_level": {str(level): {"samples_per_s": value, "fine_cycles_mean": cyc_mean,
                                    "effective_vcycle_GBps": eff,
                                    "batch_latency_ms": ms_step}},

@@ -121,8 +121,10 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
 
 /* Execution options (no effect on results beyond rounding order unless
  * stated):
- *   "smoother": 0 = fused single-pass red-black sweep (default),
- *               1 = two-pass in-place colour sweeps (same iterates);
+ *   "smoother": 0 = fused single-pass red-black sweep (default; grids
+ *               whose arrays reach 2 GiB, e.g. 1025^3 in FP64, use the
+ *               colour sweeps), 1 = two-pass in-place colour sweeps (same
+ *               iterates);
  *   "graph":    1 = capture the cycles of mlmc_sample_batch into HIP graphs
  *               (default), 0 = launch eagerly;
  *   "transfer": 0 = residual and full weighting in one pass where a launch
@@ -138,7 +140,7 @@ int mg_plan_set_option(mg_plan plan, const char* name, long long value);
 /* Tile shape of the fused smoother on grids of size n: tj rows (j) by tk
  * columns (k) per workgroup, the planes split into `chunks` pieces (0 = chosen
  * per launch from the number of grids: the march is split until the launch
- * has about 1024 workgroups, at least four planes per piece).  Only the
+ * has about 512 workgroups, at least four planes per piece).  Only the
  * compiled shapes whose tj, tk divide n-1 are accepted (MG_EINVAL otherwise).
  * A server captures the shapes in force at its first step. */
 int mg_set_tile(mg_plan plan, int n, int tj, int tk, int chunks);

@@ -182,6 +182,8 @@ struct mg_plan_s {
   int use_graph = 1;     // capture cycles into HIP graphs (mlmc_sample_batch)
   int small_ns = 17;     // grids of this size and below: the LDS V-cycle (0: off)
   int transfer = 0;      // 0: fused residual + restriction, 1: separate kernels
+  int norm_sweep = 1;    // 1: a cycle's first sweep also takes the residual norm of
+                         // the previous iterate (convergence judged one cycle late)
   std::map<int, SweepShape> shape;      // tile shape per grid size
   std::map<int, SweepShape> shape_pro;  // same, sweeps with the fused coarse correction
   // profiling of the finest-grid smoothing launches
@@ -288,6 +290,7 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
     int* ai = (int*)take(sizeof(int) * (ns * 4 + 2));
     double* dd = (double*)take(sizeof(double) * ns * 3);
     double* pp = (double*)take(sizeof(double) * npart);
+    double* sp = (double*)take(sizeof(double) * ns * 2 * kSweepParts);
     if (pass == 0) {
       if (size_only) {
         *size_only = total;
@@ -310,6 +313,7 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
       B->ss.bnorm = dd + ns;
       B->ss.q = dd + 2 * ns;
       B->ss.partials = pp;
+      B->ss.spart = sp;
     }
   }
   CK(hipHostMalloc((void**)&B->h_count, sizeof(int), hipHostMallocDefault));
@@ -348,6 +352,7 @@ static GridDescT<T> make_desc(const std::vector<LevelT<T>>& lv, size_t j, int so
   d.solve = solve;
   d.n = L.n;
   d.poff = poff;
+  d.spoff = j == 0 ? solve * 2 * kSweepParts : -1;
   return d;
 }
 
@@ -531,7 +536,7 @@ static void collect_profile(mg_plan_s* P) {
 // One red-black sweep on the grids of size index si; returns the new buffer.
 template <typename T>
 static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf, int cbuf,
-                       bool timed) {
+                       bool timed, T* spart = nullptr, int norm = 0) {
   const int n = B->sizes[si];
   const int cnt = (int)Ls.h[si].size();
   hipStream_t st = B->st;
@@ -540,8 +545,11 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
     CK(hipEventRecord(next_event(P), st));
   }
   int out = buf;
-  if (P->smoother == 0) {
-    launch_sweep<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, shape_for(P, n, cbuf >= 0), st);
+  if (P->smoother == 0 && sweep_fits(n, sizeof(T))) {
+    // (the sweep with the input's red residuals takes the register budget and
+    // shape of the sweep with the coarse correction)
+    launch_sweep<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf,
+                    shape_for(P, n, cbuf >= 0 || (spart && norm == 1)), st, spart, norm);
     out = 1 - buf;
   } else {
     if (cbuf >= 0) launch_prolong<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, st);
@@ -555,11 +563,39 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
   return out;
 }
 
+void launch_tick(int* ctr, hipStream_t st);
+
+// Partials per grid when the top grids of size index si take their
+// convergence norm from the sweeps (the black residuals from a cycle's last
+// sweep, the red ones from the next cycle's first sweep, which runs in the
+// shape of the sweep with the coarse correction: *red gets its count), else 0
+// (a reduction after the cycle).
+static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr) {
+  const int n = B->sizes[si];
+  if (B->spec.mixed || !P->norm_sweep || P->smoother != 0 || P->desc.nu1 < 1 ||
+      P->desc.nu2 < 2 || n < 5)
+    return 0;
+  if (B->L64.chain_si >= 0 && si >= (size_t)B->L64.chain_si) return 0;  // LDS V-cycle sizes
+  if (std::find(B->top_sizes.begin(), B->top_sizes.end(), n) == B->top_sizes.end()) return 0;
+  if (!sweep_fits(n, sizeof(double))) return 0;
+  const int cnt = (int)B->L64.h[si].size();
+  const int per = sweep_blocks(n, cnt, shape_for(P, n, false));
+  const int per_red = sweep_blocks(n, cnt, shape_for(P, n, true));
+  if (red) *red = per_red;
+  return per <= kSweepParts && per_red <= kSweepParts ? per : 0;
+}
+
 // One V(nu1,nu2) cycle on every active solve.  Each level starts in buffer 0
 // (the iterate of a top grid, the zero guess of a coarse one); returns the
-// buffer that holds the top grids' iterates afterwards.
+// buffer that holds the top grids' iterates afterwards.  With norms (the FP64
+// cycles), on a size whose top grids qualify (lagged_parts) the last sweep
+// sums the squared residuals at the black points of the iterate it makes, the
+// next cycle's first sweep those at the red points of the same iterate, and
+// the solves are judged right after that sweep (the iterate of the previous
+// cycle: lag 1).
 template <typename T>
-static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
+static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls, bool norms = false, double tol = 0.0,
+                     int fixed = 0) {
   const int nu1 = P->desc.nu1, nu2 = P->desc.nu2;
   const size_t L = B->sizes.size();
   hipStream_t st = B->st;
@@ -573,8 +609,19 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
       launch_coarsest<T>(Ls.d[si], cnt, B->ss.active, st);
       continue;
     }
-    for (int s = 0; s < nu1; ++s)
-      cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0);
+    int lpr = 0;
+    const int lp = norms ? lagged_parts(P, B, si, &lpr) : 0;
+    for (int s = 0; s < nu1; ++s) {
+      cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0,
+                               s == 0 && lp > 0 ? (T*)B->ss.spart + kSweepParts : nullptr, 1);
+      if (s == 0 && lp > 0) {
+        // judge the incoming iterates now: a solve that stops keeps it in
+        // buffer 0 (this sweep wrote buffer 1; nothing after it runs for it)
+        const size_t ti = size_index(B->top_sizes, n);
+        launch_finalize2(B->L64.dtop[ti], (int)B->L64.htop[ti].size(), B->ss, RED_RESID,
+                         B->d_cycle, 1, fixed, P->desc.max_cycles, tol, st, lp, lpr);
+      }
+    }
     // the one-pass transfer marches planes with a barrier each: with few
     // workgroups the separate kernels (same results) finish sooner
     if (P->transfer == 0 && cnt * resrestrict_blocks(n) >= 128) {
@@ -599,30 +646,28 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls) {
       launch_prolong<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], cbuf, st);
       continue;
     }
+    const int lp = norms ? lagged_parts(P, B, si) : 0;
     cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], cbuf, P->prof && si == 0);
     for (int s = 1; s < nu2; ++s)
-      cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0);
+      cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0,
+                               s == nu2 - 1 && lp > 0 ? (T*)B->ss.spart : nullptr, 2);
   }
   return cur[0];
 }
-
-void launch_tick(int* ctr, hipStream_t st);
-void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
-                      const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
-                      hipStream_t st);
 
 // One outer iteration for every active solve (recorded into graphs as is).
 static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed) {
   hipStream_t st = B->st;
   launch_tick(B->d_cycle, st);
   if (!B->spec.mixed) {
-    const int out = run_cycle<double>(P, B, B->L64);
+    const int out = run_cycle<double>(P, B, B->L64, true, tol, fixed);
     if (out != 0)  // odd sweep count: bring the top iterates back to buffer 0
       for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
         launch_copy_buf<double>(B->L64.dtop[ti], (int)B->L64.htop[ti].size(), B->top_sizes[ti],
                                 B->ss.active, 1, st);
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
       const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+      if (lagged_parts(P, B, size_index(B->sizes, n)) > 0) continue;  // judged in the sweep
       launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_RESID, B->ss.partials, st);
       launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, 0, fixed,
                        P->desc.max_cycles, tol, st);
@@ -668,8 +713,11 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
     launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, B->d_cycle, 0, fixed,
                      P->desc.max_cycles, tol, st);
   }
-  // mixed precision decides convergence one step late: one extra step
-  const int extra = B->spec.mixed ? 1 : 0;
+  // mixed precision, and top grids judged in the next cycle's first sweep,
+  // decide convergence one step late: one extra step
+  int extra = B->spec.mixed ? 1 : 0;
+  for (int n : B->top_sizes)
+    if (lagged_parts(P, B, size_index(B->sizes, n)) > 0) extra = 1;
   const int limit = (fixed > 0 ? fixed : P->desc.max_cycles) + extra;
   const bool use_graphs = graphs && P->use_graph && !P->prof;
   int done = 0, maxc = 0;
@@ -1241,6 +1289,9 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
   } else if (k == "transfer") {
     if (value != 0 && value != 1) return MG_EINVAL;
     P->transfer = (int)value;
+  } else if (k == "norm") {
+    if (value != 0 && value != 1) return MG_EINVAL;
+    P->norm_sweep = (int)value;
   } else if (k == "small_vcycle") {
     if (value != 0 && value != 5 && value != 9 && value != 17) return MG_EINVAL;
     P->small_ns = (int)value;
@@ -1387,6 +1438,7 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
   for (size_t si = 0; si < B->sizes.size(); ++si) {
     const int n = B->sizes[si];
     if (n < 5 || n <= P->small_ns) continue;  // small grids run in the LDS V-cycle
+    if (!sweep_fits(n, mixed ? sizeof(float) : sizeof(double))) continue;  // colour sweeps
     SweepShape shapes[32];
     const int c = sweep_shapes(n, shapes, 32);
     // the plain sweep and the one with the fused coarse correction are tuned

@@ -29,6 +29,8 @@ struct GridDescT {
   int solve;        // owning solve: index into per-solve arrays
   int n;            // vertices per axis
   int poff;         // offset of this grid's reduction partials (top grids only)
+  int spoff;        // top grids: offset of the in-sweep residual-norm partials
+                    // (spart[spoff + workgroup], 2 x kSweepParts); -1 otherwise
   int bstride;      // n*n for a full right-hand side array, 0 for a constant plane
 };
 using GridDesc = GridDescT<double>;
@@ -51,7 +53,14 @@ struct SolveState {
   double* partials; // reduction partials
   int* start;       // cycle counter value when the solve was started
   int* qpend;       // 1 from admission until the QoI of a stopped solve is taken
+  double* spart;    // 2 x kSweepParts in-sweep residual-norm partials per solve
+                    // (black points of the output of a cycle's last sweep, then
+                    // red points of the input of the next cycle's first sweep)
 };
+
+// Workgroups per grid that a sweep computing the residual norm may use (the
+// capacity of SolveState::spart per solve).
+constexpr int kSweepParts = 1024;
 
 // RED_QOI_PENDING: the QoI of solves that have stopped (active 0) but whose
 // QoI is still pending (qpend 1); it clears qpend.
@@ -77,6 +86,10 @@ int sweep_shapes(int n, SweepShape* out, int max_out);
 // fused_correction: the sweep that also adds the coarse correction;
 // single: FP32 sweeps (the inner cycles of mixed precision)
 SweepShape default_sweep_shape(int n, bool fused_correction = false, bool single = false);
+// Whether the fused smoother can run on grids of size n with elements of
+// elem bytes: it addresses a whole grid array with 32-bit byte offsets, so the
+// array must stay below 2 GiB (larger grids use the two-pass colour sweeps).
+bool sweep_fits(int n, size_t elem);
 
 // ---- launchers (all asynchronous on `st`) --------------------------------
 // Normals of `count` samples; the counter's level word is d_levels[s] when
@@ -102,10 +115,17 @@ void launch_fill(double* p, long count, double value, hipStream_t st);
 // Multigrid steps on a device list of `count` grids of size n.
 // The fused smoother: one red-black sweep from u[buf] into u[1-buf]; with
 // cbuf_prolong >= 0 the input is first corrected by the trilinear
-// interpolation of the coarse iterate uc[cbuf_prolong].
+// interpolation of the coarse iterate uc[cbuf_prolong].  With spart (FP64,
+// no correction) it also writes, for every grid with spoff >= 0, one partial
+// per workgroup to spart[spoff + wg]: the sum of squared residuals at the red
+// points of its input (norm 1) or at the black points of its output (norm 2).
+// Returns the workgroups per grid.
 template <typename T>
-void launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
-                  int cbuf_prolong, SweepShape shape, hipStream_t st);
+int launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
+                 int cbuf_prolong, SweepShape shape, hipStream_t st, T* spart = nullptr,
+                 int norm = 0);
+// Workgroups per grid of launch_sweep for `count` grids of size n.
+int sweep_blocks(int n, int count, SweepShape shape);
 template <typename T>
 void launch_rbgs_colour(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                         int colour, int buf, hipStream_t st);
@@ -152,11 +172,15 @@ void launch_defect(const GridDesc* d_list, const GridDesc32* d_list32, int count
 // Mixed precision: u[0] += (double) e32 on the top grids.
 void launch_correct(const GridDesc* d_list, const GridDesc32* d_list32, int count, int n,
                     const int* d_active, int buf32, hipStream_t st);
-// Finalise per solve.  The cycle judged is *cycle_ctr - start - lag;
-// fixed_cycles > 0 selects fixed-count mode.
+// Finalise per solve.  The cycle judged is *cycle_ctr - start - lag (an
+// iterate before the first cycle is never judged); fixed_cycles > 0 selects
+// fixed-count mode.  RED_RESID with sweep_parts > 0 sums the in-sweep
+// partials spart[spoff + q], q < sweep_parts, and then
+// spart[spoff + kSweepParts + q], q < sweep_parts_red, instead of the
+// reduction's.
 void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
                       const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
-                      hipStream_t st);
+                      hipStream_t st, int sweep_parts = 0, int sweep_parts_red = 0);
 // active = 1, cycles = 0, start = 0, qpend = 0, *cycle_ctr = 0;
 // launch_tick: *cycle_ctr += 1.
 void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st);

@@ -387,18 +387,35 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int n, const double* __restr
 // The loads of plane i+3 are issued at the end of plane i.  LDS holds, per
 // plane parity: u_in and wh of black positions (for red neighbours), the new
 // red values and the +j / +k faces (for black points), so each plane needs a
-// single barrier.
+// single barrier.  Position q of the tile is stored at LDS index
+// (q & 1) * PAIRS + (q >> 1): even and odd positions of a row lie apart, so the
+// lanes of a row touch consecutive words although each owns two positions
+// (indexing by q directly makes every access a two-way bank conflict).
 template <int TJ, int TK>
 struct SweepGeom {
   static constexpr int W2 = TK + 4, H2 = TJ + 4, A2 = W2 * H2;
   static constexpr int PAIRS = H2 * (W2 / 2);
   static constexpr int THREADS = ((PAIRS + 63) / 64) * 64;
+  // LDS index of tile position q (A2 is even: W2 is)
+  static __device__ __forceinline__ int lidx(int q) { return (q & 1) * PAIRS + (q >> 1); }
+  static constexpr int DJ = W2 / 2;  // LDS index step of one row
 };
 
-template <typename T, int TJ, int TK, bool PRO>
-__global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
-    k_sweep(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
-            int cbuf, int tiles_k, int tiles_jk, int chunk_len, int count, int per) {
+// NM: the sweep also sums squared residuals over its tile, for grids with
+// spoff >= 0, one partial per workgroup into spart[spoff + workgroup]:
+//   NM = 1: the red points of its input iterate: the red update forms their
+//           D and S from the input values already, only their own input
+//           values are loaded (one plane ahead; the lines are cached);
+//   NM = 2: the black points of its output iterate: a black update's D and S
+//           are those of the residual of the new black value.
+// Red points depend only on black values and vice versa, so the residual of
+// an iterate is the NM = 2 sums of the sweep that produced it plus the NM = 1
+// sums of the next sweep, both evaluated exactly as the residual kernels do.
+template <typename T, int TJ, int TK, bool PRO, int NM>
+__device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list,
+                                           const int* __restrict__ active, int buf, int cbuf,
+                                           int tiles_k, int tiles_jk, int chunk_len, int count,
+                                           int per, T* __restrict__ spart) {
   using Geo = SweepGeom<TJ, TK>;
   constexpr int W2 = Geo::W2, A2 = Geo::A2, HW = W2 / 2;
   __shared__ T sU[2][A2];   // u_in of black positions, plane parity
@@ -445,6 +462,20 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
   }
   const int jc = min(max(j, 0), n - 1);
   const int jI = min(max(j, 1), n - 2);
+  // LDS indexes, per role: own position (lq), and for the stencil reads of a
+  // ring-1 position (the others read around a safe interior position whose
+  // results are not used) the position itself (lc; its j-neighbours are
+  // lc -+ one row) and its k-neighbours (lm and lm + 1: q - 1 and q + 1 have the
+  // same parity and q >> 1 apart by one)
+  int lq[2], lc[2], lm[2], lp[2];
+#pragma unroll
+  for (int rho = 0; rho < 2; ++rho) {
+    const int qq = t1[rho] ? qr[rho] : W2 + 1;
+    lq[rho] = Geo::lidx(qr[rho]);
+    lc[rho] = Geo::lidx(qq);
+    lm[rho] = Geo::lidx(qq - 1);
+    lp[rho] = lm[rho] + 1;
+  }
 
   T UB[4], W[4][2], B[4][2], NR[4], FIP[4];
   // plane m = istart + rel: black role (rel + 1) & 1
@@ -456,22 +487,33 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
 #pragma unroll
   for (int rho = 0; rho < 2; ++rho) {
     offi[rho] = in[rho] ? (uint32_t)((jc * n + col[rho]) * sizeof(T)) : kOut;
-    offo[rho] = tl[rho] ? (uint32_t)((j * n + kc[rho]) * sizeof(T)) : kOut;
+    // outputs: the tile's interior points, and the boundary columns k = 0 and
+    // k = n-1 of its rows (rewritten with their value 0, so that no cache
+    // line of the output is left partly written: partial lines cost the
+    // memory system a read-modify-write)
+    const bool tb = t1[rho] && r >= 2 && r < TJ + 2 && intJ && (kc[rho] == 0 || kc[rho] == n - 1);
+    offo[rho] = (tl[rho] || tb) ? (uint32_t)((j * n + kc[rho]) * sizeof(T)) : kOut;
   }
+  const uint32_t gbytes = (uint32_t)n * pbytes;
+  const auto rw0 = rsrc(d.wh, gbytes), rb0 = rsrc(d.b, bs ? gbytes : pbytes);
+  const auto ru0 = rsrc(buf ? d.u[1] : d.u[0], gbytes);
+  const T* const uout = buf ? d.u[0] : d.u[1];
   auto load = [&](int rel, T& ub, T (&w)[2], T (&b)[2]) {
+    // planes past the grid are past the range and read 0
     const int m = istart + rel;
-    const bool ok = m >= 0 && m <= n - 1;  // uniform: a plane outside reads 0
-    const int mc = ok ? m : 0;
+    const uint32_t so = (uint32_t)m * pbytes, sob = bs ? so : 0u;
     const int rb = (rel + 1) & 1;
-    const auto rw = rsrc(d.wh + (size_t)mc * sn2, ok ? pbytes : 0u);
-    const auto rbb = rsrc(d.b + (size_t)mc * bs, pbytes);
-    const auto ru = rsrc((buf ? d.u[1] : d.u[0]) + (size_t)mc * sn2, ok ? pbytes : 0u);
 #pragma unroll
     for (int rho = 0; rho < 2; ++rho) {
-      w[rho] = bload<T>(rw, offi[rho]);
-      b[rho] = bload<T>(rbb, offi[rho]);
+      w[rho] = bload<T>(rw0, offi[rho] + so);
+      b[rho] = bload<T>(rb0, offi[rho] + sob);
     }
-    ub = bload<T>(ru, rb ? offi[1] : offi[0]);
+    ub = bload<T>(ru0, (rb ? offi[1] : offi[0]) + so);
+  };
+  // NM = 1: input value of the red role on plane istart + rel
+  T UR[2];
+  auto load_red = [&](int rel) {
+    UR[rel & 1] = bload<T>(ru0, (rel & 1 ? offi[1] : offi[0]) + (uint32_t)(istart + rel) * pbytes);
   };
 
   // Coarse correction (PRO): the coarse iterate's planes under the tile are
@@ -508,10 +550,12 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
 
   // prologue: planes istart-1 .. istart+2, the +i face of the red point below
   // plane istart (the black points of plane istart use it), plane istart to LDS
+  if (NM == 1) load_red(0);
   load(-1, UB[3], W[3], B[3]);
   load(0, UB[0], W[0], B[0]);
   load(1, UB[1], W[1], B[1]);
   load(2, UB[2], W[2], B[2]);
+  T acc = 0;  // NM: this thread's sum of squared residuals
   if (PRO) {
     const int clo = max((istart - 1) >> 1, 0), chi = ((istart + 2) >> 1) + 1;
     for (int C = clo; C <= chi; ++C) {
@@ -530,8 +574,8 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
   FIP[3] = rcp<T>(W[3][1] + W[0][1]);  // plane istart-1 is red in role 1
   FIP[2] = 0;
   if (live) {
-    sU[0][qr[1]] = UB[0];
-    sW[0][qr[1]] = W[0][1];
+    sU[0][lq[1]] = UB[0];
+    sW[0][lq[1]] = W[0][1];
   }
   __syncthreads();
 
@@ -541,9 +585,8 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     constexpr int RHO = K & 1;                 // red role on plane i
     constexpr int S0 = K, SM = (K + 3) & 3, SP = (K + 1) & 3, SM2 = (K + 2) & 3;
     constexpr int PB = K & 1, PBM = (K + 1) & 1;  // LDS buffers of planes i and i-1
-    // stencil reads only for ring-1 positions (the others read a safe
-    // interior position; their results are not used)
-    const int qq = t1[RHO] ? qr[RHO] : W2 + 1;
+    const int qc = lc[RHO], qm = lm[RHO], qp = lp[RHO];
+    constexpr int DJ = Geo::DJ;  // LDS index step of one row
     if (PRO) {
       UB[SP] += PA[SP];                                          // plane i+1 (black role RHO)
       PA[SM2] = pa_of(i + 2, kc[1 - RHO], intr[1 - RHO]);        // plane i+2
@@ -553,13 +596,17 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     const T* Wl = sW[PB];
     const T* Ul = sU[PB];
     const T fim = rcp<T>(wc + W[SM][RHO]), fip = rcp<T>(wc + W[SP][RHO]);
-    const T fjm = rcp<T>(wc + Wl[qq - W2]), fjp = rcp<T>(wc + Wl[qq + W2]);
-    const T fkm = rcp<T>(wc + Wl[qq - 1]), fkp = rcp<T>(wc + Wl[qq + 1]);
-    const St<T> sr = stencil_faces<T>(fim, fip, fjm, fjp, fkm, fkp, UB[SM], UB[SP], Ul[qq - W2],
-                                      Ul[qq + W2], Ul[qq - 1], Ul[qq + 1]);
+    const T fjm = rcp<T>(wc + Wl[qc - DJ]), fjp = rcp<T>(wc + Wl[qc + DJ]);
+    const T fkm = rcp<T>(wc + Wl[qm]), fkp = rcp<T>(wc + Wl[qp]);
+    const St<T> sr = stencil_faces<T>(fim, fip, fjm, fjp, fkm, fkp, UB[SM], UB[SP], Ul[qc - DJ],
+                                      Ul[qc + DJ], Ul[qm], Ul[qp]);
     const T vr = gs_value<T>(sr, B[S0][RHO]);
     NR[S0] = (t1[RHO] && intr[RHO] && i <= n - 2) ? vr : (T)0;
     FIP[S0] = fip;
+    if (NM == 1) {
+      const T rr = res_value<T>(sr, B[S0][RHO], UR[K & 1]);
+      acc += (tl[RHO] && i >= ia && i <= ib) ? rr * rr : (T)0;
+    }
     // black point of plane p = i - 1 (the column that is red on plane i)
     // (planes outside this chunk, including the ones the last unrolled step
     // may run past the end, are computed and their stores dropped: the
@@ -571,30 +618,37 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
       const T* Rl = sR[PBM];
       const T* Fj = sFj[PBM];
       const T* Fk = sFk[PBM];
-      const St<T> sb = stencil_faces<T>(FIP[SM2], fim, Fj[qq - W2], Fj[qq], Fk[qq - 1], Fk[qq],
-                                        NR[SM2], NR[S0], Rl[qq - W2], Rl[qq + W2], Rl[qq - 1],
-                                        Rl[qq + 1]);
+      const St<T> sb = stencil_faces<T>(FIP[SM2], fim, Fj[qc - DJ], Fj[qc], Fk[qm], Fk[qc],
+                                        NR[SM2], NR[S0], Rl[qc - DJ], Rl[qc + DJ], Rl[qm],
+                                        Rl[qp]);
       const T vb = gs_value<T>(sb, B[SM][RHO]);
-      const auto ro = rsrc((buf ? d.u[0] : d.u[1]) + (size_t)(outp ? p : 0) * sn2,
-                           outp ? pbytes : 0u);
-      bstore<T>(ro, offo[RHO], vb);
-      bstore<T>(ro, offo[1 - RHO], NR[SM]);
+      if (NM == 2) {
+        const T rb = res_value<T>(sb, B[SM][RHO], vb);
+        acc += (tl[RHO] && outp) ? rb * rb : (T)0;
+      }
+      const uint32_t sop = (uint32_t)p * pbytes;
+      const auto ro = rsrc(uout, outp ? gbytes : 0u);
+      bstore<T>(ro, offo[RHO] + sop, intr[RHO] ? vb : (T)0);
+      bstore<T>(ro, offo[1 - RHO] + sop, NR[SM]);
     }
     // publish plane i's red values and faces, and plane i+1's black u_in and
     // wh (the buffers read in this plane are the other parity)
     if (t1[RHO]) {
-      sR[PB][qq] = NR[S0];
-      sFj[PB][qq - W2] = fjm;
-      sFj[PB][qq] = fjp;
-      sFk[PB][qq - 1] = fkm;
-      sFk[PB][qq] = fkp;
+      sR[PB][qc] = NR[S0];
+      sFj[PB][qc - DJ] = fjm;
+      sFj[PB][qc] = fjp;
+      sFk[PB][qm] = fkm;
+      sFk[PB][qc] = fkp;
     }
     if (live) {
-      sU[PBM][qr[RHO]] = UB[SP];
-      sW[PBM][qr[RHO]] = W[SP][RHO];
+      sU[PBM][lq[RHO]] = UB[SP];
+      sW[PBM][lq[RHO]] = W[SP][RHO];
     }
     // loads of plane i+3 (into the ring slot plane i-1 leaves); the next
     // coarse plane to LDS every second plane
+    // (the next red input value first: waiting for it then leaves the
+    // plane loads in flight)
+    if (NM == 1) load_red(i - istart + 1);
     load(i - istart + 3, UB[SM], W[SM], B[SM]);
     if (PRO) {
       // coarse plane ((i+3)>>1)+1 to LDS (a second store of the same plane
@@ -613,6 +667,54 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     plane(std::integral_constant<int, 2>{}, i + 2);
     plane(std::integral_constant<int, 3>{}, i + 3);
   }
+  if (NM) {
+    // workgroup sum in a fixed order: within waves by shuffles, then the
+    // wave totals in wave order
+    constexpr int NW = Geo::THREADS / 64;
+    __shared__ T ws[NM ? NW : 1];
+    T v = acc;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((t & 63) == 0) ws[t >> 6] = v;
+    __syncthreads();
+    if (t == 0 && d.spoff >= 0) {
+      T sum = 0;
+      for (int w = 0; w < NW; ++w) sum += ws[w];
+      spart[d.spoff + blk] = sum;
+    }
+  }
+}
+
+template <typename T, int TJ, int TK, bool PRO>
+__global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
+    k_sweep(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
+            int cbuf, int tiles_k, int tiles_jk, int chunk_len, int count, int per) {
+  sweep_tile<T, TJ, TK, PRO, 0>(list, active, buf, cbuf, tiles_k, tiles_jk, chunk_len, count,
+                                per, nullptr);
+}
+
+// The sweep with the black residuals of its output, held to the plain
+// sweep's register budget (four waves per SIMD) so that it runs with the
+// plain sweep's shape and occupancy.
+template <typename T, int TJ, int TK>
+__global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(4)))
+    k_sweep_res_out(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
+                    int buf, int tiles_k, int tiles_jk, int chunk_len, int count, int per,
+                    T* __restrict__ spart) {
+  sweep_tile<T, TJ, TK, false, 2>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len, count,
+                                  per, spart);
+}
+
+// The sweep with the red residuals of its input: it keeps the input values of
+// the red role in registers as well, so it takes the register budget (and
+// the tile shapes) of the sweep with the coarse correction.
+template <typename T, int TJ, int TK>
+__global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
+    k_sweep_res_in(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
+                   int buf, int tiles_k, int tiles_jk, int chunk_len, int count, int per,
+                   T* __restrict__ spart) {
+  sweep_tile<T, TJ, TK, false, 1>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len, count,
+                                  per, spart);
 }
 
 // ---- point kernels: colour sweep, residual, transfer -------------------------
@@ -928,7 +1030,7 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
   const bool hgrid = halo && hj >= 0 && hj <= n - 1 && hk >= 0 && hk <= n - 1;
   const int hq = hr * W + hc;
   // this thread's coarse column
-  const bool cl = t < RJ * RK;
+  const bool cl = t < RJ * RK;  // coarse threads: the first waves
   const int cj = cl ? t / RK : 0, ck = cl ? t - (t / RK) * RK : 0;
   const int J = J0 + cj, K = K0 + ck;
   const bool cin = cl && J <= nc - 2 && K <= nc - 2;
@@ -937,7 +1039,12 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
   const uint32_t cbytes = (uint32_t)(nc * nc * sizeof(T));
   const uint32_t oo = fgrid ? (uint32_t)((j * n + k) * sizeof(T)) : kOut;
   const uint32_t oh = hgrid ? (uint32_t)((hj * n + hk) * sizeof(T)) : kOut;
-  const uint32_t oco = cin ? (uint32_t)((J * nc + K) * sizeof(T)) : kOut;
+  // coarse outputs: interior points, and the boundary columns K = 0 (a second
+  // store by the threads of column K0 = 1) and K = nc-1 of interior rows,
+  // rewritten with 0 so that no cache line is left partly written
+  const bool cbr = cl && J <= nc - 2 && K == nc - 1;
+  const uint32_t oco = (cin || cbr) ? (uint32_t)((J * nc + K) * sizeof(T)) : kOut;
+  const uint32_t oc0 = (cl && K == 1 && J <= nc - 2) ? (uint32_t)(J * nc * sizeof(T)) : kOut;
   const T* u_ = buf ? d.u[1] : d.u[0];
   auto plane = [&](const T* base, int pm, bool ok) {
     return rsrc(base + (size_t)(ok ? pm : 0) * sn2, ok ? pbytes : 0u);
@@ -953,22 +1060,24 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
     HU[sl] = bload<T>(ru, oh);
     HW[sl] = bload<T>(rw, oh);
   };
-  load(0, 3);
-  load(1, 0);
-  load(2, 1);
-  load(3, 2);
-  if (fl) {
-    LU[1][q] = OU[0];
-    LW[1][q] = OW[0];
-  }
-  if (halo) {
-    LU[1][hq] = HU[0];
-    LW[1][hq] = HW[0];
-  }
-  __syncthreads();
-  T fim = rcp<T>(OW[0] + OW[3]);
+  auto prologue = [&]() {
+    load(0, 3);
+    load(1, 0);
+    load(2, 1);
+    load(3, 2);
+    if (fl) {
+      LU[1][q] = OU[0];
+      LW[1][q] = OW[0];
+    }
+    if (halo) {
+      LU[1][hq] = HU[0];
+      LW[1][hq] = HW[0];
+    }
+  };
+  T fim = 0;
   T s = 0;
-  auto step = [&](auto kk, int i) {
+  // the residual of plane i into R (fine threads), the next plane to LDS
+  auto fine = [&](auto kk, int i) {
     constexpr int KS = decltype(kk)::value;
     constexpr int S0 = KS, SM = (KS + 3) & 3, SP = (KS + 1) & 3;
     constexpr int PB = (KS + 1) & 1, PN = KS & 1;  // buffers of planes i and i+1
@@ -992,10 +1101,13 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
       LW[PN][hq] = HW[SP];
     }
     load(i + 3, SM);
-    __syncthreads();
-    // this plane's share of the 27-point weights (coarse threads: the first
-    // two waves), in increasing plane order; an odd plane closes coarse plane
-    // (i-1)/2 (stored if interior) and opens (i+1)/2
+  };
+  // plane i's share of the 27-point weights (coarse threads), in increasing
+  // plane order; an odd plane closes coarse plane (i-1)/2 (stored if
+  // interior) and opens (i+1)/2
+  auto coarse = [&](auto kk, int i) {
+    constexpr int KS = decltype(kk)::value;
+    constexpr int PB = (KS + 1) & 1;
     if (cl) {
       const T* Rp = R[PB];
       const bool odd = (i & 1) != 0;
@@ -1013,10 +1125,12 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
       s1 += tm[2];
       const int I = (i - 1) >> 1;
       const bool st_ok = odd && I >= 1 && I <= nc - 2;
-      bstore<T>(rsrc(d.bc + (size_t)(st_ok ? I : 0) * nc * nc, st_ok ? cbytes : 0u), oco,
-                (T)0.5 * s1);
-      bstore<T>(rsrc(d.uc[0] + (size_t)(st_ok ? I : 0) * nc * nc, st_ok ? cbytes : 0u), oco,
-                (T)0);
+      const auto rbc = rsrc(d.bc + (size_t)(st_ok ? I : 0) * nc * nc, st_ok ? cbytes : 0u);
+      const auto ruc = rsrc(d.uc[0] + (size_t)(st_ok ? I : 0) * nc * nc, st_ok ? cbytes : 0u);
+      bstore<T>(rbc, oco, cin ? (T)0.5 * s1 : (T)0);
+      bstore<T>(ruc, oco, (T)0);
+      bstore<T>(rbc, oc0, (T)0);
+      bstore<T>(ruc, oc0, (T)0);
       T s0 = 0;
       s0 += tm[0];
       s0 += tm[1];
@@ -1024,11 +1138,26 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
       s = odd ? s0 : s1;
     }
   };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  prologue();
+  fim = rcp<T>(OW[0] + OW[3]);
+  __syncthreads();
   for (int i = 1; i <= n - 2; i += 4) {
-    step(std::integral_constant<int, 0>{}, i);
-    step(std::integral_constant<int, 1>{}, i + 1);
-    step(std::integral_constant<int, 2>{}, i + 2);
-    step(std::integral_constant<int, 3>{}, i + 3);
+    fine(I0{}, i);
+    __syncthreads();
+    coarse(I0{}, i);
+    fine(I1{}, i + 1);
+    __syncthreads();
+    coarse(I1{}, i + 1);
+    fine(I2{}, i + 2);
+    __syncthreads();
+    coarse(I2{}, i + 2);
+    fine(I3{}, i + 3);
+    __syncthreads();
+    coarse(I3{}, i + 3);
   }
 }
 
@@ -1335,14 +1464,19 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
                                                      SolveState s, int mode,
                                                      const int* __restrict__ cycle_ctr, int lag,
                                                      int fixed_cycles, int max_cycles,
-                                                     double tol) {
+                                                     double tol, int sweep_parts,
+                                                     int sweep_parts_red) {
   const GridDesc d = list[blockIdx.x];
   const int sv = d.solve;
   if (mode == RED_RESID && !s.active[sv]) return;
   if (mode == RED_QOI_PENDING && (!s.qpend[sv] || s.active[sv])) return;
-  const int P = reduce_blocks(d.n);
+  const bool sw = mode == RED_RESID && sweep_parts > 0;
+  const int P = sw ? sweep_parts : reduce_blocks(d.n);
+  const double* src = sw ? s.spart + d.spoff : s.partials + d.poff;
   double v = 0.0;
-  for (int q = threadIdx.x; q < P; q += kBlock) v += s.partials[d.poff + q];
+  for (int q = threadIdx.x; q < P; q += kBlock) v += src[q];
+  if (sw)
+    for (int q = threadIdx.x; q < sweep_parts_red; q += kBlock) v += src[kSweepParts + q];
   v = block_sum(v);
   if (threadIdx.x != 0) return;
   if (mode == RED_BNORM) {
@@ -1352,6 +1486,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
     const int cycle = *cycle_ctr - s.start[sv] - lag;
     const double rho = sqrt(v) / s.bnorm[sv];
     s.relres[sv] = rho;
+    if (cycle < 1) return;  // the initial iterate: convergence is judged after cycles
     if (fixed_cycles > 0) {
       if (cycle >= fixed_cycles) {
         s.active[sv] = 0;
@@ -1429,21 +1564,30 @@ __global__ void k_fill(double* __restrict__ p, long count, double value) {
 inline dim3 xcd_grid(int count, int per) { return dim3(8 * ceil_div(count * per, 8)); }
 
 template <typename T, int TJ, int TK>
-void sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
-                  int cbuf, int chunks, hipStream_t st) {
+int sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
+                 int cbuf, int chunks, hipStream_t st, T* spart, int norm) {
   const int tiles_k = (n - 1) / TK, tiles_j = (n - 1) / TJ;
   const int tiles = tiles_k * tiles_j;
   const int chunk_len = ceil_div(n - 2, chunks);
   const int nch = ceil_div(n - 2, chunk_len);
   const int per = tiles * nch;
-  if (cbuf >= 0)
-    hipLaunchKernelGGL((k_sweep<T, TJ, TK, true>), xcd_grid(count, per),
-                       dim3(SweepGeom<TJ, TK>::THREADS), 0, st, d_list, d_active, buf, cbuf, tiles_k,
-                       tiles, chunk_len, count, per);
-  else
-    hipLaunchKernelGGL((k_sweep<T, TJ, TK, false>), xcd_grid(count, per),
-                       dim3(SweepGeom<TJ, TK>::THREADS), 0, st, d_list, d_active, buf, cbuf, tiles_k,
-                       tiles, chunk_len, count, per);
+  const dim3 grid = xcd_grid(count, per), block(SweepGeom<TJ, TK>::THREADS);
+  if (cbuf >= 0) {
+    hipLaunchKernelGGL((k_sweep<T, TJ, TK, true>), grid, block, 0, st, d_list, d_active, buf, cbuf,
+                       tiles_k, tiles, chunk_len, count, per);
+  } else if (spart && norm == 1) {
+    if constexpr (std::is_same<T, double>::value)
+      hipLaunchKernelGGL((k_sweep_res_in<T, TJ, TK>), grid, block, 0, st, d_list, d_active, buf,
+                         tiles_k, tiles, chunk_len, count, per, spart);
+  } else if (spart && norm == 2) {
+    if constexpr (std::is_same<T, double>::value)
+      hipLaunchKernelGGL((k_sweep_res_out<T, TJ, TK>), grid, block, 0, st, d_list, d_active, buf,
+                         tiles_k, tiles, chunk_len, count, per, spart);
+  } else {
+    hipLaunchKernelGGL((k_sweep<T, TJ, TK, false>), grid, block, 0, st, d_list, d_active, buf,
+                       cbuf, tiles_k, tiles, chunk_len, count, per);
+  }
+  return per;
 }
 
 }  // namespace
@@ -1462,19 +1606,28 @@ int sweep_shapes(int n, SweepShape* out, int max_out) {
   return c;
 }
 
+bool sweep_fits(int n, size_t elem) {
+  // offsets up to kOut + (n + 6) planes must not wrap, and the array must end
+  // below kOut so that kOut-based offsets stay out of range
+  const uint64_t g = (uint64_t)n * n * n * elem, plane = (uint64_t)n * n * elem;
+  return g < kOut && (uint64_t)kOut + (uint64_t)(n + 6) * plane < (1ull << 32);
+}
+
 SweepShape default_sweep_shape(int n, bool fused_correction, bool single) {
   // measured best on MI355X: 65^3 and 33^3 for a batch of 64 MLMC level pairs
   // (64 grids of 65^3, 128 of 33^3); 257^3 and 129^3 for batches of 16 and 48
   // grids; FP32 (the inner cycles of mixed precision) for 16 grids of 257^3
+  // (the plane split is automatic where one piece per tile measured best
+  // for those batches, so that small launches still get split)
   if (single) {
     if (n >= 257) return fused_correction ? SweepShape{8, 64, 0} : SweepShape{8, 64, 4};
-    if (n == 129) return {8, 64, 1};
-    if (n == 65) return {16, 32, 4};
+    if (n == 129) return {8, 64, 0};
+    if (n == 65) return {16, 32, 0};
     if (n == 33) return fused_correction ? SweepShape{16, 32, 0} : SweepShape{16, 16, 0};
   } else {
-    if (n >= 129) return {16, 32, 1};
-    if (n == 65) return fused_correction ? SweepShape{16, 32, 1} : SweepShape{8, 64, 1};
-    if (n == 33) return fused_correction ? SweepShape{8, 16, 1} : SweepShape{16, 16, 1};
+    if (n >= 129) return {16, 32, 0};
+    if (n == 65) return fused_correction ? SweepShape{16, 32, 0} : SweepShape{8, 64, 0};
+    if (n == 33) return fused_correction ? SweepShape{8, 16, 0} : SweepShape{16, 16, 0};
   }
   if (n - 1 >= 16) return {8, 16, 0};
   if (n - 1 >= 8) return {8, 8, 0};
@@ -1525,23 +1678,29 @@ void launch_prepare_problem(int n, const double* k, const double* f, double* wh,
   hipLaunchKernelGGL(k_prepare, dim3(point_blocks(n)), dim3(kBlock), 0, st, n, k, f, wh, b, u);
 }
 
+// Plane pieces of a sweep launch: the shape's, or automatic: split the plane
+// march until the launch has about 512 workgroups (two per CU; small batches
+// and small grids are latency-bound by the sequential march), keeping at
+// least four planes per piece.
+static int sweep_chunks(int n, int count, SweepShape s) {
+  if (s.chunks >= 1) return s.chunks;
+  const int tiles = ((n - 1) / s.tj) * ((n - 1) / s.tk);
+  return std::max(1, std::min(ceil_div(512, std::max(1, count * tiles)), (n - 2) / 4));
+}
+
+int sweep_blocks(int n, int count, SweepShape s) {
+  const int chunk_len = ceil_div(n - 2, sweep_chunks(n, count, s));
+  return ((n - 1) / s.tj) * ((n - 1) / s.tk) * ceil_div(n - 2, chunk_len);
+}
+
 template <typename T>
-void launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
-                  int cbuf, SweepShape s, hipStream_t st) {
-  if (count <= 0) return;
-  int c = s.chunks;
-  if (c < 1) {
-    // automatic: split the plane march until the launch has about 1024
-    // workgroups (small batches and small grids are latency-bound by the
-    // sequential march), keeping at least four planes per piece
-    const int tiles = ((n - 1) / s.tj) * ((n - 1) / s.tk);
-    c = std::max(1, std::min(ceil_div(1024, std::max(1, count * tiles)), (n - 2) / 4));
-  }
-#define MG_SWEEP_CASE(TJ_, TK_)                                                     \
-  if (s.tj == TJ_ && s.tk == TK_) {                                                 \
-    sweep_launch<T, TJ_, TK_>(d_list, count, n, d_active, buf, cbuf, c, st);        \
-    return;                                                                         \
-  }
+int launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
+                 int cbuf, SweepShape s, hipStream_t st, T* spart, int norm) {
+  if (count <= 0) return 0;
+  const int c = sweep_chunks(n, count, s);
+#define MG_SWEEP_CASE(TJ_, TK_)                                                       \
+  if (s.tj == TJ_ && s.tk == TK_)                                                     \
+    return sweep_launch<T, TJ_, TK_>(d_list, count, n, d_active, buf, cbuf, c, st, spart, norm);
   MG_SWEEP_CASE(8, 64)
   MG_SWEEP_CASE(4, 64)
   MG_SWEEP_CASE(16, 32)
@@ -1555,6 +1714,7 @@ void launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_act
   MG_SWEEP_CASE(4, 4)
   MG_SWEEP_CASE(2, 2)
 #undef MG_SWEEP_CASE
+  return 0;
 }
 
 template <typename T>
@@ -1575,9 +1735,11 @@ void launch_residual(const GridDescT<T>* d_list, int count, int n, const int* d_
                      buf, count, per);
 }
 
+// coarse tile shapes of the one-pass transfer (grids from 65^3 up, smaller)
+constexpr int kRRJ1 = 4, kRRK1 = 32, kRRJ2 = 8, kRRK2 = 16;
 int resrestrict_blocks(int n) {
   const int m = (n - 1) / 2 - 1;
-  return n >= 65 ? ceil_div(m, 4) * ceil_div(m, 32) : ceil_div(m, 8) * ceil_div(m, 16);
+  return n >= 65 ? ceil_div(m, kRRJ1) * ceil_div(m, kRRK1) : ceil_div(m, kRRJ2) * ceil_div(m, kRRK2);
 }
 
 template <typename T>
@@ -1586,13 +1748,15 @@ void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int*
   if (count <= 0) return;
   const int m = (n - 1) / 2 - 1;  // coarse interior points per axis
   if (n >= 65) {
-    const int tk = ceil_div(m, 32), per = ceil_div(m, 4) * tk;
-    hipLaunchKernelGGL((k_resrestrict<T, 4, 32>), xcd_grid(count, per),
-                       dim3(RRGeom<4, 32>::THREADS), 0, st, d_list, d_active, buf, tk, count, per);
+    const int tk = ceil_div(m, kRRK1), per = ceil_div(m, kRRJ1) * tk;
+    hipLaunchKernelGGL((k_resrestrict<T, kRRJ1, kRRK1>), xcd_grid(count, per),
+                       dim3(RRGeom<kRRJ1, kRRK1>::THREADS), 0, st, d_list, d_active, buf, tk, count,
+                       per);
   } else {
-    const int tk = ceil_div(m, 16), per = ceil_div(m, 8) * tk;
-    hipLaunchKernelGGL((k_resrestrict<T, 8, 16>), xcd_grid(count, per),
-                       dim3(RRGeom<8, 16>::THREADS), 0, st, d_list, d_active, buf, tk, count, per);
+    const int tk = ceil_div(m, kRRK2), per = ceil_div(m, kRRJ2) * tk;
+    hipLaunchKernelGGL((k_resrestrict<T, kRRJ2, kRRK2>), xcd_grid(count, per),
+                       dim3(RRGeom<kRRJ2, kRRK2>::THREADS), 0, st, d_list, d_active, buf, tk, count,
+                       per);
   }
 }
 
@@ -1638,8 +1802,8 @@ void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_
 }
 
 #define MG_INSTANTIATE(T)                                                                       \
-  template void launch_sweep<T>(const GridDescT<T>*, int, int, const int*, int, int, SweepShape, \
-                                hipStream_t);                                                   \
+  template int launch_sweep<T>(const GridDescT<T>*, int, int, const int*, int, int, SweepShape,  \
+                               hipStream_t, T*, int);                                           \
   template void launch_rbgs_colour<T>(const GridDescT<T>*, int, int, const int*, int, int,      \
                                       hipStream_t);                                             \
   template void launch_residual<T>(const GridDescT<T>*, int, int, const int*, int, hipStream_t); \
@@ -1699,10 +1863,10 @@ void launch_correct(const GridDesc* d_list, const GridDesc32* d_list32, int coun
 
 void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
                       const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
-                      hipStream_t st) {
+                      hipStream_t st, int sweep_parts, int sweep_parts_red) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_finalize, dim3(count), dim3(kBlock), 0, st, d_list, s, mode, cycle_ctr, lag,
-                     fixed_cycles, max_cycles, tol);
+                     fixed_cycles, max_cycles, tol, sweep_parts, sweep_parts_red);
 }
 
 void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st) {

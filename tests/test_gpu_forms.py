@@ -93,6 +93,46 @@ def test_fused_transfer_matches_separate_kernels(M, torch, n0, level, prec):
     assert _same(out[0], out[1])
 
 
+@pytest.mark.parametrize("n0,level,fixed", [(33, 1, 0), (17, 2, 0), (33, 0, 0), (33, 1, 3)])
+def test_norm_in_sweeps_matches_separate_reduction(M, torch, n0, level, fixed):
+    # the convergence norm summed inside the sweeps (black points in a cycle's
+    # last sweep, red points in the next cycle's first, judged one cycle late)
+    # against the residual reduction after each cycle: the same per-point
+    # residuals, so the same stopping cycle and bit-identical results
+    seeds = [41, 42, 43, 44]
+    out = {}
+    for nm in (0, 1):
+        P = M.mg_plan_create(n0=n0, max_level=level)
+        M.mg_plan_set_option(P, "norm", nm)
+        out[nm] = _batch(M, torch, P, level, seeds, fixed=fixed)
+        assert out[nm][0] == M.MG_OK
+    assert _same(out[0], out[1])
+
+
+def test_norm_in_sweeps_single_solve_relres(M, torch):
+    # mg_solve: same cycles and iterate; the relative residual differs only by
+    # the summation order of the squared residuals
+    n = 65
+    k = O.field(n, 2.0, 0.05, O.gaussians(12, 0))
+    f = np.ones_like(k)
+    res = {}
+    for nm in (0, 1):
+        P = M.mg_plan_create()
+        M.mg_plan_set_option(P, "norm", nm)
+        res[nm] = _solve(M, torch, P, k, f)
+        assert res[nm][0] == M.MG_OK
+    assert res[0][1] == res[1][1]
+    assert np.array_equal(res[0][3], res[1][3])
+    assert abs(res[0][2] - res[1][2]) <= 1e-12 * res[0][2]
+    # against the oracle's residual of the same iterate: near tol the residual
+    # is a difference of terms ~||b||, each point's rounding ~1e-16 ||b||, so
+    # its relative accuracy is ~1e-16 / rho ~ 1e-8 for rho ~ 1e-8
+    h = 1.0 / (n - 1)
+    b = h * h * f
+    ro = O.norm2(O.residual(k, b, res[1][3])) / O.norm2(b)
+    assert abs(res[1][2] - ro) <= 1e-6 * ro
+
+
 def test_small_vcycle_single_solve(M, torch):
     # a whole 17^3 solve in the LDS kernel (mg_solve), against per-level launches
     n = 17
