@@ -73,6 +73,12 @@ struct BatchSpec {
 template <typename T>
 struct Lists {
   std::vector<std::vector<GridDescT<T>>> h;  // per size index
+  // whether every grid of h[si] has a constant right-hand side plane
+  bool const_b(size_t si) const {
+    for (const auto& g : h[si])
+      if (g.bstride != 0) return false;
+    return !h[si].empty();
+  }
   std::vector<GridDescT<T>*> d;
   std::vector<std::vector<GridDescT<T>>> htop;  // per top size index
   std::vector<GridDescT<T>*> dtop;
@@ -546,10 +552,13 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
   }
   int out = buf;
   if (P->smoother == 0 && sweep_fits(n, sizeof(T))) {
-    // (the sweep with the input's red residuals takes the register budget and
-    // shape of the sweep with the coarse correction)
+    // (with a full right-hand side, the sweep with the input's red residuals
+    // takes the register budget and shape of the sweep with the coarse
+    // correction)
+    const bool cb = Ls.const_b(si);
     launch_sweep<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf,
-                    shape_for(P, n, cbuf >= 0 || (spart && norm == 1)), st, spart, norm);
+                    shape_for(P, n, cbuf >= 0 || (spart && norm == 1 && !cb)), st, spart, norm,
+                    cb);
     out = 1 - buf;
   } else {
     if (cbuf >= 0) launch_prolong<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, st);
@@ -568,8 +577,8 @@ void launch_tick(int* ctr, hipStream_t st);
 // Partials per grid when the top grids of size index si take their
 // convergence norm from the sweeps (the black residuals from a cycle's last
 // sweep, the red ones from the next cycle's first sweep, which runs in the
-// shape of the sweep with the coarse correction: *red gets its count), else 0
-// (a reduction after the cycle).
+// shape of the sweep with the coarse correction unless the right-hand side is
+// constant: *red gets its count), else 0 (a reduction after the cycle).
 static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr) {
   const int n = B->sizes[si];
   if (B->spec.mixed || !P->norm_sweep || P->smoother != 0 || P->desc.nu1 < 1 ||
@@ -580,7 +589,7 @@ static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr) {
   if (!sweep_fits(n, sizeof(double))) return 0;
   const int cnt = (int)B->L64.h[si].size();
   const int per = sweep_blocks(n, cnt, shape_for(P, n, false));
-  const int per_red = sweep_blocks(n, cnt, shape_for(P, n, true));
+  const int per_red = sweep_blocks(n, cnt, shape_for(P, n, !B->L64.const_b(si)));
   if (red) *red = per_red;
   return per <= kSweepParts && per_red <= kSweepParts ? per : 0;
 }
@@ -1458,10 +1467,10 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
           auto one = [&]() {
             if (mixed)
               launch_sweep<float>(B->L32.d[si], (int)B->L32.h[si].size(), n, B->ss.active, 0, cb,
-                                  s, P->work);
+                                  s, P->work, nullptr, 0, B->L32.const_b(si));
             else
               launch_sweep<double>(B->L64.d[si], (int)B->L64.h[si].size(), n, B->ss.active, 0,
-                                   cb, s, P->work);
+                                   cb, s, P->work, nullptr, 0, B->L64.const_b(si));
           };
           one();
           CK(hipEventRecord(e0, P->work));

@@ -119,11 +119,12 @@ void launch_fill(double* p, long count, double value, hipStream_t st);
 // no correction) it also writes, for every grid with spoff >= 0, one partial
 // per workgroup to spart[spoff + wg]: the sum of squared residuals at the red
 // points of its input (norm 1) or at the black points of its output (norm 2).
-// Returns the workgroups per grid.
+// const_b: every grid of the list has a constant right-hand side plane
+// (bstride 0).  Returns the workgroups per grid.
 template <typename T>
 int launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                  int cbuf_prolong, SweepShape shape, hipStream_t st, T* spart = nullptr,
-                 int norm = 0);
+                 int norm = 0, bool const_b = false);
 // Workgroups per grid of launch_sweep for `count` grids of size n.
 int sweep_blocks(int n, int count, SweepShape shape);
 template <typename T>

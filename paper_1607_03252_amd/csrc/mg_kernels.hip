@@ -411,7 +411,9 @@ struct SweepGeom {
 // Red points depend only on black values and vice versa, so the residual of
 // an iterate is the NM = 2 sums of the sweep that produced it plus the NM = 1
 // sums of the next sweep, both evaluated exactly as the residual kernels do.
-template <typename T, int TJ, int TK, bool PRO, int NM>
+// CB: every grid of the launch has a constant right-hand side (bstride 0):
+// its two values per thread are loaded once instead of per plane.
+template <typename T, int TJ, int TK, bool PRO, int NM, bool CB>
 __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list,
                                            const int* __restrict__ active, int buf, int cbuf,
                                            int tiles_k, int tiles_jk, int chunk_len, int count,
@@ -477,7 +479,9 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     lp[rho] = lm[rho] + 1;
   }
 
-  T UB[4], W[4][2], B[4][2], NR[4], FIP[4];
+  T UB[4], W[4][2], B[CB ? 1 : 4][2], NR[4], FIP[4];
+  // right-hand side at this thread's positions on the plane in ring slot sl
+  auto bv = [&](int sl, int rho) -> T { return CB ? B[0][rho] : B[CB ? 0 : sl][rho]; };
   // plane m = istart + rel: black role (rel + 1) & 1
   // byte offsets within a plane of this thread's two columns (past the plane
   // for positions outside the grid, which then read 0), and of its outputs
@@ -506,7 +510,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
 #pragma unroll
     for (int rho = 0; rho < 2; ++rho) {
       w[rho] = bload<T>(rw0, offi[rho] + so);
-      b[rho] = bload<T>(rb0, offi[rho] + sob);
+      if (!CB) b[rho] = bload<T>(rb0, offi[rho] + sob);
     }
     ub = bload<T>(ru0, (rb ? offi[1] : offi[0]) + so);
   };
@@ -551,10 +555,14 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   // prologue: planes istart-1 .. istart+2, the +i face of the red point below
   // plane istart (the black points of plane istart use it), plane istart to LDS
   if (NM == 1) load_red(0);
-  load(-1, UB[3], W[3], B[3]);
+  if (CB) {
+    B[0][0] = bload<T>(rb0, offi[0]);
+    B[0][1] = bload<T>(rb0, offi[1]);
+  }
+  load(-1, UB[3], W[3], B[CB ? 0 : 3]);
   load(0, UB[0], W[0], B[0]);
-  load(1, UB[1], W[1], B[1]);
-  load(2, UB[2], W[2], B[2]);
+  load(1, UB[1], W[1], B[CB ? 0 : 1]);
+  load(2, UB[2], W[2], B[CB ? 0 : 2]);
   T acc = 0;  // NM: this thread's sum of squared residuals
   if (PRO) {
     const int clo = max((istart - 1) >> 1, 0), chi = ((istart + 2) >> 1) + 1;
@@ -600,11 +608,11 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     const T fkm = rcp<T>(wc + Wl[qm]), fkp = rcp<T>(wc + Wl[qp]);
     const St<T> sr = stencil_faces<T>(fim, fip, fjm, fjp, fkm, fkp, UB[SM], UB[SP], Ul[qc - DJ],
                                       Ul[qc + DJ], Ul[qm], Ul[qp]);
-    const T vr = gs_value<T>(sr, B[S0][RHO]);
+    const T vr = gs_value<T>(sr, bv(S0, RHO));
     NR[S0] = (t1[RHO] && intr[RHO] && i <= n - 2) ? vr : (T)0;
     FIP[S0] = fip;
     if (NM == 1) {
-      const T rr = res_value<T>(sr, B[S0][RHO], UR[K & 1]);
+      const T rr = res_value<T>(sr, bv(S0, RHO), UR[K & 1]);
       acc += (tl[RHO] && i >= ia && i <= ib) ? rr * rr : (T)0;
     }
     // black point of plane p = i - 1 (the column that is red on plane i)
@@ -621,9 +629,9 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
       const St<T> sb = stencil_faces<T>(FIP[SM2], fim, Fj[qc - DJ], Fj[qc], Fk[qm], Fk[qc],
                                         NR[SM2], NR[S0], Rl[qc - DJ], Rl[qc + DJ], Rl[qm],
                                         Rl[qp]);
-      const T vb = gs_value<T>(sb, B[SM][RHO]);
+      const T vb = gs_value<T>(sb, bv(SM, RHO));
       if (NM == 2) {
-        const T rb = res_value<T>(sb, B[SM][RHO], vb);
+        const T rb = res_value<T>(sb, bv(SM, RHO), vb);
         acc += (tl[RHO] && outp) ? rb * rb : (T)0;
       }
       const uint32_t sop = (uint32_t)p * pbytes;
@@ -649,7 +657,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     // (the next red input value first: waiting for it then leaves the
     // plane loads in flight)
     if (NM == 1) load_red(i - istart + 1);
-    load(i - istart + 3, UB[SM], W[SM], B[SM]);
+    load(i - istart + 3, UB[SM], W[SM], B[CB ? 0 : SM]);
     if (PRO) {
       // coarse plane ((i+3)>>1)+1 to LDS (a second store of the same plane
       // rewrites identical values), the next one into the staging register
@@ -684,37 +692,48 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   }
 }
 
-template <typename T, int TJ, int TK, bool PRO>
+template <typename T, int TJ, int TK, bool PRO, bool CB>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     k_sweep(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
             int cbuf, int tiles_k, int tiles_jk, int chunk_len, int count, int per) {
-  sweep_tile<T, TJ, TK, PRO, 0>(list, active, buf, cbuf, tiles_k, tiles_jk, chunk_len, count,
-                                per, nullptr);
+  sweep_tile<T, TJ, TK, PRO, 0, CB>(list, active, buf, cbuf, tiles_k, tiles_jk, chunk_len, count,
+                                    per, nullptr);
 }
 
 // The sweep with the black residuals of its output, held to the plain
 // sweep's register budget (four waves per SIMD) so that it runs with the
 // plain sweep's shape and occupancy.
-template <typename T, int TJ, int TK>
+template <typename T, int TJ, int TK, bool CB>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     __attribute__((amdgpu_waves_per_eu(4)))
     k_sweep_res_out(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
                     int buf, int tiles_k, int tiles_jk, int chunk_len, int count, int per,
                     T* __restrict__ spart) {
-  sweep_tile<T, TJ, TK, false, 2>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len, count,
-                                  per, spart);
+  sweep_tile<T, TJ, TK, false, 2, CB>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len, count,
+                                      per, spart);
 }
 
-// The sweep with the red residuals of its input: it keeps the input values of
-// the red role in registers as well, so it takes the register budget (and
-// the tile shapes) of the sweep with the coarse correction.
+// The sweep with the red residuals of its input keeps the input values of
+// the red role in registers as well.  With a constant right-hand side (no
+// right-hand-side ring) it fits the plain sweep's budget and shapes; with a
+// full one it takes the budget and shapes of the sweep with the coarse
+// correction.
+template <typename T, int TJ, int TK>
+__global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(4)))
+    k_sweep_res_in_cb(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
+                      int buf, int tiles_k, int tiles_jk, int chunk_len, int count, int per,
+                      T* __restrict__ spart) {
+  sweep_tile<T, TJ, TK, false, 1, true>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len,
+                                        count, per, spart);
+}
 template <typename T, int TJ, int TK>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     k_sweep_res_in(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
                    int buf, int tiles_k, int tiles_jk, int chunk_len, int count, int per,
                    T* __restrict__ spart) {
-  sweep_tile<T, TJ, TK, false, 1>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len, count,
-                                  per, spart);
+  sweep_tile<T, TJ, TK, false, 1, false>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len,
+                                         count, per, spart);
 }
 
 // ---- point kernels: colour sweep, residual, transfer -------------------------
@@ -1563,7 +1582,7 @@ __global__ void k_fill(double* __restrict__ p, long count, double value) {
 
 inline dim3 xcd_grid(int count, int per) { return dim3(8 * ceil_div(count * per, 8)); }
 
-template <typename T, int TJ, int TK>
+template <typename T, int TJ, int TK, bool CB>
 int sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                  int cbuf, int chunks, hipStream_t st, T* spart, int norm) {
   const int tiles_k = (n - 1) / TK, tiles_j = (n - 1) / TJ;
@@ -1573,19 +1592,24 @@ int sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_acti
   const int per = tiles * nch;
   const dim3 grid = xcd_grid(count, per), block(SweepGeom<TJ, TK>::THREADS);
   if (cbuf >= 0) {
-    hipLaunchKernelGGL((k_sweep<T, TJ, TK, true>), grid, block, 0, st, d_list, d_active, buf, cbuf,
-                       tiles_k, tiles, chunk_len, count, per);
+    hipLaunchKernelGGL((k_sweep<T, TJ, TK, true, CB>), grid, block, 0, st, d_list, d_active, buf,
+                       cbuf, tiles_k, tiles, chunk_len, count, per);
   } else if (spart && norm == 1) {
-    if constexpr (std::is_same<T, double>::value)
-      hipLaunchKernelGGL((k_sweep_res_in<T, TJ, TK>), grid, block, 0, st, d_list, d_active, buf,
-                         tiles_k, tiles, chunk_len, count, per, spart);
+    if constexpr (std::is_same<T, double>::value) {
+      if constexpr (CB)
+        hipLaunchKernelGGL((k_sweep_res_in_cb<T, TJ, TK>), grid, block, 0, st, d_list, d_active,
+                           buf, tiles_k, tiles, chunk_len, count, per, spart);
+      else
+        hipLaunchKernelGGL((k_sweep_res_in<T, TJ, TK>), grid, block, 0, st, d_list, d_active,
+                           buf, tiles_k, tiles, chunk_len, count, per, spart);
+    }
   } else if (spart && norm == 2) {
     if constexpr (std::is_same<T, double>::value)
-      hipLaunchKernelGGL((k_sweep_res_out<T, TJ, TK>), grid, block, 0, st, d_list, d_active, buf,
-                         tiles_k, tiles, chunk_len, count, per, spart);
+      hipLaunchKernelGGL((k_sweep_res_out<T, TJ, TK, CB>), grid, block, 0, st, d_list, d_active,
+                         buf, tiles_k, tiles, chunk_len, count, per, spart);
   } else {
-    hipLaunchKernelGGL((k_sweep<T, TJ, TK, false>), grid, block, 0, st, d_list, d_active, buf,
-                       cbuf, tiles_k, tiles, chunk_len, count, per);
+    hipLaunchKernelGGL((k_sweep<T, TJ, TK, false, CB>), grid, block, 0, st, d_list, d_active,
+                       buf, cbuf, tiles_k, tiles, chunk_len, count, per);
   }
   return per;
 }
@@ -1695,12 +1719,15 @@ int sweep_blocks(int n, int count, SweepShape s) {
 
 template <typename T>
 int launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
-                 int cbuf, SweepShape s, hipStream_t st, T* spart, int norm) {
+                 int cbuf, SweepShape s, hipStream_t st, T* spart, int norm, bool const_b) {
   if (count <= 0) return 0;
   const int c = sweep_chunks(n, count, s);
-#define MG_SWEEP_CASE(TJ_, TK_)                                                       \
-  if (s.tj == TJ_ && s.tk == TK_)                                                     \
-    return sweep_launch<T, TJ_, TK_>(d_list, count, n, d_active, buf, cbuf, c, st, spart, norm);
+#define MG_SWEEP_CASE(TJ_, TK_)                                                              \
+  if (s.tj == TJ_ && s.tk == TK_)                                                            \
+    return const_b ? sweep_launch<T, TJ_, TK_, true>(d_list, count, n, d_active, buf, cbuf, c, \
+                                                     st, spart, norm)                       \
+                   : sweep_launch<T, TJ_, TK_, false>(d_list, count, n, d_active, buf, cbuf,  \
+                                                      c, st, spart, norm);
   MG_SWEEP_CASE(8, 64)
   MG_SWEEP_CASE(4, 64)
   MG_SWEEP_CASE(16, 32)
@@ -1803,7 +1830,7 @@ void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_
 
 #define MG_INSTANTIATE(T)                                                                       \
   template int launch_sweep<T>(const GridDescT<T>*, int, int, const int*, int, int, SweepShape,  \
-                               hipStream_t, T*, int);                                           \
+                               hipStream_t, T*, int, bool);                                     \
   template void launch_rbgs_colour<T>(const GridDescT<T>*, int, int, const int*, int, int,      \
                                       hipStream_t);                                             \
   template void launch_residual<T>(const GridDescT<T>*, int, int, const int*, int, hipStream_t); \
