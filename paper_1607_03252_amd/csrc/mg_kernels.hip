@@ -287,6 +287,11 @@ __global__ void __launch_bounds__(64) k_philox(const uint64_t* __restrict__ seed
 // Field on `count` grids of size n: Z = sum_{a,b,c} coef[abc] xi[abc]
 // phi_a(x_i) phi_b(y_j) phi_c(z_k), as nested 1D contractions over a, then b,
 // then c.  mode 0 stores wh = exp(-Z)/2, mode 1 stores k = exp(Z).
+// One workgroup per plane i of a grid: first the row factors
+// G_c(j) = sum_b (sum_a C_abc phi_a(x_i)) phi_b(y_j) of every row j into LDS,
+// then Z = sum_c G_c(j) phi_c(z_k) at every point of the plane, the points
+// dealt to the threads in memory order (whole rows for any n, full lanes).
+constexpr int kFieldMaxN = 1025;
 __global__ void __launch_bounds__(kBlock) k_field(int n, double* const* __restrict__ out,
                                                   const int* __restrict__ xi_index,
                                                   const double* __restrict__ normals,
@@ -294,37 +299,39 @@ __global__ void __launch_bounds__(kBlock) k_field(int n, double* const* __restri
                                                   const double* __restrict__ coef, int mode,
                                                   int count, int per) {
   __shared__ double C[64];
-  int g, blk;
-  if (!xcd_unit(count, per, g, blk)) return;
-  if (threadIdx.x < 64)
-    C[threadIdx.x] = coef[threadIdx.x] * normals[(size_t)xi_index[g] * 64 + threadIdx.x];
+  __shared__ double G[4 * kFieldMaxN];
+  int g, i;
+  if (!xcd_unit(count, per, g, i)) return;
+  const int t = threadIdx.x;
+  if (t < 64) C[t] = coef[t] * normals[(size_t)xi_index[g] * 64 + t];
   __syncthreads();
-  const Pt p = full_point(n, blk);
-  // a wave covers one row (i, j): lane c < 4 forms the row's partial sum
-  // G_c = sum_b (sum_a C_abc phi_a(x_i)) phi_b(y_j), shared by shuffles
-  const int lane = threadIdx.x & 63;
-  // (the row's coordinates hold for every lane of the wave, also for lanes
-  // whose column lies past the grid)
-  const int ic = min(p.i, n - 1), jc = min(p.j, n - 1);
-  double G = 0.0;
-  if (lane < 4) {
-    const int c = lane;
+  for (int q = t; q < 4 * n; q += kBlock) {
+    const int j = q >> 2, c = q & 3;
+    double G1 = 0.0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       double g1 = 0.0;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) g1 += C[16 * a + 4 * b + c] * phi[a * n + ic];
-      G += g1 * phi[b * n + jc];
+      for (int a = 0; a < 4; ++a) g1 += C[16 * a + 4 * b + c] * phi[a * n + i];
+      G1 += g1 * phi[b * n + j];
     }
+    G[q] = G1;
   }
-  double Gc[4];
+  __syncthreads();
+  const gptr<double> o = gview<double>(out[g] + (size_t)i * n * n);
+  const int np = n * n;
+  // row and column of point q by a float quotient corrected by one step
+  const float rn = 1.0f / (float)n;
+  for (int q = t; q < np; q += kBlock) {
+    int j = (int)((float)q * rn);
+    j -= j * n > q;
+    j += (j + 1) * n <= q;
+    const int k = q - j * n;
+    double Z = 0.0;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) Gc[c] = __shfl(G, c, 64);
-  if (!p.ok) return;
-  double Z = 0.0;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) Z += Gc[c] * phi[c * n + p.k];
-  out[g][vidx(n, p.i, p.j, p.k)] = mode == 0 ? 0.5 * exp(-Z) : exp(Z);
+    for (int c = 0; c < 4; ++c) Z += G[4 * j + c] * phi[c * n + k];
+    o[q] = mode == 0 ? 0.5 * exp(-Z) : exp(Z);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_inject(int nf, const double* const* __restrict__ fine,
@@ -479,7 +486,9 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     lp[rho] = lm[rho] + 1;
   }
 
-  T UB[4], W[4][2], B[CB ? 1 : 4][2], NR[4], FIP[4];
+  // rings indexed by plane offset from istart: UB, W, B, NR mod 4, FIP (the
+  // red point's +i face, read two planes later) and PA mod 2
+  T UB[4], W[4][2], B[CB ? 1 : 4][2], NR[4], FIP[2];
   // right-hand side at this thread's positions on the plane in ring slot sl
   auto bv = [&](int sl, int rho) -> T { return CB ? B[0][rho] : B[CB ? 0 : sl][rho]; };
   // plane m = istart + rel: black role (rel + 1) & 1
@@ -531,7 +540,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   const int CJ = (min(j0 + TJ + 1, n - 2) >> 1) + 2 - cj0;
   const bool cown = PRO && t < CJ * CK;
   const int crow = cown ? t / CK : 0, ccol = cown ? t - (t / CK) * CK : 0;
-  T cstage = 0, PA[4] = {0, 0, 0, 0};
+  T cstage = 0, PA[2] = {0, 0};
   auto c_issue = [&](int C) {
     const int Cc = min(max(C, 0), nc - 1);
     cstage = ec[(Cc * nc + min(cj0 + crow, nc - 1)) * nc + min(ck0 + ccol, nc - 1)];
@@ -579,8 +588,8 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   }
   NR[3] = 0;
   NR[2] = 0;
-  FIP[3] = rcp<T>(W[3][1] + W[0][1]);  // plane istart-1 is red in role 1
-  FIP[2] = 0;
+  FIP[1] = rcp<T>(W[3][1] + W[0][1]);  // plane istart-1 is red in role 1
+  FIP[0] = 0;
   if (live) {
     sU[0][lq[1]] = UB[0];
     sW[0][lq[1]] = W[0][1];
@@ -596,8 +605,8 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     const int qc = lc[RHO], qm = lm[RHO], qp = lp[RHO];
     constexpr int DJ = Geo::DJ;  // LDS index step of one row
     if (PRO) {
-      UB[SP] += PA[SP];                                          // plane i+1 (black role RHO)
-      PA[SM2] = pa_of(i + 2, kc[1 - RHO], intr[1 - RHO]);        // plane i+2
+      UB[SP] += PA[(K + 1) & 1];                                 // plane i+1 (black role RHO)
+      PA[K & 1] = pa_of(i + 2, kc[1 - RHO], intr[1 - RHO]);      // plane i+2
     }
     // red point of plane i
     const T wc = W[S0][RHO];
@@ -610,7 +619,6 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
                                       Ul[qc + DJ], Ul[qm], Ul[qp]);
     const T vr = gs_value<T>(sr, bv(S0, RHO));
     NR[S0] = (t1[RHO] && intr[RHO] && i <= n - 2) ? vr : (T)0;
-    FIP[S0] = fip;
     if (NM == 1) {
       const T rr = res_value<T>(sr, bv(S0, RHO), UR[K & 1]);
       acc += (tl[RHO] && i >= ia && i <= ib) ? rr * rr : (T)0;
@@ -626,7 +634,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
       const T* Rl = sR[PBM];
       const T* Fj = sFj[PBM];
       const T* Fk = sFk[PBM];
-      const St<T> sb = stencil_faces<T>(FIP[SM2], fim, Fj[qc - DJ], Fj[qc], Fk[qm], Fk[qc],
+      const St<T> sb = stencil_faces<T>(FIP[K & 1], fim, Fj[qc - DJ], Fj[qc], Fk[qm], Fk[qc],
                                         NR[SM2], NR[S0], Rl[qc - DJ], Rl[qc + DJ], Rl[qm],
                                         Rl[qp]);
       const T vb = gs_value<T>(sb, bv(SM, RHO));
@@ -639,6 +647,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
       bstore<T>(ro, offo[RHO] + sop, intr[RHO] ? vb : (T)0);
       bstore<T>(ro, offo[1 - RHO] + sop, NR[SM]);
     }
+    FIP[K & 1] = fip;  // after the black point above read plane i-2's
     // publish plane i's red values and faces, and plane i+1's black u_in and
     // wh (the buffers read in this plane are the other parity)
     if (t1[RHO]) {
@@ -1671,9 +1680,9 @@ void launch_field(int n, int count, double* const* d_out, const int* d_xi_index,
                   const double* d_normals, const double* d_phi, const double* d_coef, int mode,
                   hipStream_t st) {
   if (count <= 0) return;
-  const int per = point_blocks(n);
-  hipLaunchKernelGGL(k_field, xcd_grid(count, per), dim3(kBlock), 0, st, n, d_out, d_xi_index,
-                     d_normals, d_phi, d_coef, mode, count, per);
+  if (n > kFieldMaxN) return;  // plans stop at 1025 vertices per axis
+  hipLaunchKernelGGL(k_field, xcd_grid(count, n), dim3(kBlock), 0, st, n, d_out, d_xi_index,
+                     d_normals, d_phi, d_coef, mode, count, n);
 }
 
 void launch_inject(int nf, int count, const double* const* d_fine, double* const* d_coarse,
