@@ -133,7 +133,17 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *   "small_vcycle": 17 (default), 9 or 5 = from the largest grid of at most
  *               this size down, each V-cycle runs in one launch with the
  *               grids held in LDS; 0 = one launch per level and step
- *               (same results, bit for bit).
+ *               (same results, bit for bit);
+ *   "norm":     1 (default) = the residual norm of an iterate is summed in
+ *               the sweeps around it (black points in the cycle's last sweep,
+ *               red points in the next cycle's first) and the solve is judged
+ *               after that first sweep; 0 = a residual pass after each cycle
+ *               (same stopping cycle and results; the reported relative
+ *               residual differs by summation order only);
+ *   "tail":     1 (default) = once at most a quarter of a batch's solves
+ *               still cycle, the remaining cycles run on those solves' grids
+ *               only (more plane pieces per grid); 0 = always on the whole
+ *               batch (same results, bit for bit).
  * Returns MG_EINVAL for an unknown name or value. */
 int mg_plan_set_option(mg_plan plan, const char* name, long long value);
 

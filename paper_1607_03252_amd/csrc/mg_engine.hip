@@ -104,6 +104,9 @@ struct Batch {
   std::vector<int> top_sizes;                      // distinct top sizes, descending
   Lists<double> L64;
   Lists<float> L32;
+  // the grids of the solves still cycling, for the last cycles of a batch
+  // (device buffers sized for L64 on first use)
+  Lists<double> L64t;
   SolveState ss{};
   int* d_count = nullptr;
   int* d_cycle = nullptr;                          // device cycle counter
@@ -141,9 +144,12 @@ struct Batch {
     extra.push_back(p);
     return p;
   }
+  hipGraphExec_t tail_graph = nullptr;  // one cycle on L64t
   void drop_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
+    if (tail_graph) (void)hipGraphExecDestroy(tail_graph);
+    tail_graph = nullptr;
   }
   ~Batch() {
     drop_graphs();
@@ -188,6 +194,7 @@ struct mg_plan_s {
   int use_graph = 1;     // capture cycles into HIP graphs (mlmc_sample_batch)
   int small_ns = 17;     // grids of this size and below: the LDS V-cycle (0: off)
   int transfer = 0;      // 0: fused residual + restriction, 1: separate kernels
+  int tail_lists = 1;    // 1: a batch's last cycles run on its unfinished solves only
   int norm_sweep = 1;    // 1: a cycle's first sweep also takes the residual norm of
                          // the previous iterate (convergence judged one cycle late)
   std::map<int, SweepShape> shape;      // tile shape per grid size
@@ -296,7 +303,7 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
     int* ai = (int*)take(sizeof(int) * (ns * 4 + 2));
     double* dd = (double*)take(sizeof(double) * ns * 3);
     double* pp = (double*)take(sizeof(double) * npart);
-    double* sp = (double*)take(sizeof(double) * ns * 2 * kSweepParts);
+    double* sp = (double*)take(sizeof(double) * ns * (2 * kSweepParts + 2));
     if (pass == 0) {
       if (size_only) {
         *size_only = total;
@@ -358,7 +365,7 @@ static GridDescT<T> make_desc(const std::vector<LevelT<T>>& lv, size_t j, int so
   d.solve = solve;
   d.n = L.n;
   d.poff = poff;
-  d.spoff = j == 0 ? solve * 2 * kSweepParts : -1;
+  d.spoff = j == 0 ? solve * (2 * kSweepParts + 2) : -1;
   return d;
 }
 
@@ -557,8 +564,7 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
     // correction)
     const bool cb = Ls.const_b(si);
     launch_sweep<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf,
-                    shape_for(P, n, cbuf >= 0 || (spart && norm == 1 && !cb)), st, spart, norm,
-                    cb);
+                    shape_for(P, n, cbuf >= 0 || (spart && norm == 1 && !cb)), st, spart, norm, cb);
     out = 1 - buf;
   } else {
     if (cbuf >= 0) launch_prolong<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, st);
@@ -579,7 +585,11 @@ void launch_tick(int* ctr, hipStream_t st);
 // sweep, the red ones from the next cycle's first sweep, which runs in the
 // shape of the sweep with the coarse correction unless the right-hand side is
 // constant: *red gets its count), else 0 (a reduction after the cycle).
-static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr) {
+// Decided on the full lists L64 (the same for every cycle of a batch); the
+// counts are those of the given lists.
+static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr,
+                        const Lists<double>* Lp = nullptr) {
+  const Lists<double>& L = Lp ? *Lp : B->L64;
   const int n = B->sizes[si];
   if (B->spec.mixed || !P->norm_sweep || P->smoother != 0 || P->desc.nu1 < 1 ||
       P->desc.nu2 < 2 || n < 5)
@@ -587,11 +597,14 @@ static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr) {
   if (B->L64.chain_si >= 0 && si >= (size_t)B->L64.chain_si) return 0;  // LDS V-cycle sizes
   if (std::find(B->top_sizes.begin(), B->top_sizes.end(), n) == B->top_sizes.end()) return 0;
   if (!sweep_fits(n, sizeof(double))) return 0;
-  const int cnt = (int)B->L64.h[si].size();
-  const int per = sweep_blocks(n, cnt, shape_for(P, n, false));
-  const int per_red = sweep_blocks(n, cnt, shape_for(P, n, !B->L64.const_b(si)));
-  if (red) *red = per_red;
-  return per <= kSweepParts && per_red <= kSweepParts ? per : 0;
+  // decided per size for lists of any length: at most kSweepParts workgroups
+  // per grid (a list of one grid gets the most plane pieces)
+  if (std::max(sweep_blocks(n, 1, shape_for(P, n, false)), sweep_blocks(n, 1, shape_for(P, n, true))) >
+      kSweepParts)
+    return 0;
+  const int cnt = std::max<int>(1, (int)L.h[si].size());
+  if (red) *red = sweep_blocks(n, cnt, shape_for(P, n, !L.const_b(si)));
+  return sweep_blocks(n, cnt, shape_for(P, n, false));
 }
 
 // One V(nu1,nu2) cycle on every active solve.  Each level starts in buffer 0
@@ -618,17 +631,20 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls, bool norms = false, d
       launch_coarsest<T>(Ls.d[si], cnt, B->ss.active, st);
       continue;
     }
-    int lpr = 0;
-    const int lp = norms ? lagged_parts(P, B, si, &lpr) : 0;
+    int lpr = 0, lp = 0;
+    if constexpr (std::is_same<T, double>::value)
+      if (norms) lp = lagged_parts(P, B, si, &lpr, &Ls);
     for (int s = 0; s < nu1; ++s) {
       cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0,
                                s == 0 && lp > 0 ? (T*)B->ss.spart + kSweepParts : nullptr, 1);
-      if (s == 0 && lp > 0) {
-        // judge the incoming iterates now: a solve that stops keeps it in
-        // buffer 0 (this sweep wrote buffer 1; nothing after it runs for it)
-        const size_t ti = size_index(B->top_sizes, n);
-        launch_finalize2(B->L64.dtop[ti], (int)B->L64.htop[ti].size(), B->ss, RED_RESID,
-                         B->d_cycle, 1, fixed, P->desc.max_cycles, tol, st, lp, lpr);
+      if constexpr (std::is_same<T, double>::value) {
+        if (s == 0 && lp > 0) {
+          // judge the incoming iterates now: a solve that stops keeps it in
+          // buffer 0 (this sweep wrote buffer 1; nothing after it runs for it)
+          const size_t ti = size_index(B->top_sizes, n);
+          launch_finalize2(Ls.dtop[ti], (int)Ls.htop[ti].size(), B->ss, RED_RESID, B->d_cycle, 1,
+                           fixed, P->desc.max_cycles, tol, st, lp, lpr);
+        }
       }
     }
     // the one-pass transfer marches planes with a barrier each: with few
@@ -655,7 +671,9 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls, bool norms = false, d
       launch_prolong<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], cbuf, st);
       continue;
     }
-    const int lp = norms ? lagged_parts(P, B, si) : 0;
+    int lp = 0;
+    if constexpr (std::is_same<T, double>::value)
+      if (norms) lp = lagged_parts(P, B, si, nullptr, &Ls);
     cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], cbuf, P->prof && si == 0);
     for (int s = 1; s < nu2; ++s)
       cur[si] = smooth_once<T>(P, B, Ls, si, cur[si], -1, P->prof && si == 0,
@@ -665,20 +683,23 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls, bool norms = false, d
 }
 
 // One outer iteration for every active solve (recorded into graphs as is).
-static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed) {
+// Lp: the lists to cycle (default: all grids of the batch).
+static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
+                       Lists<double>* Lp = nullptr) {
   hipStream_t st = B->st;
+  Lists<double>& L = Lp ? *Lp : B->L64;
   launch_tick(B->d_cycle, st);
   if (!B->spec.mixed) {
-    const int out = run_cycle<double>(P, B, B->L64, true, tol, fixed);
+    const int out = run_cycle<double>(P, B, L, true, tol, fixed);
     if (out != 0)  // odd sweep count: bring the top iterates back to buffer 0
       for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
-        launch_copy_buf<double>(B->L64.dtop[ti], (int)B->L64.htop[ti].size(), B->top_sizes[ti],
+        launch_copy_buf<double>(L.dtop[ti], (int)L.htop[ti].size(), B->top_sizes[ti],
                                 B->ss.active, 1, st);
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
-      const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+      const int n = B->top_sizes[ti], cnt = (int)L.htop[ti].size();
       if (lagged_parts(P, B, size_index(B->sizes, n)) > 0) continue;  // judged in the sweep
-      launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_RESID, B->ss.partials, st);
-      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, 0, fixed,
+      launch_reduce(L.dtop[ti], cnt, n, B->ss.active, 0, RED_RESID, B->ss.partials, st);
+      launch_finalize2(L.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, 0, fixed,
                        P->desc.max_cycles, tol, st);
     }
   } else {
@@ -711,6 +732,40 @@ static hipGraphExec_t graph_for(mg_plan_s* P, Batch* B, int c, double tol, int f
   return ex;
 }
 
+// The tail of a batch: at most tail_cap(B) solves still cycle.
+static int tail_cap(const Batch* B) { return std::max(1, B->ns / 4); }
+
+// B->L64t := per list, the grids of the solves with act[solve] != 0, padded
+// with grids of stopped solves (their kernels exit at once) to a fixed
+// length (min(list length, tail_cap)), so that one graph serves every tail.
+static void build_tail_lists(Batch* B, const std::vector<int>& act) {
+  Lists<double>& T = B->L64t;
+  const Lists<double>& F = B->L64;
+  const size_t cap = (size_t)tail_cap(B);
+  auto fill = [&](auto& out, const auto& full, auto solve_of) {
+    const size_t len = std::min(full.size(), cap);
+    out.clear();
+    for (const auto& x : full)
+      if (act[solve_of(x)] && out.size() < len) out.push_back(x);
+    for (const auto& x : full)
+      if (!act[solve_of(x)] && out.size() < len) out.push_back(x);
+  };
+  auto grid_solve = [](const GridDesc& d) { return d.solve; };
+  auto chain_solve = [](const SmallChain<double>& c) { return c.lv[0].solve; };
+  const bool first = T.d.empty();
+  if (first) {
+    T.h.assign(F.h.size(), {});
+    T.htop.assign(F.htop.size(), {});
+    T.chain_si = F.chain_si;
+    T.chains.clear();
+    for (const auto& g : F.chains) T.chains.push_back({g.ns, {}, nullptr});
+  }
+  for (size_t si = 0; si < F.h.size(); ++si) fill(T.h[si], F.h[si], grid_solve);
+  for (size_t ti = 0; ti < F.htop.size(); ++ti) fill(T.htop[ti], F.htop[ti], grid_solve);
+  for (size_t g = 0; g < F.chains.size(); ++g) fill(T.chains[g].h, F.chains[g].h, chain_solve);
+  upload(B, T, B->st);  // (device arrays sized by the first call: the fixed lengths)
+}
+
 // Cycle every solve of the batch until each has converged (or run exactly
 // fixed_cycles).  Returns true when every solve met tol.
 static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graphs) {
@@ -729,10 +784,30 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
     if (lagged_parts(P, B, size_index(B->sizes, n)) > 0) extra = 1;
   const int limit = (fixed > 0 ? fixed : P->desc.max_cycles) + extra;
   const bool use_graphs = graphs && P->use_graph && !P->prof;
+  // the last cycles of a batch, once at most a quarter of the solves still
+  // cycle, run on lists of those solves' grids only: the sweeps then split
+  // the plane march of the few remaining grids over more workgroups
+  const bool tail_ok = !B->spec.mixed && !P->prof && P->tail_lists && B->ns >= 4;
+  bool in_tail = false;
+  std::vector<int> act(B->ns);
   int done = 0, maxc = 0;
   while (done < limit) {
     int c = 1;
-    if (use_graphs) {
+    if (in_tail) {
+      if (use_graphs) {
+        if (!B->tail_graph) {
+          hipGraph_t g = nullptr;
+          CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          cycle_step(P, B, tol, fixed, &B->L64t);
+          CK(hipStreamEndCapture(st, &g));
+          CK(hipGraphInstantiate(&B->tail_graph, g, nullptr, nullptr, 0));
+          CK(hipGraphDestroy(g));
+        }
+        CK(hipGraphLaunch(B->tail_graph, st));
+      } else {
+        cycle_step(P, B, tol, fixed, &B->L64t);
+      }
+    } else if (use_graphs) {
       // the first launch covers the cycles the last batch needed, less one
       const int guess = fixed > 0 ? fixed + extra : B->last_cycles;
       c = done == 0 ? std::max(1, std::min(limit, guess - 1)) : 1;
@@ -743,8 +818,16 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
     done += c;
     launch_count_active(B->ss.active, B->ns, B->d_count, st);
     CK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (tail_ok)
+      CK(hipMemcpyAsync(act.data(), B->ss.active, sizeof(int) * B->ns, hipMemcpyDeviceToHost,
+                        st));
     CK(hipStreamSynchronize(st));
-    if (*B->h_count == 0) break;
+    const int left = *B->h_count;
+    if (left == 0) break;
+    if (tail_ok && left <= tail_cap(B) && !in_tail) {
+      build_tail_lists(B, act);
+      in_tail = true;
+    }
   }
   std::vector<int> cyc(B->ns);
   CK(hipMemcpyAsync(cyc.data(), B->ss.cycles, sizeof(int) * B->ns, hipMemcpyDeviceToHost, st));
@@ -1298,6 +1381,9 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
   } else if (k == "transfer") {
     if (value != 0 && value != 1) return MG_EINVAL;
     P->transfer = (int)value;
+  } else if (k == "tail") {
+    if (value != 0 && value != 1) return MG_EINVAL;
+    P->tail_lists = (int)value;
   } else if (k == "norm") {
     if (value != 0 && value != 1) return MG_EINVAL;
     P->norm_sweep = (int)value;

@@ -30,7 +30,7 @@ struct GridDescT {
   int n;            // vertices per axis
   int poff;         // offset of this grid's reduction partials (top grids only)
   int spoff;        // top grids: offset of the in-sweep residual-norm partials
-                    // (spart[spoff + workgroup], 2 x kSweepParts); -1 otherwise
+                    // (SolveState::spart); -1 otherwise
   int bstride;      // n*n for a full right-hand side array, 0 for a constant plane
 };
 using GridDesc = GridDescT<double>;
@@ -53,9 +53,10 @@ struct SolveState {
   double* partials; // reduction partials
   int* start;       // cycle counter value when the solve was started
   int* qpend;       // 1 from admission until the QoI of a stopped solve is taken
-  double* spart;    // 2 x kSweepParts in-sweep residual-norm partials per solve
-                    // (black points of the output of a cycle's last sweep, then
-                    // red points of the input of the next cycle's first sweep)
+  double* spart;    // per solve 2 x kSweepParts + 2: in-sweep residual-norm
+                    // partials (black points of the output of a cycle's last
+                    // sweep, red points of the input of the next cycle's first
+                    // sweep), then the two partial counts
 };
 
 // Workgroups per grid that a sweep computing the residual norm may use (the
@@ -176,9 +177,9 @@ void launch_correct(const GridDesc* d_list, const GridDesc32* d_list32, int coun
 // Finalise per solve.  The cycle judged is *cycle_ctr - start - lag (an
 // iterate before the first cycle is never judged); fixed_cycles > 0 selects
 // fixed-count mode.  RED_RESID with sweep_parts > 0 sums the in-sweep
-// partials spart[spoff + q], q < sweep_parts, and then
-// spart[spoff + kSweepParts + q], q < sweep_parts_red, instead of the
-// reduction's.
+// partials instead of the reduction's: spart[spoff + q] and
+// spart[spoff + kSweepParts + q] for the counts the sweeps stored at
+// spart[spoff + 2 kSweepParts] and [... + 1] (sweep_parts_red is unused).
 void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
                       const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
                       hipStream_t st, int sweep_parts = 0, int sweep_parts_red = 0);

@@ -697,6 +697,8 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
       T sum = 0;
       for (int w = 0; w < NW; ++w) sum += ws[w];
       spart[d.spoff + blk] = sum;
+      // the number of partials of this grid, for the judgement that sums them
+      if (blk == 0) spart[d.spoff + (NM == 2 ? 2 * kSweepParts : kSweepParts + 1)] = (T)per;
     }
   }
 }
@@ -1499,12 +1501,15 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
   if (mode == RED_RESID && !s.active[sv]) return;
   if (mode == RED_QOI_PENDING && (!s.qpend[sv] || s.active[sv])) return;
   const bool sw = mode == RED_RESID && sweep_parts > 0;
-  const int P = sw ? sweep_parts : reduce_blocks(d.n);
   const double* src = sw ? s.spart + d.spoff : s.partials + d.poff;
+  // in-sweep sums: the counts the two sweeps recorded after their partials
+  const int P = sw ? (int)src[2 * kSweepParts] : reduce_blocks(d.n);
   double v = 0.0;
   for (int q = threadIdx.x; q < P; q += kBlock) v += src[q];
-  if (sw)
-    for (int q = threadIdx.x; q < sweep_parts_red; q += kBlock) v += src[kSweepParts + q];
+  if (sw) {
+    const int P2 = (int)src[2 * kSweepParts + 1];
+    for (int q = threadIdx.x; q < P2; q += kBlock) v += src[kSweepParts + q];
+  }
   v = block_sum(v);
   if (threadIdx.x != 0) return;
   if (mode == RED_BNORM) {
