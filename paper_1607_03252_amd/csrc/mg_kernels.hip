@@ -420,11 +420,19 @@ struct SweepGeom {
 // sums of the next sweep, both evaluated exactly as the residual kernels do.
 // CB: every grid of the launch has a constant right-hand side (bstride 0):
 // its two values per thread are loaded once instead of per plane.
+//
+// Work: the launch has nwg workgroups (a multiple of 8) for the list's count
+// grids.  Every wave counts the active grids of the list by ballots; with
+// nact of them active, each active grid's tiles are split into C pieces of
+// its plane march (chunks > 0: C = chunks; else as many as the workgroups
+// allow, at least four planes per piece), so a launch in which most solves
+// have stopped still spreads its work over the machine.  Workgroups are
+// numbered XCD-contiguously (neighbouring tiles share an L2).
 template <typename T, int TJ, int TK, bool PRO, int NM, bool CB>
 __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list,
                                            const int* __restrict__ active, int buf, int cbuf,
-                                           int tiles_k, int tiles_jk, int chunk_len, int count,
-                                           int per, T* __restrict__ spart) {
+                                           int tiles_k, int tiles_jk, int chunks, int count,
+                                           int nwg, T* __restrict__ spart) {
   using Geo = SweepGeom<TJ, TK>;
   constexpr int W2 = Geo::W2, A2 = Geo::A2, HW = W2 / 2;
   __shared__ T sU[2][A2];   // u_in of black positions, plane parity
@@ -433,8 +441,51 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   __shared__ T sFj[2][A2];  // face between x and x + W2 (x red or black)
   __shared__ T sFk[2][A2];  // face between x and x + 1
 
-  int gi, blk;
-  if (!xcd_unit(count, per, gi, blk)) return;
+  const int nl = list[0].n;
+  const int wl = threadIdx.x & 63;
+  // active masks of the first 128 grids kept for the search below
+  const bool on0 = wl < count && active[list[wl].solve];
+  const bool on1 = 64 + wl < count && active[list[64 + wl].solve];
+  const unsigned long long m0 = __ballot(on0), m1 = __ballot(on1);
+  int nact = __popcll(m0) + __popcll(m1);
+  for (int b = 128; b < count; b += 64) {
+    const bool on = b + wl < count && active[list[b + wl].solve];
+    nact += __popcll(__ballot(on));
+  }
+  if (nact == 0) return;
+  // (at most kSweepParts workgroups per grid: the residual sums keep one
+  // partial per workgroup)
+  const int C = chunks > 0 ? chunks
+                           : max(1, min(min(nwg / (nact * tiles_jk), (nl - 2) / 4),
+                                        kSweepParts / tiles_jk));
+  const int chunk_len = ceil_div(nl - 2, C);
+  const int per = tiles_jk * ceil_div(nl - 2, chunk_len);  // workgroups per active grid
+  const int w = (int)(blockIdx.x & 7) * (nwg >> 3) + (int)(blockIdx.x >> 3);
+  if (w >= nact * per) return;
+  int a = w / per;
+  const int blk = w - a * per;
+  int gi = 0;
+  // the a-th active grid: its bit among the masks
+  auto nth = [&](unsigned long long m, int r) {
+    const bool hit = ((m >> wl) & 1ull) && __popcll(m & ((1ull << wl) - 1ull)) == r;
+    return __ffsll(__ballot(hit)) - 1;
+  };
+  if (a < __popcll(m0)) {
+    gi = nth(m0, a);
+  } else if ((a -= __popcll(m0)) < __popcll(m1)) {
+    gi = 64 + nth(m1, a);
+  } else {
+    a -= __popcll(m1);
+    for (int b = 128; b < count; b += 64) {
+      const bool on = b + wl < count && active[list[b + wl].solve];
+      const unsigned long long m = __ballot(on);
+      if (a < __popcll(m)) {
+        gi = b + nth(m, a);
+        break;
+      }
+      a -= __popcll(m);
+    }
+  }
   const GridDescT<T> d = list[gi];
   if (!active[d.solve]) return;
   const int n = d.n, sn2 = n * n, bs = d.bstride;
@@ -706,9 +757,9 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
 template <typename T, int TJ, int TK, bool PRO, bool CB>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     k_sweep(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
-            int cbuf, int tiles_k, int tiles_jk, int chunk_len, int count, int per) {
-  sweep_tile<T, TJ, TK, PRO, 0, CB>(list, active, buf, cbuf, tiles_k, tiles_jk, chunk_len, count,
-                                    per, nullptr);
+            int cbuf, int tiles_k, int tiles_jk, int chunks, int count, int nwg) {
+  sweep_tile<T, TJ, TK, PRO, 0, CB>(list, active, buf, cbuf, tiles_k, tiles_jk, chunks, count,
+                                    nwg, nullptr);
 }
 
 // The sweep with the black residuals of its output, held to the plain
@@ -718,10 +769,10 @@ template <typename T, int TJ, int TK, bool CB>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     __attribute__((amdgpu_waves_per_eu(4)))
     k_sweep_res_out(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
-                    int buf, int tiles_k, int tiles_jk, int chunk_len, int count, int per,
+                    int buf, int tiles_k, int tiles_jk, int chunks, int count, int nwg,
                     T* __restrict__ spart) {
-  sweep_tile<T, TJ, TK, false, 2, CB>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len, count,
-                                      per, spart);
+  sweep_tile<T, TJ, TK, false, 2, CB>(list, active, buf, -1, tiles_k, tiles_jk, chunks, count,
+                                      nwg, spart);
 }
 
 // The sweep with the red residuals of its input keeps the input values of
@@ -733,18 +784,18 @@ template <typename T, int TJ, int TK>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     __attribute__((amdgpu_waves_per_eu(4)))
     k_sweep_res_in_cb(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
-                      int buf, int tiles_k, int tiles_jk, int chunk_len, int count, int per,
+                      int buf, int tiles_k, int tiles_jk, int chunks, int count, int nwg,
                       T* __restrict__ spart) {
-  sweep_tile<T, TJ, TK, false, 1, true>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len,
-                                        count, per, spart);
+  sweep_tile<T, TJ, TK, false, 1, true>(list, active, buf, -1, tiles_k, tiles_jk, chunks,
+                                        count, nwg, spart);
 }
 template <typename T, int TJ, int TK>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
     k_sweep_res_in(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
-                   int buf, int tiles_k, int tiles_jk, int chunk_len, int count, int per,
+                   int buf, int tiles_k, int tiles_jk, int chunks, int count, int nwg,
                    T* __restrict__ spart) {
-  sweep_tile<T, TJ, TK, false, 1, false>(list, active, buf, -1, tiles_k, tiles_jk, chunk_len,
-                                         count, per, spart);
+  sweep_tile<T, TJ, TK, false, 1, false>(list, active, buf, -1, tiles_k, tiles_jk, chunks,
+                                         count, nwg, spart);
 }
 
 // ---- point kernels: colour sweep, residual, transfer -------------------------
@@ -1596,34 +1647,44 @@ __global__ void k_fill(double* __restrict__ p, long count, double value) {
 
 inline dim3 xcd_grid(int count, int per) { return dim3(8 * ceil_div(count * per, 8)); }
 
+// Workgroups of a sweep launch: with automatic plane pieces (chunks 0) at
+// least kSweepUnits (the kernel spreads them over the grids still active),
+// otherwise the count x tiles x pieces of the fixed split.
+constexpr int kSweepUnits = 512;
 template <typename T, int TJ, int TK, bool CB>
 int sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                  int cbuf, int chunks, hipStream_t st, T* spart, int norm) {
   const int tiles_k = (n - 1) / TK, tiles_j = (n - 1) / TJ;
   const int tiles = tiles_k * tiles_j;
-  const int chunk_len = ceil_div(n - 2, chunks);
-  const int nch = ceil_div(n - 2, chunk_len);
-  const int per = tiles * nch;
-  const dim3 grid = xcd_grid(count, per), block(SweepGeom<TJ, TK>::THREADS);
+  int units;
+  if (chunks > 0) {
+    const int chunk_len = ceil_div(n - 2, chunks);
+    units = count * tiles * ceil_div(n - 2, chunk_len);
+  } else {
+    units = std::max(count * tiles, kSweepUnits);
+  }
+  const int nwg = 8 * ceil_div(units, 8);
+  const int per = nwg;  // (returned: an upper bound of the workgroups per grid)
+  const dim3 grid(nwg), block(SweepGeom<TJ, TK>::THREADS);
   if (cbuf >= 0) {
     hipLaunchKernelGGL((k_sweep<T, TJ, TK, true, CB>), grid, block, 0, st, d_list, d_active, buf,
-                       cbuf, tiles_k, tiles, chunk_len, count, per);
+                       cbuf, tiles_k, tiles, chunks, count, nwg);
   } else if (spart && norm == 1) {
     if constexpr (std::is_same<T, double>::value) {
       if constexpr (CB)
         hipLaunchKernelGGL((k_sweep_res_in_cb<T, TJ, TK>), grid, block, 0, st, d_list, d_active,
-                           buf, tiles_k, tiles, chunk_len, count, per, spart);
+                           buf, tiles_k, tiles, chunks, count, nwg, spart);
       else
         hipLaunchKernelGGL((k_sweep_res_in<T, TJ, TK>), grid, block, 0, st, d_list, d_active,
-                           buf, tiles_k, tiles, chunk_len, count, per, spart);
+                           buf, tiles_k, tiles, chunks, count, nwg, spart);
     }
   } else if (spart && norm == 2) {
     if constexpr (std::is_same<T, double>::value)
       hipLaunchKernelGGL((k_sweep_res_out<T, TJ, TK, CB>), grid, block, 0, st, d_list, d_active,
-                         buf, tiles_k, tiles, chunk_len, count, per, spart);
+                         buf, tiles_k, tiles, chunks, count, nwg, spart);
   } else {
     hipLaunchKernelGGL((k_sweep<T, TJ, TK, false, CB>), grid, block, 0, st, d_list, d_active,
-                       buf, cbuf, tiles_k, tiles, chunk_len, count, per);
+                       buf, cbuf, tiles_k, tiles, chunks, count, nwg);
   }
   return per;
 }
@@ -1720,10 +1781,13 @@ void launch_prepare_problem(int n, const double* k, const double* f, double* wh,
 // march until the launch has about 512 workgroups (two per CU; small batches
 // and small grids are latency-bound by the sequential march), keeping at
 // least four planes per piece.
+// (automatic: as the kernel splits a launch of this many active grids)
 static int sweep_chunks(int n, int count, SweepShape s) {
   if (s.chunks >= 1) return s.chunks;
   const int tiles = ((n - 1) / s.tj) * ((n - 1) / s.tk);
-  return std::max(1, std::min(ceil_div(512, std::max(1, count * tiles)), (n - 2) / 4));
+  const int nwg = 8 * ceil_div(std::max(count * tiles, kSweepUnits), 8);
+  return std::max(1, std::min(std::min(nwg / std::max(1, count * tiles), (n - 2) / 4),
+                              kSweepParts / tiles));
 }
 
 int sweep_blocks(int n, int count, SweepShape s) {
@@ -1735,7 +1799,7 @@ template <typename T>
 int launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                  int cbuf, SweepShape s, hipStream_t st, T* spart, int norm, bool const_b) {
   if (count <= 0) return 0;
-  const int c = sweep_chunks(n, count, s);
+  const int c = s.chunks;  // 0: chosen in the kernel from the active grids
 #define MG_SWEEP_CASE(TJ_, TK_)                                                              \
   if (s.tj == TJ_ && s.tk == TK_)                                                            \
     return const_b ? sweep_launch<T, TJ_, TK_, true>(d_list, count, n, d_active, buf, cbuf, c, \
