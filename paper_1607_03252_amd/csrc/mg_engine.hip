@@ -808,9 +808,11 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
         cycle_step(P, B, tol, fixed, &B->L64t);
       }
     } else if (use_graphs) {
-      // the first launch covers the cycles the last batch needed, less one
+      // the first launch covers the steps the last batch needed (a step in
+      // which every solve has stopped costs only launches that exit at once;
+      // a missing one costs a round trip to the host)
       const int guess = fixed > 0 ? fixed + extra : B->last_cycles;
-      c = done == 0 ? std::max(1, std::min(limit, guess - 1)) : 1;
+      c = done == 0 ? std::max(1, std::min(limit, guess)) : 1;
       CK(hipGraphLaunch(graph_for(P, B, c, tol, fixed), st));
     } else {
       cycle_step(P, B, tol, fixed);
