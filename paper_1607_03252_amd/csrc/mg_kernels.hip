@@ -599,18 +599,30 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   auto c_store = [&](int C) {
     if (cown) sC[C & 3][crow * CKM + ccol] = cstage;
   };
-  // correction at fine (m, j, kk), zero off the interior
-  auto pa_of = [&](int m, int kk, bool intk) -> T {
-    const int mi = min(max(m, 1), n - 2), ki = min(max(kk, 1), n - 2);
-    const int rr = (jI >> 1) - cj0, cc = (ki >> 1) - ck0;
-    const T* c0 = sC[(mi >> 1) & 3];
-    const T* c1 = sC[((mi >> 1) + 1) & 3];
-    const int o = rr * CKM + cc;
-    const T v[8] = {c0[o], c0[o + 1], c0[o + CKM], c0[o + CKM + 1],
-                    c1[o], c1[o + 1], c1[o + CKM], c1[o + CKM + 1]};
-    const T pa = prolong_combine<T>(mi, jI, ki, v);
+  // Correction at fine (m, j, kk), zero off the interior, evaluated as the
+  // trilinear interpolation is written (prolong_combine): the (j, k) part on
+  // the coarse planes (m >> 1) and (m >> 1) + 1, then the i part.  The (j, k)
+  // part on the upper plane is the lower one of plane m + 2, the next plane
+  // of the same role: it is returned in P1 and passed back as P0 then.
+  auto pjk = [&](int I, int kk) -> T {
+    const int ki = min(max(kk, 1), n - 2);
+    const T* c = sC[I & 3];
+    const int o = ((jI >> 1) - cj0) * CKM + (ki >> 1) - ck0;
+    const T wj1 = (jI & 1) ? (T)0.5 : (T)0, wj0 = (jI & 1) ? (T)0.5 : (T)1;
+    const T wk1 = (ki & 1) ? (T)0.5 : (T)0, wk0 = (ki & 1) ? (T)0.5 : (T)1;
+    return wj0 * (wk0 * c[o] + wk1 * c[o + 1]) + wj1 * (wk0 * c[o + CKM] + wk1 * c[o + CKM + 1]);
+  };
+  auto pa_from = [&](int m, int kk, bool intk, T P0, T& P1) -> T {
+    const int mi = min(max(m, 1), n - 2);
+    P1 = pjk((mi >> 1) + 1, kk);
+    const T wi1 = (mi & 1) ? (T)0.5 : (T)0, wi0 = (mi & 1) ? (T)0.5 : (T)1;
+    const T pa = wi0 * P0 + wi1 * P1;
     return (m >= 1 && m <= n - 2 && intk) ? pa : (T)0;
   };
+  auto pa_of = [&](int m, int kk, bool intk, T& P1) -> T {
+    return pa_from(m, kk, intk, pjk(min(max(m, 1), n - 2) >> 1, kk), P1);
+  };
+  T PJ[2] = {0, 0};  // per role: the (j, k) part for its next plane
 
   // prologue: planes istart-1 .. istart+2, the +i face of the red point below
   // plane istart (the black points of plane istart use it), plane istart to LDS
@@ -633,9 +645,10 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     c_issue(((istart + 3) >> 1) + 1);  // stored at the end of plane istart
     __syncthreads();
     // black roles: plane istart-1 -> 0, istart -> 1, istart+1 -> 0
-    UB[3] += pa_of(istart - 1, kc[0], intr[0]);
-    UB[0] += pa_of(istart, kc[1], intr[1]);
-    PA[1] = pa_of(istart + 1, kc[0], intr[0]);
+    T P1;
+    UB[3] += pa_of(istart - 1, kc[0], intr[0], P1);
+    UB[0] += pa_of(istart, kc[1], intr[1], PJ[1]);     // role 1 again on plane istart + 2
+    PA[1] = pa_of(istart + 1, kc[0], intr[0], PJ[0]);  // role 0 again on plane istart + 3
   }
   NR[3] = 0;
   NR[2] = 0;
@@ -657,7 +670,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     constexpr int DJ = Geo::DJ;  // LDS index step of one row
     if (PRO) {
       UB[SP] += PA[(K + 1) & 1];                                 // plane i+1 (black role RHO)
-      PA[K & 1] = pa_of(i + 2, kc[1 - RHO], intr[1 - RHO]);      // plane i+2
+      PA[K & 1] = pa_from(i + 2, kc[1 - RHO], intr[1 - RHO], PJ[1 - RHO], PJ[1 - RHO]);  // i+2
     }
     // red point of plane i
     const T wc = W[S0][RHO];
