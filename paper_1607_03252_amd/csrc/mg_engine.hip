@@ -649,8 +649,9 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls, bool norms = false, d
     }
     // the one-pass transfer marches planes with a barrier each: with few
     // workgroups the separate kernels (same results) finish sooner
-    if (P->transfer == 0 && cnt * resrestrict_blocks(n) >= 128) {
-      launch_resrestrict<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);
+    // (it addresses whole grids with 32-bit offsets, as the fused sweep)
+    if (P->transfer == 0 && cnt * resrestrict_blocks(n) >= 128 && sweep_fits(n, sizeof(T))) {
+      launch_resrestrict<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st, Ls.const_b(si));
     } else {
       launch_residual<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);
       launch_restrict<T>(Ls.d[si], cnt, n, B->ss.active, st);

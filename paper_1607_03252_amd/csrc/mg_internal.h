@@ -142,7 +142,7 @@ void launch_restrict(const GridDescT<T>* d_list, int count, int n, const int* d_
 int resrestrict_blocks(int n);
 template <typename T>
 void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
-                        int buf, hipStream_t st);
+                        int buf, hipStream_t st, bool const_b = false);
 template <typename T>
 void launch_coarsest(const GridDescT<T>* d_list, int count, const int* d_active, hipStream_t st);
 template <typename T>

@@ -1087,7 +1087,10 @@ struct RRGeom {
   static constexpr int THREADS = ((FT + 63) / 64) * 64;
 };
 
-template <typename T, int RJ, int RK>
+// CB: every grid has a constant right-hand side plane (loaded once).  Grid
+// arrays are addressed as in the sweep: one descriptor per array, the
+// plane's offset added to the per-lane offsets.
+template <typename T, int RJ, int RK, bool CB>
 __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
     k_resrestrict(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
                   int tiles_k, int count, int per) {
@@ -1139,20 +1142,20 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
   const bool cbr = cl && J <= nc - 2 && K == nc - 1;
   const uint32_t oco = (cin || cbr) ? (uint32_t)((J * nc + K) * sizeof(T)) : kOut;
   const uint32_t oc0 = (cl && K == 1 && J <= nc - 2) ? (uint32_t)(J * nc * sizeof(T)) : kOut;
-  const T* u_ = buf ? d.u[1] : d.u[0];
-  auto plane = [&](const T* base, int pm, bool ok) {
-    return rsrc(base + (size_t)(ok ? pm : 0) * sn2, ok ? pbytes : 0u);
-  };
-  T OU[4], OW[4], OB[4], HU[4], HW[4];
+  // (planes past the grid are past the range and read 0; the residual of
+  // the boundary planes is not used)
+  const uint32_t gbytes = (uint32_t)n * pbytes;
+  const auto ru = rsrc(buf ? d.u[1] : d.u[0], gbytes), rw = rsrc(d.wh, gbytes);
+  const auto rb = rsrc(d.b, d.bstride ? gbytes : pbytes);
+  T OU[4], OW[4], OB[CB ? 1 : 4], HU[4], HW[4];
+  if (CB) OB[0] = bload<T>(rb, oo);
   auto load = [&](int pm, int sl) {
-    const bool ok = pm <= n - 1, okb = pm <= n - 2;
-    const auto ru = plane(u_, pm, ok), rw = plane(d.wh, pm, ok);
-    const auto rb = rsrc(d.b + (size_t)(okb ? pm : 0) * d.bstride, okb ? pbytes : 0u);
-    OU[sl] = bload<T>(ru, oo);
-    OW[sl] = bload<T>(rw, oo);
-    OB[sl] = bload<T>(rb, oo);
-    HU[sl] = bload<T>(ru, oh);
-    HW[sl] = bload<T>(rw, oh);
+    const uint32_t so = (uint32_t)pm * pbytes;
+    OU[sl] = bload<T>(ru, oo + so);
+    OW[sl] = bload<T>(rw, oo + so);
+    if (!CB) OB[sl] = bload<T>(rb, oo + (d.bstride ? so : 0u));  // (a constant plane: stride 0)
+    HU[sl] = bload<T>(ru, oh + so);
+    HW[sl] = bload<T>(rw, oh + so);
   };
   auto prologue = [&]() {
     load(0, 3);
@@ -1183,7 +1186,7 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
     const St<T> st = stencil_faces<T>(fim, fip, rcp<T>(w + Lw[qs - W]), rcp<T>(w + Lw[qs + W]),
                                       rcp<T>(w + Lw[qs - 1]), rcp<T>(w + Lw[qs + 1]), OU[SM],
                                       OU[SP], Lu[qs - W], Lu[qs + W], Lu[qs - 1], Lu[qs + 1]);
-    const T rv = res_value<T>(st, OB[S0], OU[S0]);
+    const T rv = res_value<T>(st, OB[CB ? 0 : S0], OU[S0]);
     fim = fip;
     if (fl) {
       R[PB][t] = (fin && i <= n - 2) ? rv : (T)0;
@@ -1219,12 +1222,12 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
       s1 += tm[2];
       const int I = (i - 1) >> 1;
       const bool st_ok = odd && I >= 1 && I <= nc - 2;
-      const auto rbc = rsrc(d.bc + (size_t)(st_ok ? I : 0) * nc * nc, st_ok ? cbytes : 0u);
-      const auto ruc = rsrc(d.uc[0] + (size_t)(st_ok ? I : 0) * nc * nc, st_ok ? cbytes : 0u);
-      bstore<T>(rbc, oco, cin ? (T)0.5 * s1 : (T)0);
-      bstore<T>(ruc, oco, (T)0);
-      bstore<T>(rbc, oc0, (T)0);
-      bstore<T>(ruc, oc0, (T)0);
+      const uint32_t cso = (uint32_t)I * cbytes, cg = st_ok ? (uint32_t)nc * cbytes : 0u;
+      const auto rbc = rsrc(d.bc, cg), ruc = rsrc(d.uc[0], cg);
+      bstore<T>(rbc, oco + cso, cin ? (T)0.5 * s1 : (T)0);
+      bstore<T>(ruc, oco + cso, (T)0);
+      bstore<T>(rbc, oc0 + cso, (T)0);
+      bstore<T>(ruc, oc0 + cso, (T)0);
       T s0 = 0;
       s0 += tm[0];
       s0 += tm[1];
@@ -1862,20 +1865,27 @@ int resrestrict_blocks(int n) {
 
 template <typename T>
 void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
-                        int buf, hipStream_t st) {
+                        int buf, hipStream_t st, bool const_b) {
   if (count <= 0) return;
   const int m = (n - 1) / 2 - 1;  // coarse interior points per axis
-  if (n >= 65) {
-    const int tk = ceil_div(m, kRRK1), per = ceil_div(m, kRRJ1) * tk;
-    hipLaunchKernelGGL((k_resrestrict<T, kRRJ1, kRRK1>), xcd_grid(count, per),
-                       dim3(RRGeom<kRRJ1, kRRK1>::THREADS), 0, st, d_list, d_active, buf, tk, count,
-                       per);
-  } else {
-    const int tk = ceil_div(m, kRRK2), per = ceil_div(m, kRRJ2) * tk;
-    hipLaunchKernelGGL((k_resrestrict<T, kRRJ2, kRRK2>), xcd_grid(count, per),
-                       dim3(RRGeom<kRRJ2, kRRK2>::THREADS), 0, st, d_list, d_active, buf, tk, count,
-                       per);
-  }
+  auto go = [&](auto cb) {
+    constexpr bool CB = decltype(cb)::value;
+    if (n >= 65) {
+      const int tk = ceil_div(m, kRRK1), per = ceil_div(m, kRRJ1) * tk;
+      hipLaunchKernelGGL((k_resrestrict<T, kRRJ1, kRRK1, CB>), xcd_grid(count, per),
+                         dim3(RRGeom<kRRJ1, kRRK1>::THREADS), 0, st, d_list, d_active, buf, tk,
+                         count, per);
+    } else {
+      const int tk = ceil_div(m, kRRK2), per = ceil_div(m, kRRJ2) * tk;
+      hipLaunchKernelGGL((k_resrestrict<T, kRRJ2, kRRK2, CB>), xcd_grid(count, per),
+                         dim3(RRGeom<kRRJ2, kRRK2>::THREADS), 0, st, d_list, d_active, buf, tk,
+                         count, per);
+    }
+  };
+  if (const_b)
+    go(std::true_type{});
+  else
+    go(std::false_type{});
 }
 
 template <typename T>
@@ -1926,7 +1936,8 @@ void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_
                                       hipStream_t);                                             \
   template void launch_residual<T>(const GridDescT<T>*, int, int, const int*, int, hipStream_t); \
   template void launch_restrict<T>(const GridDescT<T>*, int, int, const int*, hipStream_t);      \
-  template void launch_resrestrict<T>(const GridDescT<T>*, int, int, const int*, int, hipStream_t); \
+  template void launch_resrestrict<T>(const GridDescT<T>*, int, int, const int*, int, hipStream_t, \
+                                      bool);                                                      \
   template void launch_coarsest<T>(const GridDescT<T>*, int, const int*, hipStream_t);           \
   template void launch_prolong<T>(const GridDescT<T>*, int, int, const int*, int, int,           \
                                   hipStream_t);                                                 \
