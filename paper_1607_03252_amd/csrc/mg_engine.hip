@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -135,6 +136,7 @@ struct Batch {
   // graphs of c consecutive cycles
   std::map<int, hipGraphExec_t> graphs;
   int last_cycles = 0;
+  bool bnorm_ready = false;  // ||b'|| of every solve computed (constant top rhs)
   void* mem = nullptr;
   size_t bytes = 0;
   std::vector<void*> extra;
@@ -769,14 +771,22 @@ static void build_tail_lists(Batch* B, const std::vector<int>& act) {
 
 // Cycle every solve of the batch until each has converged (or run exactly
 // fixed_cycles).  Returns true when every solve met tol.
-static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graphs) {
+// post: enqueued after every launch of cycles, before the host waits (work
+// that is valid once the last launch is done, e.g. the QoI of stopped solves).
+static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graphs,
+                       const std::function<void()>& post = nullptr) {
   hipStream_t st = B->st;
   launch_init_state2(B->ss, B->d_cycle, B->ns, st);
-  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
-    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
-    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_BNORM, B->ss.partials, st);
-    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, B->d_cycle, 0, fixed,
-                     P->desc.max_cycles, tol, st);
+  // ||b'|| per solve (a constant top right-hand side gives the same norms for
+  // every batch of this workspace)
+  if (!(B->spec.const_b_top && B->bnorm_ready)) {
+    for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+      const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+      launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_BNORM, B->ss.partials, st);
+      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, B->d_cycle, 0, fixed,
+                       P->desc.max_cycles, tol, st);
+    }
+    B->bnorm_ready = B->spec.const_b_top;
   }
   // mixed precision, and top grids judged in the next cycle's first sweep,
   // decide convergence one step late: one extra step
@@ -790,7 +800,7 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
   // the plane march of the few remaining grids over more workgroups
   const bool tail_ok = !B->spec.mixed && !P->prof && P->tail_lists && B->ns >= 4;
   bool in_tail = false;
-  std::vector<int> act(B->ns);
+  std::vector<int> act(B->ns), cyc(B->ns);
   int done = 0, maxc = 0;
   while (done < limit) {
     int c = 1;
@@ -819,11 +829,13 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
       cycle_step(P, B, tol, fixed);
     }
     done += c;
+    if (post) post();
     launch_count_active(B->ss.active, B->ns, B->d_count, st);
     CK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
     if (tail_ok)
       CK(hipMemcpyAsync(act.data(), B->ss.active, sizeof(int) * B->ns, hipMemcpyDeviceToHost,
                         st));
+    CK(hipMemcpyAsync(cyc.data(), B->ss.cycles, sizeof(int) * B->ns, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     const int left = *B->h_count;
     if (left == 0) break;
@@ -832,9 +844,6 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
       in_tail = true;
     }
   }
-  std::vector<int> cyc(B->ns);
-  CK(hipMemcpyAsync(cyc.data(), B->ss.cycles, sizeof(int) * B->ns, hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
   bool ok = *B->h_count == 0;
   for (int c : cyc) {
     if (c < 0) ok = false;
@@ -942,15 +951,18 @@ static int run_samples(mg_plan_s* P, const std::vector<int>& levels, const uint6
   const int n_samples = (int)levels.size();
   setup_samples(P, B, levels, seeds);
   if (fixed_cycles > 0) B->drop_graphs();  // graphs bake in the stopping mode
-  const bool ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0);
-  for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
-    const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
-    launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_QOI, B->ss.partials, st);
-    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI, B->d_cycle, 0, 0, 0, 0.0, st);
-  }
-  launch_ydiff(B->ss.q, B->d_fi, B->d_ci, n_samples, Y_out, Qf_out, Qc_out, B->ss.cycles,
-               cycles_out, st);
-  CK(hipStreamSynchronize(st));
+  // the QoI and Y are enqueued after every launch of cycles: once the solves
+  // have stopped, the host's wait for the last launch covers them too
+  auto qoi = [&]() {
+    for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+      const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
+      launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_QOI, B->ss.partials, st);
+      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI, B->d_cycle, 0, 0, 0, 0.0, st);
+    }
+    launch_ydiff(B->ss.q, B->d_fi, B->d_ci, n_samples, Y_out, Qf_out, Qc_out, B->ss.cycles,
+                 cycles_out, st);
+  };
+  const bool ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0, qoi);
   if (P->prof) collect_profile(P);
   if (!ok) {
     P->err = "some solve missed tol within max_cycles";
