@@ -66,6 +66,9 @@ __device__ __forceinline__ gptr<const T> gview(const T* p) {
 // per-lane byte offsets.  Loads past the range read 0 and stores past it are
 // dropped, which lets a kernel express "outside the grid" by an offset.
 constexpr uint32_t kOut = 0x7ffffff0u;  // an offset past any range used here
+// s_waitcnt immediate (gfx9 encoding) that waits for every vector memory
+// operation and for nothing else: vmcnt 0, expcnt 7, lgkmcnt 15.
+constexpr int kWaitVmem0 = 0x0F70;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
                                            0x00020000);
@@ -412,7 +415,7 @@ struct SweepGeom {
 // spoff >= 0, one partial per workgroup into spart[spoff + workgroup]:
 //   NM = 1: the red points of its input iterate: the red update forms their
 //           D and S from the input values already, only their own input
-//           values are loaded (one plane ahead; the lines are cached);
+//           values are loaded (two planes ahead, in a ring of two);
 //   NM = 2: the black points of its output iterate: a black update's D and S
 //           are those of the residual of the new black value.
 // Red points depend only on black values and vice versa, so the residual of
@@ -574,7 +577,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     }
     ub = bload<T>(ru0, (rb ? offi[1] : offi[0]) + so);
   };
-  // NM = 1: input value of the red role on plane istart + rel
+  // NM = 1: input value of the red role on plane istart + rel, in slot rel & 1
   T UR[2];
   auto load_red = [&](int rel) {
     UR[rel & 1] = bload<T>(ru0, (rel & 1 ? offi[1] : offi[0]) + (uint32_t)(istart + rel) * pbytes);
@@ -626,7 +629,10 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
 
   // prologue: planes istart-1 .. istart+2, the +i face of the red point below
   // plane istart (the black points of plane istart use it), plane istart to LDS
-  if (NM == 1) load_red(0);
+  if (NM == 1) {
+    load_red(0);
+    load_red(1);
+  }
   if (CB) {
     B[0][0] = bload<T>(rb0, offi[0]);
     B[0][1] = bload<T>(rb0, offi[1]);
@@ -659,6 +665,12 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     sW[0][lq[1]] = W[0][1];
   }
   __syncthreads();
+  // All prologue loads are waited for once here.  The compiler sets the
+  // memory waits at the head of the march for the loads pending on both ways
+  // into it: without this wait the prologue's issue order would set them,
+  // and every group of four planes would wait for almost all of its loads
+  // in flight instead of those it uses.
+  __builtin_amdgcn_s_waitcnt(kWaitVmem0);
 
   // one plane, K = (i - istart) mod 4 at compile time
   auto plane = [&](auto kk, int i) {
@@ -727,9 +739,10 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     }
     // loads of plane i+3 (into the ring slot plane i-1 leaves); the next
     // coarse plane to LDS every second plane
-    // (the next red input value first: waiting for it then leaves the
-    // plane loads in flight)
-    if (NM == 1) load_red(i - istart + 1);
+    // (the red input value of plane i+2 first: waiting for it then leaves
+    // the plane loads in flight; two planes ahead, like the black values it
+    // shares its lines with, it has as long to arrive)
+    if (NM == 1) load_red(i - istart + 2);
     load(i - istart + 3, UB[SM], W[SM], B[CB ? 0 : SM]);
     if (PRO) {
       // coarse plane ((i+3)>>1)+1 to LDS (a second store of the same plane
@@ -1242,6 +1255,9 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
   prologue();
   fim = rcp<T>(OW[0] + OW[3]);
   __syncthreads();
+  // prologue loads waited for once (as in the smoother: the waits at the
+  // head of the march then follow the loop's own load order)
+  __builtin_amdgcn_s_waitcnt(kWaitVmem0);
   for (int i = 1; i <= n - 2; i += 4) {
     fine(I0{}, i);
     __syncthreads();
