@@ -504,6 +504,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
 
   // this thread's pair: T2 row r, positions 2*c2 and 2*c2 + 1
   const int t = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const bool live = t < Geo::PAIRS;
   const int r = live ? t / HW : 0, c2 = live ? t - (t / HW) * HW : 0;
   const int j = j0 - 2 + r;
@@ -768,9 +769,12 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     __shared__ T ws[NM ? NW : 1];
     T v = acc;
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((t & 63) == 0) ws[t >> 6] = v;
+    // (lane from the lane counter and wave index from a scalar register: the
+    // thread index then need not stay live through the march)
+    const int lane = __lane_id();
+    if (lane == 0) ws[wave] = v;
     __syncthreads();
-    if (t == 0 && d.spoff >= 0) {
+    if (wave == 0 && lane == 0 && d.spoff >= 0) {
       T sum = 0;
       for (int w = 0; w < NW; ++w) sum += ws[w];
       spart[d.spoff + blk] = sum;
