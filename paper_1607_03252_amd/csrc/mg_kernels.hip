@@ -587,7 +587,9 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   // Coarse correction (PRO): the coarse iterate's planes under the tile are
   // staged in LDS (four slots by plane index mod 4), one value per thread,
   // loaded two planes ahead; the correction of a fine plane is formed from
-  // LDS one plane before its values are first used.
+  // LDS one plane before its values are first used.  A coarse value goes to
+  // LDS two fine planes after its load is issued (two staging registers by
+  // plane parity), so it has as long to arrive as the fine plane loads.
   constexpr int CJM = PRO ? TJ / 2 + 4 : 1, CKM = PRO ? TK / 2 + 4 : 1;
   __shared__ T sC[PRO ? 4 : 1][CJM * CKM];
   const int cj0 = max(j0 - 2, 1) >> 1, ck0 = max(k0 - 2, 1) >> 1;
@@ -595,13 +597,13 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   const int CJ = (min(j0 + TJ + 1, n - 2) >> 1) + 2 - cj0;
   const bool cown = PRO && t < CJ * CK;
   const int crow = cown ? t / CK : 0, ccol = cown ? t - (t / CK) * CK : 0;
-  T cstage = 0, PA[2] = {0, 0};
-  auto c_issue = [&](int C) {
+  T cstage[2] = {0, 0}, PA[2] = {0, 0};
+  auto c_issue = [&](int C, int sl) {
     const int Cc = min(max(C, 0), nc - 1);
-    cstage = ec[(Cc * nc + min(cj0 + crow, nc - 1)) * nc + min(ck0 + ccol, nc - 1)];
+    cstage[sl] = ec[(Cc * nc + min(cj0 + crow, nc - 1)) * nc + min(ck0 + ccol, nc - 1)];
   };
-  auto c_store = [&](int C) {
-    if (cown) sC[C & 3][crow * CKM + ccol] = cstage;
+  auto c_store = [&](int C, int sl) {
+    if (cown) sC[C & 3][crow * CKM + ccol] = cstage[sl];
   };
   // Correction at fine (m, j, kk), zero off the interior, evaluated as the
   // trilinear interpolation is written (prolong_combine): the (j, k) part on
@@ -646,10 +648,11 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   if (PRO) {
     const int clo = max((istart - 1) >> 1, 0), chi = ((istart + 2) >> 1) + 1;
     for (int C = clo; C <= chi; ++C) {
-      c_issue(C);
-      c_store(C);
+      c_issue(C, 0);
+      c_store(C, 0);
     }
-    c_issue(((istart + 3) >> 1) + 1);  // stored at the end of plane istart
+    c_issue(((istart + 3) >> 1) + 1, 0);  // stored at the end of plane istart
+    c_issue(((istart + 4) >> 1) + 1, 1);  // and of plane istart + 1
     __syncthreads();
     // black roles: plane istart-1 -> 0, istart -> 1, istart+1 -> 0
     T P1;
@@ -747,9 +750,9 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     load(i - istart + 3, UB[SM], W[SM], B[CB ? 0 : SM]);
     if (PRO) {
       // coarse plane ((i+3)>>1)+1 to LDS (a second store of the same plane
-      // rewrites identical values), the next one into the staging register
-      c_store(((i + 3) >> 1) + 1);
-      c_issue(((i + 4) >> 1) + 1);
+      // rewrites identical values), the one for plane i+2 into its register
+      c_store(((i + 3) >> 1) + 1, K & 1);
+      c_issue(((i + 5) >> 1) + 1, K & 1);
     }
     __syncthreads();
   };
