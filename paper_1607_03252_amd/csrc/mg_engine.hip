@@ -109,12 +109,12 @@ struct Batch {
   // (device buffers sized for L64 on first use)
   Lists<double> L64t;
   SolveState ss{};
-  int* d_count = nullptr;
   int* d_cycle = nullptr;                          // device cycle counter
-  int* h_count = nullptr;                          // pinned
+  int* h_state = nullptr;  // pinned: active then cycles of every solve (2 ns)
   // MLMC sample plumbing
   int nsamples = 0;
   uint64_t* d_seeds = nullptr;
+  uint64_t* h_seeds = nullptr;  // pinned staging of the seeds (an asynchronous upload)
   double* d_normals = nullptr;
   int* d_levels = nullptr;
   int* d_fi = nullptr;
@@ -157,7 +157,8 @@ struct Batch {
     drop_graphs();
     for (void* p : extra) (void)hipFree(p);
     if (mem) (void)hipFree(mem);
-    if (h_count) (void)hipHostFree(h_count);
+    if (h_state) (void)hipHostFree(h_state);
+    if (h_seeds) (void)hipHostFree(h_seeds);
   }
 };
 
@@ -302,7 +303,7 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
     }
     int npart = 0;
     for (int s = 0; s < ns; ++s) npart += reduce_blocks(spec.top_n[s]);
-    int* ai = (int*)take(sizeof(int) * (ns * 4 + 2));
+    int* ai = (int*)take(sizeof(int) * (ns * 4 + 1));
     double* dd = (double*)take(sizeof(double) * ns * 3);
     double* pp = (double*)take(sizeof(double) * npart);
     double* sp = (double*)take(sizeof(double) * ns * (2 * kSweepParts + 2));
@@ -319,11 +320,10 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
       cur = (char*)B->mem;
     } else {
       B->ss.active = ai;
-      B->ss.cycles = ai + ns;
+      B->ss.cycles = ai + ns;  // (right after active: the host reads both in one copy)
       B->ss.start = ai + 2 * ns;
       B->ss.qpend = ai + 3 * ns;
-      B->d_count = ai + 4 * ns;
-      B->d_cycle = ai + 4 * ns + 1;
+      B->d_cycle = ai + 4 * ns;
       B->ss.relres = dd;
       B->ss.bnorm = dd + ns;
       B->ss.q = dd + 2 * ns;
@@ -331,7 +331,7 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
       B->ss.spart = sp;
     }
   }
-  CK(hipHostMalloc((void**)&B->h_count, sizeof(int), hipHostMallocDefault));
+  CK(hipHostMalloc((void**)&B->h_state, sizeof(int) * 2 * ns, hipHostMallocDefault));
   int nmax = 0;
   for (int n : spec.top_n) nmax = std::max(nmax, n);
   B->sizes = hierarchy(nmax);
@@ -741,7 +741,7 @@ static int tail_cap(const Batch* B) { return std::max(1, B->ns / 4); }
 // B->L64t := per list, the grids of the solves with act[solve] != 0, padded
 // with grids of stopped solves (their kernels exit at once) to a fixed
 // length (min(list length, tail_cap)), so that one graph serves every tail.
-static void build_tail_lists(Batch* B, const std::vector<int>& act) {
+static void build_tail_lists(Batch* B, const int* act) {
   Lists<double>& T = B->L64t;
   const Lists<double>& F = B->L64;
   const size_t cap = (size_t)tail_cap(B);
@@ -800,8 +800,9 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
   // the plane march of the few remaining grids over more workgroups
   const bool tail_ok = !B->spec.mixed && !P->prof && P->tail_lists && B->ns >= 4;
   bool in_tail = false;
-  std::vector<int> act(B->ns), cyc(B->ns);
-  int done = 0, maxc = 0;
+  const int* act = B->h_state;
+  const int* cyc = B->h_state + B->ns;
+  int done = 0, maxc = 0, left = B->ns;
   while (done < limit) {
     int c = 1;
     if (in_tail) {
@@ -830,24 +831,22 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
     }
     done += c;
     if (post) post();
-    launch_count_active(B->ss.active, B->ns, B->d_count, st);
-    CK(hipMemcpyAsync(B->h_count, B->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
-    if (tail_ok)
-      CK(hipMemcpyAsync(act.data(), B->ss.active, sizeof(int) * B->ns, hipMemcpyDeviceToHost,
-                        st));
-    CK(hipMemcpyAsync(cyc.data(), B->ss.cycles, sizeof(int) * B->ns, hipMemcpyDeviceToHost, st));
+    // the active flags and cycle counts of every solve in one copy
+    CK(hipMemcpyAsync(B->h_state, B->ss.active, sizeof(int) * 2 * B->ns, hipMemcpyDeviceToHost,
+                      st));
     CK(hipStreamSynchronize(st));
-    const int left = *B->h_count;
+    left = 0;
+    for (int q = 0; q < B->ns; ++q) left += B->h_state[q] != 0;
     if (left == 0) break;
     if (tail_ok && left <= tail_cap(B) && !in_tail) {
       build_tail_lists(B, act);
       in_tail = true;
     }
   }
-  bool ok = *B->h_count == 0;
-  for (int c : cyc) {
-    if (c < 0) ok = false;
-    maxc = std::max(maxc, c);
+  bool ok = left == 0;
+  for (int q = 0; q < B->ns; ++q) {
+    if (cyc[q] < 0) ok = false;
+    maxc = std::max(maxc, cyc[q]);
   }
   B->last_cycles = maxc + extra;
   return ok;
@@ -900,6 +899,8 @@ static void setup_samples(mg_plan_s* P, Batch* B, const std::vector<int>& levels
     upload_lists(P, B);
     B->nsamples = n_samples;
     B->d_seeds = (uint64_t*)B->dalloc(sizeof(uint64_t) * n_samples);
+    if (B->h_seeds) CK(hipHostFree(B->h_seeds));
+    CK(hipHostMalloc((void**)&B->h_seeds, sizeof(uint64_t) * n_samples, hipHostMallocDefault));
     B->d_levels = (int*)B->dalloc(sizeof(int) * n_samples);
     B->d_normals = (double*)B->dalloc(sizeof(double) * 64 * n_samples);
     std::vector<int> fi(n_samples), ci(n_samples);
@@ -928,7 +929,11 @@ static void setup_samples(mg_plan_s* P, Batch* B, const std::vector<int>& levels
       B->fields.push_back(g);
     }
   }
-  CK(hipMemcpyAsync(B->d_seeds, seeds, sizeof(uint64_t) * n_samples, hipMemcpyHostToDevice, st));
+  // (the previous batch's upload from the staging buffer finished before that
+  // batch returned)
+  std::memcpy(B->h_seeds, seeds, sizeof(uint64_t) * n_samples);
+  CK(hipMemcpyAsync(B->d_seeds, B->h_seeds, sizeof(uint64_t) * n_samples, hipMemcpyHostToDevice,
+                    st));
   launch_philox(B->d_seeds, n_samples, 0, nullptr, B->d_normals, st, B->d_levels);
   for (const auto& g : B->fields)
     launch_field(g.n, g.count, g.d_out, g.d_xi, B->d_normals, phi_table(P, g.n), P->d_coef, 0, st);

@@ -191,7 +191,6 @@ void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st);
 void launch_admit(const int* d_solves, int count, SolveState s, const int* cycle_ctr,
                   hipStream_t st);
 void launch_tick(int* ctr, hipStream_t st);
-void launch_count_active(const int* d_active, int nsolves, int* d_count, hipStream_t st);
 void launch_ydiff(const double* d_q, const int* d_fine_idx, const int* d_coarse_idx, int count,
                   double* d_y, double* d_qf, double* d_qc, const int* d_cycles, int* d_cycles_out,
                   hipStream_t st);

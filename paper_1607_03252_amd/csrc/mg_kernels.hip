@@ -1654,14 +1654,6 @@ __global__ void k_tick(int* __restrict__ ctr) {
   if (threadIdx.x == 0) *ctr += 1;
 }
 
-__global__ void __launch_bounds__(kBlock) k_count_active(const int* __restrict__ active, int ns,
-                                                         int* __restrict__ count) {
-  double c = 0.0;
-  for (int q = threadIdx.x; q < ns; q += kBlock) c += (double)active[q];
-  c = block_sum(c);
-  if (threadIdx.x == 0) *count = (int)c;
-}
-
 __global__ void k_ydiff(const double* __restrict__ q, const int* __restrict__ fi,
                         const int* __restrict__ ci, int count, double* __restrict__ y,
                         double* __restrict__ qf, double* __restrict__ qc,
@@ -2034,10 +2026,6 @@ void launch_admit(const int* d_solves, int count, SolveState s, const int* cycle
 
 void launch_tick(int* ctr, hipStream_t st) {
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, ctr);
-}
-
-void launch_count_active(const int* d_active, int nsolves, int* d_count, hipStream_t st) {
-  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(kBlock), 0, st, d_active, nsolves, d_count);
 }
 
 void launch_ydiff(const double* d_q, const int* d_fi, const int* d_ci, int count, double* d_y,
