@@ -1378,6 +1378,25 @@ struct SmallGeo {
 template <int L>
 using IC = std::integral_constant<int, L>;
 
+// Item q of a pass over a level with m interior points per axis, dealt to the
+// threads as q = t + r * kSmallThreads: the point (i, jj, k) of a colour pass
+// of colour c (k > m: no point) and of a pass over every interior point.
+template <int m>
+__device__ __forceinline__ void vs_colour_point(int c, int q, int& i, int& jj, int& k) {
+  constexpr int hk = (m + 1) / 2;
+  i = q / (m * hk) + 1;
+  const int rr = q % (m * hk);
+  jj = rr / hk + 1;
+  k = 2 - ((c + i + jj) & 1) + 2 * (rr % hk);
+}
+template <int m>
+__device__ __forceinline__ void vs_point(int q, int& i, int& jj, int& k) {
+  i = q / (m * m) + 1;
+  const int rr = q % (m * m);
+  jj = rr / m + 1;
+  k = rr % m + 1;
+}
+
 template <typename T, int NS>
 __global__ void __launch_bounds__(kSmallThreads) k_vsmall(const SmallChain<T>* __restrict__ chains,
                                                           const int* __restrict__ active,
@@ -1390,6 +1409,32 @@ __global__ void __launch_bounds__(kSmallThreads) k_vsmall(const SmallChain<T>* _
   if (!active[top.solve]) return;
   const int t = threadIdx.x;
 
+  // The top level's right-hand side stays in memory (LDS holds u, wh and r of
+  // every level): the values of this thread's points in the top level's
+  // colour passes and residual pass are read once, here, into registers.
+  constexpr int kM0 = NS - 2, kColQ = kM0 * kM0 * ((kM0 + 1) / 2), kResQ = kM0 * kM0 * kM0;
+  constexpr int kColR = (kColQ + kSmallThreads - 1) / kSmallThreads;
+  constexpr int kResR = (kResQ + kSmallThreads - 1) / kSmallThreads;
+  T b0c[2][kColR], b0r[kResR];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int r = 0; r < kColR; ++r) {
+      const int q = t + r * kSmallThreads;
+      int i, jj, k;
+      vs_colour_point<kM0>(c, q, i, jj, k);
+      b0c[c][r] = 0;
+      if (q < kColQ && k <= kM0) b0c[c][r] = b_at<T>(top, i, jj, k);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kResR; ++r) {
+    const int q = t + r * kSmallThreads;
+    int i, jj, k;
+    vs_point<kM0>(q, i, jj, k);
+    b0r[r] = 0;
+    if (q < kResQ) b0r[r] = b_at<T>(top, i, jj, k);
+  }
   // load wh of every level and u of the top level; coarse u and every r = 0
   for (int j = 0; j <= J; ++j) {
     const int v = Geo::vol(j);
@@ -1402,41 +1447,51 @@ __global__ void __launch_bounds__(kSmallThreads) k_vsmall(const SmallChain<T>* _
   }
   __syncthreads();
 
-  // every level's size is a compile-time constant below, so the index
-  // arithmetic needs no division
-  auto bval = [&](auto lvl, int i, int jj, int k) -> T {
-    constexpr int Lv = decltype(lvl)::value, n = Geo::n(Lv);
-    if constexpr (Lv == 0) return b_at<T>(top, i, jj, k);
-    else return lds[Geo::off_b(Lv) + (i * n + jj) * n + k];
-  };
+  // (every level's size is a compile-time constant below, so the index
+  // arithmetic needs no division)
   // one colour pass on level L (in place), over the points of that colour only
-  auto colour = [&](auto lvl, int c) {
-    constexpr int Lv = decltype(lvl)::value, n = Geo::n(Lv), m = n - 2, hk = (m + 1) / 2;
+  auto colour = [&](auto lvl, auto cc) {
+    constexpr int Lv = decltype(lvl)::value, c = decltype(cc)::value;
+    constexpr int n = Geo::n(Lv), m = n - 2, NQ = m * m * ((m + 1) / 2);
     T* u = lds + Geo::off_u(Lv);
     const T* w = lds + Geo::off_w(Lv);
-    for (int q = t; q < m * m * hk; q += kSmallThreads) {
-      const int i = q / (m * hk) + 1, rr = q % (m * hk), jj = rr / hk + 1;
-      const int k = 2 - ((c + i + jj) & 1) + 2 * (rr % hk);
-      if (k > m) continue;
-      const int p = (i * n + jj) * n + k;
-      u[p] = gs_value<T>(stencil_at<T>(u, w, p, n, n * n), bval(lvl, i, jj, k));
+#pragma unroll
+    for (int r = 0; r < (NQ + kSmallThreads - 1) / kSmallThreads; ++r) {
+      const int q = t + r * kSmallThreads;
+      int i, jj, k;
+      vs_colour_point<m>(c, q, i, jj, k);
+      if (q < NQ && k <= m) {
+        const int p = (i * n + jj) * n + k;
+        T bv;
+        if constexpr (Lv == 0) bv = b0c[c][r];
+        else bv = lds[Geo::off_b(Lv) + p];
+        u[p] = gs_value<T>(stencil_at<T>(u, w, p, n, n * n), bv);
+      }
     }
     __syncthreads();
   };
   auto down = [&](auto lvl) {
-    constexpr int Lv = decltype(lvl)::value, n = Geo::n(Lv), m = n - 2;
+    constexpr int Lv = decltype(lvl)::value, n = Geo::n(Lv), m = n - 2, NQ = m * m * m;
     for (int s = 0; s < nu1; ++s) {
-      colour(lvl, 0);
-      colour(lvl, 1);
+      colour(lvl, IC<0>{});
+      colour(lvl, IC<1>{});
     }
     // residual of this level, then full weighting into b of the next
     const T* u = lds + Geo::off_u(Lv);
     const T* w = lds + Geo::off_w(Lv);
     T* r = lds + Geo::off_r(Lv);
-    for (int q = t; q < m * m * m; q += kSmallThreads) {
-      const int i = q / (m * m) + 1, rr = q % (m * m), jj = rr / m + 1, k = rr % m + 1;
-      const int p = (i * n + jj) * n + k;
-      r[p] = res_value<T>(stencil_at<T>(u, w, p, n, n * n), bval(lvl, i, jj, k), u[p]);
+#pragma unroll
+    for (int ri = 0; ri < (NQ + kSmallThreads - 1) / kSmallThreads; ++ri) {
+      const int q = t + ri * kSmallThreads;
+      int i, jj, k;
+      vs_point<m>(q, i, jj, k);
+      if (q < NQ) {
+        const int p = (i * n + jj) * n + k;
+        T bv;
+        if constexpr (Lv == 0) bv = b0r[ri];
+        else bv = lds[Geo::off_b(Lv) + p];
+        r[p] = res_value<T>(stencil_at<T>(u, w, p, n, n * n), bv, u[p]);
+      }
     }
     __syncthreads();
     constexpr int nc = Geo::n(Lv + 1), mc = nc - 2;
@@ -1466,8 +1521,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_vsmall(const SmallChain<T>* _
     }
     __syncthreads();
     for (int s = 0; s < nu2; ++s) {
-      colour(lvl, 0);
-      colour(lvl, 1);
+      colour(lvl, IC<0>{});
+      colour(lvl, IC<1>{});
     }
   };
 
