@@ -95,6 +95,23 @@ __device__ __forceinline__ void bstore<float>(__amdgpu_buffer_rsrc_t r, uint32_t
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
 }
 
+// Two consecutive elements in one load (16 bytes for double): offsets need
+// only the alignment of one element (8 bytes, a multiple of the dword).
+template <typename T>
+struct Two {
+  T lo, hi;
+};
+template <typename T>
+__device__ __forceinline__ Two<T> bload2(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ Two<double> bload2<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(Two<double>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ Two<float> bload2<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(Two<float>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 // Interior point of block `bid` of a grid with m = n-2 interior points per
 // axis: blocks cover (plane i, 4 rows j, 64 columns k).
 struct Pt {
@@ -414,8 +431,8 @@ struct SweepGeom {
 // NM: the sweep also sums squared residuals over its tile, for grids with
 // spoff >= 0, one partial per workgroup into spart[spoff + workgroup]:
 //   NM = 1: the red points of its input iterate: the red update forms their
-//           D and S from the input values already, only their own input
-//           values are loaded (two planes ahead, in a ring of two);
+//           D and S from the input values already; their own input values
+//           come with the black ones (one load of both positions of a pair);
 //   NM = 2: the black points of its output iterate: a black update's D and S
 //           are those of the residual of the new black value.
 // Red points depend only on black values and vice versa, so the residual of
@@ -566,19 +583,45 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   const auto rw0 = rsrc(d.wh, gbytes), rb0 = rsrc(d.b, bs ? gbytes : pbytes);
   const auto ru0 = rsrc(buf ? d.u[1] : d.u[0], gbytes);
   const T* const uout = buf ? d.u[0] : d.u[1];
-  auto load = [&](int rel, T& ub, T (&w)[2], T (&b)[2]) {
+  // NM = 1: u_in of both positions of the pair in one load (the black one
+  // feeds the red update, the red one the residual of the input), kept in
+  // position order and picked by role where used.  The pair starts at an odd
+  // k; a pair reaching out of the grid on the left (k = -1) reads the last
+  // value of the previous row there (a boundary value, zero like the values
+  // outside the grid), and the pair (-1, 0) of row 0 is not loaded (both
+  // positions are boundary or outside).
+  constexpr bool PL = NM == 1 && !CB;  // (see below)
+  T UP[PL ? 4 : 1][2];
+  const bool pin = live && j >= 0 && j < n && kA <= n - 2 && (kA >= 0 || j >= 1);
+  const uint32_t offp = pin ? (uint32_t)((j * n + kA) * (int)sizeof(T)) : kOut;
+  // this slot's (plane istart + rel, rel = sl mod 4) u_in of role rho
+  auto u_role = [&](int sl, int rho) -> T { return (rho ^ sw) ? UP[sl][1] : UP[sl][0]; };
+  auto load = [&](int rel, int sl) {
     // planes past the grid are past the range and read 0
     const int m = istart + rel;
     const uint32_t so = (uint32_t)m * pbytes, sob = bs ? so : 0u;
     const int rb = (rel + 1) & 1;
 #pragma unroll
     for (int rho = 0; rho < 2; ++rho) {
-      w[rho] = bload<T>(rw0, offi[rho] + so);
-      if (!CB) b[rho] = bload<T>(rb0, offi[rho] + sob);
+      W[sl][rho] = bload<T>(rw0, offi[rho] + so);
+      if (!CB) B[CB ? 0 : sl][rho] = bload<T>(rb0, offi[rho] + sob);
     }
-    ub = bload<T>(ru0, (rb ? offi[1] : offi[0]) + so);
+    if constexpr (PL) {
+      const Two<T> v = bload2<T>(ru0, offp + so);
+      UP[sl][0] = v.lo;
+      UP[sl][1] = v.hi;
+    } else {
+      UB[sl] = bload<T>(ru0, (rb ? offi[1] : offi[0]) + so);
+    }
   };
-  // NM = 1: input value of the red role on plane istart + rel, in slot rel & 1
+  // u_in of the black role on the plane in slot sl
+  auto ubv = [&](int sl) -> T {
+    if constexpr (PL) return u_role(sl, (sl + 1) & 1);
+    else return UB[sl];
+  };
+  // NM = 1 with a constant right-hand side (held to the plain sweep's
+  // registers, which the pair ring does not fit): the red role's input
+  // value loaded on its own, two planes ahead, in slot rel & 1
   T UR[2];
   auto load_red = [&](int rel) {
     UR[rel & 1] = bload<T>(ru0, (rel & 1 ? offi[1] : offi[0]) + (uint32_t)(istart + rel) * pbytes);
@@ -632,18 +675,18 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
 
   // prologue: planes istart-1 .. istart+2, the +i face of the red point below
   // plane istart (the black points of plane istart use it), plane istart to LDS
-  if (NM == 1) {
-    load_red(0);
-    load_red(1);
-  }
   if (CB) {
     B[0][0] = bload<T>(rb0, offi[0]);
     B[0][1] = bload<T>(rb0, offi[1]);
   }
-  load(-1, UB[3], W[3], B[CB ? 0 : 3]);
-  load(0, UB[0], W[0], B[0]);
-  load(1, UB[1], W[1], B[CB ? 0 : 1]);
-  load(2, UB[2], W[2], B[CB ? 0 : 2]);
+  if (NM == 1 && !PL) {
+    load_red(0);
+    load_red(1);
+  }
+  load(-1, 3);
+  load(0, 0);
+  load(1, 1);
+  load(2, 2);
   T acc = 0;  // NM: this thread's sum of squared residuals
   if (PRO) {
     const int clo = max((istart - 1) >> 1, 0), chi = ((istart + 2) >> 1) + 1;
@@ -665,7 +708,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   FIP[1] = rcp<T>(W[3][1] + W[0][1]);  // plane istart-1 is red in role 1
   FIP[0] = 0;
   if (live) {
-    sU[0][lq[1]] = UB[0];
+    sU[0][lq[1]] = ubv(0);
     sW[0][lq[1]] = W[0][1];
   }
   __syncthreads();
@@ -695,12 +738,12 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     const T fim = rcp<T>(wc + W[SM][RHO]), fip = rcp<T>(wc + W[SP][RHO]);
     const T fjm = rcp<T>(wc + Wl[qc - DJ]), fjp = rcp<T>(wc + Wl[qc + DJ]);
     const T fkm = rcp<T>(wc + Wl[qm]), fkp = rcp<T>(wc + Wl[qp]);
-    const St<T> sr = stencil_faces<T>(fim, fip, fjm, fjp, fkm, fkp, UB[SM], UB[SP], Ul[qc - DJ],
+    const St<T> sr = stencil_faces<T>(fim, fip, fjm, fjp, fkm, fkp, ubv(SM), ubv(SP), Ul[qc - DJ],
                                       Ul[qc + DJ], Ul[qm], Ul[qp]);
     const T vr = gs_value<T>(sr, bv(S0, RHO));
     NR[S0] = (t1[RHO] && intr[RHO] && i <= n - 2) ? vr : (T)0;
     if (NM == 1) {
-      const T rr = res_value<T>(sr, bv(S0, RHO), UR[K & 1]);
+      const T rr = res_value<T>(sr, bv(S0, RHO), PL ? u_role(S0, RHO) : UR[K & 1]);
       acc += (tl[RHO] && i >= ia && i <= ib) ? rr * rr : (T)0;
     }
     // black point of plane p = i - 1 (the column that is red on plane i)
@@ -738,16 +781,13 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
       sFk[PB][qc] = fkp;
     }
     if (live) {
-      sU[PBM][lq[RHO]] = UB[SP];
+      sU[PBM][lq[RHO]] = ubv(SP);
       sW[PBM][lq[RHO]] = W[SP][RHO];
     }
     // loads of plane i+3 (into the ring slot plane i-1 leaves); the next
     // coarse plane to LDS every second plane
-    // (the red input value of plane i+2 first: waiting for it then leaves
-    // the plane loads in flight; two planes ahead, like the black values it
-    // shares its lines with, it has as long to arrive)
-    if (NM == 1) load_red(i - istart + 2);
-    load(i - istart + 3, UB[SM], W[SM], B[CB ? 0 : SM]);
+    if (NM == 1 && !PL) load_red(i - istart + 2);
+    load(i - istart + 3, SM);
     if (PRO) {
       // coarse plane ((i+3)>>1)+1 to LDS (a second store of the same plane
       // rewrites identical values), the one for plane i+2 into its register
