@@ -562,7 +562,21 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   // red point's +i face, read two planes later) and PA mod 2
   T UB[4], W[4][2], B[CB ? 1 : 4][2], NR[4], FIP[2];
   // right-hand side at this thread's positions on the plane in ring slot sl
-  auto bv = [&](int sl, int rho) -> T { return CB ? B[0][rho] : B[CB ? 0 : sl][rho]; };
+  // With PW, W and (a full right-hand side) B hold a pair's two positions in
+  // position order (one load each), else in role order (one load per role);
+  // these pick role rho's value.  (The sweeps held to four waves per SIMD
+  // keep the role loads: the selects' registers do not fit their budget;
+  // the sweep with the coarse correction measured slower with pairs.)
+  constexpr bool PW = (NM == 0 && !PRO) || (NM == 1 && !CB);
+  auto bv = [&](int sl, int rho) -> T {
+    if constexpr (CB) return B[0][rho];
+    else if constexpr (PW) return (rho ^ sw) ? B[sl][1] : B[sl][0];
+    else return B[sl][rho];
+  };
+  auto w_role = [&](int sl, int rho) -> T {
+    if constexpr (PW) return (rho ^ sw) ? W[sl][1] : W[sl][0];
+    else return W[sl][rho];
+  };
   // plane m = istart + rel: black role (rel + 1) & 1
   // byte offsets within a plane of this thread's two columns (past the plane
   // for positions outside the grid, which then read 0), and of its outputs
@@ -583,13 +597,15 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   const auto rw0 = rsrc(d.wh, gbytes), rb0 = rsrc(d.b, bs ? gbytes : pbytes);
   const auto ru0 = rsrc(buf ? d.u[1] : d.u[0], gbytes);
   const T* const uout = buf ? d.u[0] : d.u[1];
-  // NM = 1: u_in of both positions of the pair in one load (the black one
-  // feeds the red update, the red one the residual of the input), kept in
-  // position order and picked by role where used.  The pair starts at an odd
-  // k; a pair reaching out of the grid on the left (k = -1) reads the last
-  // value of the previous row there (a boundary value, zero like the values
-  // outside the grid), and the pair (-1, 0) of row 0 is not loaded (both
-  // positions are boundary or outside).
+  // wh (and a full right-hand side) of both positions of the pair come in one
+  // 16-byte load, kept in position order and picked by role where used; with
+  // NM = 1 and a full right-hand side u_in too (the black value feeds the red
+  // update, the red one the residual of the input).  The pair starts at an
+  // odd k; a pair reaching out of the grid on the left (k = -1) reads the
+  // last values of the previous row there (where the outside used to read
+  // zero: those positions feed only results that are masked or dropped, and
+  // u there is a boundary zero either way), and the pair (-1, 0) of row 0 is
+  // not loaded (both positions are boundary or outside).
   constexpr bool PL = NM == 1 && !CB;  // (see below)
   T UP[PL ? 4 : 1][2];
   const bool pin = live && j >= 0 && j < n && kA <= n - 2 && (kA >= 0 || j >= 1);
@@ -601,10 +617,21 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     const int m = istart + rel;
     const uint32_t so = (uint32_t)m * pbytes, sob = bs ? so : 0u;
     const int rb = (rel + 1) & 1;
+    if constexpr (PW) {
+      const Two<T> wv = bload2<T>(rw0, offp + so);
+      W[sl][0] = wv.lo;
+      W[sl][1] = wv.hi;
+      if constexpr (!CB) {
+        const Two<T> bb = bload2<T>(rb0, offp + sob);
+        B[sl][0] = bb.lo;
+        B[sl][1] = bb.hi;
+      }
+    } else {
 #pragma unroll
-    for (int rho = 0; rho < 2; ++rho) {
-      W[sl][rho] = bload<T>(rw0, offi[rho] + so);
-      if (!CB) B[CB ? 0 : sl][rho] = bload<T>(rb0, offi[rho] + sob);
+      for (int rho = 0; rho < 2; ++rho) {
+        W[sl][rho] = bload<T>(rw0, offi[rho] + so);
+        if (!CB) B[CB ? 0 : sl][rho] = bload<T>(rb0, offi[rho] + sob);
+      }
     }
     if constexpr (PL) {
       const Two<T> v = bload2<T>(ru0, offp + so);
@@ -705,11 +732,11 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   }
   NR[3] = 0;
   NR[2] = 0;
-  FIP[1] = rcp<T>(W[3][1] + W[0][1]);  // plane istart-1 is red in role 1
+  FIP[1] = rcp<T>(w_role(3, 1) + w_role(0, 1));  // plane istart-1 is red in role 1
   FIP[0] = 0;
   if (live) {
     sU[0][lq[1]] = ubv(0);
-    sW[0][lq[1]] = W[0][1];
+    sW[0][lq[1]] = w_role(0, 1);
   }
   __syncthreads();
   // All prologue loads are waited for once here.  The compiler sets the
@@ -732,10 +759,10 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
       PA[K & 1] = pa_from(i + 2, kc[1 - RHO], intr[1 - RHO], PJ[1 - RHO], PJ[1 - RHO]);  // i+2
     }
     // red point of plane i
-    const T wc = W[S0][RHO];
+    const T wc = w_role(S0, RHO);
     const T* Wl = sW[PB];
     const T* Ul = sU[PB];
-    const T fim = rcp<T>(wc + W[SM][RHO]), fip = rcp<T>(wc + W[SP][RHO]);
+    const T fim = rcp<T>(wc + w_role(SM, RHO)), fip = rcp<T>(wc + w_role(SP, RHO));
     const T fjm = rcp<T>(wc + Wl[qc - DJ]), fjp = rcp<T>(wc + Wl[qc + DJ]);
     const T fkm = rcp<T>(wc + Wl[qm]), fkp = rcp<T>(wc + Wl[qp]);
     const St<T> sr = stencil_faces<T>(fim, fip, fjm, fjp, fkm, fkp, ubv(SM), ubv(SP), Ul[qc - DJ],
@@ -782,7 +809,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     }
     if (live) {
       sU[PBM][lq[RHO]] = ubv(SP);
-      sW[PBM][lq[RHO]] = W[SP][RHO];
+      sW[PBM][lq[RHO]] = w_role(SP, RHO);
     }
     // loads of plane i+3 (into the ring slot plane i-1 leaves); the next
     // coarse plane to LDS every second plane
