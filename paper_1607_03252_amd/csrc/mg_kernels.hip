@@ -406,11 +406,14 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int n, const double* __restr
 // ones from the same thread's registers, the four in-plane ones through LDS),
 // so a black point needs no reciprocal but 1/D.  A red update reads no old
 // value of its own and a black update reads no old values at all, so only
-// the black position of each pair is loaded from u_in.
+// the black position of each pair is needed from u_in (the input-residual
+// sweep also needs the red one).
 //
 // Registers hold, per plane, in rings of four indexed by plane offset from
 // istart (the march is unrolled by four, so no value moves): the black
-// u_in, wh and b of both roles, the new red value and the red point's +i face.
+// u_in, wh and b of both positions of the pair (one 16-byte load each where
+// the register budget allows, else one load per role), the new red value and
+// the red point's +i face.
 // The loads of plane i+3 are issued at the end of plane i.  LDS holds, per
 // plane parity: u_in and wh of black positions (for red neighbours), the new
 // red values and the +j / +k faces (for black points), so each plane needs a
