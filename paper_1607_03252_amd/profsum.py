@@ -38,10 +38,15 @@ SWEEP_END = b"// ---- point kernels"
 
 def source_hash(path=KERNEL_SOURCE):
     """SHA-256 of the device code the fused sweep is built from: the kernel
-    source up to the end of the sweep kernel (its helpers and the kernel)."""
+    source up to the end of the sweep kernel (its helpers and the kernel),
+    with comments and blank space removed, so that an edit of the comments
+    alone does not invalidate counters taken on the same code."""
     with open(path, "rb") as f:
-        src = f.read()
-    return hashlib.sha256(src.split(SWEEP_END, 1)[0]).hexdigest()
+        src = f.read().split(SWEEP_END, 1)[0].decode()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()
 
 
 def short_name(s):
