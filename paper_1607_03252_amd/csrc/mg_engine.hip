@@ -772,11 +772,12 @@ static void build_tail_lists(Batch* B, const int* act) {
 // Cycle every solve of the batch until each has converged (or run exactly
 // fixed_cycles).  Returns true when every solve met tol.
 // post: enqueued after every launch of cycles, before the host waits (work
-// that is valid once the last launch is done, e.g. the QoI of stopped solves).
+// that is valid once the last launch is done, e.g. the QoI of stopped solves);
+// qpend: the initial QoI-pending flag of every solve.
 static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graphs,
-                       const std::function<void()>& post = nullptr) {
+                       const std::function<void()>& post = nullptr, int qpend = 0) {
   hipStream_t st = B->st;
-  launch_init_state2(B->ss, B->d_cycle, B->ns, st);
+  launch_init_state2(B->ss, B->d_cycle, B->ns, st, qpend);
   // ||b'|| per solve (a constant top right-hand side gives the same norms for
   // every batch of this workspace)
   if (!(B->spec.const_b_top && B->bnorm_ready)) {
@@ -957,17 +958,26 @@ static int run_samples(mg_plan_s* P, const std::vector<int>& levels, const uint6
   setup_samples(P, B, levels, seeds);
   if (fixed_cycles > 0) B->drop_graphs();  // graphs bake in the stopping mode
   // the QoI and Y are enqueued after every launch of cycles: once the solves
-  // have stopped, the host's wait for the last launch covers them too
-  auto qoi = [&]() {
+  // have stopped, the host's wait for the last launch covers them too.  Each
+  // solve's QoI is taken once, after the launch in which it stopped (its
+  // iterate does not change afterwards); Y is formed again each time.
+  auto qoi = [&](int mode) {
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
       const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
-      launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_QOI, B->ss.partials, st);
-      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI, B->d_cycle, 0, 0, 0, 0.0, st);
+      launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, mode, B->ss.partials, st,
+                    B->ss.qpend);
+      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, mode, B->d_cycle, 0, 0, 0, 0.0, st);
     }
     launch_ydiff(B->ss.q, B->d_fi, B->d_ci, n_samples, Y_out, Qf_out, Qc_out, B->ss.cycles,
                  cycles_out, st);
   };
-  const bool ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0, qoi);
+  const bool ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0,
+                             [&]() { qoi(RED_QOI_PENDING); }, 1);
+  if (!ok) {
+    // solves that missed tol never stopped: their QoI from the last iterate
+    qoi(RED_QOI);
+    CK(hipStreamSynchronize(st));
+  }
   if (P->prof) collect_profile(P);
   if (!ok) {
     P->err = "some solve missed tol within max_cycles";

@@ -1754,14 +1754,14 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
   }
 }
 
-__global__ void k_init_state(SolveState s, int* __restrict__ cycle_ctr, int ns) {
+__global__ void k_init_state(SolveState s, int* __restrict__ cycle_ctr, int ns, int qpend) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) *cycle_ctr = 0;
   if (t >= ns) return;
   s.active[t] = 1;
   s.cycles[t] = 0;
   s.start[t] = 0;
-  s.qpend[t] = 0;
+  s.qpend[t] = qpend;
 }
 
 __global__ void k_admit(const int* __restrict__ solves, int count, SolveState s,
@@ -2138,8 +2138,9 @@ void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
                      fixed_cycles, max_cycles, tol, sweep_parts, sweep_parts_red);
 }
 
-void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_state, dim3((ns + 255) / 256), dim3(256), 0, st, s, cycle_ctr, ns);
+void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st, int qpend) {
+  hipLaunchKernelGGL(k_init_state, dim3((ns + 255) / 256), dim3(256), 0, st, s, cycle_ctr, ns,
+                     qpend);
 }
 
 void launch_admit(const int* d_solves, int count, SolveState s, const int* cycle_ctr,
