@@ -1882,7 +1882,7 @@ SweepShape default_sweep_shape(int n, bool fused_correction, bool single) {
   } else {
     if (n >= 129) return {16, 32, 0};
     if (n == 65) return fused_correction ? SweepShape{16, 32, 0} : SweepShape{8, 64, 0};
-    if (n == 33) return fused_correction ? SweepShape{8, 16, 0} : SweepShape{16, 16, 0};
+    if (n == 33) return fused_correction ? SweepShape{8, 32, 0} : SweepShape{16, 16, 0};
   }
   if (n - 1 >= 16) return {8, 16, 0};
   if (n - 1 >= 8) return {8, 8, 0};
