@@ -232,3 +232,81 @@ def test_initial_guess_boundary_is_forced_to_zero():
     assert np.all(u[0] == 0)
     # both iterates solve the same system to 1e-12: they agree far below the QoI scale
     assert np.max(np.abs(u - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+
+def _series_conductivity(k_of_x, a, b):
+    """Effective conductivity of the segment [a, b] of a 1D medium k(x): the
+    steady flux per unit gradient, (b - a) / int_a^b dx / k(x), with the
+    integral taken by adaptive quadrature (layers in series)."""
+    import scipy.integrate
+    mid = 0.5 * (a + b)
+    inv, _ = scipy.integrate.quad(lambda x: 1.0 / k_of_x(x), a, b, points=[mid],
+                                  epsabs=0.0, epsrel=1e-13)
+    return (b - a) / inv
+
+
+def test_face_coefficient_is_series_conductance_of_two_half_edges():
+    """Section 3, eq. (modweak): the flux k grad u across the face between two
+    vertices.  With k_p on the half-edge at p and k_q on the half-edge at q,
+    the exact flux of the 1D two-layer problem fixes the face coefficient;
+    the h^2-scaled operator's off-diagonal entry is minus that effective
+    conductivity and its diagonal the sum over the six faces.  High-contrast
+    vertex values (1e-2 .. 1e2) make any other mean (arithmetic, geometric)
+    fail."""
+    n = 5
+    h = 1.0 / (n - 1)
+    rng = np.random.Generator(np.random.PCG64(7))
+    k = np.exp(rng.uniform(np.log(1e-2), np.log(1e2), size=(n, n, n)))
+    steps = [(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+
+    def ceff(p, q):
+        kp, kq = k[p], k[q]
+        return _series_conductivity(lambda x: kp if x < 0.5 * h else kq, 0.0, h)
+
+    for p in [(2, 2, 2), (1, 2, 3)]:
+        diag = 0.0
+        for d in steps:
+            q = tuple(a + b for a, b in zip(p, d))
+            c = ceff(p, q)
+            diag += c
+            if min(q) >= 1 and max(q) <= n - 2:
+                e = np.zeros((n, n, n))
+                e[q] = 1.0
+                assert O.apply(k, e)[p] == pytest.approx(-c, rel=1e-12, abs=0.0)
+        # faces toward the boundary enter the diagonal with the boundary vertex's k
+        e = np.zeros((n, n, n))
+        e[p] = 1.0
+        assert O.apply(k, e)[p] == pytest.approx(diag, rel=1e-12, abs=0.0)
+
+
+def test_layered_high_contrast_exact_flux_solution():
+    """A medium layered in x: k = 1e-3 up to x = 1/2 + h/2 (the vertex at 1/2
+    and the half-edge beyond it), k = 1 beyond.  The exact solution of
+    -(k u')' = 0 with constant flux F has u(x_{i+1}) - u(x_i) = F int dx/k over
+    the edge (quadrature).  Sampled at the vertices and constant in y, z, it
+    must satisfy the h^2-scaled equations exactly in every row whose y, z
+    neighbours are interior and whose x neighbours carry the exact values,
+    including the two rows at the interface; an arithmetic face mean gives a
+    residual of the order of the flux there."""
+    n = 9
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    xi_if = 0.5 + 0.5 * h
+
+    def kx(s):
+        return 1e-3 if s < xi_if else 1.0
+
+    F = 1.0
+    u = np.zeros(n)
+    for i in range(n - 1):
+        u[i + 1] = u[i] + F * h / _series_conductivity(kx, x[i], x[i + 1])
+    k = np.broadcast_to(np.array([kx(s) for s in x])[:, None, None], (n, n, n)).copy()
+    U = np.broadcast_to(u[:, None, None], (n, n, n)).copy()
+    Au = O.apply(k, U)
+    # rows i = 1..n-3 (i = n-2 has the boundary vertex, where u is forced to 0,
+    # as a neighbour), j and k away from the y and z boundaries
+    rows = Au[1:n - 2, 2:n - 2, 2:n - 2]
+    assert np.max(np.abs(rows)) <= 1e-12 * F * h
+    # the interface rows are really exercised: their two x fluxes are non-zero
+    assert abs(u[5] - u[4]) > 100 * abs(u[6] - u[5])

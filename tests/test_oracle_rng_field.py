@@ -184,3 +184,36 @@ def test_field_pointwise_variance():
     # sample variance of a Gaussian: sd = var * sqrt(2/S)
     assert np.all(np.abs(var - var_expected) < 5 * var_expected * math.sqrt(2.0 / S))
     assert np.all(np.abs(Z.mean(axis=0)) < 5 * np.sqrt(var_expected / S))
+
+
+def test_box_muller_pairs_radius_and_angle():
+    """The normals come in Box-Muller pairs built from two uniforms of the same
+    sample: (xi_2p, xi_2p+1) = R (cos a, sin a) with R^2 = -2 ln U_2p and
+    a = 2 pi U_2p+1.  The uniforms come from the oracle's 53-bit integers,
+    U = (M + 1) 2^-53, so both identities pin the pairing (which uniform is the
+    radius, which the angle, cos on the even and sin on the odd index) beyond
+    what the marginal moments can see."""
+    for seed, level in [(0, 0), (1, 3), (2**40 + 5, 1), (0xFFFFFFFFFFFFFFFF, 7)]:
+        M = O.uniform_ints(seed, level)
+        U = (M.astype(np.float64) + 1.0) * 2.0**-53
+        xi = O.gaussians(seed, level)
+        x, y = xi[0::2], xi[1::2]
+        r2 = -2.0 * np.log(U[0::2])
+        assert np.allclose(x * x + y * y, r2, rtol=1e-13, atol=1e-300)
+        a = np.mod(np.arctan2(y, x), 2.0 * np.pi)
+        want = np.mod(2.0 * np.pi * U[1::2], 2.0 * np.pi)
+        d = np.abs(a - want)
+        d = np.minimum(d, 2.0 * np.pi - d)
+        assert np.all(d <= 1e-12 * np.maximum(1.0, 1.0 / np.sqrt(r2)))
+
+
+def test_box_muller_pair_members_uncorrelated():
+    """Members of a pair are independent N(0,1): their correlation over 10^5
+    pairs is zero within sampling error, and the angle is uniform (a repeated
+    angle, xi_2p+1 = R cos a, would give correlation 1)."""
+    xi = np.concatenate([O.gaussians(s, 2) for s in range(3200)])
+    x, y = xi[0::2], xi[1::2]
+    r = np.corrcoef(x, y)[0, 1]
+    assert abs(r) < 5.0 / math.sqrt(x.size)
+    a = np.mod(np.arctan2(y, x), 2.0 * np.pi) / (2.0 * np.pi)
+    assert scipy.stats.kstest(a, "uniform").pvalue > 1e-4
