@@ -73,9 +73,15 @@ typedef struct {
  * tol = 1e-8, MG_FP64, sigma2 = 1, lambda = 0.1, 4 modes, no budget, NULL. */
 void mg_plan_desc_default(mg_plan_desc* d);
 
-/* Create a plan (validates *desc, precomputes the 1D KL tables for every
- * grid of levels 0..max_level).  *out receives the handle.  Returns MG_OK,
- * MG_EINVAL, MG_ENOMEM or MG_EHIP. */
+/* Create a plan: the fixed data of one MLMC run (Section 2.2, Algorithm 1:
+ * the hierarchy of levels h_l = 2^-l h_0 on which samples Y_l are drawn; the
+ * problem of Section 3, eq. modweak, with f = 1; the lognormal coefficient
+ * of Section 3.2, eq. def:expcov, with the plan's sigma^2 and lambda).
+ * Validates *desc and precomputes the 1D KL eigenpairs and their tables at
+ * the vertices of every grid of levels 0..max_level.  *out (host) receives
+ * the handle, which the caller releases with mg_plan_destroy.  Returns MG_OK,
+ * MG_EINVAL (bad field, or a finest grid above 1025^3), MG_ENOTIMPL
+ * (kl_per_axis != 4), MG_ENOMEM or MG_EHIP; *out is NULL on failure. */
 int mg_plan_create(const mg_plan_desc* desc, mg_plan* out);
 int mg_plan_destroy(mg_plan plan);
 
@@ -258,8 +264,21 @@ int mg_serve_slots(mg_server s, int level);
 int mlmc_philox(mg_plan plan, const uint64_t* seeds, int n_samples, int level,
                 uint32_t* words_out, double* normals_out);
 
-/* Coefficient k = exp(Z(seed, level)) at the n^3 vertices of an n grid (any
- * n = 2^m + 1), computed by the same kernel the samples use.  k_out: device. */
+/* Host Philox4x32-10 words of one sample (Salmon, Moraes, Dror, Shaw,
+ * SC'11): block j = 0..31 uses counter (j, level, 0, 0) and key (seed lo,
+ * seed hi); out (host, caller-owned, 128 entries) receives the four words of
+ * block j at out[4j..4j+3].  These words define omega of sample (seed,
+ * level) (Section 2.2: one omega shared by the two solves of Y_l, independent
+ * draws across levels).  No device work.  MG_EINVAL for out == NULL or
+ * level < 0. */
+int mlmc_philox_words(uint64_t seed, int level, uint32_t out[128]);
+
+/* Coefficient k = exp(Z(seed, level)) (Section 3.2, eq. def:expcov: the
+ * lognormal field, here its 4x4x4 separable KL truncation, sampled from the
+ * normals of omega(seed, level)) at the n^3 vertices of an n grid (any
+ * n = 2^m + 1 up to 1025, z fastest), computed by the same kernel the
+ * samples use.  k_out: device, caller-owned, n^3 doubles.  Blocking.
+ * MG_EINVAL for a bad n, level < 0 or k_out == NULL. */
 int mlmc_field(mg_plan plan, int n, uint64_t seed, int level, double* k_out);
 
 /* Host-side MLMC level statistics (Section 2.3: sample mean and s_l^2 with

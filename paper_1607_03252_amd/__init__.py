@@ -79,6 +79,7 @@ def lib():
                                         vp, vp, vp, vp, C.c_int]
         L.mlmc_philox.argtypes = [vp, C.POINTER(C.c_uint64), C.c_int, C.c_int, vp, vp]
         L.mlmc_field.argtypes = [vp, C.c_int, C.c_uint64, C.c_int, vp]
+        L.mlmc_philox_words.argtypes = [C.c_uint64, C.c_int, C.POINTER(C.c_uint32)]
         L.mlmc_acc_init.argtypes = [C.POINTER(mlmc_level_acc)]
         L.mlmc_acc_init.restype = None
         L.mlmc_acc_add.argtypes = [C.POINTER(mlmc_level_acc), vp, C.c_int, C.c_int]
@@ -123,7 +124,7 @@ def exported_symbols():
             "mg_sched_submit", "mg_sched_admit", "mg_sched_release", "mg_sched_counts",
             "mg_serve_create", "mg_serve_destroy", "mg_serve_submit", "mg_serve_step",
             "mg_serve_now", "mg_serve_counts", "mg_serve_slots", "mg_set_tile_for",
-            "mg_get_tile_for"]
+            "mg_get_tile_for", "mlmc_philox_words"]
 
 
 def _torch():
@@ -290,6 +291,15 @@ def mlmc_philox(plan: Plan, seeds, n: int, level: int, words_out=None, normals_o
     pn = _ptr(normals_out, "float64", 64 * n, "normals_out")
     mg_plan_set_stream(plan)
     return plan.check(lib().mlmc_philox(plan.handle, sp, n, level, pw, pn))
+
+
+def mlmc_philox_words(seed: int, level: int) -> np.ndarray:
+    """The 128 Philox words of sample (seed, level), computed on the host."""
+    out = np.zeros(128, dtype=np.uint32)
+    st = lib().mlmc_philox_words(int(seed), int(level), out.ctypes.data_as(C.POINTER(C.c_uint32)))
+    if st != MG_OK:
+        raise MGError(st, "mlmc_philox_words rejected its arguments")
+    return out
 
 
 def mlmc_field(plan: Plan, n: int, seed: int, level: int, k_out):

@@ -1626,6 +1626,16 @@ int mlmc_philox(mg_plan P, const uint64_t* seeds, int n_samples, int level, uint
   API_END(P)
 }
 
+int mlmc_philox_words(uint64_t seed, int level, uint32_t* out) {
+  if (!out || level < 0) return MG_EINVAL;
+  for (uint32_t j = 0; j < 32; ++j) {
+    uint32_t c[4] = {j, (uint32_t)level, 0u, 0u};
+    philox_block(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    for (int q = 0; q < 4; ++q) out[4 * j + q] = c[q];
+  }
+  return MG_OK;
+}
+
 int mlmc_field(mg_plan P, int n, uint64_t seed, int level, double* k_out) {
   if (!P) return MG_EINVAL;
   if (!valid_n(n) || n > 1025 || level < 0 || !k_out) return MG_EINVAL;

@@ -15,6 +15,27 @@
 
 namespace mg {
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// 4x32 bijection on counter c under key (k0, k1), in place.  One definition
+// for the device kernel and the host export: the high word of each 32x32-bit
+// product is taken from the 64-bit product (the device compiler maps it to
+// its multiply-high instruction).
+__host__ __device__ __forceinline__ void philox_block(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = (uint32_t)p1;
+    c[2] = n2;
+    c[3] = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
 // One grid of one solve at one multigrid level, in precision T.
 template <typename T>
 struct GridDescT {

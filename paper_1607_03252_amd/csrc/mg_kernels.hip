@@ -255,24 +255,7 @@ __device__ __forceinline__ T prolong_at(P e, int nc, int i, int j, int k) {
   return prolong_combine<T>(i, j, k, v);
 }
 
-// ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ----------------------
-__device__ __forceinline__ void philox_block(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c[0];
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
-    const uint32_t lo1 = 0xCD9E8D57u * c[2];
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
-    const uint32_t n0 = hi1 ^ c[1] ^ k0;
-    const uint32_t n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
+// ---- Philox4x32-10: philox_block (mg_internal.h) ----------------------------
 
 // One 64-thread block per sample: 32 Philox blocks -> 128 words -> 64
 // uniforms on (0,1] with 53 random bits -> 32 Box-Muller pairs.

@@ -95,3 +95,19 @@ def test_level_accumulator_host(M):
     assert abs(var - v_ref) <= 1e-10 * v_ref
     empty = M.mlmc_acc_init()
     assert M.mlmc_acc_result(empty) == (0.0, 0.0)
+
+
+@pytest.mark.parametrize("seed,level", [(0, 0), (1, 0), (63, 1), (2**32 + 7, 2),
+                                        (0xFFFFFFFFFFFFFFFF, 3), (123456789, 2**31 - 1)])
+def test_host_philox_words_match_oracle(M, seed, level):
+    """mlmc_philox_words (host, no device work) gives the oracle's words of
+    sample (seed, level) bit for bit; the oracle's generator is itself pinned
+    against rocRAND's philox4x32_10 engine."""
+    import oracle as O
+    assert np.array_equal(M.mlmc_philox_words(seed, level), O.philox_words(seed, level))
+
+
+def test_host_philox_words_rejects_bad_arguments(M):
+    out = (C.c_uint32 * 128)()
+    assert M.lib().mlmc_philox_words(0, -1, out) == M.MG_EINVAL
+    assert M.lib().mlmc_philox_words(0, 0, None) == M.MG_EINVAL
