@@ -230,9 +230,11 @@ def test_mixed_precision_reaches_fp64_residual(M, torch, n, sigma2, lam):
     uo, co, _, _ = O.solve(k, b, tol=1e-8)
     du = np.linalg.norm((u - uo).ravel()) / np.linalg.norm(uo.ravel())
     dq = abs(O.qoi(u) - O.qoi(uo)) / abs(O.qoi(uo))
-    # both iterates have relative residual <= 1e-8; their difference is an
-    # algebraic error of the same order (a few times 1e-8 for these k)
-    assert du <= 1e-6 and dq <= 1e-6, (du, dq)
+    # the FP32 inner cycles' rounding is contracted by the later outer steps:
+    # the mixed solution agrees with the FP64 oracle's at the same stopping
+    # cycle to the FP64 parity bars (measured: about 1e-14 in u and Q)
+    assert abs(cyc - co) <= 1
+    assert du <= 1e-10 and dq <= 1e-9, (du, dq)
     print("mixed n=%d cycles=%d (fp64 %d) rel=%.2e du=%.2e dq=%.2e" % (n, cyc, co, rel, du, dq))
 
 
@@ -243,8 +245,8 @@ def test_mixed_precision_batch(M, torch):
     assert st == M.MG_OK and np.all(cyc > 0)
     for i in (0, 7, 19):
         r = O.mlmc_sample(33, 1, seeds[i])
-        assert abs(Qf[i] - r["Qf"]) <= 1e-6 * abs(r["Qf"])
-        assert abs(Qc[i] - r["Qc"]) <= 1e-6 * abs(r["Qc"])
+        assert abs(Qf[i] - r["Qf"]) <= 1e-9 * abs(r["Qf"])
+        assert abs(Qc[i] - r["Qc"]) <= 1e-9 * abs(r["Qc"])
 
 
 def test_mixed_level_batch_equals_per_level_batches(M, torch):
