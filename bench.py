@@ -1,24 +1,33 @@
 """Benchmark of the MLMC multigrid hot path on one MI355X.
 
-Workload (one step): one MLMC level-pair batch of 64 coupled samples, fine
-65^3 and coarse 33^3 grids on one omega each (n0 = 33, level 1), seeds
-64*s .. 64*s+63 for step s, sigma^2 = 1, lambda = 0.1, f = 1, V(2,2)
-red-black Gauss-Seidel to relative residual 1e-8, QoI = integral of u,
-Y_1 = Q_1 - Q_0 per sample.  Inputs are generated on the device from seeds;
-everything stays resident in HBM.
+Default workload (one step): one batch of 16 MLMC samples of one 257^3 solve
+each (level 0 of n0 = 257), seeds 16*s .. 16*s+15 for step s, lognormal
+coefficient with sigma^2 = 2, lambda = 0.05 (4x4x4 separable KL), f = 1,
+FP64 V(2,2) red-black Gauss-Seidel to relative residual 1e-8, QoI = integral
+of u.  Inputs are generated on the device from seeds; everything stays
+resident in HBM (only the 16 seeds cross PCIe per step).
 
-Prints one JSON line (see the repository's design notes for the byte model):
-  value      = samples (Y_1 values) per second over the timed steps;
-  roofline   = the finest-grid smoothing kernel's algorithmic bytes per
-               launch / its mean launch time (HIP events on the plan's stream)
-               against the 8 TB/s HBM peak;
-  cpu_baseline = the FP64 CPU oracle on a bounded sample of the same
-               workload, one sample per thread.
+Prints one JSON line (the byte model is in the repository's design notes):
+  value        = samples per second over the timed steps;
+  roofline     = the fused red-black sweeps on the 257^3 grids: algorithmic
+                 bytes of the launches of the cycles in which every solve
+                 still cycles, over their summed duration (HIP events on the
+                 plan's stream, eager profiled steps after the timed region),
+                 against the 8 TB/s HBM peak; traffic from the committed
+                 counter summary when it was taken on the same sweep source
+                 and tile shapes;
+  cpu_baseline = the FP64 CPU oracle on the same workload: every host thread
+                 generates one sample's field and runs one V-cycle (with its
+                 residual), scaled by the GPU run's mean cycle count to
+                 samples per second; plus the single-thread latency;
+  extra        = the 64-pair level-1 batch (65^3 + 33^3), the mixed-precision
+                 form on the same 257^3 inputs, and a device copy's rate.
 """
 import argparse
 import concurrent.futures as cf
 import json
 import os
+import platform
 import sys
 import time
 
@@ -28,17 +37,67 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 # algorithmic bytes per interior node of one fused red-black sweep with a
-# constant right-hand side: wh (8) + u read (8) + u written (8)
+# constant right-hand side: wh (8) + u read (8) + u written (8); the sweep
+# with the coarse-grid correction also reads the coarse iterate once
 SWEEP_BYTES_PER_NODE = 24.0
+COARSE_BYTES_PER_NODE = 8.0
 # byte model of one FP64 V(2,2) cycle per finest-grid node (whole hierarchy)
 VCYCLE_BYTES_PER_NODE = 195.0
 # mixed precision per outer step: FP32 V(2,2) (~98) + FP64 defect and update (48)
 MIXED_BYTES_PER_NODE = 146.0
+KIND_NAMES = {0: "plain", 1: "coarse_correction", 2: "output_residual", 3: "input_residual"}
+
+CFG4 = dict(n=257, samples=16, sigma2=2.0, corr_len=0.05, tol=1e-8)
 
 
-def cpu_baseline(n0, level, threads, min_seconds, max_samples=4096):
-    """The oracle on `threads` host threads, one sample per thread, in rounds
-    of `threads` samples until min_seconds have passed."""
+def host_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline_config4(threads, cycles_mean):
+    """The oracle on the default workload's inputs.  Each of `threads` host
+    threads takes one sample (seeds 10^6..): the coefficient field, then one
+    V(2,2) cycle with its residual norm (the oracle's solve with one fixed
+    cycle); per-sample time = field + cycles_mean x cycle.  Also one sample's
+    field and cycle on a single thread (latency)."""
+    import oracle as O
+    n, s2, lam = CFG4["n"], CFG4["sigma2"], CFG4["corr_len"]
+
+    def one(seed):
+        t0 = time.perf_counter()
+        k = O.field(n, s2, lam, O.gaussians(seed, 0))
+        t1 = time.perf_counter()
+        O.solve(k, O.rhs(n), fixed_cycles=1)
+        return t1 - t0, time.perf_counter() - t1
+
+    tf1, tc1 = one(10**6)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(one, range(10**6 + 1, 10**6 + 1 + threads)))
+    wall = time.perf_counter() - t0
+    tf = sum(r[0] for r in res) / len(res)
+    tc = sum(r[1] for r in res) / len(res)
+    per_sample = tf + cycles_mean * tc
+    return {"value": threads / per_sample, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": "%d samples of the 257^3 workload (seeds 1e6+1..), one per thread: field "
+                      "(%.2f s) + one V(2,2) cycle with residual (%.2f s) each, scaled to %.2f "
+                      "cycles per sample; %.1f s wall" % (threads, tf, tc, cycles_mean, wall),
+            "single_thread_latency_s": tf1 + cycles_mean * tc1,
+            "single_thread_field_s": tf1, "single_thread_cycle_s": tc1, **host_info()}
+
+
+def cpu_baseline_pairs(n0, level, threads, min_seconds, max_samples=4096):
+    """The oracle on `threads` host threads, one level-pair sample per thread,
+    in rounds of `threads` samples until min_seconds have passed."""
     import oracle as O
     done, seed = 0, 10**6
     t0 = time.perf_counter()
@@ -54,34 +113,43 @@ def cpu_baseline(n0, level, threads, min_seconds, max_samples=4096):
     return done / dt, dt, done
 
 
-def main():
+def parse_args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--samples", type=int, default=64)
+    ap.add_argument("--samples", type=int, default=64, help="level-pair batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline only (no level-pair, mixed-precision or copy figures)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the oracle baseline (default min(16, nproc))")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="minimum wall time of the CPU oracle baseline")
-    ap.add_argument("--workload", default="levelpair",
-                    choices=["levelpair", "single", "mixed", "fp32mix", "serve"])
+                    help="minimum wall time of the level-pair oracle baseline")
+    ap.add_argument("--workload", default="config4",
+                    choices=["config4", "levelpair", "single", "mixed", "fp32mix", "serve"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="precision of the default workload")
     ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--serve-slots", default="128,64,16,4")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--no-fifo", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the smoother's tile shapes first (default: the library's shapes)")
-    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--tile", action="append", default=[],
                     help="n:tj:tk:chunks, pins a smoother tile shape (skips the autotuner)")
     ap.add_argument("--tile-pro", action="append", default=[],
                     help="n:tj:tk:chunks, the shape of the sweep with the fused coarse correction")
     ap.add_argument("--opt", action="append", default=[],
-                    help="name=value, a plan option (mg_plan_set_option) for the level-pair "
-                         "workload, e.g. norm=0 or transfer=1")
+                    help="name=value, a plan option (mg_plan_set_option), e.g. norm=0")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (counter calibration)")
-    args = ap.parse_args()
+    return ap.parse_args()
+
+
+def main():
+    args = parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(samples shard across GPUs by seed range; see the design notes)", file=sys.stderr)
@@ -96,13 +164,204 @@ def main():
         sys.exit(3)
     if not os.path.exists(M.LIB_PATH):
         raise SystemExit("libmlmcmg.so is not built: run `python -m paper_1607_03252_amd.build`")
-    if args.workload != "levelpair":
-        fn = {"single": bench_single, "mixed": bench_mixed, "fp32mix": bench_fp32mix,
-              "serve": bench_serve}[args.workload]
-        print(json.dumps(fn(args, M, torch, np)), flush=True)
+    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+    if args.workload != "config4":
+        fn = {"levelpair": bench_levelpair, "single": bench_single, "mixed": bench_mixed,
+              "fp32mix": bench_fp32mix, "serve": bench_serve}[args.workload]
+        out = fn(args, M, torch, np)
+        if args.workload == "levelpair" and not args.no_cpu_baseline:
+            v, cdt, done = cpu_baseline_pairs(33, 1, threads, args.cpu_seconds)
+            out["cpu_baseline"] = {"value": v, "unit": "samples/s", "cores": threads,
+                                   "kind": "oracle",
+                                   "sample": "%d samples of the same level pair (seeds 1e6..), "
+                                             "one sample per thread, %.1f s wall" % (done, cdt),
+                                   **host_info()}
+        print(json.dumps(out), flush=True)
         return
 
+    out = bench_config4(args, M, torch, np, M.MG_FP64 if args.precision == "fp64" else M.MG_MIXED)
+    if not args.no_extra:
+        extra = {}
+        lp = bench_levelpair(args, M, torch, np, steps=min(args.steps, 10), profile=False)
+        extra["levelpair_65_33_x64"] = {k: lp[k] for k in ("value", "unit", "ms_per_step")}
+        extra["levelpair_65_33_x64"]["fine_cycles_mean"] = lp["per_level"]["1"]["fine_cycles_mean"]
+        if args.precision == "fp64":
+            mx = bench_config4(args, M, torch, np, M.MG_MIXED, steps=min(args.steps, 5),
+                               warmup=1, profile=False)
+            extra["mixed_precision_257_x16"] = {
+                "value": mx["value"], "unit": "samples/s", "ms_per_step": mx["ms_per_step"],
+                "speedup_vs_fp64": mx["value"] / out["value"],
+                "max_rel_dQ_vs_fp64": float(np.max(np.abs(mx["_Q"] - out["_Q"]) / np.abs(out["_Q"])))}
+        cp = device_copy(torch)
+        cp["sweep_fraction_of_copy"] = out["roofline"]["achieved"] / cp["GBps"]
+        extra["device_copy"] = cp
+        out["extra"] = extra
+    out.pop("_Q", None)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_config4(threads, out["per_level"]["0"]["fine_cycles_mean"])
+    print(json.dumps(out), flush=True)
+
+
+def device_copy(torch, nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of nbytes (the streaming rate any kernel
+    of this path can hope for on this GPU), timed with events."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbps = 2.0 * nbytes / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "GBps": gbps, "frac_of_peak": gbps / HBM_PEAK_GBPS}
+
+
+def sweep_roofline(M, P, n, samples, cycles_min):
+    """Algorithmic bytes over duration of the timed sweep launches on the n^3
+    grids in cycles 1..cycles_min of each profiled batch (every solve still
+    cycles there, so every launch moves every grid)."""
+    cyc, kind, ms = M.mg_profile_records(P)
+    nodes = samples * float(n - 2) ** 3
+    nc = (n - 1) // 2 + 1
+    coarse = samples * float(nc - 2) ** 3
+    sel = cyc <= cycles_min
+    per_kind = {}
+    tot_b, tot_ms = 0.0, 0.0
+    for k in sorted(set(kind[sel].tolist())):
+        m = sel & (kind == k)
+        b = SWEEP_BYTES_PER_NODE * nodes + (COARSE_BYTES_PER_NODE * coarse if k == 1 else 0.0)
+        avg = float(ms[m].mean())
+        per_kind[KIND_NAMES[k]] = {"launches": int(m.sum()), "avg_us": 1e3 * avg,
+                                   "bytes_per_launch": b, "GBps": b / (avg * 1e-3) / 1e9}
+        tot_b += b * int(m.sum())
+        tot_ms += float(ms[m].sum())
+    achieved = tot_b / (tot_ms * 1e-3) / 1e9 if tot_ms else 0.0
+    return {"achieved": achieved, "launches": int(sel.sum()),
+            "avg_launch_us": 1e3 * tot_ms / max(1, int(sel.sum())),
+            "bytes_per_launch": tot_b / max(1, int(sel.sum())), "per_kind": per_kind,
+            "launches_excluded": int((~sel).sum())}
+
+
+def read_traffic(name, tiles):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current sweep source and the same tile shapes."""
+    summ = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(summ):
+        return None, None, None
+    from paper_1607_03252_amd import profsum
+    rec = profsum.read_summary(summ)
+    if rec.get("kernel_source_sha256") == profsum.source_hash() and rec.get("tiles") == tiles:
+        return rec.get("hbm_bytes_per_launch"), os.path.relpath(summ, ROOT), rec
+    return None, None, None
+
+
+def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profile=True):
+    n, S = CFG4["n"], CFG4["samples"]
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    P = M.mg_plan_create(n0=n, max_level=0, sigma2=CFG4["sigma2"], corr_len=CFG4["corr_len"],
+                         tol=CFG4["tol"], nu1=2, nu2=2, max_cycles=50, precision=precision)
+    for spec in args.opt:
+        name, value = spec.split("=")
+        M.mg_plan_set_option(P, name, int(value))
+    for spec in args.tile:
+        nn, tj, tk, ch = (int(x) for x in spec.split(":"))
+        M.mg_set_tile(P, nn, tj, tk, ch)
+    for spec in args.tile_pro:
+        nn, tj, tk, ch = (int(x) for x in spec.split(":"))
+        M.mg_set_tile_for(P, nn, 1, tj, tk, ch)
+    Y = torch.zeros(S, dtype=torch.float64, device="cuda")
+    Qf, Qc = torch.zeros_like(Y), torch.zeros_like(Y)
+
+    def step(s, cyc_out):
+        seeds = np.arange(s * S, (s + 1) * S, dtype=np.uint64)
+        st = M.mlmc_sample_batch(P, 0, seeds, S, Y, Qf, Qc, cyc_out)
+        assert st == M.MG_OK, st
+
+    if args.autotune and not args.tile:
+        M.mg_autotune(P, 0, S, 3)
+    tiles = [list(M.mg_get_tile(P, n)), list(M.mg_get_tile_for(P, n, 1))]
+    cyc_w = torch.zeros(2 * S, dtype=torch.int32, device="cuda")
+    for s in range(warmup):
+        step(10**5 + s, cyc_w)
+    cyc_all = torch.zeros(max(1, steps), 2 * S, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        step(s, cyc_all[s])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cyc_np = cyc_all.cpu().numpy().reshape(max(1, steps), S, 2)[:, :, 0]
+    cyc_mean = float(cyc_np.mean())
+    value = S * steps / dt
+    ms_step = 1e3 * dt / steps
+    per_node = VCYCLE_BYTES_PER_NODE if precision == M.MG_FP64 else MIXED_BYTES_PER_NODE
+    eff = per_node * n**3 * float(cyc_np.sum()) / dt / 1e9
+    out = {
+        "metric": "MLMC samples/sec per level + V-cycle HBM GB/s; p50/p99 solve latency",
+        "value": value, "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == M.MG_FP64 else "f64+f32",
+        "data": "synthetic (Philox-seeded 64-term KL lognormal fields)",
+        "config": {"workload": "mlmc_level0_n257_x16_sigma2_2_lambda_0.05"
+                               + ("" if precision == M.MG_FP64 else "_mixed_precision"),
+                   "n": n, "samples_per_step": S, "sigma2": CFG4["sigma2"],
+                   "corr_len": CFG4["corr_len"], "tol": CFG4["tol"],
+                   "cycle": "V(2,2) red-black GS, 8 levels", "parallelism": "single GPU",
+                   "tiles": {str(n): tiles[0]}, "tiles_pro": {str(n): tiles[1]},
+                   "options": dict(o.split("=") for o in args.opt)},
+        "per_level": {"0": {"samples_per_s": value, "fine_cycles_mean": cyc_mean,
+                            "effective_vcycle_GBps": eff, "batch_latency_ms": ms_step}},
+    }
+    # the QoI of step 0's seeds (an untimed step), for the mixed vs FP64 comparison
+    step(0, cyc_w)
+    out["_Q"] = Qf.cpu().numpy().copy()
+    if profile and precision == M.MG_FP64:
+        # eager steps with every sweep launch on the 257^3 grids timed by HIP
+        # events; only the cycles in which every solve still cycles count
+        M.mg_profile_enable(P, True)
+        cyc_p = torch.zeros(max(1, args.profile_steps), 2 * S, dtype=torch.int32, device="cuda")
+        for s in range(args.profile_steps):
+            step(s, cyc_p[s])
+        torch.cuda.synchronize()
+        cmin = int(cyc_p.cpu().numpy().reshape(-1, S, 2)[:, :, 0].min())
+        rf = sweep_roofline(M, P, n, S, cmin)
+        M.mg_profile_enable(P, False)
+        traffic, src, rec = read_traffic("k_sweep_config4_257x16.txt", tiles)
+        out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBPS,
+                           "unit": "GB/s", "frac": rf["achieved"] / HBM_PEAK_GBPS,
+                           "traffic": traffic, "traffic_source": src,
+                           "kernel": "k_sweep family (fused red-black sweeps, 257^3 grids)",
+                           "launches": rf["launches"], "avg_launch_us": rf["avg_launch_us"],
+                           "bytes_per_launch": rf["bytes_per_launch"],
+                           "profile_steps": args.profile_steps,
+                           "all_active_cycles": cmin,
+                           "launches_excluded": rf["launches_excluded"],
+                           "per_kind": rf["per_kind"], "tiles": tiles}
+        if rec:
+            out["roofline"]["traffic_over_algorithmic"] = traffic / rf["bytes_per_launch"]
+    if args.calib_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    P.destroy()
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_levelpair(args, M, torch, np, steps=None, profile=True):
+    """64 coupled samples of fine 65^3 and coarse 33^3 per step (level 1 of
+    n0 = 33, sigma^2 = 1, lambda = 0.1), seeds 64*s .. 64*s+63 for step s."""
     n0, level, S = 33, 1, args.samples
+    steps = args.steps if steps is None else steps
     P = M.mg_plan_create(n0=n0, max_level=level, sigma2=1.0, corr_len=0.1, tol=1e-8,
                          nu1=2, nu2=2, max_cycles=50)
     for spec in args.opt:
@@ -119,10 +378,12 @@ def main():
 
     for spec in args.tile:
         nn, tj, tk, ch = (int(x) for x in spec.split(":"))
-        M.mg_set_tile(P, nn, tj, tk, ch)
+        if nn in (65, 33):
+            M.mg_set_tile(P, nn, tj, tk, ch)
     for spec in args.tile_pro:
         nn, tj, tk, ch = (int(x) for x in spec.split(":"))
-        M.mg_set_tile_for(P, nn, 1, tj, tk, ch)
+        if nn in (65, 33):
+            M.mg_set_tile_for(P, nn, 1, tj, tk, ch)
     if args.autotune and not args.tile:
         M.mg_autotune(P, level, S, 3)
     tiles = {n: M.mg_get_tile(P, n) for n in (65, 33)}
@@ -130,85 +391,49 @@ def main():
     for s in range(args.warmup):
         step(10**5 + s)
     torch.cuda.synchronize()
-    # each step's cycle counts land in its own row (written by the library)
-    cyc_all = torch.zeros(args.steps, 2 * S, dtype=torch.int32, device="cuda")
+    cyc_all = torch.zeros(max(1, steps), 2 * S, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
+    for s in range(steps):
         step(s, cyc_all[s])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    cyc_mean = float(cyc_all.view(args.steps, S, 2)[:, :, 0].double().mean().item())
-    # per-kernel timing of the finest-grid smoother: HIP events on the plan's
-    # stream around each launch (eager launches, same kernels and inputs)
-    M.mg_profile_enable(P, True)
-    for s in range(args.profile_steps):
-        step(s)
-    launches, ms, nodes = M.mg_profile_read(P)
-    M.mg_profile_enable(P, False)
-
-    if args.calib_copy:
-        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-
-    value = S * args.steps / dt
-    ms_step = 1e3 * dt / args.steps
-    avg_ms = ms / max(launches, 1)
-    bytes_launch = SWEEP_BYTES_PER_NODE * nodes
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    cyc_np = cyc_all.cpu().numpy().reshape(max(1, steps), S, 2)
+    cyc_mean = float(cyc_np[:, :, 0].mean())
+    value = S * steps / dt
+    ms_step = 1e3 * dt / steps
     nf, nc = (n0 - 1) * 2**level + 1, (n0 - 1) * 2**(level - 1) + 1
-    eff = VCYCLE_BYTES_PER_NODE * (nf**3 + nc**3) * S * cyc_mean * args.steps / dt / 1e9
-
-    traffic, traffic_src = None, None
-    summ = os.path.join(ROOT, "profiles", "k_sweep_traffic_levelpair65_33x64.txt")
-    if os.path.exists(summ):
-        from paper_1607_03252_amd import profsum
-        rec = profsum.read_summary(summ)
-        # counters apply only to the same kernel source and tile shape
-        if rec.get("kernel_source_sha256") == profsum.source_hash() and \
-                rec.get("tiles") == [list(tiles[65]), list(tiles_pro[65])]:
-            traffic = rec.get("hbm_bytes_per_launch")
-            traffic_src = os.path.relpath(summ, ROOT)
-
-    out = {
-        "metric": "MLMC samples/sec per level + V-cycle HBM GB/s; p50/p99 solve latency",
-        "value": value,
-        "unit": "samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (Philox-seeded 64-term KL lognormal fields)",
-        "config": {"workload": "mlmc_level_pair_fine65_coarse33_x64", "n0": n0, "level": level,
-                   "samples_per_step": S, "sigma2": 1.0, "corr_len": 0.1, "tol": 1e-8,
-                   "cycle": "V(2,2) red-black GS", "parallelism": "single GPU",
-                   "tiles": {str(k): list(v) for k, v in tiles.items()},
-                   "tiles_pro": {str(k): list(v) for k, v in tiles_pro.items()},
-                   "options": dict(o.split("=") for o in args.opt)},
-        "per_level": {str(level): {"samples_per_s": value, "fine_cycles_mean": cyc_mean,
-                                   "effective_vcycle_GBps": eff,
-                                   "batch_latency_ms": ms_step}},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "traffic_source": traffic_src,
-                     "kernel": "k_sweep (fused red-black sweep, 65^3 grids)", "launches": launches,
-                     "tiles": [list(tiles[65]), list(tiles_pro[65])],
-                     "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_launch},
-    }
-    if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        v, cdt, done = cpu_baseline(n0, level, threads, args.cpu_seconds)
-        out["cpu_baseline"] = {"value": v, "unit": "samples/s", "cores": threads, "kind": "oracle",
-                               "sample": "%d samples of the same level pair (seeds 1e6..), one "
-                                         "sample per thread, %.1f s wall" % (done, cdt)}
-    print(json.dumps(out), flush=True)
+    nodes = (nf**3 * cyc_np[:, :, 0].sum() + nc**3 * cyc_np[:, :, 1].sum())
+    eff = VCYCLE_BYTES_PER_NODE * float(nodes) / dt / 1e9
+    out = _line("MLMC samples/sec per level + V-cycle HBM GB/s; p50/p99 solve latency", value,
+                "samples/s", steps, args.warmup, ms_step,
+                {"workload": "mlmc_level_pair_fine65_coarse33_x64", "n0": n0, "level": level,
+                 "samples_per_step": S, "sigma2": 1.0, "corr_len": 0.1, "tol": 1e-8,
+                 "cycle": "V(2,2) red-black GS", "parallelism": "single GPU",
+                 "tiles": {str(k): list(v) for k, v in tiles.items()},
+                 "tiles_pro": {str(k): list(v) for k, v in tiles_pro.items()},
+                 "options": dict(o.split("=") for o in args.opt)})
+    out["per_level"] = {str(level): {"samples_per_s": value, "fine_cycles_mean": cyc_mean,
+                                     "effective_vcycle_GBps": eff, "batch_latency_ms": ms_step}}
+    if profile:
+        M.mg_profile_enable(P, True)
+        cyc_p = torch.zeros(max(1, args.profile_steps), 2 * S, dtype=torch.int32, device="cuda")
+        for s in range(args.profile_steps):
+            step(s, cyc_p[s])
+        torch.cuda.synchronize()
+        cmin = int(cyc_p.cpu().numpy().reshape(-1, S, 2)[:, :, 0].min())
+        rf = sweep_roofline(M, P, nf, S, cmin)
+        M.mg_profile_enable(P, False)
+        out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBPS,
+                           "unit": "GB/s", "frac": rf["achieved"] / HBM_PEAK_GBPS,
+                           "traffic": None,
+                           "kernel": "k_sweep family (fused red-black sweeps, 65^3 grids)",
+                           "launches": rf["launches"], "avg_launch_us": rf["avg_launch_us"],
+                           "bytes_per_launch": rf["bytes_per_launch"],
+                           "all_active_cycles": cmin, "per_kind": rf["per_kind"],
+                           "tiles": [list(tiles[65]), list(tiles_pro[65])]}
+    P.destroy()
+    return out
 
 
 # ---- the other execution forms (one JSON line each, --workload ...) ----------------

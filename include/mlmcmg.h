@@ -299,6 +299,14 @@ void mlmc_acc_result(const mlmc_level_acc* a, double* mean, double* var);
  * their summed duration in milliseconds since the last reset. */
 int mg_profile_enable(mg_plan plan, int on);
 int mg_profile_read(mg_plan plan, long long* launches, double* total_ms, double* nodes_per_launch);
+/* The timed launches one by one (since the last mg_profile_enable), in launch
+ * order: cycle[i] is the V-cycle of its batch it belongs to (1-based; a batch
+ * restarts the count), kind[i] the sweep (0 plain, 1 with the coarse-grid
+ * correction, 2 with the residual norm of its output's black points, 3 with
+ * the residual norm of its input's red points), ms[i] its duration.  Host
+ * arrays of max_out entries; *n_out receives the number of records (which
+ * may exceed max_out; only max_out are written). */
+int mg_profile_records(mg_plan plan, int max_out, int* cycle, int* kind, double* ms, int* n_out);
 
 const char* mg_last_error(mg_plan plan);
 

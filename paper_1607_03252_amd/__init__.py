@@ -87,6 +87,7 @@ def lib():
         L.mlmc_acc_result.restype = None
         L.mg_profile_enable.argtypes = [vp, C.c_int]
         L.mg_profile_read.argtypes = [vp, C.POINTER(C.c_longlong), dp, dp]
+        L.mg_profile_records.argtypes = [vp, C.c_int, ip, ip, dp, ip]
         L.mg_plan_set_option.argtypes = [vp, C.c_char_p, C.c_longlong]
         L.mg_set_tile.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.mg_get_tile.argtypes = [vp, C.c_int, ip, ip, ip]
@@ -124,7 +125,8 @@ def exported_symbols():
             "mg_sched_submit", "mg_sched_admit", "mg_sched_release", "mg_sched_counts",
             "mg_serve_create", "mg_serve_destroy", "mg_serve_submit", "mg_serve_step",
             "mg_serve_now", "mg_serve_counts", "mg_serve_slots", "mg_set_tile_for",
-            "mg_get_tile_for", "mlmc_philox_words"]
+            "mg_get_tile_for", "mlmc_philox_words",
+            "mg_profile_records"]
 
 
 def _torch():
@@ -347,6 +349,19 @@ def mg_profile_read(plan: Plan):
     n, ms, nodes = C.c_longlong(), C.c_double(), C.c_double()
     plan.check(lib().mg_profile_read(plan.handle, C.byref(n), C.byref(ms), C.byref(nodes)))
     return n.value, ms.value, nodes.value
+
+
+def mg_profile_records(plan: Plan):
+    """Per timed launch: (cycle, kind, ms) arrays (see mg_profile_records)."""
+    n = C.c_int()
+    plan.check(lib().mg_profile_records(plan.handle, 0, None, None, None, C.byref(n)))
+    m = n.value
+    cyc, kind = np.zeros(m, dtype=np.int32), np.zeros(m, dtype=np.int32)
+    ms = np.zeros(m)
+    plan.check(lib().mg_profile_records(plan.handle, m, cyc.ctypes.data_as(C.POINTER(C.c_int)),
+                                        kind.ctypes.data_as(C.POINTER(C.c_int)),
+                                        ms.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
+    return cyc, kind, ms
 
 
 # ---- serving -------------------------------------------------------------------

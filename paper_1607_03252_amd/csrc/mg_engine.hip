@@ -209,6 +209,15 @@ struct mg_plan_s {
   long long prof_launches = 0;
   double prof_ms = 0.0;
   double prof_nodes = 0.0;
+  // per timed launch: the cycle of its batch (1-based), its sweep kind and
+  // its duration; ev_meta holds the (cycle, kind) of each pending event pair
+  struct ProfRec {
+    int cycle, kind;
+    double ms;
+  };
+  std::vector<ProfRec> prof_recs;
+  std::vector<std::pair<int, int>> ev_meta;
+  int prof_cycle = 0;
 
   ~mg_plan_s() {
     batch.reset();
@@ -544,8 +553,11 @@ static void collect_profile(mg_plan_s* P) {
     CK(hipEventElapsedTime(&ms, P->ev_pool[i], P->ev_pool[i + 1]));
     P->prof_ms += ms;
     P->prof_launches += 1;
+    const auto& m = P->ev_meta[i / 2];
+    P->prof_recs.push_back({m.first, m.second, (double)ms});
   }
   P->ev_used = 0;
+  P->ev_meta.clear();
 }
 
 // One red-black sweep on the grids of size index si; returns the new buffer.
@@ -557,6 +569,10 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
   hipStream_t st = B->st;
   if (timed) {
     if (P->ev_used + 4 > 8192) collect_profile(P);
+    // kind: 0 plain sweep, 1 with the coarse correction, 2 with the black
+    // residuals of its output, 3 with the red residuals of its input
+    const int kind = cbuf >= 0 ? 1 : (spart ? (norm == 2 ? 2 : 3) : 0);
+    P->ev_meta.push_back({P->prof_cycle, kind});
     CK(hipEventRecord(next_event(P), st));
   }
   int out = buf;
@@ -691,6 +707,7 @@ static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
                        Lists<double>* Lp = nullptr) {
   hipStream_t st = B->st;
   Lists<double>& L = Lp ? *Lp : B->L64;
+  if (P->prof) ++P->prof_cycle;  // (eager while profiling: one call per cycle)
   launch_tick(B->d_cycle, st);
   if (!B->spec.mixed) {
     const int out = run_cycle<double>(P, B, L, true, tol, fixed);
@@ -777,6 +794,7 @@ static void build_tail_lists(Batch* B, const int* act) {
 static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graphs,
                        const std::function<void()>& post = nullptr, int qpend = 0) {
   hipStream_t st = B->st;
+  P->prof_cycle = 0;
   launch_init_state2(B->ss, B->d_cycle, B->ns, st, qpend);
   // ||b'|| per solve (a constant top right-hand side gives the same norms for
   // every batch of this workspace)
@@ -1310,6 +1328,39 @@ static void serve_step(mg_server_s* S, int c) {
   }
 }
 
+
+// The solve of mg_solve on a batch of one solve whose top u is the caller's.
+static int solve_one(mg_plan_s* P, Batch* B, int n, const double* k, const double* f, double* u,
+                     double t, int fixed_cycles, int* cycles, double* relres) {
+  B->lev[0][0].u[0] = u;  // the caller's u is the top iterate
+  B->drop_graphs();
+  upload_lists(P, B);
+  const LevelT<double>& T = B->lev[0][0];
+  launch_prepare_problem(n, k, f, T.wh, T.b, u, P->work);
+  prepare_coefficients(P, B);
+  const bool ok = run_solves(P, B, t, fixed_cycles, false);
+  int cyc = 0;
+  double rel = 0.0;
+  CK(hipMemcpy(&cyc, B->ss.cycles, sizeof(int), hipMemcpyDeviceToHost));
+  CK(hipMemcpy(&rel, B->ss.relres, sizeof(double), hipMemcpyDeviceToHost));
+  if (cycles) *cycles = cyc >= 0 ? cyc : P->desc.max_cycles;
+  if (relres) *relres = rel;
+  if (!ok) {
+    P->err = "mg_solve: tolerance not reached within max_cycles";
+    return MG_ENOCONV;
+  }
+  return MG_OK;
+}
+
+static BatchSpec solve_spec(mg_plan_s* P, int n) {
+  BatchSpec spec;
+  spec.top_n = {n};
+  spec.share = {-1};
+  spec.const_b_top = false;
+  spec.ext_u_top = true;
+  spec.mixed = P->desc.precision == MG_MIXED;
+  return spec;
+}
 }  // namespace mg
 
 // ============================== C ABI ==========================================
@@ -1477,35 +1528,13 @@ int mg_solve(mg_plan P, int n, const double* k, const double* f, double* u, doub
   }
   API_BEGIN
   const double t = tol > 0.0 ? tol : P->desc.tol;
-  BatchSpec spec;
-  spec.top_n = {n};
-  spec.share = {-1};
-  spec.const_b_top = false;
-  spec.ext_u_top = true;
-  spec.mixed = P->desc.precision == MG_MIXED;
   int status = MG_OK;
   order_after_caller(P);
-  Batch* B = get_batch(P, spec, &status);
+  Batch* B = get_batch(P, solve_spec(P, n), &status);
   if (!B) return status;
-  B->lev[0][0].u[0] = u;  // the caller's u is the top iterate
-  B->drop_graphs();
-  upload_lists(P, B);
-  const LevelT<double>& T = B->lev[0][0];
-  launch_prepare_problem(n, k, f, T.wh, T.b, u, P->work);
-  prepare_coefficients(P, B);
-  const bool ok = run_solves(P, B, t, fixed_cycles, false);
-  int cyc = 0;
-  double rel = 0.0;
-  CK(hipMemcpy(&cyc, B->ss.cycles, sizeof(int), hipMemcpyDeviceToHost));
-  CK(hipMemcpy(&rel, B->ss.relres, sizeof(double), hipMemcpyDeviceToHost));
+  const int st = solve_one(P, B, n, k, f, u, t, fixed_cycles, cycles, relres);
   if (P->prof) collect_profile(P);
-  if (cycles) *cycles = cyc >= 0 ? cyc : P->desc.max_cycles;
-  if (relres) *relres = rel;
-  if (!ok) {
-    P->err = "mg_solve: tolerance not reached within max_cycles";
-    return MG_ENOCONV;
-  }
-  return MG_OK;
+  return st;
   API_END(P)
 }
 
@@ -1713,6 +1742,8 @@ int mg_profile_enable(mg_plan P, int on) {
   P->prof = on != 0;
   P->prof_launches = 0;
   P->prof_ms = 0.0;
+  P->prof_recs.clear();
+  P->ev_meta.clear();
   P->ev_used = 0;
   return MG_OK;
 }
@@ -1724,6 +1755,21 @@ int mg_profile_read(mg_plan P, long long* launches, double* total_ms, double* no
   if (launches) *launches = P->prof_launches;
   if (total_ms) *total_ms = P->prof_ms;
   if (nodes_per_launch) *nodes_per_launch = P->prof_nodes;
+  return MG_OK;
+  API_END(P)
+}
+
+int mg_profile_records(mg_plan P, int max_out, int* cycle, int* kind, double* ms, int* n_out) {
+  if (!P || !n_out || max_out < 0 || (max_out > 0 && (!cycle || !kind || !ms))) return MG_EINVAL;
+  API_BEGIN
+  collect_profile(P);
+  const int n = (int)std::min<size_t>((size_t)max_out, P->prof_recs.size());
+  for (int i = 0; i < n; ++i) {
+    cycle[i] = P->prof_recs[i].cycle;
+    kind[i] = P->prof_recs[i].kind;
+    ms[i] = P->prof_recs[i].ms;
+  }
+  *n_out = (int)P->prof_recs.size();
   return MG_OK;
   API_END(P)
 }

@@ -8,9 +8,17 @@
          the same process (``bench.py --calib-copy``), written as JSON together
          with the hash of the kernel source it was taken on.
 
+  sweeps: the finest-grid smoothing launches of the last K batches of a run,
+         restricted to the V-cycles in which every solve still cycles (the
+         selection bench.py's roofline uses): durations from a kernel trace,
+         and HBM bytes from the two counter runs when given.
+
   python -m paper_1607_03252_amd.profsum trace CSV OUT --title T --command C
   python -m paper_1607_03252_amd.profsum pmc FETCH_CSV WRITE_CSV OUT --match K@GRID ...
          --command C [--copy-bytes B] [--tiles TJ:TK:CH,TJ:TK:CH]
+  python -m paper_1607_03252_amd.profsum sweeps TRACE_CSV OUT --batches K --cycles-upto M
+         --bytes-per-kind B0,B1,B2,B3 --title T --command C
+         [--fetch FETCH_CSV --write WRITE_CSV --pmc-command C2 --tiles ...]
 """
 import argparse
 import collections
@@ -128,6 +136,128 @@ def pmc_summary(fetch_csv, write_csv, matches, copy_bytes):
     return res, "\n".join(table)
 
 
+KIND_NAMES = ["plain", "coarse_correction", "output_residual", "input_residual"]
+
+
+def sweep_kind(name):
+    """0 plain, 1 with the coarse-grid correction, 2 output residual norm,
+    3 input residual norm (the kinds of mg_profile_records)."""
+    if "res_out" in name:
+        return 2
+    if "res_in" in name:
+        return 3
+    m = re.match(r"k_sweep<[^,]+,\s*\d+,\s*\d+,\s*(true|false)", name)
+    return 1 if m and m.group(1) == "true" else 0
+
+
+def _order_key(r):
+    for k in ("Dispatch_Id", "Correlation_Id"):
+        if r.get(k) not in (None, ""):
+            return int(r[k])
+    return int(r["Start_Timestamp"])
+
+
+def finest_sweeps(rows, batches, cycles_upto, nu1=2, nu2=2):
+    """Rows (one per dispatch) of the finest-grid sweeps in cycles 1..cycles_upto
+    of the last `batches` batches.  A batch starts at k_init_state, a cycle at
+    k_tick; within a cycle the finest grid's sweeps are the first nu1 and the
+    last nu2 sweep dispatches (a V-cycle descends from, and returns to, the
+    finest grid).  Returns [(kind, cycle, row)]."""
+    rows = sorted(rows, key=_order_key)
+    names = [short_name(r["Kernel_Name"]) for r in rows]
+    starts = [i for i, nm in enumerate(names) if nm == "k_init_state"]
+    if len(starts) < batches:
+        raise ValueError("the run has %d batches, fewer than %d" % (len(starts), batches))
+    out = []
+    for b in range(len(starts) - batches, len(starts)):
+        lo = starts[b]
+        hi = starts[b + 1] if b + 1 < len(starts) else len(rows)
+        cycle, sweeps = 0, []
+
+        def flush():
+            if cycle >= 1 and cycle <= cycles_upto and sweeps:
+                pick = sweeps[:nu1] + sweeps[max(nu1, len(sweeps) - nu2):]
+                for i in pick:
+                    out.append((sweep_kind(names[i]), cycle, rows[i]))
+        for i in range(lo, hi):
+            if names[i] == "k_tick":
+                flush()
+                cycle += 1
+                sweeps = []
+            elif names[i].startswith("k_sweep"):
+                sweeps.append(i)
+        flush()
+    return out
+
+
+def sweeps_summary(trace_csv, batches, cycles_upto, bytes_per_kind, fetch_csv=None,
+                   write_csv=None, copy_bytes=float(1 << 30)):
+    rows = list(csv.DictReader(open(trace_csv)))
+    sel = finest_sweeps(rows, batches, cycles_upto)
+    per = collections.defaultdict(list)
+    names = {}
+    for kind, cyc, r in sel:
+        per[kind].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        names[kind] = short_name(r["Kernel_Name"])
+    res = {"launches": len(sel), "batches": batches, "cycles_upto": cycles_upto, "per_kind": {}}
+    tot_ns, tot_b = 0, 0.0
+    for k in sorted(per):
+        v = per[k]
+        b = bytes_per_kind[k]
+        res["per_kind"][KIND_NAMES[k]] = {"kernel": names[k], "launches": len(v),
+                                          "avg_us": sum(v) / len(v) / 1e3, "bytes": b,
+                                          "GBps": b * len(v) / (sum(v) * 1e-9) / 1e9}
+        tot_ns += sum(v)
+        tot_b += b * len(v)
+    res["avg_launch_us"] = tot_ns / max(1, len(sel)) / 1e3
+    res["bytes_per_launch"] = tot_b / max(1, len(sel))
+    res["achieved_GBps"] = tot_b / (tot_ns * 1e-9) / 1e9 if tot_ns else None
+    if fetch_csv and write_csv:
+        fsel = _counter_sel(fetch_csv, "FETCH_SIZE", batches, cycles_upto)
+        wsel = _counter_sel(write_csv, "WRITE_SIZE", batches, cycles_upto)
+        cf = _copy_kib(fetch_csv, "FETCH_SIZE")
+        cw = _copy_kib(write_csv, "WRITE_SIZE")
+        fs = (copy_bytes / 1024.0) / cf if cf else None
+        ws = (copy_bytes / 1024.0) / cw if cw else None
+        tr = {}
+        for k in sorted(set(fsel) | set(wsel)):
+            fk, wk = fsel.get(k, []), wsel.get(k, [])
+            if fk and wk and fs and ws:
+                hbm = 1024.0 * (sum(fk) / len(fk) * fs + sum(wk) / len(wk) * ws)
+                tr[KIND_NAMES[k]] = {"dispatches": [len(fk), len(wk)], "fetch_kib": sum(fk) / len(fk),
+                                     "write_kib": sum(wk) / len(wk), "hbm_bytes": hbm,
+                                     "over_algorithmic": hbm / bytes_per_kind[k]}
+        res["traffic_per_kind"] = tr
+        res["fetch_scale"], res["write_scale"] = fs, ws
+        res["copy_fetch_kib"], res["copy_write_kib"] = cf, cw
+        if tr:
+            # weighted like the durations: by the launches of each kind
+            w = {KIND_NAMES[k]: len(per[k]) for k in per}
+            tot = sum(w[nm] for nm in tr)
+            res["hbm_bytes_per_launch"] = sum(tr[nm]["hbm_bytes"] * w[nm] for nm in tr) / tot
+    return res
+
+
+def _counter_sel(path, counter, batches, cycles_upto):
+    rows = [r for r in csv.DictReader(open(path)) if r.get("Counter_Name") == counter]
+    sel = finest_sweeps(rows, batches, cycles_upto)
+    d = collections.defaultdict(list)
+    for kind, _, r in sel:
+        d[kind].append(float(r["Counter_Value"]))
+    return d
+
+
+def _copy_kib(path, counter):
+    best = 0.0
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        nm = short_name(r["Kernel_Name"])
+        if nm in ("copyBuffer", "torch_elementwise") or "copy" in nm:
+            best = max(best, float(r["Counter_Value"]))
+    return best
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -147,7 +277,55 @@ def main():
     p.add_argument("--copy-bytes", type=float, default=float(1 << 30))
     p.add_argument("--tiles", default="",
                    help="TJ:TK:CHUNKS,TJ:TK:CHUNKS of the plain and the fused-correction sweep")
+    w = sub.add_parser("sweeps")
+    w.add_argument("csv")
+    w.add_argument("out")
+    w.add_argument("--batches", type=int, required=True)
+    w.add_argument("--cycles-upto", type=int, required=True)
+    w.add_argument("--bytes-per-kind", required=True,
+                   help="algorithmic bytes per launch of kinds 0,1,2,3")
+    w.add_argument("--title", required=True)
+    w.add_argument("--command", required=True)
+    w.add_argument("--stats", default="")
+    w.add_argument("--fetch", default="")
+    w.add_argument("--write", default="")
+    w.add_argument("--pmc-command", default="")
+    w.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    w.add_argument("--tiles", default="")
     a = ap.parse_args()
+    if a.cmd == "sweeps":
+        bpk = [float(x) for x in a.bytes_per_kind.split(",")]
+        res = sweeps_summary(a.csv, a.batches, a.cycles_upto, bpk, a.fetch or None,
+                             a.write or None, a.copy_bytes)
+        res["command"] = a.command
+        if a.pmc_command:
+            res["pmc_command"] = a.pmc_command
+        res["tiles"] = ([[int(x) for x in t.split(":")] for t in a.tiles.split(",")]
+                        if a.tiles else None)
+        res["kernel_source_sha256"] = source_hash()
+        lines = ["%s" % a.title, "command: %s" % a.command]
+        if a.pmc_command:
+            lines.append("counters: %s" % a.pmc_command)
+        lines += ["", "finest-grid sweeps, cycles 1..%d of the last %d batches (every solve active):"
+                  % (a.cycles_upto, a.batches),
+                  "%-18s %-40s %6s %10s %12s %9s" % ("kind", "kernel", "calls", "avg_us", "bytes", "GB/s")]
+        for nm, v in res["per_kind"].items():
+            lines.append("%-18s %-40s %6d %10.1f %12.4g %9.1f" % (nm, v["kernel"][:40], v["launches"],
+                                                                 v["avg_us"], v["bytes"], v["GBps"]))
+        lines.append("all kinds: %d launches, mean %.1f us, %.4g B algorithmic per launch, %.1f GB/s"
+                     % (res["launches"], res["avg_launch_us"], res["bytes_per_launch"],
+                        res["achieved_GBps"] or 0.0))
+        for nm, v in res.get("traffic_per_kind", {}).items():
+            lines.append("traffic %-18s %10.4g B per launch (%.3f x algorithmic)"
+                         % (nm, v["hbm_bytes"], v["over_algorithmic"]))
+        if a.stats:
+            lines += ["", "rocprofv3 --stats (every launch of the run, per kernel name):",
+                      stats_table(a.stats)]
+        lines += ["", "per kernel and launch grid (every launch of the run):", trace_table(a.csv)]
+        txt = "\n".join(lines) + "\n\n" + JSON_MARK + "\n" + json.dumps(res, indent=1) + "\n"
+        open(a.out, "w").write(txt)
+        print(txt)
+        return
     if a.cmd == "trace":
         txt = "%s\ncommand: %s\n\nper kernel and launch grid:\n%s\n" % (a.title, a.command,
                                                                   trace_table(a.csv))
