@@ -254,3 +254,80 @@ class LevelAcc(C.Structure):
         m, v = C.c_double(), C.c_double()
         lib().or_acc_result(C.byref(self), C.byref(m), C.byref(v))
         return m.value, v.value
+
+
+# ---- adaptive MLMC (Section 2.3, Algorithm 2) -------------------------------
+def quasioptimal_n(eps_s2, var, cost):
+    """Eq. (quasioptimal_Nl): N_l ~ eps_s^-2 (sum_k sqrt(s_k^2 C_k)) sqrt(s_l^2 / C_l),
+    rounded up; 0 for a level with s_l^2 = 0."""
+    import math
+    tot = sum(math.sqrt(v * c) for v, c in zip(var, cost))
+    return [int(math.ceil(tot * math.sqrt(v / c) / eps_s2)) if v > 0.0 else 0
+            for v, c in zip(var, cost)]
+
+
+def adaptive_mlmc(n0, max_level, eps, theta, alpha, n_init, seed0=0, sigma2=1.0, lam=0.1,
+                  tol=1e-8, max_iter=64):
+    """Algorithm 2 step by step on the oracle's samples.
+
+    Step 1: L = 1, N_0 = N_1 = N_Init.  Step 2: for every level, new samples
+    (sample i of level l has seed seed0 + i) until there are N_l; the level's
+    mean and s_l^2 (divisor N) and its cost C_l.  Step 3: N_l from eq.
+    (quasioptimal_Nl) with eps_s^2 = theta eps^2 (eq. def:eps), never below
+    the samples already taken; if |Yhat_L| > (8^alpha - 1) eps_b with
+    eps_b^2 = (1 - theta) eps^2 (the bias estimate, eq. bias_estimate) and
+    L < max_level, L -> L + 1 with N_L = N_Init.  Step 4: stop when no N_l
+    and not L changed.  Step 5: Q = sum of the level means.
+
+    Readings: C_l is the mean work of a sample of Y_l in node-cycles (fine
+    grid vertices x its cycles, plus the coarse grid's), which only enters
+    through ratios; the bias test takes the absolute value of Yhat_L.
+    Returns a dict with the final L, N, means, variances, costs, Q, the
+    sampling RMS sqrt(sum s_l^2 / N_l), the bias estimate, and `trace`: the
+    (L, N) after every step 3."""
+    import math
+    eps_s2 = theta * eps * eps
+    eps_b = math.sqrt((1.0 - theta) * eps * eps)
+    L = 1
+    N = [n_init, n_init]
+    accs, work, done = [], [], []
+    trace = []
+    it = 0
+    while True:
+        it += 1
+        while len(accs) < L + 1:
+            accs.append(LevelAcc())
+            work.append(0.0)
+            done.append(0)
+        for l in range(L + 1):
+            while done[l] < N[l]:
+                r = mlmc_sample(n0, l, seed0 + done[l], sigma2, lam, tol)
+                accs[l].add(r["Y"])
+                nf = grid_n(n0, l)
+                w = float(nf) ** 3 * r["cycles"][0]
+                if l > 0:
+                    w += float(grid_n(n0, l - 1)) ** 3 * r["cycles"][1]
+                work[l] += w
+                done[l] += 1
+        means = [a.result()[0] for a in accs[:L + 1]]
+        var = [a.result()[1] for a in accs[:L + 1]]
+        cost = [work[l] / done[l] for l in range(L + 1)]
+        newN = [max(N[l], q) for l, q in enumerate(quasioptimal_n(eps_s2, var, cost))]
+        changed = newN != N
+        N = newN
+        if abs(means[L]) > (8.0 ** alpha - 1.0) * eps_b and L < max_level:
+            L += 1
+            N.append(n_init)
+            changed = True
+        trace.append((L, list(N)))
+        if not changed or it >= max_iter:
+            break
+    means = [a.result()[0] for a in accs[:L + 1]]
+    var = [a.result()[1] for a in accs[:L + 1]]
+    cost = [work[l] / done[l] for l in range(L + 1)]
+    bias = abs(means[L]) / (8.0 ** alpha - 1.0)
+    return {"L": L, "N": N, "mean": means, "var": var, "cost": cost,
+            "Q": math.fsum(means),
+            "sampling_rms": math.sqrt(sum(v / n for v, n in zip(var, N))),
+            "bias_estimate": bias, "bias_ok": bias <= eps_b, "iterations": it,
+            "trace": trace}
