@@ -101,6 +101,23 @@ int mg_plan_set_stream(mg_plan plan, void* stream);
 int mg_solve(mg_plan plan, int n, const double* k, const double* f, double* u,
              double tol, int fixed_cycles, int* cycles, double* relres);
 
+/* Allocation-free variant of mg_solve, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, results and status
+ * codes as mg_solve (the same kernels, bit for bit), with these limits:
+ *   - the whole workspace (hierarchy, solve state, descriptor lists) lives
+ *     in a static device array of 96 MiB that the library holds on every GPU
+ *     it runs on until the process ends; no device or pinned host memory is
+ *     allocated or freed by the call;
+ *   - n <= 129 (the 129^3 hierarchy, FP64 or mixed precision, fits); larger
+ *     n returns MG_EINVAL;
+ *   - every call on one GPU uses the same array, which keeps the last call's
+ *     contents (each call clears what it needs).  Calls that overlapped on
+ *     one GPU would race: the library serialises them within a process (a
+ *     lock per device), and each call blocks until its solve is done. */
+int mg_solve_noalloc(mg_plan plan, int n, const double* k, const double* f, double* u,
+                     double tol, int fixed_cycles, int* cycles, double* relres);
+
 /* n_samples MLMC samples of Y_level (Algorithm 1, steps 1.a.i-ii): for each
  * seed s the normals xi(s, level) define omega; the solve on n_level and (for
  * level > 0) the solve on n_{level-1} use the same omega, with f = 1 and a

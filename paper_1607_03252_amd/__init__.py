@@ -73,6 +73,7 @@ def lib():
         L.mg_plan_destroy.argtypes = [vp]
         L.mg_plan_set_stream.argtypes = [vp, vp]
         L.mg_solve.argtypes = [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, ip, dp]
+        L.mg_solve_noalloc.argtypes = [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, ip, dp]
         L.mlmc_sample_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_uint64), C.c_int, vp, vp, vp,
                                         vp, C.c_int]
         L.mlmc_sample_mixed.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.c_int,
@@ -125,7 +126,7 @@ def exported_symbols():
             "mg_sched_submit", "mg_sched_admit", "mg_sched_release", "mg_sched_counts",
             "mg_serve_create", "mg_serve_destroy", "mg_serve_submit", "mg_serve_step",
             "mg_serve_now", "mg_serve_counts", "mg_serve_slots", "mg_set_tile_for",
-            "mg_get_tile_for", "mlmc_philox_words",
+            "mg_get_tile_for", "mlmc_philox_words", "mg_solve_noalloc",
             "mg_profile_records"]
 
 
@@ -245,6 +246,19 @@ def mg_solve(plan: Plan, n: int, k, f, u, tol: float = 0.0, fixed_cycles: int = 
     mg_plan_set_stream(plan)
     cyc, rel = C.c_int(0), C.c_double(0.0)
     st = lib().mg_solve(plan.handle, n, pk, pf, pu, tol, fixed_cycles, C.byref(cyc), C.byref(rel))
+    plan.check(st, (MG_OK, MG_ENOCONV))
+    return st, cyc.value, rel.value
+
+
+def mg_solve_noalloc(plan: Plan, n: int, k, f, u, tol: float = 0.0, fixed_cycles: int = 0):
+    """mg_solve on the library's static device workspace (n <= 129); returns
+    (status, cycles, relres) like mg_solve."""
+    N = n * n * n
+    pk, pf, pu = _ptr(k, "float64", N, "k"), _ptr(f, "float64", N, "f"), _ptr(u, "float64", N, "u")
+    mg_plan_set_stream(plan)
+    cyc, rel = C.c_int(0), C.c_double(0.0)
+    st = lib().mg_solve_noalloc(plan.handle, n, pk, pf, pu, tol, fixed_cycles, C.byref(cyc),
+                                C.byref(rel))
     plan.check(st, (MG_OK, MG_ENOCONV))
     return st, cyc.value, rel.value
 

@@ -22,6 +22,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -140,7 +141,18 @@ struct Batch {
   void* mem = nullptr;
   size_t bytes = 0;
   std::vector<void*> extra;
+  // a batch built over caller-provided device memory (the allocation-free
+  // solve): mem and every later dalloc are carved from it, nothing is freed
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_off = 0;
   void* dalloc(size_t bytes) {
+    if (arena) {
+      const size_t a = align256(bytes);
+      if (arena_off + a > arena_cap) throw HipError{hipErrorOutOfMemory, "static workspace full"};
+      void* p = arena + arena_off;
+      arena_off += a;
+      return p;
+    }
     void* p = nullptr;
     CK(hipMalloc(&p, bytes));
     extra.push_back(p);
@@ -156,8 +168,8 @@ struct Batch {
   ~Batch() {
     drop_graphs();
     for (void* p : extra) (void)hipFree(p);
-    if (mem) (void)hipFree(mem);
-    if (h_state) (void)hipHostFree(h_state);
+    if (mem && !arena) (void)hipFree(mem);
+    if (h_state && !arena) (void)hipHostFree(h_state);
     if (h_seeds) (void)hipHostFree(h_seeds);
   }
 };
@@ -218,9 +230,16 @@ struct mg_plan_s {
   std::vector<ProfRec> prof_recs;
   std::vector<std::pair<int, int>> ev_meta;
   int prof_cycle = 0;
+  // allocation-free solve: this device's static workspace and a small pinned
+  // host buffer for the per-solve state read back after each cycle (both
+  // set up at plan creation)
+  void* scratch = nullptr;
+  int scratch_dev = 0;
+  int* h_small = nullptr;
 
   ~mg_plan_s() {
     batch.reset();
+    if (h_small) (void)hipHostFree(h_small);
     for (auto& kv : d_phi) (void)hipFree(kv.second);
     if (d_coef) (void)hipFree(d_coef);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
@@ -259,7 +278,8 @@ static const double* phi_table(mg_plan_s* P, int n) {
 // Allocate a batch.  One device allocation holds every grid buffer.  With
 // size_only, only the bytes that allocation would take are computed.
 static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
-                                          size_t* size_only = nullptr) {
+                                          size_t* size_only = nullptr, char* arena = nullptr,
+                                          size_t arena_cap = 0) {
   auto B = std::make_unique<Batch>();
   B->spec = spec;
   B->st = P->work;
@@ -321,10 +341,21 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
         *size_only = total;
         return nullptr;
       }
-      if (P->desc.hbm_budget && total > P->desc.hbm_budget) return nullptr;
-      CK(hipMalloc(&B->mem, total));
-      // zero boundaries and state once; later kernels only write interiors
-      CK(hipMemsetAsync(B->mem, 0, total, P->work));
+      if (arena) {
+        if (total > arena_cap) return nullptr;
+        B->arena = arena;
+        B->arena_cap = arena_cap;
+        B->arena_off = total;
+        B->mem = arena;
+        // the static workspace keeps the last call's contents: clear it with
+        // a fill kernel (no memset node, no allocation)
+        launch_fill((double*)arena, (long)(total / sizeof(double)), 0.0, P->work);
+      } else {
+        if (P->desc.hbm_budget && total > P->desc.hbm_budget) return nullptr;
+        CK(hipMalloc(&B->mem, total));
+        // zero boundaries and state once; later kernels only write interiors
+        CK(hipMemsetAsync(B->mem, 0, total, P->work));
+      }
       B->bytes = total;
       cur = (char*)B->mem;
     } else {
@@ -340,7 +371,8 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
       B->ss.spart = sp;
     }
   }
-  CK(hipHostMalloc((void**)&B->h_state, sizeof(int) * 2 * ns, hipHostMallocDefault));
+  if (arena) B->h_state = P->h_small;  // one solve: two ints
+  else CK(hipHostMalloc((void**)&B->h_state, sizeof(int) * 2 * ns, hipHostMallocDefault));
   int nmax = 0;
   for (int n : spec.top_n) nmax = std::max(nmax, n);
   B->sizes = hierarchy(nmax);
@@ -1328,6 +1360,44 @@ static void serve_step(mg_server_s* S, int c) {
   }
 }
 
+}  // namespace mg
+
+// ---- allocation-free solve: a static device workspace ----------------------------
+//
+// mg_solve_noalloc runs the solve of mg_solve with its whole workspace (the
+// multigrid hierarchy, the solve state and the descriptor lists) carved from
+// one file-scope device array instead of device allocations.  Each GPU the
+// library runs on holds its own copy of the array until the process ends.
+// In host code the array's name is only a stand-in: its device address on
+// the current GPU comes from hipGetSymbolAddress, taken once per device (at
+// plan creation, with that device current) and kept in scratch_ptr.
+namespace mg {
+constexpr size_t kScratchBytes = (size_t)96 << 20;  // the 129^3 hierarchy (FP64 or mixed) + lists
+constexpr int kScratchMaxN = 129;
+constexpr int kScratchDevices = 64;
+}  // namespace mg
+
+static __device__ __align__(256) char scratch[mg::kScratchBytes];
+
+namespace mg {
+static std::mutex scratch_mu;                  // guards scratch_ptr
+static void* scratch_ptr[kScratchDevices];     // device address of `scratch` per device
+static std::mutex scratch_use[kScratchDevices];  // one allocation-free solve per device at a time
+
+// The device address of the static workspace on the current device (resolved
+// once per device); nullptr if HIP cannot resolve it.
+static void* scratch_for_current_device(int* dev_out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return nullptr;
+  *dev_out = dev;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    scratch_ptr[dev] = p;
+  }
+  return scratch_ptr[dev];
+}
 
 // The solve of mg_solve on a batch of one solve whose top u is the caller's.
 static int solve_one(mg_plan_s* P, Batch* B, int n, const double* k, const double* f, double* u,
@@ -1421,6 +1491,9 @@ int mg_plan_create(const mg_plan_desc* desc, mg_plan* out) {
     }
     CK(hipStreamCreateWithFlags(&P->work, hipStreamNonBlocking));
     CK(hipEventCreateWithFlags(&P->order_ev, hipEventDisableTiming));
+    P->scratch = scratch_for_current_device(&P->scratch_dev);
+    if (!P->scratch) throw HipError{hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)"};
+    CK(hipHostMalloc((void**)&P->h_small, 256, hipHostMallocDefault));
     double coef[64];
     const double sigma = std::sqrt(desc->sigma2);
     for (int a = 0; a < 4; ++a)
@@ -1534,6 +1607,53 @@ int mg_solve(mg_plan P, int n, const double* k, const double* f, double* u, doub
   if (!B) return status;
   const int st = solve_one(P, B, n, k, f, u, t, fixed_cycles, cycles, relres);
   if (P->prof) collect_profile(P);
+  return st;
+  API_END(P)
+}
+
+int mg_solve_noalloc(mg_plan P, int n, const double* k, const double* f, double* u, double tol,
+                     int fixed_cycles, int* cycles, double* relres) {
+  if (!P) return MG_EINVAL;
+  if (!valid_n(n) || !k || !f || !u || fixed_cycles < 0) {
+    P->err = "mg_solve_noalloc: n must be 2^m+1 (m>=1) and k, f, u non-null";
+    return MG_EINVAL;
+  }
+  if (n > kScratchMaxN) {
+    P->err = "mg_solve_noalloc: n above 129 exceeds the static workspace (96 MiB)";
+    return MG_EINVAL;
+  }
+  API_BEGIN
+  if (!P->scratch || !P->h_small) {
+    P->err = "mg_solve_noalloc: no static workspace on this plan's device";
+    return MG_EHIP;
+  }
+  const BatchSpec spec = solve_spec(P, n);
+  size_t need = 0;
+  build_batch(P, spec, &need);  // bytes only, no allocation
+  if (need > kScratchBytes - ((size_t)1 << 20)) {  // (1 MiB kept for the lists)
+    P->err = "mg_solve_noalloc: the hierarchy exceeds the static workspace";
+    return MG_EINVAL;
+  }
+  const double t = tol > 0.0 ? tol : P->desc.tol;
+  // every call on this device shares the array: one at a time in this process
+  std::lock_guard<std::mutex> g(scratch_use[P->scratch_dev]);
+  const bool prof = P->prof;  // no timing events in this path
+  P->prof = false;
+  order_after_caller(P);
+  std::unique_ptr<Batch> B = build_batch(P, spec, nullptr, (char*)P->scratch, kScratchBytes);
+  int st = MG_EINVAL;
+  if (B) {
+    B->st = P->work;
+    try {
+      st = solve_one(P, B.get(), n, k, f, u, t, fixed_cycles, cycles, relres);
+    } catch (...) {
+      P->prof = prof;
+      throw;
+    }
+  } else {
+    P->err = "mg_solve_noalloc: the hierarchy exceeds the static workspace";
+  }
+  P->prof = prof;
   return st;
   API_END(P)
 }
