@@ -69,6 +69,14 @@ def lib():
         L.or_mlmc_sample.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_double, C.c_double,
                                      C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                      dp, dp, dp, ip]
+        L.or_point_qoi.argtypes = [C.c_int, dp]
+        L.or_point_qoi.restype = C.c_double
+        L.or_flux_qoi.argtypes = [C.c_int, dp, dp]
+        L.or_flux_qoi.restype = C.c_double
+        L.or_fmg.argtypes = [C.c_int, dp, dp, dp, C.c_int, C.c_int, C.c_int]
+        L.or_mlmc_sample_ex.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_double, C.c_double,
+                                        C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                        C.c_int, C.c_int, dp, dp, dp, ip]
         L.or_sum.argtypes = [dp, C.c_long]
         L.or_sum.restype = C.c_double
         _lib = L
@@ -211,6 +219,40 @@ def mlmc_sample(n0, level, seed, sigma2=1.0, lam=0.1, tol=1e-8, max_cycles=50,
     st = lib().or_mlmc_sample(n0, level, seed, sigma2, lam, nu1, nu2, tol, max_cycles,
                               fixed_cycles, C.byref(Y), C.byref(Qf), C.byref(Qc), cyc)
     _check(st, "mlmc_sample")
+    return dict(Y=Y.value, Qf=Qf.value, Qc=Qc.value, cycles=(cyc[0], cyc[1]))
+
+
+def point_qoi(u):
+    """u(1/4, 1/4, 1/4) (Section 3's point QoI; n = 4m + 1)."""
+    return lib().or_point_qoi(u.shape[0], _d(np.ascontiguousarray(u)))
+
+
+def flux_qoi(k, u):
+    """Flux of -k grad u in +x_2 across x_2 = 1/4 (Section 3's flux QoI)."""
+    return lib().or_flux_qoi(k.shape[0], _d(k), _d(np.ascontiguousarray(u)))
+
+
+def fmg(k, f, nu1=4, nu2=4, ncycles=2):
+    """Full multigrid (Section 7.1's FMG-ncycles V(nu1,nu2)); f: vertex values."""
+    n = k.shape[0]
+    u = np.zeros_like(k)
+    _check(lib().or_fmg(n, _d(k), _d(np.ascontiguousarray(f, dtype=np.float64)), _d(u), nu1, nu2,
+                        ncycles), "fmg")
+    return u
+
+
+QOI_KINDS = {"integral": 0, "point": 1, "flux": 2}
+
+
+def mlmc_sample_ex(n0, level, seed, sigma2=1.0, lam=0.1, solver="vcycle", qoi="integral",
+                   nu1=2, nu2=2, fmg_cycles=2, tol=1e-8, max_cycles=50, fixed_cycles=0):
+    """One sample with solver 'vcycle' (to tol) or 'fmg' and a QoI kind."""
+    Y, Qf, Qc = C.c_double(), C.c_double(), C.c_double()
+    cyc = (C.c_int * 2)()
+    st = lib().or_mlmc_sample_ex(n0, level, seed, sigma2, lam, nu1, nu2,
+                                 1 if solver == "fmg" else 0, fmg_cycles, QOI_KINDS[qoi], tol,
+                                 max_cycles, fixed_cycles, C.byref(Y), C.byref(Qf), C.byref(Qc), cyc)
+    _check(st, "mlmc_sample_ex")
     return dict(Y=Y.value, Qf=Qf.value, Qc=Qc.value, cycles=(cyc[0], cyc[1]))
 
 

@@ -441,6 +441,87 @@ double or_qoi(int n, const double *u) {
   return h * h * h * (s + c);
 }
 
+/* Point QoI of Section 3: Q(u) = u(x*) at x* = (1/4, 1/4, 1/4), the vertex
+ * ((n-1)/4, (n-1)/4, (n-1)/4) for n = 4m + 1 (the paper's point in its
+ * Section 7.1 experiments). */
+double or_point_qoi(int n, const double *u) {
+  if (n < 5 || ((n - 1) % 4) != 0) return 0.0;
+  int c = (n - 1) / 4;
+  return u[IDX(n, c, c, c)];
+}
+
+/* Flux QoI of Section 3 across Gamma = {x_2 = 1/4} (the plane of the
+ * Section 7.2 experiments), as the flux of -k grad u in the +x_2 direction
+ * with |Gamma| = 1.  x_2 is the j index; the plane is the vertex plane
+ * j* = (n-1)/4.  The discrete flux through the face plane between vertex
+ * planes a and a+1 is h^2 sum over interior (i,k) of c * (u(a) - u(a+1)) / h
+ * with the operator's face coefficient c; the flux through Gamma is the mean
+ * of the face planes j* - 1/2 and j* + 1/2 (second order). */
+double or_flux_qoi(int n, const double *k, const double *u) {
+  if (n < 5 || ((n - 1) % 4) != 0) return 0.0;
+  int js = (n - 1) / 4;
+  double h = 1.0 / (double)(n - 1);
+  double F[2];
+  for (int side = 0; side < 2; ++side) {
+    int a = js - 1 + side; /* face between planes a and a + 1 */
+    double s = 0.0, c = 0.0;
+    for (int i = 1; i < n - 1; ++i)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        size_t p = IDX(n, i, a, kk), q = IDX(n, i, a + 1, kk);
+        double x = hmean(k[p], k[q]) * (uval(n, u, p) - uval(n, u, q));
+        double t = s + x;
+        if (fabs(s) >= fabs(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+      }
+    F[side] = h * (s + c);
+  }
+  return 0.5 * (F[0] + F[1]);
+}
+
+/* Full multigrid (nested iteration, the FMG-nu V(nu1,nu2) schedule of
+ * Section 7.1): on every grid of the hierarchy the problem itself is
+ * discretised (coefficient and f injected, b' = h_j^2 f); the 3^3 grid is
+ * solved exactly; each finer grid starts from the trilinear interpolation of
+ * the coarser grid's result and runs ncycles V(nu1,nu2) cycles.  u (n^3)
+ * receives the finest grid's result; f is an n^3 array of vertex values. */
+int or_fmg(int n, const double *k, const double *f, double *u, int nu1, int nu2, int ncycles) {
+  if (!valid_n(n) || nu1 < 0 || nu2 < 0 || ncycles < 1) return OR_EINVAL;
+  int nl = 0, ns[32];
+  for (int m = n; ; m = (m - 1) / 2 + 1) {
+    ns[nl++] = m;
+    if (m == 3) break;
+  }
+  double *K[32], *B[32], *U[32];
+  for (int j = 0; j < nl; ++j) {
+    size_t N = (size_t)ns[j] * ns[j] * ns[j];
+    K[j] = (double *)malloc(sizeof(double) * N);
+    B[j] = (double *)malloc(sizeof(double) * N);
+    U[j] = (double *)calloc(N, sizeof(double));
+  }
+  /* coefficients and f injected level by level; b' = h_j^2 f */
+  memcpy(K[0], k, sizeof(double) * (size_t)n * n * n);
+  memcpy(B[0], f, sizeof(double) * (size_t)n * n * n);
+  for (int j = 1; j < nl; ++j) {
+    or_inject(ns[j - 1], K[j - 1], K[j]);
+    or_inject(ns[j - 1], B[j - 1], B[j]);
+  }
+  for (int j = 0; j < nl; ++j) {
+    size_t N = (size_t)ns[j] * ns[j] * ns[j];
+    double h = 1.0 / (double)(ns[j] - 1);
+    for (size_t p = 0; p < N; ++p) B[j][p] *= h * h;
+  }
+  /* coarsest: the single unknown exactly */
+  vcycle_rec(3, K[nl - 1], B[nl - 1], U[nl - 1], nu1, nu2);
+  for (int j = nl - 2; j >= 0; --j) {
+    or_prolong_add(ns[j + 1], U[j + 1], U[j]); /* U[j] = 0 + P U[j+1] */
+    for (int c = 0; c < ncycles; ++c) vcycle_rec(ns[j], K[j], B[j], U[j], nu1, nu2);
+  }
+  memcpy(u, U[0], sizeof(double) * (size_t)n * n * n);
+  for (int j = 0; j < nl; ++j) { free(K[j]); free(B[j]); free(U[j]); }
+  return OR_OK;
+}
+
 /* Solve one grid for one sample: field, right-hand side h^2 * f with f = 1,
  * zero initial guess, V-cycles, QoI. */
 static int solve_q(int n, double sigma2, double lambda, const double xi[64], int nu1, int nu2,
@@ -474,6 +555,61 @@ int or_mlmc_sample(int n0, int level, uint64_t seed, double sigma2, double lambd
     int nc = (n0 - 1) * (1 << (level - 1)) + 1;
     st2 = solve_q(nc, sigma2, lambda, xi, nu1, nu2, tol, max_cycles, fixed_cycles, &qc, &cc);
   }
+  if (Qf) *Qf = qf;
+  if (Qc) *Qc = qc;
+  if (Y) *Y = qf - qc;
+  if (cycles) { cycles[0] = cf; cycles[1] = cc; }
+  return st ? st : st2;
+}
+
+/* One sample with a chosen solver and QoI: solver 0 = V(nu1,nu2) cycles to
+ * tol (or fixed_cycles) from zero, 1 = FMG with fmg_cycles V(nu1,nu2) cycles
+ * per grid; qoi 0 = integral of u, 1 = u(1/4,1/4,1/4), 2 = flux across
+ * x_2 = 1/4.  Both solves of a pair use the same normals xi(seed, level).
+ * cycles[] receives the V-cycles run on the top grid of each solve. */
+static int solve_q_ex(int n, double sigma2, double lambda, const double xi[64], int nu1, int nu2,
+                      int solver, int fmg_cycles, int qoi, double tol, int max_cycles,
+                      int fixed_cycles, double *Q, int *cycles) {
+  size_t N = (size_t)n * n * n;
+  double *k = (double *)malloc(sizeof(double) * N);
+  double *b = (double *)malloc(sizeof(double) * N);
+  double *u = (double *)calloc(N, sizeof(double));
+  if (!k || !b || !u) { free(k); free(b); free(u); return OR_EINVAL; }
+  int st = or_field(n, sigma2, lambda, xi, k);
+  double h = 1.0 / (double)(n - 1);
+  if (!st && solver == 1) {
+    for (size_t p = 0; p < N; ++p) b[p] = 1.0; /* f = 1 */
+    st = or_fmg(n, k, b, u, nu1, nu2, fmg_cycles);
+    *cycles = fmg_cycles;
+  } else if (!st) {
+    for (size_t p = 0; p < N; ++p) b[p] = h * h * 1.0;
+    st = or_solve(n, k, b, u, nu1, nu2, tol, max_cycles, fixed_cycles, cycles, NULL, NULL);
+  }
+  *Q = qoi == 1 ? or_point_qoi(n, u) : qoi == 2 ? or_flux_qoi(n, k, u) : or_qoi(n, u);
+  free(k); free(b); free(u);
+  return st;
+}
+
+int or_mlmc_sample_ex(int n0, int level, uint64_t seed, double sigma2, double lambda,
+                      int nu1, int nu2, int solver, int fmg_cycles, int qoi, double tol,
+                      int max_cycles, int fixed_cycles, double *Y, double *Qf, double *Qc,
+                      int cycles[2]) {
+  if (!valid_n(n0) || level < 0 || level > 12 || solver < 0 || solver > 1 || qoi < 0 || qoi > 2)
+    return OR_EINVAL;
+  int nf = (n0 - 1) * (1 << level) + 1;
+  int nc = level > 0 ? (n0 - 1) * (1 << (level - 1)) + 1 : 0;
+  if (qoi > 0 && ((nf - 1) % 4 != 0 || nf < 5 || (level > 0 && ((nc - 1) % 4 != 0 || nc < 5))))
+    return OR_EINVAL;
+  double xi[64];
+  or_gaussians(seed, (uint32_t)level, xi);
+  double qf = 0.0, qc = 0.0;
+  int cf = 0, cc = 0;
+  int st = solve_q_ex(nf, sigma2, lambda, xi, nu1, nu2, solver, fmg_cycles, qoi, tol, max_cycles,
+                      fixed_cycles, &qf, &cf);
+  int st2 = OR_OK;
+  if (level > 0)
+    st2 = solve_q_ex(nc, sigma2, lambda, xi, nu1, nu2, solver, fmg_cycles, qoi, tol, max_cycles,
+                     fixed_cycles, &qc, &cc);
   if (Qf) *Qf = qf;
   if (Qc) *Qc = qc;
   if (Y) *Y = qf - qc;

@@ -67,12 +67,28 @@ int or_solve(int n, const double *k, const double *b, double *u, int nu1, int nu
 /* Q = h^3 * sum of u over interior vertices (compensated). */
 double or_qoi(int n, const double *u);
 
+/* Point QoI u(1/4, 1/4, 1/4) (n = 4m + 1). */
+double or_point_qoi(int n, const double *u);
+/* Flux of -k grad u in +x_2 across the plane x_2 = 1/4 (n = 4m + 1). */
+double or_flux_qoi(int n, const double *k, const double *u);
+/* Full multigrid: exact 3^3 solve, then on each finer grid trilinear
+ * interpolation of the coarser result and ncycles V(nu1,nu2) cycles. */
+int or_fmg(int n, const double *k, const double *f, double *u, int nu1, int nu2, int ncycles);
+
 /* One MLMC sample Y_level = Q(n_level) - Q(n_level-1) (Y_0 = Q(n_0)), with
  * n_level = (n0-1) 2^level + 1, f = 1, u0 = 0, both solves from the same
  * normals xi(seed, level).  Qc = 0 and cycles[1] = 0 for level 0. */
 int or_mlmc_sample(int n0, int level, uint64_t seed, double sigma2, double lambda,
                    int nu1, int nu2, double tol, int max_cycles, int fixed_cycles,
                    double *Y, double *Qf, double *Qc, int cycles[2]);
+
+/* As or_mlmc_sample with a solver (0 = V-cycles to tol, 1 = FMG with
+ * fmg_cycles V(nu1,nu2) cycles per grid) and a QoI (0 = integral of u,
+ * 1 = u(1/4,1/4,1/4), 2 = flux across x_2 = 1/4). */
+int or_mlmc_sample_ex(int n0, int level, uint64_t seed, double sigma2, double lambda,
+                      int nu1, int nu2, int solver, int fmg_cycles, int qoi, double tol,
+                      int max_cycles, int fixed_cycles, double *Y, double *Qf, double *Qc,
+                      int cycles[2]);
 
 /* Compensated (Neumaier) summation of a vector. */
 double or_sum(const double *x, long n);
