@@ -85,6 +85,9 @@ void mg_plan_desc_default(mg_plan_desc* d);
 int mg_plan_create(const mg_plan_desc* desc, mg_plan* out);
 int mg_plan_destroy(mg_plan plan);
 
+/* Copy the description the plan was created with into *out (host). */
+int mg_plan_get_desc(mg_plan plan, mg_plan_desc* out);
+
 /* Switch the stream later calls run on (e.g. torch's current stream). */
 int mg_plan_set_stream(mg_plan plan, void* stream);
 
@@ -309,6 +312,60 @@ void mlmc_acc_init(mlmc_level_acc* a);
 int mlmc_acc_add(mlmc_level_acc* a, const double* y, int count, int on_device);
 /* mean = shift + S1/N, var = S2/N - (S1/N)^2 (N = count so far). */
 void mlmc_acc_result(const mlmc_level_acc* a, double* mean, double* var);
+
+/* Adaptive MLMC (Section 2.3, Algorithm 2) --------------------------------
+ *
+ * Step 1: L = 1, N_0 = N_1 = N_Init.  Step 2: for every level l <= L the
+ * missing samples of Y_l (sample i of level l has seed seed0 + i, computed
+ * with mlmc_sample_mixed, every level in the same batches of at most
+ * max_batch samples), then the level mean, s_l^2 (divisor N) and the cost
+ * C_l.  Step 3: N_l from eq. (quasioptimal_Nl) with eps_s^2 = theta eps^2
+ * (eq. def:eps), never below the samples already taken; if
+ * |Yhat_L| > (8^alpha - 1) eps_b with eps_b^2 = (1 - theta) eps^2 (the bias
+ * estimate of eq. bias_estimate) and L < the plan's max_level, L -> L + 1
+ * with N_L = N_Init.  Step 4: repeat from step 2 until neither any N_l nor L
+ * changed (or max_iter rounds).  Step 5: Q = sum of the level means.
+ * C_l is the mean work of one sample of Y_l in node-cycles (grid vertices
+ * times V-cycles of each of its solves); only cost ratios enter step 3.
+ * The plan's description fixes n0, the field, the solver and max_level
+ * (>= 1, at most MLMC_MAX_LEVELS - 1). */
+#define MLMC_MAX_LEVELS 11
+#define MLMC_MAX_TRACE 64
+typedef struct {
+  double eps;       /* target root mean square error (> 0)                       */
+  double theta;     /* share of eps^2 given to the sampling error, in (0, 1)     */
+  double alpha;     /* bias rate: |E[Q_l - Q]| ~ M_l^-alpha, M_l ~ 8^l M_0 (> 0) */
+  int n_init;       /* N_Init (>= 2)                                             */
+  int max_iter;     /* rounds of steps 2-4 at most (>= 1)                        */
+  int max_batch;    /* samples per device batch (>= 1)                           */
+  uint64_t seed0;   /* sample i of every level uses seed seed0 + i               */
+} mlmc_adaptive_desc;
+
+typedef struct {
+  int status;                         /* MG_OK                                    */
+  int L;                              /* finest level used                        */
+  int iterations;                     /* rounds of steps 2-4                      */
+  int bias_ok;                        /* 1 if the bias estimate is <= eps_b       */
+  long long N[MLMC_MAX_LEVELS];       /* samples per level (levels 0..L)          */
+  double mean[MLMC_MAX_LEVELS];       /* Yhat_l                                   */
+  double var[MLMC_MAX_LEVELS];        /* s_l^2, divisor N_l                       */
+  double cost[MLMC_MAX_LEVELS];       /* C_l in node-cycles per sample            */
+  double Q;                           /* sum of the level means (compensated)     */
+  double sampling_rms;                /* sqrt(sum_l s_l^2 / N_l)                   */
+  double bias_estimate;               /* |Yhat_L| / (8^alpha - 1)                 */
+  int trace_len;                      /* rounds recorded below (<= MLMC_MAX_TRACE) */
+  int trace_L[MLMC_MAX_TRACE];        /* L after step 3 of each round             */
+  long long trace_N[MLMC_MAX_TRACE][MLMC_MAX_LEVELS];  /* N_l after step 3       */
+} mlmc_adaptive_result;
+
+/* Defaults: eps = 1e-3, theta = 0.5, alpha = 2/3, N_Init = 32, 64 rounds,
+ * batches of 256, seed0 = 0. */
+void mlmc_adaptive_desc_default(mlmc_adaptive_desc* d);
+/* Run Algorithm 2 on the plan.  *desc and *result are host memory (result
+ * caller-owned, fully overwritten).  Blocking.  Returns MG_OK, MG_EINVAL (bad
+ * description, or a plan with max_level < 1), MG_ENOCONV (a solve missed
+ * its tolerance; the run stops there), MG_ENOMEM or MG_EHIP. */
+int mlmc_adaptive(mg_plan plan, const mlmc_adaptive_desc* desc, mlmc_adaptive_result* result);
 
 /* Kernel timing: when enabled, the plan records HIP events around every
  * launch of the smoothing kernel on the finest grids of a batch (on the

@@ -51,6 +51,24 @@ class mg_result(C.Structure):
                 ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
+MLMC_MAX_LEVELS, MLMC_MAX_TRACE = 11, 64
+
+
+class mlmc_adaptive_desc(C.Structure):
+    _fields_ = [("eps", C.c_double), ("theta", C.c_double), ("alpha", C.c_double),
+                ("n_init", C.c_int), ("max_iter", C.c_int), ("max_batch", C.c_int),
+                ("seed0", C.c_uint64)]
+
+
+class mlmc_adaptive_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("L", C.c_int), ("iterations", C.c_int), ("bias_ok", C.c_int),
+                ("N", C.c_longlong * MLMC_MAX_LEVELS), ("mean", C.c_double * MLMC_MAX_LEVELS),
+                ("var", C.c_double * MLMC_MAX_LEVELS), ("cost", C.c_double * MLMC_MAX_LEVELS),
+                ("Q", C.c_double), ("sampling_rms", C.c_double), ("bias_estimate", C.c_double),
+                ("trace_len", C.c_int), ("trace_L", C.c_int * MLMC_MAX_TRACE),
+                ("trace_N", (C.c_longlong * MLMC_MAX_LEVELS) * MLMC_MAX_TRACE)]
+
+
 class mlmc_level_acc(C.Structure):
     _fields_ = [("n", C.c_longlong), ("shift", C.c_double), ("s1", C.c_double),
                 ("c1", C.c_double), ("s2", C.c_double), ("c2", C.c_double)]
@@ -72,6 +90,10 @@ def lib():
         L.mg_plan_create.argtypes = [C.POINTER(mg_plan_desc), C.POINTER(vp)]
         L.mg_plan_destroy.argtypes = [vp]
         L.mg_plan_set_stream.argtypes = [vp, vp]
+        L.mg_plan_get_desc.argtypes = [vp, C.POINTER(mg_plan_desc)]
+        L.mlmc_adaptive_desc_default.argtypes = [C.POINTER(mlmc_adaptive_desc)]
+        L.mlmc_adaptive_desc_default.restype = None
+        L.mlmc_adaptive.argtypes = [vp, C.POINTER(mlmc_adaptive_desc), C.POINTER(mlmc_adaptive_result)]
         L.mg_solve.argtypes = [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, ip, dp]
         L.mg_solve_noalloc.argtypes = [vp, C.c_int, vp, vp, vp, C.c_double, C.c_int, ip, dp]
         L.mlmc_sample_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_uint64), C.c_int, vp, vp, vp,
@@ -127,7 +149,8 @@ def exported_symbols():
             "mg_serve_create", "mg_serve_destroy", "mg_serve_submit", "mg_serve_step",
             "mg_serve_now", "mg_serve_counts", "mg_serve_slots", "mg_set_tile_for",
             "mg_get_tile_for", "mlmc_philox_words", "mg_solve_noalloc",
-            "mg_profile_records"]
+            "mg_profile_records", "mg_plan_get_desc", "mlmc_adaptive_desc_default",
+            "mlmc_adaptive"]
 
 
 def _torch():
@@ -322,6 +345,25 @@ def mlmc_field(plan: Plan, n: int, seed: int, level: int, k_out):
     pk = _ptr(k_out, "float64", n * n * n, "k_out")
     mg_plan_set_stream(plan)
     return plan.check(lib().mlmc_field(plan.handle, n, seed, level, pk))
+
+
+def mlmc_adaptive(plan: Plan, eps: float, theta: float = 0.5, alpha: float = 2.0 / 3.0,
+                  n_init: int = 32, max_iter: int = 64, max_batch: int = 256, seed0: int = 0):
+    """Algorithm 2 on the plan's samples; returns a dict like the C result."""
+    d = mlmc_adaptive_desc()
+    lib().mlmc_adaptive_desc_default(C.byref(d))
+    d.eps, d.theta, d.alpha = eps, theta, alpha
+    d.n_init, d.max_iter, d.max_batch, d.seed0 = n_init, max_iter, max_batch, seed0
+    r = mlmc_adaptive_result()
+    mg_plan_set_stream(plan)
+    plan.check(lib().mlmc_adaptive(plan.handle, C.byref(d), C.byref(r)))
+    L = r.L
+    return {"L": L, "N": [r.N[l] for l in range(L + 1)], "mean": [r.mean[l] for l in range(L + 1)],
+            "var": [r.var[l] for l in range(L + 1)], "cost": [r.cost[l] for l in range(L + 1)],
+            "Q": r.Q, "sampling_rms": r.sampling_rms, "bias_estimate": r.bias_estimate,
+            "bias_ok": bool(r.bias_ok), "iterations": r.iterations,
+            "trace": [(r.trace_L[t], [r.trace_N[t][l] for l in range(r.trace_L[t] + 1)])
+                      for t in range(r.trace_len)]}
 
 
 def mlmc_acc_init() -> mlmc_level_acc:

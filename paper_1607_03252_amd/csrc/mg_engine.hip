@@ -1518,6 +1518,12 @@ int mg_plan_destroy(mg_plan P) {
   return MG_OK;
 }
 
+int mg_plan_get_desc(mg_plan P, mg_plan_desc* out) {
+  if (!P || !out) return MG_EINVAL;
+  *out = P->desc;
+  return MG_OK;
+}
+
 int mg_plan_set_stream(mg_plan P, void* stream) {
   if (!P) return MG_EINVAL;
   P->caller = (hipStream_t)stream;
