@@ -170,6 +170,24 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *               still cycle, the remaining cycles run on those solves' grids
  *               only (more plane pieces per grid); 0 = always on the whole
  *               batch (same results, bit for bit).
+ * Options that change what the samples compute (mlmc_sample_batch and
+ * mlmc_sample_mixed; the server supports only the defaults):
+ *   "qoi":      0 (default) = Q = integral of u over D; 1 = u at
+ *               x* = (1/4, 1/4, 1/4); 2 = the flux of -k grad u in the +x_2
+ *               direction across the plane x_2 = 1/4 (|Gamma| = 1), the mean
+ *               of the discrete face fluxes on either side of that vertex
+ *               plane (Section 3's two other QoIs; 1 and 2 need n0 = 4m + 1);
+ *   "solver":   0 (default) = V(nu1,nu2) cycles from zero until tol;
+ *               1 = full multigrid (nested iteration, Section 7.1): the 3^3
+ *               grid solved exactly, then on every finer grid the trilinear
+ *               interpolation of the coarser result and "fmg_cycles"
+ *               V(nu1,nu2) cycles against that grid's own problem; FMG-2V(4,4)
+ *               is nu1 = nu2 = 4 in the plan and fmg_cycles = 2.  The coarse
+ *               solve of Y_l is the fine schedule's n_(l-1) stage.  FP64 only
+ *               (MG_ENOTIMPL on a mixed-precision plan); cycles_out reports
+ *               fmg_cycles; fixed_cycles is ignored;
+ *   "fmg_cycles": V-cycles per grid of the full multigrid schedule (1..64,
+ *               default 2).
  * Returns MG_EINVAL for an unknown name or value. */
 int mg_plan_set_option(mg_plan plan, const char* name, long long value);
 

@@ -159,6 +159,10 @@ struct Batch {
     return p;
   }
   hipGraphExec_t tail_graph = nullptr;  // one cycle on L64t
+  // full multigrid stage: the top descriptors with uc = the previous stage's
+  // top iterates (link_src: that stage's batch)
+  GridDesc* d_link = nullptr;
+  const Batch* link_src = nullptr;
   void drop_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
@@ -212,6 +216,11 @@ struct mg_plan_s {
   int tail_lists = 1;    // 1: a batch's last cycles run on its unfinished solves only
   int norm_sweep = 1;    // 1: a cycle's first sweep also takes the residual norm of
                          // the previous iterate (convergence judged one cycle late)
+  int qoi_kind = QOI_INTEGRAL;  // the samples' QoI (Section 3)
+  int solver = 0;        // 0: V-cycles to tol, 1: full multigrid (fixed schedule)
+  int fmg_cycles = 2;    // V-cycles per grid of the full multigrid schedule
+  // full multigrid: one batch per grid size of the schedule (n -> batch)
+  std::map<int, std::unique_ptr<Batch>> fmg;
   std::map<int, SweepShape> shape;      // tile shape per grid size
   std::map<int, SweepShape> shape_pro;  // same, sweeps with the fused coarse correction
   // profiling of the finest-grid smoothing launches
@@ -239,6 +248,7 @@ struct mg_plan_s {
 
   ~mg_plan_s() {
     batch.reset();
+    fmg.clear();
     if (h_small) (void)hipHostFree(h_small);
     for (auto& kv : d_phi) (void)hipFree(kv.second);
     if (d_coef) (void)hipFree(d_coef);
@@ -1021,11 +1031,23 @@ static int run_samples(mg_plan_s* P, const std::vector<int>& levels, const uint6
     launch_ydiff(B->ss.q, B->d_fi, B->d_ci, n_samples, Y_out, Qf_out, Qc_out, B->ss.cycles,
                  cycles_out, st);
   };
-  const bool ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0,
-                             [&]() { qoi(RED_QOI_PENDING); }, 1);
-  if (!ok) {
-    // solves that missed tol never stopped: their QoI from the last iterate
-    qoi(RED_QOI);
+  bool ok;
+  if (P->qoi_kind == QOI_INTEGRAL) {
+    ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0,
+                    [&]() { qoi(RED_QOI_PENDING); }, 1);
+    if (!ok) {
+      // solves that missed tol never stopped: their QoI from the last iterate
+      qoi(RED_QOI);
+      CK(hipStreamSynchronize(st));
+    }
+  } else {
+    // the point value or the plane flux, once every solve has stopped (the
+    // top iterates are in buffer 0)
+    ok = run_solves(P, B, P->desc.tol, fixed_cycles, fixed_cycles == 0);
+    for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
+      launch_qoi_pf(B->L64.dtop[ti], (int)B->L64.htop[ti].size(), P->qoi_kind, B->ss.q, st);
+    launch_ydiff(B->ss.q, B->d_fi, B->d_ci, n_samples, Y_out, Qf_out, Qc_out, B->ss.cycles,
+                 cycles_out, st);
     CK(hipStreamSynchronize(st));
   }
   if (P->prof) collect_profile(P);
@@ -1036,6 +1058,147 @@ static int run_samples(mg_plan_s* P, const std::vector<int>& levels, const uint6
   return MG_OK;
 }
 
+
+// ---- full multigrid samples (Section 7.1's FMG-nu V(nu1,nu2) schedule) -----------
+//
+// Nested iteration on every solve of a sample: the 3^3 grid solved exactly,
+// then on each finer grid size the trilinear interpolation of the coarser
+// grid's result as initial guess and fmg_cycles V(nu1,nu2) cycles against
+// that grid's own problem (f = 1: b' = h^2).  One batch per grid size holds
+// the samples' grids of that size with their coefficient hierarchies (the
+// field evaluated at that size's vertices: the same formula at the same
+// dyadic points as injection).  The schedule of the fine solve of Y_l passes
+// through the coarse solve's whole schedule, so both QoIs of a sample come
+// from one pass: Q_f from the n_l stage, Q_c from the n_(l-1) stage.
+
+static Batch* fmg_stage(mg_plan_s* P, int n, int S) {
+  auto& slot = P->fmg[n];
+  if (!slot || slot->ns != S) {
+    slot.reset();
+    BatchSpec spec;
+    spec.top_n.assign(S, n);
+    spec.share.assign(S, -1);
+    spec.const_b_top = true;
+    spec.ext_u_top = false;
+    spec.mixed = false;
+    auto B = build_batch(P, spec);
+    if (!B) return nullptr;
+    upload_lists(P, B.get());
+    B->nsamples = S;
+    B->d_seeds = (uint64_t*)B->dalloc(sizeof(uint64_t) * S);
+    B->d_levels = (int*)B->dalloc(sizeof(int) * S);
+    B->d_normals = (double*)B->dalloc(sizeof(double) * 64 * S);
+    B->d_fi = (int*)B->dalloc(sizeof(int) * S);  // output position of each sample
+    Batch::FieldGroup g;
+    g.n = n;
+    g.count = S;
+    g.d_out = (double**)B->dalloc(sizeof(double*) * S);
+    g.d_xi = (int*)B->dalloc(sizeof(int) * S);
+    std::vector<double*> outs(S);
+    std::vector<int> xi(S);
+    for (int i = 0; i < S; ++i) {
+      outs[i] = B->lev[i][0].wh;
+      xi[i] = i;
+    }
+    CK(hipMemcpy(g.d_out, outs.data(), sizeof(double*) * S, hipMemcpyHostToDevice));
+    CK(hipMemcpy(g.d_xi, xi.data(), sizeof(int) * S, hipMemcpyHostToDevice));
+    B->fields.push_back(g);
+    slot = std::move(B);
+  }
+  return slot.get();
+}
+
+// The top descriptors of `fine` with uc[0] = the top iterate of the same
+// sample in `coarse` (the previous stage), for the interpolation.
+static GridDesc* fmg_link(Batch* fine, Batch* coarse) {
+  if (fine->link_src == coarse && fine->d_link) return fine->d_link;
+  const int S = fine->ns;
+  std::vector<GridDesc> h = fine->L64.htop[0];
+  for (int i = 0; i < S; ++i) {
+    h[i].uc[0] = coarse->lev[i][0].u[0];
+    h[i].uc[1] = coarse->lev[i][0].u[0];
+  }
+  if (!fine->d_link) fine->d_link = (GridDesc*)fine->dalloc(sizeof(GridDesc) * S);
+  CK(hipMemcpy(fine->d_link, h.data(), sizeof(GridDesc) * S, hipMemcpyHostToDevice));
+  fine->link_src = coarse;
+  return fine->d_link;
+}
+
+// Samples of one level by full multigrid; out_pos[i]: the output position of
+// sample i.  Every stage runs a fixed schedule, so no solve can miss a tol.
+static int run_fmg_level(mg_plan_s* P, int level, const uint64_t* seeds,
+                         const std::vector<int>& out_pos, double* Y_out, double* Qf_out,
+                         double* Qc_out, int* cycles_out) {
+  hipStream_t st = P->work;
+  const int S = (int)out_pos.size();
+  const int nL = level_n(P, level);
+  std::vector<int> sizes = hierarchy(nL);
+  std::reverse(sizes.begin(), sizes.end());  // 3, 5, ..., n_level
+  Batch* prev = nullptr;
+  Batch* fine = nullptr;
+  Batch* coarse = nullptr;
+  std::vector<int> lv(S, level);
+  for (int n : sizes) {
+    Batch* B = fmg_stage(P, n, S);
+    if (!B) {
+      P->err = "full multigrid stages exceed the plan's HBM budget";
+      return MG_ENOMEM;
+    }
+    // the samples' normals (omega of (seed, level)) and the field at this size
+    CK(hipMemcpy(B->d_seeds, seeds, sizeof(uint64_t) * S, hipMemcpyHostToDevice));
+    CK(hipMemcpy(B->d_levels, lv.data(), sizeof(int) * S, hipMemcpyHostToDevice));
+    CK(hipMemcpy(B->d_fi, out_pos.data(), sizeof(int) * S, hipMemcpyHostToDevice));
+    launch_philox(B->d_seeds, S, 0, nullptr, B->d_normals, st, B->d_levels);
+    for (const auto& g : B->fields)
+      launch_field(g.n, g.count, g.d_out, g.d_xi, B->d_normals, phi_table(P, g.n), P->d_coef, 0,
+                   st);
+    prepare_coefficients(P, B);
+    launch_zero_u<double>(B->L64.dtop[0], S, n, st);
+    if (prev) {
+      GridDesc* d_link = fmg_link(B, prev);
+      launch_init_state2(B->ss, B->d_cycle, S, st);  // active flags for the interpolation
+      launch_prolong<double>(d_link, S, n, B->ss.active, 0, 0, st);
+    }
+    // the 3^3 grid: one exact solve; above: the fixed V-cycles
+    run_solves(P, B, P->desc.tol, n == 3 ? 1 : P->fmg_cycles, false);
+    if (n == nL) fine = B;
+    if (level > 0 && n == level_n(P, level - 1)) coarse = B;
+    prev = B;
+  }
+  for (Batch* B : {fine, coarse}) {
+    if (!B) continue;
+    if (P->qoi_kind == QOI_INTEGRAL) {
+      launch_reduce(B->L64.dtop[0], S, B->top_sizes[0], B->ss.active, 0, RED_QOI, B->ss.partials,
+                    st);
+      launch_finalize2(B->L64.dtop[0], S, B->ss, RED_QOI, B->d_cycle, 0, 0, 0, 0.0, st);
+    } else {
+      launch_qoi_pf(B->L64.dtop[0], S, P->qoi_kind, B->ss.q, st);
+    }
+  }
+  launch_ydiff2(fine->ss.q, coarse ? coarse->ss.q : nullptr, S, fine->d_fi, Y_out, Qf_out,
+                Qc_out, P->fmg_cycles, P->fmg_cycles, cycles_out, st);
+  CK(hipStreamSynchronize(st));
+  return MG_OK;
+}
+
+static int run_samples_fmg(mg_plan_s* P, const std::vector<int>& levels, const uint64_t* seeds,
+                           double* Y_out, double* Qf_out, double* Qc_out, int* cycles_out) {
+  if (P->desc.precision != MG_FP64) {
+    P->err = "full multigrid runs in FP64 only";
+    return MG_ENOTIMPL;
+  }
+  order_after_caller(P);
+  std::map<int, std::vector<int>> groups;
+  for (int i = 0; i < (int)levels.size(); ++i) groups[levels[i]].push_back(i);
+  for (auto& kv : groups) {
+    std::vector<uint64_t> sd;
+    for (int i : kv.second) sd.push_back(seeds[i]);
+    const int st = run_fmg_level(P, kv.first, sd.data(), kv.second, Y_out, Qf_out, Qc_out,
+                                 cycles_out);
+    if (st != MG_OK) return st;
+  }
+  return MG_OK;
+}
 
 // ---- serving: continuous batching over resident sample slots --------------------
 //
@@ -1547,6 +1710,23 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
   } else if (k == "norm") {
     if (value != 0 && value != 1) return MG_EINVAL;
     P->norm_sweep = (int)value;
+  } else if (k == "qoi") {
+    if (value < QOI_INTEGRAL || value > QOI_FLUX) return MG_EINVAL;
+    if (value != QOI_INTEGRAL && ((P->desc.n0 - 1) % 4 != 0)) {
+      P->err = "point and flux QoIs need n0 = 4m + 1 (the point and plane are vertices)";
+      return MG_EINVAL;
+    }
+    P->qoi_kind = (int)value;
+  } else if (k == "solver") {
+    if (value != 0 && value != 1) return MG_EINVAL;
+    if (value == 1 && P->desc.precision != MG_FP64) {
+      P->err = "full multigrid runs in FP64 only";
+      return MG_ENOTIMPL;
+    }
+    P->solver = (int)value;
+  } else if (k == "fmg_cycles") {
+    if (value < 1 || value > 64) return MG_EINVAL;
+    P->fmg_cycles = (int)value;
   } else if (k == "small_vcycle") {
     if (value != 0 && value != 5 && value != 9 && value != 17) return MG_EINVAL;
     P->small_ns = (int)value;
@@ -1557,6 +1737,7 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
     return MG_EINVAL;
   }
   if (P->batch) P->batch->drop_graphs();
+  for (auto& kv : P->fmg) kv.second->drop_graphs();
   return MG_OK;
 }
 
@@ -1674,6 +1855,7 @@ int mlmc_sample_batch(mg_plan P, int level, const uint64_t* seeds, int n_samples
   }
   API_BEGIN
   const std::vector<int> levels(n_samples, level);
+  if (P->solver == 1) return run_samples_fmg(P, levels, seeds, Y_out, Qf_out, Qc_out, cycles_out);
   return run_samples(P, levels, seeds, Y_out, Qf_out, Qc_out, cycles_out, fixed_cycles);
   API_END(P)
 }
@@ -1693,6 +1875,7 @@ int mlmc_sample_mixed(mg_plan P, const int* levels, const uint64_t* seeds, int n
     }
   API_BEGIN
   const std::vector<int> lv(levels, levels + n_samples);
+  if (P->solver == 1) return run_samples_fmg(P, lv, seeds, Y_out, Qf_out, Qc_out, cycles_out);
   return run_samples(P, lv, seeds, Y_out, Qf_out, Qc_out, cycles_out, fixed_cycles);
   API_END(P)
 }
@@ -1914,6 +2097,10 @@ int mg_serve_create(mg_plan P, const int* slots_per_level, int queue_capacity, m
   if (queue_capacity < 1) {
     P->err = "mg_serve_create: queue_capacity must be >= 1";
     return MG_EINVAL;
+  }
+  if (P->solver != 0 || P->qoi_kind != QOI_INTEGRAL) {
+    P->err = "mg_serve_create: the server runs V-cycles to tol with the integral QoI";
+    return MG_ENOTIMPL;
   }
   API_BEGIN
   const int L = P->desc.max_level;

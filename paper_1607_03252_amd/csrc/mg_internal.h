@@ -87,6 +87,8 @@ constexpr int kSweepParts = 1024;
 // RED_QOI_PENDING: the QoI of solves that have stopped (active 0) but whose
 // QoI is still pending (qpend 1); it clears qpend.
 enum ReduceMode { RED_BNORM = 0, RED_RESID = 1, RED_QOI = 2, RED_QOI_PENDING = 3 };
+// QoI kinds (Section 3): the integral of u, u(1/4,1/4,1/4), the flux across x_2 = 1/4
+enum QoiKind { QOI_INTEGRAL = 0, QOI_POINT = 1, QOI_FLUX = 2 };
 
 // Point kernels cover the interior (or, for the "full" kernels, every vertex)
 // with 256-thread blocks of 4 rows (j) x 64 columns (k) of one plane i.
@@ -215,5 +217,15 @@ void launch_tick(int* ctr, hipStream_t st);
 void launch_ydiff(const double* d_q, const int* d_fine_idx, const int* d_coarse_idx, int count,
                   double* d_y, double* d_qf, double* d_qc, const int* d_cycles, int* d_cycles_out,
                   hipStream_t st);
+
+// Point or flux QoI (QOI_POINT, QOI_FLUX) of the listed top grids (u[0])
+// into d_q[solve]; one workgroup per grid.
+void launch_qoi_pf(const GridDesc* d_list, int count, int mode, double* d_q, hipStream_t st);
+// Y = Q_f - Q_c per sample from two per-solve QoI arrays (d_qc may be null:
+// level 0), with fixed cycle counts cyc_f, cyc_c; sample t is written at
+// output position d_pos[t].
+void launch_ydiff2(const double* d_qf, const double* d_qc, int count, const int* d_pos,
+                   double* d_y, double* d_qf_out, double* d_qc_out, int cyc_f, int cyc_c,
+                   int* d_cycles_out, hipStream_t st);
 
 }  // namespace mg

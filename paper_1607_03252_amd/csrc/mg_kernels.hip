@@ -2137,6 +2137,71 @@ void launch_tick(int* ctr, hipStream_t st) {
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, ctr);
 }
 
+// QoIs of Section 3 besides the integral, on the top grids (u[0]), one
+// workgroup per grid.  Mode QOI_POINT: u at the vertex x* = (1/4, 1/4, 1/4),
+// index (n-1)/4 on every axis.  Mode QOI_FLUX: the flux of -k grad u in +x_2
+// (the j direction) across the vertex plane j* = (n-1)/4, as the mean of the
+// face planes j* -+ 1/2, each h * sum over interior (i, k) of
+// c (u_a - u_(a+1)) with the operator's face coefficient c = 1/(wh_a + wh_(a+1)).
+// Boundary values of u are stored zeros.  Each thread sums a fixed stride of
+// the (i, k) points, then a fixed tree over the workgroup: the result does
+// not depend on the rest of the batch.
+__global__ void __launch_bounds__(kBlock) k_qoi_pf(const GridDesc* __restrict__ list, int mode,
+                                                   double* __restrict__ q) {
+  const GridDesc d = list[blockIdx.x];
+  const int n = d.n, c = (n - 1) / 4, m = n - 2;
+  if (mode == QOI_POINT) {
+    if (threadIdx.x == 0) q[d.solve] = d.u[0][((size_t)c * n + c) * n + c];
+    return;
+  }
+  const double h = 1.0 / (double)(n - 1);
+  double sm = 0.0, sp = 0.0;
+  for (int e = threadIdx.x; e < m * m; e += kBlock) {
+    const int i = 1 + e / m, k = 1 + e - (e / m) * m;
+    const size_t p1 = ((size_t)i * n + c) * n + k, p0 = p1 - n, p2 = p1 + n;
+    const double u0 = d.u[0][p0], u1 = d.u[0][p1], u2 = d.u[0][p2];
+    const double w0 = d.wh[p0], w1 = d.wh[p1], w2 = d.wh[p2];
+    sm += (u0 - u1) / (w0 + w1);
+    sp += (u1 - u2) / (w1 + w2);
+  }
+  sm = block_sum(sm);
+  sp = block_sum(sp);
+  if (threadIdx.x == 0) q[d.solve] = 0.5 * (h * sm + h * sp);
+}
+
+// Y = Q_f - Q_c from two batches' per-solve QoIs (solve t of each is sample
+// t; qc == nullptr: level 0), with the cycle counts of both solves, written
+// at output position pos[t].
+__global__ void k_ydiff2(const double* __restrict__ qf, const double* __restrict__ qc,
+                         const int* __restrict__ pos, int count, double* __restrict__ y,
+                         double* __restrict__ qfo, double* __restrict__ qco, int cyc_f, int cyc_c,
+                         int* __restrict__ cyc_out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const double a = qf[t], b = qc ? qc[t] : 0.0;
+  const int o = pos[t];
+  y[o] = a - b;
+  if (qfo) qfo[o] = a;
+  if (qco) qco[o] = b;
+  if (cyc_out) {
+    cyc_out[2 * o] = cyc_f;
+    cyc_out[2 * o + 1] = qc ? cyc_c : 0;
+  }
+}
+
+void launch_qoi_pf(const GridDesc* d_list, int count, int mode, double* d_q, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_qoi_pf, dim3(count), dim3(kBlock), 0, st, d_list, mode, d_q);
+}
+
+void launch_ydiff2(const double* d_qf, const double* d_qc, int count, const int* d_pos,
+                   double* d_y, double* d_qf_out, double* d_qc_out, int cyc_f, int cyc_c,
+                   int* d_cycles_out, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ydiff2, dim3((count + 255) / 256), dim3(256), 0, st, d_qf, d_qc, d_pos,
+                     count, d_y, d_qf_out, d_qc_out, cyc_f, cyc_c, d_cycles_out);
+}
+
 void launch_ydiff(const double* d_q, const int* d_fi, const int* d_ci, int count, double* d_y,
                   double* d_qf, double* d_qc, const int* d_cycles, int* d_cycles_out,
                   hipStream_t st) {
