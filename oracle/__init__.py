@@ -77,6 +77,13 @@ def lib():
         L.or_mlmc_sample_ex.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_double, C.c_double,
                                         C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                                         C.c_int, C.c_int, dp, dp, dp, ip]
+        L.or_fe_stencil.argtypes = [C.c_int, dp, dp]
+        L.or_fe_apply.argtypes = [C.c_int, dp, dp, dp]
+        L.or_fe_solve.argtypes = [C.c_int, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int,
+                                  C.c_int, ip, dp]
+        L.or_mlmc_sample_fe.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_double, C.c_double,
+                                        C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                        dp, dp, dp, ip]
         L.or_sum.argtypes = [dp, C.c_long]
         L.or_sum.restype = C.c_double
         _lib = L
@@ -253,6 +260,42 @@ def mlmc_sample_ex(n0, level, seed, sigma2=1.0, lam=0.1, solver="vcycle", qoi="i
                                  1 if solver == "fmg" else 0, fmg_cycles, QOI_KINDS[qoi], tol,
                                  max_cycles, fixed_cycles, C.byref(Y), C.byref(Qf), C.byref(Qc), cyc)
     _check(st, "mlmc_sample_ex")
+    return dict(Y=Y.value, Qf=Qf.value, Qc=Qc.value, cycles=(cyc[0], cyc[1]))
+
+
+# ---- P1 finite elements on Kuhn tetrahedra (Section 3.1) ---------------------
+def fe_stencil(k):
+    """27 couplings per vertex of the 1/h-scaled P1 operator: array (n,n,n,3,3,3)."""
+    n = k.shape[0]
+    S = np.zeros((n, n, n, 3, 3, 3))
+    _check(lib().or_fe_stencil(n, _d(k), _d(S)), "fe_stencil")
+    return S
+
+
+def fe_apply(k, u):
+    out = np.zeros_like(k)
+    _check(lib().or_fe_apply(k.shape[0], _d(k), _d(np.ascontiguousarray(u)), _d(out)), "fe_apply")
+    return out
+
+
+def fe_solve(k, b, tol=1e-8, max_cycles=50, fixed_cycles=0, nu1=2, nu2=2):
+    """Returns (u, cycles, relres)."""
+    n = k.shape[0]
+    u = np.zeros_like(k)
+    cyc, rel = C.c_int(0), C.c_double(0.0)
+    _check(lib().or_fe_solve(n, _d(k), _d(b), _d(u), nu1, nu2, tol, max_cycles, fixed_cycles,
+                             C.byref(cyc), C.byref(rel)), "fe_solve")
+    return u, cyc.value, rel.value
+
+
+def mlmc_sample_fe(n0, level, seed, sigma2=1.0, lam=0.1, qoi="integral", tol=1e-8,
+                   max_cycles=50, fixed_cycles=0, nu1=2, nu2=2):
+    Y, Qf, Qc = C.c_double(), C.c_double(), C.c_double()
+    cyc = (C.c_int * 2)()
+    st = lib().or_mlmc_sample_fe(n0, level, seed, sigma2, lam, nu1, nu2, QOI_KINDS[qoi], tol,
+                                 max_cycles, fixed_cycles, C.byref(Y), C.byref(Qf), C.byref(Qc),
+                                 cyc)
+    _check(st, "mlmc_sample_fe")
     return dict(Y=Y.value, Qf=Qf.value, Qc=Qc.value, cycles=(cyc[0], cyc[1]))
 
 

@@ -618,6 +618,235 @@ int or_mlmc_sample_ex(int n0, int level, uint64_t seed, double sigma2, double la
 }
 
 /* ------------------------------------------------------------------------ */
+/* P1 finite elements (Section 3.1): the system matrix assembled element by  */
+/* element, A_ij = sum over tetrahedra of grad(phi_i).grad(phi_j) |tau| times */
+/* the mean of k at the tetrahedron's four vertices (the four-node           */
+/* quadrature).  Mesh (reading of "uniformly refined simplicial meshes" on a  */
+/* vertex grid): every cell [i,i+1]x[j,j+1]x[k,k+1] split into the 6 Kuhn     */
+/* tetrahedra v0 = corner, v1 = v0 + e_a, v2 = v1 + e_b, v3 = v2 + e_c, one   */
+/* for each ordering (a, b, c) of the axes.  Scaled by 1/h, so that with      */
+/* F_i = int f phi_i = h^3 f the system reads A' u = h^2 f as the FD one.     */
+/* ------------------------------------------------------------------------ */
+static const int kuhn_perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+/* The scaled element matrix of one tetrahedron with integer vertex offsets
+ * v[4][3] (in units of h) and coefficient kbar: Ke[m][q] = kbar |tau|/h *
+ * grad(lambda_m).grad(lambda_q), the barycentric gradients from the inverse
+ * of the edge matrix E = [v1-v0, v2-v0, v3-v0]. */
+static void p1_element(const int v[4][3], double kbar, double Ke[4][4]) {
+  double E[3][3], adj[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) E[r][c] = (double)(v[c + 1][r] - v[0][r]);
+  double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+               E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+               E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+  /* inverse = adjugate / det; lambda_{m+1}(x) = row m of E^-1 applied to x - v0 */
+  adj[0][0] = E[1][1] * E[2][2] - E[1][2] * E[2][1];
+  adj[0][1] = E[0][2] * E[2][1] - E[0][1] * E[2][2];
+  adj[0][2] = E[0][1] * E[1][2] - E[0][2] * E[1][1];
+  adj[1][0] = E[1][2] * E[2][0] - E[1][0] * E[2][2];
+  adj[1][1] = E[0][0] * E[2][2] - E[0][2] * E[2][0];
+  adj[1][2] = E[0][2] * E[1][0] - E[0][0] * E[1][2];
+  adj[2][0] = E[1][0] * E[2][1] - E[1][1] * E[2][0];
+  adj[2][1] = E[0][1] * E[2][0] - E[0][0] * E[2][1];
+  adj[2][2] = E[0][0] * E[1][1] - E[0][1] * E[1][0];
+  double g[4][3];
+  for (int m = 0; m < 3; ++m)
+    for (int c = 0; c < 3; ++c) g[m + 1][c] = adj[m][c] / det;
+  for (int c = 0; c < 3; ++c) g[0][c] = -(g[1][c] + g[2][c] + g[3][c]);
+  double vol = fabs(det) / 6.0; /* |tau| / h^3 */
+  for (int m = 0; m < 4; ++m)
+    for (int q = 0; q < 4; ++q)
+      Ke[m][q] = kbar * vol * (g[m][0] * g[q][0] + g[m][1] * g[q][1] + g[m][2] * g[q][2]);
+}
+
+/* The scaled P1 operator as a 27-point stencil per vertex: S[27 p + t] is the
+ * coupling of vertex p to its neighbour p + (di, dj, dk), t = (di+1)*9 +
+ * (dj+1)*3 + (dk+1), summed over every tetrahedron of every cell (rows of
+ * boundary vertices are assembled too; they are not used). */
+int or_fe_stencil(int n, const double *k, double *S) {
+  if (n < 3) return OR_EINVAL;
+  size_t N = (size_t)n * n * n;
+  memset(S, 0, sizeof(double) * 27 * N);
+  for (int i = 0; i < n - 1; ++i)
+    for (int j = 0; j < n - 1; ++j)
+      for (int kk = 0; kk < n - 1; ++kk)
+        for (int t = 0; t < 6; ++t) {
+          int v[4][3] = {{i, j, kk}};
+          for (int s2 = 1; s2 < 4; ++s2) {
+            for (int c = 0; c < 3; ++c) v[s2][c] = v[s2 - 1][c];
+            v[s2][kuhn_perm[t][s2 - 1]] += 1;
+          }
+          double kbar = 0.0;
+          for (int m = 0; m < 4; ++m) kbar += k[IDX(n, v[m][0], v[m][1], v[m][2])];
+          kbar *= 0.25;
+          double Ke[4][4];
+          p1_element(v, kbar, Ke);
+          for (int m = 0; m < 4; ++m)
+            for (int q = 0; q < 4; ++q) {
+              int di = v[q][0] - v[m][0], dj = v[q][1] - v[m][1], dk = v[q][2] - v[m][2];
+              S[27 * IDX(n, v[m][0], v[m][1], v[m][2]) + (di + 1) * 9 + (dj + 1) * 3 + (dk + 1)] +=
+                  Ke[m][q];
+            }
+        }
+  return OR_OK;
+}
+
+/* (A'u)_p over interior rows with u = 0 on the boundary. */
+static void fe_apply_s(int n, const double *S, const double *u, double *out) {
+  size_t N = (size_t)n * n * n;
+  for (size_t p = 0; p < N; ++p) out[p] = 0.0;
+  for (int i = 1; i < n - 1; ++i)
+    for (int j = 1; j < n - 1; ++j)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        size_t p = IDX(n, i, j, kk);
+        double s = 0.0;
+        for (int t = 0; t < 27; ++t) {
+          size_t q = IDX(n, i + t / 9 - 1, j + (t / 3) % 3 - 1, kk + t % 3 - 1);
+          s += S[27 * p + t] * uval(n, u, q);
+        }
+        out[p] = s;
+      }
+}
+
+int or_fe_apply(int n, const double *k, const double *u, double *out) {
+  if (n < 3) return OR_EINVAL;
+  size_t N = (size_t)n * n * n;
+  double *S = (double *)malloc(sizeof(double) * 27 * N);
+  if (!S) return OR_EINVAL;
+  or_fe_stencil(n, k, S);
+  fe_apply_s(n, S, u, out);
+  free(S);
+  return OR_OK;
+}
+
+/* Gauss-Seidel on one colour ((i+j+k) even = red) with the full 27-point
+ * row: u_p = (b_p - sum_{q != p} S_pq u_q) / S_pp. */
+static void fe_gs_colour(int n, const double *S, const double *b, double *u, int colour) {
+  for (int i = 1; i < n - 1; ++i)
+    for (int j = 1; j < n - 1; ++j)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        if (((i + j + kk) & 1) != colour) continue;
+        size_t p = IDX(n, i, j, kk);
+        double s = 0.0;
+        for (int t = 0; t < 27; ++t) {
+          if (t == 13) continue;
+          size_t q = IDX(n, i + t / 9 - 1, j + (t / 3) % 3 - 1, kk + t % 3 - 1);
+          s += S[27 * p + t] * uval(n, u, q);
+        }
+        u[p] = (b[p] - s) / S[27 * p + 13];
+      }
+}
+
+static void fe_residual_s(int n, const double *S, const double *b, const double *u, double *r) {
+  fe_apply_s(n, S, u, r);
+  for (int i = 1; i < n - 1; ++i)
+    for (int j = 1; j < n - 1; ++j)
+      for (int kk = 1; kk < n - 1; ++kk) {
+        size_t p = IDX(n, i, j, kk);
+        r[p] = b[p] - r[p];
+      }
+}
+
+/* V(nu1,nu2) with the P1 operator rediscretised on every level (k injected). */
+static int fe_vcycle_rec(int n, const double *k, const double *b, double *u, int nu1, int nu2) {
+  size_t N = (size_t)n * n * n;
+  double *S = (double *)malloc(sizeof(double) * 27 * N);
+  if (!S) return OR_EINVAL;
+  or_fe_stencil(n, k, S);
+  if (n == 3) {
+    size_t p = IDX(3, 1, 1, 1);
+    u[p] = b[p] / S[27 * p + 13];
+    free(S);
+    return OR_OK;
+  }
+  int nc = (n - 1) / 2 + 1;
+  size_t Nc = (size_t)nc * nc * nc;
+  double *r = (double *)malloc(sizeof(double) * N);
+  double *kc = (double *)malloc(sizeof(double) * Nc);
+  double *bc = (double *)malloc(sizeof(double) * Nc);
+  double *ec = (double *)calloc(Nc, sizeof(double));
+  for (int s2 = 0; s2 < nu1; ++s2) { fe_gs_colour(n, S, b, u, 0); fe_gs_colour(n, S, b, u, 1); }
+  fe_residual_s(n, S, b, u, r);
+  or_restrict(n, r, bc);
+  or_inject(n, k, kc);
+  fe_vcycle_rec(nc, kc, bc, ec, nu1, nu2);
+  or_prolong_add(nc, ec, u);
+  for (int s2 = 0; s2 < nu2; ++s2) { fe_gs_colour(n, S, b, u, 0); fe_gs_colour(n, S, b, u, 1); }
+  free(S); free(r); free(kc); free(bc); free(ec);
+  return OR_OK;
+}
+
+/* Solve the P1 system as or_solve does the FD one (same stopping rule). */
+int or_fe_solve(int n, const double *k, const double *b, double *u, int nu1, int nu2,
+                double tol, int max_cycles, int fixed_cycles, int *cycles, double *relres) {
+  if (!valid_n(n) || nu1 < 0 || nu2 < 0) return OR_EINVAL;
+  if (fixed_cycles <= 0 && (max_cycles < 1 || !(tol > 0.0))) return OR_EINVAL;
+  size_t N = (size_t)n * n * n;
+  double *r = (double *)malloc(sizeof(double) * N);
+  double *S = (double *)malloc(sizeof(double) * 27 * N);
+  if (!r || !S) { free(r); free(S); return OR_EINVAL; }
+  or_fe_stencil(n, k, S);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int kk = 0; kk < n; ++kk)
+        if (i == 0 || j == 0 || kk == 0 || i == n - 1 || j == n - 1 || kk == n - 1) u[IDX(n, i, j, kk)] = 0.0;
+  double bn = or_norm2(n, b);
+  double scale = bn > 0.0 ? bn : 1.0;
+  int limit = fixed_cycles > 0 ? fixed_cycles : max_cycles;
+  int m = 0, status = OR_ENOCONV;
+  double rho = 0.0;
+  for (m = 1; m <= limit; ++m) {
+    fe_vcycle_rec(n, k, b, u, nu1, nu2);
+    fe_residual_s(n, S, b, u, r);
+    rho = or_norm2(n, r) / scale;
+    if (fixed_cycles > 0) {
+      if (m == fixed_cycles) { status = OR_OK; break; }
+    } else if (rho <= tol) {
+      status = OR_OK;
+      break;
+    }
+  }
+  if (m > limit) m = limit;
+  if (cycles) *cycles = m;
+  if (relres) *relres = rho;
+  free(r); free(S);
+  return status;
+}
+
+/* One MLMC sample with the P1 operator (V-cycles to tol; qoi 0 = integral,
+ * 1 = point value). */
+int or_mlmc_sample_fe(int n0, int level, uint64_t seed, double sigma2, double lambda, int nu1,
+                      int nu2, int qoi, double tol, int max_cycles, int fixed_cycles, double *Y,
+                      double *Qf, double *Qc, int cycles[2]) {
+  if (!valid_n(n0) || level < 0 || level > 12 || qoi < 0 || qoi > 1) return OR_EINVAL;
+  double xi[64];
+  or_gaussians(seed, (uint32_t)level, xi);
+  double q[2] = {0.0, 0.0};
+  int cyc[2] = {0, 0}, st = OR_OK;
+  for (int s2 = 0; s2 < (level > 0 ? 2 : 1); ++s2) {
+    int n = (n0 - 1) * (1 << (level - s2)) + 1;
+    if (qoi == 1 && ((n - 1) % 4 != 0 || n < 5)) return OR_EINVAL;
+    size_t N = (size_t)n * n * n;
+    double *k = (double *)malloc(sizeof(double) * N);
+    double *b = (double *)malloc(sizeof(double) * N);
+    double *u = (double *)calloc(N, sizeof(double));
+    int st2 = or_field(n, sigma2, lambda, xi, k);
+    double h = 1.0 / (double)(n - 1);
+    for (size_t p = 0; p < N; ++p) b[p] = h * h;
+    if (!st2) st2 = or_fe_solve(n, k, b, u, nu1, nu2, tol, max_cycles, fixed_cycles, &cyc[s2], NULL);
+    q[s2] = qoi == 1 ? or_point_qoi(n, u) : or_qoi(n, u);
+    if (st2 && !st) st = st2;
+    free(k); free(b); free(u);
+  }
+  if (Qf) *Qf = q[0];
+  if (Qc) *Qc = q[1];
+  if (Y) *Y = q[0] - q[1];
+  if (cycles) { cycles[0] = cyc[0]; cycles[1] = cyc[1]; }
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Level accumulator: shift K = first Y; compensated sums of (Y-K) and       */
 /* (Y-K)^2; mean = K + S1/N, s^2 = S2/N - (S1/N)^2 (divisor N as in the      */
 /* paper's estimator of V[Y_l]).                                            */

@@ -90,6 +90,18 @@ int or_mlmc_sample_ex(int n0, int level, uint64_t seed, double sigma2, double la
                       int max_cycles, int fixed_cycles, double *Y, double *Qf, double *Qc,
                       int cycles[2]);
 
+/* P1 finite elements on the Kuhn triangulation of the vertex grid, the
+ * tetrahedron's coefficient the mean of its four vertex values, scaled by 1/h
+ * (so A'u = h^2 f as in the FD form).  S: 27 couplings per vertex,
+ * S[27 p + (di+1)*9 + (dj+1)*3 + (dk+1)]. */
+int or_fe_stencil(int n, const double *k, double *S);
+int or_fe_apply(int n, const double *k, const double *u, double *out);
+int or_fe_solve(int n, const double *k, const double *b, double *u, int nu1, int nu2,
+                double tol, int max_cycles, int fixed_cycles, int *cycles, double *relres);
+int or_mlmc_sample_fe(int n0, int level, uint64_t seed, double sigma2, double lambda, int nu1,
+                      int nu2, int qoi, double tol, int max_cycles, int fixed_cycles, double *Y,
+                      double *Qf, double *Qc, int cycles[2]);
+
 /* Compensated (Neumaier) summation of a vector. */
 double or_sum(const double *x, long n);
 
