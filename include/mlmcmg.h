@@ -188,6 +188,18 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *               fmg_cycles; fixed_cycles is ignored;
  *   "fmg_cycles": V-cycles per grid of the full multigrid schedule (1..64,
  *               default 2).
+ *   "operator": 0 (default) = 7-point finite differences with harmonic-mean
+ *               face coefficients; 1 = the paper's P1 finite elements
+ *               (Section 3.1) on the Kuhn tetrahedra of the vertex grid (every
+ *               cell split into the six tetrahedra x_a >= x_b >= x_c), each
+ *               tetrahedron's coefficient the mean of its four vertex values
+ *               (the four-node quadrature), rediscretised on every level with
+ *               injected k.  This operator couples axis neighbours only, with
+ *               the coupling of an edge the sum of the four-vertex means of
+ *               its six tetrahedra over 6, so the same red-black V-cycle
+ *               applies (two-pass colour sweeps, separate residual and
+ *               restriction; no LDS cycle).  FP64, V-cycles to tol, integral
+ *               or point QoI (MG_ENOTIMPL otherwise); also used by mg_solve. 
  * Returns MG_EINVAL for an unknown name or value. */
 int mg_plan_set_option(mg_plan plan, const char* name, long long value);
 
@@ -210,7 +222,10 @@ int mg_get_tile_for(mg_plan plan, int n, int fused_correction, int* tj, int* tk,
  * 0x5eed0000 + i), then times every compiled tile shape with chunk counts
  * 0 (automatic), 1, 2, 4 of both kinds of smoothing sweep on each grid size
  * of that batch above the LDS V-cycle's sizes (reps launches each, HIP
- * events) and keeps the fastest per size and kind in the plan. */
+ * events) and picks the fastest per size and kind.  The picks are kept only
+ * if whole batches (reps each, alternated with the shapes in force before
+ * tuning, best of two rounds) run faster with them; otherwise the plan keeps
+ * its previous shapes. */
 int mg_autotune(mg_plan plan, int level, int n_samples, int reps);
 
 /* Serving: continuous batching of MLMC sample requests --------------------

@@ -54,6 +54,7 @@ struct LevelT {
   T* wh = nullptr;
   T* b = nullptr;
   T* r = nullptr;
+  T* fc = nullptr;  // P1 finite elements: the axis couplings (3 n^3)
 };
 
 struct BatchSpec {
@@ -62,8 +63,10 @@ struct BatchSpec {
   bool const_b_top = true;  // top right-hand side is the constant h^2 (f = 1)
   bool ext_u_top = false;   // top u is caller memory (mg_solve)
   bool mixed = false;       // FP32 inner cycles inside FP64 defect correction
+  bool fe = false;          // P1 finite-element operator (FP64)
   std::string key() const {
-    std::string s = const_b_top ? "c" : "v";
+    std::string s = fe ? "f" : "";
+    s += const_b_top ? "c" : "v";
     s += ext_u_top ? "e" : "i";
     s += mixed ? "m" : "d";
     for (size_t i = 0; i < top_n.size(); ++i)
@@ -132,6 +135,9 @@ struct Batch {
   std::vector<double**> d_cvt_src;
   std::vector<float**> d_cvt_dst;
   std::vector<int> cvt_n, cvt_count;
+  // P1 finite elements: per size, the wh and fc arrays of the grids that own them
+  std::vector<double**> d_fe_wh, d_fe_fc;
+  std::vector<int> fe_n, fe_count;
   bool uploaded = false;
   std::vector<double*> const_plane;  // per size index: n^2 values h^2
   // graphs of c consecutive cycles
@@ -219,6 +225,7 @@ struct mg_plan_s {
   int qoi_kind = QOI_INTEGRAL;  // the samples' QoI (Section 3)
   int solver = 0;        // 0: V-cycles to tol, 1: full multigrid (fixed schedule)
   int fmg_cycles = 2;    // V-cycles per grid of the full multigrid schedule
+  int op_fe = 0;         // 1: the P1 finite-element operator instead of FD
   // full multigrid: one batch per grid size of the schedule (n -> batch)
   std::map<int, std::unique_ptr<Batch>> fmg;
   std::map<int, SweepShape> shape;      // tile shape per grid size
@@ -321,6 +328,10 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
         const bool top = j == 0;
         if (spec.share[s] < 0) L.wh = (double*)take(N * 8);
         else if (pass == 1) L.wh = B->lev[spec.share[s]][j + 1].wh;
+        if (spec.fe) {
+          if (spec.share[s] < 0) L.fc = (double*)take(3 * N * 8);
+          else if (pass == 1) L.fc = B->lev[spec.share[s]][j + 1].fc;
+        }
         if (!spec.mixed) {
           if (!(top && spec.ext_u_top)) L.u[0] = (double*)take(N * 8);
           L.u[1] = (double*)take(N * 8);
@@ -405,6 +416,7 @@ static GridDescT<T> make_desc(const std::vector<LevelT<T>>& lv, size_t j, int so
   d.u[0] = L.u[0];
   d.u[1] = L.u[1];
   d.wh = L.wh;
+  d.fc = L.fc;
   d.b = L.b ? L.b : const_plane;  // constant right-hand side: one plane, stride 0
   d.bstride = L.b ? L.n * L.n : 0;
   d.r = L.r;
@@ -468,7 +480,7 @@ static void upload_lists(mg_plan_s* P, Batch* B) {
   // the small-grid V-cycle takes over from each solve's largest grid of at
   // most P->small_ns (and at least 5) vertices per axis; a batch with a 3^3
   // top grid keeps the per-level path
-  bool small_ok = P->small_ns >= 5;
+  bool small_ok = P->small_ns >= 5 && !spec.fe;
   for (int s = 0; s < B->ns; ++s)
     if (spec.top_n[s] < 5) small_ok = false;
   int chain_si = -1;
@@ -551,6 +563,27 @@ static void upload_lists(mg_plan_s* P, Batch* B) {
         B->inj_n.push_back(B->sizes[si]);
         B->inj_count.push_back((int)src.size());
       }
+      if (spec.fe) {
+        std::vector<double*> fw, ff;
+        for (int s = 0; s < B->ns; ++s) {
+          if (spec.share[s] >= 0) continue;
+          for (const auto& L : B->lev[s])
+            if (L.n == B->sizes[si]) {
+              fw.push_back(L.wh);
+              ff.push_back(L.fc);
+            }
+        }
+        if (!fw.empty()) {
+          double** dw = (double**)B->dalloc(sizeof(double*) * fw.size());
+          double** df = (double**)B->dalloc(sizeof(double*) * ff.size());
+          CK(hipMemcpyAsync(dw, fw.data(), sizeof(double*) * fw.size(), hipMemcpyHostToDevice, P->work));
+          CK(hipMemcpyAsync(df, ff.data(), sizeof(double*) * ff.size(), hipMemcpyHostToDevice, P->work));
+          B->d_fe_wh.push_back(dw);
+          B->d_fe_fc.push_back(df);
+          B->fe_n.push_back(B->sizes[si]);
+          B->fe_count.push_back((int)fw.size());
+        }
+      }
       if (!csrc.empty()) {
         double** ds = (double**)B->dalloc(sizeof(double*) * csrc.size());
         float** dd = (float**)B->dalloc(sizeof(float*) * cdst.size());
@@ -576,6 +609,10 @@ static void prepare_coefficients(mg_plan_s* P, Batch* B) {
   for (size_t j = 0; j < B->cvt_n.size(); ++j)
     launch_to_float(B->cvt_n[j], B->cvt_count[j], (const double* const*)B->d_cvt_src[j],
                     B->d_cvt_dst[j], P->work);
+  // P1 finite elements: every level's couplings from its (injected) coefficient
+  for (size_t j = 0; j < B->fe_n.size(); ++j)
+    launch_fe_faces(B->fe_n[j], B->fe_count[j], (const double* const*)B->d_fe_wh[j],
+                    B->d_fe_fc[j], P->work);
 }
 
 static hipEvent_t next_event(mg_plan_s* P) {
@@ -651,7 +688,7 @@ static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr,
                         const Lists<double>* Lp = nullptr) {
   const Lists<double>& L = Lp ? *Lp : B->L64;
   const int n = B->sizes[si];
-  if (B->spec.mixed || !P->norm_sweep || P->smoother != 0 || P->desc.nu1 < 1 ||
+  if (B->spec.mixed || B->spec.fe || !P->norm_sweep || P->smoother != 0 || P->desc.nu1 < 1 ||
       P->desc.nu2 < 2 || n < 5)
     return 0;
   if (B->L64.chain_si >= 0 && si >= (size_t)B->L64.chain_si) return 0;  // LDS V-cycle sizes
@@ -665,6 +702,38 @@ static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr,
   const int cnt = std::max<int>(1, (int)L.h[si].size());
   if (red) *red = sweep_blocks(n, cnt, shape_for(P, n, !L.const_b(si)));
   return sweep_blocks(n, cnt, shape_for(P, n, false));
+}
+
+// One V(nu1,nu2) cycle with the P1 finite-element operator: two-pass
+// red-black Gauss-Seidel in place in buffer 0, residual and full weighting as
+// two kernels, trilinear correction, exact 3^3 solve.
+static void run_cycle_fe(mg_plan_s* P, Batch* B, Lists<double>& Ls) {
+  const int nu1 = P->desc.nu1, nu2 = P->desc.nu2;
+  const size_t L = B->sizes.size();
+  hipStream_t st = B->st;
+  for (size_t si = 0; si < L; ++si) {
+    const int n = B->sizes[si];
+    const int cnt = (int)Ls.h[si].size();
+    if (n == 3) {
+      launch_fe_coarsest(Ls.d[si], cnt, B->ss.active, st);
+      continue;
+    }
+    for (int s = 0; s < nu1; ++s) {
+      launch_fe_colour(Ls.d[si], cnt, n, B->ss.active, 0, st);
+      launch_fe_colour(Ls.d[si], cnt, n, B->ss.active, 1, st);
+    }
+    launch_fe_residual(Ls.d[si], cnt, n, B->ss.active, st);
+    launch_restrict<double>(Ls.d[si], cnt, n, B->ss.active, st);
+  }
+  for (size_t si = L - 1; si-- > 0;) {
+    const int n = B->sizes[si];
+    const int cnt = (int)Ls.h[si].size();
+    launch_prolong<double>(Ls.d[si], cnt, n, B->ss.active, 0, 0, st);
+    for (int s = 0; s < nu2; ++s) {
+      launch_fe_colour(Ls.d[si], cnt, n, B->ss.active, 0, st);
+      launch_fe_colour(Ls.d[si], cnt, n, B->ss.active, 1, st);
+    }
+  }
 }
 
 // One V(nu1,nu2) cycle on every active solve.  Each level starts in buffer 0
@@ -751,7 +820,16 @@ static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
   Lists<double>& L = Lp ? *Lp : B->L64;
   if (P->prof) ++P->prof_cycle;  // (eager while profiling: one call per cycle)
   launch_tick(B->d_cycle, st);
-  if (!B->spec.mixed) {
+  if (B->spec.fe) {
+    run_cycle_fe(P, B, L);
+    for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
+      const int n = B->top_sizes[ti], cnt = (int)L.htop[ti].size();
+      launch_fe_residual(L.dtop[ti], cnt, n, B->ss.active, st);
+      launch_reduce(L.dtop[ti], cnt, n, B->ss.active, 0, RED_R2, B->ss.partials, st);
+      launch_finalize2(L.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, 0, fixed,
+                       P->desc.max_cycles, tol, st);
+    }
+  } else if (!B->spec.mixed) {
     const int out = run_cycle<double>(P, B, L, true, tol, fixed);
     if (out != 0)  // odd sweep count: bring the top iterates back to buffer 0
       for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
@@ -948,6 +1026,7 @@ static BatchSpec mlmc_spec(mg_plan_s* P, const std::vector<int>& levels) {
   spec.const_b_top = true;
   spec.ext_u_top = false;
   spec.mixed = P->desc.precision == MG_MIXED;
+  spec.fe = P->op_fe != 0;
   return spec;
 }
 
@@ -1592,6 +1671,7 @@ static BatchSpec solve_spec(mg_plan_s* P, int n) {
   spec.const_b_top = false;
   spec.ext_u_top = true;
   spec.mixed = P->desc.precision == MG_MIXED;
+  spec.fe = P->op_fe != 0;
   return spec;
 }
 }  // namespace mg
@@ -1716,14 +1796,27 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
       P->err = "point and flux QoIs need n0 = 4m + 1 (the point and plane are vertices)";
       return MG_EINVAL;
     }
+    if (value == QOI_FLUX && P->op_fe) {
+      P->err = "the flux QoI uses the FD face coefficients";
+      return MG_ENOTIMPL;
+    }
     P->qoi_kind = (int)value;
   } else if (k == "solver") {
     if (value != 0 && value != 1) return MG_EINVAL;
-    if (value == 1 && P->desc.precision != MG_FP64) {
-      P->err = "full multigrid runs in FP64 only";
+    if (value == 1 && (P->desc.precision != MG_FP64 || P->op_fe)) {
+      P->err = "full multigrid runs in FP64 with the FD operator";
       return MG_ENOTIMPL;
     }
     P->solver = (int)value;
+  } else if (k == "operator") {
+    if (value != 0 && value != 1) return MG_EINVAL;
+    if (value == 1 && (P->desc.precision != MG_FP64 || P->solver != 0 || P->qoi_kind == QOI_FLUX)) {
+      P->err = "the P1 operator runs in FP64 with V-cycles to tol and the integral or point QoI";
+      return MG_ENOTIMPL;
+    }
+    P->op_fe = (int)value;
+    P->batch.reset();  // the workspace layout differs
+    P->batch_key.clear();
   } else if (k == "fmg_cycles") {
     if (value < 1 || value > 64) return MG_EINVAL;
     P->fmg_cycles = (int)value;
@@ -1894,6 +1987,8 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
   if (st != MG_OK && st != MG_ENOCONV) return st;
   Batch* B = P->batch.get();
   const bool mixed = B->spec.mixed;
+  // the shapes in force before tuning: a pick must beat them on whole batches
+  const std::map<int, SweepShape> before = P->shape, before_pro = P->shape_pro;
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
@@ -1944,6 +2039,35 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
   CK(hipEventDestroy(e0));
   CK(hipEventDestroy(e1));
   B->drop_graphs();
+  // whole batches (graphs, every sweep kind, the real stopping) with the
+  // picks and with the shapes before tuning, alternately, best of two each
+  const std::map<int, SweepShape> picked = P->shape, picked_pro = P->shape_pro;
+  CK(hipMalloc(&d_y, sizeof(double) * n_samples));
+  auto batch_ms = [&]() {
+    B->drop_graphs();
+    (void)mlmc_sample_batch(P, level, seeds.data(), n_samples, d_y, nullptr, nullptr, nullptr, 0);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < reps; ++r)
+      (void)mlmc_sample_batch(P, level, seeds.data(), n_samples, d_y, nullptr, nullptr, nullptr,
+                              0);
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  };
+  double t_pick = 1e300, t_before = 1e300;
+  for (int round = 0; round < 2; ++round) {
+    P->shape = picked;
+    P->shape_pro = picked_pro;
+    t_pick = std::min(t_pick, batch_ms());
+    P->shape = before;
+    P->shape_pro = before_pro;
+    t_before = std::min(t_before, batch_ms());
+  }
+  CK(hipFree(d_y));
+  if (t_pick < t_before) {
+    P->shape = picked;
+    P->shape_pro = picked_pro;
+  }
+  B = P->batch.get();
+  if (B) B->drop_graphs();
   return MG_OK;
   API_END(P)
 }
@@ -2098,8 +2222,8 @@ int mg_serve_create(mg_plan P, const int* slots_per_level, int queue_capacity, m
     P->err = "mg_serve_create: queue_capacity must be >= 1";
     return MG_EINVAL;
   }
-  if (P->solver != 0 || P->qoi_kind != QOI_INTEGRAL) {
-    P->err = "mg_serve_create: the server runs V-cycles to tol with the integral QoI";
+  if (P->solver != 0 || P->qoi_kind != QOI_INTEGRAL || P->op_fe) {
+    P->err = "mg_serve_create: the server runs FD V-cycles to tol with the integral QoI";
     return MG_ENOTIMPL;
   }
   API_BEGIN

@@ -41,6 +41,9 @@ template <typename T>
 struct GridDescT {
   T* u[2];          // iterate: the smoother reads u[buf] and writes u[1-buf]
   const T* wh;      // 1/(2k) at all n^3 vertices
+  const T* fc;      // P1 finite-element operator only: the couplings of every
+                    // vertex to its +i, +j and +k neighbours, three n^3 arrays
+                    // one after the other (nullptr for the FD operator)
   T* b;             // h^2-scaled right-hand side: b[i*bstride + j*n + k] (bstride 0:
                     // one n^2 plane holding a constant right-hand side)
   T* r;             // residual scratch, n^3 (nullptr on 3^3)
@@ -86,7 +89,7 @@ constexpr int kSweepParts = 1024;
 
 // RED_QOI_PENDING: the QoI of solves that have stopped (active 0) but whose
 // QoI is still pending (qpend 1); it clears qpend.
-enum ReduceMode { RED_BNORM = 0, RED_RESID = 1, RED_QOI = 2, RED_QOI_PENDING = 3 };
+enum ReduceMode { RED_BNORM = 0, RED_RESID = 1, RED_QOI = 2, RED_QOI_PENDING = 3, RED_R2 = 4 };
 // QoI kinds (Section 3): the integral of u, u(1/4,1/4,1/4), the flux across x_2 = 1/4
 enum QoiKind { QOI_INTEGRAL = 0, QOI_POINT = 1, QOI_FLUX = 2 };
 
@@ -227,5 +230,17 @@ void launch_qoi_pf(const GridDesc* d_list, int count, int mode, double* d_q, hip
 void launch_ydiff2(const double* d_qf, const double* d_qc, int count, const int* d_pos,
                    double* d_y, double* d_qf_out, double* d_qc_out, int cyc_f, int cyc_c,
                    int* d_cycles_out, hipStream_t st);
+
+// P1 finite elements (FP64): the axis couplings fc of `count` grids of size
+// n from their wh (k = 1/(2 wh)); d_wh[g] and d_fc[g] per grid.
+void launch_fe_faces(int n, int count, const double* const* d_wh, double* const* d_fc,
+                     hipStream_t st);
+// In-place Gauss-Seidel on one colour, residual into r, and the 3^3 solve,
+// with the operator given by the grids' fc.
+void launch_fe_colour(const GridDesc* d_list, int count, int n, const int* d_active, int colour,
+                      hipStream_t st);
+void launch_fe_residual(const GridDesc* d_list, int count, int n, const int* d_active,
+                        hipStream_t st);
+void launch_fe_coarsest(const GridDesc* d_list, int count, const int* d_active, hipStream_t st);
 
 }  // namespace mg

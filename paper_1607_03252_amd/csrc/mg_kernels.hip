@@ -1616,7 +1616,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const GridDesc* __restrict__ 
   int gi, blk;
   if (!xcd_unit(count, per, gi, blk)) return;
   const GridDesc d = list[gi];
-  if (mode == RED_RESID && !active[d.solve]) return;
+  if ((mode == RED_RESID || mode == RED_R2) && !active[d.solve]) return;
   if (mode == RED_QOI_PENDING && (!pend[d.solve] || active[d.solve])) return;
   const int n = d.n, sn2 = n * n;
   const Col c = column_of(n - 2, blk);
@@ -1631,6 +1631,8 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const GridDesc* __restrict__ 
         if (mode == RED_BNORM) {
           const double bp = b_at<double>(d, i, c.j, c.k);
           acc += bp * bp;
+        } else if (mode == RED_R2) {
+          acc += d.r[p] * d.r[p];
         } else {
           acc += u[p];
         }
@@ -2167,6 +2169,131 @@ __global__ void __launch_bounds__(kBlock) k_qoi_pf(const GridDesc* __restrict__ 
   sm = block_sum(sm);
   sp = block_sum(sp);
   if (threadIdx.x == 0) q[d.solve] = 0.5 * (h * sm + h * sp);
+}
+
+// ---- P1 finite elements on the Kuhn tetrahedra (Section 3.1) -----------------
+// The P1 operator of the vertex grid's Kuhn triangulation (each cell split
+// into the six tetrahedra x_a >= x_b >= x_c, one per ordering of the axes),
+// each tetrahedron's coefficient the mean of its four vertex values, couples
+// axis neighbours only: in a Kuhn tetrahedron the barycentric gradients are
+// orthogonal across its diagonal edges.  An axis edge p -- p + e_d lies in six
+// of the tetrahedra; its coupling, scaled by 1/h like the FD form, is the sum
+// of their four-vertex means over 6:
+//   c_d(p) = [6 (k_p + k_(p+e_d)) + 2 (k_(p+e_d+e_a) + k_(p+e_d+e_b)
+//            + k_(p+e_d+e_a+e_b) + k_(p-e_a) + k_(p-e_b) + k_(p-e_a-e_b))] / 24
+// with a, b the other two axes.  The stencil of an interior vertex then has
+// the FD form with these six faces (red-black colouring stays exact).
+__global__ void __launch_bounds__(kBlock) k_fe_faces(int n, const double* const* __restrict__ wh_l,
+                                                     double* const* __restrict__ fc_l, int count,
+                                                     int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const Pt p = full_point(n, blk);
+  if (!p.ok) return;
+  const int i = p.i, j = p.j, k = p.k;
+  const double* w = wh_l[gi];
+  double* fc = fc_l[gi];
+  const int sn2 = n * n;
+  const size_t N = (size_t)sn2 * n;
+  const int v = (i * n + j) * n + k;
+  const int step[3] = {sn2, n, 1};
+  const int c[3] = {i, j, k};
+  auto kv = [&](int q) { return 0.5 / w[q]; };
+#pragma unroll
+  for (int dd = 0; dd < 3; ++dd) {
+    const int a = dd == 0 ? 1 : 0, b = dd == 2 ? 1 : 2;
+    const bool ok = c[dd] <= n - 2 && c[a] >= 1 && c[a] <= n - 2 && c[b] >= 1 && c[b] <= n - 2;
+    double val = 0.0;
+    if (ok) {
+      const int sd = step[dd], sa = step[a], sb = step[b];
+      const double s6 = kv(v) + kv(v + sd);
+      const double s2 = ((kv(v + sd + sa) + kv(v + sd + sb)) + kv(v + sd + sa + sb)) +
+                        ((kv(v - sa) + kv(v - sb)) + kv(v - sa - sb));
+      val = (6.0 * s6 + 2.0 * s2) / 24.0;
+    }
+    fc[dd * N + v] = val;
+  }
+}
+
+// The six faces of interior vertex v from fc (at v and at v - e_d).
+__device__ __forceinline__ St<double> fe_stencil_at(const double* fc, const double* u, int v, int n,
+                                                    size_t N) {
+  const int sj = n, si = n * n;
+  return stencil_faces<double>(fc[v - si], fc[v], fc[N + v - sj], fc[N + v], fc[2 * N + v - 1],
+                               fc[2 * N + v], u[v - si], u[v + si], u[v - sj], u[v + sj],
+                               u[v - 1], u[v + 1]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fe_colour(const GridDesc* __restrict__ list,
+                                                      const int* __restrict__ active, int colour,
+                                                      int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDesc d = list[gi];
+  if (!active[d.solve]) return;
+  const int n = d.n;
+  const Pt p = interior_point(n - 2, blk);
+  if (!p.ok || ((p.i + p.j + p.k) & 1) != colour) return;
+  const int v = vidx(n, p.i, p.j, p.k);
+  double* u = d.u[0];
+  const St<double> st = fe_stencil_at(d.fc, u, v, n, (size_t)n * n * n);
+  u[v] = gs_value<double>(st, b_at<double>(d, p.i, p.j, p.k));
+}
+
+__global__ void __launch_bounds__(kBlock) k_fe_residual(const GridDesc* __restrict__ list,
+                                                        const int* __restrict__ active, int count,
+                                                        int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const GridDesc d = list[gi];
+  if (!active[d.solve]) return;
+  const int n = d.n;
+  const Pt p = interior_point(n - 2, blk);
+  if (!p.ok) return;
+  const int v = vidx(n, p.i, p.j, p.k);
+  const St<double> st = fe_stencil_at(d.fc, d.u[0], v, n, (size_t)n * n * n);
+  d.r[v] = res_value<double>(st, b_at<double>(d, p.i, p.j, p.k), d.u[0][v]);
+}
+
+__global__ void k_fe_coarsest(const GridDesc* __restrict__ list, int count,
+                              const int* __restrict__ active) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  const GridDesc d = list[g];
+  if (!active[d.solve]) return;
+  const double zero[27] = {};
+  const St<double> st = fe_stencil_at(d.fc, zero, 13, 3, 27);
+  d.u[0][13] = gs_value<double>(st, b_at<double>(d, 1, 1, 1));
+}
+
+void launch_fe_faces(int n, int count, const double* const* d_wh, double* const* d_fc,
+                     hipStream_t st) {
+  if (count <= 0) return;
+  const int per = point_blocks(n);
+  hipLaunchKernelGGL(k_fe_faces, xcd_grid(count, per), dim3(kBlock), 0, st, n, d_wh, d_fc, count,
+                     per);
+}
+
+void launch_fe_colour(const GridDesc* d_list, int count, int n, const int* d_active, int colour,
+                      hipStream_t st) {
+  if (count <= 0) return;
+  const int per = point_blocks(n - 2);
+  hipLaunchKernelGGL(k_fe_colour, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
+                     colour, count, per);
+}
+
+void launch_fe_residual(const GridDesc* d_list, int count, int n, const int* d_active,
+                        hipStream_t st) {
+  if (count <= 0) return;
+  const int per = point_blocks(n - 2);
+  hipLaunchKernelGGL(k_fe_residual, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
+                     count, per);
+}
+
+void launch_fe_coarsest(const GridDesc* d_list, int count, const int* d_active, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fe_coarsest, dim3((count + 63) / 64), dim3(64), 0, st, d_list, count,
+                     d_active);
 }
 
 // Y = Q_f - Q_c from two batches' per-solve QoIs (solve t of each is sample
