@@ -84,6 +84,18 @@ def lib():
         L.or_mlmc_sample_fe.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_double, C.c_double,
                                         C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                         dp, dp, dp, ip]
+        L.or_white_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_long, dp]
+        L.or_white_noise.restype = None
+        L.or_spde_operator.argtypes = [C.c_int, dp, dp]
+        L.or_spde_restrict.argtypes = [C.c_int, dp, dp]
+        L.or_spde_prolong_add.argtypes = [C.c_int, dp, dp]
+        L.or_spde_solve.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, C.c_int, C.c_int,
+                                    C.c_double, C.c_int, ip, dp]
+        L.or_spde_rhs.argtypes = [C.c_int, dp, dp]
+        L.or_spde_to_k.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
+        L.or_mlmc_sample_spde.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_double, C.c_double,
+                                          C.c_int, C.c_int, C.c_double, C.c_int, C.c_double,
+                                          dp, dp, dp, ip, ip]
         L.or_sum.argtypes = [dp, C.c_long]
         L.or_sum.restype = C.c_double
         _lib = L
@@ -297,6 +309,75 @@ def mlmc_sample_fe(n0, level, seed, sigma2=1.0, lam=0.1, qoi="integral", tol=1e-
                                  cyc)
     _check(st, "mlmc_sample_fe")
     return dict(Y=Y.value, Qf=Qf.value, Qc=Qc.value, cycles=(cyc[0], cyc[1]))
+
+
+# ---- SPDE sampler (Section 3.2, eq. spde) -----------------------------------
+def box_n(n: int) -> int:
+    """Vertices per axis of the box (-1,2)^3 at the spacing of an n grid on D."""
+    return 3 * (n - 1) + 1
+
+
+def white_noise(seed: int, level: int, count: int) -> np.ndarray:
+    o = np.zeros(count)
+    lib().or_white_noise(seed, level, count, _d(o))
+    return o
+
+
+def spde_operator(nt: int):
+    """(stiffness couplings (nt,nt,nt,3,3,3), lumped mass m (nt,nt,nt)) of the box grid."""
+    S = np.zeros((nt, nt, nt, 3, 3, 3))
+    m = np.zeros((nt, nt, nt))
+    _check(lib().or_spde_operator(nt, _d(S), _d(m)), "spde_operator")
+    return S, m
+
+
+def spde_restrict(r):
+    nt = r.shape[0]
+    ntc = (nt - 1) // 2 + 1
+    bc = np.zeros((ntc, ntc, ntc))
+    _check(lib().or_spde_restrict(nt, _d(np.ascontiguousarray(r)), _d(bc)), "spde_restrict")
+    return bc
+
+
+def spde_prolong_add(zc, zf):
+    zf = np.array(zf, dtype=np.float64, copy=True, order="C")
+    _check(lib().or_spde_prolong_add(zc.shape[0], _d(np.ascontiguousarray(zc)), _d(zf)), "spde_prolong")
+    return zf
+
+
+def spde_solve(b, h, kappa, tol=1e-10, max_cycles=50, nu1=2, nu2=2):
+    """Returns (z, cycles, relres) of the scaled box system."""
+    nt = b.shape[0]
+    z = np.zeros_like(b)
+    cyc, rel = C.c_int(0), C.c_double(0.0)
+    st = lib().or_spde_solve(nt, h, kappa, _d(np.ascontiguousarray(b)), _d(z), nu1, nu2, tol,
+                             max_cycles, C.byref(cyc), C.byref(rel))
+    _check(st, "spde_solve")
+    return z, cyc.value, rel.value
+
+
+def spde_rhs(n: int, xi):
+    nt = box_n(n)
+    b = np.zeros((nt, nt, nt))
+    _check(lib().or_spde_rhs(n, _d(np.ascontiguousarray(xi, dtype=np.float64)), _d(b)), "spde_rhs")
+    return b
+
+
+def spde_to_k(n, sigma2, lam, z):
+    k = np.zeros((n, n, n))
+    _check(lib().or_spde_to_k(n, sigma2, lam, _d(np.ascontiguousarray(z)), _d(k)), "spde_to_k")
+    return k
+
+
+def mlmc_sample_spde(n0, level, seed, sigma2=1.0, lam=0.1, tol=1e-8, max_cycles=50,
+                     spde_tol=1e-10, nu1=2, nu2=2):
+    Y, Qf, Qc = C.c_double(), C.c_double(), C.c_double()
+    cyc, sc = (C.c_int * 2)(), (C.c_int * 2)()
+    st = lib().or_mlmc_sample_spde(n0, level, seed, sigma2, lam, nu1, nu2, tol, max_cycles,
+                                   spde_tol, C.byref(Y), C.byref(Qf), C.byref(Qc), cyc, sc)
+    _check(st, "mlmc_sample_spde")
+    return dict(Y=Y.value, Qf=Qf.value, Qc=Qc.value, cycles=(cyc[0], cyc[1]),
+                spde_cycles=(sc[0], sc[1]))
 
 
 def grid_n(n0: int, level: int) -> int:

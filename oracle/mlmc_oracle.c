@@ -847,6 +847,282 @@ int or_mlmc_sample_fe(int n0, int level, uint64_t seed, double sigma2, double la
 }
 
 /* ------------------------------------------------------------------------ */
+/* SPDE sampler of the lognormal field (Section 3.2, eq. spde):              */
+/* (kappa^2 - Laplace) Z = W on the box (-1,2)^3 with natural (homogeneous  */
+/* Neumann) boundary conditions, P1 elements on the Kuhn tetrahedra of the   */
+/* extended vertex grid (spacing h = 1/(n-1) of the n grid on D, nt =        */
+/* 3(n-1)+1 vertices per axis, D's vertex i at nt-index i + n - 1), with the */
+/* mass matrix lumped (its row sums).  White noise: the load <W, phi_p> has  */
+/* variance M_pp, so b_p = sqrt(M_pp) xi_p.  Divided by h like the FD form:  */
+/*   (K' + kappa^2 h^2 diag(m)) Z = sqrt(h m_p) xi_p,  m_p = M_pp / h^3.     */
+/* Whittle: Z has covariance exp(-kappa r) / (8 pi kappa); reading: kappa =  */
+/* 1/lambda and k = exp(sigma sqrt(8 pi kappa) Z).                          */
+/* ------------------------------------------------------------------------ */
+
+/* Normals of the white noise of sample (seed, level): count values, block j of
+ * Philox4x32-10 with counter (j, level, 1, 0) and key (seed lo, seed hi)
+ * giving normals 2j and 2j+1 (53-bit uniforms from word pairs, Box-Muller). */
+void or_white_noise(uint64_t seed, uint32_t level, long count, double *xi) {
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  const double two_pi = 6.283185307179586;
+  for (long j = 0; 2 * j < count; ++j) {
+    uint32_t ctr[4] = {(uint32_t)j, level, 1u, 0u}, w[4];
+    or_philox4x32_10(ctr, key, w);
+    double U0 = ((double)((uint64_t)(w[0] >> 5) * 67108864ull + (uint64_t)(w[1] >> 6)) + 1.0) * 0x1p-53;
+    double U1 = ((double)((uint64_t)(w[2] >> 5) * 67108864ull + (uint64_t)(w[3] >> 6)) + 1.0) * 0x1p-53;
+    double R = sqrt(-2.0 * log(U0)), a = two_pi * U1;
+    xi[2 * j] = R * cos(a);
+    if (2 * j + 1 < count) xi[2 * j + 1] = R * sin(a);
+  }
+}
+
+/* Stiffness (unit coefficient, 27 couplings per vertex, every vertex of the
+ * box) and lumped mass m_p = sum over tetrahedra at p of |tau|/4 / h^3, both
+ * by element-wise assembly (the same elements as or_fe_stencil). */
+int or_spde_operator(int nt, double *S, double *m) {
+  if (nt < 2) return OR_EINVAL;
+  size_t N = (size_t)nt * nt * nt;
+  memset(S, 0, sizeof(double) * 27 * N);
+  memset(m, 0, sizeof(double) * N);
+  for (int i = 0; i < nt - 1; ++i)
+    for (int j = 0; j < nt - 1; ++j)
+      for (int kk = 0; kk < nt - 1; ++kk)
+        for (int t = 0; t < 6; ++t) {
+          int v[4][3] = {{i, j, kk}};
+          for (int s2 = 1; s2 < 4; ++s2) {
+            for (int c = 0; c < 3; ++c) v[s2][c] = v[s2 - 1][c];
+            v[s2][kuhn_perm[t][s2 - 1]] += 1;
+          }
+          double Ke[4][4];
+          p1_element(v, 1.0, Ke);
+          for (int a = 0; a < 4; ++a) {
+            size_t pa = IDX(nt, v[a][0], v[a][1], v[a][2]);
+            m[pa] += (1.0 / 6.0) / 4.0;
+            for (int q = 0; q < 4; ++q) {
+              int di = v[q][0] - v[a][0], dj = v[q][1] - v[a][1], dk = v[q][2] - v[a][2];
+              S[27 * pa + (di + 1) * 9 + (dj + 1) * 3 + (dk + 1)] += Ke[a][q];
+            }
+          }
+        }
+  return OR_OK;
+}
+
+/* value of z at nt-index (i,j,k), 0 outside the box */
+static double zval(int nt, const double *z, int i, int j, int k) {
+  if (i < 0 || j < 0 || k < 0 || i >= nt || j >= nt || k >= nt) return 0.0;
+  return z[IDX(nt, i, j, k)];
+}
+
+/* Red-black Gauss-Seidel over every vertex of the box (one colour). */
+static void spde_gs_colour(int nt, const double *S, const double *m, double k2h2, const double *b,
+                           double *z, int colour) {
+  for (int i = 0; i < nt; ++i)
+    for (int j = 0; j < nt; ++j)
+      for (int kk = 0; kk < nt; ++kk) {
+        if (((i + j + kk) & 1) != colour) continue;
+        size_t p = IDX(nt, i, j, kk);
+        double s = 0.0;
+        for (int t = 0; t < 27; ++t)
+          if (t != 13) s += S[27 * p + t] * zval(nt, z, i + t / 9 - 1, j + (t / 3) % 3 - 1, kk + t % 3 - 1);
+        z[p] = (b[p] - s) / (S[27 * p + 13] + k2h2 * m[p]);
+      }
+}
+
+static void spde_residual(int nt, const double *S, const double *m, double k2h2, const double *b,
+                          const double *z, double *r) {
+  for (int i = 0; i < nt; ++i)
+    for (int j = 0; j < nt; ++j)
+      for (int kk = 0; kk < nt; ++kk) {
+        size_t p = IDX(nt, i, j, kk);
+        double s = k2h2 * m[p] * z[p];
+        for (int t = 0; t < 27; ++t)
+          s += S[27 * p + t] * zval(nt, z, i + t / 9 - 1, j + (t / 3) % 3 - 1, kk + t % 3 - 1);
+        r[p] = b[p] - s;
+      }
+}
+
+/* Coarse right-hand side from a fine one: b_c = (1/2) P^T b_f with P the
+ * trilinear interpolation (the 1/2 is h / h_c of the scaled form); fine
+ * points outside the box do not exist. */
+int or_spde_restrict(int nt, const double *r, double *bc) {
+  if (nt < 3 || ((nt - 1) & 1)) return OR_EINVAL;
+  int ntc = (nt - 1) / 2 + 1;
+  for (int I = 0; I < ntc; ++I)
+    for (int J = 0; J < ntc; ++J)
+      for (int K = 0; K < ntc; ++K) {
+        double s = 0.0;
+        for (int di = -1; di <= 1; ++di)
+          for (int dj = -1; dj <= 1; ++dj)
+            for (int dk = -1; dk <= 1; ++dk) {
+              int l1 = abs(di) + abs(dj) + abs(dk);
+              s += ldexp(1.0, -l1) * zval(nt, r, 2 * I + di, 2 * J + dj, 2 * K + dk);
+            }
+        bc[IDX(ntc, I, J, K)] = 0.5 * s;
+      }
+  return OR_OK;
+}
+
+/* z_f += P z_c over every fine vertex (trilinear, coarse boundary included). */
+int or_spde_prolong_add(int ntc, const double *zc, double *zf) {
+  int nt = 2 * (ntc - 1) + 1;
+  for (int i = 0; i < nt; ++i)
+    for (int j = 0; j < nt; ++j)
+      for (int kk = 0; kk < nt; ++kk) {
+        double s = 0.0;
+        for (int a = 0; a <= (i & 1); ++a)
+          for (int b2 = 0; b2 <= (j & 1); ++b2)
+            for (int c = 0; c <= (kk & 1); ++c) {
+              double w = ((i & 1) ? 0.5 : 1.0) * ((j & 1) ? 0.5 : 1.0) * ((kk & 1) ? 0.5 : 1.0);
+              s += w * zc[IDX(ntc, i / 2 + a, j / 2 + b2, kk / 2 + c)];
+            }
+        zf[IDX(nt, i, j, kk)] += s;
+      }
+  return OR_OK;
+}
+
+/* V(nu1,nu2) cycle on the box grid nt at spacing h; the coarsest grid (an odd
+ * number of intervals, 4^3 for these boxes) gets 32 red-black sweeps. */
+static int spde_vcycle(int nt, double h, double kappa, const double *b, double *z, int nu1, int nu2) {
+  size_t N = (size_t)nt * nt * nt;
+  double *S = (double *)malloc(sizeof(double) * 27 * N), *m = (double *)malloc(sizeof(double) * N);
+  or_spde_operator(nt, S, m);
+  double k2h2 = kappa * kappa * h * h;
+  if ((nt - 1) & 1) {
+    for (int s2 = 0; s2 < 32; ++s2) {
+      spde_gs_colour(nt, S, m, k2h2, b, z, 0);
+      spde_gs_colour(nt, S, m, k2h2, b, z, 1);
+    }
+    free(S); free(m);
+    return OR_OK;
+  }
+  int ntc = (nt - 1) / 2 + 1;
+  size_t Nc = (size_t)ntc * ntc * ntc;
+  double *r = (double *)malloc(sizeof(double) * N);
+  double *bc = (double *)malloc(sizeof(double) * Nc), *ec = (double *)calloc(Nc, sizeof(double));
+  for (int s2 = 0; s2 < nu1; ++s2) {
+    spde_gs_colour(nt, S, m, k2h2, b, z, 0);
+    spde_gs_colour(nt, S, m, k2h2, b, z, 1);
+  }
+  spde_residual(nt, S, m, k2h2, b, z, r);
+  or_spde_restrict(nt, r, bc);
+  spde_vcycle(ntc, 2.0 * h, kappa, bc, ec, nu1, nu2);
+  or_spde_prolong_add(ntc, ec, z);
+  for (int s2 = 0; s2 < nu2; ++s2) {
+    spde_gs_colour(nt, S, m, k2h2, b, z, 0);
+    spde_gs_colour(nt, S, m, k2h2, b, z, 1);
+  }
+  free(S); free(m); free(r); free(bc); free(ec);
+  return OR_OK;
+}
+
+static double norm2_all(long N, const double *v) {
+  double s = 0.0, c = 0.0;
+  for (long p = 0; p < N; ++p) {
+    double y = v[p] * v[p], t = s + y;
+    if (fabs(s) >= fabs(y)) c += (s - t) + y;
+    else c += (y - t) + s;
+    s = t;
+  }
+  return sqrt(s + c);
+}
+
+/* Solve the scaled SPDE system from z = 0 with V(nu1,nu2) cycles until
+ * ||b - A z|| / ||b|| <= tol over all vertices (or max_cycles). */
+int or_spde_solve(int nt, double h, double kappa, const double *b, double *z, int nu1, int nu2,
+                  double tol, int max_cycles, int *cycles, double *relres) {
+  size_t N = (size_t)nt * nt * nt;
+  double *S = (double *)malloc(sizeof(double) * 27 * N), *m = (double *)malloc(sizeof(double) * N);
+  double *r = (double *)malloc(sizeof(double) * N);
+  or_spde_operator(nt, S, m);
+  memset(z, 0, sizeof(double) * N);
+  double bn = norm2_all((long)N, b), rho = 1.0;
+  int c = 0, st = OR_ENOCONV;
+  for (c = 1; c <= max_cycles; ++c) {
+    spde_vcycle(nt, h, kappa, b, z, nu1, nu2);
+    spde_residual(nt, S, m, kappa * kappa * h * h, b, z, r);
+    rho = norm2_all((long)N, r) / (bn > 0.0 ? bn : 1.0);
+    if (rho <= tol) { st = OR_OK; break; }
+  }
+  if (c > max_cycles) c = max_cycles;
+  if (cycles) *cycles = c;
+  if (relres) *relres = rho;
+  free(S); free(m); free(r);
+  return st;
+}
+
+/* The scaled white-noise load on the box grid of an n grid. */
+int or_spde_rhs(int n, const double *xi, double *b) {
+  int nt = 3 * (n - 1) + 1;
+  size_t N = (size_t)nt * nt * nt;
+  double *S = (double *)malloc(sizeof(double) * 27 * N), *m = (double *)malloc(sizeof(double) * N);
+  or_spde_operator(nt, S, m);
+  double h = 1.0 / (double)(n - 1);
+  for (size_t p = 0; p < N; ++p) b[p] = sqrt(h * m[p]) * xi[p];
+  free(S); free(m);
+  return OR_OK;
+}
+
+/* k = exp(sigma sqrt(8 pi kappa) Z) at the n^3 vertices of D from a box
+ * solution z (nt = 3(n-1)+1). */
+int or_spde_to_k(int n, double sigma2, double lambda, const double *z, double *k) {
+  int nt = 3 * (n - 1) + 1, o = n - 1;
+  double kappa = 1.0 / lambda, sc = sqrt(sigma2) * sqrt(8.0 * 3.141592653589793 * kappa);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int kk = 0; kk < n; ++kk) k[IDX(n, i, j, kk)] = exp(sc * z[IDX(nt, i + o, j + o, kk + o)]);
+  return OR_OK;
+}
+
+/* One MLMC sample with the SPDE field: the fine field from the white noise of
+ * (seed, level) on the fine box grid, the coarse field (level > 0) from the
+ * same noise, b_c = (1/2) P^T b_f, on the coarse box grid; each SPDE solve to
+ * spde_tol with V(2,2); the PDE solves as or_mlmc_sample (FD, V(nu1,nu2) to
+ * tol, integral QoI).  spde_cycles[2] (optional) receives the SPDE cycles. */
+int or_mlmc_sample_spde(int n0, int level, uint64_t seed, double sigma2, double lambda, int nu1,
+                        int nu2, double tol, int max_cycles, double spde_tol, double *Y,
+                        double *Qf, double *Qc, int cycles[2], int spde_cycles[2]) {
+  if (!valid_n(n0) || level < 0 || level > 10) return OR_EINVAL;
+  int n[2] = {(n0 - 1) * (1 << level) + 1, level > 0 ? (n0 - 1) * (1 << (level - 1)) + 1 : 0};
+  int nt = 3 * (n[0] - 1) + 1;
+  size_t Nt = (size_t)nt * nt * nt;
+  double *xi = (double *)malloc(sizeof(double) * Nt), *bf = (double *)malloc(sizeof(double) * Nt);
+  or_white_noise(seed, (uint32_t)level, (long)Nt, xi);
+  or_spde_rhs(n[0], xi, bf);
+  free(xi);
+  double q[2] = {0.0, 0.0};
+  int cyc[2] = {0, 0}, sc[2] = {0, 0}, st = OR_OK;
+  double *b = bf;
+  for (int s2 = 0; s2 < (level > 0 ? 2 : 1); ++s2) {
+    int ns = n[s2], nts = 3 * (ns - 1) + 1;
+    size_t Ns = (size_t)nts * nts * nts, N = (size_t)ns * ns * ns;
+    if (s2 == 1) {
+      double *bc = (double *)malloc(sizeof(double) * Ns);
+      or_spde_restrict(nt, bf, bc);
+      b = bc;
+    }
+    double *z = (double *)malloc(sizeof(double) * Ns);
+    double h = 1.0 / (double)(ns - 1);
+    int st1 = or_spde_solve(nts, h, 1.0 / lambda, b, z, 2, 2, spde_tol, 50, &sc[s2], NULL);
+    double *k = (double *)malloc(sizeof(double) * N), *bb = (double *)malloc(sizeof(double) * N);
+    double *u = (double *)calloc(N, sizeof(double));
+    or_spde_to_k(ns, sigma2, lambda, z, k);
+    for (size_t p = 0; p < N; ++p) bb[p] = h * h;
+    int st2 = or_solve(ns, k, bb, u, nu1, nu2, tol, max_cycles, 0, &cyc[s2], NULL, NULL);
+    q[s2] = or_qoi(ns, u);
+    if (!st) st = st1 ? st1 : st2;
+    free(z); free(k); free(bb); free(u);
+    if (s2 == 1) free(b);
+  }
+  free(bf);
+  if (Qf) *Qf = q[0];
+  if (Qc) *Qc = q[1];
+  if (Y) *Y = q[0] - q[1];
+  if (cycles) { cycles[0] = cyc[0]; cycles[1] = cyc[1]; }
+  if (spde_cycles) { spde_cycles[0] = sc[0]; spde_cycles[1] = sc[1]; }
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Level accumulator: shift K = first Y; compensated sums of (Y-K) and       */
 /* (Y-K)^2; mean = K + S1/N, s^2 = S2/N - (S1/N)^2 (divisor N as in the      */
 /* paper's estimator of V[Y_l]).                                            */

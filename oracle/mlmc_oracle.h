@@ -102,6 +102,22 @@ int or_mlmc_sample_fe(int n0, int level, uint64_t seed, double sigma2, double la
                       int nu2, int qoi, double tol, int max_cycles, int fixed_cycles, double *Y,
                       double *Qf, double *Qc, int cycles[2]);
 
+/* SPDE sampler (Section 3.2): white noise, the box operator (stiffness
+ * S[27 p + t] and lumped mass m_p), restriction b_c = P^T b_f / 2 and
+ * prolongation on box grids, the V-cycle solve, the scaled load, the field
+ * on D, and an MLMC sample with the SPDE field. */
+void or_white_noise(uint64_t seed, uint32_t level, long count, double *xi);
+int or_spde_operator(int nt, double *S, double *m);
+int or_spde_restrict(int nt, const double *r, double *bc);
+int or_spde_prolong_add(int ntc, const double *zc, double *zf);
+int or_spde_solve(int nt, double h, double kappa, const double *b, double *z, int nu1, int nu2,
+                  double tol, int max_cycles, int *cycles, double *relres);
+int or_spde_rhs(int n, const double *xi, double *b);
+int or_spde_to_k(int n, double sigma2, double lambda, const double *z, double *k);
+int or_mlmc_sample_spde(int n0, int level, uint64_t seed, double sigma2, double lambda, int nu1,
+                        int nu2, double tol, int max_cycles, double spde_tol, double *Y,
+                        double *Qf, double *Qc, int cycles[2], int spde_cycles[2]);
+
 /* Compensated (Neumaier) summation of a vector. */
 double or_sum(const double *x, long n);
 
