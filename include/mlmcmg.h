@@ -65,7 +65,8 @@ typedef struct {
   double sigma2;      /* variance sigma^2 of log k (>= 0)                      */
   double corr_len;    /* correlation length lambda (> 0)                       */
   int kl_per_axis;    /* 1D modes per axis; this build supports 4 (4^3 terms)  */
-  size_t hbm_budget;  /* bytes of workspace the plan may hold; 0 = no limit    */
+  size_t hbm_budget;  /* bytes a batch workspace may hold; 0 = no limit (a     */
+                      /* server sizing its pools from it takes 8 GiB for 0)  */
   void* stream;       /* hipStream_t to run on; NULL = the null stream         */
 } mg_plan_desc;
 
@@ -200,6 +201,21 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *               applies (two-pass colour sweeps, separate residual and
  *               restriction; no LDS cycle).  FP64, V-cycles to tol, integral
  *               or point QoI (MG_ENOTIMPL otherwise); also used by mg_solve. 
+ *   "field":    0 (default) = the 4x4x4 separable KL field; 1 = the paper's
+ *               SPDE sampler (Section 3.2, eq. spde): (kappa^2 - Laplace) Z = W
+ *               on the box (-1,2)^3 with natural Neumann boundary, lumped-mass
+ *               P1 elements on the Kuhn tetrahedra of the box grid at the
+ *               sample grid's spacing (3(n-1)+1 vertices per axis), the white
+ *               noise load sqrt(M_pp) xi_p from Philox4x32-10 with counter
+ *               (j, level, 1, 0) (normals 2j, 2j+1), V(2,2) cycles to relative
+ *               residual 1e-10 over all box vertices, and
+ *               k = exp(sigma sqrt(8 pi kappa) Z) at D's vertices with
+ *               kappa = 1/lambda (the Whittle variance 1/(8 pi kappa)
+ *               rescaled to sigma^2).  The coarse solve of Y_l takes the same
+ *               noise on the coarse box grid (load P^T b / 2) and a box solve
+ *               of its own.  Not with "solver" = 1 or the server (MG_ENOTIMPL);
+ *               mlmc_field then serves n = n_level (fine) and n_(level-1)
+ *               (coarse) of a level <= max_level.
  * Returns MG_EINVAL for an unknown name or value. */
 int mg_plan_set_option(mg_plan plan, const char* name, long long value);
 

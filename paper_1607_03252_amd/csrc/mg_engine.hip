@@ -203,6 +203,10 @@ static bool valid_n(int n) {
 
 using namespace mg;
 
+namespace mg {
+struct SpdeWork;
+}
+
 struct mg_plan_s {
   mg_plan_desc desc{};
   hipStream_t caller = nullptr;  // stream the caller's data is ordered on
@@ -226,6 +230,9 @@ struct mg_plan_s {
   int solver = 0;        // 0: V-cycles to tol, 1: full multigrid (fixed schedule)
   int fmg_cycles = 2;    // V-cycles per grid of the full multigrid schedule
   int op_fe = 0;         // 1: the P1 finite-element operator instead of FD
+  int field_spde = 0;    // 1: coefficient fields from the SPDE sampler instead of KL
+  // SPDE sampler workspaces keyed by (finest box size, solves)
+  std::map<std::pair<int, int>, std::unique_ptr<mg::SpdeWork>> spde;
   // full multigrid: one batch per grid size of the schedule (n -> batch)
   std::map<int, std::unique_ptr<Batch>> fmg;
   std::map<int, SweepShape> shape;      // tile shape per grid size
@@ -253,16 +260,7 @@ struct mg_plan_s {
   int scratch_dev = 0;
   int* h_small = nullptr;
 
-  ~mg_plan_s() {
-    batch.reset();
-    fmg.clear();
-    if (h_small) (void)hipHostFree(h_small);
-    for (auto& kv : d_phi) (void)hipFree(kv.second);
-    if (d_coef) (void)hipFree(d_coef);
-    for (auto e : ev_pool) (void)hipEventDestroy(e);
-    if (order_ev) (void)hipEventDestroy(order_ev);
-    if (work) (void)hipStreamDestroy(work);
-  }
+  ~mg_plan_s();
 };
 
 namespace mg {
@@ -1020,7 +1018,9 @@ static BatchSpec mlmc_spec(mg_plan_s* P, const std::vector<int>& levels) {
     spec.share.push_back(-1);
     if (l > 0) {
       spec.top_n.push_back(level_n(P, l - 1));
-      spec.share.push_back((int)spec.top_n.size() - 2);
+      // the coarse solve's coefficient is the fine one's injection (KL), or a
+      // field of its own (SPDE: a coarse box solve of the same noise)
+      spec.share.push_back(P->field_spde ? -1 : (int)spec.top_n.size() - 2);
     }
   }
   spec.const_b_top = true;
@@ -1031,8 +1031,12 @@ static BatchSpec mlmc_spec(mg_plan_s* P, const std::vector<int>& levels) {
 }
 
 // Fields, coefficient hierarchy and zero iterates for a batch of samples.
-static void setup_samples(mg_plan_s* P, Batch* B, const std::vector<int>& levels,
-                          const uint64_t* seeds) {
+static int spde_fields(mg_plan_s* P, int level, const uint64_t* seeds, int S,
+                       const std::vector<double*>& outs_f, const std::vector<double*>& outs_c,
+                       int mode);
+
+static int setup_samples(mg_plan_s* P, Batch* B, const std::vector<int>& levels,
+                         const uint64_t* seeds) {
   hipStream_t st = P->work;
   const int n_samples = (int)levels.size();
   if (B->nsamples != n_samples) {
@@ -1074,13 +1078,37 @@ static void setup_samples(mg_plan_s* P, Batch* B, const std::vector<int>& levels
   std::memcpy(B->h_seeds, seeds, sizeof(uint64_t) * n_samples);
   CK(hipMemcpyAsync(B->d_seeds, B->h_seeds, sizeof(uint64_t) * n_samples, hipMemcpyHostToDevice,
                     st));
-  launch_philox(B->d_seeds, n_samples, 0, nullptr, B->d_normals, st, B->d_levels);
-  for (const auto& g : B->fields)
-    launch_field(g.n, g.count, g.d_out, g.d_xi, B->d_normals, phi_table(P, g.n), P->d_coef, 0, st);
+  if (P->field_spde) {
+    // the SPDE sampler, level by level (fine and coarse box solves)
+    std::map<int, std::vector<int>> groups;
+    for (int i = 0; i < n_samples; ++i) groups[levels[i]].push_back(i);
+    std::vector<int> fi(n_samples);
+    for (int i = 0, s = 0; i < n_samples; ++i) {
+      fi[i] = s;
+      s += levels[i] > 0 ? 2 : 1;
+    }
+    for (const auto& kv : groups) {
+      std::vector<double*> outs_f, outs_c;
+      std::vector<uint64_t> sd;
+      for (int i : kv.second) {
+        outs_f.push_back(B->lev[fi[i]][0].wh);
+        if (kv.first > 0) outs_c.push_back(B->lev[fi[i] + 1][0].wh);
+        sd.push_back(seeds[i]);
+      }
+      const int stt = spde_fields(P, kv.first, sd.data(), (int)sd.size(), outs_f, outs_c, 0);
+      if (stt != MG_OK) return stt;
+    }
+  } else {
+    launch_philox(B->d_seeds, n_samples, 0, nullptr, B->d_normals, st, B->d_levels);
+    for (const auto& g : B->fields)
+      launch_field(g.n, g.count, g.d_out, g.d_xi, B->d_normals, phi_table(P, g.n), P->d_coef, 0,
+                   st);
+  }
   prepare_coefficients(P, B);
   // every sample starts from the zero iterate (the workspace may hold the last batch)
   for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
     launch_zero_u<double>(B->L64.dtop[ti], (int)B->L64.htop[ti].size(), B->top_sizes[ti], st);
+  return MG_OK;
 }
 
 // Samples of (possibly different) levels in one batch: one launch per grid
@@ -1094,7 +1122,13 @@ static int run_samples(mg_plan_s* P, const std::vector<int>& levels, const uint6
   if (!B) return status;
   hipStream_t st = P->work;
   const int n_samples = (int)levels.size();
-  setup_samples(P, B, levels, seeds);
+  {
+    const int stt = setup_samples(P, B, levels, seeds);
+    if (stt != MG_OK) {
+      P->err = "an SPDE field solve missed its tolerance";
+      return stt;
+    }
+  }
   if (fixed_cycles > 0) B->drop_graphs();  // graphs bake in the stopping mode
   // the QoI and Y are enqueued after every launch of cycles: once the solves
   // have stopped, the host's wait for the last launch covers them too.  Each
@@ -1276,6 +1310,184 @@ static int run_samples_fmg(mg_plan_s* P, const std::vector<int>& levels, const u
                                  cycles_out);
     if (st != MG_OK) return st;
   }
+  return MG_OK;
+}
+
+// ---- SPDE field sampler (Section 3.2, eq. spde) ------------------------------------
+//
+// The fields of a batch's samples from (kappa^2 - Laplace) Z = W on the box
+// (-1,2)^3: per sample the white-noise load on the fine box grid, a V(2,2)
+// solve to relative residual 1e-10 over every box vertex (natural Neumann
+// boundary), k = exp(sigma sqrt(8 pi kappa) Z) at D's vertices (kappa =
+// 1/lambda); the coarse solve of Y_l takes the same noise on the coarse box
+// grid (its load P^T b / 2) and its own box solve.
+constexpr double kSpdeTol = 1e-10;
+constexpr int kSpdeMaxCycles = 50;
+
+struct SpdeWork {
+  int S = 0;
+  std::vector<int> nts;                  // box sizes per level, descending (.. 4)
+  std::vector<std::vector<SpdeGrid>> h;  // per level: S descriptors
+  std::vector<SpdeGrid*> d;              // their device copies
+  void* mem = nullptr;
+  int* d_active = nullptr;
+  int* d_cycles = nullptr;
+  double* d_bnorm = nullptr;
+  double* d_part = nullptr;
+  int* h_active = nullptr;               // pinned
+  uint64_t* d_seeds = nullptr;
+  int* d_levels = nullptr;
+  double** d_out = nullptr;              // field targets of the S solves
+  SpdeGrid* d_link = nullptr;            // top descriptors with bc/zc of another box size
+  ~SpdeWork() {
+    if (mem) (void)hipFree(mem);
+    if (h_active) (void)hipHostFree(h_active);
+  }
+};
+
+static SpdeWork* spde_work(mg_plan_s* P, int nt, int S, double h) {
+  auto& slot = P->spde[{nt, S}];
+  if (slot) return slot.get();
+  auto W = std::make_unique<SpdeWork>();
+  W->S = S;
+  for (int m = nt;; m = (m - 1) / 2 + 1) {
+    W->nts.push_back(m);
+    if ((m - 1) & 1) break;  // an odd number of intervals: the coarsest box grid
+  }
+  const int L = (int)W->nts.size();
+  size_t total = 0;
+  for (int m : W->nts) total += align256(3 * sizeof(double) * (size_t)m * m * m) * (size_t)S;
+  const int part = spde_blocks(nt);
+  const size_t extra = align256(sizeof(int) * 2 * S) + align256(sizeof(double) * S) +
+                       align256(sizeof(double) * (size_t)S * part) + align256(sizeof(uint64_t) * S) +
+                       align256(sizeof(int) * S) + align256(sizeof(double*) * S) +
+                       align256(sizeof(SpdeGrid) * S) * (size_t)(L + 1);
+  CK(hipMalloc(&W->mem, total + extra));
+  char* cur = (char*)W->mem;
+  auto take = [&](size_t b) {
+    void* p = cur;
+    cur += align256(b);
+    return p;
+  };
+  W->h.assign(L, std::vector<SpdeGrid>(S));
+  double hl = h;
+  const double kappa = 1.0 / P->desc.corr_len;
+  for (int l = 0; l < L; ++l, hl *= 2.0) {
+    const size_t N = (size_t)W->nts[l] * W->nts[l] * W->nts[l];
+    for (int g = 0; g < S; ++g) {
+      SpdeGrid& G = W->h[l][g];
+      double* a = (double*)take(3 * sizeof(double) * N);
+      G.z = a;
+      G.b = a + N;
+      G.r = a + 2 * N;
+      G.nt = W->nts[l];
+      G.k2h2 = kappa * kappa * hl * hl;
+      G.solve = g;
+    }
+  }
+  for (int l = 0; l + 1 < L; ++l)
+    for (int g = 0; g < S; ++g) {
+      W->h[l][g].zc = W->h[l + 1][g].z;
+      W->h[l][g].bc = W->h[l + 1][g].b;
+    }
+  W->d_active = (int*)take(sizeof(int) * 2 * S);
+  W->d_cycles = W->d_active + S;
+  W->d_bnorm = (double*)take(sizeof(double) * S);
+  W->d_part = (double*)take(sizeof(double) * (size_t)S * part);
+  W->d_seeds = (uint64_t*)take(sizeof(uint64_t) * S);
+  W->d_levels = (int*)take(sizeof(int) * S);
+  W->d_out = (double**)take(sizeof(double*) * S);
+  for (int l = 0; l < L; ++l) {
+    W->d.push_back((SpdeGrid*)take(sizeof(SpdeGrid) * S));
+    CK(hipMemcpy(W->d[l], W->h[l].data(), sizeof(SpdeGrid) * S, hipMemcpyHostToDevice));
+  }
+  W->d_link = (SpdeGrid*)take(sizeof(SpdeGrid) * S);
+  CK(hipHostMalloc((void**)&W->h_active, sizeof(int) * S, hipHostMallocDefault));
+  slot = std::move(W);
+  return slot.get();
+}
+
+// Solve every grid of W from z = 0 (its top b set); returns false if a solve
+// missed kSpdeTol.
+static bool spde_solve(mg_plan_s* P, SpdeWork* W) {
+  hipStream_t st = P->work;
+  const int S = W->S, L = (int)W->nts.size(), nt = W->nts[0];
+  CK(hipMemsetD32Async(W->d_active, 1, S, st));
+  for (int g = 0; g < S; ++g)
+    launch_fill(W->h[0][g].z, (long)nt * nt * nt, 0.0, st);
+  launch_spde_sumsq(W->d[0], S, nt, W->d_active, 1, W->d_part, st);
+  launch_spde_judge(W->d[0], S, nt, W->d_active, W->d_cycles, W->d_bnorm, W->d_part, 0, 0.0, 0, 1,
+                    st);
+  int left = S;
+  for (int c = 1; c <= kSpdeMaxCycles && left > 0; ++c) {
+    for (int l = 0; l + 1 < L; ++l) {
+      for (int s2 = 0; s2 < 2; ++s2) {
+        launch_spde_colour(W->d[l], S, W->nts[l], W->d_active, 0, st);
+        launch_spde_colour(W->d[l], S, W->nts[l], W->d_active, 1, st);
+      }
+      launch_spde_residual(W->d[l], S, W->nts[l], W->d_active, st);
+      launch_spde_restrict(W->d[l], S, W->nts[l], W->d_active, false, st);
+    }
+    launch_spde_coarsest(W->d[L - 1], S, W->nts[L - 1], W->d_active, st);
+    for (int l = L - 1; l-- > 0;) {
+      launch_spde_prolong(W->d[l], S, W->nts[l], W->d_active, st);
+      for (int s2 = 0; s2 < 2; ++s2) {
+        launch_spde_colour(W->d[l], S, W->nts[l], W->d_active, 0, st);
+        launch_spde_colour(W->d[l], S, W->nts[l], W->d_active, 1, st);
+      }
+    }
+    launch_spde_residual(W->d[0], S, nt, W->d_active, st);
+    launch_spde_sumsq(W->d[0], S, nt, W->d_active, 0, W->d_part, st);
+    launch_spde_judge(W->d[0], S, nt, W->d_active, W->d_cycles, W->d_bnorm, W->d_part, c,
+                      kSpdeTol, kSpdeMaxCycles, 0, st);
+    CK(hipMemcpyAsync(W->h_active, W->d_active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    left = 0;
+    for (int g = 0; g < S; ++g) left += W->h_active[g] != 0;
+  }
+  std::vector<int> cyc(S);
+  CK(hipMemcpy(cyc.data(), W->d_cycles, sizeof(int) * S, hipMemcpyDeviceToHost));
+  for (int c : cyc)
+    if (c < 0) return false;
+  return true;
+}
+
+// Fields of S samples of one MLMC level: fine into outs_f (n_f grids), for
+// level > 0 coarse into outs_c (n_c grids); mode 0 writes wh, 1 writes k.
+static int spde_fields(mg_plan_s* P, int level, const uint64_t* seeds, int S,
+                       const std::vector<double*>& outs_f, const std::vector<double*>& outs_c,
+                       int mode) {
+  hipStream_t st = P->work;
+  const int nf = level_n(P, level), ntf = 3 * (nf - 1) + 1;
+  const double kappa = 1.0 / P->desc.corr_len;
+  const double sc = std::sqrt(P->desc.sigma2) * std::sqrt(8.0 * 3.141592653589793 * kappa);
+  SpdeWork* Wf = spde_work(P, ntf, S, 1.0 / (double)(nf - 1));
+  const std::vector<int> lv(S, level);
+  CK(hipMemcpy(Wf->d_seeds, seeds, sizeof(uint64_t) * S, hipMemcpyHostToDevice));
+  CK(hipMemcpy(Wf->d_levels, lv.data(), sizeof(int) * S, hipMemcpyHostToDevice));
+  launch_spde_noise(Wf->d[0], S, ntf, Wf->d_seeds, Wf->d_levels, 1.0 / (double)(nf - 1), st);
+  if (!outs_f.empty()) {
+    if (!spde_solve(P, Wf)) return MG_ENOCONV;
+    CK(hipMemcpy(Wf->d_out, outs_f.data(), sizeof(double*) * S, hipMemcpyHostToDevice));
+    launch_spde_field(Wf->d[0], S, nf, sc, Wf->d_out, mode, st);
+  }
+  if (level > 0 && !outs_c.empty()) {
+    const int nc = level_n(P, level - 1), ntc = 3 * (nc - 1) + 1;
+    SpdeWork* Wc = spde_work(P, ntc, S, 1.0 / (double)(nc - 1));
+    // the same noise on the coarse box grid: b_c = P^T b_f / 2
+    std::vector<SpdeGrid> link = Wf->h[0];
+    for (int g = 0; g < S; ++g) {
+      link[g].bc = Wc->h[0][g].b;
+      link[g].zc = Wc->h[0][g].z;
+    }
+    CK(hipMemcpy(Wf->d_link, link.data(), sizeof(SpdeGrid) * S, hipMemcpyHostToDevice));
+    CK(hipMemsetD32Async(Wf->d_active, 1, S, st));
+    launch_spde_restrict(Wf->d_link, S, ntf, Wf->d_active, true, st);
+    if (!spde_solve(P, Wc)) return MG_ENOCONV;
+    CK(hipMemcpy(Wc->d_out, outs_c.data(), sizeof(double*) * S, hipMemcpyHostToDevice));
+    launch_spde_field(Wc->d[0], S, nc, sc, Wc->d_out, mode, st);
+  }
+  CK(hipStreamSynchronize(st));
   return MG_OK;
 }
 
@@ -1676,6 +1888,18 @@ static BatchSpec solve_spec(mg_plan_s* P, int n) {
 }
 }  // namespace mg
 
+mg_plan_s::~mg_plan_s() {
+  batch.reset();
+  fmg.clear();
+  spde.clear();
+  if (h_small) (void)hipHostFree(h_small);
+  for (auto& kv : d_phi) (void)hipFree(kv.second);
+  if (d_coef) (void)hipFree(d_coef);
+  for (auto e : ev_pool) (void)hipEventDestroy(e);
+  if (order_ev) (void)hipEventDestroy(order_ev);
+  if (work) (void)hipStreamDestroy(work);
+}
+
 // ============================== C ABI ==========================================
 
 #define API_BEGIN try {
@@ -1803,8 +2027,8 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
     P->qoi_kind = (int)value;
   } else if (k == "solver") {
     if (value != 0 && value != 1) return MG_EINVAL;
-    if (value == 1 && (P->desc.precision != MG_FP64 || P->op_fe)) {
-      P->err = "full multigrid runs in FP64 with the FD operator";
+    if (value == 1 && (P->desc.precision != MG_FP64 || P->op_fe || P->field_spde)) {
+      P->err = "full multigrid runs in FP64 with the FD operator and the KL field";
       return MG_ENOTIMPL;
     }
     P->solver = (int)value;
@@ -1816,6 +2040,15 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
     }
     P->op_fe = (int)value;
     P->batch.reset();  // the workspace layout differs
+    P->batch_key.clear();
+  } else if (k == "field") {
+    if (value != 0 && value != 1) return MG_EINVAL;
+    if (value == 1 && P->solver != 0) {
+      P->err = "full multigrid samples use the KL field";
+      return MG_ENOTIMPL;
+    }
+    P->field_spde = (int)value;
+    P->batch.reset();  // coarse solves own their coefficient with the SPDE field
     P->batch_key.clear();
   } else if (k == "fmg_cycles") {
     if (value < 1 || value > 64) return MG_EINVAL;
@@ -2103,6 +2336,23 @@ int mlmc_field(mg_plan P, int n, uint64_t seed, int level, double* k_out) {
   if (!valid_n(n) || n > 1025 || level < 0 || !k_out) return MG_EINVAL;
   API_BEGIN
   order_after_caller(P);
+  if (P->field_spde) {
+    if (level > P->desc.max_level) {
+      P->err = "mlmc_field: the SPDE field needs level <= max_level";
+      return MG_EINVAL;
+    }
+    int st;
+    if (n == level_n(P, level))
+      st = spde_fields(P, level, &seed, 1, {k_out}, {}, 1);
+    else if (level > 0 && n == level_n(P, level - 1))
+      st = spde_fields(P, level, &seed, 1, {}, {k_out}, 1);
+    else {
+      P->err = "mlmc_field: with the SPDE field n must be n_level or n_(level-1)";
+      return MG_EINVAL;
+    }
+    if (st != MG_OK) P->err = "mlmc_field: the SPDE solve missed its tolerance";
+    return st;
+  }
   uint64_t* d_seed = nullptr;
   double* d_norm = nullptr;
   double** d_out = nullptr;
@@ -2222,8 +2472,9 @@ int mg_serve_create(mg_plan P, const int* slots_per_level, int queue_capacity, m
     P->err = "mg_serve_create: queue_capacity must be >= 1";
     return MG_EINVAL;
   }
-  if (P->solver != 0 || P->qoi_kind != QOI_INTEGRAL || P->op_fe) {
-    P->err = "mg_serve_create: the server runs FD V-cycles to tol with the integral QoI";
+  if (P->solver != 0 || P->qoi_kind != QOI_INTEGRAL || P->op_fe || P->field_spde) {
+    P->err = "mg_serve_create: the server runs FD V-cycles to tol with the KL field and the "
+             "integral QoI";
     return MG_ENOTIMPL;
   }
   API_BEGIN

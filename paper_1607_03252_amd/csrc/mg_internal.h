@@ -243,4 +243,49 @@ void launch_fe_residual(const GridDesc* d_list, int count, int n, const int* d_a
                         hipStream_t st);
 void launch_fe_coarsest(const GridDesc* d_list, int count, const int* d_active, hipStream_t st);
 
+// ---- SPDE field sampler: (kappa^2 - Laplace) Z = W on the box (-1,2)^3 ----
+// One grid of one SPDE solve: the box grid at spacing h (nt = 3(n-1)+1
+// vertices per axis on the finest level), every vertex an unknown (natural
+// Neumann boundary), z fastest like the solver's grids.
+struct SpdeGrid {
+  double* z;      // iterate
+  double* b;      // scaled load (restricted residual on coarse levels)
+  double* r;      // residual scratch
+  double* zc;     // the next coarser level's z (nullptr on the coarsest)
+  double* bc;     // the next coarser level's b
+  double k2h2;    // kappa^2 h^2 of this level
+  int nt;         // vertices per axis
+  int solve;      // index into the active / cycle arrays
+};
+// load b_p = sqrt(h m_p) xi_p of `count` grids from the white noise of
+// (seeds[g], levels[g]): Philox counter (j, level, 1, 0), normals 2j, 2j+1
+void launch_spde_noise(const SpdeGrid* d_list, int count, int nt, const uint64_t* d_seeds,
+                       const int* d_levels, double h, hipStream_t st);
+void launch_spde_colour(const SpdeGrid* d_list, int count, int nt, const int* d_active, int colour,
+                        hipStream_t st);
+void launch_spde_residual(const SpdeGrid* d_list, int count, int nt, const int* d_active,
+                          hipStream_t st);
+// bc = P^T r / 2 on the next coarser level (and zc = 0); with from_b, of b
+// instead of r (the load of the same noise on a coarser box grid)
+void launch_spde_restrict(const SpdeGrid* d_list, int count, int nt, const int* d_active,
+                          bool from_b, hipStream_t st);
+void launch_spde_prolong(const SpdeGrid* d_list, int count, int nt, const int* d_active,
+                         hipStream_t st);
+// 32 red-black sweeps on an odd-interval coarsest grid (one workgroup per grid)
+void launch_spde_coarsest(const SpdeGrid* d_list, int count, int nt, const int* d_active,
+                          hipStream_t st);
+// per-grid partial sums of r^2 (which = 0) or b^2 (which = 1): spde_blocks(nt) per grid
+int spde_blocks(int nt);
+void launch_spde_sumsq(const SpdeGrid* d_list, int count, int nt, const int* d_active, int which,
+                       double* d_partials, hipStream_t st);
+// judge after a cycle: relres = sqrt(sum r^2) / bnorm; with bnorm_mode, store
+// bnorm = sqrt(sum b^2) instead
+void launch_spde_judge(const SpdeGrid* d_list, int count, int nt, int* d_active, int* d_cycles,
+                       double* d_bnorm, const double* d_partials, int cycle, double tol,
+                       int max_cycles, int bnorm_mode, hipStream_t st);
+// wh = exp(-s z) / 2 (mode 0) or k = exp(s z) (mode 1) at the n^3 vertices
+// of D (box index i + n - 1)
+void launch_spde_field(const SpdeGrid* d_list, int count, int n, double s, double* const* d_wh,
+                       int mode, hipStream_t st);
+
 }  // namespace mg

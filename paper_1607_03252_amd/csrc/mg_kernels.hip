@@ -2296,6 +2296,315 @@ void launch_fe_coarsest(const GridDesc* d_list, int count, const int* d_active, 
                      d_active);
 }
 
+// ---- SPDE field sampler (Section 3.2, eq. spde) --------------------------------
+// (kappa^2 - Laplace) Z = W on the box (-1,2)^3, natural Neumann boundary,
+// lumped-mass P1 elements on the Kuhn tetrahedra of the box grid, scaled by
+// 1/h: (K' + kappa^2 h^2 diag(m)) Z = sqrt(h m) xi.  With unit coefficient the
+// element couplings count tetrahedra: an axis edge p -- p + e_d lies in the
+// four cells p - s_a e_a - s_b e_b (s_a, s_b in {0, 1}; a, b the other axes),
+// which hold 2 Kuhn tetrahedra containing it when s_a == s_b and 1 otherwise,
+// each adding 1/6; a cell outside the box adds nothing.  The lumped mass of p
+// (in units of h^3) is 1/24 times, over the cells at p, 6 where p is the
+// cell's (0,0,0) or (1,1,1) corner (all six tetrahedra) and 2 at the other
+// corners.
+__device__ __forceinline__ bool spde_cell(int nt, int a, int b, int c) {
+  return a >= 0 && b >= 0 && c >= 0 && a <= nt - 2 && b <= nt - 2 && c <= nt - 2;
+}
+__device__ __forceinline__ double spde_mass(int nt, int i, int j, int k) {
+  int w = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int di = q >> 2, dj = (q >> 1) & 1, dk = q & 1;
+    if (spde_cell(nt, i - di, j - dj, k - dk)) w += (di == dj && dj == dk) ? 6 : 2;
+  }
+  return (double)w / 24.0;
+}
+// coupling of p = (i, j, k) to p + e_d (0 if that edge leaves the box)
+__device__ __forceinline__ double spde_coupling(int nt, int i, int j, int k, int d) {
+  const int p[3] = {i, j, k};
+  if (p[d] < 0 || p[d] > nt - 2) return 0.0;
+  const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+  int w = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int sa = q >> 1, sb = q & 1;
+    int c[3] = {i, j, k};
+    c[a] -= sa;
+    c[b] -= sb;
+    if (spde_cell(nt, c[0], c[1], c[2])) w += sa == sb ? 2 : 1;
+  }
+  return (double)w / 6.0;
+}
+// D + kappa^2 h^2 m and S = sum of couplings times neighbour values at p
+__device__ __forceinline__ St<double> spde_stencil(const double* z, int nt, int i, int j, int k) {
+  const int si = nt * nt, sj = nt, v = (i * nt + j) * nt + k;
+  const double a0 = i >= 1 ? spde_coupling(nt, i - 1, j, k, 0) : 0.0;
+  const double a1 = spde_coupling(nt, i, j, k, 0);
+  const double a2 = j >= 1 ? spde_coupling(nt, i, j - 1, k, 1) : 0.0;
+  const double a3 = spde_coupling(nt, i, j, k, 1);
+  const double a4 = k >= 1 ? spde_coupling(nt, i, j, k - 1, 2) : 0.0;
+  const double a5 = spde_coupling(nt, i, j, k, 2);
+  // neighbours outside the box have coupling 0: read p itself there
+  return stencil_faces<double>(a0, a1, a2, a3, a4, a5, z[i >= 1 ? v - si : v],
+                               z[i <= nt - 2 ? v + si : v], z[j >= 1 ? v - sj : v],
+                               z[j <= nt - 2 ? v + sj : v], z[k >= 1 ? v - 1 : v],
+                               z[k <= nt - 2 ? v + 1 : v]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_spde_noise(const SpdeGrid* __restrict__ list,
+                                                       const uint64_t* __restrict__ seeds,
+                                                       const int* __restrict__ levels, int nt,
+                                                       double h, int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const long N = (long)nt * nt * nt;
+  const long jb = (long)blk * kBlock + threadIdx.x;
+  if (2 * jb >= N) return;
+  const SpdeGrid g = list[gi];
+  const uint64_t seed = seeds[gi];
+  uint32_t c[4] = {(uint32_t)jb, (uint32_t)levels[gi], 1u, 0u};
+  philox_block(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t M0 = ((uint64_t)(c[0] >> 5) << 26) | (uint64_t)(c[1] >> 6);
+  const uint64_t M1 = ((uint64_t)(c[2] >> 5) << 26) | (uint64_t)(c[3] >> 6);
+  const double U0 = (double)(M0 + 1) * 0x1p-53, U1 = (double)(M1 + 1) * 0x1p-53;
+  const double R = sqrt(-2.0 * log(U0)), ang = 6.283185307179586 * U1;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const long p = 2 * jb + e;
+    if (p >= N) break;
+    const int k = (int)(p % nt), j = (int)((p / nt) % nt), i = (int)(p / ((long)nt * nt));
+    const double xi = e == 0 ? R * cos(ang) : R * sin(ang);
+    g.b[p] = sqrt(h * spde_mass(nt, i, j, k)) * xi;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_spde_colour(const SpdeGrid* __restrict__ list,
+                                                        const int* __restrict__ active, int colour,
+                                                        int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const SpdeGrid g = list[gi];
+  if (!active[g.solve]) return;
+  const int nt = g.nt;
+  const Pt p = full_point(nt, blk);
+  if (!p.ok || ((p.i + p.j + p.k) & 1) != colour) return;
+  const int v = (p.i * nt + p.j) * nt + p.k;
+  const St<double> st = spde_stencil(g.z, nt, p.i, p.j, p.k);
+  g.z[v] = (g.b[v] + st.S) / (st.D + g.k2h2 * spde_mass(nt, p.i, p.j, p.k));
+}
+
+__global__ void __launch_bounds__(kBlock) k_spde_residual(const SpdeGrid* __restrict__ list,
+                                                          const int* __restrict__ active,
+                                                          int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const SpdeGrid g = list[gi];
+  if (!active[g.solve]) return;
+  const int nt = g.nt;
+  const Pt p = full_point(nt, blk);
+  if (!p.ok) return;
+  const int v = (p.i * nt + p.j) * nt + p.k;
+  const St<double> st = spde_stencil(g.z, nt, p.i, p.j, p.k);
+  const double diag = st.D + g.k2h2 * spde_mass(nt, p.i, p.j, p.k);
+  g.r[v] = g.b[v] - (diag * g.z[v] - st.S);
+}
+
+// over the coarse vertices: bc = P^T src / 2 (src = r, or b with from_b), zc = 0
+__global__ void __launch_bounds__(kBlock) k_spde_restrict(const SpdeGrid* __restrict__ list,
+                                                          const int* __restrict__ active,
+                                                          int from_b, int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const SpdeGrid g = list[gi];
+  if (!active[g.solve]) return;
+  const int nt = g.nt, ntc = (nt - 1) / 2 + 1;
+  const Pt p = full_point(ntc, blk);
+  if (!p.ok) return;
+  const double* src = from_b ? g.b : g.r;
+  double sum = 0.0;
+  for (int di = -1; di <= 1; ++di)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int dk = -1; dk <= 1; ++dk) {
+        const int i = 2 * p.i + di, j = 2 * p.j + dj, k = 2 * p.k + dk;
+        if (i < 0 || j < 0 || k < 0 || i >= nt || j >= nt || k >= nt) continue;
+        const double w = (di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * (dk ? 0.5 : 1.0);
+        sum += w * src[(i * nt + j) * nt + k];
+      }
+  const int vc = (p.i * ntc + p.j) * ntc + p.k;
+  g.bc[vc] = 0.5 * sum;
+  g.zc[vc] = 0.0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_spde_prolong(const SpdeGrid* __restrict__ list,
+                                                         const int* __restrict__ active, int count,
+                                                         int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const SpdeGrid g = list[gi];
+  if (!active[g.solve]) return;
+  const int nt = g.nt, ntc = (nt - 1) / 2 + 1;
+  const Pt p = full_point(nt, blk);
+  if (!p.ok) return;
+  double sum = 0.0;
+  for (int a = 0; a <= (p.i & 1); ++a)
+    for (int b = 0; b <= (p.j & 1); ++b)
+      for (int c = 0; c <= (p.k & 1); ++c) {
+        const double w = ((p.i & 1) ? 0.5 : 1.0) * ((p.j & 1) ? 0.5 : 1.0) * ((p.k & 1) ? 0.5 : 1.0);
+        sum += w * g.zc[((p.i / 2 + a) * ntc + p.j / 2 + b) * ntc + p.k / 2 + c];
+      }
+  g.z[(p.i * nt + p.j) * nt + p.k] += sum;
+}
+
+// the coarsest grid (64 vertices for these boxes): 32 red-black sweeps in LDS
+__global__ void __launch_bounds__(64) k_spde_coarsest(const SpdeGrid* __restrict__ list,
+                                                      const int* __restrict__ active) {
+  const SpdeGrid g = list[blockIdx.x];
+  if (!active[g.solve]) return;
+  const int nt = g.nt, N = nt * nt * nt, t = threadIdx.x;
+  __shared__ double z[64];
+  const bool own = t < N;
+  if (own) z[t] = g.z[t];
+  __syncthreads();
+  const int i = t / (nt * nt), j = (t / nt) % nt, k = t % nt;
+  for (int s = 0; s < 32; ++s)
+    for (int colour = 0; colour < 2; ++colour) {
+      if (own && ((i + j + k) & 1) == colour) {
+        const St<double> st = spde_stencil(z, nt, i, j, k);
+        z[t] = (g.b[t] + st.S) / (st.D + g.k2h2 * spde_mass(nt, i, j, k));
+      }
+      __syncthreads();
+    }
+  if (own) g.z[t] = z[t];
+}
+
+int spde_blocks(int nt) {
+  const long N = (long)nt * nt * nt;
+  return (int)std::min<long>(256, std::max<long>(1, (N + 4095) / 4096));
+}
+
+// a fixed contiguous range of the grid per workgroup, fixed order inside
+__global__ void __launch_bounds__(kBlock) k_spde_sumsq(const SpdeGrid* __restrict__ list,
+                                                       const int* __restrict__ active, int which,
+                                                       double* __restrict__ partials, int count,
+                                                       int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const SpdeGrid g = list[gi];
+  if (!active[g.solve]) return;
+  const long N = (long)g.nt * g.nt * g.nt;
+  const long chunk = (N + per - 1) / per;
+  const long lo = (long)blk * chunk, hi = std::min<long>(N, lo + chunk);
+  const double* x = which ? g.b : g.r;
+  double acc = 0.0;
+  for (long p = lo + threadIdx.x; p < hi; p += kBlock) acc += x[p] * x[p];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partials[(size_t)gi * per + blk] = acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_spde_judge(const SpdeGrid* __restrict__ list,
+                                                       int* __restrict__ active,
+                                                       int* __restrict__ cycles,
+                                                       double* __restrict__ bnorm,
+                                                       const double* __restrict__ partials,
+                                                       int per, int cycle, double tol,
+                                                       int max_cycles, int bnorm_mode) {
+  const int gi = blockIdx.x;
+  const int sv = list[gi].solve;
+  if (!active[sv]) return;
+  double v = 0.0;
+  for (int q = threadIdx.x; q < per; q += kBlock) v += partials[(size_t)gi * per + q];
+  v = block_sum(v);
+  if (threadIdx.x != 0) return;
+  if (bnorm_mode) {
+    bnorm[sv] = v > 0.0 ? sqrt(v) : 1.0;
+    return;
+  }
+  const double rho = sqrt(v) / bnorm[sv];
+  if (rho <= tol) {
+    active[sv] = 0;
+    cycles[sv] = cycle;
+  } else if (cycle >= max_cycles) {
+    active[sv] = 0;
+    cycles[sv] = -1;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_spde_field(const SpdeGrid* __restrict__ list, int n,
+                                                       double s, double* const* __restrict__ whl,
+                                                       int mode, int count, int per) {
+  int gi, blk;
+  if (!xcd_unit(count, per, gi, blk)) return;
+  const Pt p = full_point(n, blk);
+  if (!p.ok) return;
+  const SpdeGrid g = list[gi];
+  const int nt = g.nt, o = n - 1;
+  const double z = g.z[((p.i + o) * nt + p.j + o) * nt + p.k + o];
+  whl[gi][(p.i * n + p.j) * n + p.k] = mode ? exp(s * z) : 0.5 * exp(-s * z);
+}
+
+void launch_spde_noise(const SpdeGrid* d_list, int count, int nt, const uint64_t* d_seeds,
+                       const int* d_levels, double h, hipStream_t st) {
+  if (count <= 0) return;
+  const long N = (long)nt * nt * nt;
+  const int per = (int)(((N + 1) / 2 + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_spde_noise, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_seeds,
+                     d_levels, nt, h, count, per);
+}
+void launch_spde_colour(const SpdeGrid* d_list, int count, int nt, const int* d_active, int colour,
+                        hipStream_t st) {
+  if (count <= 0) return;
+  const int per = point_blocks(nt);
+  hipLaunchKernelGGL(k_spde_colour, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
+                     colour, count, per);
+}
+void launch_spde_residual(const SpdeGrid* d_list, int count, int nt, const int* d_active,
+                          hipStream_t st) {
+  if (count <= 0) return;
+  const int per = point_blocks(nt);
+  hipLaunchKernelGGL(k_spde_residual, xcd_grid(count, per), dim3(kBlock), 0, st, d_list,
+                     d_active, count, per);
+}
+void launch_spde_restrict(const SpdeGrid* d_list, int count, int nt, const int* d_active,
+                          bool from_b, hipStream_t st) {
+  if (count <= 0) return;
+  const int per = point_blocks((nt - 1) / 2 + 1);
+  hipLaunchKernelGGL(k_spde_restrict, xcd_grid(count, per), dim3(kBlock), 0, st, d_list,
+                     d_active, from_b ? 1 : 0, count, per);
+}
+void launch_spde_prolong(const SpdeGrid* d_list, int count, int nt, const int* d_active,
+                         hipStream_t st) {
+  if (count <= 0) return;
+  const int per = point_blocks(nt);
+  hipLaunchKernelGGL(k_spde_prolong, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
+                     count, per);
+}
+void launch_spde_coarsest(const SpdeGrid* d_list, int count, int nt, const int* d_active,
+                          hipStream_t st) {
+  if (count <= 0 || nt * nt * nt > 64) return;
+  hipLaunchKernelGGL(k_spde_coarsest, dim3(count), dim3(64), 0, st, d_list, d_active);
+}
+void launch_spde_sumsq(const SpdeGrid* d_list, int count, int nt, const int* d_active, int which,
+                       double* d_partials, hipStream_t st) {
+  if (count <= 0) return;
+  const int per = spde_blocks(nt);
+  hipLaunchKernelGGL(k_spde_sumsq, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
+                     which, d_partials, count, per);
+}
+void launch_spde_judge(const SpdeGrid* d_list, int count, int nt, int* d_active, int* d_cycles,
+                       double* d_bnorm, const double* d_partials, int cycle, double tol,
+                       int max_cycles, int bnorm_mode, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_spde_judge, dim3(count), dim3(kBlock), 0, st, d_list, d_active, d_cycles,
+                     d_bnorm, d_partials, spde_blocks(nt), cycle, tol, max_cycles, bnorm_mode);
+}
+void launch_spde_field(const SpdeGrid* d_list, int count, int n, double s, double* const* d_wh,
+                       int mode, hipStream_t st) {
+  if (count <= 0) return;
+  const int per = point_blocks(n);
+  hipLaunchKernelGGL(k_spde_field, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, n, s, d_wh,
+                     mode, count, per);
+}
+
 // Y = Q_f - Q_c from two batches' per-solve QoIs (solve t of each is sample
 // t; qc == nullptr: level 0), with the cycle counts of both solves, written
 // at output position pos[t].
