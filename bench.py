@@ -21,7 +21,8 @@ Prints one JSON line (the byte model is in the repository's design notes):
                  residual), scaled by the GPU run's mean cycle count to
                  samples per second; plus the single-thread latency;
   extra        = the 64-pair level-1 batch (65^3 + 33^3), the mixed-precision
-                 form on the same 257^3 inputs, and a device copy's rate.
+                 form on the same 257^3 inputs (one and two FP32 V-cycles per
+                 FP64 defect-correction step), and a device copy's rate.
 """
 import argparse
 import concurrent.futures as cf
@@ -43,8 +44,17 @@ SWEEP_BYTES_PER_NODE = 24.0
 COARSE_BYTES_PER_NODE = 8.0
 # byte model of one FP64 V(2,2) cycle per finest-grid node (whole hierarchy)
 VCYCLE_BYTES_PER_NODE = 195.0
-# mixed precision per outer step: FP32 V(2,2) (~98) + FP64 defect and update (48)
-MIXED_BYTES_PER_NODE = 146.0
+# mixed precision: an FP32 V(2,2) cycle (~98) per cycle, plus the FP64 defect
+# and update (48) once per outer step of inner_cycles cycles
+MIXED_FP32_CYCLE_BYTES = 98.0
+MIXED_FP64_STEP_BYTES = 48.0
+
+
+def mixed_bytes_per_node(inner_cycles=1):
+    """Byte model of one V-cycle of mixed precision per finest-grid node."""
+    return MIXED_FP32_CYCLE_BYTES + MIXED_FP64_STEP_BYTES / inner_cycles
+
+
 KIND_NAMES = {0: "plain", 1: "coarse_correction", 2: "output_residual", 3: "input_residual"}
 
 CFG4 = dict(n=257, samples=16, sigma2=2.0, corr_len=0.05, tol=1e-8)
@@ -130,6 +140,8 @@ def parse_args():
                     choices=["config4", "levelpair", "single", "mixed", "fp32mix", "serve"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="precision of the default workload")
+    ap.add_argument("--inner-cycles", type=int, default=1,
+                    help="mixed precision: FP32 V-cycles per FP64 defect-correction step")
     ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--serve-slots", default="128,64,16,4")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
@@ -179,19 +191,25 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    out = bench_config4(args, M, torch, np, M.MG_FP64 if args.precision == "fp64" else M.MG_MIXED)
+    out = bench_config4(args, M, torch, np, M.MG_FP64 if args.precision == "fp64" else M.MG_MIXED,
+                        inner=args.inner_cycles)
     if not args.no_extra:
         extra = {}
         lp = bench_levelpair(args, M, torch, np, steps=min(args.steps, 10), profile=False)
         extra["levelpair_65_33_x64"] = {k: lp[k] for k in ("value", "unit", "ms_per_step")}
         extra["levelpair_65_33_x64"]["fine_cycles_mean"] = lp["per_level"]["1"]["fine_cycles_mean"]
         if args.precision == "fp64":
-            mx = bench_config4(args, M, torch, np, M.MG_MIXED, steps=min(args.steps, 5),
-                               warmup=1, profile=False)
-            extra["mixed_precision_257_x16"] = {
-                "value": mx["value"], "unit": "samples/s", "ms_per_step": mx["ms_per_step"],
-                "speedup_vs_fp64": mx["value"] / out["value"],
-                "max_rel_dQ_vs_fp64": float(np.max(np.abs(mx["_Q"] - out["_Q"]) / np.abs(out["_Q"])))}
+            for inner in (1, 2):
+                mx = bench_config4(args, M, torch, np, M.MG_MIXED, steps=min(args.steps, 5),
+                                   warmup=1, profile=False, inner=inner)
+                key = "mixed_precision_257_x16" + ("" if inner == 1 else "_inner%d" % inner)
+                extra[key] = {
+                    "value": mx["value"], "unit": "samples/s", "ms_per_step": mx["ms_per_step"],
+                    "inner_cycles": inner,
+                    "fine_cycles_mean": mx["per_level"]["0"]["fine_cycles_mean"],
+                    "speedup_vs_fp64": mx["value"] / out["value"],
+                    "max_rel_dQ_vs_fp64": float(np.max(np.abs(mx["_Q"] - out["_Q"])
+                                                       / np.abs(out["_Q"])))}
         cp = device_copy(torch)
         cp["sweep_fraction_of_copy"] = out["roofline"]["achieved"] / cp["GBps"]
         extra["device_copy"] = cp
@@ -260,7 +278,7 @@ def read_traffic(name, tiles):
     return None, None, None
 
 
-def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profile=True):
+def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profile=True, inner=1):
     n, S = CFG4["n"], CFG4["samples"]
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
@@ -269,6 +287,8 @@ def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profil
     for spec in args.opt:
         name, value = spec.split("=")
         M.mg_plan_set_option(P, name, int(value))
+    if precision == M.MG_MIXED:
+        M.mg_plan_set_option(P, "inner_cycles", inner)
     for spec in args.tile:
         nn, tj, tk, ch = (int(x) for x in spec.split(":"))
         M.mg_set_tile(P, nn, tj, tk, ch)
@@ -300,7 +320,7 @@ def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profil
     cyc_mean = float(cyc_np.mean())
     value = S * steps / dt
     ms_step = 1e3 * dt / steps
-    per_node = VCYCLE_BYTES_PER_NODE if precision == M.MG_FP64 else MIXED_BYTES_PER_NODE
+    per_node = VCYCLE_BYTES_PER_NODE if precision == M.MG_FP64 else mixed_bytes_per_node(inner)
     eff = per_node * n**3 * float(cyc_np.sum()) / dt / 1e9
     out = {
         "metric": "MLMC samples/sec per level + V-cycle HBM GB/s; p50/p99 solve latency",
@@ -309,7 +329,8 @@ def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profil
         "dtype": "f64" if precision == M.MG_FP64 else "f64+f32",
         "data": "synthetic (Philox-seeded 64-term KL lognormal fields)",
         "config": {"workload": "mlmc_level0_n257_x16_sigma2_2_lambda_0.05"
-                               + ("" if precision == M.MG_FP64 else "_mixed_precision"),
+                               + ("" if precision == M.MG_FP64 else "_mixed_precision"
+                                  + ("" if inner == 1 else "_inner%d" % inner)),
                    "n": n, "samples_per_step": S, "sigma2": CFG4["sigma2"],
                    "corr_len": CFG4["corr_len"], "tol": CFG4["tol"],
                    "cycle": "V(2,2) red-black GS, 8 levels", "parallelism": "single GPU",
@@ -580,8 +601,11 @@ def bench_fp32mix(args, M, torch, np):
     seeds = np.arange(S, dtype=np.uint64)
     res = {}
     Q = {}
-    for name, prec in (("fp64", M.MG_FP64), ("mixed", M.MG_MIXED)):
+    for name, prec, inner in (("fp64", M.MG_FP64, 1), ("mixed", M.MG_MIXED, 1),
+                              ("mixed_inner2", M.MG_MIXED, 2)):
         P = M.mg_plan_create(n0=n, max_level=0, sigma2=2.0, corr_len=0.05, precision=prec)
+        if prec == M.MG_MIXED:
+            M.mg_plan_set_option(P, "inner_cycles", inner)
         Y, Qf, Qc, cyc = _samples(M, torch, P, 0, seeds)
         M.mlmc_sample_batch(P, 0, seeds, S, Y, Qf, Qc, cyc)
         steps = max(1, min(args.steps, 3))
@@ -592,7 +616,7 @@ def bench_fp32mix(args, M, torch, np):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         c = cyc.cpu().numpy().reshape(S, 2)[:, 0]
-        per_node = VCYCLE_BYTES_PER_NODE if prec == M.MG_FP64 else MIXED_BYTES_PER_NODE
+        per_node = VCYCLE_BYTES_PER_NODE if prec == M.MG_FP64 else mixed_bytes_per_node(inner)
         res[name] = {"batch_s": dt, "samples_per_s": S / dt, "cycles_mean": float(c.mean()),
                      "effective_GBps": per_node * n**3 * float(c.sum()) / dt / 1e9}
         Q[name] = Qf.cpu().numpy()
@@ -606,6 +630,9 @@ def bench_fp32mix(args, M, torch, np):
     out["forms"] = res
     out["speedup_mixed_vs_fp64"] = res["fp64"]["batch_s"] / res["mixed"]["batch_s"]
     out["max_rel_dQ_mixed_vs_fp64"] = dq
+    out["speedup_mixed_inner2_vs_fp64"] = res["fp64"]["batch_s"] / res["mixed_inner2"]["batch_s"]
+    out["max_rel_dQ_mixed_inner2_vs_fp64"] = float(
+        np.max(np.abs(Q["mixed_inner2"] - Q["fp64"]) / np.abs(Q["fp64"])))
     return out
 
 

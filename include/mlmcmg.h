@@ -189,6 +189,15 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *               fmg_cycles; fixed_cycles is ignored;
  *   "fmg_cycles": V-cycles per grid of the full multigrid schedule (1..64,
  *               default 2).
+ *   "inner_cycles": mixed precision (MG_MIXED plans): FP32 V(nu1,nu2) cycles
+ *               per FP64 defect-correction step (1..8, default 1).  With c
+ *               inner cycles a step applies, in exact arithmetic, the same
+ *               correction as c FP64 V-cycles (the cycle is linear in the
+ *               error), so the FP64 defect and correction passes are paid once
+ *               per c cycles; convergence is still judged by the FP64 residual
+ *               after each step, and cycles_out counts V-cycles (steps x c):
+ *               a multiple of c, so fixed_cycles and max_cycles are in effect
+ *               rounded up to multiples of c.  Ignored by FP64 plans.
  *   "operator": 0 (default) = 7-point finite differences with harmonic-mean
  *               face coefficients; 1 = the paper's P1 finite elements
  *               (Section 3.1) on the Kuhn tetrahedra of the vertex grid (every

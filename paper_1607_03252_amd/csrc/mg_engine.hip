@@ -230,6 +230,7 @@ struct mg_plan_s {
   int solver = 0;        // 0: V-cycles to tol, 1: full multigrid (fixed schedule)
   int fmg_cycles = 2;    // V-cycles per grid of the full multigrid schedule
   int op_fe = 0;         // 1: the P1 finite-element operator instead of FD
+  int inner_cycles = 1;  // mixed precision: FP32 V-cycles per FP64 defect-correction step
   int field_spde = 0;    // 1: coefficient fields from the SPDE sampler instead of KL
   // SPDE sampler workspaces keyed by (finest box size, solves)
   std::map<std::pair<int, int>, std::unique_ptr<mg::SpdeWork>> spde;
@@ -673,7 +674,6 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
   return out;
 }
 
-void launch_tick(int* ctr, hipStream_t st);
 
 // Partials per grid when the top grids of size index si take their
 // convergence norm from the sweeps (the black residuals from a cycle's last
@@ -817,7 +817,9 @@ static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
   hipStream_t st = B->st;
   Lists<double>& L = Lp ? *Lp : B->L64;
   if (P->prof) ++P->prof_cycle;  // (eager while profiling: one call per cycle)
-  launch_tick(B->d_cycle, st);
+  // the counter counts V-cycles: a mixed-precision step applies inner_cycles
+  const int per_step = B->spec.mixed ? P->inner_cycles : 1;
+  launch_tick(B->d_cycle, st, per_step);
   if (B->spec.fe) {
     run_cycle_fe(P, B, L);
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
@@ -846,10 +848,19 @@ static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
       const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
       launch_defect(B->L64.dtop[ti], B->L32.dtop[ti], cnt, n, B->ss.active, B->ss.partials, st);
-      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, 1, fixed,
+      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, per_step, fixed,
                        P->desc.max_cycles, tol, st);
     }
-    const int out = run_cycle<float>(P, B, B->L32);
+    // inner_cycles FP32 V-cycles on A e = r from e = 0; the next one starts
+    // from the last one's e (in buffer 0)
+    int out = 0;
+    for (int c = 0; c < P->inner_cycles; ++c) {
+      if (out != 0)
+        for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
+          launch_copy_buf<float>(B->L32.dtop[ti], (int)B->L32.htop[ti].size(), B->top_sizes[ti],
+                                 B->ss.active, 1, st);
+      out = run_cycle<float>(P, B, B->L32);
+    }
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti)
       launch_correct(B->L64.dtop[ti], B->L32.dtop[ti], (int)B->L64.htop[ti].size(),
                      B->top_sizes[ti], B->ss.active, out, st);
@@ -930,7 +941,9 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
   int extra = B->spec.mixed ? 1 : 0;
   for (int n : B->top_sizes)
     if (lagged_parts(P, B, size_index(B->sizes, n)) > 0) extra = 1;
-  const int limit = (fixed > 0 ? fixed : P->desc.max_cycles) + extra;
+  // (in steps of cycle_step: a mixed-precision step is inner_cycles V-cycles)
+  const int per_step = B->spec.mixed ? P->inner_cycles : 1;
+  const int limit = ceil_div(fixed > 0 ? fixed : P->desc.max_cycles, per_step) + extra;
   const bool use_graphs = graphs && P->use_graph && !P->prof;
   // the last cycles of a batch, once at most a quarter of the solves still
   // cycle, run on lists of those solves' grids only: the sweeps then split
@@ -960,7 +973,7 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
       // the first launch covers the steps the last batch needed (a step in
       // which every solve has stopped costs only launches that exit at once;
       // a missing one costs a round trip to the host)
-      const int guess = fixed > 0 ? fixed + extra : B->last_cycles;
+      const int guess = fixed > 0 ? ceil_div(fixed, per_step) + extra : B->last_cycles;
       c = done == 0 ? std::max(1, std::min(limit, guess)) : 1;
       CK(hipGraphLaunch(graph_for(P, B, c, tol, fixed), st));
     } else {
@@ -985,7 +998,7 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
     if (cyc[q] < 0) ok = false;
     maxc = std::max(maxc, cyc[q]);
   }
-  B->last_cycles = maxc + extra;
+  B->last_cycles = ceil_div(maxc, per_step) + extra;
   return ok;
 }
 
@@ -2050,6 +2063,9 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
     P->field_spde = (int)value;
     P->batch.reset();  // coarse solves own their coefficient with the SPDE field
     P->batch_key.clear();
+  } else if (k == "inner_cycles") {
+    if (value < 1 || value > 8) return MG_EINVAL;
+    P->inner_cycles = (int)value;
   } else if (k == "fmg_cycles") {
     if (value < 1 || value > 64) return MG_EINVAL;
     P->fmg_cycles = (int)value;

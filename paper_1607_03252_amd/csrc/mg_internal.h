@@ -210,13 +210,13 @@ void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
                       const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
                       hipStream_t st, int sweep_parts = 0, int sweep_parts_red = 0);
 // active = 1, cycles = 0, start = 0, qpend = qpend, *cycle_ctr = 0;
-// launch_tick: *cycle_ctr += 1.
+// launch_tick: *cycle_ctr += inc (the V-cycles of one step).
 void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st, int qpend = 0);
 // Start the listed solves now: active = 1, cycles = 0, start = *cycle_ctr,
 // qpend = 1.
 void launch_admit(const int* d_solves, int count, SolveState s, const int* cycle_ctr,
                   hipStream_t st);
-void launch_tick(int* ctr, hipStream_t st);
+void launch_tick(int* ctr, hipStream_t st, int inc = 1);
 void launch_ydiff(const double* d_q, const int* d_fine_idx, const int* d_coarse_idx, int count,
                   double* d_y, double* d_qf, double* d_qc, const int* d_cycles, int* d_cycles_out,
                   hipStream_t st);

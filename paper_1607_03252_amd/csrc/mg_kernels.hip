@@ -1760,8 +1760,8 @@ __global__ void k_admit(const int* __restrict__ solves, int count, SolveState s,
   s.qpend[sv] = 1;
 }
 
-__global__ void k_tick(int* __restrict__ ctr) {
-  if (threadIdx.x == 0) *ctr += 1;
+__global__ void k_tick(int* __restrict__ ctr, int inc) {
+  if (threadIdx.x == 0) *ctr += inc;
 }
 
 __global__ void k_ydiff(const double* __restrict__ q, const int* __restrict__ fi,
@@ -2135,8 +2135,8 @@ void launch_admit(const int* d_solves, int count, SolveState s, const int* cycle
                      cycle_ctr);
 }
 
-void launch_tick(int* ctr, hipStream_t st) {
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, ctr);
+void launch_tick(int* ctr, hipStream_t st, int inc) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, ctr, inc);
 }
 
 // QoIs of Section 3 besides the integral, on the top grids (u[0]), one

@@ -5,7 +5,8 @@ zero initial guess, V(2,2) red-black Gauss-Seidel to relative residual 1e-8).
 
 Calls only the oracle (oracle/); nothing here comes from the HIP library.
 For every seed: Q = integral of u, the cycle count and the relative residual
-history.  For seeds 0 and 1 also ||u||_2 over the interior, u on the
+history, and Q_next, the integral of the iterate after one more V(2,2) cycle
+(the result of a solver that stops one cycle later, e.g. at an even count).  For seeds 0 and 1 also ||u||_2 over the interior, u on the
 sub-lattice of every 16th vertex per axis, and the projections <u, w_q> on
 16 Rademacher vectors w_q (entries +-1 over the interior vertices, drawn
 from numpy's PCG64 with seed 1000 + q, 0 -> -1 and 1 -> +1), from which a
@@ -42,7 +43,8 @@ def one(seed):
     xi = O.gaussians(seed, 0)
     k = O.field(N, SIGMA2, LAM, xi)
     u, cyc, rel, hist = O.solve(k, O.rhs(N), tol=TOL, max_cycles=50)
-    rec = {"seed": seed, "Q": O.qoi(u), "cycles": cyc, "relres": rel, "history": hist.tolist()}
+    rec = {"seed": seed, "Q": O.qoi(u), "cycles": cyc, "relres": rel, "history": hist.tolist(),
+           "Q_next": O.qoi(O.vcycle(k, O.rhs(N), u))}
     if seed in DETAIL:
         ui = u[1:-1, 1:-1, 1:-1].ravel()
         rec["norm2"] = O.norm2(u)
