@@ -38,12 +38,26 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 # algorithmic bytes per interior node of one fused red-black sweep with a
-# constant right-hand side: wh (8) + u read (8) + u written (8); the sweep
-# with the coarse-grid correction also reads the coarse iterate once
+# constant right-hand side: wh (8) + u read (8) + u written (8); with the KL
+# coefficient evaluated in the sweep (plan option kl = 1) wh is not read: 16;
+# the sweep with the coarse-grid correction also reads the coarse iterate once
 SWEEP_BYTES_PER_NODE = 24.0
+SWEEP_KL_BYTES_PER_NODE = 16.0
 COARSE_BYTES_PER_NODE = 8.0
+
+
+def kl_inline(args):
+    """Whether the plan options turn the in-kernel KL coefficient on."""
+    for spec in args.opt:
+        name, value = spec.split("=")
+        if name == "kl":
+            return int(value) != 0
+    return False
 # byte model of one FP64 V(2,2) cycle per finest-grid node (whole hierarchy)
 VCYCLE_BYTES_PER_NODE = 195.0
+# the same with the KL coefficient formed in the finest grid's four sweeps and
+# its residual-restriction (8 bytes per node each not read)
+VCYCLE_KL_BYTES_PER_NODE = VCYCLE_BYTES_PER_NODE - 5 * 8.0
 # mixed precision: an FP32 V(2,2) cycle (~98) per cycle, plus the FP64 defect
 # and update (48) once per outer step of inner_cycles cycles
 MIXED_FP32_CYCLE_BYTES = 98.0
@@ -239,10 +253,11 @@ def device_copy(torch, nbytes=1 << 30, reps=5):
     return {"bytes": nbytes, "GBps": gbps, "frac_of_peak": gbps / HBM_PEAK_GBPS}
 
 
-def sweep_roofline(M, P, n, samples, cycles_min):
+def sweep_roofline(M, P, n, samples, cycles_min, kl=True):
     """Algorithmic bytes over duration of the timed sweep launches on the n^3
     grids in cycles 1..cycles_min of each profiled batch (every solve still
-    cycles there, so every launch moves every grid)."""
+    cycles there, so every launch moves every grid); kl: the sweeps form the
+    coefficient themselves (16 instead of 24 bytes per node)."""
     cyc, kind, ms = M.mg_profile_records(P)
     nodes = samples * float(n - 2) ** 3
     nc = (n - 1) // 2 + 1
@@ -252,7 +267,8 @@ def sweep_roofline(M, P, n, samples, cycles_min):
     tot_b, tot_ms = 0.0, 0.0
     for k in sorted(set(kind[sel].tolist())):
         m = sel & (kind == k)
-        b = SWEEP_BYTES_PER_NODE * nodes + (COARSE_BYTES_PER_NODE * coarse if k == 1 else 0.0)
+        per = SWEEP_KL_BYTES_PER_NODE if kl else SWEEP_BYTES_PER_NODE
+        b = per * nodes + (COARSE_BYTES_PER_NODE * coarse if k == 1 else 0.0)
         avg = float(ms[m].mean())
         per_kind[KIND_NAMES[k]] = {"launches": int(m.sum()), "avg_us": 1e3 * avg,
                                    "bytes_per_launch": b, "GBps": b / (avg * 1e-3) / 1e9}
@@ -320,7 +336,8 @@ def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profil
     cyc_mean = float(cyc_np.mean())
     value = S * steps / dt
     ms_step = 1e3 * dt / steps
-    per_node = VCYCLE_BYTES_PER_NODE if precision == M.MG_FP64 else mixed_bytes_per_node(inner)
+    vc = VCYCLE_KL_BYTES_PER_NODE if kl_inline(args) else VCYCLE_BYTES_PER_NODE
+    per_node = vc if precision == M.MG_FP64 else mixed_bytes_per_node(inner)
     eff = per_node * n**3 * float(cyc_np.sum()) / dt / 1e9
     out = {
         "metric": "MLMC samples/sec per level + V-cycle HBM GB/s; p50/p99 solve latency",
@@ -351,13 +368,17 @@ def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profil
             step(s, cyc_p[s])
         torch.cuda.synchronize()
         cmin = int(cyc_p.cpu().numpy().reshape(-1, S, 2)[:, :, 0].min())
-        rf = sweep_roofline(M, P, n, S, cmin)
+        rf = sweep_roofline(M, P, n, S, cmin, kl_inline(args))
         M.mg_profile_enable(P, False)
         traffic, src, rec = read_traffic("k_sweep_config4_257x16.txt", tiles)
         out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBPS,
                            "unit": "GB/s", "frac": rf["achieved"] / HBM_PEAK_GBPS,
                            "traffic": traffic, "traffic_source": src,
                            "kernel": "k_sweep family (fused red-black sweeps, 257^3 grids)",
+                           "bytes_per_node": (SWEEP_KL_BYTES_PER_NODE if kl_inline(args)
+                                              else SWEEP_BYTES_PER_NODE),
+                           "coefficient": "evaluated in the sweep (KL)" if kl_inline(args)
+                                          else "read from memory",
                            "launches": rf["launches"], "avg_launch_us": rf["avg_launch_us"],
                            "bytes_per_launch": rf["bytes_per_launch"],
                            "profile_steps": args.profile_steps,
@@ -425,7 +446,7 @@ def bench_levelpair(args, M, torch, np, steps=None, profile=True):
     ms_step = 1e3 * dt / steps
     nf, nc = (n0 - 1) * 2**level + 1, (n0 - 1) * 2**(level - 1) + 1
     nodes = (nf**3 * cyc_np[:, :, 0].sum() + nc**3 * cyc_np[:, :, 1].sum())
-    eff = VCYCLE_BYTES_PER_NODE * float(nodes) / dt / 1e9
+    eff = (VCYCLE_KL_BYTES_PER_NODE if kl_inline(args) else VCYCLE_BYTES_PER_NODE) * float(nodes) / dt / 1e9
     out = _line("MLMC samples/sec per level + V-cycle HBM GB/s; p50/p99 solve latency", value,
                 "samples/s", steps, args.warmup, ms_step,
                 {"workload": "mlmc_level_pair_fine65_coarse33_x64", "n0": n0, "level": level,
@@ -443,7 +464,7 @@ def bench_levelpair(args, M, torch, np, steps=None, profile=True):
             step(s, cyc_p[s])
         torch.cuda.synchronize()
         cmin = int(cyc_p.cpu().numpy().reshape(-1, S, 2)[:, :, 0].min())
-        rf = sweep_roofline(M, P, nf, S, cmin)
+        rf = sweep_roofline(M, P, nf, S, cmin, kl_inline(args))
         M.mg_profile_enable(P, False)
         out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBPS,
                            "unit": "GB/s", "frac": rf["achieved"] / HBM_PEAK_GBPS,
@@ -590,7 +611,8 @@ def bench_mixed(args, M, torch, np):
     out["per_level"] = per_level
     out["speedup_vs_level_batches"] = t_levels / t_mixed
     out["speedup_vs_one_at_a_time"] = t_plain / t_mixed
-    out["effective_vcycle_GBps"] = VCYCLE_BYTES_PER_NODE * nodes / t_mixed / 1e9
+    out["effective_vcycle_GBps"] = ((VCYCLE_KL_BYTES_PER_NODE if kl_inline(args)
+                                     else VCYCLE_BYTES_PER_NODE) * nodes / t_mixed / 1e9)
     return out
 
 
@@ -616,7 +638,7 @@ def bench_fp32mix(args, M, torch, np):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         c = cyc.cpu().numpy().reshape(S, 2)[:, 0]
-        per_node = VCYCLE_BYTES_PER_NODE if prec == M.MG_FP64 else mixed_bytes_per_node(inner)
+        per_node = VCYCLE_KL_BYTES_PER_NODE if prec == M.MG_FP64 else mixed_bytes_per_node(inner)
         res[name] = {"batch_s": dt, "samples_per_s": S / dt, "cycles_mean": float(c.mean()),
                      "effective_GBps": per_node * n**3 * float(c.sum()) / dt / 1e9}
         Q[name] = Qf.cpu().numpy()

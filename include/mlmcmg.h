@@ -189,6 +189,14 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *               fmg_cycles; fixed_cycles is ignored;
  *   "fmg_cycles": V-cycles per grid of the full multigrid schedule (1..64,
  *               default 2).
+ *   "kl":       1 = the FP64 smoother and residual-restriction launches on
+ *               the top grids of KL-field samples (constant right-hand side,
+ *               up to 257^3) evaluate the coefficient wh = exp(-Z)/2 from the
+ *               sample's normals and the 1D modes instead of reading it, in
+ *               the operations of the field kernel that stores it: identical
+ *               results with 16 instead of 24 bytes per node and sweep, but
+ *               slower on MI355X, where these kernels are bound by FP64
+ *               issue rather than by bytes; 0 (default) = read wh.
  *   "inner_cycles": mixed precision (MG_MIXED plans): FP32 V(nu1,nu2) cycles
  *               per FP64 defect-correction step (1..8, default 1).  With c
  *               inner cycles a step applies, in exact arithmetic, the same
@@ -350,6 +358,14 @@ int mlmc_philox(mg_plan plan, const uint64_t* seeds, int n_samples, int level,
  * draws across levels).  No device work.  MG_EINVAL for out == NULL or
  * level < 0. */
 int mlmc_philox_words(uint64_t seed, int level, uint32_t out[128]);
+
+/* The exponential with which the kernels form the KL coefficient
+ * k = exp(Z) and wh = exp(-Z)/2 (Section 3: the lognormal field), evaluated
+ * on the host by the same code and table: Tang's table-driven method
+ * (32-entry 2^(j/32) table, degree-6 polynomial), relative error below 2
+ * units in the last place, x clamped to [-700, 700].  For tests; no device
+ * work. */
+double mlmc_exp(double x);
 
 /* Coefficient k = exp(Z(seed, level)) (Section 3.2, eq. def:expcov: the
  * lognormal field, here its 4x4x4 separable KL truncation, sampled from the

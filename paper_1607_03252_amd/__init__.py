@@ -103,6 +103,8 @@ def lib():
         L.mlmc_philox.argtypes = [vp, C.POINTER(C.c_uint64), C.c_int, C.c_int, vp, vp]
         L.mlmc_field.argtypes = [vp, C.c_int, C.c_uint64, C.c_int, vp]
         L.mlmc_philox_words.argtypes = [C.c_uint64, C.c_int, C.POINTER(C.c_uint32)]
+        L.mlmc_exp.argtypes = [C.c_double]
+        L.mlmc_exp.restype = C.c_double
         L.mlmc_acc_init.argtypes = [C.POINTER(mlmc_level_acc)]
         L.mlmc_acc_init.restype = None
         L.mlmc_acc_add.argtypes = [C.POINTER(mlmc_level_acc), vp, C.c_int, C.c_int]
@@ -150,7 +152,7 @@ def exported_symbols():
             "mg_serve_now", "mg_serve_counts", "mg_serve_slots", "mg_set_tile_for",
             "mg_get_tile_for", "mlmc_philox_words", "mg_solve_noalloc",
             "mg_profile_records", "mg_plan_get_desc", "mlmc_adaptive_desc_default",
-            "mlmc_adaptive"]
+            "mlmc_adaptive", "mlmc_exp"]
 
 
 def _torch():
@@ -339,6 +341,11 @@ def mlmc_philox_words(seed: int, level: int) -> np.ndarray:
     if st != MG_OK:
         raise MGError(st, "mlmc_philox_words rejected its arguments")
     return out
+
+
+def mlmc_exp(x: float) -> float:
+    """The exponential the kernels form the KL coefficient with (host evaluation)."""
+    return lib().mlmc_exp(float(x))
 
 
 def mlmc_field(plan: Plan, n: int, seed: int, level: int, k_out):

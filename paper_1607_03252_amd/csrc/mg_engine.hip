@@ -84,6 +84,12 @@ struct Lists {
       if (g.bstride != 0) return false;
     return !h[si].empty();
   }
+  // whether every grid of h[si] carries its KL coefficient data
+  bool kl(size_t si) const {
+    for (const auto& g : h[si])
+      if (!g.kln) return false;
+    return !h[si].empty();
+  }
   std::vector<GridDescT<T>*> d;
   std::vector<std::vector<GridDescT<T>>> htop;  // per top size index
   std::vector<GridDescT<T>*> dtop;
@@ -129,6 +135,9 @@ struct Batch {
     int* d_xi;       // their rows of d_normals
   };
   std::vector<FieldGroup> fields;
+  // per solve: the normals of its KL field (its grids' descriptors then carry
+  // the KL data), or nullptr; empty when the batch has no KL samples
+  std::vector<const double*> kl_normals;
   // coefficient injection per fine size, and FP32 conversion per size
   std::vector<double**> d_inj_src, d_inj_dst;
   std::vector<int> inj_n, inj_count;
@@ -231,6 +240,9 @@ struct mg_plan_s {
   int fmg_cycles = 2;    // V-cycles per grid of the full multigrid schedule
   int op_fe = 0;         // 1: the P1 finite-element operator instead of FD
   int inner_cycles = 1;  // mixed precision: FP32 V-cycles per FP64 defect-correction step
+  int kl_inline = 0;     // 1: FP64 sweeps and transfers of KL-field samples evaluate the
+                         // coefficient instead of reading it (same values; slower on
+                         // MI355X: the sweeps are bound by FP64 issue, not by bytes)
   int field_spde = 0;    // 1: coefficient fields from the SPDE sampler instead of KL
   // SPDE sampler workspaces keyed by (finest box size, solves)
   std::map<std::pair<int, int>, std::unique_ptr<mg::SpdeWork>> spde;
@@ -502,7 +514,14 @@ static void upload_lists(mg_plan_s* P, Batch* B) {
     const auto& lv = B->lev[s];
     for (size_t j = 0; j < lv.size(); ++j) {
       const size_t si = size_index(B->sizes, lv[j].n);
-      const GridDesc d = make_desc(lv, j, s, j == 0 ? poff : 0, B->const_plane[si]);
+      GridDesc d = make_desc(lv, j, s, j == 0 ? poff : 0, B->const_plane[si]);
+      if (!B->kl_normals.empty() && B->kl_normals[s]) {
+        // every grid of a KL solve: the coarse grids' wh is the injection of
+        // the finest one's, i.e. the same field at their own vertices
+        d.kln = B->kl_normals[s];
+        d.klcoef = P->d_coef;
+        d.klphi = phi_table(P, lv[j].n);
+      }
       B->L64.h[si].push_back(d);
       if (spec.mixed)
         B->L32.h[si].push_back(make_desc<float>(B->lev32[s], j, s, j == 0 ? poff : 0, nullptr));
@@ -660,7 +679,8 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
     // correction)
     const bool cb = Ls.const_b(si);
     launch_sweep<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf,
-                    shape_for(P, n, cbuf >= 0 || (spart && norm == 1 && !cb)), st, spart, norm, cb);
+                    shape_for(P, n, cbuf >= 0 || (spart && norm == 1 && !cb)), st, spart, norm, cb,
+                    P->kl_inline && Ls.kl(si));
     out = 1 - buf;
   } else {
     if (cbuf >= 0) launch_prolong<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf, st);
@@ -778,7 +798,8 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls, bool norms = false, d
     // workgroups the separate kernels (same results) finish sooner
     // (it addresses whole grids with 32-bit offsets, as the fused sweep)
     if (P->transfer == 0 && cnt * resrestrict_blocks(n) >= 128 && sweep_fits(n, sizeof(T))) {
-      launch_resrestrict<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st, Ls.const_b(si));
+      launch_resrestrict<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st, Ls.const_b(si),
+                            P->kl_inline && Ls.kl(si));
     } else {
       launch_residual<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st);
       launch_restrict<T>(Ls.d[si], cnt, n, B->ss.active, st);
@@ -1053,7 +1074,6 @@ static int setup_samples(mg_plan_s* P, Batch* B, const std::vector<int>& levels,
   hipStream_t st = P->work;
   const int n_samples = (int)levels.size();
   if (B->nsamples != n_samples) {
-    upload_lists(P, B);
     B->nsamples = n_samples;
     B->d_seeds = (uint64_t*)B->dalloc(sizeof(uint64_t) * n_samples);
     if (B->h_seeds) CK(hipHostFree(B->h_seeds));
@@ -1062,14 +1082,22 @@ static int setup_samples(mg_plan_s* P, Batch* B, const std::vector<int>& levels,
     B->d_normals = (double*)B->dalloc(sizeof(double) * 64 * n_samples);
     std::vector<int> fi(n_samples), ci(n_samples);
     std::map<int, std::pair<std::vector<double*>, std::vector<int>>> groups;
+    const bool kl = !P->field_spde && !B->spec.fe;
+    B->kl_normals.assign(kl ? B->ns : 0, nullptr);
     int s = 0;
     for (int i = 0; i < n_samples; ++i) {
       fi[i] = s;
       ci[i] = levels[i] > 0 ? s + 1 : -1;
       groups[levels[i]].first.push_back(B->lev[s][0].wh);
       groups[levels[i]].second.push_back(i);
+      if (kl) {
+        // both solves of a pair take the sample's normals
+        B->kl_normals[s] = B->d_normals + 64 * (size_t)i;
+        if (levels[i] > 0) B->kl_normals[s + 1] = B->kl_normals[s];
+      }
       s += levels[i] > 0 ? 2 : 1;
     }
+    upload_lists(P, B);
     B->d_fi = (int*)B->dalloc(sizeof(int) * n_samples);
     B->d_ci = (int*)B->dalloc(sizeof(int) * n_samples);
     CK(hipMemcpy(B->d_fi, fi.data(), sizeof(int) * n_samples, hipMemcpyHostToDevice));
@@ -1209,11 +1237,15 @@ static Batch* fmg_stage(mg_plan_s* P, int n, int S) {
     spec.mixed = false;
     auto B = build_batch(P, spec);
     if (!B) return nullptr;
-    upload_lists(P, B.get());
     B->nsamples = S;
     B->d_seeds = (uint64_t*)B->dalloc(sizeof(uint64_t) * S);
     B->d_levels = (int*)B->dalloc(sizeof(int) * S);
     B->d_normals = (double*)B->dalloc(sizeof(double) * 64 * S);
+    if (!P->field_spde && !P->op_fe) {
+      B->kl_normals.resize(S);
+      for (int i = 0; i < S; ++i) B->kl_normals[i] = B->d_normals + 64 * (size_t)i;
+    }
+    upload_lists(P, B.get());
     B->d_fi = (int*)B->dalloc(sizeof(int) * S);  // output position of each sample
     Batch::FieldGroup g;
     g.n = n;
@@ -2063,6 +2095,9 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
     P->field_spde = (int)value;
     P->batch.reset();  // coarse solves own their coefficient with the SPDE field
     P->batch_key.clear();
+  } else if (k == "kl") {
+    if (value != 0 && value != 1) return MG_EINVAL;
+    P->kl_inline = (int)value;
   } else if (k == "inner_cycles") {
     if (value < 1 || value > 8) return MG_EINVAL;
     P->inner_cycles = (int)value;
@@ -2268,7 +2303,8 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
                                   s, P->work, nullptr, 0, B->L32.const_b(si));
             else
               launch_sweep<double>(B->L64.d[si], (int)B->L64.h[si].size(), n, B->ss.active, 0,
-                                   cb, s, P->work, nullptr, 0, B->L64.const_b(si));
+                                   cb, s, P->work, nullptr, 0, B->L64.const_b(si),
+                                   P->kl_inline && B->L64.kl(si));
           };
           one();
           CK(hipEventRecord(e0, P->work));
@@ -2346,6 +2382,8 @@ int mlmc_philox_words(uint64_t seed, int level, uint32_t* out) {
   }
   return MG_OK;
 }
+
+double mlmc_exp(double x) { return mg::kl_exp_host(x); }
 
 int mlmc_field(mg_plan P, int n, uint64_t seed, int level, double* k_out) {
   if (!P) return MG_EINVAL;

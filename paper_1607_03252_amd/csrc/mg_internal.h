@@ -56,6 +56,15 @@ struct GridDescT {
   int spoff;        // top grids: offset of the in-sweep residual-norm partials
                     // (SolveState::spart); -1 otherwise
   int bstride;      // n*n for a full right-hand side array, 0 for a constant plane
+  // The KL coefficient evaluated in the kernel instead of read from wh (FP64
+  // smoother and transfer launches with kl = true): the solve's 64 normals,
+  // the 64 mode weights, and the 1D modes at this grid's vertex coordinates
+  // (klphi[a*n + i]).  The kernels form wh = exp(-Z)/2 in the operations of
+  // the field kernel that wrote wh, so they see the same values.  nullptr:
+  // the grid's coefficient is not such a field.
+  const double* kln;
+  const double* klcoef;
+  const double* klphi;
 };
 using GridDesc = GridDescT<double>;
 using GridDesc32 = GridDescT<float>;
@@ -118,6 +127,10 @@ SweepShape default_sweep_shape(int n, bool fused_correction = false, bool single
 // array must stay below 2 GiB (larger grids use the two-pass colour sweeps).
 bool sweep_fits(int n, size_t elem);
 
+// exp as the kernels form the KL coefficient (table-driven, below 2 ulp),
+// evaluated on the host
+double kl_exp_host(double x);
+
 // ---- launchers (all asynchronous on `st`) --------------------------------
 // Normals of `count` samples; the counter's level word is d_levels[s] when
 // d_levels is given, else `level`.
@@ -147,11 +160,17 @@ void launch_fill(double* p, long count, double value, hipStream_t st);
 // per workgroup to spart[spoff + wg]: the sum of squared residuals at the red
 // points of its input (norm 1) or at the black points of its output (norm 2).
 // const_b: every grid of the list has a constant right-hand side plane
-// (bstride 0).  Returns the workgroups per grid.
+// (bstride 0).  kl: every grid has a KL coefficient (kln != nullptr), which
+// the FP64 sweep then evaluates instead of reading wh where the list also has
+// a constant right-hand side and n <= kKLMaxN (the results are the same
+// either way).  Returns the workgroups per grid.
 template <typename T>
 int launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                  int cbuf_prolong, SweepShape shape, hipStream_t st, T* spart = nullptr,
-                 int norm = 0, bool const_b = false);
+                 int norm = 0, bool const_b = false, bool kl = false);
+// Largest grid on which the kernels evaluate the KL coefficient themselves
+// (its 1D mode table is staged in LDS).
+constexpr int kKLMaxN = 257;
 // Workgroups per grid of launch_sweep for `count` grids of size n.
 int sweep_blocks(int n, int count, SweepShape shape);
 template <typename T>
@@ -168,7 +187,7 @@ void launch_restrict(const GridDescT<T>* d_list, int count, int n, const int* d_
 int resrestrict_blocks(int n);
 template <typename T>
 void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
-                        int buf, hipStream_t st, bool const_b = false);
+                        int buf, hipStream_t st, bool const_b = false, bool kl = false);
 template <typename T>
 void launch_coarsest(const GridDescT<T>* d_list, int count, const int* d_active, hipStream_t st);
 template <typename T>

@@ -25,17 +25,19 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Reciprocals: the hardware estimate refined by Newton-Raphson steps
-// y <- y + y (1 - x y) (two for double, one for float).
+// Reciprocals: the hardware estimate y refined.  The FP64 estimate is good
+// to about 2^-25, so with e = 1 - x y the third-order step
+// y (1 + e + e^2) = 1/x (1 - e^3) leaves a truncation of 2^-75 and the result
+// is within half a unit in the last place bar rounding (three FMAs: the same
+// accuracy as two Newton-Raphson steps, one FMA fewer on a path whose
+// sweeps are bound by FP64 issue).  FP32: one Newton-Raphson step.
 template <typename T>
 __device__ __forceinline__ T rcp(T x);
 template <>
 __device__ __forceinline__ double rcp<double>(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, y, 1.0);
-  y = __builtin_fma(y, e, y);
-  e = __builtin_fma(-x, y, 1.0);
-  return __builtin_fma(y, e, y);
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = __builtin_fma(-x, y, 1.0);
+  return __builtin_fma(y, __builtin_fma(e, e, e), y);
 }
 template <>
 __device__ __forceinline__ float rcp<float>(float x) {
@@ -287,13 +289,92 @@ __global__ void __launch_bounds__(64) k_philox(const uint64_t* __restrict__ seed
   }
 }
 
-// Field on `count` grids of size n: Z = sum_{a,b,c} coef[abc] xi[abc]
-// phi_a(x_i) phi_b(y_j) phi_c(z_k), as nested 1D contractions over a, then b,
-// then c.  mode 0 stores wh = exp(-Z)/2, mode 1 stores k = exp(Z).
-// One workgroup per plane i of a grid: first the row factors
-// G_c(j) = sum_b (sum_a C_abc phi_a(x_i)) phi_b(y_j) of every row j into LDS,
-// then Z = sum_c G_c(j) phi_c(z_k) at every point of the plane, the points
-// dealt to the threads in memory order (whole rows for any n, full lanes).
+// The KL field at a vertex, in one fixed order of operations shared by every
+// kernel that forms it, so that the stored coefficient and one recomputed
+// inside a smoother are the same bits:
+//   P[4a + c] = sum_b C[16a + 4b + c] phi_b(y)    (b ascending)
+//   H[a]      = sum_c P[4a + c] phi_c(z)          (c ascending)
+//   Z         = sum_a phi_a(x) H[a]               (a ascending)
+// with C[abc] = coef[abc] * xi[abc]; wh = exp(-Z)/2 and k = exp(Z).
+__device__ __forceinline__ void kl_rows(const double* C, const double (&py)[4], double (&P)[16]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double v = C[16 * a + c] * py[0];
+      v = __builtin_fma(C[16 * a + 4 + c], py[1], v);
+      v = __builtin_fma(C[16 * a + 8 + c], py[2], v);
+      P[4 * a + c] = __builtin_fma(C[16 * a + 12 + c], py[3], v);
+    }
+}
+__device__ __forceinline__ void kl_cols(const double (&P)[16], const double (&pz)[4],
+                                        double (&H)[4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double v = P[4 * a] * pz[0];
+    v = __builtin_fma(P[4 * a + 1], pz[1], v);
+    v = __builtin_fma(P[4 * a + 2], pz[2], v);
+    H[a] = __builtin_fma(P[4 * a + 3], pz[3], v);
+  }
+}
+// px: phi_0..3 at the plane's coordinate
+__device__ __forceinline__ double kl_z(const double (&H)[4], const double* px) {
+  double z = H[0] * px[0];
+  z = __builtin_fma(H[1], px[1], z);
+  z = __builtin_fma(H[2], px[2], z);
+  return __builtin_fma(H[3], px[3], z);
+}
+
+// exp by the table-driven method of P. T. P. Tang (ACM TOMS 15(2), 1989):
+// x = (32 m + j) ln2/32 + r with |r| <= ln2/64, exp(x) = 2^m 2^(j/32) exp(r),
+// exp(r) - 1 from its degree-6 Taylor polynomial (truncation below 4e-18),
+// ln2/32 split so that (32 m + j) times the leading part is exact.  tab[j] is
+// 2^(j/32) rounded to double (kExp2Tab, staged in LDS by the kernels).
+// Relative error below 2 units in the last place for |x| <= 700 (x is
+// clamped to that range).  Every kernel that forms the KL coefficient uses
+// this function, so the stored and the recomputed coefficient are the same bits.
+__host__ __device__ __forceinline__ double kl_exp(double x, const double* tab) {
+  constexpr double kInvL = 0x1.71547652b82fep+5;  // 32 / ln2
+  constexpr double kLhi = 0x1.62e42fefa0000p-6;   // ln2/32, leading 37 bits
+  constexpr double kLlo = 0x1.cf79abc9e3b3ap-45;  // ln2/32 - kLhi
+  x = fmin(fmax(x, -700.0), 700.0);
+  const double kf = rint(x * kInvL);
+  const int kq = (int)kf;
+  const int j = kq & 31, m = kq >> 5;  // kq = 32 m + j (arithmetic shift)
+  double r = __builtin_fma(-kf, kLhi, x);
+  r = __builtin_fma(-kf, kLlo, r);
+  double p = __builtin_fma(r, 1.0 / 720.0, 1.0 / 120.0);
+  p = __builtin_fma(r, p, 1.0 / 24.0);
+  p = __builtin_fma(r, p, 1.0 / 6.0);
+  p = __builtin_fma(r, p, 0.5);
+  p = __builtin_fma(r * r, p, r);  // exp(r) - 1
+  const double tj = tab[j];
+  return ldexp(__builtin_fma(tj, p, tj), m);
+}
+#define MG_EXP2_TAB { \
+    0x1.0000000000000p+0, 0x1.059b0d3158574p+0, 0x1.0b5586cf9890fp+0, 0x1.11301d0125b51p+0, \
+    0x1.172b83c7d517bp+0, 0x1.1d4873168b9aap+0, 0x1.2387a6e756238p+0, 0x1.29e9df51fdee1p+0, \
+    0x1.306fe0a31b715p+0, 0x1.371a7373aa9cbp+0, 0x1.3dea64c123422p+0, 0x1.44e086061892dp+0, \
+    0x1.4bfdad5362a27p+0, 0x1.5342b569d4f82p+0, 0x1.5ab07dd485429p+0, 0x1.6247eb03a5585p+0, \
+    0x1.6a09e667f3bcdp+0, 0x1.71f75e8ec5f74p+0, 0x1.7a11473eb0187p+0, 0x1.82589994cce13p+0, \
+    0x1.8ace5422aa0dbp+0, 0x1.93737b0cdc5e5p+0, 0x1.9c49182a3f090p+0, 0x1.a5503b23e255dp+0, \
+    0x1.ae89f995ad3adp+0, 0x1.b7f76f2fb5e47p+0, 0x1.c199bdd85529cp+0, 0x1.cb720dcef9069p+0, \
+    0x1.d5818dcfba487p+0, 0x1.dfc97337b9b5fp+0, 0x1.ea4afa2a490dap+0, 0x1.f50765b6e4540p+0}
+__device__ const double kExp2Tab[32] = MG_EXP2_TAB;
+static const double kExp2TabHost[32] = MG_EXP2_TAB;
+#undef MG_EXP2_TAB
+// LDS layout of the KL data of a launch (doubles): the mode table
+// [0, 4n) as tab[4m + a] = phi_a(x_m), the weights [4n, 4n + 64), the exp
+// table [4n + 64, 4n + 96).
+__host__ __device__ constexpr int kl_lds_doubles(int n) { return 4 * n + 96; }
+__device__ __forceinline__ double kl_wh(double z, const double* etab) {
+  return 0.5 * kl_exp(-z, etab);
+}
+
+// Field on `count` grids of size n (mode 0: wh = exp(-Z)/2, mode 1:
+// k = exp(Z)).  A thread owns one column (j, k) of a grid: it forms the
+// column parts H once and marches the planes i, its stores coalesced with
+// the neighbouring columns'.
 constexpr int kFieldMaxN = 1025;
 __global__ void __launch_bounds__(kBlock) k_field(int n, double* const* __restrict__ out,
                                                   const int* __restrict__ xi_index,
@@ -301,39 +382,30 @@ __global__ void __launch_bounds__(kBlock) k_field(int n, double* const* __restri
                                                   const double* __restrict__ phi,
                                                   const double* __restrict__ coef, int mode,
                                                   int count, int per) {
-  __shared__ double C[64];
-  __shared__ double G[4 * kFieldMaxN];
-  int g, i;
-  if (!xcd_unit(count, per, g, i)) return;
+  __shared__ double C[64], E[32];
+  int g, blk;
+  if (!xcd_unit(count, per, g, blk)) return;
   const int t = threadIdx.x;
   if (t < 64) C[t] = coef[t] * normals[(size_t)xi_index[g] * 64 + t];
+  if (t < 32) E[t] = kExp2Tab[t];
   __syncthreads();
-  for (int q = t; q < 4 * n; q += kBlock) {
-    const int j = q >> 2, c = q & 3;
-    double G1 = 0.0;
+  const int q = blk * kBlock + t;
+  if (q >= n * n) return;
+  const int j = q / n, k = q - (q / n) * n;
+  double py[4], pz[4], P[16], H[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      double g1 = 0.0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) g1 += C[16 * a + 4 * b + c] * phi[a * n + i];
-      G1 += g1 * phi[b * n + j];
-    }
-    G[q] = G1;
+  for (int a = 0; a < 4; ++a) {
+    py[a] = phi[a * n + j];
+    pz[a] = phi[a * n + k];
   }
-  __syncthreads();
-  const gptr<double> o = gview<double>(out[g] + (size_t)i * n * n);
-  const int np = n * n;
-  // row and column of point q by a float quotient corrected by one step
-  const float rn = 1.0f / (float)n;
-  for (int q = t; q < np; q += kBlock) {
-    int j = (int)((float)q * rn);
-    j -= j * n > q;
-    j += (j + 1) * n <= q;
-    const int k = q - j * n;
-    double Z = 0.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Z += G[4 * j + c] * phi[c * n + k];
-    o[q] = mode == 0 ? 0.5 * exp(-Z) : exp(Z);
+  kl_rows(C, py, P);
+  kl_cols(P, pz, H);
+  double* o = out[g] + q;
+  const size_t np = (size_t)n * n;
+  for (int i = 0; i < n; ++i) {
+    const double px[4] = {phi[i], phi[n + i], phi[2 * n + i], phi[3 * n + i]};
+    const double z = kl_z(H, px);
+    o[(size_t)i * np] = mode == 0 ? kl_wh(z, E) : kl_exp(z, E);
   }
 }
 
@@ -426,6 +498,10 @@ struct SweepGeom {
 // sums of the next sweep, both evaluated exactly as the residual kernels do.
 // CB: every grid of the launch has a constant right-hand side (bstride 0):
 // its two values per thread are loaded once instead of per plane.
+// KL (FP64): the coefficient wh is evaluated from the grid's KL data instead
+// of read (kl_rows/kl_cols once per column, kl_z and exp per plane, the 1D
+// mode table staged in dynamic LDS), in the operations of the field kernel,
+// so the sweep's results are the same bits; the sweep then reads only u.
 //
 // Work: the launch has nwg workgroups (a multiple of 8) for the list's count
 // grids.  Every wave counts the active grids of the list by ballots; with
@@ -434,7 +510,7 @@ struct SweepGeom {
 // allow, at least four planes per piece), so a launch in which most solves
 // have stopped still spreads its work over the machine.  Workgroups are
 // numbered XCD-contiguously (neighbouring tiles share an L2).
-template <typename T, int TJ, int TK, bool PRO, int NM, bool CB>
+template <typename T, int TJ, int TK, bool PRO, int NM, bool CB, bool KL>
 __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list,
                                            const int* __restrict__ active, int buf, int cbuf,
                                            int tiles_k, int tiles_jk, int chunks, int count,
@@ -529,6 +605,34 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   }
   const int jc = min(max(j, 0), n - 1);
   const int jI = min(max(j, 1), n - 2);
+  // KL: the mode table (sPhi[4m + a] = phi_a at plane m) and the weights in
+  // LDS, then the column parts of this thread's two positions (a position
+  // outside the grid gets wh = 0, as a read past a buffer's range does)
+  static_assert(!KL || std::is_same<T, double>::value, "the KL sweep is FP64");
+  extern __shared__ double kl_lds[];
+  double KH[KL ? 2 : 1][4];
+  bool kin[2] = {false, false};
+  const double* etab = kl_lds + 4 * n + 64;
+  if constexpr (KL) {
+    double* sC = kl_lds + 4 * n;
+    for (int q = t; q < 4 * n; q += Geo::THREADS) kl_lds[q] = d.klphi[(q & 3) * n + (q >> 2)];
+    if (t < 64) sC[t] = d.klcoef[t] * d.kln[t];
+    if (t < 32) sC[64 + t] = kExp2Tab[t];
+    __syncthreads();
+    double py[4], P[16];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) py[b] = kl_lds[4 * jc + b];
+    kl_rows(sC, py, P);
+#pragma unroll
+    for (int pos = 0; pos < 2; ++pos) {
+      const int kk = min(max(kA + pos, 0), n - 1);
+      double pz[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) pz[c] = kl_lds[4 * kk + c];
+      kl_cols(P, pz, KH[pos]);
+      kin[pos] = live && j >= 0 && j < n && kA + pos >= 0 && kA + pos < n;
+    }
+  }
   // LDS indexes, per role: own position (lq), and for the stencil reads of a
   // ring-1 position (the others read around a safe interior position whose
   // results are not used) the position itself (lc; its j-neighbours are
@@ -603,10 +707,30 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     const int m = istart + rel;
     const uint32_t so = (uint32_t)m * pbytes, sob = bs ? so : 0u;
     const int rb = (rel + 1) & 1;
+    if constexpr (KL) {
+      // wh of both positions on plane m (0 off the grid)
+      const double* px = kl_lds + 4 * min(max(m, 0), n - 1);
+      const bool pin = m >= 0 && m <= n - 1;
+      T wv[2];
+#pragma unroll
+      for (int pos = 0; pos < 2; ++pos) {
+        const double w = kl_wh(kl_z(KH[pos], px), etab);
+        wv[pos] = (kin[pos] && pin) ? w : 0.0;
+      }
+      if constexpr (PW) {
+        W[sl][0] = wv[0];
+        W[sl][1] = wv[1];
+      } else {
+        W[sl][0] = sw ? wv[1] : wv[0];
+        W[sl][1] = sw ? wv[0] : wv[1];
+      }
+    }
     if constexpr (PW) {
-      const Two<T> wv = bload2<T>(rw0, offp + so);
-      W[sl][0] = wv.lo;
-      W[sl][1] = wv.hi;
+      if constexpr (!KL) {
+        const Two<T> wv = bload2<T>(rw0, offp + so);
+        W[sl][0] = wv.lo;
+        W[sl][1] = wv.hi;
+      }
       if constexpr (!CB) {
         const Two<T> bb = bload2<T>(rb0, offp + sob);
         B[sl][0] = bb.lo;
@@ -615,7 +739,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
     } else {
 #pragma unroll
       for (int rho = 0; rho < 2; ++rho) {
-        W[sl][rho] = bload<T>(rw0, offi[rho] + so);
+        if constexpr (!KL) W[sl][rho] = bload<T>(rw0, offi[rho] + so);
         if (!CB) B[CB ? 0 : sl][rho] = bload<T>(rb0, offi[rho] + sob);
       }
     }
@@ -840,25 +964,28 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   }
 }
 
-template <typename T, int TJ, int TK, bool PRO, bool CB>
+// (KL: held to three waves per SIMD, the occupancy its LDS allows on the
+// larger tiles)
+template <typename T, int TJ, int TK, bool PRO, bool CB, bool KL>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(KL ? 3 : 1)))
     k_sweep(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
             int cbuf, int tiles_k, int tiles_jk, int chunks, int count, int nwg) {
-  sweep_tile<T, TJ, TK, PRO, 0, CB>(list, active, buf, cbuf, tiles_k, tiles_jk, chunks, count,
-                                    nwg, nullptr);
+  sweep_tile<T, TJ, TK, PRO, 0, CB, KL>(list, active, buf, cbuf, tiles_k, tiles_jk, chunks,
+                                        count, nwg, nullptr);
 }
 
 // The sweep with the black residuals of its output, held to the plain
 // sweep's register budget (four waves per SIMD) so that it runs with the
 // plain sweep's shape and occupancy.
-template <typename T, int TJ, int TK, bool CB>
+template <typename T, int TJ, int TK, bool CB, bool KL>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
-    __attribute__((amdgpu_waves_per_eu(4)))
+    __attribute__((amdgpu_waves_per_eu(KL ? 3 : 4)))
     k_sweep_res_out(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
                     int buf, int tiles_k, int tiles_jk, int chunks, int count, int nwg,
                     T* __restrict__ spart) {
-  sweep_tile<T, TJ, TK, false, 2, CB>(list, active, buf, -1, tiles_k, tiles_jk, chunks, count,
-                                      nwg, spart);
+  sweep_tile<T, TJ, TK, false, 2, CB, KL>(list, active, buf, -1, tiles_k, tiles_jk, chunks,
+                                          count, nwg, spart);
 }
 
 // The sweep with the red residuals of its input keeps the input values of
@@ -866,22 +993,23 @@ __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
 // right-hand-side ring) it fits the plain sweep's budget and shapes; with a
 // full one it takes the budget and shapes of the sweep with the coarse
 // correction.
-template <typename T, int TJ, int TK>
+template <typename T, int TJ, int TK, bool KL>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
-    __attribute__((amdgpu_waves_per_eu(4)))
+    __attribute__((amdgpu_waves_per_eu(KL ? 3 : 4)))
     k_sweep_res_in_cb(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
                       int buf, int tiles_k, int tiles_jk, int chunks, int count, int nwg,
                       T* __restrict__ spart) {
-  sweep_tile<T, TJ, TK, false, 1, true>(list, active, buf, -1, tiles_k, tiles_jk, chunks,
-                                        count, nwg, spart);
+  sweep_tile<T, TJ, TK, false, 1, true, KL>(list, active, buf, -1, tiles_k, tiles_jk, chunks,
+                                            count, nwg, spart);
 }
-template <typename T, int TJ, int TK>
+template <typename T, int TJ, int TK, bool KL>
 __global__ void __launch_bounds__((SweepGeom<TJ, TK>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(KL ? 3 : 1)))
     k_sweep_res_in(const GridDescT<T>* __restrict__ list, const int* __restrict__ active,
                    int buf, int tiles_k, int tiles_jk, int chunks, int count, int nwg,
                    T* __restrict__ spart) {
-  sweep_tile<T, TJ, TK, false, 1, false>(list, active, buf, -1, tiles_k, tiles_jk, chunks,
-                                         count, nwg, spart);
+  sweep_tile<T, TJ, TK, false, 1, false, KL>(list, active, buf, -1, tiles_k, tiles_jk, chunks,
+                                             count, nwg, spart);
 }
 
 // ---- point kernels: colour sweep, residual, transfer -------------------------
@@ -1162,8 +1290,9 @@ struct RRGeom {
 
 // CB: every grid has a constant right-hand side plane (loaded once).  Grid
 // arrays are addressed as in the sweep: one descriptor per array, the
-// plane's offset added to the per-lane offsets.
-template <typename T, int RJ, int RK, bool CB>
+// plane's offset added to the per-lane offsets.  KL (FP64): wh evaluated from
+// the grid's KL data as in the sweep (the mode table in dynamic LDS).
+template <typename T, int RJ, int RK, bool CB, bool KL>
 __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
     k_resrestrict(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
                   int tiles_k, int count, int per) {
@@ -1222,13 +1351,45 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
   const auto rb = rsrc(d.b, d.bstride ? gbytes : pbytes);
   T OU[4], OW[4], OB[CB ? 1 : 4], HU[4], HW[4];
   if (CB) OB[0] = bload<T>(rb, oo);
+  // KL: mode table and weights in LDS, the column parts of the own column
+  // (wh = 0 off the grid, as a read past the range gives); the ring columns
+  // still read wh (values a neighbouring workgroup streams: cache hits)
+  static_assert(!KL || std::is_same<T, double>::value, "the KL transfer is FP64");
+  extern __shared__ double kl_lds[];
+  double KO[KL ? 4 : 1];
+  const double* etab = kl_lds + 4 * n + 64;
+  if constexpr (KL) {
+    double* sC = kl_lds + 4 * n;
+    for (int qq = t; qq < 4 * n; qq += G::THREADS) kl_lds[qq] = d.klphi[(qq & 3) * n + (qq >> 2)];
+    if (t < 64) sC[t] = d.klcoef[t] * d.kln[t];
+    if (t < 32) sC[64 + t] = kExp2Tab[t];
+    __syncthreads();
+    auto column = [&](int jj, int kk, double (&H)[4]) {
+      const int jy = min(max(jj, 0), n - 1), kz = min(max(kk, 0), n - 1);
+      double py[4], pz[4], P[16];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        py[b] = kl_lds[4 * jy + b];
+        pz[b] = kl_lds[4 * kz + b];
+      }
+      kl_rows(sC, py, P);
+      kl_cols(P, pz, H);
+    };
+    column(j, k, KO);
+  }
   auto load = [&](int pm, int sl) {
     const uint32_t so = (uint32_t)pm * pbytes;
     OU[sl] = bload<T>(ru, oo + so);
-    OW[sl] = bload<T>(rw, oo + so);
+    if constexpr (KL) {
+      const double* px = kl_lds + 4 * min(pm, n - 1);
+      const double wo = kl_wh(kl_z(KO, px), etab);
+      OW[sl] = (fgrid && pm <= n - 1) ? wo : 0.0;
+    } else {
+      OW[sl] = bload<T>(rw, oo + so);
+    }
+    HW[sl] = bload<T>(rw, oh + so);
     if (!CB) OB[sl] = bload<T>(rb, oo + (d.bstride ? so : 0u));  // (a constant plane: stride 0)
     HU[sl] = bload<T>(ru, oh + so);
-    HW[sl] = bload<T>(rw, oh + so);
   };
   auto prologue = [&]() {
     load(0, 3);
@@ -1792,9 +1953,9 @@ inline dim3 xcd_grid(int count, int per) { return dim3(8 * ceil_div(count * per,
 // least kSweepUnits (the kernel spreads them over the grids still active),
 // otherwise the count x tiles x pieces of the fixed split.
 constexpr int kSweepUnits = 512;
-template <typename T, int TJ, int TK, bool CB>
-int sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
-                 int cbuf, int chunks, hipStream_t st, T* spart, int norm) {
+template <typename T, int TJ, int TK, bool CB, bool KL>
+int sweep_launch_kl(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
+                    int cbuf, int chunks, hipStream_t st, T* spart, int norm) {
   const int tiles_k = (n - 1) / TK, tiles_j = (n - 1) / TJ;
   const int tiles = tiles_k * tiles_j;
   int units;
@@ -1807,30 +1968,49 @@ int sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_acti
   const int nwg = 8 * ceil_div(units, 8);
   const int per = nwg;  // (returned: an upper bound of the workgroups per grid)
   const dim3 grid(nwg), block(SweepGeom<TJ, TK>::THREADS);
+  // KL: the mode table and the weights in dynamic LDS
+  const size_t lds = KL ? sizeof(double) * (size_t)kl_lds_doubles(n) : 0;
   if (cbuf >= 0) {
-    hipLaunchKernelGGL((k_sweep<T, TJ, TK, true, CB>), grid, block, 0, st, d_list, d_active, buf,
-                       cbuf, tiles_k, tiles, chunks, count, nwg);
+    hipLaunchKernelGGL((k_sweep<T, TJ, TK, true, CB, KL>), grid, block, lds, st, d_list, d_active,
+                       buf, cbuf, tiles_k, tiles, chunks, count, nwg);
   } else if (spart && norm == 1) {
     if constexpr (std::is_same<T, double>::value) {
       if constexpr (CB)
-        hipLaunchKernelGGL((k_sweep_res_in_cb<T, TJ, TK>), grid, block, 0, st, d_list, d_active,
-                           buf, tiles_k, tiles, chunks, count, nwg, spart);
+        hipLaunchKernelGGL((k_sweep_res_in_cb<T, TJ, TK, KL>), grid, block, lds, st, d_list,
+                           d_active, buf, tiles_k, tiles, chunks, count, nwg, spart);
       else
-        hipLaunchKernelGGL((k_sweep_res_in<T, TJ, TK>), grid, block, 0, st, d_list, d_active,
-                           buf, tiles_k, tiles, chunks, count, nwg, spart);
+        hipLaunchKernelGGL((k_sweep_res_in<T, TJ, TK, KL>), grid, block, lds, st, d_list,
+                           d_active, buf, tiles_k, tiles, chunks, count, nwg, spart);
     }
   } else if (spart && norm == 2) {
     if constexpr (std::is_same<T, double>::value)
-      hipLaunchKernelGGL((k_sweep_res_out<T, TJ, TK, CB>), grid, block, 0, st, d_list, d_active,
-                         buf, tiles_k, tiles, chunks, count, nwg, spart);
+      hipLaunchKernelGGL((k_sweep_res_out<T, TJ, TK, CB, KL>), grid, block, lds, st, d_list,
+                         d_active, buf, tiles_k, tiles, chunks, count, nwg, spart);
   } else {
-    hipLaunchKernelGGL((k_sweep<T, TJ, TK, false, CB>), grid, block, 0, st, d_list, d_active,
-                       buf, cbuf, tiles_k, tiles, chunks, count, nwg);
+    hipLaunchKernelGGL((k_sweep<T, TJ, TK, false, CB, KL>), grid, block, lds, st, d_list,
+                       d_active, buf, cbuf, tiles_k, tiles, chunks, count, nwg);
   }
   return per;
 }
 
+// KL launches for FP64 grids with a constant right-hand side (the top grids
+// of samples; with a full right-hand side the KL sweeps exceed the register
+// budget of three waves per SIMD), on the shapes the larger grids use
+template <typename T, int TJ, int TK, bool CB>
+int sweep_launch(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
+                 int cbuf, int chunks, hipStream_t st, T* spart, int norm, bool kl) {
+  if constexpr (std::is_same<T, double>::value && TJ * TK >= 256 && CB)
+    if (kl && n <= kKLMaxN)
+      return sweep_launch_kl<T, TJ, TK, CB, true>(d_list, count, n, d_active, buf, cbuf, chunks,
+                                                  st, spart, norm);
+  return sweep_launch_kl<T, TJ, TK, CB, false>(d_list, count, n, d_active, buf, cbuf, chunks, st,
+                                               spart, norm);
+}
+
 }  // namespace
+
+// the coefficient's exponential on the host (the kernels' code and table)
+double kl_exp_host(double x) { return kl_exp(x, kExp2TabHost); }
 
 // ---- tile shapes ------------------------------------------------------------
 static const SweepShape kShapes[] = {
@@ -1888,8 +2068,9 @@ void launch_field(int n, int count, double* const* d_out, const int* d_xi_index,
                   hipStream_t st) {
   if (count <= 0) return;
   if (n > kFieldMaxN) return;  // plans stop at 1025 vertices per axis
-  hipLaunchKernelGGL(k_field, xcd_grid(count, n), dim3(kBlock), 0, st, n, d_out, d_xi_index,
-                     d_normals, d_phi, d_coef, mode, count, n);
+  const int per = ceil_div(n * n, kBlock);
+  hipLaunchKernelGGL(k_field, xcd_grid(count, per), dim3(kBlock), 0, st, n, d_out, d_xi_index,
+                     d_normals, d_phi, d_coef, mode, count, per);
 }
 
 void launch_inject(int nf, int count, const double* const* d_fine, double* const* d_coarse,
@@ -1938,15 +2119,16 @@ int sweep_blocks(int n, int count, SweepShape s) {
 
 template <typename T>
 int launch_sweep(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
-                 int cbuf, SweepShape s, hipStream_t st, T* spart, int norm, bool const_b) {
+                 int cbuf, SweepShape s, hipStream_t st, T* spart, int norm, bool const_b,
+                 bool kl) {
   if (count <= 0) return 0;
   const int c = s.chunks;  // 0: chosen in the kernel from the active grids
 #define MG_SWEEP_CASE(TJ_, TK_)                                                              \
   if (s.tj == TJ_ && s.tk == TK_)                                                            \
     return const_b ? sweep_launch<T, TJ_, TK_, true>(d_list, count, n, d_active, buf, cbuf, c, \
-                                                     st, spart, norm)                       \
+                                                     st, spart, norm, kl)                   \
                    : sweep_launch<T, TJ_, TK_, false>(d_list, count, n, d_active, buf, cbuf,  \
-                                                      c, st, spart, norm);
+                                                      c, st, spart, norm, kl);
   MG_SWEEP_CASE(8, 64)
   MG_SWEEP_CASE(4, 64)
   MG_SWEEP_CASE(16, 32)
@@ -1990,27 +2172,35 @@ int resrestrict_blocks(int n) {
 
 template <typename T>
 void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
-                        int buf, hipStream_t st, bool const_b) {
+                        int buf, hipStream_t st, bool const_b, bool kl) {
   if (count <= 0) return;
   const int m = (n - 1) / 2 - 1;  // coarse interior points per axis
-  auto go = [&](auto cb) {
-    constexpr bool CB = decltype(cb)::value;
+  auto go = [&](auto cb, auto klc) {
+    constexpr bool CB = decltype(cb)::value, KL = decltype(klc)::value;
+    const size_t lds = KL ? sizeof(double) * (size_t)kl_lds_doubles(n) : 0;
     if (n >= 65) {
       const int tk = ceil_div(m, kRRK1), per = ceil_div(m, kRRJ1) * tk;
-      hipLaunchKernelGGL((k_resrestrict<T, kRRJ1, kRRK1, CB>), xcd_grid(count, per),
-                         dim3(RRGeom<kRRJ1, kRRK1>::THREADS), 0, st, d_list, d_active, buf, tk,
+      hipLaunchKernelGGL((k_resrestrict<T, kRRJ1, kRRK1, CB, KL>), xcd_grid(count, per),
+                         dim3(RRGeom<kRRJ1, kRRK1>::THREADS), lds, st, d_list, d_active, buf, tk,
                          count, per);
     } else {
       const int tk = ceil_div(m, kRRK2), per = ceil_div(m, kRRJ2) * tk;
-      hipLaunchKernelGGL((k_resrestrict<T, kRRJ2, kRRK2, CB>), xcd_grid(count, per),
-                         dim3(RRGeom<kRRJ2, kRRK2>::THREADS), 0, st, d_list, d_active, buf, tk,
+      hipLaunchKernelGGL((k_resrestrict<T, kRRJ2, kRRK2, CB, KL>), xcd_grid(count, per),
+                         dim3(RRGeom<kRRJ2, kRRK2>::THREADS), lds, st, d_list, d_active, buf, tk,
                          count, per);
     }
   };
+  // KL launches for FP64 grids with a constant right-hand side (as the sweep)
+  if constexpr (std::is_same<T, double>::value) {
+    if (kl && const_b && n <= kKLMaxN) {
+      go(std::true_type{}, std::true_type{});
+      return;
+    }
+  }
   if (const_b)
-    go(std::true_type{});
+    go(std::true_type{}, std::false_type{});
   else
-    go(std::false_type{});
+    go(std::false_type{}, std::false_type{});
 }
 
 template <typename T>
@@ -2056,13 +2246,13 @@ void launch_copy_buf(const GridDescT<T>* d_list, int count, int n, const int* d_
 
 #define MG_INSTANTIATE(T)                                                                       \
   template int launch_sweep<T>(const GridDescT<T>*, int, int, const int*, int, int, SweepShape,  \
-                               hipStream_t, T*, int, bool);                                     \
+                               hipStream_t, T*, int, bool, bool);                               \
   template void launch_rbgs_colour<T>(const GridDescT<T>*, int, int, const int*, int, int,      \
                                       hipStream_t);                                             \
   template void launch_residual<T>(const GridDescT<T>*, int, int, const int*, int, hipStream_t); \
   template void launch_restrict<T>(const GridDescT<T>*, int, int, const int*, hipStream_t);      \
   template void launch_resrestrict<T>(const GridDescT<T>*, int, int, const int*, int, hipStream_t, \
-                                      bool);                                                      \
+                                      bool, bool);                                                \
   template void launch_coarsest<T>(const GridDescT<T>*, int, const int*, hipStream_t);           \
   template void launch_prolong<T>(const GridDescT<T>*, int, int, const int*, int, int,           \
                                   hipStream_t);                                                 \

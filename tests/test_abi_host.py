@@ -111,3 +111,34 @@ def test_host_philox_words_rejects_bad_arguments(M):
     out = (C.c_uint32 * 128)()
     assert M.lib().mlmc_philox_words(0, -1, out) == M.MG_EINVAL
     assert M.lib().mlmc_philox_words(0, 0, None) == M.MG_EINVAL
+
+
+def _exact_exp(x):
+    from decimal import Decimal, getcontext
+    getcontext().prec = 40
+    return Decimal(x).exp()
+
+
+def test_kl_exp_within_two_ulp_of_exact(M):
+    """The exponential the kernels form k = exp(Z) and wh = exp(-Z)/2 with
+    (Tang's table-driven method, evaluated on the host by the same code and
+    table) against the exactly rounded value: within 2 units in the last
+    place on random arguments that reach every table entry and both signs,
+    on the multiples of ln2/32 (the table's nodes) and near 0, and exact
+    at x = 0."""
+    from decimal import Decimal
+    rng = np.random.default_rng(7)
+    xs = np.concatenate([rng.uniform(-40.0, 40.0, 4000), rng.uniform(-0.05, 0.05, 1000),
+                         np.arange(-64, 65) * (math.log(2.0) / 32.0)])
+    worst = 0.0
+    for x in xs:
+        got = M.mlmc_exp(float(x))
+        ref = _exact_exp(float(x))
+        ulp = math.ulp(float(ref))
+        err = abs(Decimal(got) - ref) / Decimal(ulp)
+        worst = max(worst, float(err))
+    assert worst <= 2.0, worst
+    assert M.mlmc_exp(0.0) == 1.0
+    # arguments beyond +-700 are clamped
+    assert M.mlmc_exp(800.0) == M.mlmc_exp(700.0)
+    assert M.mlmc_exp(-800.0) == M.mlmc_exp(-700.0)
