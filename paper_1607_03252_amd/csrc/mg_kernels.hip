@@ -30,7 +30,10 @@ constexpr int kBlock = 256;
 // y (1 + e + e^2) = 1/x (1 - e^3) leaves a truncation of 2^-75 and the result
 // is within half a unit in the last place bar rounding (three FMAs: the same
 // accuracy as two Newton-Raphson steps, one FMA fewer on a path whose
-// sweeps are bound by FP64 issue).  FP32: one Newton-Raphson step.
+// sweeps are bound by FP64 issue).  FP32 (the inner cycles of mixed
+// precision, whose corrections the FP64 defect of the next outer step
+// checks): the hardware estimate as it is, within about one unit in the
+// last place.
 template <typename T>
 __device__ __forceinline__ T rcp(T x);
 template <>
@@ -41,9 +44,7 @@ __device__ __forceinline__ double rcp<double>(double x) {
 }
 template <>
 __device__ __forceinline__ float rcp<float>(float x) {
-  float y = __builtin_amdgcn_rcpf(x);
-  const float e = __builtin_fmaf(-x, y, 1.0f);
-  return __builtin_fmaf(y, e, y);
+  return __builtin_amdgcn_rcpf(x);
 }
 
 __device__ __forceinline__ int vidx(int n, int i, int j, int k) { return (i * n + j) * n + k; }
