@@ -154,9 +154,10 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *               iterates);
  *   "graph":    1 = capture the cycles of mlmc_sample_batch into HIP graphs
  *               (default), 0 = launch eagerly;
- *   "transfer": 0 = residual and full weighting in one pass where a launch
- *               has at least 128 workgroups (default), 1 = always separate
- *               residual and restriction kernels (same results, bit for bit);
+ *   "transfer": 0 = residual and full weighting in one pass (default; a
+ *               launch with few grids splits each tile's plane march into
+ *               pieces of coarse planes), 1 = separate residual and
+ *               restriction kernels (same results, bit for bit);
  *   "small_vcycle": 17 (default), 9 or 5 = from the largest grid of at most
  *               this size down, each V-cycle runs in one launch with the
  *               grids held in LDS; 0 = one launch per level and step

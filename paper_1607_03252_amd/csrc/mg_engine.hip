@@ -119,7 +119,6 @@ struct Batch {
   // (device buffers sized for L64 on first use)
   Lists<double> L64t;
   SolveState ss{};
-  int* d_cycle = nullptr;                          // device cycle counter
   int* h_state = nullptr;  // pinned: active then cycles of every solve (2 ns)
   // MLMC sample plumbing
   int nsamples = 0;
@@ -393,9 +392,8 @@ static std::unique_ptr<Batch> build_batch(mg_plan_s* P, const BatchSpec& spec,
     } else {
       B->ss.active = ai;
       B->ss.cycles = ai + ns;  // (right after active: the host reads both in one copy)
-      B->ss.start = ai + 2 * ns;
+      B->ss.ran = ai + 2 * ns;
       B->ss.qpend = ai + 3 * ns;
-      B->d_cycle = ai + 4 * ns;
       B->ss.relres = dd;
       B->ss.bnorm = dd + ns;
       B->ss.q = dd + 2 * ns;
@@ -789,15 +787,15 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls, bool norms = false, d
           // judge the incoming iterates now: a solve that stops keeps it in
           // buffer 0 (this sweep wrote buffer 1; nothing after it runs for it)
           const size_t ti = size_index(B->top_sizes, n);
-          launch_finalize2(Ls.dtop[ti], (int)Ls.htop[ti].size(), B->ss, RED_RESID, B->d_cycle, 1,
+          launch_finalize2(Ls.dtop[ti], (int)Ls.htop[ti].size(), B->ss, RED_RESID, 1, 1,
                            fixed, P->desc.max_cycles, tol, st, lp, lpr);
         }
       }
     }
-    // the one-pass transfer marches planes with a barrier each: with few
-    // workgroups the separate kernels (same results) finish sooner
-    // (it addresses whole grids with 32-bit offsets, as the fused sweep)
-    if (P->transfer == 0 && cnt * resrestrict_blocks(n) >= 128 && sweep_fits(n, sizeof(T))) {
+    // the one-pass transfer (same results as the separate kernels; it splits
+    // its plane marches when a launch has few grids, and addresses whole
+    // grids with 32-bit offsets, as the fused sweep)
+    if (P->transfer == 0 && sweep_fits(n, sizeof(T))) {
       launch_resrestrict<T>(Ls.d[si], cnt, n, B->ss.active, cur[si], st, Ls.const_b(si),
                             P->kl_inline && Ls.kl(si));
     } else {
@@ -838,16 +836,16 @@ static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
   hipStream_t st = B->st;
   Lists<double>& L = Lp ? *Lp : B->L64;
   if (P->prof) ++P->prof_cycle;  // (eager while profiling: one call per cycle)
-  // the counter counts V-cycles: a mixed-precision step applies inner_cycles
+  // V-cycles per step, credited to each active solve by its judgement: a
+  // mixed-precision step applies inner_cycles
   const int per_step = B->spec.mixed ? P->inner_cycles : 1;
-  launch_tick(B->d_cycle, st, per_step);
   if (B->spec.fe) {
     run_cycle_fe(P, B, L);
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
       const int n = B->top_sizes[ti], cnt = (int)L.htop[ti].size();
       launch_fe_residual(L.dtop[ti], cnt, n, B->ss.active, st);
       launch_reduce(L.dtop[ti], cnt, n, B->ss.active, 0, RED_R2, B->ss.partials, st);
-      launch_finalize2(L.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, 0, fixed,
+      launch_finalize2(L.dtop[ti], cnt, B->ss, RED_RESID, 1, 0, fixed,
                        P->desc.max_cycles, tol, st);
     }
   } else if (!B->spec.mixed) {
@@ -860,7 +858,7 @@ static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
       const int n = B->top_sizes[ti], cnt = (int)L.htop[ti].size();
       if (lagged_parts(P, B, size_index(B->sizes, n)) > 0) continue;  // judged in the sweep
       launch_reduce(L.dtop[ti], cnt, n, B->ss.active, 0, RED_RESID, B->ss.partials, st);
-      launch_finalize2(L.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, 0, fixed,
+      launch_finalize2(L.dtop[ti], cnt, B->ss, RED_RESID, 1, 0, fixed,
                        P->desc.max_cycles, tol, st);
     }
   } else {
@@ -869,7 +867,7 @@ static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
       const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
       launch_defect(B->L64.dtop[ti], B->L32.dtop[ti], cnt, n, B->ss.active, B->ss.partials, st);
-      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_RESID, B->d_cycle, per_step, fixed,
+      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_RESID, per_step, per_step, fixed,
                        P->desc.max_cycles, tol, st);
     }
     // inner_cycles FP32 V-cycles on A e = r from e = 0; the next one starts
@@ -945,14 +943,14 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
                        const std::function<void()>& post = nullptr, int qpend = 0) {
   hipStream_t st = B->st;
   P->prof_cycle = 0;
-  launch_init_state2(B->ss, B->d_cycle, B->ns, st, qpend);
+  launch_init_state2(B->ss, B->ns, st, qpend);
   // ||b'|| per solve (a constant top right-hand side gives the same norms for
   // every batch of this workspace)
   if (!(B->spec.const_b_top && B->bnorm_ready)) {
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
       const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
       launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_BNORM, B->ss.partials, st);
-      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, B->d_cycle, 0, fixed,
+      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, 0, 0, fixed,
                        P->desc.max_cycles, tol, st);
     }
     B->bnorm_ready = B->spec.const_b_top;
@@ -1180,7 +1178,7 @@ static int run_samples(mg_plan_s* P, const std::vector<int>& levels, const uint6
       const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
       launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, mode, B->ss.partials, st,
                     B->ss.qpend);
-      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, mode, B->d_cycle, 0, 0, 0, 0.0, st);
+      launch_finalize2(B->L64.dtop[ti], cnt, B->ss, mode, 0, 0, 0, 0, 0.0, st);
     }
     launch_ydiff(B->ss.q, B->d_fi, B->d_ci, n_samples, Y_out, Qf_out, Qc_out, B->ss.cycles,
                  cycles_out, st);
@@ -1314,7 +1312,7 @@ static int run_fmg_level(mg_plan_s* P, int level, const uint64_t* seeds,
     launch_zero_u<double>(B->L64.dtop[0], S, n, st);
     if (prev) {
       GridDesc* d_link = fmg_link(B, prev);
-      launch_init_state2(B->ss, B->d_cycle, S, st);  // active flags for the interpolation
+      launch_init_state2(B->ss, S, st);  // active flags for the interpolation
       launch_prolong<double>(d_link, S, n, B->ss.active, 0, 0, st);
     }
     // the 3^3 grid: one exact solve; above: the fixed V-cycles
@@ -1328,7 +1326,7 @@ static int run_fmg_level(mg_plan_s* P, int level, const uint64_t* seeds,
     if (P->qoi_kind == QOI_INTEGRAL) {
       launch_reduce(B->L64.dtop[0], S, B->top_sizes[0], B->ss.active, 0, RED_QOI, B->ss.partials,
                     st);
-      launch_finalize2(B->L64.dtop[0], S, B->ss, RED_QOI, B->d_cycle, 0, 0, 0, 0.0, st);
+      launch_finalize2(B->L64.dtop[0], S, B->ss, RED_QOI, 0, 0, 0, 0, 0.0, st);
     } else {
       launch_qoi_pf(B->L64.dtop[0], S, P->qoi_kind, B->ss.q, st);
     }
@@ -1654,7 +1652,7 @@ static std::unique_ptr<Lane> make_lane(mg_plan_s* P, int level, int first, int n
   for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
     const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
     launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_BNORM, B->ss.partials, ln->st);
-    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, B->d_cycle, 0, 0,
+    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_BNORM, 0, 0, 0,
                      P->desc.max_cycles, P->desc.tol, ln->st);
   }
   CK(hipStreamSynchronize(ln->st));
@@ -1725,7 +1723,7 @@ static void serve_admit(mg_plan_s* P, Lane* ln, const std::vector<Ticket>& tk) {
   for (const auto& l : cvt) launch_to_float(l.n, l.count, (const double* const*)l.src, l.fdst, st);
   for (size_t ti = 0; ti < zero.size(); ++ti)
     if (zero[ti].first) launch_zero_u<double>(zero[ti].second, zero[ti].first, B->top_sizes[ti], st);
-  launch_admit(d_admit, (int)admit.size(), B->ss, B->d_cycle, st);
+  launch_admit(d_admit, (int)admit.size(), B->ss, st);
 }
 
 // c cycles of every resident solve of a lane, then the QoI of the solves
@@ -1737,7 +1735,7 @@ static void serve_cycles(mg_plan_s* P, Lane* ln, int c) {
     const int n = B->top_sizes[ti], cnt = (int)B->L64.htop[ti].size();
     launch_reduce(B->L64.dtop[ti], cnt, n, B->ss.active, 0, RED_QOI_PENDING, B->ss.partials,
                   ln->st, B->ss.qpend);
-    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI_PENDING, B->d_cycle, 0, 0, 0, 0.0,
+    launch_finalize2(B->L64.dtop[ti], cnt, B->ss, RED_QOI_PENDING, 0, 0, 0, 0, 0.0,
                      ln->st);
   }
 }
@@ -2295,7 +2293,7 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
           SweepShape s = shapes[i];
           s.chunks = chunks;
           // every solve active while timing; the next batch reinitialises the workspace
-          launch_init_state2(B->ss, B->d_cycle, B->ns, P->work);
+          launch_init_state2(B->ss, B->ns, P->work);
           const int cb = pro ? 0 : -1;
           auto one = [&]() {
             if (mixed)

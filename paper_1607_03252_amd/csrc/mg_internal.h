@@ -84,7 +84,8 @@ struct SolveState {
   double* bnorm;    // ||b'||_2 (1 when b' = 0)
   double* q;        // QoI of the solve's top grid
   double* partials; // reduction partials
-  int* start;       // cycle counter value when the solve was started
+  int* ran;         // V-cycles credited to the solve so far: the judgement of
+                    // each outer step adds that step's cycles
   int* qpend;       // 1 from admission until the QoI of a stopped solve is taken
   double* spart;    // per solve 2 x kSweepParts + 2: in-sweep residual-norm
                     // partials (black points of the output of a cycle's last
@@ -183,8 +184,8 @@ template <typename T>
 void launch_restrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                      hipStream_t st);
 // Residual of u[buf] and full weighting into bc, in one pass (r is not stored);
-// resrestrict_blocks: its workgroups per grid.
-int resrestrict_blocks(int n);
+// each tile's plane march is split into resrestrict_chunks(n, count) pieces.
+int resrestrict_chunks(int n, int count);
 template <typename T>
 void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int* d_active,
                         int buf, hipStream_t st, bool const_b = false, bool kl = false);
@@ -219,23 +220,21 @@ void launch_defect(const GridDesc* d_list, const GridDesc32* d_list32, int count
 // Mixed precision: u[0] += (double) e32 on the top grids.
 void launch_correct(const GridDesc* d_list, const GridDesc32* d_list32, int count, int n,
                     const int* d_active, int buf32, hipStream_t st);
-// Finalise per solve.  The cycle judged is *cycle_ctr - start - lag (an
-// iterate before the first cycle is never judged); fixed_cycles > 0 selects
-// fixed-count mode.  RED_RESID with sweep_parts > 0 sums the in-sweep
-// partials instead of the reduction's: spart[spoff + q] and
+// Finalise per solve.  RED_RESID runs once per outer step for every active
+// solve: it credits the step's `step` cycles to the solve (ran += step) and
+// judges the iterate after ran - lag cycles (an iterate before the first
+// cycle is never judged); fixed_cycles > 0 selects fixed-count mode.
+// RED_RESID with sweep_parts > 0 sums the in-sweep partials instead of the
+// reduction's: spart[spoff + q] and
 // spart[spoff + kSweepParts + q] for the counts the sweeps stored at
 // spart[spoff + 2 kSweepParts] and [... + 1] (sweep_parts_red is unused).
-void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
-                      const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
-                      hipStream_t st, int sweep_parts = 0, int sweep_parts_red = 0);
-// active = 1, cycles = 0, start = 0, qpend = qpend, *cycle_ctr = 0;
-// launch_tick: *cycle_ctr += inc (the V-cycles of one step).
-void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st, int qpend = 0);
-// Start the listed solves now: active = 1, cycles = 0, start = *cycle_ctr,
-// qpend = 1.
-void launch_admit(const int* d_solves, int count, SolveState s, const int* cycle_ctr,
-                  hipStream_t st);
-void launch_tick(int* ctr, hipStream_t st, int inc = 1);
+void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode, int step,
+                      int lag, int fixed_cycles, int max_cycles, double tol, hipStream_t st,
+                      int sweep_parts = 0, int sweep_parts_red = 0);
+// active = 1, cycles = 0, ran = 0, qpend = qpend.
+void launch_init_state2(SolveState s, int ns, hipStream_t st, int qpend = 0);
+// Start the listed solves now: active = 1, cycles = 0, ran = 0, qpend = 1.
+void launch_admit(const int* d_solves, int count, SolveState s, hipStream_t st);
 void launch_ydiff(const double* d_q, const int* d_fine_idx, const int* d_coarse_idx, int count,
                   double* d_y, double* d_qf, double* d_qc, const int* d_cycles, int* d_cycles_out,
                   hipStream_t st);

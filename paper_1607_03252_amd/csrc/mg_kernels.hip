@@ -1293,10 +1293,15 @@ struct RRGeom {
 // arrays are addressed as in the sweep: one descriptor per array, the
 // plane's offset added to the per-lane offsets.  KL (FP64): wh evaluated from
 // the grid's KL data as in the sweep (the mode table in dynamic LDS).
+// chunks: pieces of the coarse planes per tile (a launch with few grids
+// splits each tile's march so that it still has many workgroups); a piece
+// of coarse planes Ia..Ib marches the fine planes 2Ia-1..2Ib+1 and stores
+// only its own coarse planes, each summed over its fine planes in the same
+// order as by a whole march.
 template <typename T, int RJ, int RK, bool CB, bool KL>
 __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
     k_resrestrict(const GridDescT<T>* __restrict__ list, const int* __restrict__ active, int buf,
-                  int tiles_k, int count, int per) {
+                  int tiles_k, int tiles, int chunks, int count, int per) {
   using G = RRGeom<RJ, RK>;
   // fine tile FJ x FK with a one-point ring in LDS (u, wh per plane parity)
   constexpr int FJ = G::FJ, FK = G::FK, W = FK + 2, H = FJ + 2, A = W * H;
@@ -1308,8 +1313,13 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
   const GridDescT<T> d = list[gi];
   if (!active[d.solve]) return;
   const int n = d.n, sn2 = n * n, nc = (n - 1) / 2 + 1;
-  const int tj = blk / tiles_k, tk = blk - tj * tiles_k;
+  const int ch = blk / tiles, tile = blk - ch * tiles;
+  const int tj = tile / tiles_k, tk = tile - tj * tiles_k;
   const int J0 = 1 + tj * RJ, K0 = 1 + tk * RK;
+  // this piece's coarse planes and the fine planes it marches
+  const int clen = ceil_div(nc - 2, chunks);
+  const int Ia = 1 + ch * clen, Ib = min(nc - 2, Ia + clen - 1);
+  const int i0 = 2 * Ia - 1, i1 = 2 * Ib + 1;
   const int jb = 2 * J0 - 1, kb = 2 * K0 - 1;  // fine origin of the tile
   const int t = threadIdx.x;
   // this thread's fine column
@@ -1393,10 +1403,10 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
     HU[sl] = bload<T>(ru, oh + so);
   };
   auto prologue = [&]() {
-    load(0, 3);
-    load(1, 0);
-    load(2, 1);
-    load(3, 2);
+    load(i0 - 1, 3);
+    load(i0, 0);
+    load(i0 + 1, 1);
+    load(i0 + 2, 2);
     if (fl) {
       LU[1][q] = OU[0];
       LW[1][q] = OW[0];
@@ -1456,7 +1466,7 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
       s1 += tm[1];
       s1 += tm[2];
       const int I = (i - 1) >> 1;
-      const bool st_ok = odd && I >= 1 && I <= nc - 2;
+      const bool st_ok = odd && I >= Ia && I <= Ib;
       const uint32_t cso = (uint32_t)I * cbytes, cg = st_ok ? (uint32_t)nc * cbytes : 0u;
       const auto rbc = rsrc(d.bc, cg), ruc = rsrc(d.uc[0], cg);
       bstore<T>(rbc, oco + cso, cin ? (T)0.5 * s1 : (T)0);
@@ -1480,7 +1490,7 @@ __global__ void __launch_bounds__((RRGeom<RJ, RK>::THREADS))
   // prologue loads waited for once (as in the smoother: the waits at the
   // head of the march then follow the loop's own load order)
   __builtin_amdgcn_s_waitcnt(kWaitVmem0);
-  for (int i = 1; i <= n - 2; i += 4) {
+  for (int i = i0; i <= i1; i += 4) {
     fine(I0{}, i);
     __syncthreads();
     coarse(I0{}, i);
@@ -1849,13 +1859,13 @@ __global__ void __launch_bounds__(kBlock) k_correct(const GridDesc* __restrict__
   d.u[0][q] += (double)(buf32 ? e.u[1] : e.u[0])[q];
 }
 
-// Per-solve finalisation of the reductions.  For RED_RESID the cycle being
-// judged is *cycle_ctr - lag (lag 1 when the residual belongs to the iterate
-// of the previous outer step).
+// Per-solve finalisation of the reductions.  RED_RESID runs once per outer
+// step of each active solve: it credits the step's cycles to the solve and
+// judges the iterate after ran - lag cycles (lag 1 when the residual belongs
+// to the iterate of the previous outer step).
 __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict__ list,
-                                                     SolveState s, int mode,
-                                                     const int* __restrict__ cycle_ctr, int lag,
-                                                     int fixed_cycles, int max_cycles,
+                                                     SolveState s, int mode, int step,
+                                                     int lag, int fixed_cycles, int max_cycles,
                                                      double tol, int sweep_parts,
                                                      int sweep_parts_red) {
   const GridDesc d = list[blockIdx.x];
@@ -1878,7 +1888,10 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
     const double nb = sqrt(v);
     s.bnorm[sv] = nb > 0.0 ? nb : 1.0;
   } else if (mode == RED_RESID) {
-    const int cycle = *cycle_ctr - s.start[sv] - lag;
+    // (once per outer step of an active solve: credit the step's cycles)
+    const int ran = s.ran[sv] + step;
+    s.ran[sv] = ran;
+    const int cycle = ran - lag;
     const double rho = sqrt(v) / s.bnorm[sv];
     s.relres[sv] = rho;
     if (cycle < 1) return;  // the initial iterate: convergence is judged after cycles
@@ -1901,29 +1914,23 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
   }
 }
 
-__global__ void k_init_state(SolveState s, int* __restrict__ cycle_ctr, int ns, int qpend) {
+__global__ void k_init_state(SolveState s, int ns, int qpend) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) *cycle_ctr = 0;
   if (t >= ns) return;
   s.active[t] = 1;
   s.cycles[t] = 0;
-  s.start[t] = 0;
+  s.ran[t] = 0;
   s.qpend[t] = qpend;
 }
 
-__global__ void k_admit(const int* __restrict__ solves, int count, SolveState s,
-                        const int* __restrict__ cycle_ctr) {
+__global__ void k_admit(const int* __restrict__ solves, int count, SolveState s) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   const int sv = solves[t];
   s.active[sv] = 1;
   s.cycles[sv] = 0;
-  s.start[sv] = *cycle_ctr;
+  s.ran[sv] = 0;
   s.qpend[sv] = 1;
-}
-
-__global__ void k_tick(int* __restrict__ ctr, int inc) {
-  if (threadIdx.x == 0) *ctr += inc;
 }
 
 __global__ void k_ydiff(const double* __restrict__ q, const int* __restrict__ fi,
@@ -2166,9 +2173,15 @@ void launch_residual(const GridDescT<T>* d_list, int count, int n, const int* d_
 
 // coarse tile shapes of the one-pass transfer (grids from 65^3 up, smaller)
 constexpr int kRRJ1 = 4, kRRK1 = 32, kRRJ2 = 8, kRRK2 = 16;
-int resrestrict_blocks(int n) {
+static int rr_tiles(int n) {
   const int m = (n - 1) / 2 - 1;
   return n >= 65 ? ceil_div(m, kRRJ1) * ceil_div(m, kRRK1) : ceil_div(m, kRRJ2) * ceil_div(m, kRRK2);
+}
+// pieces per tile: enough workgroups for two per CU, at least two coarse
+// planes per piece
+int resrestrict_chunks(int n, int count) {
+  const int m = (n - 1) / 2 - 1;
+  return std::max(1, std::min(m / 2, ceil_div(512, std::max(1, count) * rr_tiles(n))));
 }
 
 template <typename T>
@@ -2176,19 +2189,20 @@ void launch_resrestrict(const GridDescT<T>* d_list, int count, int n, const int*
                         int buf, hipStream_t st, bool const_b, bool kl) {
   if (count <= 0) return;
   const int m = (n - 1) / 2 - 1;  // coarse interior points per axis
+  const int ch = resrestrict_chunks(n, count), tiles = rr_tiles(n), per = tiles * ch;
   auto go = [&](auto cb, auto klc) {
     constexpr bool CB = decltype(cb)::value, KL = decltype(klc)::value;
     const size_t lds = KL ? sizeof(double) * (size_t)kl_lds_doubles(n) : 0;
     if (n >= 65) {
-      const int tk = ceil_div(m, kRRK1), per = ceil_div(m, kRRJ1) * tk;
+      const int tk = ceil_div(m, kRRK1);
       hipLaunchKernelGGL((k_resrestrict<T, kRRJ1, kRRK1, CB, KL>), xcd_grid(count, per),
                          dim3(RRGeom<kRRJ1, kRRK1>::THREADS), lds, st, d_list, d_active, buf, tk,
-                         count, per);
+                         tiles, ch, count, per);
     } else {
-      const int tk = ceil_div(m, kRRK2), per = ceil_div(m, kRRJ2) * tk;
+      const int tk = ceil_div(m, kRRK2);
       hipLaunchKernelGGL((k_resrestrict<T, kRRJ2, kRRK2, CB, KL>), xcd_grid(count, per),
                          dim3(RRGeom<kRRJ2, kRRK2>::THREADS), lds, st, d_list, d_active, buf, tk,
-                         count, per);
+                         tiles, ch, count, per);
     }
   };
   // KL launches for FP64 grids with a constant right-hand side (as the sweep)
@@ -2306,28 +2320,21 @@ void launch_correct(const GridDesc* d_list, const GridDesc32* d_list32, int coun
                      d_active, buf32, count, per);
 }
 
-void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode,
-                      const int* cycle_ctr, int lag, int fixed_cycles, int max_cycles, double tol,
-                      hipStream_t st, int sweep_parts, int sweep_parts_red) {
+void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode, int step,
+                      int lag, int fixed_cycles, int max_cycles, double tol, hipStream_t st,
+                      int sweep_parts, int sweep_parts_red) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_finalize, dim3(count), dim3(kBlock), 0, st, d_list, s, mode, cycle_ctr, lag,
+  hipLaunchKernelGGL(k_finalize, dim3(count), dim3(kBlock), 0, st, d_list, s, mode, step, lag,
                      fixed_cycles, max_cycles, tol, sweep_parts, sweep_parts_red);
 }
 
-void launch_init_state2(SolveState s, int* cycle_ctr, int ns, hipStream_t st, int qpend) {
-  hipLaunchKernelGGL(k_init_state, dim3((ns + 255) / 256), dim3(256), 0, st, s, cycle_ctr, ns,
-                     qpend);
+void launch_init_state2(SolveState s, int ns, hipStream_t st, int qpend) {
+  hipLaunchKernelGGL(k_init_state, dim3((ns + 255) / 256), dim3(256), 0, st, s, ns, qpend);
 }
 
-void launch_admit(const int* d_solves, int count, SolveState s, const int* cycle_ctr,
-                  hipStream_t st) {
+void launch_admit(const int* d_solves, int count, SolveState s, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_admit, dim3((count + 255) / 256), dim3(256), 0, st, d_solves, count, s,
-                     cycle_ctr);
-}
-
-void launch_tick(int* ctr, hipStream_t st, int inc) {
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, ctr, inc);
+  hipLaunchKernelGGL(k_admit, dim3((count + 255) / 256), dim3(256), 0, st, d_solves, count, s);
 }
 
 // QoIs of Section 3 besides the integral, on the top grids (u[0]), one
