@@ -12,7 +12,9 @@
   * serving at n0 = 33 (levels 0..2: 33^3 .. 129^3 fine grids): served results
     equal the same samples computed alone, bit for bit, and the oracle;
   * the MLMC level accumulator (Section 2.3: mean and s^2 with divisor N)
-    fed a batch's device Y, against the oracle's accumulator.
+    fed a batch's device Y, against the oracle's accumulator;
+  * the largest grids (513^3, 1025^3) with k = 1 against the closed form of
+    the discrete QoI.
 
 Bars: Q within 1e-9 |Q| and equal cycle counts (the oracle's stopping rule;
 mixed precision with two FP32 cycles per step: the count rounded up to an even
@@ -281,3 +283,31 @@ def test_level_accumulator_fed_device_y(M, torch):
     # s^2 of values that agree to 1e-9 * scale agrees to about 2 * 1e-9 * scale * |Y|
     assert abs(var - v_o) <= 4e-9 * scale * float(np.max(np.abs(yg))) + 1e-300
     assert var > 0.0
+
+
+@pytest.mark.parametrize("n", [513, 1025])
+def test_largest_grids_constant_coefficient_closed_form(M, torch, n):
+    """The largest grids: 513^3 (the largest on which the fused kernels'
+    32-bit whole-grid offsets fit) and 1025^3 (the largest a plan takes; its
+    finest level runs the colour sweeps and the separate residual kernels).
+    With sigma^2 = 0 (k = 1) the QoI of the discrete problem has the mode-sum
+    closed form of tests/closed_forms.py; 16 fixed V(2,2) cycles leave an
+    algebraic error far below the bar (the FP64 residual floor at 1025^3,
+    about 4e-11 relative, is above the usual tolerance's reach)."""
+    from closed_forms import q_const_modes
+    print("largest grids: one sample of %d^3, sigma^2 = 0, 16 cycles" % n, flush=True)
+    P = M.mg_plan_create(n0=n, max_level=0, sigma2=0.0)
+    Y = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Qf, Qc = torch.zeros_like(Y), torch.zeros_like(Y)
+    cyc = torch.zeros(2, dtype=torch.int32, device="cuda")
+    st = M.mlmc_sample_batch(P, 0, np.array([3], dtype=np.uint64), 1, Y, Qf, Qc, cyc,
+                             fixed_cycles=16)
+    assert st == M.MG_OK
+    q = q_const_modes(n)
+    got = float(Qf.item())
+    measure(check="largest_grid_closed_form", n=n, cycles=int(cyc[0].item()), Q=got,
+            closed_form=q, rel_dQ=abs(got - q) / q)
+    assert int(cyc[0].item()) == 16
+    assert abs(got - q) <= 1e-9 * q
+    P.destroy()
+    torch.cuda.empty_cache()

@@ -85,3 +85,12 @@ def test_random_field_run_meets_sampling_tolerance():
         v = math.fsum((y - m) ** 2 for y in ys) / len(ys)
         assert r["mean"][l] == pytest.approx(m, rel=1e-12, abs=1e-18)
         assert r["var"][l] == pytest.approx(v, rel=1e-9, abs=1e-24)
+
+
+@pytest.mark.parametrize("n", [5, 9, 17, 33])
+def test_mode_sum_closed_form_matches_dst_solution(n):
+    """The mode-sum closed form of the k = 1 QoI (used at 1025^3 on the GPU,
+    where a transform of the whole grid is out of reach) against the DST-I
+    solution of the same discrete problem."""
+    from closed_forms import q_const_modes
+    assert q_const_modes(n) == pytest.approx(_q_const(n), rel=1e-13)
