@@ -157,36 +157,40 @@ def _order_key(r):
     return int(r["Start_Timestamp"])
 
 
+def _grid_size(r):
+    for k in ("Grid_Size_X", "Grid_Size"):
+        if r.get(k) not in (None, ""):
+            return int(r[k])
+    return 0
+
+
 def finest_sweeps(rows, batches, cycles_upto, nu1=2, nu2=2):
     """Rows (one per dispatch) of the finest-grid sweeps in cycles 1..cycles_upto
-    of the last `batches` batches.  A batch starts at k_init_state, a cycle at
-    k_tick; within a cycle the finest grid's sweeps are the first nu1 and the
-    last nu2 sweep dispatches (a V-cycle descends from, and returns to, the
-    finest grid).  Returns [(kind, cycle, row)]."""
+    of the last `batches` batches.  A batch starts at k_init_state; its
+    finest grid's sweeps are the sweep dispatches with the largest launch grid
+    in the batch, nu1 + nu2 of them per V-cycle (a cycle descends from, and
+    returns to, the finest grid), so the c-th group of nu1 + nu2 is cycle c.
+    (Profiled steps launch every cycle on the whole list, so no cycle has
+    fewer.)  Returns [(kind, cycle, row)]."""
     rows = sorted(rows, key=_order_key)
     names = [short_name(r["Kernel_Name"]) for r in rows]
     starts = [i for i, nm in enumerate(names) if nm == "k_init_state"]
     if len(starts) < batches:
         raise ValueError("the run has %d batches, fewer than %d" % (len(starts), batches))
+    per_cycle = nu1 + nu2
     out = []
     for b in range(len(starts) - batches, len(starts)):
         lo = starts[b]
         hi = starts[b + 1] if b + 1 < len(starts) else len(rows)
-        cycle, sweeps = 0, []
-
-        def flush():
-            if cycle >= 1 and cycle <= cycles_upto and sweeps:
-                pick = sweeps[:nu1] + sweeps[max(nu1, len(sweeps) - nu2):]
-                for i in pick:
-                    out.append((sweep_kind(names[i]), cycle, rows[i]))
-        for i in range(lo, hi):
-            if names[i] == "k_tick":
-                flush()
-                cycle += 1
-                sweeps = []
-            elif names[i].startswith("k_sweep"):
-                sweeps.append(i)
-        flush()
+        sweeps = [i for i in range(lo, hi) if names[i].startswith("k_sweep")]
+        if not sweeps:
+            continue
+        top = max(_grid_size(rows[i]) for i in sweeps)
+        fine = [i for i in sweeps if _grid_size(rows[i]) == top]
+        for q, i in enumerate(fine):
+            cycle = q // per_cycle + 1
+            if cycle <= cycles_upto:
+                out.append((sweep_kind(names[i]), cycle, rows[i]))
     return out
 
 

@@ -48,3 +48,28 @@ def test_committed_traffic_summary_is_readable():
     assert len(rec["kernel_source_sha256"]) == 64
     assert rec["fetch_scale"] > 0 and rec["write_scale"] > 0
     json.dumps(rec)
+
+
+def test_finest_sweeps_groups_the_largest_launches_by_cycle():
+    # two batches; each cycle: two sweeps on the finest grid, a transfer, a
+    # coarser grid's sweeps, two more finest sweeps (the first is judged)
+    def row(i, name, grid):
+        return {"Dispatch_Id": str(i), "Kernel_Name": name, "Grid_Size_X": str(grid),
+                "Start_Timestamp": str(10 * i), "End_Timestamp": str(10 * i + 5)}
+    seq, i = [], 0
+    for _ in range(2):
+        seq.append(row(i, "k_init_state(...)", 256)); i += 1
+        for _c in range(3):
+            for nm, g in (("k_sweep_res_in_cb<double, 16, 32, false>", 900),
+                          ("k_finalize(...)", 4096),
+                          ("k_sweep<double, 16, 32, false, true, false>", 900),
+                          ("k_resrestrict<double, 4, 32, true, false>", 9000),
+                          ("k_sweep<double, 16, 32, false, false, false>", 100),
+                          ("k_sweep<double, 16, 32, true, true, false>", 900),
+                          ("k_sweep_res_out<double, 16, 32, true, false>", 900)):
+                seq.append(row(i, nm, g)); i += 1
+    sel = profsum.finest_sweeps(seq, batches=1, cycles_upto=2)
+    assert [(k, c) for k, c, _ in sel] == [(3, 1), (0, 1), (1, 1), (2, 1),
+                                           (3, 2), (0, 2), (1, 2), (2, 2)]
+    # the selected rows belong to the last batch
+    assert min(int(r["Dispatch_Id"]) for _, _, r in sel) > 22
