@@ -388,15 +388,21 @@ def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profil
         if rec:
             out["roofline"]["traffic_over_algorithmic"] = traffic / rf["bytes_per_launch"]
     if args.calib_copy:
-        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        calib_copy(torch)
     P.destroy()
     torch.cuda.empty_cache()
     return out
+
+
+def calib_copy(torch):
+    """A plain 1 GiB device-to-device copy (three times): the counter runs
+    scale FETCH_SIZE and WRITE_SIZE by what they read for it."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def bench_levelpair(args, M, torch, np, steps=None, profile=True):
@@ -466,14 +472,19 @@ def bench_levelpair(args, M, torch, np, steps=None, profile=True):
         cmin = int(cyc_p.cpu().numpy().reshape(-1, S, 2)[:, :, 0].min())
         rf = sweep_roofline(M, P, nf, S, cmin, kl_inline(args))
         M.mg_profile_enable(P, False)
+        tl = [list(tiles[65]), list(tiles_pro[65])]
+        traffic, src, rec = read_traffic("k_sweep_levelpair65_33x64.txt", tl)
         out["roofline"] = {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBPS,
                            "unit": "GB/s", "frac": rf["achieved"] / HBM_PEAK_GBPS,
-                           "traffic": None,
+                           "traffic": traffic, "traffic_source": src,
                            "kernel": "k_sweep family (fused red-black sweeps, 65^3 grids)",
                            "launches": rf["launches"], "avg_launch_us": rf["avg_launch_us"],
                            "bytes_per_launch": rf["bytes_per_launch"],
-                           "all_active_cycles": cmin, "per_kind": rf["per_kind"],
-                           "tiles": [list(tiles[65]), list(tiles_pro[65])]}
+                           "all_active_cycles": cmin, "per_kind": rf["per_kind"], "tiles": tl}
+        if rec:
+            out["roofline"]["traffic_over_algorithmic"] = traffic / rf["bytes_per_launch"]
+    if args.calib_copy:
+        calib_copy(torch)
     P.destroy()
     return out
 

@@ -157,40 +157,49 @@ def _order_key(r):
     return int(r["Start_Timestamp"])
 
 
-def _grid_size(r):
-    for k in ("Grid_Size_X", "Grid_Size"):
-        if r.get(k) not in (None, ""):
-            return int(r[k])
-    return 0
-
-
 def finest_sweeps(rows, batches, cycles_upto, nu1=2, nu2=2):
     """Rows (one per dispatch) of the finest-grid sweeps in cycles 1..cycles_upto
-    of the last `batches` batches.  A batch starts at k_init_state; its
-    finest grid's sweeps are the sweep dispatches with the largest launch grid
-    in the batch, nu1 + nu2 of them per V-cycle (a cycle descends from, and
-    returns to, the finest grid), so the c-th group of nu1 + nu2 is cycle c.
-    (Profiled steps launch every cycle on the whole list, so no cycle has
-    fewer.)  Returns [(kind, cycle, row)]."""
+    of the last `batches` batches.  A batch starts at k_init_state.  Each
+    V-cycle has one bottom (k_vsmall or k_coarsest dispatches, consecutive
+    ones taken together), which splits the batch's sweep dispatches into
+    segments: S_0 before the first bottom is cycle 1's pre-smoothing, K levels
+    of nu1 sweeps from the finest grid down; S_c between bottoms c and c + 1
+    is cycle c's post-smoothing (K levels of nu2 sweeps, the finest grid's
+    last) followed by cycle c + 1's pre-smoothing.  So cycle c's finest
+    sweeps are the first nu1 of its pre-smoothing and the last nu2 of its
+    post-smoothing.  (Every cycle of a batch, also one on the lists of its
+    last solves, visits the same K levels.)  Returns [(kind, cycle, row)]."""
     rows = sorted(rows, key=_order_key)
     names = [short_name(r["Kernel_Name"]) for r in rows]
     starts = [i for i, nm in enumerate(names) if nm == "k_init_state"]
     if len(starts) < batches:
         raise ValueError("the run has %d batches, fewer than %d" % (len(starts), batches))
-    per_cycle = nu1 + nu2
     out = []
     for b in range(len(starts) - batches, len(starts)):
         lo = starts[b]
         hi = starts[b + 1] if b + 1 < len(starts) else len(rows)
-        sweeps = [i for i in range(lo, hi) if names[i].startswith("k_sweep")]
-        if not sweeps:
+        segs, cur, at_bottom = [], [], False
+        for i in range(lo, hi):
+            nm = names[i]
+            if nm.startswith("k_vsmall") or nm.startswith("k_coarsest"):
+                if not at_bottom:
+                    segs.append(cur)
+                    cur = []
+                at_bottom = True
+            elif nm.startswith("k_sweep"):
+                cur.append(i)
+                at_bottom = False
+        segs.append(cur)
+        if len(segs) < 2 or len(segs[0]) % nu1:
             continue
-        top = max(_grid_size(rows[i]) for i in sweeps)
-        fine = [i for i in sweeps if _grid_size(rows[i]) == top]
-        for q, i in enumerate(fine):
-            cycle = q // per_cycle + 1
-            if cycle <= cycles_upto:
-                out.append((sweep_kind(names[i]), cycle, rows[i]))
+        K = len(segs[0]) // nu1
+        for c in range(1, len(segs)):
+            if c > cycles_upto:
+                break
+            pre = (segs[0] if c == 1 else segs[c - 1][K * nu2:])[:nu1]
+            post = segs[c][:K * nu2][-nu2:]
+            for i in pre + post:
+                out.append((sweep_kind(names[i]), c, rows[i]))
     return out
 
 

@@ -50,26 +50,34 @@ def test_committed_traffic_summary_is_readable():
     json.dumps(rec)
 
 
-def test_finest_sweeps_groups_the_largest_launches_by_cycle():
-    # two batches; each cycle: two sweeps on the finest grid, a transfer, a
-    # coarser grid's sweeps, two more finest sweeps (the first is judged)
-    def row(i, name, grid):
-        return {"Dispatch_Id": str(i), "Kernel_Name": name, "Grid_Size_X": str(grid),
+def test_finest_sweeps_follow_the_v_cycle():
+    # two batches of three cycles on two sweep levels (finest F, coarser C)
+    # above a small-grid V-cycle; the finest grid's sweep kinds differ in
+    # launch shape (the selection must not depend on it)
+    def row(i, name):
+        return {"Dispatch_Id": str(i), "Kernel_Name": name,
                 "Start_Timestamp": str(10 * i), "End_Timestamp": str(10 * i + 5)}
+    F = {"in": "k_sweep_res_in_cb<double, 8, 64, false>",
+         "plain": "k_sweep<double, 8, 64, false, true, false>",
+         "pro": "k_sweep<double, 16, 32, true, true, false>",
+         "out": "k_sweep_res_out<double, 8, 64, true, false>"}
+    C = {"in": "k_sweep_res_in<double, 16, 16, false>",
+         "plain": "k_sweep<double, 16, 16, false, false, false>",
+         "pro": "k_sweep<double, 8, 32, true, false, false>",
+         "out": "k_sweep_res_out<double, 16, 16, false, false>"}
     seq, i = [], 0
     for _ in range(2):
-        seq.append(row(i, "k_init_state(...)", 256)); i += 1
+        seq.append(row(i, "k_init_state(...)")); i += 1
         for _c in range(3):
-            for nm, g in (("k_sweep_res_in_cb<double, 16, 32, false>", 900),
-                          ("k_finalize(...)", 4096),
-                          ("k_sweep<double, 16, 32, false, true, false>", 900),
-                          ("k_resrestrict<double, 4, 32, true, false>", 9000),
-                          ("k_sweep<double, 16, 32, false, false, false>", 100),
-                          ("k_sweep<double, 16, 32, true, true, false>", 900),
-                          ("k_sweep_res_out<double, 16, 32, true, false>", 900)):
-                seq.append(row(i, nm, g)); i += 1
+            for nm in (F["in"], "k_finalize(...)", F["plain"], "k_resrestrict<double, 4, 32, true, false>",
+                       C["in"], "k_finalize(...)", C["plain"], "k_resrestrict<double, 8, 16, false, false>",
+                       "k_vsmall<double, 17>(...)", C["pro"], C["out"], F["pro"], F["out"]):
+                seq.append(row(i, nm)); i += 1
+        seq.append(row(i, "k_reduce(...)")); i += 1
     sel = profsum.finest_sweeps(seq, batches=1, cycles_upto=2)
     assert [(k, c) for k, c, _ in sel] == [(3, 1), (0, 1), (1, 1), (2, 1),
                                            (3, 2), (0, 2), (1, 2), (2, 2)]
+    assert all(r["Kernel_Name"] in F.values() for _, _, r in sel)
     # the selected rows belong to the last batch
-    assert min(int(r["Dispatch_Id"]) for _, _, r in sel) > 22
+    assert min(int(r["Dispatch_Id"]) for _, _, r in sel) > 40
+    assert len(profsum.finest_sweeps(seq, batches=2, cycles_upto=9)) == 2 * 3 * 4
