@@ -151,11 +151,14 @@ def parse_args():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="minimum wall time of the level-pair oracle baseline")
     ap.add_argument("--workload", default="config4",
-                    choices=["config4", "levelpair", "single", "mixed", "fp32mix", "serve"])
+                    choices=["config4", "levelpair", "single", "mixed", "fp32mix", "serve",
+                             "adaptive"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="precision of the default workload")
     ap.add_argument("--inner-cycles", type=int, default=1,
                     help="mixed precision: FP32 V-cycles per FP64 defect-correction step")
+    ap.add_argument("--eps", type=float, default=5e-6,
+                    help="adaptive workload: the MLMC tolerance (absolute, on Q)")
     ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--serve-slots", default="128,64,16,4")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
@@ -193,7 +196,8 @@ def main():
     threads = args.cpu_threads or min(16, os.cpu_count() or 1)
     if args.workload != "config4":
         fn = {"levelpair": bench_levelpair, "single": bench_single, "mixed": bench_mixed,
-              "fp32mix": bench_fp32mix, "serve": bench_serve}[args.workload]
+              "fp32mix": bench_fp32mix, "serve": bench_serve,
+              "adaptive": bench_adaptive}[args.workload]
         out = fn(args, M, torch, np)
         if args.workload == "levelpair" and not args.no_cpu_baseline:
             v, cdt, done = cpu_baseline_pairs(33, 1, threads, args.cpu_seconds)
@@ -666,6 +670,32 @@ def bench_fp32mix(args, M, torch, np):
     out["speedup_mixed_inner2_vs_fp64"] = res["fp64"]["batch_s"] / res["mixed_inner2"]["batch_s"]
     out["max_rel_dQ_mixed_inner2_vs_fp64"] = float(
         np.max(np.abs(Q["mixed_inner2"] - Q["fp64"]) / np.abs(Q["fp64"])))
+    return out
+
+
+def bench_adaptive(args, M, torch, np):
+    """The whole estimator: Algorithm 2 (adaptive MLMC) to tolerance eps on
+    levels 0..4 of n0 = 17 (17^3 .. 257^3 fine grids), sigma^2 = 1,
+    lambda = 0.1, theta = 1/2, alpha = 2/3, N_Init = 32; wall time from eps to
+    the estimate, with the number of samples and V-cycles it took."""
+    P = M.mg_plan_create(n0=17, max_level=4, sigma2=1.0, corr_len=0.1)
+    M.mlmc_adaptive(P, eps=4 * args.eps, n_init=8, seed0=10**6)  # warm-up: workspaces, graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = M.mlmc_adaptive(P, eps=args.eps, n_init=32, seed0=0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    total = int(sum(r["N"]))
+    out = _line("MLMC estimate to tolerance (Algorithm 2): wall time", dt, "s", 1, 1, 1e3 * dt,
+                {"workload": "adaptive_mlmc_n0_17_levels_0_4", "n0": 17, "max_level": 4,
+                 "eps": args.eps, "theta": 0.5, "alpha": 2.0 / 3.0, "n_init": 32,
+                 "sigma2": 1.0, "corr_len": 0.1, "tol": 1e-8}, higher=False)
+    out["estimate"] = {"Q": r["Q"], "L": r["L"], "N": r["N"], "mean": r["mean"], "var": r["var"],
+                       "sampling_rms": r["sampling_rms"], "bias_estimate": r["bias_estimate"],
+                       "bias_ok": r["bias_ok"], "iterations": r["iterations"]}
+    out["samples"] = total
+    out["samples_per_s"] = total / dt
+    P.destroy()
     return out
 
 
