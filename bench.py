@@ -160,7 +160,10 @@ def parse_args():
     ap.add_argument("--eps", type=float, default=5e-6,
                     help="adaptive workload: the MLMC tolerance (absolute, on Q)")
     ap.add_argument("--serve-requests", type=int, default=2048)
-    ap.add_argument("--serve-slots", default="128,64,16,4")
+    ap.add_argument("--serve-slots", default="128,64,16,4",
+                    help="slots per lane of each level, or 'auto' (an eighth of the budget)")
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0,
+                    help="HBM budget the server's lanes share (GiB)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--no-fifo", action="store_true")
     ap.add_argument("--autotune", action="store_true",
@@ -706,13 +709,15 @@ def bench_serve(args, M, torch, np):
     at fractions of it (p50/p99 latency), and the same traces through a plain
     first-in-first-out path that solves one sample at a time."""
     L, N = 3, args.serve_requests
-    slots = [int(x) for x in args.serve_slots.split(",")]
+    slots = None if args.serve_slots == "auto" else [int(x) for x in args.serve_slots.split(",")]
+    budget = int(args.serve_budget_gib * (1 << 30))
     loads = [float(x) for x in args.serve_loads.split(",")]
     p = np.array([4.0 ** -l for l in range(L + 1)])
     lv = np.random.Generator(np.random.PCG64(0)).choice(L + 1, size=N, p=p / p.sum())
     gaps = np.random.Generator(np.random.PCG64(1)).exponential(1.0, size=N)
-    P = M.mg_plan_create(n0=33, max_level=L)
+    P = M.mg_plan_create(n0=33, max_level=L, hbm_budget=budget)
     S = M.Server(P, slots, queue_capacity=N + 1)
+    slots = [S.slots(l) for l in range(L + 1)]
 
     def run_server(arrivals):
         # arrivals: server-clock times (None: all at once)
@@ -734,12 +739,13 @@ def bench_serve(args, M, torch, np):
         span = max(x["t_done"] for x in res) - base
         return res, lat, span
 
-    # warm: graphs and every slot once
-    for i in range(sum(slots)):
-        S.submit(min(L, i % (L + 1)), 10**6 + i, -1)
+    # warm: the lanes a burst opens and their graphs
+    for i in range(N):
+        S.submit(int(lv[i]), 10**6 + i, -1)
     while S.counts()[1] or S.counts()[0]:
         S.step(1)
     res, lat, span = run_server(None)
+    mem_sat = S.memory()
     sat = N / span
     acc = {l: M.mlmc_acc_init() for l in range(L + 1)}
     for x in res:
@@ -750,13 +756,14 @@ def bench_serve(args, M, torch, np):
         est += m
         var_sum += v / max(1, acc[l].n)
     out = _line("served MLMC samples/s at saturation (levels 0..3 of n0=33)", sat, "samples/s",
-                N, sum(slots), 1e3 * span / N,
+                N, N, 1e3 * span / N,
                 {"workload": "serve_n0_33_levels_0_3_p_4^-l", "n0": 33, "levels": "0..3",
-                 "requests": N, "slots_per_level": slots, "cycles_per_step": 1, "sigma2": 1.0,
-                 "corr_len": 0.1, "tol": 1e-8})
+                 "requests": N, "lane_slots": slots, "hbm_budget_bytes": budget,
+                 "cycles_per_step": 1, "sigma2": 1.0, "corr_len": 0.1, "tol": 1e-8})
     out["saturation"] = {"samples_per_s": sat, "p50_ms": 1e3 * _pct(lat, 50),
                          "p99_ms": 1e3 * _pct(lat, 99),
                          "mlmc_estimate": est, "sampling_rms": var_sum ** 0.5,
+                         "memory": mem_sat,
                          "requests_per_level": [int((lv == l).sum()) for l in range(L + 1)]}
     # the plain path: one plan per level, one sample per call, in arrival order
     fifo_plans = {}
@@ -772,7 +779,7 @@ def bench_serve(args, M, torch, np):
         arr = np.cumsum(gaps) / lam
         res, lat, span = run_server(arr)
         rec = {"offered_per_s": lam, "served_per_s": N / span, "p50_ms": 1e3 * _pct(lat, 50),
-               "p99_ms": 1e3 * _pct(lat, 99),
+               "p99_ms": 1e3 * _pct(lat, 99), "memory": S.memory(),
                "per_level_p50_p99_ms": {
                    str(l): [1e3 * _pct([x["t_done"] - x["t_arrival"] for x in res if x["level"] == l], q)
                             for q in (50, 99)] for l in range(L + 1)}}

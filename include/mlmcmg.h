@@ -66,7 +66,7 @@ typedef struct {
   double corr_len;    /* correlation length lambda (> 0)                       */
   int kl_per_axis;    /* 1D modes per axis; this build supports 4 (4^3 terms)  */
   size_t hbm_budget;  /* bytes a batch workspace may hold; 0 = no limit (a     */
-                      /* server sizing its pools from it takes 8 GiB for 0)  */
+                      /* server's lanes share it; 8 GiB for a server if 0)   */
   void* stream;       /* hipStream_t to run on; NULL = the null stream         */
 } mg_plan_desc;
 
@@ -265,15 +265,21 @@ int mg_autotune(mg_plan plan, int level, int n_samples, int reps);
 /* Serving: continuous batching of MLMC sample requests --------------------
  *
  * A request asks for one sample Y_level(seed) (Algorithm 1, steps 1.a.i-ii,
- * as mlmc_sample_batch with one seed).  The server keeps, per level, a fixed
- * pool of resident sample slots (a lane: one workspace, its own stream and
- * graphs; the grids stay in HBM for the server's life).  Lanes progress
- * independently: when a lane's launch has finished, its finished samples
- * leave, queued requests of its level are admitted into the freed slots
- * (fields and coefficient hierarchies generated on the device), and the lane
- * is launched again while the other lanes' work is still on the device.  A
- * sample's results do not depend on what else is resident: they equal those
- * of mlmc_sample_batch for that seed and level, bit for bit.
+ * as mlmc_sample_batch with one seed).  Resident samples live in lanes: a
+ * lane holds a fixed number of sample slots of one level (one workspace,
+ * its own stream and graphs; its grids stay in HBM while the lane lives).
+ * All lanes share the plan's HBM budget.  Lanes are opened when requests of
+ * their level find no free slot and the budget has room, and evicted when
+ * empty and their bytes are needed by another level, so memory left idle by
+ * one level admits requests of another.  Lanes progress independently: when
+ * a lane's launch has finished, its finished samples leave, queued requests
+ * of its level are admitted into the freed slots (fields and coefficient
+ * hierarchies generated on the device), and the lane is launched again while
+ * the other lanes' work is still on the device.  A sample's results do not
+ * depend on what else is resident: they equal those of mlmc_sample_batch for
+ * that seed and level, bit for bit.  (The paper's dynamic strategies, which
+ * hand a new sample to whichever processor group has finished one, are the
+ * prior art; Section 5.3.)
  */
 
 /* Device bytes of one resident sample slot of `level` (fine and coarse
@@ -281,29 +287,66 @@ int mg_autotune(mg_plan plan, int level, int n_samples, int reps);
 int mg_sample_footprint(mg_plan plan, int level, size_t* bytes);
 
 /* Admission scheduler (host only, no device work; the server uses it).
- * Requests wait in one queue in arrival order; level l owns slots
- * [first_l, first_l + slots_per_level[l]).  mg_sched_admit walks the queue
- * from its head and gives each request whose level has a free slot the
- * lowest free slot of that level, so each level is served in arrival order
- * and a full level does not hold back the others. */
+ * Level l is served in lanes of lane_slots[l] slots costing lane_bytes[l]
+ * bytes each; all lanes together stay within `budget` bytes.  Requests wait
+ * in one queue in arrival order.  mg_sched_admit walks the queue from its
+ * head; a request
+ *  - takes the lowest free slot of the lowest-numbered idle lane of its
+ *    level that is not draining; if its level's free slots are all in lanes
+ *    marked in flight, it waits for them;
+ *  - otherwise opens a lane of its level, evicting empty idle lanes when the
+ *    budget is short (the smallest one that covers the shortfall, else the
+ *    largest first until it is covered);
+ *  - if no lane can be opened and its level has no lane, it reserves the
+ *    memory: until it is admitted no other request opens a lane, and lanes of
+ *    other levels covering the shortfall (empty idle ones, then the fewest
+ *    resident samples first) drain: they take no new samples, so they empty
+ *    and are evicted for it.
+ * Once a request waits, later requests of its level wait for the rest of
+ * that walk.  So requests of one level are admitted in arrival order, the
+ * lanes' bytes never exceed the budget, and every request is admitted once
+ * enough resident samples have finished.  Lanes opened and evicted are reported as
+ * events, which the executor applies before using the tickets of that pass. */
 typedef struct mg_sched_s* mg_sched;
 typedef struct {
   long long tag;     /* caller's request id */
   uint64_t seed;
   int level;
   int slot;          /* assigned slot */
+  int lane;          /* lane holding that slot */
   double t_arrival;  /* caller's arrival time, seconds */
 } mg_ticket;
-/* slots_per_level: host int[n_levels], each >= 0; queue_capacity >= 1. */
-int mg_sched_create(int n_levels, const int* slots_per_level, int queue_capacity, mg_sched* out);
+enum { MG_LANE_OPEN = 1, MG_LANE_CLOSE = 2 };
+typedef struct {
+  int kind;    /* MG_LANE_OPEN or MG_LANE_CLOSE */
+  int lane;    /* lane id (ids are never reused) */
+  int level;
+  int first;   /* the lane's slots are first .. first + nslots - 1 */
+  int nslots;
+  size_t bytes;
+} mg_lane_event;
+/* lane_slots, lane_bytes: host arrays of n_levels; lane_slots[l] in [0, 4096]
+ * (0: level l is not served), lane_bytes[l] > 0 where lane_slots[l] > 0;
+ * budget > 0 bytes; queue_capacity >= 1. */
+int mg_sched_create(int n_levels, const int* lane_slots, const size_t* lane_bytes, size_t budget,
+                    int queue_capacity, mg_sched* out);
 int mg_sched_destroy(mg_sched s);
-/* MG_EINVAL for a level outside [0, n_levels), MG_EBUSY when the queue is full. */
+/* MG_EINVAL for a level outside [0, n_levels), MG_ENOMEM when a lane of that
+ * level exceeds the budget or the level is not served, MG_EBUSY when the
+ * queue is full. */
 int mg_sched_submit(mg_sched s, int level, uint64_t seed, long long tag, double t_arrival);
 /* Writes up to max_out admitted tickets to out (host) and their number to *n_out. */
 int mg_sched_admit(mg_sched s, mg_ticket* out, int max_out, int* n_out);
+/* Takes up to max_out pending lane events (oldest first) into out (host). */
+int mg_sched_events(mg_sched s, mg_lane_event* out, int max_out, int* n_out);
+/* Marks a lane as running on the device (nonzero: it neither admits nor is
+ * evicted) or idle.  MG_EINVAL for an unknown lane. */
+int mg_sched_set_inflight(mg_sched s, int lane, int inflight);
 /* MG_EINVAL if the slot is not busy. */
 int mg_sched_release(mg_sched s, int slot);
 int mg_sched_counts(mg_sched s, int* queued, int* busy);
+/* Bytes of the open lanes, their maximum so far, and how many are open. */
+int mg_sched_memory(mg_sched s, size_t* used, size_t* peak, int* lanes);
 
 typedef struct mg_server_s* mg_server;
 typedef struct {
@@ -317,29 +360,40 @@ typedef struct {
   double t_admit, t_done;  /* server clock (mg_serve_now), seconds          */
 } mg_result;
 
-/* Create a server on a plan (levels 0..max_level of the plan).
- * slots_per_level: host int[max_level + 1] (each >= 0), or NULL to size the
- * pools from the plan's hbm_budget (8 GiB if 0): each level gets an equal
- * share of the budget, divided by mg_sample_footprint, clamped to [1, 256].
- * MG_ENOMEM if the pools exceed the budget.  The plan must outlive the
+/* Create a server on a plan (levels 0..max_level of the plan).  Its budget is
+ * the plan's hbm_budget, or 8 GiB if that is 0.  lane_slots: host
+ * int[max_level + 1], slots per lane of each level (each >= 0, 0: level not
+ * served), or NULL to size each level's lanes to at most an eighth of the
+ * budget (clamped to [1, 256] slots).  A lane's bytes are its workspace
+ * (mg_sample_footprint per slot plus descriptor lists) and its staging
+ * buffers.  Nothing is allocated until requests arrive.  MG_ENOMEM if one
+ * lane of a served level exceeds the budget.  The plan must outlive the
  * server; calls on the plan and on its servers must not overlap. */
-int mg_serve_create(mg_plan plan, const int* slots_per_level, int queue_capacity, mg_server* out);
+int mg_serve_create(mg_plan plan, const int* lane_slots, int queue_capacity, mg_server* out);
 int mg_serve_destroy(mg_server s);
-/* Queue one request.  t_arrival < 0: stamped with mg_serve_now(). */
+/* Queue one request.  t_arrival < 0: stamped with mg_serve_now().  Errors as
+ * mg_sched_submit. */
 int mg_serve_submit(mg_server s, int level, uint64_t seed, long long tag, double t_arrival);
 /* One scheduling step: harvest every lane whose last launch has finished,
- * admit queued requests into the free slots of idle lanes, launch `cycles`
- * V-cycles (>= 1; graph-captured) on every idle lane that holds samples, and
- * wait until at least one lane has finished if none had.  Returns the
- * samples that finished (up to max_out per call; the rest come with the next
- * call).  out: host mg_result[max_out]; *n_out: how many were written.  With
- * nothing queued or resident it returns at once. */
+ * admit queued requests (opening and evicting lanes as the scheduler
+ * decides), launch `cycles` V-cycles (>= 1; graph-captured) on every idle
+ * lane that holds samples, and wait until at least one lane has finished if
+ * none had.  Returns the samples that finished (up to max_out per call; the
+ * rest come with the next call).  out: host mg_result[max_out]; *n_out: how
+ * many were written.  With nothing queued or resident it returns at once. */
 int mg_serve_step(mg_server s, int cycles, mg_result* out, int max_out, int* n_out);
 /* Seconds since the server was created (steady clock). */
 double mg_serve_now(mg_server s);
 int mg_serve_counts(mg_server s, int* queued, int* resident, long long* completed);
-/* Slot pool size of a level (after NULL sizing), or -1. */
+/* Slots per lane of a level (after NULL sizing), or -1. */
 int mg_serve_slots(mg_server s, int level);
+/* Device bytes of the open lanes (each lane counted at its stated bytes,
+ * which bound what it allocates: creating a lane that allocates more fails
+ * with MG_EHIP), their maximum so far, the budget, the number of open lanes,
+ * and how many lanes were opened and evicted so far.  Any pointer may be
+ * NULL. */
+int mg_serve_memory(mg_server s, size_t* used, size_t* peak, size_t* budget, int* lanes,
+                    long long* opened, long long* evicted);
 
 /* Test and parity exports ------------------------------------------------- */
 

@@ -41,7 +41,15 @@ class mg_plan_desc(C.Structure):
 
 class mg_ticket(C.Structure):
     _fields_ = [("tag", C.c_longlong), ("seed", C.c_uint64), ("level", C.c_int), ("slot", C.c_int),
-                ("t_arrival", C.c_double)]
+                ("lane", C.c_int), ("t_arrival", C.c_double)]
+
+
+MG_LANE_OPEN, MG_LANE_CLOSE = 1, 2
+
+
+class mg_lane_event(C.Structure):
+    _fields_ = [("kind", C.c_int), ("lane", C.c_int), ("level", C.c_int), ("first", C.c_int),
+                ("nslots", C.c_int), ("bytes", C.c_size_t)]
 
 
 class mg_result(C.Structure):
@@ -120,12 +128,16 @@ def lib():
         L.mg_get_tile_for.argtypes = [vp, C.c_int, C.c_int, ip, ip, ip]
         L.mg_autotune.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.mg_sample_footprint.argtypes = [vp, C.c_int, C.POINTER(C.c_size_t)]
-        L.mg_sched_create.argtypes = [C.c_int, ip, C.c_int, C.POINTER(vp)]
+        L.mg_sched_create.argtypes = [C.c_int, ip, C.POINTER(C.c_size_t), C.c_size_t, C.c_int,
+                                      C.POINTER(vp)]
         L.mg_sched_destroy.argtypes = [vp]
         L.mg_sched_submit.argtypes = [vp, C.c_int, C.c_uint64, C.c_longlong, C.c_double]
         L.mg_sched_admit.argtypes = [vp, C.POINTER(mg_ticket), C.c_int, ip]
         L.mg_sched_release.argtypes = [vp, C.c_int]
         L.mg_sched_counts.argtypes = [vp, ip, ip]
+        L.mg_sched_events.argtypes = [vp, C.POINTER(mg_lane_event), C.c_int, ip]
+        L.mg_sched_set_inflight.argtypes = [vp, C.c_int, C.c_int]
+        L.mg_sched_memory.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), ip]
         L.mg_serve_create.argtypes = [vp, ip, C.c_int, C.POINTER(vp)]
         L.mg_serve_destroy.argtypes = [vp]
         L.mg_serve_submit.argtypes = [vp, C.c_int, C.c_uint64, C.c_longlong, C.c_double]
@@ -134,6 +146,9 @@ def lib():
         L.mg_serve_now.restype = C.c_double
         L.mg_serve_counts.argtypes = [vp, ip, ip, C.POINTER(C.c_longlong)]
         L.mg_serve_slots.argtypes = [vp, C.c_int]
+        L.mg_serve_memory.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                                      C.POINTER(C.c_size_t), ip, C.POINTER(C.c_longlong),
+                                      C.POINTER(C.c_longlong)]
         L.mg_last_error.argtypes = [vp]
         L.mg_last_error.restype = C.c_char_p
         _lib = L
@@ -152,7 +167,8 @@ def exported_symbols():
             "mg_serve_now", "mg_serve_counts", "mg_serve_slots", "mg_set_tile_for",
             "mg_get_tile_for", "mlmc_philox_words", "mg_solve_noalloc",
             "mg_profile_records", "mg_plan_get_desc", "mlmc_adaptive_desc_default",
-            "mlmc_adaptive", "mlmc_exp"]
+            "mlmc_adaptive", "mlmc_exp", "mg_sched_events", "mg_sched_set_inflight",
+            "mg_sched_memory", "mg_serve_memory"]
 
 
 def _torch():
@@ -436,29 +452,49 @@ def mg_sample_footprint(plan: Plan, level: int) -> int:
 
 
 class Sched:
-    """Admission scheduler (host only): mg_sched_* on one handle."""
+    """Admission scheduler (host only): mg_sched_* on one handle.  Level l is
+    served in lanes of lane_slots[l] slots costing lane_bytes[l] bytes; the
+    open lanes share `budget` bytes."""
 
-    def __init__(self, slots_per_level, queue_capacity=1 << 16):
-        a = np.ascontiguousarray(np.asarray(slots_per_level, dtype=np.int32))
+    def __init__(self, lane_slots, lane_bytes, budget, queue_capacity=1 << 16):
+        a = np.ascontiguousarray(np.asarray(lane_slots, dtype=np.int32))
+        b = np.ascontiguousarray(np.asarray(lane_bytes, dtype=np.uint64))
+        if a.size != b.size:
+            raise ValueError("lane_slots and lane_bytes need one entry per level")
         h = C.c_void_p()
         st = lib().mg_sched_create(int(a.size), a.ctypes.data_as(C.POINTER(C.c_int)),
+                                   b.ctypes.data_as(C.POINTER(C.c_size_t)), int(budget),
                                    int(queue_capacity), C.byref(h))
         if st != MG_OK:
             raise MGError(st, "mg_sched_create rejected its arguments")
         self.handle = h
 
     def submit(self, level, seed, tag, t_arrival=0.0):
-        """Returns the status (MG_OK, MG_EBUSY or MG_EINVAL)."""
+        """Returns the status (MG_OK, MG_EBUSY, MG_ENOMEM or MG_EINVAL)."""
         return lib().mg_sched_submit(self.handle, int(level), int(seed), int(tag), float(t_arrival))
 
     def admit(self, max_out=1024):
-        buf = (mg_ticket * max_out)()
+        """Tickets (tag, seed, level, slot, lane, t_arrival) of one pass."""
+        buf = (mg_ticket * max(1, max_out))()
         n = C.c_int()
         st = lib().mg_sched_admit(self.handle, buf, max_out, C.byref(n))
         if st != MG_OK:
             raise MGError(st, "mg_sched_admit")
-        return [(buf[i].tag, buf[i].seed, buf[i].level, buf[i].slot, buf[i].t_arrival)
+        return [(buf[i].tag, buf[i].seed, buf[i].level, buf[i].slot, buf[i].lane, buf[i].t_arrival)
                 for i in range(n.value)]
+
+    def events(self, max_out=1024):
+        """Pending lane events (kind, lane, level, first, nslots, bytes)."""
+        buf = (mg_lane_event * max_out)()
+        n = C.c_int()
+        st = lib().mg_sched_events(self.handle, buf, max_out, C.byref(n))
+        if st != MG_OK:
+            raise MGError(st, "mg_sched_events")
+        return [(buf[i].kind, buf[i].lane, buf[i].level, buf[i].first, buf[i].nslots, buf[i].bytes)
+                for i in range(n.value)]
+
+    def set_inflight(self, lane, inflight):
+        return lib().mg_sched_set_inflight(self.handle, int(lane), int(bool(inflight)))
 
     def release(self, slot):
         return lib().mg_sched_release(self.handle, int(slot))
@@ -467,6 +503,12 @@ class Sched:
         q, b = C.c_int(), C.c_int()
         lib().mg_sched_counts(self.handle, C.byref(q), C.byref(b))
         return q.value, b.value
+
+    def memory(self):
+        """(bytes of the open lanes, their maximum so far, open lanes)."""
+        u, p, n = C.c_size_t(), C.c_size_t(), C.c_int()
+        lib().mg_sched_memory(self.handle, C.byref(u), C.byref(p), C.byref(n))
+        return u.value, p.value, n.value
 
     def __del__(self):
         try:
@@ -480,21 +522,22 @@ class Sched:
 class Server:
     """Serving handle (mg_serve_*): continuous batching on one plan."""
 
-    def __init__(self, plan: Plan, slots_per_level=None, queue_capacity=1 << 16):
+    def __init__(self, plan: Plan, lane_slots=None, queue_capacity=1 << 16):
         self.plan = plan
         h = C.c_void_p()
-        if slots_per_level is None:
+        if lane_slots is None:
             p = None
         else:
-            self._slots = np.ascontiguousarray(np.asarray(slots_per_level, dtype=np.int32))
+            self._slots = np.ascontiguousarray(np.asarray(lane_slots, dtype=np.int32))
             if self._slots.size != plan.desc.max_level + 1:
-                raise ValueError("slots_per_level needs max_level + 1 entries")
+                raise ValueError("lane_slots needs max_level + 1 entries")
             p = self._slots.ctypes.data_as(C.POINTER(C.c_int))
         plan.check(lib().mg_serve_create(plan.handle, p, int(queue_capacity), C.byref(h)))
         self.handle = h
 
     def submit(self, level, seed, tag, t_arrival=-1.0):
-        """Returns MG_OK or MG_EBUSY (queue full); raises on bad arguments."""
+        """Returns MG_OK or MG_EBUSY (queue full); raises on bad arguments and
+        on a level that is not served."""
         st = lib().mg_serve_submit(self.handle, int(level), int(seed), int(tag), float(t_arrival))
         return self.plan.check(st, (MG_OK, MG_EBUSY))
 
@@ -520,7 +563,17 @@ class Server:
         return q.value, r.value, c.value
 
     def slots(self, level):
+        """Slots per lane of a level."""
         return lib().mg_serve_slots(self.handle, int(level))
+
+    def memory(self):
+        """Dict: used, peak and budget bytes, open lanes, lanes opened and evicted."""
+        u, p, b = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        n, o, e = C.c_int(), C.c_longlong(), C.c_longlong()
+        lib().mg_serve_memory(self.handle, C.byref(u), C.byref(p), C.byref(b), C.byref(n),
+                              C.byref(o), C.byref(e))
+        return {"used": u.value, "peak": p.value, "budget": b.value, "lanes": n.value,
+                "opened": o.value, "evicted": e.value}
 
     def destroy(self):
         if getattr(self, "handle", None):
@@ -534,5 +587,5 @@ class Server:
             pass
 
 
-def mg_serve_create(plan: Plan, slots_per_level=None, queue_capacity=1 << 16) -> Server:
-    return Server(plan, slots_per_level, queue_capacity)
+def mg_serve_create(plan: Plan, lane_slots=None, queue_capacity=1 << 16) -> Server:
+    return Server(plan, lane_slots, queue_capacity)

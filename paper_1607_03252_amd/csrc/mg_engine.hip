@@ -23,6 +23,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <vector>
@@ -155,6 +156,7 @@ struct Batch {
   void* mem = nullptr;
   size_t bytes = 0;
   std::vector<void*> extra;
+  size_t extra_bytes = 0;  // what the extra allocations hold (256-byte units)
   // a batch built over caller-provided device memory (the allocation-free
   // solve): mem and every later dalloc are carved from it, nothing is freed
   char* arena = nullptr;
@@ -170,6 +172,7 @@ struct Batch {
     void* p = nullptr;
     CK(hipMalloc(&p, bytes));
     extra.push_back(p);
+    extra_bytes += align256(bytes);
     return p;
   }
   hipGraphExec_t tail_graph = nullptr;  // one cycle on L64t
@@ -1544,7 +1547,7 @@ static int spde_fields(mg_plan_s* P, int level, const uint64_t* seeds, int S,
 // small sample never waits for the cycles of larger ones.
 
 struct Lane {
-  int level = 0, first = 0, nslots = 0;
+  int id = -1, level = 0, first = 0, nslots = 0;
   std::unique_ptr<Batch> B;
   hipStream_t st = nullptr;
   std::vector<int> fi, ci;                   // per local slot: fine and coarse solve
@@ -1577,15 +1580,17 @@ struct Lane {
 
 struct mg_server_s {
   mg_plan_s* P = nullptr;
-  std::vector<std::unique_ptr<mg::Lane>> lanes;  // by level (empty pools: null)
+  std::map<int, std::unique_ptr<mg::Lane>> lanes;  // open lanes by scheduler id
   std::unique_ptr<mg::Scheduler> sched;
+  std::vector<int> lane_slots;
+  long long opened = 0, evicted = 0;
   struct Slot {
     bool busy = false;
     long long tag = 0;
     uint64_t seed = 0;
     double t_arrival = 0, t_admit = 0;
   };
-  std::vector<Slot> slot;  // global slot index
+  std::vector<Slot> slot;  // by slot number (grows with the scheduler's slot space)
   int resident = 0;
   long long completed = 0;
   std::deque<mg_result> done;
@@ -1620,7 +1625,41 @@ static size_t sample_bytes(mg_plan_s* P, int level) {
   return b;
 }
 
-static std::unique_ptr<Lane> make_lane(mg_plan_s* P, int level, int first, int nslots) {
+static size_t lane_stage_bytes(int nslots) { return (size_t)nslots * 1536 + 65536; }
+
+// Device bytes of a lane of k slots of `level`: the batch workspace, what
+// upload_lists adds to it (constant right-hand-side planes, descriptor
+// lists; the small-grid chain lists counted for every grid size, so this
+// bounds them), the staging buffer and the normals.
+static size_t lane_bytes(mg_plan_s* P, int level, int k) {
+  const BatchSpec spec = mlmc_spec(P, std::vector<int>(k, level));
+  size_t b = 0;
+  build_batch(P, spec, &b);
+  std::set<int> sizes;
+  size_t grids = 0;
+  const size_t ns = spec.top_n.size();
+  for (int n : spec.top_n) {
+    const auto h = hierarchy(n);
+    grids += h.size();
+    sizes.insert(h.begin(), h.end());
+  }
+  const size_t nm = spec.mixed ? 2 : 1;
+  const size_t desc = std::max(sizeof(GridDesc), sizeof(GridDesc32));
+  const size_t chain = std::max(sizeof(SmallChain<double>), sizeof(SmallChain<float>));
+  b += nm * align256(desc * (grids + ns));
+  for (int n : sizes) {
+    b += align256(sizeof(double) * (size_t)n * n);
+    b += nm * align256(chain * ns);
+    b += 2 * align256(sizeof(double*) * ns);
+    if (spec.mixed) b += 2 * align256(sizeof(double*) * ns);
+  }
+  return b + align256(lane_stage_bytes(k)) + align256(sizeof(double) * 64 * k);
+}
+
+// A lane's workspace, lists and buffers; `bytes` is what the scheduler counts
+// for it, which what it allocates must not exceed.
+static std::unique_ptr<Lane> make_lane(mg_plan_s* P, int level, int first, int nslots,
+                                       size_t bytes) {
   auto ln = std::make_unique<Lane>();
   ln->level = level;
   ln->first = first;
@@ -1641,12 +1680,15 @@ static std::unique_ptr<Lane> make_lane(mg_plan_s* P, int level, int first, int n
   for (size_t ti = 0; ti < B->L64.htop.size(); ++ti)
     for (size_t i = 0; i < B->L64.htop[ti].size(); ++i)
       ln->top_pos[B->L64.htop[ti][i].solve] = {(int)ti, (int)i};
-  ln->stage_bytes = (size_t)nslots * 1536 + 65536;
+  ln->stage_bytes = lane_stage_bytes(nslots);
   CK(hipHostMalloc((void**)&ln->h_stage, ln->stage_bytes, hipHostMallocDefault));
   CK(hipMalloc((void**)&ln->d_stage, ln->stage_bytes));
   CK(hipMalloc((void**)&ln->d_normals, sizeof(double) * 64 * nslots));
   CK(hipHostMalloc((void**)&ln->h_state, sizeof(int) * 4 * B->ns, hipHostMallocDefault));
   CK(hipHostMalloc((void**)&ln->h_q, sizeof(double) * B->ns, hipHostMallocDefault));
+  const size_t got = B->bytes + B->extra_bytes + align256(ln->stage_bytes) +
+                     align256(sizeof(double) * 64 * nslots);
+  if (got > bytes) throw HipError{hipErrorOutOfMemory, "serving lane larger than its stated bytes"};
   // ||b'|| of every solve (constant right-hand side, fixed for the lane's
   // life); the workspace starts zeroed: no solve active, counter 0
   for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
@@ -1769,6 +1811,7 @@ static void lane_launch(mg_plan_s* P, Lane* ln, int c) {
 // Finished samples of a lane whose launch has completed.
 static void lane_harvest(mg_server_s* S, Lane* ln) {
   ln->inflight = false;
+  S->sched->set_inflight(ln->id, false);
   const double t = S->now();
   const int ns = ln->B->ns;
   const int* cyc = ln->h_state + ns;
@@ -1800,29 +1843,45 @@ static void lane_harvest(mg_server_s* S, Lane* ln) {
   }
 }
 
-// Harvest finished lanes, admit into idle lanes and relaunch them.  Waits
-// until at least one lane has finished when nothing else can progress.
+// Harvest finished lanes, admit queued requests (opening and evicting lanes
+// as the scheduler decides), launch every idle lane that holds samples.
+// Waits until at least one lane has finished when nothing else can progress.
 static void serve_step(mg_server_s* S, int c) {
   mg_plan_s* P = S->P;
-  const int L = (int)S->lanes.size();
   bool harvested = false;
   for (;;) {
-    for (auto& ln : S->lanes)
-      if (ln && ln->inflight) {
-        const hipError_t q = hipEventQuery(ln->done);
-        if (q == hipSuccess) {
-          lane_harvest(S, ln.get());
-          harvested = true;
-        } else if (q != hipErrorNotReady) {
-          throw HipError{q, "hipEventQuery"};
-        }
+    for (auto& kv : S->lanes) {
+      Lane* ln = kv.second.get();
+      if (!ln->inflight) continue;
+      const hipError_t q = hipEventQuery(ln->done);
+      if (q == hipSuccess) {
+        lane_harvest(S, ln);
+        harvested = true;
+      } else if (q != hipErrorNotReady) {
+        throw HipError{q, "hipEventQuery"};
       }
-    // admission into idle lanes only (an in-flight lane's staging is busy)
-    std::vector<char> open(L, 0);
-    for (int l = 0; l < L; ++l) open[l] = S->lanes[l] && !S->lanes[l]->inflight;
-    std::vector<Ticket> tk(S->slot.size());
-    tk.resize(S->sched->admit(tk.data(), (int)tk.size(), &open));
-    std::vector<std::vector<Ticket>> per(L);
+    }
+    // admission (the scheduler admits only into lanes not in flight: an
+    // in-flight lane's staging buffer is busy)
+    std::vector<Ticket> tk(std::max(1, S->sched->queued()));
+    tk.resize(S->sched->admit(tk.data(), (int)tk.size()));
+    LaneEvent ev[64];
+    for (int ne; (ne = S->sched->take_events(ev, 64)) > 0;)
+      for (int i = 0; i < ne; ++i) {
+        if (ev[i].kind == LaneEvent::kClose) {
+          S->lanes.erase(ev[i].lane);  // idle and empty; its destructor frees it
+          ++S->evicted;
+          continue;
+        }
+        auto ln = make_lane(P, ev[i].level, ev[i].first, ev[i].nslots, ev[i].bytes);
+        if (!ln) throw HipError{hipErrorOutOfMemory, "serving lane"};
+        ln->id = ev[i].lane;
+        S->lanes.emplace(ev[i].lane, std::move(ln));
+        if ((int)S->slot.size() < ev[i].first + ev[i].nslots)
+          S->slot.resize(ev[i].first + ev[i].nslots);
+        ++S->opened;
+      }
+    std::map<int, std::vector<Ticket>> per;
     const double t = S->now();
     for (const Ticket& x : tk) {
       auto& sl = S->slot[x.slot];
@@ -1832,26 +1891,23 @@ static void serve_step(mg_server_s* S, int c) {
       sl.t_arrival = x.t_arrival;
       sl.t_admit = t;
       ++S->resident;
-      per[x.level].push_back(x);
+      per[x.lane].push_back(x);
     }
-    bool launched = false;
-    for (int l = 0; l < L; ++l) {
-      Lane* ln = S->lanes[l].get();
-      if (!ln || ln->inflight) continue;
-      if (!per[l].empty()) {
-        ln->resident += (int)per[l].size();
-        serve_admit(P, ln, per[l]);
-      }
-      if (ln->resident > 0) {
-        lane_launch(P, ln, c);
-        launched = true;
-      }
+    for (auto& kv : per) {
+      Lane* ln = S->lanes.at(kv.first).get();
+      ln->resident += (int)kv.second.size();
+      serve_admit(P, ln, kv.second);
+    }
+    for (auto& kv : S->lanes) {
+      Lane* ln = kv.second.get();
+      if (ln->inflight || ln->resident == 0) continue;
+      lane_launch(P, ln, c);
+      S->sched->set_inflight(ln->id, true);
     }
     if (harvested || S->resident == 0) return;
-    (void)launched;
     // nothing finished yet: wait for the first lane to finish
     bool any = false;
-    for (auto& ln : S->lanes) any = any || (ln && ln->inflight);
+    for (auto& kv : S->lanes) any = any || kv.second->inflight;
     if (!any) return;
     std::this_thread::yield();
   }
@@ -2517,7 +2573,7 @@ int mg_sample_footprint(mg_plan P, int level, size_t* bytes) {
   API_END(P)
 }
 
-int mg_serve_create(mg_plan P, const int* slots_per_level, int queue_capacity, mg_server* out) {
+int mg_serve_create(mg_plan P, const int* lane_slots, int queue_capacity, mg_server* out) {
   if (!P || !out) return MG_EINVAL;
   *out = nullptr;
   if (queue_capacity < 1) {
@@ -2532,49 +2588,39 @@ int mg_serve_create(mg_plan P, const int* slots_per_level, int queue_capacity, m
   API_BEGIN
   const int L = P->desc.max_level;
   const size_t budget = P->desc.hbm_budget ? P->desc.hbm_budget : ((size_t)8 << 30);
-  std::vector<int> cap(L + 1);
-  size_t need = 0;
-  int total = 0;
+  std::vector<int> k(L + 1);
+  std::vector<size_t> bytes(L + 1, 0);
+  bool any = false;
   for (int l = 0; l <= L; ++l) {
-    const size_t f = sample_bytes(P, l);
-    if (slots_per_level) {
-      cap[l] = slots_per_level[l];
-      if (cap[l] < 0) {
-        P->err = "mg_serve_create: negative slot count";
+    if (lane_slots) {
+      k[l] = lane_slots[l];
+      if (k[l] < 0 || k[l] > Scheduler::kMaxLaneSlots) {
+        P->err = "mg_serve_create: slots per lane outside [0, 4096]";
         return MG_EINVAL;
       }
     } else {
-      const size_t c = budget / (size_t)(L + 1) / f;
-      cap[l] = (int)std::max<size_t>(1, std::min<size_t>(256, c));
+      // at most an eighth of the budget per lane, 1..256 slots
+      const size_t c = budget / 8 / sample_bytes(P, l);
+      k[l] = (int)std::max<size_t>(1, std::min<size_t>(256, c));
+      while (k[l] > 1 && lane_bytes(P, l, k[l]) > budget / 8) --k[l];
     }
-    if (cap[l] > 0) {
-      size_t b = 0;
-      build_batch(P, mlmc_spec(P, std::vector<int>(cap[l], l)), &b);
-      need += b;
+    if (k[l] == 0) continue;
+    bytes[l] = lane_bytes(P, l, k[l]);
+    if (bytes[l] > budget) {
+      P->err = "mg_serve_create: a lane of level " + std::to_string(l) + " (" +
+               std::to_string(bytes[l]) + " bytes) exceeds the HBM budget";
+      return MG_ENOMEM;
     }
-    total += cap[l];
+    any = true;
   }
-  if (total == 0) {
-    P->err = "mg_serve_create: no slots";
+  if (!any) {
+    P->err = "mg_serve_create: no level has slots";
     return MG_EINVAL;
-  }
-  if (need > budget) {
-    P->err = "mg_serve_create: slot pools exceed the HBM budget";
-    return MG_ENOMEM;
   }
   auto S = std::make_unique<mg_server_s>();
   S->P = P;
-  S->sched = std::make_unique<Scheduler>(cap, queue_capacity);
-  S->slot.assign(total, mg_server_s::Slot{});
-  S->lanes.resize(L + 1);
-  for (int l = 0; l <= L; ++l) {
-    if (cap[l] == 0) continue;
-    S->lanes[l] = make_lane(P, l, S->sched->first_slot(l), cap[l]);
-    if (!S->lanes[l]) {
-      P->err = "mg_serve_create: slot pools exceed the HBM budget";
-      return MG_ENOMEM;
-    }
-  }
+  S->lane_slots = k;
+  S->sched = std::make_unique<Scheduler>(k, bytes, budget, queue_capacity);
   S->t0 = std::chrono::steady_clock::now();
   *out = S.release();
   return MG_OK;
@@ -2592,6 +2638,7 @@ int mg_serve_submit(mg_server S, int level, uint64_t seed, long long tag, double
   const int st = S->sched->submit(level, seed, tag, t_arrival < 0 ? S->now() : t_arrival);
   if (st == MG_EINVAL) S->P->err = "mg_serve_submit: level outside [0, max_level]";
   if (st == MG_EBUSY) S->P->err = "mg_serve_submit: queue full";
+  if (st == MG_ENOMEM) S->P->err = "mg_serve_submit: the level is not served (no slots)";
   return st;
 }
 
@@ -2623,7 +2670,19 @@ int mg_serve_counts(mg_server S, int* queued, int* resident, long long* complete
 
 int mg_serve_slots(mg_server S, int level) {
   if (!S || level < 0 || level >= S->sched->levels()) return -1;
-  return S->sched->first_slot(level + 1) - S->sched->first_slot(level);
+  return S->sched->lane_slots(level);
+}
+
+int mg_serve_memory(mg_server S, size_t* used, size_t* peak, size_t* budget, int* lanes,
+                    long long* opened, long long* evicted) {
+  if (!S) return MG_EINVAL;
+  if (used) *used = S->sched->used();
+  if (peak) *peak = S->sched->peak();
+  if (budget) *budget = S->sched->budget();
+  if (lanes) *lanes = (int)S->lanes.size();
+  if (opened) *opened = S->opened;
+  if (evicted) *evicted = S->evicted;
+  return MG_OK;
 }
 
 }  // extern "C"

@@ -222,19 +222,41 @@ def test_batched_uneven_counts_against_oracle(M, torch):
 
 def test_serving_n0_33_equals_alone_and_oracle(M, torch):
     """Requests of levels 0..2 of n0 = 33 (33^3, 65^3 + 33^3, 129^3 + 65^3)
-    through resident slots of a server, admitted while others are mid-solve."""
-    P = M.mg_plan_create(n0=33, max_level=2)
-    S = M.Server(P, [4, 2, 2])
+    through resident slots of a server, admitted while others are mid-solve;
+    again under an HBM budget that holds the level-2 lane beside a level-0
+    lane but not beside a level-1 lane, so lanes are evicted and reopened."""
     reqs = [(l, 500 + 7 * i) for i, l in enumerate([0, 1, 2, 0, 0, 1, 2, 0, 1, 0, 2, 0])]
-    for tag, (lv, sd) in enumerate(reqs):
-        assert S.submit(lv, sd, tag) == M.MG_OK
-    res = {}
-    for _ in range(100000):
-        for r in S.step(1):
-            res[r["tag"]] = r
-        if len(res) == len(reqs):
-            break
-    assert len(res) == len(reqs)
+
+    def serve(S, reqs):
+        for tag, (lv, sd) in enumerate(reqs):
+            assert S.submit(lv, sd, tag) == M.MG_OK
+        res = {}
+        for _ in range(100000):
+            for r in S.step(1):
+                res[r["tag"]] = r
+            if len(res) == len(reqs):
+                break
+        assert len(res) == len(reqs)
+        return res
+
+    def lane_bytes(level):
+        # the bytes a server counts for one lane of `level`
+        Sx = M.Server(M.mg_plan_create(n0=33, max_level=2), [4, 2, 2])
+        serve(Sx, [(level, 1)])
+        return Sx.memory()["used"]
+
+    lb = [lane_bytes(l) for l in range(3)]
+    S = M.Server(M.mg_plan_create(n0=33, max_level=2), [4, 2, 2])
+    res = serve(S, reqs)
+    budget = lb[2] + lb[0] + lb[0] // 2
+    assert budget < lb[2] + lb[1]
+    St = M.Server(M.mg_plan_create(n0=33, max_level=2, hbm_budget=budget), [4, 2, 2])
+    res_t = serve(St, reqs)
+    mem = St.memory()
+    assert mem["peak"] <= budget and mem["evicted"] > 0
+    for tag in res:
+        a, b = res[tag], res_t[tag]
+        assert (a["Y"], a["Qf"], a["Qc"], a["cycles"]) == (b["Y"], b["Qf"], b["Qc"], b["cycles"])
     Pr = M.mg_plan_create(n0=33, max_level=2)
     for tag, (lv, sd) in enumerate(reqs):
         st, Y, Qf, Qc, cyc = batch(M, torch, Pr, lv, [sd])
@@ -250,6 +272,7 @@ def test_serving_n0_33_equals_alone_and_oracle(M, torch):
         assert abs(r["Y"] - o["Y"]) <= 1e-9 * (abs(o["Qf"]) + abs(o["Qc"]))
         assert r["cycles"] == tuple(o["cycles"])
     S.destroy()
+    St.destroy()
 
 
 def test_level_accumulator_fed_device_y(M, torch):

@@ -134,13 +134,64 @@ def test_budget_sizing_and_queue_limit(M, torch):
     S = M.Server(P, None, queue_capacity=3)
     for l in range(4):
         f = M.mg_sample_footprint(P, l)
-        assert f > 0
-        assert S.slots(l) == max(1, min(256, budget // 4 // f))
+        k = S.slots(l)
+        assert f > 0 and 1 <= k <= 256
+        assert k == 1 or (k - 1) * f <= budget // 8
+    assert S.memory()["lanes"] == 0 and S.memory()["used"] == 0  # nothing until requests come
     assert all(S.submit(0, i, i) == M.MG_OK for i in range(3))
     assert S.submit(0, 9, 9) == M.MG_EBUSY
     with pytest.raises(M.MGError):
         S.submit(4, 0, 0)
     while S.counts()[2] < 3:
         S.step()
+    mem = S.memory()
+    assert mem["lanes"] == 1 and 0 < mem["used"] <= budget and mem["budget"] == budget
+    # one lane of a level larger than the budget: refused at creation
     with pytest.raises(M.MGError):
         M.Server(M.mg_plan_create(n0=9, max_level=1, hbm_budget=1 << 20), [64, 64])
+    # a level with no slots is not served
+    S0 = M.Server(M.mg_plan_create(n0=9, max_level=1), [2, 0])
+    with pytest.raises(M.MGError):
+        S0.submit(1, 0, 0)
+
+
+def _lane_bytes(M, n0, L, slots, level):
+    """Bytes the server counts for one lane of `level` (a server that opens
+    only that lane)."""
+    S = M.Server(M.mg_plan_create(n0=n0, max_level=L), slots)
+    S.submit(level, 1, 0)
+    while S.counts()[2] < 1:
+        S.step()
+    return S.memory()["used"]
+
+
+def test_footprint_admission_under_a_tight_budget(M, torch):
+    # the budget holds the level-3 lane and the level-0 lane but not one more
+    # lane beside them: requests of mixed levels force lanes to be evicted and
+    # larger requests to reserve memory; every sample still equals its value
+    # computed alone, and the counted bytes never pass the budget
+    slots = [4, 2, 2, 1]
+    lb = [_lane_bytes(M, 9, 3, slots, l) for l in range(4)]
+    assert lb[0] < lb[1] < lb[2] < lb[3]
+    budget = lb[3] + lb[0] + lb[0] // 2
+    assert budget < lb[3] + lb[1] and budget >= lb[2] + lb[1] + lb[0]
+    P = M.mg_plan_create(n0=9, max_level=3, hbm_budget=budget)
+    S = M.Server(P, slots)
+    reqs = _requests(5, 40)
+    res = _serve_all(S, reqs)
+    assert len(res) == len(reqs)
+    mem = S.memory()
+    assert mem["peak"] <= budget and mem["used"] <= budget
+    assert mem["evicted"] > 0 and mem["opened"] > 4
+    _check_equal_alone(M, torch, M.mg_plan_create(n0=9, max_level=3), reqs, res)
+    # a level-3 request behind many small ones, on a fresh server: the
+    # level-0 lanes hold too much for its lane, so it reserves memory, they
+    # drain and are evicted, and it is served
+    S2 = M.Server(M.mg_plan_create(n0=9, max_level=3, hbm_budget=budget), slots)
+    small = [(0, 9000 + i) for i in range(24)] + [(3, 9100)] + [(0, 9200 + i) for i in range(8)]
+    assert 6 * lb[0] + lb[3] > budget
+    res2 = _serve_all(S2, small)
+    assert len(res2) == len(small)
+    mem = S2.memory()
+    assert mem["peak"] <= budget and mem["evicted"] > 0
+    _check_equal_alone(M, torch, M.mg_plan_create(n0=9, max_level=3), small, res2)
