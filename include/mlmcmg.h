@@ -380,7 +380,10 @@ int mg_serve_submit(mg_server s, int level, uint64_t seed, long long tag, double
  * lane that holds samples, and wait until at least one lane has finished if
  * none had.  Returns the samples that finished (up to max_out per call; the
  * rest come with the next call).  out: host mg_result[max_out]; *n_out: how
- * many were written.  With nothing queued or resident it returns at once. */
+ * many were written.  With nothing queued or resident it returns at once.
+ * MG_EHIP or MG_ENOMEM (a device allocation failed while opening a lane,
+ * e.g. a budget above the device's free memory) leave the server unusable:
+ * later steps return MG_EINVAL; destroy it. */
 int mg_serve_step(mg_server s, int cycles, mg_result* out, int max_out, int* n_out);
 /* Seconds since the server was created (steady clock). */
 double mg_serve_now(mg_server s);

@@ -1584,6 +1584,7 @@ struct mg_server_s {
   std::unique_ptr<mg::Scheduler> sched;
   std::vector<int> lane_slots;
   long long opened = 0, evicted = 0;
+  bool failed = false;  // a step threw: lanes and scheduler may disagree
   struct Slot {
     bool busy = false;
     long long tag = 0;
@@ -2646,8 +2647,19 @@ int mg_serve_step(mg_server S, int cycles, mg_result* out, int max_out, int* n_o
   if (!S || !n_out || cycles < 1 || max_out < 0 || (max_out > 0 && !out)) return MG_EINVAL;
   mg_plan P = S->P;
   *n_out = 0;
+  if (S->failed) {
+    P->err = "mg_serve_step: an earlier step failed; destroy the server";
+    return MG_EINVAL;
+  }
   API_BEGIN
-  if (S->resident > 0 || S->sched->queued() > 0) serve_step(S, cycles);
+  if (S->resident > 0 || S->sched->queued() > 0) {
+    try {
+      serve_step(S, cycles);
+    } catch (...) {
+      S->failed = true;
+      throw;
+    }
+  }
   int n = 0;
   while (n < max_out && !S->done.empty()) {
     out[n++] = S->done.front();
