@@ -152,7 +152,7 @@ def parse_args():
                     help="minimum wall time of the level-pair oracle baseline")
     ap.add_argument("--workload", default="config4",
                     choices=["config4", "levelpair", "single", "mixed", "fp32mix", "serve",
-                             "adaptive"])
+                             "adaptive", "fmg", "fe", "spde"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="precision of the default workload")
     ap.add_argument("--inner-cycles", type=int, default=1,
@@ -200,7 +200,8 @@ def main():
     if args.workload != "config4":
         fn = {"levelpair": bench_levelpair, "single": bench_single, "mixed": bench_mixed,
               "fp32mix": bench_fp32mix, "serve": bench_serve,
-              "adaptive": bench_adaptive}[args.workload]
+              "adaptive": bench_adaptive, "fmg": bench_option, "fe": bench_option,
+              "spde": bench_option}[args.workload]
         out = fn(args, M, torch, np)
         if args.workload == "levelpair" and not args.no_cpu_baseline:
             v, cdt, done = cpu_baseline_pairs(33, 1, threads, args.cpu_seconds)
@@ -265,11 +266,11 @@ def sweep_roofline(M, P, n, samples, cycles_min, kl=True):
     grids in cycles 1..cycles_min of each profiled batch (every solve still
     cycles there, so every launch moves every grid); kl: the sweeps form the
     coefficient themselves (16 instead of 24 bytes per node)."""
-    cyc, kind, ms = M.mg_profile_records(P)
+    cyc, kind, gn, ms = M.mg_profile_records(P)
     nodes = samples * float(n - 2) ** 3
     nc = (n - 1) // 2 + 1
     coarse = samples * float(nc - 2) ** 3
-    sel = cyc <= cycles_min
+    sel = (cyc <= cycles_min) & (gn == n) & (kind <= 3)
     per_kind = {}
     tot_b, tot_ms = 0.0, 0.0
     for k in sorted(set(kind[sel].tolist())):
@@ -493,6 +494,166 @@ def bench_levelpair(args, M, torch, np, steps=None, profile=True):
     if args.calib_copy:
         calib_copy(torch)
     P.destroy()
+    return out
+
+
+# ---- the paper's own choices as plan options (one JSON line each) ---------------------
+
+# algorithmic bytes per node of one sweep of each option's dominant kernel:
+# the finite-element colour passes read u and the three coupling arrays and
+# write u (40); the SPDE box colour passes read z and b and write z (24)
+FE_SWEEP_BYTES_PER_NODE = 40.0
+SPDE_SWEEP_BYTES_PER_NODE = 24.0
+
+OPTION_FORMS = {
+    # workload: (plan options, nu1, nu2, oracle call, description)
+    "fmg": ({"solver": 1, "qoi": 1}, 4, 4,
+            "FMG-2V(4,4) with the point QoI u(1/4,1/4,1/4) (Section 7.1)"),
+    "fe": ({"operator": 1}, 2, 2,
+           "P1 finite elements on Kuhn tetrahedra, V(2,2) to 1e-8 (Section 3.1)"),
+    "spde": ({"field": 1}, 2, 2,
+             "SPDE (Whittle-Matern) field sampler on the box (-1,2)^3, V(2,2) to 1e-8 "
+             "(Section 3.2)"),
+}
+
+
+def cpu_baseline_option(form, n0, level, threads, min_seconds, max_samples=256):
+    """The oracle's step-by-step version of the same option on `threads` host
+    threads, one level-pair sample per thread, in rounds until min_seconds.
+    The oracle's SPDE sample at n0 = 33 takes minutes on one thread, so that
+    form is timed on the same pipeline at n0 = 17 (a level pair with 1/8 of
+    the nodes, box and sample grids alike) and its per-sample time scaled by
+    the node ratio, 8."""
+    import oracle as O
+    scale, n0o = (8.0, (n0 - 1) // 2 + 1) if form == "spde" else (1.0, n0)
+    call = {"fmg": lambda s: O.mlmc_sample_ex(n0o, level, s, solver="fmg", qoi="point", nu1=4,
+                                              nu2=4, fmg_cycles=2),
+            "fe": lambda s: O.mlmc_sample_fe(n0o, level, s),
+            "spde": lambda s: O.mlmc_sample_spde(n0o, level, s)}[form]
+    t1 = time.perf_counter()
+    call(10**6)
+    single = time.perf_counter() - t1
+    print("oracle %s: one sample on one thread %.2f s" % (form, single), file=sys.stderr, flush=True)
+    done, seed = 0, 10**6 + 1
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        while True:
+            list(ex.map(call, range(seed, seed + threads)))
+            seed += threads
+            done += threads
+            dt = time.perf_counter() - t0
+            print("oracle %s: %d samples, %.1f s" % (form, done, dt), file=sys.stderr, flush=True)
+            if dt >= min_seconds or done >= max_samples:
+                break
+    what = ("%d samples of the same level pair and option (seeds 1e6+1..), one per thread, "
+            "%.1f s wall" % (done, dt))
+    if scale != 1.0:
+        what = ("%d SPDE level-pair samples of n0 = %d (box 97^3 + 49^3, grids 33^3 + 17^3; "
+                "seeds 1e6+1..), one per thread, %.1f s wall; rate divided by %g, the node "
+                "ratio to the n0 = 33 workload" % (done, n0o, dt, scale))
+    return {"value": done / dt / scale, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": what, "single_thread_latency_s": single * scale, **host_info()}
+
+
+def bench_option(args, M, torch, np):
+    """One of the paper's own choices (plan options) on the level-pair shape:
+    64 coupled samples of fine 65^3 and coarse 33^3 per step (level 1 of
+    n0 = 33, sigma^2 = 1, lambda = 0.1), seeds 64*s .. 64*s+63 for step s;
+    samples/s, the roofline of the option's dominant sweep on the 65^3 grids
+    (HIP events around every such sweep in profiled eager steps), the FD
+    V(2,2) level pair in the same process, and the oracle beside it."""
+    form = args.workload
+    opts, nu1, nu2, desc = OPTION_FORMS[form]
+    n0, level, S = 33, 1, args.samples
+    nf, nc = (n0 - 1) * 2**level + 1, (n0 - 1) * 2**(level - 1) + 1
+    P = M.mg_plan_create(n0=n0, max_level=level, sigma2=1.0, corr_len=0.1, tol=1e-8,
+                         nu1=nu1, nu2=nu2, max_cycles=50)
+    for name, value in opts.items():
+        M.mg_plan_set_option(P, name, value)
+    Y = torch.zeros(S, dtype=torch.float64, device="cuda")
+    Qf, Qc = torch.zeros_like(Y), torch.zeros_like(Y)
+
+    def step(s, cyc_out):
+        seeds = np.arange(s * S, (s + 1) * S, dtype=np.uint64)
+        st = M.mlmc_sample_batch(P, level, seeds, S, Y, Qf, Qc, cyc_out)
+        assert st == M.MG_OK, st
+
+    cyc_w = torch.zeros(2 * S, dtype=torch.int32, device="cuda")
+    for s in range(args.warmup):
+        step(10**5 + s, cyc_w)
+    steps = args.steps
+    cyc_all = torch.zeros(max(1, steps), 2 * S, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        step(s, cyc_all[s])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cyc_np = cyc_all.cpu().numpy().reshape(max(1, steps), S, 2)
+    value = S * steps / dt
+    out = _line("MLMC samples/sec per level + V-cycle HBM GB/s; p50/p99 solve latency", value,
+                "samples/s", steps, args.warmup, 1e3 * dt / steps,
+                {"workload": "mlmc_level_pair_fine65_coarse33_x64_" + form, "n0": n0,
+                 "level": level, "samples_per_step": S, "sigma2": 1.0, "corr_len": 0.1,
+                 "form": desc, "options": opts, "cycle": "V(%d,%d)" % (nu1, nu2),
+                 "parallelism": "single GPU"})
+    out["per_level"] = {str(level): {"samples_per_s": value,
+                                     "fine_cycles_mean": float(cyc_np[:, :, 0].mean()),
+                                     "coarse_cycles_mean": float(cyc_np[:, :, 1].mean()),
+                                     "batch_latency_ms": 1e3 * dt / steps}}
+    # the dominant sweep: HIP events around every sweep on the 65^3 grids (the
+    # 193^3 box grids for the SPDE sampler) of profiled eager steps, counted
+    # in the cycles in which every solve still cycles
+    M.mg_profile_enable(P, True)
+    cyc_p = torch.zeros(max(1, args.profile_steps), 2 * S, dtype=torch.int32, device="cuda")
+    for s in range(args.profile_steps):
+        step(s, cyc_p[s])
+    torch.cuda.synchronize()
+    cyc_r, kind, gn, ms = M.mg_profile_records(P)
+    M.mg_profile_enable(P, False)
+    if form == "spde":
+        nt = 3 * (nf - 1) + 1
+        sel = (kind == 5) & (gn == nt)
+        # the cycles before each box solve's last one (in the last, solves
+        # that converged earlier may have stopped; cycle numbers restart with
+        # every box solve)
+        idx = np.flatnonzero(sel)
+        runs = np.split(idx, np.flatnonzero(np.diff(cyc_r[idx]) < 0) + 1) if idx.size else []
+        for r in runs:
+            last = cyc_r[r].max()
+            sel[r[cyc_r[r] == last]] = False
+        per_launch = SPDE_SWEEP_BYTES_PER_NODE * S * float(nt) ** 3
+        kname = "k_spde_colour (two colour passes, %d^3 box grids)" % nt
+        bpn = SPDE_SWEEP_BYTES_PER_NODE
+    elif form == "fe":
+        cmin = int(cyc_p.cpu().numpy().reshape(-1, S, 2)[:, :, 0].min())
+        sel = (kind == 4) & (gn == nf) & (cyc_r <= cmin)
+        per_launch = FE_SWEEP_BYTES_PER_NODE * S * float(nf - 2) ** 3
+        kname = "k_fe_colour (two colour passes, %d^3 grids)" % nf
+        bpn = FE_SWEEP_BYTES_PER_NODE
+    else:
+        # the fixed FMG schedule on its last stage: every solve takes every
+        # one of the stage's cycles
+        sel = (kind <= 3) & (gn == nf) & (cyc_r <= 2)
+        per_launch = SWEEP_BYTES_PER_NODE * S * float(nf - 2) ** 3
+        kname = "k_sweep family (fused red-black sweeps, %d^3 grids, last FMG stage)" % nf
+        bpn = SWEEP_BYTES_PER_NODE
+    n_sel = int(sel.sum())
+    avg_ms = float(ms[sel].mean()) if n_sel else float("nan")
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if n_sel else 0.0
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": kname,
+                       "bytes_per_node": bpn, "launches": n_sel, "avg_launch_us": 1e3 * avg_ms,
+                       "bytes_per_launch": per_launch, "profile_steps": args.profile_steps}
+    P.destroy()
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        fd = bench_levelpair(args, M, torch, np, steps=max(3, steps // 2), profile=False)
+        out["extra"] = {"fd_vcycle_level_pair_samples_per_s": fd["value"],
+                        "speed_vs_fd_vcycle": value / fd["value"]}
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline_option(form, n0, level, threads, args.cpu_seconds)
     return out
 
 

@@ -500,19 +500,25 @@ void mlmc_adaptive_desc_default(mlmc_adaptive_desc* d);
 int mlmc_adaptive(mg_plan plan, const mlmc_adaptive_desc* desc, mlmc_adaptive_result* result);
 
 /* Kernel timing: when enabled, the plan records HIP events around every
- * launch of the smoothing kernel on the finest grids of a batch (on the
- * plan's stream).  mg_profile_read returns the number of such launches and
- * their summed duration in milliseconds since the last reset. */
+ * smoothing sweep on the finest grids of a batch (the top grids of each
+ * stage under FMG; both colour passes of a finite-element sweep; both
+ * colour passes of a sweep on the SPDE sampler's finest box grid), on the
+ * plan's stream, and runs its cycles eagerly.  mg_profile_read returns the
+ * number of such launches and their summed duration in milliseconds since
+ * the last reset. */
 int mg_profile_enable(mg_plan plan, int on);
 int mg_profile_read(mg_plan plan, long long* launches, double* total_ms, double* nodes_per_launch);
-/* The timed launches one by one (since the last mg_profile_enable), in launch
- * order: cycle[i] is the V-cycle of its batch it belongs to (1-based; a batch
- * restarts the count), kind[i] the sweep (0 plain, 1 with the coarse-grid
- * correction, 2 with the residual norm of its output's black points, 3 with
- * the residual norm of its input's red points), ms[i] its duration.  Host
+/* The timed sweeps one by one (since the last mg_profile_enable), in launch
+ * order: cycle[i] is the V-cycle of its batch or box solve it belongs to
+ * (1-based; each batch restarts the count), kind[i] the sweep (0 plain,
+ * 1 with the coarse-grid correction, 2 with the residual norm of its
+ * output's black points, 3 with the residual norm of its input's red
+ * points, 4 finite-element colour passes, 5 SPDE box colour passes),
+ * grid_n[i] the vertices per axis of its grids, ms[i] its duration.  Host
  * arrays of max_out entries; *n_out receives the number of records (which
  * may exceed max_out; only max_out are written). */
-int mg_profile_records(mg_plan plan, int max_out, int* cycle, int* kind, double* ms, int* n_out);
+int mg_profile_records(mg_plan plan, int max_out, int* cycle, int* kind, int* grid_n, double* ms,
+                       int* n_out);
 
 const char* mg_last_error(mg_plan plan);
 

@@ -120,7 +120,7 @@ def lib():
         L.mlmc_acc_result.restype = None
         L.mg_profile_enable.argtypes = [vp, C.c_int]
         L.mg_profile_read.argtypes = [vp, C.POINTER(C.c_longlong), dp, dp]
-        L.mg_profile_records.argtypes = [vp, C.c_int, ip, ip, dp, ip]
+        L.mg_profile_records.argtypes = [vp, C.c_int, ip, ip, ip, dp, ip]
         L.mg_plan_set_option.argtypes = [vp, C.c_char_p, C.c_longlong]
         L.mg_set_tile.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.mg_get_tile.argtypes = [vp, C.c_int, ip, ip, ip]
@@ -431,16 +431,17 @@ def mg_profile_read(plan: Plan):
 
 
 def mg_profile_records(plan: Plan):
-    """Per timed launch: (cycle, kind, ms) arrays (see mg_profile_records)."""
+    """Per timed sweep: (cycle, kind, grid_n, ms) arrays (see mg_profile_records)."""
     n = C.c_int()
-    plan.check(lib().mg_profile_records(plan.handle, 0, None, None, None, C.byref(n)))
+    plan.check(lib().mg_profile_records(plan.handle, 0, None, None, None, None, C.byref(n)))
     m = n.value
     cyc, kind = np.zeros(m, dtype=np.int32), np.zeros(m, dtype=np.int32)
-    ms = np.zeros(m)
+    gn, ms = np.zeros(m, dtype=np.int32), np.zeros(m)
     plan.check(lib().mg_profile_records(plan.handle, m, cyc.ctypes.data_as(C.POINTER(C.c_int)),
                                         kind.ctypes.data_as(C.POINTER(C.c_int)),
+                                        gn.ctypes.data_as(C.POINTER(C.c_int)),
                                         ms.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
-    return cyc, kind, ms
+    return cyc, kind, gn, ms
 
 
 # ---- serving -------------------------------------------------------------------

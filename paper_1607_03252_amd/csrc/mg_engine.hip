@@ -153,6 +153,9 @@ struct Batch {
   std::map<int, hipGraphExec_t> graphs;
   int last_cycles = 0;
   bool bnorm_ready = false;  // ||b'|| of every solve computed (constant top rhs)
+  // a fixed schedule whose residuals nobody reads (full multigrid stages):
+  // steps are counted, no residual norm is formed
+  bool count_only = false;
   void* mem = nullptr;
   size_t bytes = 0;
   std::vector<void*> extra;
@@ -259,14 +262,15 @@ struct mg_plan_s {
   long long prof_launches = 0;
   double prof_ms = 0.0;
   double prof_nodes = 0.0;
-  // per timed launch: the cycle of its batch (1-based), its sweep kind and
-  // its duration; ev_meta holds the (cycle, kind) of each pending event pair
+  // per timed launch: the cycle of its batch (1-based), its sweep kind, the
+  // grid size and its duration; ev_meta holds the (cycle, kind, n) of each
+  // pending event pair
   struct ProfRec {
-    int cycle, kind;
+    int cycle, kind, n;
     double ms;
   };
   std::vector<ProfRec> prof_recs;
-  std::vector<std::pair<int, int>> ev_meta;
+  std::vector<ProfRec> ev_meta;
   int prof_cycle = 0;
   // allocation-free solve: this device's static workspace and a small pinned
   // host buffer for the per-solve state read back after each cycle (both
@@ -651,12 +655,22 @@ static void collect_profile(mg_plan_s* P) {
     CK(hipEventElapsedTime(&ms, P->ev_pool[i], P->ev_pool[i + 1]));
     P->prof_ms += ms;
     P->prof_launches += 1;
-    const auto& m = P->ev_meta[i / 2];
-    P->prof_recs.push_back({m.first, m.second, (double)ms});
+    auto m = P->ev_meta[i / 2];
+    m.ms = (double)ms;
+    P->prof_recs.push_back(m);
   }
   P->ev_used = 0;
   P->ev_meta.clear();
 }
+
+// Timed region of one sweep of another operator (kind 4: the finite-element
+// colour passes, 5: the SPDE box colour passes) on the grids of size n.
+static void prof_begin(mg_plan_s* P, int kind, int n, int cycle, hipStream_t st) {
+  if (P->ev_used + 4 > 8192) collect_profile(P);
+  P->ev_meta.push_back({cycle, kind, n, 0.0});
+  CK(hipEventRecord(next_event(P), st));
+}
+static void prof_end(mg_plan_s* P, hipStream_t st) { CK(hipEventRecord(next_event(P), st)); }
 
 // One red-black sweep on the grids of size index si; returns the new buffer.
 template <typename T>
@@ -670,7 +684,7 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
     // kind: 0 plain sweep, 1 with the coarse correction, 2 with the black
     // residuals of its output, 3 with the red residuals of its input
     const int kind = cbuf >= 0 ? 1 : (spart ? (norm == 2 ? 2 : 3) : 0);
-    P->ev_meta.push_back({P->prof_cycle, kind});
+    P->ev_meta.push_back({P->prof_cycle, kind, n, 0.0});
     CK(hipEventRecord(next_event(P), st));
   }
   int out = buf;
@@ -707,7 +721,7 @@ static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr,
                         const Lists<double>* Lp = nullptr) {
   const Lists<double>& L = Lp ? *Lp : B->L64;
   const int n = B->sizes[si];
-  if (B->spec.mixed || B->spec.fe || !P->norm_sweep || P->smoother != 0 || P->desc.nu1 < 1 ||
+  if (B->count_only || B->spec.mixed || B->spec.fe || !P->norm_sweep || P->smoother != 0 || P->desc.nu1 < 1 ||
       P->desc.nu2 < 2 || n < 5)
     return 0;
   if (B->L64.chain_si >= 0 && si >= (size_t)B->L64.chain_si) return 0;  // LDS V-cycle sizes
@@ -738,8 +752,10 @@ static void run_cycle_fe(mg_plan_s* P, Batch* B, Lists<double>& Ls) {
       continue;
     }
     for (int s = 0; s < nu1; ++s) {
+      if (P->prof && si == 0) prof_begin(P, 4, n, P->prof_cycle, st);
       launch_fe_colour(Ls.d[si], cnt, n, B->ss.active, 0, st);
       launch_fe_colour(Ls.d[si], cnt, n, B->ss.active, 1, st);
+      if (P->prof && si == 0) prof_end(P, st);
     }
     launch_fe_residual(Ls.d[si], cnt, n, B->ss.active, st);
     launch_restrict<double>(Ls.d[si], cnt, n, B->ss.active, st);
@@ -749,8 +765,10 @@ static void run_cycle_fe(mg_plan_s* P, Batch* B, Lists<double>& Ls) {
     const int cnt = (int)Ls.h[si].size();
     launch_prolong<double>(Ls.d[si], cnt, n, B->ss.active, 0, 0, st);
     for (int s = 0; s < nu2; ++s) {
+      if (P->prof && si == 0) prof_begin(P, 4, n, P->prof_cycle, st);
       launch_fe_colour(Ls.d[si], cnt, n, B->ss.active, 0, st);
       launch_fe_colour(Ls.d[si], cnt, n, B->ss.active, 1, st);
+      if (P->prof && si == 0) prof_end(P, st);
     }
   }
 }
@@ -860,6 +878,11 @@ static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
     for (size_t ti = 0; ti < B->top_sizes.size(); ++ti) {
       const int n = B->top_sizes[ti], cnt = (int)L.htop[ti].size();
       if (lagged_parts(P, B, size_index(B->sizes, n)) > 0) continue;  // judged in the sweep
+      if (B->count_only) {
+        launch_finalize2(L.dtop[ti], cnt, B->ss, RED_COUNT, 1, 0, fixed, P->desc.max_cycles, tol,
+                         st);
+        continue;
+      }
       launch_reduce(L.dtop[ti], cnt, n, B->ss.active, 0, RED_RESID, B->ss.partials, st);
       launch_finalize2(L.dtop[ti], cnt, B->ss, RED_RESID, 1, 0, fixed,
                        P->desc.max_cycles, tol, st);
@@ -1238,6 +1261,7 @@ static Batch* fmg_stage(mg_plan_s* P, int n, int S) {
     spec.mixed = false;
     auto B = build_batch(P, spec);
     if (!B) return nullptr;
+    B->count_only = true;  // stages run fixed cycles; no residual is reported
     B->nsamples = S;
     B->d_seeds = (uint64_t*)B->dalloc(sizeof(uint64_t) * S);
     B->d_levels = (int*)B->dalloc(sizeof(int) * S);
@@ -1468,8 +1492,10 @@ static bool spde_solve(mg_plan_s* P, SpdeWork* W) {
   for (int c = 1; c <= kSpdeMaxCycles && left > 0; ++c) {
     for (int l = 0; l + 1 < L; ++l) {
       for (int s2 = 0; s2 < 2; ++s2) {
+        if (P->prof && l == 0) prof_begin(P, 5, nt, c, st);
         launch_spde_colour(W->d[l], S, W->nts[l], W->d_active, 0, st);
         launch_spde_colour(W->d[l], S, W->nts[l], W->d_active, 1, st);
+        if (P->prof && l == 0) prof_end(P, st);
       }
       launch_spde_residual(W->d[l], S, W->nts[l], W->d_active, st);
       launch_spde_restrict(W->d[l], S, W->nts[l], W->d_active, false, st);
@@ -1478,8 +1504,10 @@ static bool spde_solve(mg_plan_s* P, SpdeWork* W) {
     for (int l = L - 1; l-- > 0;) {
       launch_spde_prolong(W->d[l], S, W->nts[l], W->d_active, st);
       for (int s2 = 0; s2 < 2; ++s2) {
+        if (P->prof && l == 0) prof_begin(P, 5, nt, c, st);
         launch_spde_colour(W->d[l], S, W->nts[l], W->d_active, 0, st);
         launch_spde_colour(W->d[l], S, W->nts[l], W->d_active, 1, st);
+        if (P->prof && l == 0) prof_end(P, st);
       }
     }
     launch_spde_residual(W->d[0], S, nt, W->d_active, st);
@@ -1539,12 +1567,13 @@ static int spde_fields(mg_plan_s* P, int level, const uint64_t* seeds, int S,
 
 // ---- serving: continuous batching over resident sample slots --------------------
 //
-// One lane per MLMC level: a batch holding that level's slot pool, its own
-// stream, graphs and staging buffers.  Lanes progress independently: a lane
-// whose launch has finished is harvested (finished samples leave, their
-// slots free up), admits queued requests of its level into free slots and is
-// launched again, while the other lanes' work is still on the device.  So a
-// small sample never waits for the cycles of larger ones.
+// A lane is a batch of k sample slots of one MLMC level with its own stream,
+// graphs and staging buffers; the scheduler opens and evicts lanes under the
+// server's HBM budget.  Lanes progress independently: a lane whose launch
+// has finished is harvested (finished samples leave, their slots free up),
+// admits queued requests of its level into free slots and is launched
+// again, while the other lanes' work is still on the device.  So a small
+// sample never waits for the cycles of larger ones.
 
 struct Lane {
   int id = -1, level = 0, first = 0, nslots = 0;
@@ -2551,14 +2580,17 @@ int mg_profile_read(mg_plan P, long long* launches, double* total_ms, double* no
   API_END(P)
 }
 
-int mg_profile_records(mg_plan P, int max_out, int* cycle, int* kind, double* ms, int* n_out) {
-  if (!P || !n_out || max_out < 0 || (max_out > 0 && (!cycle || !kind || !ms))) return MG_EINVAL;
+int mg_profile_records(mg_plan P, int max_out, int* cycle, int* kind, int* grid_n, double* ms,
+                       int* n_out) {
+  if (!P || !n_out || max_out < 0 || (max_out > 0 && (!cycle || !kind || !grid_n || !ms)))
+    return MG_EINVAL;
   API_BEGIN
   collect_profile(P);
   const int n = (int)std::min<size_t>((size_t)max_out, P->prof_recs.size());
   for (int i = 0; i < n; ++i) {
     cycle[i] = P->prof_recs[i].cycle;
     kind[i] = P->prof_recs[i].kind;
+    grid_n[i] = P->prof_recs[i].n;
     ms[i] = P->prof_recs[i].ms;
   }
   *n_out = (int)P->prof_recs.size();

@@ -98,8 +98,16 @@ struct SolveState {
 constexpr int kSweepParts = 1024;
 
 // RED_QOI_PENDING: the QoI of solves that have stopped (active 0) but whose
-// QoI is still pending (qpend 1); it clears qpend.
-enum ReduceMode { RED_BNORM = 0, RED_RESID = 1, RED_QOI = 2, RED_QOI_PENDING = 3, RED_R2 = 4 };
+// QoI is still pending (qpend 1); it clears qpend.  RED_COUNT (finalise
+// only): a fixed schedule's step without a residual, see launch_finalize2.
+enum ReduceMode {
+  RED_BNORM = 0,
+  RED_RESID = 1,
+  RED_QOI = 2,
+  RED_QOI_PENDING = 3,
+  RED_R2 = 4,
+  RED_COUNT = 5
+};
 // QoI kinds (Section 3): the integral of u, u(1/4,1/4,1/4), the flux across x_2 = 1/4
 enum QoiKind { QOI_INTEGRAL = 0, QOI_POINT = 1, QOI_FLUX = 2 };
 
@@ -228,6 +236,8 @@ void launch_correct(const GridDesc* d_list, const GridDesc32* d_list32, int coun
 // reduction's: spart[spoff + q] and
 // spart[spoff + kSweepParts + q] for the counts the sweeps stored at
 // spart[spoff + 2 kSweepParts] and [... + 1] (sweep_parts_red is unused).
+// RED_COUNT credits the step to every active solve and stops it once it has
+// run fixed_cycles, reading no partials (a schedule that needs no residual).
 void launch_finalize2(const GridDesc* d_list, int count, SolveState s, int mode, int step,
                       int lag, int fixed_cycles, int max_cycles, double tol, hipStream_t st,
                       int sweep_parts = 0, int sweep_parts_red = 0);

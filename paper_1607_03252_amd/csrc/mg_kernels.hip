@@ -1870,6 +1870,16 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const GridDesc* __restrict_
                                                      int sweep_parts_red) {
   const GridDesc d = list[blockIdx.x];
   const int sv = d.solve;
+  if (mode == RED_COUNT) {
+    if (threadIdx.x != 0 || !s.active[sv]) return;
+    const int ran = s.ran[sv] + step;
+    s.ran[sv] = ran;
+    if (ran >= fixed_cycles) {
+      s.active[sv] = 0;
+      s.cycles[sv] = ran;
+    }
+    return;
+  }
   if (mode == RED_RESID && !s.active[sv]) return;
   if (mode == RED_QOI_PENDING && (!s.qpend[sv] || s.active[sv])) return;
   const bool sw = mode == RED_RESID && sweep_parts > 0;
@@ -2533,9 +2543,27 @@ __device__ __forceinline__ double spde_coupling(int nt, int i, int j, int k, int
   }
   return (double)w / 6.0;
 }
-// D + kappa^2 h^2 m and S = sum of couplings times neighbour values at p
+// D + kappa^2 h^2 m and S = sum of couplings times neighbour values at p.
+// Off the box's boundary planes every coupling is 1 (4 cells, 6 tetrahedra)
+// and the mass 1, so there D = 6 and S is the plain neighbour sum, formed in
+// the order the general sum takes (a unit-coupling FMA is the addition), so
+// both paths give the same bits.
+__device__ __forceinline__ bool spde_interior(int nt, int i, int j, int k) {
+  return i >= 1 && j >= 1 && k >= 1 && i <= nt - 2 && j <= nt - 2 && k <= nt - 2;
+}
 __device__ __forceinline__ St<double> spde_stencil(const double* z, int nt, int i, int j, int k) {
   const int si = nt * nt, sj = nt, v = (i * nt + j) * nt + k;
+  if (spde_interior(nt, i, j, k)) {
+    St<double> s;
+    s.D = 6.0;
+    double S = z[v - si];
+    S += z[v + si];
+    S += z[v - sj];
+    S += z[v + sj];
+    S += z[v - 1];
+    s.S = S + z[v + 1];
+    return s;
+  }
   const double a0 = i >= 1 ? spde_coupling(nt, i - 1, j, k, 0) : 0.0;
   const double a1 = spde_coupling(nt, i, j, k, 0);
   const double a2 = j >= 1 ? spde_coupling(nt, i, j - 1, k, 1) : 0.0;
@@ -2588,7 +2616,8 @@ __global__ void __launch_bounds__(kBlock) k_spde_colour(const SpdeGrid* __restri
   if (!p.ok || ((p.i + p.j + p.k) & 1) != colour) return;
   const int v = (p.i * nt + p.j) * nt + p.k;
   const St<double> st = spde_stencil(g.z, nt, p.i, p.j, p.k);
-  g.z[v] = (g.b[v] + st.S) / (st.D + g.k2h2 * spde_mass(nt, p.i, p.j, p.k));
+  const double m = spde_interior(nt, p.i, p.j, p.k) ? 1.0 : spde_mass(nt, p.i, p.j, p.k);
+  g.z[v] = (g.b[v] + st.S) / (st.D + g.k2h2 * m);
 }
 
 __global__ void __launch_bounds__(kBlock) k_spde_residual(const SpdeGrid* __restrict__ list,
@@ -2603,7 +2632,8 @@ __global__ void __launch_bounds__(kBlock) k_spde_residual(const SpdeGrid* __rest
   if (!p.ok) return;
   const int v = (p.i * nt + p.j) * nt + p.k;
   const St<double> st = spde_stencil(g.z, nt, p.i, p.j, p.k);
-  const double diag = st.D + g.k2h2 * spde_mass(nt, p.i, p.j, p.k);
+  const double m = spde_interior(nt, p.i, p.j, p.k) ? 1.0 : spde_mass(nt, p.i, p.j, p.k);
+  const double diag = st.D + g.k2h2 * m;
   g.r[v] = g.b[v] - (diag * g.z[v] - st.S);
 }
 
@@ -2643,13 +2673,19 @@ __global__ void __launch_bounds__(kBlock) k_spde_prolong(const SpdeGrid* __restr
   const int nt = g.nt, ntc = (nt - 1) / 2 + 1;
   const Pt p = full_point(nt, blk);
   if (!p.ok) return;
+  // the coarse vertices at the corners of the fine vertex's coarse cell
+  // face (one to eight of them, weight 2^-(odd coordinates) each), summed in
+  // the order a, b, c; the loops are unrolled over the eight corners with
+  // the absent ones skipped, so the sum takes the same operations
+  const int oi = p.i & 1, oj = p.j & 1, ok = p.k & 1;
+  const double w = (oi ? 0.5 : 1.0) * (oj ? 0.5 : 1.0) * (ok ? 0.5 : 1.0);
+  const double* zc = g.zc + ((p.i >> 1) * ntc + (p.j >> 1)) * ntc + (p.k >> 1);
   double sum = 0.0;
-  for (int a = 0; a <= (p.i & 1); ++a)
-    for (int b = 0; b <= (p.j & 1); ++b)
-      for (int c = 0; c <= (p.k & 1); ++c) {
-        const double w = ((p.i & 1) ? 0.5 : 1.0) * ((p.j & 1) ? 0.5 : 1.0) * ((p.k & 1) ? 0.5 : 1.0);
-        sum += w * g.zc[((p.i / 2 + a) * ntc + p.j / 2 + b) * ntc + p.k / 2 + c];
-      }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int a = q >> 2, b = (q >> 1) & 1, c = q & 1;
+    if (a <= oi && b <= oj && c <= ok) sum += w * zc[(a * ntc + b) * ntc + c];
+  }
   g.z[(p.i * nt + p.j) * nt + p.k] += sum;
 }
 
