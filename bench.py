@@ -905,6 +905,12 @@ def bench_serve(args, M, torch, np):
         S.submit(int(lv[i]), 10**6 + i, -1)
     while S.counts()[1] or S.counts()[0]:
         S.step(1)
+
+    def lane_changes(m0, m1):
+        return {"opened": m1["opened"] - m0["opened"], "evicted": m1["evicted"] - m0["evicted"],
+                "seconds": m1["lane_seconds"] - m0["lane_seconds"]}
+
+    mem0 = S.memory()
     res, lat, span = run_server(None)
     mem_sat = S.memory()
     sat = N / span
@@ -924,7 +930,7 @@ def bench_serve(args, M, torch, np):
     out["saturation"] = {"samples_per_s": sat, "p50_ms": 1e3 * _pct(lat, 50),
                          "p99_ms": 1e3 * _pct(lat, 99),
                          "mlmc_estimate": est, "sampling_rms": var_sum ** 0.5,
-                         "memory": mem_sat,
+                         "memory": mem_sat, "lane_changes": lane_changes(mem0, mem_sat),
                          "requests_per_level": [int((lv == l).sum()) for l in range(L + 1)]}
     # the plain path: one plan per level, one sample per call, in arrival order
     fifo_plans = {}
@@ -938,9 +944,11 @@ def bench_serve(args, M, torch, np):
     for rho in loads:
         lam = rho * sat
         arr = np.cumsum(gaps) / lam
+        mem0 = S.memory()
         res, lat, span = run_server(arr)
         rec = {"offered_per_s": lam, "served_per_s": N / span, "p50_ms": 1e3 * _pct(lat, 50),
                "p99_ms": 1e3 * _pct(lat, 99), "memory": S.memory(),
+               "lane_changes": lane_changes(mem0, S.memory()),
                "per_level_p50_p99_ms": {
                    str(l): [1e3 * _pct([x["t_done"] - x["t_arrival"] for x in res if x["level"] == l], q)
                             for q in (50, 99)] for l in range(L + 1)}}

@@ -393,10 +393,10 @@ int mg_serve_slots(mg_server s, int level);
 /* Device bytes of the open lanes (each lane counted at its stated bytes,
  * which bound what it allocates: creating a lane that allocates more fails
  * with MG_EHIP), their maximum so far, the budget, the number of open lanes,
- * and how many lanes were opened and evicted so far.  Any pointer may be
- * NULL. */
+ * how many lanes were opened and evicted so far, and the host seconds spent
+ * opening and evicting them.  Any pointer may be NULL. */
 int mg_serve_memory(mg_server s, size_t* used, size_t* peak, size_t* budget, int* lanes,
-                    long long* opened, long long* evicted);
+                    long long* opened, long long* evicted, double* lane_seconds);
 
 /* Test and parity exports ------------------------------------------------- */
 

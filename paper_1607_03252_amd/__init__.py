@@ -148,7 +148,7 @@ def lib():
         L.mg_serve_slots.argtypes = [vp, C.c_int]
         L.mg_serve_memory.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
                                       C.POINTER(C.c_size_t), ip, C.POINTER(C.c_longlong),
-                                      C.POINTER(C.c_longlong)]
+                                      C.POINTER(C.c_longlong), dp]
         L.mg_last_error.argtypes = [vp]
         L.mg_last_error.restype = C.c_char_p
         _lib = L
@@ -568,13 +568,14 @@ class Server:
         return lib().mg_serve_slots(self.handle, int(level))
 
     def memory(self):
-        """Dict: used, peak and budget bytes, open lanes, lanes opened and evicted."""
+        """Dict: used, peak and budget bytes, open lanes, lanes opened and
+        evicted, host seconds spent opening and evicting lanes."""
         u, p, b = C.c_size_t(), C.c_size_t(), C.c_size_t()
-        n, o, e = C.c_int(), C.c_longlong(), C.c_longlong()
+        n, o, e, t = C.c_int(), C.c_longlong(), C.c_longlong(), C.c_double()
         lib().mg_serve_memory(self.handle, C.byref(u), C.byref(p), C.byref(b), C.byref(n),
-                              C.byref(o), C.byref(e))
+                              C.byref(o), C.byref(e), C.byref(t))
         return {"used": u.value, "peak": p.value, "budget": b.value, "lanes": n.value,
-                "opened": o.value, "evicted": e.value}
+                "opened": o.value, "evicted": e.value, "lane_seconds": t.value}
 
     def destroy(self):
         if getattr(self, "handle", None):

@@ -1613,6 +1613,7 @@ struct mg_server_s {
   std::unique_ptr<mg::Scheduler> sched;
   std::vector<int> lane_slots;
   long long opened = 0, evicted = 0;
+  double lane_seconds = 0.0;  // host time spent opening and evicting lanes
   bool failed = false;  // a step threw: lanes and scheduler may disagree
   struct Slot {
     bool busy = false;
@@ -1896,7 +1897,8 @@ static void serve_step(mg_server_s* S, int c) {
     std::vector<Ticket> tk(std::max(1, S->sched->queued()));
     tk.resize(S->sched->admit(tk.data(), (int)tk.size()));
     LaneEvent ev[64];
-    for (int ne; (ne = S->sched->take_events(ev, 64)) > 0;)
+    for (int ne; (ne = S->sched->take_events(ev, 64)) > 0;) {
+      const double t_ev = S->now();
       for (int i = 0; i < ne; ++i) {
         if (ev[i].kind == LaneEvent::kClose) {
           S->lanes.erase(ev[i].lane);  // idle and empty; its destructor frees it
@@ -1911,6 +1913,8 @@ static void serve_step(mg_server_s* S, int c) {
           S->slot.resize(ev[i].first + ev[i].nslots);
         ++S->opened;
       }
+      S->lane_seconds += S->now() - t_ev;
+    }
     std::map<int, std::vector<Ticket>> per;
     const double t = S->now();
     for (const Ticket& x : tk) {
@@ -2718,7 +2722,7 @@ int mg_serve_slots(mg_server S, int level) {
 }
 
 int mg_serve_memory(mg_server S, size_t* used, size_t* peak, size_t* budget, int* lanes,
-                    long long* opened, long long* evicted) {
+                    long long* opened, long long* evicted, double* lane_seconds) {
   if (!S) return MG_EINVAL;
   if (used) *used = S->sched->used();
   if (peak) *peak = S->sched->peak();
@@ -2726,6 +2730,7 @@ int mg_serve_memory(mg_server S, size_t* used, size_t* peak, size_t* budget, int
   if (lanes) *lanes = (int)S->lanes.size();
   if (opened) *opened = S->opened;
   if (evicted) *evicted = S->evicted;
+  if (lane_seconds) *lane_seconds = S->lane_seconds;
   return MG_OK;
 }
 

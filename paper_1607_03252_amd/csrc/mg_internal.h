@@ -114,6 +114,7 @@ enum QoiKind { QOI_INTEGRAL = 0, QOI_POINT = 1, QOI_FLUX = 2 };
 // Point kernels cover the interior (or, for the "full" kernels, every vertex)
 // with 256-thread blocks of 4 rows (j) x 64 columns (k) of one plane i.
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline long ceil_div_l(long a, long b) { return (a + b - 1) / b; }
 __host__ __device__ inline int point_blocks(int m) { return m * ceil_div(m, 4) * ceil_div(m, 64); }
 // Column-marching kernels (residual, reductions): one 256-thread block per
 // 4 x 64 interior columns; reductions keep one partial per block.

@@ -2604,6 +2604,22 @@ __global__ void __launch_bounds__(kBlock) k_spde_noise(const SpdeGrid* __restric
   }
 }
 
+// The box kernels map threads to flat vertex indices v = (i nt + j) nt + k
+// (consecutive lanes on consecutive addresses, rows and planes run on
+// without gaps).  On a grid with an odd nt, i + j + k and v have the same
+// parity (nt and nt^2 are odd), so the vertices of colour c are exactly
+// v = 2t + c: a colour pass gives every thread one vertex of its colour.
+__device__ __forceinline__ Pt flat_point(int v, int nt) {
+  const int n2 = nt * nt;
+  Pt p;
+  p.i = v / n2;
+  const int r = v - p.i * n2;
+  p.j = r / nt;
+  p.k = r - p.j * nt;
+  p.ok = v < n2 * nt;
+  return p;
+}
+
 __global__ void __launch_bounds__(kBlock) k_spde_colour(const SpdeGrid* __restrict__ list,
                                                         const int* __restrict__ active, int colour,
                                                         int count, int per) {
@@ -2612,7 +2628,9 @@ __global__ void __launch_bounds__(kBlock) k_spde_colour(const SpdeGrid* __restri
   const SpdeGrid g = list[gi];
   if (!active[g.solve]) return;
   const int nt = g.nt;
-  const Pt p = full_point(nt, blk);
+  const int t = blk * kBlock + (int)threadIdx.x;
+  const bool odd = nt & 1;
+  const Pt p = flat_point(odd ? 2 * t + colour : t, nt);
   if (!p.ok || ((p.i + p.j + p.k) & 1) != colour) return;
   const int v = (p.i * nt + p.j) * nt + p.k;
   const St<double> st = spde_stencil(g.z, nt, p.i, p.j, p.k);
@@ -2628,7 +2646,7 @@ __global__ void __launch_bounds__(kBlock) k_spde_residual(const SpdeGrid* __rest
   const SpdeGrid g = list[gi];
   if (!active[g.solve]) return;
   const int nt = g.nt;
-  const Pt p = full_point(nt, blk);
+  const Pt p = flat_point(blk * kBlock + (int)threadIdx.x, nt);
   if (!p.ok) return;
   const int v = (p.i * nt + p.j) * nt + p.k;
   const St<double> st = spde_stencil(g.z, nt, p.i, p.j, p.k);
@@ -2646,7 +2664,7 @@ __global__ void __launch_bounds__(kBlock) k_spde_restrict(const SpdeGrid* __rest
   const SpdeGrid g = list[gi];
   if (!active[g.solve]) return;
   const int nt = g.nt, ntc = (nt - 1) / 2 + 1;
-  const Pt p = full_point(ntc, blk);
+  const Pt p = flat_point(blk * kBlock + (int)threadIdx.x, ntc);
   if (!p.ok) return;
   const double* src = from_b ? g.b : g.r;
   double sum = 0.0;
@@ -2671,7 +2689,7 @@ __global__ void __launch_bounds__(kBlock) k_spde_prolong(const SpdeGrid* __restr
   const SpdeGrid g = list[gi];
   if (!active[g.solve]) return;
   const int nt = g.nt, ntc = (nt - 1) / 2 + 1;
-  const Pt p = full_point(nt, blk);
+  const Pt p = flat_point(blk * kBlock + (int)threadIdx.x, nt);
   if (!p.ok) return;
   // the coarse vertices at the corners of the fine vertex's coarse cell
   // face (one to eight of them, weight 2^-(odd coordinates) each), summed in
@@ -2787,28 +2805,30 @@ void launch_spde_noise(const SpdeGrid* d_list, int count, int nt, const uint64_t
 void launch_spde_colour(const SpdeGrid* d_list, int count, int nt, const int* d_active, int colour,
                         hipStream_t st) {
   if (count <= 0) return;
-  const int per = point_blocks(nt);
+  const long N = (long)nt * nt * nt;
+  const int per = (int)ceil_div_l((nt & 1) ? (N + 1) / 2 : N, kBlock);
   hipLaunchKernelGGL(k_spde_colour, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
                      colour, count, per);
 }
 void launch_spde_residual(const SpdeGrid* d_list, int count, int nt, const int* d_active,
                           hipStream_t st) {
   if (count <= 0) return;
-  const int per = point_blocks(nt);
+  const int per = (int)ceil_div_l((long)nt * nt * nt, kBlock);
   hipLaunchKernelGGL(k_spde_residual, xcd_grid(count, per), dim3(kBlock), 0, st, d_list,
                      d_active, count, per);
 }
 void launch_spde_restrict(const SpdeGrid* d_list, int count, int nt, const int* d_active,
                           bool from_b, hipStream_t st) {
   if (count <= 0) return;
-  const int per = point_blocks((nt - 1) / 2 + 1);
+  const long ntc = (nt - 1) / 2 + 1;
+  const int per = (int)ceil_div_l(ntc * ntc * ntc, kBlock);
   hipLaunchKernelGGL(k_spde_restrict, xcd_grid(count, per), dim3(kBlock), 0, st, d_list,
                      d_active, from_b ? 1 : 0, count, per);
 }
 void launch_spde_prolong(const SpdeGrid* d_list, int count, int nt, const int* d_active,
                          hipStream_t st) {
   if (count <= 0) return;
-  const int per = point_blocks(nt);
+  const int per = (int)ceil_div_l((long)nt * nt * nt, kBlock);
   hipLaunchKernelGGL(k_spde_prolong, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
                      count, per);
 }
