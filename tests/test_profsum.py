@@ -38,14 +38,18 @@ def test_hash_covers_only_the_sweep_section(tmp_path):
     assert profsum.source_hash(str(p)) == h1
 
 
-def test_committed_traffic_summary_is_readable():
+@pytest.mark.parametrize("name", ["k_sweep_config4_257x16.txt", "k_sweep_levelpair65_33x64.txt"])
+def test_committed_traffic_summary_is_readable(name):
+    # the summaries bench.py reads its roofline traffic from: counter bytes
+    # per launch, the copy calibration, and the hash of the sweep source they
+    # were taken on (equal to the current source's, or bench.py reports no
+    # traffic)
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
-                        "k_sweep_traffic_levelpair65_33x64.txt")
-    if not os.path.exists(path):
-        pytest.skip("no traffic summary committed")
+                        name)
     rec = profsum.read_summary(path)
     assert rec["hbm_bytes_per_launch"] > 0
     assert len(rec["kernel_source_sha256"]) == 64
+    assert rec["kernel_source_sha256"] == profsum.source_hash()
     assert rec["fetch_scale"] > 0 and rec["write_scale"] > 0
     json.dumps(rec)
 
