@@ -429,3 +429,69 @@ def test_work_conserving_with_room():
                 assert s.release(sl) == M.MG_OK
                 busy.remove(sl)
     assert s.events()[0][0] == OPEN
+
+
+# ---- property test: arbitrary operation sequences against the model -----------
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+
+@st.composite
+def _scenario(draw):
+    levels = draw(st.integers(1, 4))
+    slots = [draw(st.integers(0, 4)) for _ in range(levels)]
+    nbytes = [draw(st.integers(1, 60)) for _ in range(levels)]
+    budget = draw(st.integers(1, 150))
+    cap = draw(st.integers(1, 12))
+    ops = draw(st.lists(st.tuples(st.integers(0, 4), st.integers(0, 9), st.integers(0, 9)),
+                        min_size=1, max_size=80))
+    return slots, nbytes, budget, cap, ops
+
+
+@settings(max_examples=300, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(_scenario())
+def test_random_operations_match_the_model(sc):
+    slots, nbytes, budget, cap, ops = sc
+    s, m = M.Sched(slots, nbytes, budget, cap), Model(slots, nbytes, budget, cap)
+    busy, tag = [], 0
+    for op, a, b in ops:
+        if op == 0:    # submit (level a mod levels + 1 probes the bad-level error)
+            lv = a % (len(slots) + 1)
+            assert s.submit(lv, a, tag, 0.0) == m.submit(lv, a, tag, 0.0)
+            tag += 1
+        elif op == 1:  # admit
+            got = s.admit(b)
+            assert got == m.admit(b)
+            busy += [t[3] for t in got]
+        elif op == 2 and busy:  # release one busy slot
+            sl = busy.pop(a % len(busy))
+            assert s.release(sl) == M.MG_OK and m.release(sl) == M.MG_OK
+        elif op == 3:  # toggle a lane in flight (only lanes the model knows)
+            ids = sorted(m.lanes)
+            if ids:
+                lid = ids[a % len(ids)]
+                flag = b & 1
+                assert s.set_inflight(lid, flag) == m.set_inflight(lid, flag) == M.MG_OK
+        else:          # release a slot that is not busy: refused by both
+            free = [q for q in range(len(m.slot_busy)) if not m.slot_busy[q]]
+            if free:
+                sl = free[a % len(free)]
+                assert s.release(sl) == m.release(sl) == M.MG_EINVAL
+        assert s.events() == m.take_events()
+        used, peak, lanes = s.memory()
+        assert used == m.used <= budget and peak <= budget and lanes == len(m.lanes)
+        assert s.counts() == (len(m.q), sum(m.slot_busy))
+    # liveness: with every lane idle and every admitted sample finishing at
+    # once, each round admits at least one request (a drain takes one round
+    # to empty its lanes), so the queue empties within twice its length
+    for lid in list(m.lanes):
+        s.set_inflight(lid, 0)
+    queued = s.counts()[0]
+    for _ in range(2 * queued + 2):
+        if s.counts()[0] == 0:
+            break
+        busy += [t[3] for t in s.admit(1000)]
+        s.events()
+        for sl in busy:
+            assert s.release(sl) == M.MG_OK
+        busy = []
+    assert s.counts()[0] == 0
