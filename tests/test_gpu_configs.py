@@ -275,6 +275,55 @@ def test_serving_n0_33_equals_alone_and_oracle(M, torch):
     St.destroy()
 
 
+def test_serving_config5_levels_0_to_3_under_a_tight_budget(M, torch):
+    """Config 5's level range (n0 = 33: 33^3 up to 257^3 + 129^3) through a
+    server whose HBM budget holds the level-3 lane beside one level-0 lane
+    and nothing else, with a mix of levels in the 4^-l proportions: lanes are
+    evicted and reopened, and every served sample equals the same sample
+    computed alone, bit for bit (Y, Q_f, Q_c and both cycle counts)."""
+    slots = [8, 4, 2, 1]
+
+    def serve(S, reqs):
+        for tag, (lv, sd) in enumerate(reqs):
+            assert S.submit(lv, sd, tag) == M.MG_OK
+        res = {}
+        for _ in range(100000):
+            for r in S.step(1):
+                res[r["tag"]] = r
+            if len(res) == len(reqs):
+                break
+        assert len(res) == len(reqs)
+        return res
+
+    def lane_bytes(level):
+        Sx = M.Server(M.mg_plan_create(n0=33, max_level=3), slots)
+        serve(Sx, [(level, 1)])
+        b = Sx.memory()["used"]
+        Sx.destroy()
+        return b
+
+    lb = [lane_bytes(l) for l in range(4)]
+    budget = lb[3] + lb[0] + lb[0] // 2
+    assert budget < lb[3] + lb[1]
+    rng = np.random.default_rng(55)
+    p = np.array([4.0 ** -l for l in range(4)])
+    lv = list(rng.choice(4, size=22, p=p / p.sum()))
+    lv[5], lv[14] = 3, 3  # two level-3 requests among the small ones
+    reqs = [(int(l), 900 + 11 * i) for i, l in enumerate(lv)]
+    S = M.Server(M.mg_plan_create(n0=33, max_level=3, hbm_budget=budget), slots)
+    res = serve(S, reqs)
+    mem = S.memory()
+    assert mem["peak"] <= budget and mem["evicted"] > 0
+    Pr = M.mg_plan_create(n0=33, max_level=3)
+    for tag, (l, sd) in enumerate(reqs):
+        st, Y, Qf, Qc, cyc = batch(M, torch, Pr, l, [sd])
+        r = res[tag]
+        assert r["status"] == M.MG_OK
+        assert (r["Y"], r["Qf"], r["Qc"]) == (Y[0], Qf[0], Qc[0]), (tag, l)
+        assert r["cycles"] == tuple(int(c) for c in cyc[0])
+    S.destroy()
+
+
 def test_level_accumulator_fed_device_y(M, torch):
     """Section 2.3: the level mean and s^2 (divisor N) from a batch's device Y
     (mlmc_acc_add reading device memory) against the oracle's accumulator
