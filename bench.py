@@ -336,10 +336,15 @@ def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profil
     cyc_all = torch.zeros(max(1, steps), 2 * S, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    t_step = []
     for s in range(steps):
+        # (a batch call returns once its solves have finished: the time
+        # between returns is that batch's solve latency)
         step(s, cyc_all[s])
+        t_step.append(time.perf_counter())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    lat_ms = 1e3 * np.diff(np.asarray([t0] + t_step))
     cyc_np = cyc_all.cpu().numpy().reshape(max(1, steps), S, 2)[:, :, 0]
     cyc_mean = float(cyc_np.mean())
     value = S * steps / dt
@@ -362,7 +367,9 @@ def bench_config4(args, M, torch, np, precision, steps=None, warmup=None, profil
                    "tiles": {str(n): tiles[0]}, "tiles_pro": {str(n): tiles[1]},
                    "options": dict(o.split("=") for o in args.opt)},
         "per_level": {"0": {"samples_per_s": value, "fine_cycles_mean": cyc_mean,
-                            "effective_vcycle_GBps": eff, "batch_latency_ms": ms_step}},
+                            "effective_vcycle_GBps": eff, "batch_latency_ms": ms_step,
+                            "batch_latency_p50_ms": _pct(lat_ms, 50),
+                            "batch_latency_p99_ms": _pct(lat_ms, 99)}},
     }
     # the QoI of step 0's seeds (an untimed step), for the mixed vs FP64 comparison
     step(0, cyc_w)
@@ -450,10 +457,13 @@ def bench_levelpair(args, M, torch, np, steps=None, profile=True):
     cyc_all = torch.zeros(max(1, steps), 2 * S, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    t_step = []
     for s in range(steps):
-        step(s, cyc_all[s])
+        step(s, cyc_all[s])  # (returns once the batch has finished)
+        t_step.append(time.perf_counter())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    lat_ms = 1e3 * np.diff(np.asarray([t0] + t_step))
     cyc_np = cyc_all.cpu().numpy().reshape(max(1, steps), S, 2)
     cyc_mean = float(cyc_np[:, :, 0].mean())
     value = S * steps / dt
@@ -470,7 +480,9 @@ def bench_levelpair(args, M, torch, np, steps=None, profile=True):
                  "tiles_pro": {str(k): list(v) for k, v in tiles_pro.items()},
                  "options": dict(o.split("=") for o in args.opt)})
     out["per_level"] = {str(level): {"samples_per_s": value, "fine_cycles_mean": cyc_mean,
-                                     "effective_vcycle_GBps": eff, "batch_latency_ms": ms_step}}
+                                     "effective_vcycle_GBps": eff, "batch_latency_ms": ms_step,
+                                     "batch_latency_p50_ms": _pct(lat_ms, 50),
+                                     "batch_latency_p99_ms": _pct(lat_ms, 99)}}
     if profile:
         M.mg_profile_enable(P, True)
         cyc_p = torch.zeros(max(1, args.profile_steps), 2 * S, dtype=torch.int32, device="cuda")
