@@ -167,11 +167,7 @@ int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, in
  *               red points in the next cycle's first) and the solve is judged
  *               after that first sweep; 0 = a residual pass after each cycle
  *               (same stopping cycle and results; the reported relative
- *               residual differs by summation order only);
- *   "tail":     1 (default) = once at most a quarter of a batch's solves
- *               still cycle, the remaining cycles run on those solves' grids
- *               only (more plane pieces per grid); 0 = always on the whole
- *               batch (same results, bit for bit).
+ *               residual differs by summation order only).
  * Options that change what the samples compute (mlmc_sample_batch and
  * mlmc_sample_mixed; the server supports only the defaults):
  *   "qoi":      0 (default) = Q = integral of u over D; 1 = u at

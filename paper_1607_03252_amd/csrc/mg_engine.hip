@@ -116,9 +116,6 @@ struct Batch {
   std::vector<int> top_sizes;                      // distinct top sizes, descending
   Lists<double> L64;
   Lists<float> L32;
-  // the grids of the solves still cycling, for the last cycles of a batch
-  // (device buffers sized for L64 on first use)
-  Lists<double> L64t;
   SolveState ss{};
   int* h_state = nullptr;  // pinned: active then cycles of every solve (2 ns)
   // MLMC sample plumbing
@@ -178,7 +175,6 @@ struct Batch {
     extra_bytes += align256(bytes);
     return p;
   }
-  hipGraphExec_t tail_graph = nullptr;  // one cycle on L64t
   // full multigrid stage: the top descriptors with uc = the previous stage's
   // top iterates (link_src: that stage's batch)
   GridDesc* d_link = nullptr;
@@ -186,8 +182,6 @@ struct Batch {
   void drop_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
-    if (tail_graph) (void)hipGraphExecDestroy(tail_graph);
-    tail_graph = nullptr;
   }
   ~Batch() {
     drop_graphs();
@@ -237,7 +231,6 @@ struct mg_plan_s {
   int use_graph = 1;     // capture cycles into HIP graphs (mlmc_sample_batch)
   int small_ns = 17;     // grids of this size and below: the LDS V-cycle (0: off)
   int transfer = 0;      // 0: fused residual + restriction, 1: separate kernels
-  int tail_lists = 1;    // 1: a batch's last cycles run on its unfinished solves only
   int norm_sweep = 1;    // 1: a cycle's first sweep also takes the residual norm of
                          // the previous iterate (convergence judged one cycle late)
   int qoi_kind = QOI_INTEGRAL;  // the samples' QoI (Section 3)
@@ -851,11 +844,9 @@ static int run_cycle(mg_plan_s* P, Batch* B, Lists<T>& Ls, bool norms = false, d
 }
 
 // One outer iteration for every active solve (recorded into graphs as is).
-// Lp: the lists to cycle (default: all grids of the batch).
-static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed,
-                       Lists<double>* Lp = nullptr) {
+static void cycle_step(mg_plan_s* P, Batch* B, double tol, int fixed) {
   hipStream_t st = B->st;
-  Lists<double>& L = Lp ? *Lp : B->L64;
+  Lists<double>& L = B->L64;
   if (P->prof) ++P->prof_cycle;  // (eager while profiling: one call per cycle)
   // V-cycles per step, credited to each active solve by its judgement: a
   // mixed-precision step applies inner_cycles
@@ -926,40 +917,6 @@ static hipGraphExec_t graph_for(mg_plan_s* P, Batch* B, int c, double tol, int f
   return ex;
 }
 
-// The tail of a batch: at most tail_cap(B) solves still cycle.
-static int tail_cap(const Batch* B) { return std::max(1, B->ns / 4); }
-
-// B->L64t := per list, the grids of the solves with act[solve] != 0, padded
-// with grids of stopped solves (their kernels exit at once) to a fixed
-// length (min(list length, tail_cap)), so that one graph serves every tail.
-static void build_tail_lists(Batch* B, const int* act) {
-  Lists<double>& T = B->L64t;
-  const Lists<double>& F = B->L64;
-  const size_t cap = (size_t)tail_cap(B);
-  auto fill = [&](auto& out, const auto& full, auto solve_of) {
-    const size_t len = std::min(full.size(), cap);
-    out.clear();
-    for (const auto& x : full)
-      if (act[solve_of(x)] && out.size() < len) out.push_back(x);
-    for (const auto& x : full)
-      if (!act[solve_of(x)] && out.size() < len) out.push_back(x);
-  };
-  auto grid_solve = [](const GridDesc& d) { return d.solve; };
-  auto chain_solve = [](const SmallChain<double>& c) { return c.lv[0].solve; };
-  const bool first = T.d.empty();
-  if (first) {
-    T.h.assign(F.h.size(), {});
-    T.htop.assign(F.htop.size(), {});
-    T.chain_si = F.chain_si;
-    T.chains.clear();
-    for (const auto& g : F.chains) T.chains.push_back({g.ns, {}, nullptr});
-  }
-  for (size_t si = 0; si < F.h.size(); ++si) fill(T.h[si], F.h[si], grid_solve);
-  for (size_t ti = 0; ti < F.htop.size(); ++ti) fill(T.htop[ti], F.htop[ti], grid_solve);
-  for (size_t g = 0; g < F.chains.size(); ++g) fill(T.chains[g].h, F.chains[g].h, chain_solve);
-  upload(B, T, B->st);  // (device arrays sized by the first call: the fixed lengths)
-}
-
 // Cycle every solve of the batch until each has converged (or run exactly
 // fixed_cycles).  Returns true when every solve met tol.
 // post: enqueued after every launch of cycles, before the host waits (work
@@ -990,31 +947,11 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
   const int per_step = B->spec.mixed ? P->inner_cycles : 1;
   const int limit = ceil_div(fixed > 0 ? fixed : P->desc.max_cycles, per_step) + extra;
   const bool use_graphs = graphs && P->use_graph && !P->prof;
-  // the last cycles of a batch, once at most a quarter of the solves still
-  // cycle, run on lists of those solves' grids only: the sweeps then split
-  // the plane march of the few remaining grids over more workgroups
-  const bool tail_ok = !B->spec.mixed && !P->prof && P->tail_lists && B->ns >= 4;
-  bool in_tail = false;
-  const int* act = B->h_state;
   const int* cyc = B->h_state + B->ns;
   int done = 0, maxc = 0, left = B->ns;
   while (done < limit) {
     int c = 1;
-    if (in_tail) {
-      if (use_graphs) {
-        if (!B->tail_graph) {
-          hipGraph_t g = nullptr;
-          CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-          cycle_step(P, B, tol, fixed, &B->L64t);
-          CK(hipStreamEndCapture(st, &g));
-          CK(hipGraphInstantiate(&B->tail_graph, g, nullptr, nullptr, 0));
-          CK(hipGraphDestroy(g));
-        }
-        CK(hipGraphLaunch(B->tail_graph, st));
-      } else {
-        cycle_step(P, B, tol, fixed, &B->L64t);
-      }
-    } else if (use_graphs) {
+    if (use_graphs) {
       // the first launch covers the steps the last batch needed (a step in
       // which every solve has stopped costs only launches that exit at once;
       // a missing one costs a round trip to the host)
@@ -1033,10 +970,6 @@ static bool run_solves(mg_plan_s* P, Batch* B, double tol, int fixed, bool graph
     left = 0;
     for (int q = 0; q < B->ns; ++q) left += B->h_state[q] != 0;
     if (left == 0) break;
-    if (tail_ok && left <= tail_cap(B) && !in_tail) {
-      build_tail_lists(B, act);
-      in_tail = true;
-    }
   }
   bool ok = left == 0;
   for (int q = 0; q < B->ns; ++q) {
@@ -2141,9 +2074,6 @@ int mg_plan_set_option(mg_plan P, const char* name, long long value) {
   } else if (k == "transfer") {
     if (value != 0 && value != 1) return MG_EINVAL;
     P->transfer = (int)value;
-  } else if (k == "tail") {
-    if (value != 0 && value != 1) return MG_EINVAL;
-    P->tail_lists = (int)value;
   } else if (k == "norm") {
     if (value != 0 && value != 1) return MG_EINVAL;
     P->norm_sweep = (int)value;

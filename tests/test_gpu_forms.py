@@ -111,24 +111,6 @@ def test_norm_in_sweeps_matches_separate_reduction(M, torch, n0, level, fixed):
     assert _same(out[0], out[1])
 
 
-@pytest.mark.parametrize("n0,level,graph", [(33, 1, 1), (17, 2, 1), (17, 2, 0)])
-def test_tail_lists_match_full_lists(M, torch, n0, level, graph):
-    # the last cycles of a batch on lists of the unfinished solves only (more
-    # plane pieces per grid): same arithmetic, so the same results bit for bit
-    seeds = list(range(100, 116))
-    out = {}
-    for tl in (0, 1):
-        P = M.mg_plan_create(n0=n0, max_level=level)
-        M.mg_plan_set_option(P, "graph", graph)
-        M.mg_plan_set_option(P, "tail", tl)
-        out[tl] = _batch(M, torch, P, level, seeds)
-        out[tl] = _batch(M, torch, P, level, seeds)  # second batch: graphs replayed
-        assert out[tl][0] == M.MG_OK
-    assert _same(out[0], out[1])
-    cyc = out[1][4]
-    assert cyc.max() > cyc.min()  # the batch has a tail
-
-
 def test_norm_in_sweeps_single_solve_relres(M, torch):
     # mg_solve: same cycles and iterate; the relative residual differs only by
     # the summation order of the squared residuals
