@@ -2432,6 +2432,25 @@ __device__ __forceinline__ St<double> fe_stencil_at(const double* fc, const doub
                                u[v - 1], u[v + 1]);
 }
 
+// Point kernels over flat vertex indices v = (i n + j) n + k: consecutive
+// lanes on consecutive addresses, rows and planes run on without gaps.  On a
+// grid with an odd n, i + j + k and v have the same parity (n and n^2 are
+// odd), so the vertices of colour c are exactly v = 2t + c: a colour pass
+// gives every thread one vertex of its colour.
+__device__ __forceinline__ Pt flat_point(int v, int nt) {
+  const int n2 = nt * nt;
+  Pt p;
+  p.i = v / n2;
+  const int r = v - p.i * n2;
+  p.j = r / nt;
+  p.k = r - p.j * nt;
+  p.ok = v < n2 * nt;
+  return p;
+}
+__device__ __forceinline__ bool interior(int n, const Pt& p) {
+  return p.i >= 1 && p.j >= 1 && p.k >= 1 && p.i <= n - 2 && p.j <= n - 2 && p.k <= n - 2;
+}
+
 __global__ void __launch_bounds__(kBlock) k_fe_colour(const GridDesc* __restrict__ list,
                                                       const int* __restrict__ active, int colour,
                                                       int count, int per) {
@@ -2440,8 +2459,9 @@ __global__ void __launch_bounds__(kBlock) k_fe_colour(const GridDesc* __restrict
   const GridDesc d = list[gi];
   if (!active[d.solve]) return;
   const int n = d.n;
-  const Pt p = interior_point(n - 2, blk);
-  if (!p.ok || ((p.i + p.j + p.k) & 1) != colour) return;
+  const int t = blk * kBlock + (int)threadIdx.x;
+  const Pt p = flat_point((n & 1) ? 2 * t + colour : t, n);
+  if (!p.ok || !interior(n, p) || ((p.i + p.j + p.k) & 1) != colour) return;
   const int v = vidx(n, p.i, p.j, p.k);
   double* u = d.u[0];
   const St<double> st = fe_stencil_at(d.fc, u, v, n, (size_t)n * n * n);
@@ -2456,8 +2476,8 @@ __global__ void __launch_bounds__(kBlock) k_fe_residual(const GridDesc* __restri
   const GridDesc d = list[gi];
   if (!active[d.solve]) return;
   const int n = d.n;
-  const Pt p = interior_point(n - 2, blk);
-  if (!p.ok) return;
+  const Pt p = flat_point(blk * kBlock + (int)threadIdx.x, n);
+  if (!p.ok || !interior(n, p)) return;
   const int v = vidx(n, p.i, p.j, p.k);
   const St<double> st = fe_stencil_at(d.fc, d.u[0], v, n, (size_t)n * n * n);
   d.r[v] = res_value<double>(st, b_at<double>(d, p.i, p.j, p.k), d.u[0][v]);
@@ -2485,7 +2505,8 @@ void launch_fe_faces(int n, int count, const double* const* d_wh, double* const*
 void launch_fe_colour(const GridDesc* d_list, int count, int n, const int* d_active, int colour,
                       hipStream_t st) {
   if (count <= 0) return;
-  const int per = point_blocks(n - 2);
+  const long N = (long)n * n * n;
+  const int per = (int)ceil_div_l((n & 1) ? (N + 1) / 2 : N, kBlock);
   hipLaunchKernelGGL(k_fe_colour, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
                      colour, count, per);
 }
@@ -2493,7 +2514,7 @@ void launch_fe_colour(const GridDesc* d_list, int count, int n, const int* d_act
 void launch_fe_residual(const GridDesc* d_list, int count, int n, const int* d_active,
                         hipStream_t st) {
   if (count <= 0) return;
-  const int per = point_blocks(n - 2);
+  const int per = (int)ceil_div_l((long)n * n * n, kBlock);
   hipLaunchKernelGGL(k_fe_residual, xcd_grid(count, per), dim3(kBlock), 0, st, d_list, d_active,
                      count, per);
 }
@@ -2604,22 +2625,7 @@ __global__ void __launch_bounds__(kBlock) k_spde_noise(const SpdeGrid* __restric
   }
 }
 
-// The box kernels map threads to flat vertex indices v = (i nt + j) nt + k
-// (consecutive lanes on consecutive addresses, rows and planes run on
-// without gaps).  On a grid with an odd nt, i + j + k and v have the same
-// parity (nt and nt^2 are odd), so the vertices of colour c are exactly
-// v = 2t + c: a colour pass gives every thread one vertex of its colour.
-__device__ __forceinline__ Pt flat_point(int v, int nt) {
-  const int n2 = nt * nt;
-  Pt p;
-  p.i = v / n2;
-  const int r = v - p.i * n2;
-  p.j = r / nt;
-  p.k = r - p.j * nt;
-  p.ok = v < n2 * nt;
-  return p;
-}
-
+// (the box kernels map threads by flat_point, as the finite-element passes)
 __global__ void __launch_bounds__(kBlock) k_spde_colour(const SpdeGrid* __restrict__ list,
                                                         const int* __restrict__ active, int colour,
                                                         int count, int per) {
