@@ -678,6 +678,13 @@ def _line(metric, value, unit, steps, warmup, ms_step, config, higher=True, dtyp
             "data": "synthetic (Philox-seeded 64-term KL lognormal fields)", "config": config}
 
 
+def _apply_opts(M, P, args):
+    """The --opt name=value plan options."""
+    for spec in args.opt:
+        name, value = spec.split("=")
+        M.mg_plan_set_option(P, name, int(value))
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x), q)) if len(x) else None
@@ -747,6 +754,7 @@ def bench_mixed(args, M, torch, np):
         s += c
     n = len(levels)
     P = M.mg_plan_create(n0=17, max_level=3)
+    _apply_opts(M, P, args)
     Y, Qf, Qc, cyc = _samples(M, torch, P, 0, seeds)
     sd = np.asarray(seeds, dtype=np.uint64)
     for _ in range(max(1, args.warmup)):
@@ -855,6 +863,7 @@ def bench_adaptive(args, M, torch, np):
     lambda = 0.1, theta = 1/2, alpha = 2/3, N_Init = 32; wall time from eps to
     the estimate, with the number of samples and V-cycles it took."""
     P = M.mg_plan_create(n0=17, max_level=4, sigma2=1.0, corr_len=0.1)
+    _apply_opts(M, P, args)
     M.mlmc_adaptive(P, eps=4 * args.eps, n_init=8, seed0=10**6)  # warm-up: workspaces, graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
