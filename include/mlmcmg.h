@@ -101,7 +101,8 @@ int mg_plan_set_stream(mg_plan plan, void* stream);
  * (tol <= 0: the plan's tol), or, when fixed_cycles > 0, exactly fixed_cycles
  * cycles.  cycles/relres (host, may be NULL) receive the cycle count and the
  * last relative residual.  MG_ENOCONV if max_cycles passed without reaching
- * tol (u then holds the last iterate). */
+ * tol (u then holds the last iterate); MG_EINVAL for n not of the form
+ * 2^m + 1 with 3 <= n <= 1025, a NULL k, f or u, or fixed_cycles < 0. */
 int mg_solve(mg_plan plan, int n, const double* k, const double* f, double* u,
              double tol, int fixed_cycles, int* cycles, double* relres);
 
@@ -131,7 +132,9 @@ int mg_solve_noalloc(mg_plan plan, int n, const double* k, const double* f, doub
  *   QoIs (Qc = 0 at level 0);  cycles_out: int[2*n_samples], fine and coarse
  *   cycle counts, -1 where a solve missed tol.
  * fixed_cycles > 0 runs exactly that many cycles per solve (parity mode).
- * Returns MG_ENOCONV if any solve missed tol (the others are complete). */
+ * Returns MG_ENOCONV if any solve missed tol (the others are complete), and
+ * MG_EINVAL, with no device work, for n_samples < 1, a level outside
+ * [0, max_level], a NULL seeds or Y_out, or fixed_cycles < 0. */
 int mlmc_sample_batch(mg_plan plan, int level, const uint64_t* seeds, int n_samples,
                       double* Y_out, double* Qf_out, double* Qc_out, int* cycles_out,
                       int fixed_cycles);
@@ -141,7 +144,8 @@ int mlmc_sample_batch(mg_plan plan, int level, const uint64_t* seeds, int n_samp
  * Y_{levels[i]} of seed seeds[i]; every grid of every sample that has the same
  * size is advanced by the same launches (the V-cycles of smaller grids nest in
  * those of larger ones), so a mix of levels runs as one batch.  Results equal
- * those of mlmc_sample_batch on each level alone, bit for bit. */
+ * those of mlmc_sample_batch on each level alone, bit for bit.  MG_EINVAL
+ * as mlmc_sample_batch, and for any levels[i] outside [0, max_level]. */
 int mlmc_sample_mixed(mg_plan plan, const int* levels, const uint64_t* seeds, int n_samples,
                       double* Y_out, double* Qf_out, double* Qc_out, int* cycles_out,
                       int fixed_cycles);

@@ -218,3 +218,41 @@ def test_constant_coefficient_closed_form(M, torch):
     st, Y, Qf, Qc, cyc = _batch(M, torch, P, 1, [1, 2])
     assert st == M.MG_OK
     assert abs(Y[0] - 8.7966342e-5) < 1e-12 and Y[0] == Y[1]
+
+
+def test_empty_and_invalid_inputs_are_rejected(M, torch):
+    """Empty batches, levels outside the plan, grid sizes that are not
+    2^m + 1 (or beyond 1025) and negative cycle counts are refused with
+    MG_EINVAL before any device work; a valid call on the same plan then
+    still gives the results of a fresh plan."""
+    import ctypes as C
+    P = M.mg_plan_create(n0=9, max_level=2)
+    L = M.lib()
+    Y = torch.zeros(4, dtype=torch.float64, device="cuda")
+    seeds = np.arange(4, dtype=np.uint64)
+    sp = seeds.ctypes.data_as(C.POINTER(C.c_uint64))
+    yp = C.c_void_p(Y.data_ptr())
+    assert L.mlmc_sample_batch(P.handle, 0, sp, 0, yp, None, None, None, 0) == M.MG_EINVAL
+    assert L.mlmc_sample_batch(P.handle, 3, sp, 4, yp, None, None, None, 0) == M.MG_EINVAL
+    assert L.mlmc_sample_batch(P.handle, -1, sp, 4, yp, None, None, None, 0) == M.MG_EINVAL
+    assert L.mlmc_sample_batch(P.handle, 1, None, 4, yp, None, None, None, 0) == M.MG_EINVAL
+    assert L.mlmc_sample_batch(P.handle, 1, sp, 4, None, None, None, None, 0) == M.MG_EINVAL
+    assert L.mlmc_sample_batch(P.handle, 1, sp, 4, yp, None, None, None, -1) == M.MG_EINVAL
+    lv = np.array([0, 1, 3, 2], dtype=np.int32)
+    lp = lv.ctypes.data_as(C.POINTER(C.c_int))
+    assert L.mlmc_sample_mixed(P.handle, lp, sp, 4, yp, None, None, None, 0) == M.MG_EINVAL
+    assert L.mlmc_sample_mixed(P.handle, lp, sp, 0, yp, None, None, None, 0) == M.MG_EINVAL
+    assert P.error()  # the reason is recorded
+    for n in (2, 8, 10, 2049):
+        k = torch.ones(max(1, n) ** 3 if n < 100 else 8, dtype=torch.float64, device="cuda")
+        assert L.mg_solve(P.handle, n, C.c_void_p(k.data_ptr()), C.c_void_p(k.data_ptr()),
+                          C.c_void_p(k.data_ptr()), 0.0, 0, None, None) == M.MG_EINVAL
+    k = torch.ones(9 ** 3, dtype=torch.float64, device="cuda")
+    assert L.mg_solve(P.handle, 9, None, C.c_void_p(k.data_ptr()), C.c_void_p(k.data_ptr()),
+                      0.0, 0, None, None) == M.MG_EINVAL
+    # the plan still works and gives the results of a fresh plan
+    Qf = torch.zeros_like(Y)
+    assert M.mlmc_sample_batch(P, 2, seeds, 4, Y, Qf) == M.MG_OK
+    Y2, Qf2 = torch.zeros_like(Y), torch.zeros_like(Y)
+    assert M.mlmc_sample_batch(M.mg_plan_create(n0=9, max_level=2), 2, seeds, 4, Y2, Qf2) == M.MG_OK
+    assert torch.equal(Y, Y2) and torch.equal(Qf, Qf2)
