@@ -271,6 +271,34 @@ def _copy_kib(path, counter):
     return best
 
 
+def kernel_overlap(rows):
+    """Concurrency of the kernels of a trace (rows with Start_Timestamp and
+    End_Timestamp, ns): busy time (the union of their intervals), summed
+    kernel time, the mean number running while any runs (their ratio), and
+    the share of busy time in which two or more run at once.  Kernels that
+    end and start at the same instant do not overlap."""
+    ev = []
+    for r in rows:
+        a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        if b > a:
+            ev += [(a, 1), (b, -1)]
+    ev.sort(key=lambda e: (e[0], e[1]))  # ends before starts at the same time
+    busy = over = total = 0
+    cur, last = 0, None
+    for t, d in ev:
+        if last is not None and cur > 0:
+            busy += t - last
+            total += cur * (t - last)
+            if cur > 1:
+                over += t - last
+        cur += d
+        last = t
+    return {"kernels": len(ev) // 2, "busy_ns": busy, "kernel_ns": total,
+            "span_ns": (ev[-1][0] - ev[0][0]) if ev else 0,
+            "mean_concurrency": total / busy if busy else 0.0,
+            "overlap_share": over / busy if busy else 0.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -280,6 +308,8 @@ def main():
     t.add_argument("--title", required=True)
     t.add_argument("--command", required=True)
     t.add_argument("--stats", default="", help="the run's *_kernel_stats.csv")
+    t.add_argument("--overlap", action="store_true",
+                   help="also the kernels' concurrency (several queues at once)")
     p = sub.add_parser("pmc")
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
@@ -344,6 +374,14 @@ def main():
                                                                   trace_table(a.csv))
         if a.stats:
             txt += "\nrocprofv3 --stats (per kernel name):\n" + stats_table(a.stats) + "\n"
+        if a.overlap:
+            with open(a.csv) as f:
+                o = kernel_overlap(list(csv.DictReader(f)))
+            txt += ("\nconcurrency: %d kernels over %.3f ms busy (%.3f ms span); summed kernel "
+                    "time %.3f ms = %.2f kernels running on average while any runs; two or more "
+                    "at once during %.1f%% of the busy time\n"
+                    % (o["kernels"], o["busy_ns"] / 1e6, o["span_ns"] / 1e6, o["kernel_ns"] / 1e6,
+                       o["mean_concurrency"], 100.0 * o["overlap_share"]))
         open(a.out, "w").write(txt)
         print(txt)
     else:

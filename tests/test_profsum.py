@@ -85,3 +85,17 @@ def test_finest_sweeps_follow_the_v_cycle():
     # the selected rows belong to the last batch
     assert min(int(r["Dispatch_Id"]) for _, _, r in sel) > 40
     assert len(profsum.finest_sweeps(seq, batches=2, cycles_upto=9)) == 2 * 3 * 4
+
+
+def test_kernel_overlap_of_a_trace():
+    def row(a, b):
+        return {"Start_Timestamp": str(a), "End_Timestamp": str(b)}
+    # [0,10) alone, [10,20) back to back (no overlap), [15,30) overlapping the
+    # second by 5, [40,50) after a gap
+    o = profsum.kernel_overlap([row(0, 10), row(10, 20), row(15, 30), row(40, 50)])
+    assert o["kernels"] == 4
+    assert o["busy_ns"] == 40 and o["span_ns"] == 50
+    assert o["kernel_ns"] == 10 + 10 + 15 + 10
+    assert abs(o["overlap_share"] - 5 / 40) < 1e-12
+    assert abs(o["mean_concurrency"] - 45 / 40) < 1e-12
+    assert profsum.kernel_overlap([])["busy_ns"] == 0
