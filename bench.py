@@ -703,6 +703,13 @@ def bench_single(args, M, torch, np):
     latency per sample, HIP graphs vs eager launches, and of mg_solve alone."""
     n0, reps = 33, max(200, args.steps)
     P = M.mg_plan_create(n0=n0, max_level=0)
+    _apply_opts(M, P, args)
+    for spec in args.tile:
+        nn, tj, tk, ch = (int(x) for x in spec.split(":"))
+        M.mg_set_tile(P, nn, tj, tk, ch)
+    for spec in args.tile_pro:
+        nn, tj, tk, ch = (int(x) for x in spec.split(":"))
+        M.mg_set_tile_for(P, nn, 1, tj, tk, ch)
     Y, Qf, Qc, cyc = _samples(M, torch, P, 0, [0])
     seeds = np.zeros(1, dtype=np.uint64)
     res = {}

@@ -277,11 +277,21 @@ struct mg_plan_s {
 
 namespace mg {
 
-static SweepShape shape_for(mg_plan_s* P, int n, bool pro = false) {
+// The sweep shape for n, for a launch over count grids (0: unknown).  A
+// launch over so few grids that the kernel's automatic split, which stops at
+// pieces of four planes, would leave it under 512 workgroups takes pieces of
+// two planes instead (one 33^3 grid: 28 -> 64 workgroups per sweep, the
+// single-sample latency 718 -> 659 us; the results are the same for any split).
+static SweepShape shape_for(mg_plan_s* P, int n, bool pro = false, int count = 0) {
   const auto& m = pro ? P->shape_pro : P->shape;
   auto it = m.find(n);
-  return it != m.end() ? it->second
-                       : default_sweep_shape(n, pro, P->desc.precision == MG_MIXED);
+  if (it != m.end()) return it->second;
+  SweepShape s = default_sweep_shape(n, pro, P->desc.precision == MG_MIXED);
+  if (count > 0 && s.chunks == 0 && n >= 9) {
+    const int tiles = ((n - 1) / s.tj) * ((n - 1) / s.tk);
+    if ((long)count * tiles * ((n - 2) / 4) < 512) s.chunks = (n - 1) / 2;
+  }
+  return s;
 }
 
 // Order the plan's stream after everything queued so far on the caller's.
@@ -687,7 +697,8 @@ static int smooth_once(mg_plan_s* P, Batch* B, Lists<T>& Ls, size_t si, int buf,
     // correction)
     const bool cb = Ls.const_b(si);
     launch_sweep<T>(Ls.d[si], cnt, n, B->ss.active, buf, cbuf,
-                    shape_for(P, n, cbuf >= 0 || (spart && norm == 1 && !cb)), st, spart, norm, cb,
+                    shape_for(P, n, cbuf >= 0 || (spart && norm == 1 && !cb), cnt), st, spart,
+                    norm, cb,
                     P->kl_inline && Ls.kl(si));
     out = 1 - buf;
   } else {
@@ -720,14 +731,14 @@ static int lagged_parts(mg_plan_s* P, Batch* B, size_t si, int* red = nullptr,
   if (B->L64.chain_si >= 0 && si >= (size_t)B->L64.chain_si) return 0;  // LDS V-cycle sizes
   if (std::find(B->top_sizes.begin(), B->top_sizes.end(), n) == B->top_sizes.end()) return 0;
   if (!sweep_fits(n, sizeof(double))) return 0;
-  // decided per size for lists of any length: at most kSweepParts workgroups
-  // per grid (a list of one grid gets the most plane pieces)
-  if (std::max(sweep_blocks(n, 1, shape_for(P, n, false)), sweep_blocks(n, 1, shape_for(P, n, true))) >
-      kSweepParts)
-    return 0;
+  // at most kSweepParts workgroups per grid (a launch whose automatic split
+  // finds one grid active gives it the most plane pieces)
   const int cnt = std::max<int>(1, (int)L.h[si].size());
-  if (red) *red = sweep_blocks(n, cnt, shape_for(P, n, !L.const_b(si)));
-  return sweep_blocks(n, cnt, shape_for(P, n, false));
+  if (std::max(sweep_blocks(n, 1, shape_for(P, n, false, cnt)),
+               sweep_blocks(n, 1, shape_for(P, n, true, cnt))) > kSweepParts)
+    return 0;
+  if (red) *red = sweep_blocks(n, cnt, shape_for(P, n, !L.const_b(si), cnt));
+  return sweep_blocks(n, cnt, shape_for(P, n, false, cnt));
 }
 
 // One V(nu1,nu2) cycle with the P1 finite-element operator: two-pass
