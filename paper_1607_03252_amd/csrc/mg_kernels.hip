@@ -2187,11 +2187,11 @@ static int rr_tiles(int n) {
   const int m = (n - 1) / 2 - 1;
   return n >= 65 ? ceil_div(m, kRRJ1) * ceil_div(m, kRRK1) : ceil_div(m, kRRJ2) * ceil_div(m, kRRK2);
 }
-// pieces per tile: enough workgroups for two per CU, at least two coarse
-// planes per piece
+// pieces per tile: enough workgroups for two per CU, down to one coarse
+// plane per piece for launches over few grids
 int resrestrict_chunks(int n, int count) {
   const int m = (n - 1) / 2 - 1;
-  return std::max(1, std::min(m / 2, ceil_div(512, std::max(1, count) * rr_tiles(n))));
+  return std::max(1, std::min(m, ceil_div(512, std::max(1, count) * rr_tiles(n))));
 }
 
 template <typename T>
