@@ -155,7 +155,8 @@ def test_tile_shapes_and_chunks_bit_identical(M, torch, n0, level):
     seeds = [11, 12, 13]
     ref = _batch(M, torch, P, level, seeds, fixed=3)
     nf = (n0 - 1) * 2**level + 1
-    shapes = [(4, 64), (16, 32), (8, 32), (4, 32), (16, 16), (8, 16), (4, 16), (8, 8)]
+    shapes = [(16, 64), (8, 64), (4, 64), (16, 32), (8, 32), (4, 32), (16, 16), (8, 16), (4, 16),
+              (8, 8)]
     for n in (nf, (nf - 1) // 2 + 1):
         for tj, tk in shapes:
             if (n - 1) % tj or (n - 1) % tk or tk > n - 1:
