@@ -2347,6 +2347,13 @@ int mg_autotune(mg_plan P, int level, int n_samples, int reps) {
             pick = s;
           }
         }
+      // a fixed split that launches what the automatic one launches with
+      // every grid active is kept as the automatic split: the same launch
+      // then, and the marches still spread out once most solves have stopped
+      const int cnt = mixed ? (int)B->L32.h[si].size() : (int)B->L64.h[si].size();
+      if (pick.chunks > 0 &&
+          sweep_blocks(n, cnt, pick) == sweep_blocks(n, cnt, SweepShape{pick.tj, pick.tk, 0}))
+        pick.chunks = 0;
       (pro ? P->shape_pro : P->shape)[n] = pick;
     }
   }

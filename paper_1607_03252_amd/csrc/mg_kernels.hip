@@ -1968,9 +1968,13 @@ __global__ void k_fill(double* __restrict__ p, long count, double value) {
 inline dim3 xcd_grid(int count, int per) { return dim3(8 * ceil_div(count * per, 8)); }
 
 // Workgroups of a sweep launch: with automatic plane pieces (chunks 0) at
-// least kSweepUnits (the kernel spreads them over the grids still active),
-// otherwise the count x tiles x pieces of the fixed split.
-constexpr int kSweepUnits = 512;
+// least one round of the machine at the shape's occupancy (the kernel
+// spreads them over the grids still active): 512 for tiles of which two
+// workgroups fit a CU, 256 for the 16x64 tile, whose FP64 LDS leaves room
+// for one; otherwise the count x tiles x pieces of the fixed split.
+constexpr int sweep_min_units(int tj, int tk) {
+  return 10 * (tj + 4) * (tk + 4) * (int)sizeof(double) > 80 * 1024 ? 256 : 512;
+}
 template <typename T, int TJ, int TK, bool CB, bool KL>
 int sweep_launch_kl(const GridDescT<T>* d_list, int count, int n, const int* d_active, int buf,
                     int cbuf, int chunks, hipStream_t st, T* spart, int norm) {
@@ -1981,7 +1985,7 @@ int sweep_launch_kl(const GridDescT<T>* d_list, int count, int n, const int* d_a
     const int chunk_len = ceil_div(n - 2, chunks);
     units = count * tiles * ceil_div(n - 2, chunk_len);
   } else {
-    units = std::max(count * tiles, kSweepUnits);
+    units = std::max(count * tiles, sweep_min_units(TJ, TK));
   }
   const int nwg = 8 * ceil_div(units, 8);
   const int per = nwg;  // (returned: an upper bound of the workgroups per grid)
@@ -2056,7 +2060,7 @@ SweepShape default_sweep_shape(int n, bool fused_correction, bool single) {
   // (64 grids of 65^3, 128 of 33^3); 257^3 and 129^3 for batches of 16 and 48
   // grids; FP32 (the inner cycles of mixed precision) for 16 grids of 257^3
   // (the plane split is automatic where one piece per tile measured best
-  // for those batches, so that small launches still get split).  From 129^3
+  // for those batches, so that small launches still get split).  From 65^3
   // up the 16x64 tile: its LDS leaves room for one workgroup (eleven waves)
   // per CU, and its rows of 68 values make fewer, longer runs of addresses
   // per plane than the two 16x32 workgroups it replaces; the sweeps are
@@ -2067,8 +2071,7 @@ SweepShape default_sweep_shape(int n, bool fused_correction, bool single) {
     if (n == 65) return {16, 32, 0};
     if (n == 33) return fused_correction ? SweepShape{16, 32, 0} : SweepShape{16, 16, 0};
   } else {
-    if (n >= 129) return {16, 64, 0};
-    if (n == 65) return fused_correction ? SweepShape{16, 32, 0} : SweepShape{8, 64, 0};
+    if (n >= 65) return {16, 64, 0};
     if (n == 33) return fused_correction ? SweepShape{8, 32, 0} : SweepShape{16, 16, 0};
   }
   if (n - 1 >= 16) return {8, 16, 0};
@@ -2129,7 +2132,7 @@ void launch_prepare_problem(int n, const double* k, const double* f, double* wh,
 static int sweep_chunks(int n, int count, SweepShape s) {
   if (s.chunks >= 1) return s.chunks;
   const int tiles = ((n - 1) / s.tj) * ((n - 1) / s.tk);
-  const int nwg = 8 * ceil_div(std::max(count * tiles, kSweepUnits), 8);
+  const int nwg = 8 * ceil_div(std::max(count * tiles, sweep_min_units(s.tj, s.tk)), 8);
   return std::max(1, std::min(std::min(nwg / std::max(1, count * tiles), (n - 2) / 4),
                               kSweepParts / tiles));
 }
