@@ -655,10 +655,15 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   // right-hand side at this thread's positions on the plane in ring slot sl
   // With PW, W and (a full right-hand side) B hold a pair's two positions in
   // position order (one load each), else in role order (one load per role);
-  // these pick role rho's value.  (The sweeps held to four waves per SIMD
-  // keep the role loads: the selects' registers do not fit their budget;
-  // the sweep with the coarse correction measured slower with pairs.)
-  constexpr bool PW = (NM == 0 && !PRO) || (NM == 1 && !CB);
+  // these pick role rho's value.  Tiles of which one workgroup fits a CU
+  // (ONE: 16x64, three waves per SIMD, up to 168 registers) load pairs in
+  // every variant, and the input-residual sweep its u_in pairs too (at 257^3
+  // that sweep took 1368 instead of 1541 us); on the smaller tiles the
+  // variants held to four waves per SIMD keep the role loads (the selects'
+  // registers do not fit that budget, and the sweep with the coarse
+  // correction measured slower with pairs).
+  constexpr bool ONE = !KL && 10 * A2 * (int)sizeof(double) > 80 * 1024;
+  constexpr bool PW = ONE || (NM == 0 && !PRO) || (NM == 1 && !CB);
   auto bv = [&](int sl, int rho) -> T {
     if constexpr (CB) return B[0][rho];
     else if constexpr (PW) return (rho ^ sw) ? B[sl][1] : B[sl][0];
@@ -697,7 +702,7 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   // zero: those positions feed only results that are masked or dropped, and
   // u there is a boundary zero either way), and the pair (-1, 0) of row 0 is
   // not loaded (both positions are boundary or outside).
-  constexpr bool PL = NM == 1 && !CB;  // (see below)
+  constexpr bool PL = NM == 1 && (!CB || ONE);  // (see below)
   T UP[PL ? 4 : 1][2];
   const bool pin = live && j >= 0 && j < n && kA <= n - 2 && (kA >= 0 || j >= 1);
   const uint32_t offp = pin ? (uint32_t)((j * n + kA) * (int)sizeof(T)) : kOut;
