@@ -240,7 +240,9 @@ int mg_plan_set_option(mg_plan plan, const char* name, long long value);
 /* Tile shape of the fused smoother on grids of size n: tj rows (j) by tk
  * columns (k) per workgroup, the planes split into `chunks` pieces (0 = chosen
  * per launch from the number of grids: the march is split until the launch
- * has about 512 workgroups, at least four planes per piece).  Only the
+ * fills the machine once at the shape's occupancy, 512 workgroups, or 256
+ * for the 16x64 tile of which one fits a CU, at least four planes per
+ * piece).  Only the
  * compiled shapes whose tj, tk divide n-1 are accepted (MG_EINVAL otherwise).
  * A server captures the shapes in force at its first step. */
 int mg_set_tile(mg_plan plan, int n, int tj, int tk, int chunks);

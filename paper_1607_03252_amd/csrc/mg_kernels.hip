@@ -2130,9 +2130,10 @@ void launch_prepare_problem(int n, const double* k, const double* f, double* wh,
 }
 
 // Plane pieces of a sweep launch: the shape's, or automatic: split the plane
-// march until the launch has about 512 workgroups (two per CU; small batches
-// and small grids are latency-bound by the sequential march), keeping at
-// least four planes per piece.
+// march until the launch fills one round of the machine at the shape's
+// occupancy (512 workgroups, two per CU, or 256 for the 16x64 tile; small
+// batches and small grids are latency-bound by the sequential march),
+// keeping at least four planes per piece.
 // (automatic: as the kernel splits a launch of this many active grids)
 static int sweep_chunks(int n, int count, SweepShape s) {
   if (s.chunks >= 1) return s.chunks;
