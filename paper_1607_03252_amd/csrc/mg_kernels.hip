@@ -796,19 +796,21 @@ __device__ __forceinline__ void sweep_tile(const GridDescT<T>* __restrict__ list
   // the coarse planes (m >> 1) and (m >> 1) + 1, then the i part.  The (j, k)
   // part on the upper plane is the lower one of plane m + 2, the next plane
   // of the same role: it is returned in P1 and passed back as P0 then.
+  // The weights 1 and 1/2 are taken as index choices: an even position
+  // pairs a coarse value with itself, so the sum of two values halved
+  // (exactly, by a power of two) gives the bits of the weighted form, with
+  // four operations instead of nine per (j, k) part.
   auto pjk = [&](int I, int kk) -> T {
     const int ki = min(max(kk, 1), n - 2);
     const T* c = sC[I & 3];
     const int o = ((jI >> 1) - cj0) * CKM + (ki >> 1) - ck0;
-    const T wj1 = (jI & 1) ? (T)0.5 : (T)0, wj0 = (jI & 1) ? (T)0.5 : (T)1;
-    const T wk1 = (ki & 1) ? (T)0.5 : (T)0, wk0 = (ki & 1) ? (T)0.5 : (T)1;
-    return wj0 * (wk0 * c[o] + wk1 * c[o + 1]) + wj1 * (wk0 * c[o + CKM] + wk1 * c[o + CKM + 1]);
+    const int dk = ki & 1, dj = (jI & 1) ? CKM : 0;
+    return (T)0.25 * ((c[o] + c[o + dk]) + (c[o + dj] + c[o + dj + dk]));
   };
   auto pa_from = [&](int m, int kk, bool intk, T P0, T& P1) -> T {
     const int mi = min(max(m, 1), n - 2);
     P1 = pjk((mi >> 1) + 1, kk);
-    const T wi1 = (mi & 1) ? (T)0.5 : (T)0, wi0 = (mi & 1) ? (T)0.5 : (T)1;
-    const T pa = wi0 * P0 + wi1 * P1;
+    const T pa = (T)0.5 * (P0 + ((mi & 1) ? P1 : P0));
     return (m >= 1 && m <= n - 2 && intk) ? pa : (T)0;
   };
   auto pa_of = [&](int m, int kk, bool intk, T& P1) -> T {
