@@ -258,10 +258,12 @@ int mg_get_tile_for(mg_plan plan, int n, int fused_correction, int* tj, int* tk,
  * 0x5eed0000 + i), then times every compiled tile shape with chunk counts
  * 0 (automatic), 1, 2, 4 of both kinds of smoothing sweep on each grid size
  * of that batch above the LDS V-cycle's sizes (reps launches each, HIP
- * events) and picks the fastest per size and kind.  The picks are kept only
- * if whole batches (reps each, alternated with the shapes in force before
- * tuning, best of two rounds) run faster with them; otherwise the plan keeps
- * its previous shapes. */
+ * events) and picks the fastest per size and kind (a fixed chunk count that
+ * launches what the automatic one launches with every grid active is kept
+ * as automatic).  The picks are kept only if whole batches (reps each,
+ * alternated with the shapes in force before tuning, best of two rounds)
+ * run more than 1% faster with them; otherwise the plan keeps its previous
+ * shapes. */
 int mg_autotune(mg_plan plan, int level, int n_samples, int reps);
 
 /* Serving: continuous batching of MLMC sample requests --------------------
